@@ -1,0 +1,243 @@
+"""Pins for the oracle's PST / FC / VC layers.
+
+Every check here is against something other than the oracle's own formulas:
+the trapdoor shadow (group elements equal known multiples of the generators,
+computed with Python integers), the pairing's bilinearity, hashlib, the printed
+proof sizes of the paper's tables, the FC correctness invariant (section 3,
+correctness theorem), Lemma 1's rejection of a wrong batched claim, the naive
+one-proof-at-a-time opener, and the verifier of appendix C.
+"""
+import hashlib
+import os
+import random
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+import oracle as O
+from paper_2601_03031_amd import inputs as I
+
+R = O.R
+G1, G2 = O.generators()
+HERE = os.path.dirname(os.path.abspath(__file__))
+SEED = I.TRAPDOOR_SEED
+
+
+def golden_sizes():
+    rows = []
+    for ln in open(os.path.join(HERE, "golden", "proof_sizes.txt")):
+        if ln.strip() and not ln.startswith("#"):
+            kind, a, b, kib = ln.split()
+            rows.append((kind, int(a), int(b), float(kib)))
+    return rows
+
+
+def test_proof_sizes_match_paper_tables():
+    rows = golden_sizes()
+    assert len(rows) == 15
+    for kind, a, b, kib in rows:
+        if kind == "vc":
+            size = O.proof_len(a, b)
+        else:  # FC batch proof alone: 2 log n (G_T + G1) + A_l (G1) + v_l, pi_v (G2)
+            size = 2 * a * 384 + (2 * a + 1) * 32 + 2 * 64
+        assert abs(size / 1024 - kib) < 0.006, (kind, a, b, size / 1024, kib)
+
+
+def eq_weight(c, s, k):
+    w = 1
+    for t in range(k):
+        w = w * (s[t] if (c >> t) & 1 else (1 - s[t])) % R
+    return w
+
+
+def trapdoor(pp):
+    raw = pp.export("trapdoor")
+    vals = [int.from_bytes(raw[32 * i:32 * i + 32], "big") for i in range(pp.lM + 1)]
+    return vals[:-1], vals[-1]
+
+
+@pytest.fixture(scope="module")
+def small():
+    L = 6
+    pp = O.Params(L, SEED)
+    w = I.field_entries(pp.N, 1)
+    m = I.limbs_to_ints(w)
+    cm = O.Commitment(pp, I.limbs_to_bytes(w))
+    return pp, m, cm
+
+
+def test_setup_keys_trapdoor_shadow(small):
+    pp, _, _ = small
+    s, beta = trapdoor(pp)
+    for k in range(pp.lM + 1):
+        ek = pp.export("ek", k)
+        for c in range(1 << k):
+            assert ek[64 * c:64 * c + 64] == O.g1_op("mul", G1, O.be32(eq_weight(c, s, k)))
+        if k < pp.lM:  # Lagrange keys telescope: ek_k[c] = ek_{k+1}[c] + ek_{k+1}[c + 2^k]
+            up = pp.export("ek", k + 1)
+            for c in range(1 << k):
+                hi = up[64 * (c + (1 << k)):64 * (c + (1 << k)) + 64]
+                assert O.g1_op("add", up[64 * c:64 * c + 64], hi) == ek[64 * c:64 * c + 64]
+    vk = pp.export("vk")
+    for t in range(pp.lM):
+        assert vk[128 * t:128 * t + 128] == O.g2_op("mul", G2, O.be32(s[t]))
+    h = pp.export("h")
+    for k in range(2 * pp.K - 1):
+        assert h[128 * k:128 * k + 128] == O.g2_op("mul", G2, O.be32(pow(beta, k, R)))
+    assert pp.export("g1beta") == O.g1_op("mul", G1, O.be32(beta))
+
+
+def test_commit_trapdoor_shadow(small):
+    pp, m, cm = small
+    s, beta = trapdoor(pp)
+    fs = []
+    for j in range(pp.K):
+        fj = sum(m[j * pp.M + a] * eq_weight(a, s, pp.lM) for a in range(pp.M)) % R
+        fs.append(fj)
+        assert cm.Cj[j] == O.g1_op("mul", G1, O.be32(fj))
+    # C = prod_j e(C_j, g2^{beta^{2j}}) = e(g1, g2)^{sum_j f_j(s) beta^{2j}}
+    expo = sum(fs[j] * pow(beta, 2 * j, R) for j in range(pp.K)) % R
+    assert cm.C == O.fp12_op("pow", O.pairing([G1], [G2]), O.be32(expo))
+
+
+def test_fc_invariant_folded_key_and_lemma1(small):
+    pp, _, cm = small
+    s, beta = trapdoor(pp)
+    O.set_invariant_check(True)
+    try:
+        op = O.Opening(cm, 3)
+        checks, fails = O.invariant_counts()
+    finally:
+        O.set_invariant_check(False)
+    assert checks == op.nb * pp.lK and fails == 0
+    # v_l = f_v(beta) g2 with f_v(X) = prod_j (1 + x_j^{-1} X^{2^{l-j+1}})
+    for k in range(op.nb):
+        xs = op.export("fc_x", k)
+        x = [int.from_bytes(xs[32 * j:32 * j + 32], "big") for j in range(pp.lK)]
+        fv = 1
+        for j in range(1, pp.lK + 1):
+            fv = fv * (1 + pow(x[j - 1], -1, R) * pow(beta, 2 ** (pp.lK - j + 1), R)) % R
+        tail = op.export("fc_tail", k)
+        assert tail[64:192] == O.g2_op("mul", G2, O.be32(fv))
+    # batched opening accepts the true claims and rejects one wrong claim (Lemma 1)
+    idx = [1, 4, 6]
+    assert cm.fc_roundtrip(idx) == 1
+    assert cm.fc_roundtrip(idx, bad_slot=1) == 0
+    assert cm.two_step_fc(5)
+
+
+def test_step2_closed_forms(small):
+    pp, m, cm = small
+    s, _ = trapdoor(pp)
+    op = O.Opening(cm, 2)
+    K, M, N = pp.K, pp.M, pp.N
+    # Merkle tree recomputed with hashlib from the leaf definition
+    mt = op.export("merkle")
+    level = [hashlib.sha256(b"\x00" + O.be32(m[i]) + cm.Cj[i // M]).digest() for i in range(N)]
+    while len(level) > 1:
+        level = [hashlib.sha256(b"\x01" + level[2 * q] + level[2 * q + 1]).digest()
+                 for q in range(len(level) // 2)]
+    root = level[0]
+    assert mt[32:64] == root
+    rho_raw = op.export("rho")
+    rho = [int.from_bytes(rho_raw[32 * j:32 * j + 32], "big") for j in range(K)]
+    for j in range(K):
+        assert rho[j] == O.hash_to_fr("FLEXPROOFS-V1-RHO", cm.C + root + j.to_bytes(8, "big"))
+    # root of the fold tree: y* = sum_j rho_j m_j, D* = (sum_j rho_j f_j(s)) g1
+    y = op.export("y")
+    top = (2 * K - 2) * M
+    for a in range(M):
+        want = sum(rho[j] * m[j * M + a] for j in range(K)) % R
+        assert int.from_bytes(y[32 * (top + a):32 * (top + a) + 32], "big") == want
+    fsum = sum(rho[j] * sum(m[j * M + a] * eq_weight(a, s, pp.lM) for a in range(M)) for j in range(K)) % R
+    D = op.export("D")
+    assert D[64 * (2 * K - 2):] == O.g1_op("mul", G1, O.be32(fsum))
+    # HyperEval is linear: W(g*, a) = sum_j rho_j W(f_j, a) (two-step PST proofs)
+    W = op.export("W")
+    for a in [0, 3, M - 1]:
+        acc = [bytes(64)] * pp.lM
+        for j in range(K):
+            wj, yj, ok = cm.two_step_pst(j * M + a)
+            assert ok and yj == m[j * M + a]
+            for d in range(pp.lM):
+                acc[d] = O.g1_op("add", acc[d], O.g1_op("mul", wj[d], O.be32(rho[j])))
+        for d in range(pp.lM):
+            n = (1 << d) - 1 + (a >> (pp.lM - d))
+            assert W[64 * n:64 * n + 64] == acc[d]
+
+
+def _check_all(pp, m, cm, b, sample=None, naive=()):
+    op = O.Opening(cm, b)
+    idx = range(pp.N) if sample is None else sample
+
+    def one(i):
+        pr = op.proof(i)
+        t = min(b, pp.K - (i // pp.M // b) * b)
+        assert len(pr) == O.proof_len(pp.log_n, t)
+        return O.verify(pp, cm.C, b, i, m[i], pr)
+
+    with ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as ex:
+        res = list(ex.map(one, idx))
+    assert all(v == 1 for v in res)
+    for i in naive:
+        assert O.naive_proof(pp, cm.m_le, b, i) == op.proof(i)
+    return op
+
+
+@pytest.mark.parametrize("L,b", [(4, 1), (4, 4), (5, 3), (6, 2)])
+def test_open_all_every_proof_verifies_and_matches_naive(L, b):
+    pp = O.Params(L, SEED)
+    w = I.field_entries(pp.N, L)
+    m = I.limbs_to_ints(w)
+    cm = O.Commitment(pp, I.limbs_to_bytes(w))
+    _check_all(pp, m, cm, b, naive=[0, pp.N - 1, pp.N // 2 + 1])
+
+
+def test_tampering_is_rejected(small):
+    pp, m, cm = small
+    b = 2
+    op = O.Opening(cm, b)
+    i = 21
+    pr = op.proof(i)
+    assert O.verify(pp, cm.C, b, i, m[i], pr) == 1
+    assert O.verify(pp, cm.C, b, i, (m[i] + 1) % R, pr) == 0
+    assert O.verify(pp, cm.C, b, i ^ 1, m[i], pr) == 0
+    # flip one byte inside each section of the wire format
+    lK, lM, t = pp.lK, pp.lM, b
+    offs = [5, 32 * t + 100, 32 * t + 390, 32 * t + lK * 832 + 3, 32 * t + lK * 832 + 40,
+            32 * t + lK * 832 + 100, 32 * t + lK * 832 + 170, 32 * t + lK * 832 + 160 + lK * 64 + 5,
+            len(pr) - 3]
+    for o in offs:
+        bad = bytearray(pr)
+        bad[o] ^= 0x04
+        assert O.verify(pp, cm.C, b, i, m[i], bytes(bad)) != 1, o
+    # another vector's commitment
+    w2 = I.field_entries(pp.N, 99)
+    cm2 = O.Commitment(pp, I.limbs_to_bytes(w2))
+    assert O.verify(pp, cm2.C, b, i, m[i], pr) == 0
+
+
+def test_zero_vector_and_identity_commitments():
+    pp = O.Params(4, SEED)
+    zero = bytes(32 * pp.N)
+    cm = O.Commitment(pp, zero)
+    assert all(c == bytes(64) for c in cm.Cj) and cm.C == O.GT_ONE
+    _check_all(pp, [0] * pp.N, cm, 2)
+
+
+def test_entry_out_of_range_rejected():
+    pp = O.Params(4, SEED)
+    bad = O.le32(R) + bytes(32 * (pp.N - 1))
+    with pytest.raises(ValueError):
+        O.Commitment(pp, bad)
+
+
+@pytest.mark.slow
+def test_c1_workload_n1024_b1_sampled():
+    """N = 2^10, b = 1 (the small parity workload), full-width seeded entries."""
+    pp = O.Params(10, SEED)
+    w = I.field_entries(pp.N, 1)
+    m = I.limbs_to_ints(w)
+    cm = O.Commitment(pp, I.limbs_to_bytes(w))
+    rng = random.Random(1)
+    _check_all(pp, m, cm, 1, sample=rng.sample(range(pp.N), 24) + [0, pp.N - 1], naive=[777])
