@@ -1,0 +1,100 @@
+/*
+ * FlexProofs vector commitment on one MI355X (gfx950): C ABI.
+ *
+ * The scheme (paper, section 4, "A VC Scheme with Linear-Time OpenAll") commits to a
+ * vector m in F_r^N, N = 2^L, in two layers: the N entries are split into K = 2^floor(L/2)
+ * subvectors of M = N/K entries, each committed with the multilinear PST scheme
+ * (Eq. genCi), and the K commitments are committed with the pairing-based functional
+ * commitment of section 3 (Eq. genC).  OpenAll (Protocol 1 and its Sub-protocol,
+ * made non-interactive with a Merkle tree as in section 4.2) produces all N opening
+ * proofs: ceil(K/b) FC batch proofs (Step 1) plus a randomized folding tree and
+ * PC.HyperEval on the folded polynomial (Step 2).  Curve: BN254 (the paper's
+ * BN_SNARK1), optimal ate pairing.
+ *
+ * Conventions for every entry point:
+ *  - Return value: VC_OK (0) or a negative VC_E* code; vc_verify returns 1 (accept),
+ *    0 (reject) or a negative code.  vc_strerror() names a code.
+ *  - Device pointers are borrowed for the duration of the call and must be device
+ *    memory on the params' device.  `stream` is a hipStream_t (NULL = default
+ *    stream); work is ordered on it and every call is synchronous on return.
+ *  - Handles (vc_params, vc_commitment, vc_proofs) own their device memory and are
+ *    released with the matching *_free; a vc_proofs handle does not reference the
+ *    commitment it was made from.
+ *  - Field entries and scalars are canonical (< r) 32-byte little-endian integers
+ *    unless stated otherwise; serialized group elements are canonical big-endian:
+ *    G1 64 B (x || y), G2 128 B (x.c0 || x.c1 || y.c0 || y.c1), G_T 384 B (12 F_p
+ *    coefficients, c0.c0.c0 first), identity = all zero bytes.
+ */
+#ifndef FLEXPROOFS_VC_H
+#define FLEXPROOFS_VC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VC_OK 0
+#define VC_EINVAL (-1)     /* bad size, b out of [1, K], entry >= r, malformed proof */
+#define VC_ENOMEM (-2)     /* device allocation failed */
+#define VC_EDEVICE (-3)    /* HIP runtime error */
+#define VC_ENOTIMPL (-4)
+#define VC_ECHALLENGE (-5) /* a Fiat-Shamir challenge was zero (probability ~2^-254) */
+
+typedef struct vc_params vc_params;
+typedef struct vc_commitment vc_commitment;
+typedef struct vc_proofs vc_proofs;
+
+/* VC.Setup(1^lambda, 1^N) (Eq. vcpp): PST keys for log M variables and FC keys for
+ * K entries, derived from a seeded TEST trapdoor (insecure: the paper requires a
+ * trusted setup).  2 <= log_n <= 20.  The keys stay resident on `device`. */
+int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out);
+
+/* VC.Commit(m) (Eq. genCi, genC).  m_dev: n entries on the device, either n x 32 B
+ * canonical little-endian (entry_bits = 256) or n x uint32 (entry_bits = 32, the
+ * entries are the integers themselves).  n must equal 2^log_n of the params.
+ * Writes the commitment C (G_T, 384 B) to C_out (host) and returns the handle that
+ * keeps aux = (C_0..C_{K-1}) and a copy of m on the device.  VC_EINVAL if an entry
+ * is >= r. */
+int vc_commit(const vc_params *pp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
+              vc_commitment **out, uint8_t C_out[384]);
+
+/* VC.OpenAll(aux, m) with batch size b, 1 <= b <= K (Protocol 1): all N proofs,
+ * kept on the device in shared form (one FC batch proof per block of b
+ * subvectors, the folding tree, the HyperEval commitments and the Merkle tree). */
+int vc_open_all(const vc_params *pp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out);
+
+/* Serialized length of a proof whose block holds t subvector commitments. */
+uint64_t vc_proof_len(uint32_t log_n, uint32_t t);
+
+/* Serialize pi_i into buf (host, cap bytes): the block's commitments, the FC batch
+ * proof (L_j, R_j, A_l, v_l and the proof of v_l), the fold-tree siblings, the PST
+ * proof and the Merkle path, with compressed G1 (32 B) / G2 (64 B) points. */
+int vc_proof_get(const vc_proofs *pr, uint64_t i, uint8_t *buf, size_t cap, size_t *len);
+
+/* VC.Verify(C, i, m_i, pi_i) for a proof made with batch size b; m_i is 32 B
+ * little-endian.  Returns 1 accept, 0 reject, VC_EINVAL for malformed input. */
+int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint32_t b, uint64_t i,
+              const uint8_t m_i[32], const uint8_t *proof, size_t len);
+
+/* Bulk canonical arrays for parity checks (host destination, cap bytes).
+ * params:     what 0 ek level idx (2^idx x G1), 1 vk (log M x G2), 2 h (2K-1 x G2), 3 beta g1
+ * commitment: what 0 C_j (K x G1), 1 C (G_T)
+ * proofs:     what 0 rounds of batch idx (log K x [L.gt L.g1 R.gt R.g1]), 1 [A_l v_l pi_v] of
+ *             batch idx, 2 challenges x_j of batch idx (32 B BE each), 3 Merkle tree (2N x 32 B,
+ *             node 1 = root), 4 rho (K x 32 B BE), 5 fold rows ((2K-1) M x 32 B BE),
+ *             6 fold commitments ((2K-1) x G1), 7 HyperEval commitments ((M-1) x G1) */
+int vc_params_export(const vc_params *pp, int what, uint32_t idx, void *dst, size_t cap, size_t *len);
+int vc_commitment_export(const vc_commitment *cm, int what, void *dst, size_t cap, size_t *len);
+int vc_proofs_export(const vc_proofs *pr, int what, uint64_t idx, void *dst, size_t cap, size_t *len);
+
+void vc_params_free(vc_params *pp);
+void vc_commitment_free(vc_commitment *cm);
+void vc_proofs_free(vc_proofs *pr);
+const char *vc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

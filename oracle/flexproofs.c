@@ -253,18 +253,28 @@ OR_API int or_commit_export(void *c, uint8_t *Cj, uint8_t C[384]) {
 /*
  * Reading of the batching coefficients r_i = H(b^(i), C, {b^(k)}, {y_k}) (FC.BOpen,
  * Eq. eqn:b): every b^(i) here is a unit vector u_{a_i}, encoded by its index, and
- * the statement is hashed once into a seed,
- *   sigma = SHA-256(DST_FC_R || enc(C) || t || (a_i || enc(y_i))_{i<t}),
+ * the whole statement is hashed once into a seed.  The statement list is hashed in
+ * chunks of FC_CHUNK entries so that the chunk digests can be computed in parallel:
+ *   H_q   = SHA-256((a_i || enc(y_i)) for i in [q FC_CHUNK, (q+1) FC_CHUNK) cap [0, t)),
+ *   sigma = SHA-256(DST_FC_R || enc(C) || t || H_0 || H_1 || ...),
  *   r_i   = H2F(DST_FC_R, sigma || i).
  */
+#define FC_CHUNK 32
 static void fc_batch_coeffs(fe *r, const fp12 *C, const uint64_t *idx, const g1a *y, uint32_t t) {
     bytes b = {0};
     bytes_put(&b, DST_FC_R, strlen(DST_FC_R));
     put_gt(&b, C);
     bytes_put_u64(&b, t);
-    for (uint32_t i = 0; i < t; i++) {
-        bytes_put_u64(&b, idx[i]);
-        put_g1(&b, &y[i]);
+    for (uint32_t q = 0; q * FC_CHUNK < t; q++) {
+        bytes c = {0};
+        for (uint32_t i = q * FC_CHUNK; i < t && i < (q + 1) * FC_CHUNK; i++) {
+            bytes_put_u64(&c, idx[i]);
+            put_g1(&c, &y[i]);
+        }
+        uint8_t hq[32];
+        sha256(hq, c.p, c.n);
+        bytes_free(&c);
+        bytes_put(&b, hq, 32);
     }
     uint8_t sigma[32];
     sha256(sigma, b.p, b.n);

@@ -1,0 +1,167 @@
+"""FlexProofs on MI355X: Python binding of the C ABI in include/vc.h.
+
+Argument marshalling only: every step of commit / open-all runs in the HIP
+kernels of lib/libvc.so.  PyTorch supplies device memory and streams.  The
+library must have been built (``python -m paper_2601_03031_amd.build``); if it is
+missing, every call raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libvc.so")
+
+VC_OK, VC_EINVAL, VC_ENOMEM, VC_EDEVICE, VC_ENOTIMPL, VC_ECHALLENGE = 0, -1, -2, -3, -4, -5
+
+_lib = None
+
+
+class VCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib().vc_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__("%s failed: %s (%d)" % (where, msg, code))
+
+
+def lib():
+    """Load lib/libvc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("FlexProofs HIP library not built: %s is missing "
+                               "(run python -m paper_2601_03031_amd.build)" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        vp, u8p, u64, u32, sz = C.c_void_p, C.c_char_p, C.c_uint64, C.c_uint32, C.c_size_t
+        L.vc_setup.argtypes = [u32, u8p, C.c_int, C.POINTER(vp)]
+        L.vc_commit.argtypes = [vp, vp, u64, u32, vp, C.POINTER(vp), vp]
+        L.vc_open_all.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
+        L.vc_proof_len.restype = u64
+        L.vc_proof_len.argtypes = [u32, u32]
+        L.vc_proof_get.argtypes = [vp, u64, vp, sz, C.POINTER(sz)]
+        L.vc_verify.argtypes = [vp, u8p, u64, u32, u64, u8p, u8p, sz]
+        L.vc_params_export.argtypes = [vp, C.c_int, u32, vp, sz, C.POINTER(sz)]
+        L.vc_commitment_export.argtypes = [vp, C.c_int, vp, sz, C.POINTER(sz)]
+        L.vc_proofs_export.argtypes = [vp, C.c_int, u64, vp, sz, C.POINTER(sz)]
+        for f in ("vc_params_free", "vc_commitment_free", "vc_proofs_free"):
+            getattr(L, f).argtypes = [vp]
+        L.vc_strerror.restype = C.c_char_p
+        L.vc_strerror.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise VCError(rc, where)
+    return rc
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+class _Handle:
+    _free = ""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            getattr(_lib, self._free)(self.ptr)
+            self.ptr = None
+
+
+class Params(_Handle):
+    _free = "vc_params_free"
+
+    def __init__(self, ptr, log_n):
+        super().__init__(ptr)
+        self.log_n = log_n
+        self.lK = log_n // 2
+        self.lM = log_n - self.lK
+        self.N, self.K, self.M = 1 << log_n, 1 << self.lK, 1 << self.lM
+
+    def export(self, what: str, idx: int = 0) -> bytes:
+        codes = {"ek": 0, "vk": 1, "h": 2, "g1beta": 3}
+        n = C.c_size_t(0)
+        lib().vc_params_export(self.ptr, codes[what], idx, None, 0, C.byref(n))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().vc_params_export(self.ptr, codes[what], idx, buf, n.value, C.byref(n)), "vc_params_export")
+        return buf.raw
+
+
+class Commitment(_Handle):
+    _free = "vc_commitment_free"
+
+    def __init__(self, ptr, pp, C_bytes):
+        super().__init__(ptr)
+        self.pp, self.C = pp, C_bytes
+
+    def export(self, what: str) -> bytes:
+        codes = {"Cj": 0, "C": 1}
+        n = C.c_size_t(0)
+        lib().vc_commitment_export(self.ptr, codes[what], None, 0, C.byref(n))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().vc_commitment_export(self.ptr, codes[what], buf, n.value, C.byref(n)), "vc_commitment_export")
+        return buf.raw
+
+
+class Proofs(_Handle):
+    _free = "vc_proofs_free"
+
+    def __init__(self, ptr, pp, b):
+        super().__init__(ptr)
+        self.pp, self.b = pp, b
+        self.nb = (pp.K + b - 1) // b
+
+    def export(self, what: str, idx: int = 0) -> bytes:
+        codes = {"fc_rounds": 0, "fc_tail": 1, "fc_x": 2, "merkle": 3, "rho": 4, "y": 5, "D": 6, "W": 7}
+        n = C.c_size_t(0)
+        lib().vc_proofs_export(self.ptr, codes[what], idx, None, 0, C.byref(n))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().vc_proofs_export(self.ptr, codes[what], idx, buf, n.value, C.byref(n)), "vc_proofs_export")
+        return buf.raw
+
+
+def vc_setup(log_n: int, seed: bytes, device: int = 0) -> Params:
+    out = C.c_void_p()
+    _check(lib().vc_setup(log_n, seed, device, C.byref(out)), "vc_setup")
+    return Params(out, log_n)
+
+
+def vc_commit(pp: Params, m, entry_bits: int = 256, stream=None) -> Commitment:
+    """m: a device tensor holding N x 32 little-endian bytes (entry_bits=256) or
+    N 32-bit integers (entry_bits=32)."""
+    out = C.c_void_p()
+    cbuf = C.create_string_buffer(384)
+    _check(lib().vc_commit(pp.ptr, C.c_void_p(m.data_ptr()), pp.N, entry_bits, _stream_ptr(stream),
+                           C.byref(out), cbuf), "vc_commit")
+    return Commitment(out, pp, cbuf.raw)
+
+
+def vc_open_all(pp: Params, cm: Commitment, b: int, stream=None) -> Proofs:
+    out = C.c_void_p()
+    _check(lib().vc_open_all(pp.ptr, cm.ptr, b, _stream_ptr(stream), C.byref(out)), "vc_open_all")
+    return Proofs(out, pp, b)
+
+
+def vc_proof_len(log_n: int, t: int) -> int:
+    return int(lib().vc_proof_len(log_n, t))
+
+
+def vc_proof_get(pr: Proofs, i: int) -> bytes:
+    cap = vc_proof_len(pr.pp.log_n, pr.b)
+    buf = C.create_string_buffer(cap)
+    n = C.c_size_t(0)
+    _check(lib().vc_proof_get(pr.ptr, i, buf, cap, C.byref(n)), "vc_proof_get")
+    return buf.raw[:n.value]
+
+
+def vc_verify(pp: Params, C_bytes: bytes, b: int, i: int, m_i: int, proof: bytes) -> int:
+    return _check(lib().vc_verify(pp.ptr, C_bytes, pp.N, b, i, int(m_i).to_bytes(32, "little"), proof, len(proof)),
+                  "vc_verify")

@@ -1,0 +1,187 @@
+// Host build of the device arithmetic headers (field, tower, curve, pairing, hash),
+// exported with canonical big-endian byte encodings so CPU tests can compare the
+// GPU path's arithmetic with the oracle before any kernel runs.  This is a test
+// harness for the HIP code path; the library itself never runs it.
+#include <cstring>
+#include "field.hpp"
+#include "tower.hpp"
+#include "curve.hpp"
+#include "pairing.hpp"
+#include "hash.hpp"
+
+#define API extern "C" __attribute__((visibility("default")))
+
+template <class F> static fe rd(const uint8_t *b) {
+  fe a;
+  for (int i = 0; i < 8; i++)
+    a.l[7 - i] = ((uint32_t)b[4 * i] << 24) | ((uint32_t)b[4 * i + 1] << 16) | ((uint32_t)b[4 * i + 2] << 8) | b[4 * i + 3];
+  return f_to_mont<F>(a);
+}
+template <class F> static void wr(uint8_t *b, const fe &m) {
+  fe a = f_from_mont<F>(m);
+  for (int i = 0; i < 8; i++) {
+    uint32_t w = a.l[7 - i];
+    b[4 * i] = w >> 24; b[4 * i + 1] = w >> 16; b[4 * i + 2] = w >> 8; b[4 * i + 3] = w;
+  }
+}
+static fp2 rd2(const uint8_t *b) { return {rd<FpP>(b), rd<FpP>(b + 32)}; }
+static void wr2(uint8_t *b, const fp2 &a) { wr<FpP>(b, a.c0); wr<FpP>(b + 32, a.c1); }
+static fp12 rd12(const uint8_t *b) {
+  fp12 f;
+  fp6 *h[2] = {&f.c0, &f.c1};
+  for (int a = 0; a < 2; a++) {
+    fp2 *q[3] = {&h[a]->c0, &h[a]->c1, &h[a]->c2};
+    for (int c = 0; c < 3; c++) *q[c] = rd2(b + 384 / 2 * a + 64 * c);
+  }
+  return f;
+}
+static void wr12(uint8_t *b, const fp12 &f) {
+  const fp6 *h[2] = {&f.c0, &f.c1};
+  for (int a = 0; a < 2; a++) {
+    const fp2 *q[3] = {&h[a]->c0, &h[a]->c1, &h[a]->c2};
+    for (int c = 0; c < 3; c++) wr2(b + 192 * a + 64 * c, *q[c]);
+  }
+}
+static g1_aff rdg1(const uint8_t *b) { return {rd<FpP>(b), rd<FpP>(b + 32)}; }
+static void wrg1(uint8_t *b, const g1_aff &p) { wr<FpP>(b, p.x); wr<FpP>(b + 32, p.y); }
+static g2_aff rdg2(const uint8_t *b) { return {rd2(b), rd2(b + 64)}; }
+static void wrg2(uint8_t *b, const g2_aff &p) { wr2(b, p.x); wr2(b + 64, p.y); }
+static void canon_scalar(uint32_t k[8], const uint8_t *b) {
+  for (int i = 0; i < 8; i++)
+    k[7 - i] = ((uint32_t)b[4 * i] << 24) | ((uint32_t)b[4 * i + 1] << 16) | ((uint32_t)b[4 * i + 2] << 8) | b[4 * i + 3];
+}
+
+// op: 0 add 1 sub 2 mul 3 inv(Fermat) 4 inv(binary) 5 half
+API int hc_field(int which, int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
+  if (which == 0) {
+    fe x = rd<FpP>(a), y = rd<FpP>(b), z;
+    switch (op) {
+      case 0: z = fp_add(x, y); break;
+      case 1: z = fp_sub(x, y); break;
+      case 2: z = fp_mul(x, y); break;
+      case 3: z = fp_inv(x); break;
+      case 4: z = fp_inv_fast(x); break;
+      case 5: z = fp_half(x); break;
+      default: return -1;
+    }
+    wr<FpP>(out, z);
+  } else {
+    fe x = rd<FpR>(a), y = rd<FpR>(b), z;
+    switch (op) {
+      case 0: z = fr_add(x, y); break;
+      case 1: z = fr_sub(x, y); break;
+      case 2: z = fr_mul(x, y); break;
+      case 3: z = fr_inv(x); break;
+      case 4: z = fr_inv_fast(x); break;
+      case 5: z = f_half<FpR>(x); break;
+      default: return -1;
+    }
+    wr<FpR>(out, z);
+  }
+  return 0;
+}
+
+// op: 0 mul 1 sqr 2 inv 3 final_exp 4 frob1 5 frob2 6 frob3 7 cyclo_sqr 8 cyclo_pow_u
+API int hc_fp12(int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
+  fp12 x = rd12(a), y = rd12(b), z;
+  switch (op) {
+    case 0: z = f12_mul(x, y); break;
+    case 1: z = f12_sqr(x); break;
+    case 2: z = f12_inv(x); break;
+    case 3: z = f12_final_exp(x); break;
+    case 4: z = f12_frob1(x); break;
+    case 5: z = f12_frob2(x); break;
+    case 6: z = f12_frob3(x); break;
+    case 7: z = f12_cyclo_sqr(x); break;
+    case 8: z = f12_cyclo_pow_u(x); break;
+    default: return -1;
+  }
+  wr12(out, z);
+  return 0;
+}
+
+API int hc_fp2(int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
+  fp2 x = rd2(a), y = rd2(b), z;
+  switch (op) {
+    case 0: z = f2_mul(x, y); break;
+    case 1: z = f2_sqr(x); break;
+    case 2: z = f2_inv(x); break;
+    case 3: z = f2_mul_xi(x); break;
+    default: return -1;
+  }
+  wr2(out, z);
+  return 0;
+}
+
+// op: 0 add 1 dbl 2 scalar mul (k canonical BE in b) 3 madd
+API int hc_g1(int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
+  g1_aff P = rdg1(a);
+  if (op == 2) {
+    uint32_t k[8];
+    canon_scalar(k, b);
+    wrg1(out, jac_to_aff(scalar_mul(P, k)));
+    return 0;
+  }
+  g1_aff Q = rdg1(b);
+  if (op == 0) wrg1(out, jac_to_aff(jac_add(jac_from_aff(P), jac_from_aff(Q))));
+  else if (op == 1) wrg1(out, jac_to_aff(jac_dbl(jac_from_aff(P))));
+  else if (op == 3) wrg1(out, jac_to_aff(jac_madd(jac_from_aff(P), Q)));
+  else return -1;
+  return 0;
+}
+
+API int hc_g2(int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
+  g2_aff P = rdg2(a);
+  if (op == 2) {
+    uint32_t k[8];
+    canon_scalar(k, b);
+    wrg2(out, jac_to_aff(scalar_mul(P, k)));
+    return 0;
+  }
+  if (op == 4) { wrg2(out, g2_frobenius(P)); return 0; }
+  g2_aff Q = rdg2(b);
+  if (op == 0) wrg2(out, jac_to_aff(jac_add(jac_from_aff(P), jac_from_aff(Q))));
+  else if (op == 1) wrg2(out, jac_to_aff(jac_dbl(jac_from_aff(P))));
+  else if (op == 3) wrg2(out, jac_to_aff(jac_madd(jac_from_aff(P), Q)));
+  else return -1;
+  return 0;
+}
+
+API int hc_pairing(const uint8_t *P, const uint8_t *Q, uint8_t *out) {
+  wr12(out, f12_final_exp(miller_loop(rdg1(P), rdg2(Q))));
+  return 0;
+}
+
+API void hc_h2f(const char *dst, const uint8_t *msg, uint64_t len, uint8_t *out) {
+  sha::Hasher h;
+  sha::xmd_begin(h);
+  h.bytes(msg, (int)len);
+  wr<FpR>(out, sha::xmd_finish_fr(h, dst));
+}
+
+API void hc_sha256(const uint8_t *msg, uint64_t len, uint8_t *out) {
+  sha::Hasher h;
+  h.init();
+  h.bytes(msg, (int)len);
+  uint32_t o[8];
+  h.final(o);
+  for (int i = 0; i < 8; i++) { out[4 * i] = o[i] >> 24; out[4 * i + 1] = o[i] >> 16; out[4 * i + 2] = o[i] >> 8; out[4 * i + 3] = o[i]; }
+}
+
+API void hc_merkle_leaf(const uint8_t m[32], const uint8_t c[64], uint8_t out[32]) {
+  uint32_t mw[8], cw[16], o[8];
+  for (int i = 0; i < 8; i++) mw[i] = ((uint32_t)m[4 * i] << 24) | ((uint32_t)m[4 * i + 1] << 16) | ((uint32_t)m[4 * i + 2] << 8) | m[4 * i + 3];
+  for (int i = 0; i < 16; i++) cw[i] = ((uint32_t)c[4 * i] << 24) | ((uint32_t)c[4 * i + 1] << 16) | ((uint32_t)c[4 * i + 2] << 8) | c[4 * i + 3];
+  sha::merkle_leaf(o, mw, cw);
+  for (int i = 0; i < 8; i++) { out[4 * i] = o[i] >> 24; out[4 * i + 1] = o[i] >> 16; out[4 * i + 2] = o[i] >> 8; out[4 * i + 3] = o[i]; }
+}
+
+API void hc_merkle_node(const uint8_t l[32], const uint8_t r[32], uint8_t out[32]) {
+  uint32_t lw[8], rw[8], o[8];
+  for (int i = 0; i < 8; i++) {
+    lw[i] = ((uint32_t)l[4 * i] << 24) | ((uint32_t)l[4 * i + 1] << 16) | ((uint32_t)l[4 * i + 2] << 8) | l[4 * i + 3];
+    rw[i] = ((uint32_t)r[4 * i] << 24) | ((uint32_t)r[4 * i + 1] << 16) | ((uint32_t)r[4 * i + 2] << 8) | r[4 * i + 3];
+  }
+  sha::merkle_node(o, lw, rw);
+  for (int i = 0; i < 8; i++) { out[4 * i] = o[i] >> 24; out[4 * i + 1] = o[i] >> 16; out[4 * i + 2] = o[i] >> 8; out[4 * i + 3] = o[i]; }
+}

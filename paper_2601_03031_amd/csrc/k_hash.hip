@@ -1,0 +1,243 @@
+// Kernels: transcript and Merkle hashing, batching coefficients, KZG quotient.
+#include "kcommon.hpp"
+
+#define FC_CHUNK 32
+#define KZG_T 1024
+#define KZG_PER 2  // coefficients per thread: D = 2K - 1 <= 2 KZG_T, so K <= 1024
+
+// ================================================================ setup
+// s_t = H2F(DST_SETUP, seed || "s" || t) for t < lM, beta = H2F(DST_SETUP, seed || "beta")
+__global__ void __launch_bounds__(TPB) k_trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta) {
+  uint32_t t = (uint32_t)gtid();
+  if (t > lM) return;
+  sha::Hasher h;
+  sha::xmd_begin(h);
+  for (int i = 0; i < 32; i++) h.byte(seed[i]);
+  if (t < lM) {
+    h.byte('s');
+    h.u64(t);
+    s[t] = sha::xmd_finish_fr(h, DSTR_SETUP);
+  } else {
+    h.byte('b'); h.byte('e'); h.byte('t'); h.byte('a');
+    *beta = sha::xmd_finish_fr(h, DSTR_SETUP);
+  }
+}
+
+// chunk digests of the batch statement: H_q over (a_i || enc(C_{a_i})) for 32 entries
+__global__ void __launch_bounds__(TPB) k_fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq) {
+  uint64_t id = gtid();
+  uint64_t qmax = (b + FC_CHUNK - 1) / FC_CHUNK;
+  if (id >= nb * qmax) return;
+  uint64_t k = id / qmax, q = id % qmax;
+  uint64_t lo = k * b, hi = (lo + b < K) ? lo + b : K;
+  uint64_t s = lo + q * FC_CHUNK;
+  if (s >= hi) return;
+  uint64_t e = (s + FC_CHUNK < hi) ? s + FC_CHUNK : hi;
+  sha::Hasher hs;
+  hs.init();
+  for (uint64_t a = s; a < e; a++) {
+    hs.u64(a);
+    hs.g1(Cj[a]);
+  }
+  hs.final(Hq + id * 8);
+}
+
+// sigma_k and r_i = H2F(DST_FC_R, sigma_k || i); the sparse exponent vector b = sum r_i u_{a_i}
+__global__ void __launch_bounds__(TPB) k_fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma) {
+  uint64_t k = gtid();
+  if (k >= nb) return;
+  uint64_t qmax = (b + FC_CHUNK - 1) / FC_CHUNK;
+  uint64_t lo = k * b, hi = (lo + b < K) ? lo + b : K;
+  uint64_t t = hi - lo;
+  sha::Hasher hs;
+  hs.init();
+  hs.str(DSTR_FC_R);
+  hs.gt(*C);
+  hs.u64(t);
+  for (uint64_t q = 0; q * FC_CHUNK < t; q++)
+    for (int w = 0; w < 8; w++) hs.word(Hq[(k * qmax + q) * 8 + w]);
+  hs.final(sigma + k * 8);
+}
+
+__global__ void __launch_bounds__(TPB) k_fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B) {
+  uint64_t id = gtid();
+  if (id >= nb * (uint64_t)b) return;
+  uint64_t k = id / b, i = id % b;
+  uint64_t a = k * b + i;
+  if (a >= K) return;
+  sha::Hasher hs;
+  sha::xmd_begin(hs);
+  for (int w = 0; w < 8; w++) hs.word(sigma[k * 8 + w]);
+  hs.u64(i);
+  B[k * K + a] = sha::xmd_finish_fr(hs, DSTR_FC_R);
+}
+
+// per batch: finish L_j, R_j (affine G1 parts), hash them into x_j, keep x_j and 1/x_j
+__global__ void __launch_bounds__(TPB) k_oa_transcript(const g1_jac *S, const fp12 *Lgt, const fp12 *Rgt, uint64_t K, uint64_t nb,
+                                uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, fe *X, fe *Xinv, int *err) {
+  uint64_t k = gtid();
+  if (k >= nb) return;
+  uint64_t slot = k * lK + (j - 1);
+  g1_aff l = jac_to_aff(S[(k * 2 + 0) * (K / 2)]);
+  g1_aff r = jac_to_aff(S[(k * 2 + 1) * (K / 2)]);
+  Lg1[slot] = l;
+  Rg1[slot] = r;
+  sha::Hasher hs;
+  sha::xmd_begin(hs);
+  if (j > 1) hs.field<FpR>(X[slot - 1]);
+  hs.gt(Lgt[slot]);
+  hs.g1(l);
+  hs.gt(Rgt[slot]);
+  hs.g1(r);
+  fe x = sha::xmd_finish_fr(hs, DSTR_FC_X);
+  if (fe_is_zero(x)) atomicOr(err, VC_ERRBIT_CHALLENGE);
+  X[slot] = x;
+  Xinv[slot] = fr_inv_fast(x);
+}
+
+// ---------------------------------------------------------------- KZG proof of v_l
+// f_v(X) = prod_{j=1}^{l} (1 + x_j^{-1} X^{2^{l-j+1}}): only even powers X^{2s} (s < K) occur,
+// with coefficient prod over the set bits t of s of x_{l-t}^{-1}.  z = H2F(DST_FC_Z, x_l || v_l);
+// q = (f_v - f_v(z)) / (X - z) has q_m = z^{-(m+1)} sum_{i > m} c_i z^i, computed with
+// block-wide scans.  One block of KZG_T threads per batch, D = 2K - 1 coefficients.
+__global__ void __launch_bounds__(KZG_T) k_kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K,
+                                                      uint32_t lK, fe *Q, fe *zout) {
+  extern __shared__ fe sh[];  // 2 * D elements
+  uint64_t k = blockIdx.x;
+  uint64_t D = 2 * K - 1;
+  fe *pw = sh, *acc = sh + D;
+  __shared__ fe zz, zi;
+  uint32_t t = threadIdx.x;
+  if (t == 0) {
+    sha::Hasher hs;
+    sha::xmd_begin(hs);
+    hs.field<FpR>(X[k * lK + lK - 1]);
+    hs.g2(V[k * K]);
+    zz = sha::xmd_finish_fr(hs, DSTR_FC_Z);
+    zi = fr_inv_fast(zz);
+    zout[k] = zz;
+  }
+  __syncthreads();
+  // pw[i] = z^i via inclusive product scan of (1, z, z, ...)
+  for (uint64_t i = t; i < D; i += KZG_T) pw[i] = (i == 0) ? f_one<FpR>() : zz;
+  __syncthreads();
+  for (uint64_t s = 1; s < D; s <<= 1) {
+    fe vals[KZG_PER];
+    int nv = 0;
+    for (uint64_t i = t; i < D; i += KZG_T, nv++) vals[nv] = (i >= s) ? fr_mul(pw[i], pw[i - s]) : pw[i];
+    __syncthreads();
+    nv = 0;
+    for (uint64_t i = t; i < D; i += KZG_T, nv++) pw[i] = vals[nv];
+    __syncthreads();
+  }
+  // acc[i] = c_i z^i
+  for (uint64_t i = t; i < D; i += KZG_T) {
+    fe c = fe_zero();
+    if ((i & 1) == 0) {
+      uint64_t s2 = i >> 1;
+      c = f_one<FpR>();
+      for (uint32_t bt = 0; bt < lK; bt++)
+        if ((s2 >> bt) & 1) c = fr_mul(c, Xinv[k * lK + (lK - bt) - 1]);
+    }
+    acc[i] = fr_mul(c, pw[i]);
+  }
+  __syncthreads();
+  // suffix sums acc[i] = sum_{i' >= i} c_i' z^i'
+  for (uint64_t s = 1; s < D; s <<= 1) {
+    fe vals[KZG_PER];
+    int nv = 0;
+    for (uint64_t i = t; i < D; i += KZG_T, nv++) vals[nv] = (i + s < D) ? fr_add(acc[i], acc[i + s]) : acc[i];
+    __syncthreads();
+    nv = 0;
+    for (uint64_t i = t; i < D; i += KZG_T, nv++) acc[i] = vals[nv];
+    __syncthreads();
+  }
+  // pw[i] = z^{-i}
+  for (uint64_t i = t; i < D; i += KZG_T) pw[i] = (i == 0) ? f_one<FpR>() : zi;
+  __syncthreads();
+  for (uint64_t s = 1; s < D; s <<= 1) {
+    fe vals[KZG_PER];
+    int nv = 0;
+    for (uint64_t i = t; i < D; i += KZG_T, nv++) vals[nv] = (i >= s) ? fr_mul(pw[i], pw[i - s]) : pw[i];
+    __syncthreads();
+    nv = 0;
+    for (uint64_t i = t; i < D; i += KZG_T, nv++) pw[i] = vals[nv];
+    __syncthreads();
+  }
+  // q_m = z^{-(m+1)} * acc[m+1], m < D - 1
+  for (uint64_t m = t; m + 1 < D; m += KZG_T) Q[k * (D - 1) + m] = fr_mul(pw[m + 1], acc[m + 1]);
+}
+
+// ================================================================ open-all, step 2
+// Merkle leaves SHA-256(0x00 || m_i || C_j), stored as 8 big-endian words per node;
+// node n of the heap (root = 1, leaf i = N + i) at tree[8n]
+__global__ void __launch_bounds__(TPB) k_merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree) {
+  uint64_t i = gtid();
+  if (i >= N) return;
+  uint32_t mw[8], cw[16];
+  const fe &mi = m[i];
+#pragma unroll
+  for (int q = 0; q < 8; q++) mw[q] = mi.l[7 - q];
+  const g1_aff &c = Cj[i / M];
+  fe x = f_from_mont<FpP>(c.x), y = f_from_mont<FpP>(c.y);
+#pragma unroll
+  for (int q = 0; q < 8; q++) { cw[q] = x.l[7 - q]; cw[8 + q] = y.l[7 - q]; }
+  uint32_t o[8];
+  sha::merkle_leaf(o, mw, cw);
+#pragma unroll
+  for (int q = 0; q < 8; q++) tree[(N + i) * 8 + q] = o[q];
+}
+
+// nodes [start, 2 start): node n = SHA-256(0x01 || node 2n || node 2n+1)
+__global__ void __launch_bounds__(TPB) k_merkle_level(uint32_t *tree, uint64_t start) {
+  uint64_t n = start + gtid();
+  if (n >= 2 * start) return;
+  uint32_t l[8], r[8], o[8];
+#pragma unroll
+  for (int q = 0; q < 8; q++) { l[q] = tree[16 * n + q]; r[q] = tree[16 * n + 8 + q]; }
+  sha::merkle_node(o, l, r);
+#pragma unroll
+  for (int q = 0; q < 8; q++) tree[8 * n + q] = o[q];
+}
+
+// rho_j = H2F(DST_RHO, C || root || j)
+__global__ void __launch_bounds__(TPB) k_rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *rho) {
+  uint64_t j = gtid();
+  if (j >= K) return;
+  sha::Hasher hs;
+  sha::xmd_begin(hs);
+  hs.gt(*C);
+  for (int q = 0; q < 8; q++) hs.word(tree[8 + q]);
+  hs.u64(j);
+  rho[j] = sha::xmd_finish_fr(hs, DSTR_RHO);
+}
+
+namespace kl {
+void trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta, hipStream_t st) { L1(k_trapdoor, lM + 1, seed, lM, s, beta); }
+void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st) {
+  L1(k_fc_chunks, nb * ((b + FC_CHUNK - 1) / FC_CHUNK), Cj, K, b, nb, Hq);
+}
+void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st) {
+  L1(k_fc_sigma, nb, C, K, b, nb, Hq, sigma);
+}
+void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st) { L1(k_fc_r, nb * b, K, b, nb, sigma, B); }
+void oa_transcript(const g1_jac *S, const fp12 *Lgt, const fp12 *Rgt, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK,
+                   g1_aff *Lg1, g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st) {
+  L1(k_oa_transcript, nb, S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err);
+}
+void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
+                  hipStream_t st) {
+  size_t shm = 2 * (2 * K - 1) * sizeof(fe);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void *)k_kzg_quotient, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (2 * KZG_T) * (int)sizeof(fe));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_kzg_quotient, dim3((unsigned)nb), dim3(KZG_T), shm, st, Xinv, X, V, K, lK, Q, z);
+}
+void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st) {
+  L1(k_merkle_leaves, N, m, Cj, M, N, tree);
+}
+void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st) { L1(k_merkle_level, start, tree, start); }
+void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st) { L1(k_rho, K, C, tree, K, r); }
+}  // namespace kl

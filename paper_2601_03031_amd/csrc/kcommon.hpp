@@ -1,0 +1,54 @@
+#pragma once
+// Shared prelude of the kernel translation units: layouts, launch helpers,
+// domain tags and the generic segmented-reduction kernels.
+//
+// Layouts (all device arrays, little-endian 32-bit limbs):
+//   fe        32 B  (Montgomery F_p or F_r, or a canonical F_r scalar where noted)
+//   g1_aff    64 B  x, y            (identity = zeros)
+//   g2_aff   128 B  x.c0 x.c1 y.c0 y.c1
+//   fp12     384 B  c0.c0.c0 c0.c0.c1 c0.c1.c0 ... c1.c2.c1
+//   g1_jac    96 B, g2_jac 192 B (scratch only)
+// Per-batch state of the FC openings is stored batch-major with stride K.
+#include <hip/hip_runtime.h>
+#include "field.hpp"
+#include "tower.hpp"
+#include "curve.hpp"
+#include "pairing.hpp"
+#include "hash.hpp"
+#include "kernels.h"
+
+#define TPB 128
+
+static inline unsigned nblk(uint64_t n, unsigned tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+__device__ __forceinline__ uint64_t gtid() { return (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+#define DSTR_SETUP "FLEXPROOFS-V1-SETUP"
+#define DSTR_FC_R "FLEXPROOFS-V1-FC-R"
+#define DSTR_FC_X "FLEXPROOFS-V1-FC-X"
+#define DSTR_FC_Z "FLEXPROOFS-V1-FC-Z"
+#define DSTR_RHO "FLEXPROOFS-V1-RHO"
+
+__device__ __forceinline__ void canon_scalar(uint32_t k[8], const fe &mont) {
+  fe c = f_from_mont<FpR>(mont);
+#pragma unroll
+  for (int i = 0; i < 8; i++) k[i] = c.l[i];
+}
+
+template <class O>
+__global__ void __launch_bounds__(TPB) k_jac_step(jac<O> *data, uint64_t nseg, uint64_t stride, uint64_t len, uint64_t s) {
+  uint64_t per = (len + 2 * s - 1) / (2 * s);
+  uint64_t id = gtid();
+  if (id >= nseg * per) return;
+  uint64_t g = id / per, q = id % per;
+  uint64_t a = 2 * s * q, b = a + s;
+  if (b >= len) return;
+  jac<O> *d = data + g * stride;
+  d[a] = jac_add(d[a], d[b]);
+}
+template <class O>
+__global__ void __launch_bounds__(TPB) k_jac_to_aff(const jac<O> *in, uint64_t stride, uint64_t n, aff<O> *out, uint64_t ostride) {
+  uint64_t i = gtid();
+  if (i >= n) return;
+  out[i * ostride] = jac_to_aff(in[i * stride]);
+}
+#define L1(kern, n, ...) hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(TPB), 0, st, __VA_ARGS__)

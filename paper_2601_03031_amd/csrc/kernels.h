@@ -1,0 +1,54 @@
+// Host-side declarations of the kernel launchers in kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "field.hpp"
+#include "tower.hpp"
+#include "curve.hpp"
+
+#define VC_ERRBIT_RANGE 1
+#define VC_ERRBIT_CHALLENGE 2
+
+namespace kl {
+void trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta, hipStream_t st);
+void ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n, hipStream_t st);
+void pow_table(const fe *beta, fe *out, uint64_t n, hipStream_t st);
+void g1_mul(const g1_aff *P, int bc, const fe *k, uint64_t n, g1_aff *out, hipStream_t st);
+void g2_mul(const g2_aff *P, int bc, const fe *k, uint64_t n, g2_aff *out, hipStream_t st);
+void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hipStream_t st);
+void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st);
+void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
+void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
+                hipStream_t st);
+void sum_g1(const g1_jac *data, uint64_t nseg, uint64_t len, g1_aff *out, hipStream_t st);
+void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st);
+void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out, uint64_t ostride, hipStream_t st);
+void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+void g2_reduce(g2_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st);
+void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint64_t ostride, hipStream_t st);
+void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st);
+void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st);
+void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
+void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st);
+void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st);
+void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st);
+void oa_transcript(const g1_jac *S, const fp12 *Lgt, const fp12 *Rgt, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK,
+                   g1_aff *Lg1, g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
+void oa_fold_g1(g1_aff *A, fe *B, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
+                hipStream_t st);
+void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
+void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
+                  hipStream_t st);
+void kzg_terms(const g2_aff *h, const fe *Q, uint64_t K, uint64_t nb, g2_jac *S, hipStream_t st);
+void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st);
+void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st);
+void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st);
+void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_t st);
+void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st);
+void dlevel(g1_aff *D, uint64_t K, uint32_t h, hipStream_t st);
+void hyper_terms(const fe *g, const g1_aff *ek, uint64_t M, uint32_t lM, g1_jac *S, hipStream_t st);
+void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st);
+void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st);
+}  // namespace kl

@@ -1,0 +1,560 @@
+// FlexProofs C ABI (include/vc.h): host orchestration of the HIP kernels.
+//
+// Every arithmetic step runs in kernels (kernels.hip); this file only sizes and
+// carves device buffers, orders launches on the caller's stream, and formats the
+// proof bytes (point compression is a byte-level encoding of values the device
+// already produced in canonical form).
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+#include "kernels.h"
+#include "vc.h"
+
+#define VC_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int hip_fail(hipError_t e, const char *where) {
+  snprintf(g_last_error, sizeof g_last_error, "%s: %s", where, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? VC_ENOMEM : VC_EDEVICE;
+}
+
+#define CK(x)                                         \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #x);    \
+  } while (0)
+#define CKL(where)                                    \
+  do {                                                \
+    hipError_t e_ = hipGetLastError();                \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// A bump allocator over one device allocation.
+struct Carve {
+  size_t off = 0;
+  template <class T> size_t take(uint64_t n) {
+    size_t o = off;
+    off = align_up(off + n * sizeof(T));
+    return o;
+  }
+};
+
+template <class T> T *at(void *base, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
+
+}  // namespace
+
+struct vc_params {
+  int device;
+  uint32_t L, lK, lM;
+  uint64_t N, K, M;
+  void *mem = nullptr;      // all keys in one allocation
+  g1_aff *ek, *g1gen, *g1beta, *table;
+  g2_aff *vk, *h, *g2gen;
+  void *ws = nullptr;       // grow-only scratch shared by calls on these params
+  size_t ws_size = 0;
+};
+
+struct vc_commitment {
+  const vc_params *pp;
+  void *mem = nullptr;
+  fe *m;          // N canonical entries
+  g1_aff *Cj;     // K
+  fp12 *C;        // 1
+};
+
+struct vc_proofs {
+  const vc_params *pp;
+  uint32_t b;
+  uint64_t nb;
+  void *mem = nullptr;  // the proof bundle
+  size_t o_Cj, o_C, o_Lgt, o_Rgt, o_Lg1, o_Rg1, o_X, o_Al, o_vl, o_piv, o_tree, o_rho, o_Y, o_D, o_W;
+};
+
+static int ensure_ws(vc_params *pp, size_t need) {
+  if (pp->ws_size >= need) return VC_OK;
+  if (pp->ws) CK(hipFree(pp->ws));
+  pp->ws = nullptr;
+  pp->ws_size = 0;
+  CK(hipMalloc(&pp->ws, need));
+  pp->ws_size = need;
+  return VC_OK;
+}
+
+static const uint32_t NWIN = 32;  // 8-bit windows of a 256-bit scalar
+
+VC_API uint64_t vc_proof_len(uint32_t log_n, uint32_t t) {
+  uint32_t lK = log_n / 2, lM = log_n - lK;
+  return 32ull * t + lK * (2ull * 384 + 2 * 32) + 32 + 64 + 64 + lK * 64ull + lM * 32ull + 32ull * log_n;
+}
+
+VC_API const char *vc_strerror(int code) {
+  switch (code) {
+    case VC_OK: return "ok";
+    case VC_EINVAL: return "invalid argument";
+    case VC_ENOMEM: return "device out of memory";
+    case VC_EDEVICE: return g_last_error[0] ? g_last_error : "device error";
+    case VC_ENOTIMPL: return "not implemented";
+    case VC_ECHALLENGE: return "zero Fiat-Shamir challenge";
+  }
+  return "unknown error";
+}
+
+// ------------------------------------------------------------------ setup
+VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out) {
+  if (!out || !seed || log_n < 2 || log_n > 20) return VC_EINVAL;
+  *out = nullptr;
+  CK(hipSetDevice(device));
+  vc_params *pp = new vc_params();
+  pp->device = device;
+  pp->L = log_n;
+  pp->lK = log_n / 2;
+  pp->lM = log_n - pp->lK;
+  pp->N = 1ull << log_n;
+  pp->K = 1ull << pp->lK;
+  pp->M = 1ull << pp->lM;
+  uint64_t K = pp->K, M = pp->M, lM = pp->lM;
+  Carve c;
+  size_t o_ek = c.take<g1_aff>(2 * M - 1), o_g1 = c.take<g1_aff>(1), o_g1b = c.take<g1_aff>(1);
+  size_t o_tab = c.take<g1_aff>(NWIN * M), o_vk = c.take<g2_aff>(lM), o_h = c.take<g2_aff>(2 * K - 1);
+  size_t o_g2 = c.take<g2_aff>(1);
+  hipError_t e = hipMalloc(&pp->mem, c.off);
+  if (e != hipSuccess) { delete pp; return hip_fail(e, "vc_setup alloc"); }
+  pp->ek = at<g1_aff>(pp->mem, o_ek);
+  pp->g1gen = at<g1_aff>(pp->mem, o_g1);
+  pp->g1beta = at<g1_aff>(pp->mem, o_g1b);
+  pp->table = at<g1_aff>(pp->mem, o_tab);
+  pp->vk = at<g2_aff>(pp->mem, o_vk);
+  pp->h = at<g2_aff>(pp->mem, o_h);
+  pp->g2gen = at<g2_aff>(pp->mem, o_g2);
+  g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
+  g2_aff g2 = {{fe_const(bn::G2X0), fe_const(bn::G2X1)}, {fe_const(bn::G2Y0), fe_const(bn::G2Y1)}};
+  // temporaries: seed, trapdoor, weights
+  Carve t;
+  size_t o_seed = t.take<uint8_t>(32), o_s = t.take<fe>(lM + 1), o_beta = t.take<fe>(1);
+  size_t o_w = t.take<fe>(2 * M - 1), o_pw = t.take<fe>(2 * K - 1);
+  int rc = ensure_ws(pp, t.off);
+  if (rc) { vc_params_free(pp); return rc; }
+  hipStream_t st = nullptr;
+  void *ws = pp->ws;
+  CK(hipMemcpy(pp->g1gen, &g1, sizeof g1, hipMemcpyHostToDevice));
+  CK(hipMemcpy(pp->g2gen, &g2, sizeof g2, hipMemcpyHostToDevice));
+  CK(hipMemcpy(at<uint8_t>(ws, o_seed), seed, 32, hipMemcpyHostToDevice));
+  fe *s = at<fe>(ws, o_s), *beta = at<fe>(ws, o_beta), *w = at<fe>(ws, o_w), *pw = at<fe>(ws, o_pw);
+  kl::trapdoor(at<uint8_t>(ws, o_seed), pp->lM, s, beta, st);
+  kl::ek_weights(pp->lM, s, w, 2 * M - 1, st);
+  kl::g1_mul(pp->g1gen, 1, w, 2 * M - 1, pp->ek, st);
+  kl::g2_mul(pp->g2gen, 1, s, lM, pp->vk, st);
+  kl::pow_table(beta, pw, 2 * K - 1, st);
+  kl::g2_mul(pp->g2gen, 1, pw, 2 * K - 1, pp->h, st);
+  kl::g1_mul(pp->g1gen, 1, beta, 1, pp->g1beta, st);
+  kl::msm_tables(pp->ek + (M - 1), M, NWIN, pp->table, st);
+  CKL("vc_setup launch");
+  CK(hipDeviceSynchronize());
+  *out = pp;
+  return VC_OK;
+}
+
+VC_API void vc_params_free(vc_params *pp) {
+  if (!pp) return;
+  hipSetDevice(pp->device);
+  if (pp->mem) hipFree(pp->mem);
+  if (pp->ws) hipFree(pp->ws);
+  delete pp;
+}
+
+// ------------------------------------------------------------------ commit
+VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
+                     vc_commitment **out, uint8_t C_out[384]) {
+  if (!cpp || !m_dev || !out || n != cpp->N || (entry_bits != 32 && entry_bits != 256)) return VC_EINVAL;
+  vc_params *pp = const_cast<vc_params *>(cpp);
+  *out = nullptr;
+  CK(hipSetDevice(pp->device));
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t N = pp->N, K = pp->K, M = pp->M;
+  vc_commitment *cm = new vc_commitment();
+  cm->pp = pp;
+  Carve c;
+  size_t o_m = c.take<fe>(N), o_Cj = c.take<g1_aff>(K), o_C = c.take<fp12>(1);
+  hipError_t e = hipMalloc(&cm->mem, c.off);
+  if (e != hipSuccess) { delete cm; return hip_fail(e, "vc_commit alloc"); }
+  cm->m = at<fe>(cm->mem, o_m);
+  cm->Cj = at<g1_aff>(cm->mem, o_Cj);
+  cm->C = at<fp12>(cm->mem, o_C);
+  uint32_t nwin = entry_bits == 32 ? 4 : NWIN;
+  uint32_t S = (uint32_t)(8192 / nwin);
+  if (S > M) S = (uint32_t)M;
+  uint64_t nslice = (M + S - 1) / S;
+  Carve t;
+  size_t o_err = t.take<int>(1), o_part = t.take<g1_jac>(K * nslice), o_F = t.take<fp12>(K), o_enc = t.take<uint8_t>(384);
+  int rc = ensure_ws(pp, t.off);
+  if (rc) { vc_commitment_free(cm); return rc; }
+  void *ws = pp->ws;
+  int *err = at<int>(ws, o_err);
+  CK(hipMemsetAsync(err, 0, sizeof(int), st));
+  if (entry_bits == 32) {
+    kl::lift_u32((const uint32_t *)m_dev, N, cm->m, st);
+  } else {
+    CK(hipMemcpyAsync(cm->m, m_dev, N * sizeof(fe), hipMemcpyDeviceToDevice, st));
+    kl::check_fr(cm->m, N, err, st);
+  }
+  // PC.Commit for every subvector: K MSMs of M terms over the shared Lagrange keys
+  g1_jac *part = at<g1_jac>(ws, o_part);
+  kl::msm_slices(cm->m, K, M, nwin, S, pp->table, part, st);
+  kl::sum_g1(part, K, nslice, cm->Cj, st);
+  // FC.Commit: C = prod_j e(C_j, v[j]), v[j] = h[2j]
+  fp12 *F = at<fp12>(ws, o_F);
+  kl::miller(cm->Cj, 1, pp->h, 2, K, F, st);
+  kl::f12_reduce(F, 1, K, K, st);
+  kl::final_exp(F, 1, 1, cm->C, 1, st);
+  uint8_t *enc = at<uint8_t>(ws, o_enc);
+  kl::encode(reinterpret_cast<const fe *>(cm->C), 12, 0, enc, st);
+  CKL("vc_commit launch");
+  int herr = 0;
+  CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (C_out) CK(hipMemcpyAsync(C_out, enc, 384, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (herr & VC_ERRBIT_RANGE) { vc_commitment_free(cm); return VC_EINVAL; }
+  *out = cm;
+  return VC_OK;
+}
+
+VC_API void vc_commitment_free(vc_commitment *cm) {
+  if (!cm) return;
+  hipSetDevice(cm->pp->device);
+  if (cm->mem) hipFree(cm->mem);
+  delete cm;
+}
+
+// ------------------------------------------------------------------ open-all
+VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out) {
+  if (!cpp || !cm || !out || cm->pp != cpp || b < 1 || b > cpp->K) return VC_EINVAL;
+  vc_params *pp = const_cast<vc_params *>(cpp);
+  *out = nullptr;
+  CK(hipSetDevice(pp->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t N = pp->N, K = pp->K, M = pp->M;
+  const uint32_t lK = pp->lK, lM = pp->lM;
+  const uint64_t nb = (K + b - 1) / b;
+  const uint64_t qmax = (b + 31) / 32;
+  const uint64_t nq = 2 * K - 2;  // KZG quotient length
+  // ---- the proof bundle
+  vc_proofs *pr = new vc_proofs();
+  pr->pp = pp;
+  pr->b = b;
+  pr->nb = nb;
+  Carve c;
+  pr->o_Cj = c.take<g1_aff>(K);
+  pr->o_C = c.take<fp12>(1);
+  pr->o_Lgt = c.take<fp12>(nb * lK);
+  pr->o_Rgt = c.take<fp12>(nb * lK);
+  pr->o_Lg1 = c.take<g1_aff>(nb * lK);
+  pr->o_Rg1 = c.take<g1_aff>(nb * lK);
+  pr->o_X = c.take<fe>(nb * lK);
+  pr->o_Al = c.take<g1_aff>(nb);
+  pr->o_vl = c.take<g2_aff>(nb);
+  pr->o_piv = c.take<g2_aff>(nb);
+  pr->o_tree = c.take<fe>(2 * N);
+  pr->o_rho = c.take<fe>(K);
+  pr->o_Y = c.take<fe>((2 * K - 1) * M);
+  pr->o_D = c.take<g1_aff>(2 * K - 1);
+  pr->o_W = c.take<g1_aff>(M - 1);
+  hipError_t e = hipMalloc(&pr->mem, c.off);
+  if (e != hipSuccess) { delete pr; return hip_fail(e, "vc_open_all alloc"); }
+  void *bm = pr->mem;
+  g1_aff *Cj = at<g1_aff>(bm, pr->o_Cj);
+  fp12 *C = at<fp12>(bm, pr->o_C);
+  fp12 *Lgt = at<fp12>(bm, pr->o_Lgt), *Rgt = at<fp12>(bm, pr->o_Rgt);
+  g1_aff *Lg1 = at<g1_aff>(bm, pr->o_Lg1), *Rg1 = at<g1_aff>(bm, pr->o_Rg1);
+  fe *X = at<fe>(bm, pr->o_X);
+  g1_aff *Al = at<g1_aff>(bm, pr->o_Al);
+  g2_aff *vl = at<g2_aff>(bm, pr->o_vl), *piv = at<g2_aff>(bm, pr->o_piv);
+  uint32_t *tree = at<uint32_t>(bm, pr->o_tree);
+  fe *rho = at<fe>(bm, pr->o_rho), *Y = at<fe>(bm, pr->o_Y);
+  g1_aff *D = at<g1_aff>(bm, pr->o_D), *W = at<g1_aff>(bm, pr->o_W);
+  // ---- scratch
+  Carve t;
+  size_t o_err = t.take<int>(1), o_A = t.take<g1_aff>(nb * K), o_V = t.take<g2_aff>(nb * K), o_B = t.take<fe>(nb * K);
+  size_t o_F = t.take<fp12>(nb * K), o_S = t.take<g1_jac>(nb * K), o_Hq = t.take<uint32_t>(nb * qmax * 8);
+  size_t o_sig = t.take<uint32_t>(nb * 8), o_Xi = t.take<fe>(nb * lK), o_Q = t.take<fe>(nb * nq), o_z = t.take<fe>(nb);
+  size_t o_S2 = t.take<g2_jac>(nb * nq), o_HS = t.take<g1_jac>(lM * (M / 2));
+  int rc = ensure_ws(pp, t.off);
+  if (rc) { vc_proofs_free(pr); return rc; }
+  void *ws = pp->ws;
+  int *err = at<int>(ws, o_err);
+  g1_aff *A = at<g1_aff>(ws, o_A);
+  g2_aff *V = at<g2_aff>(ws, o_V);
+  fe *B = at<fe>(ws, o_B);
+  fp12 *F = at<fp12>(ws, o_F);
+  g1_jac *S = at<g1_jac>(ws, o_S);
+  uint32_t *Hq = at<uint32_t>(ws, o_Hq), *sigma = at<uint32_t>(ws, o_sig);
+  fe *Xinv = at<fe>(ws, o_Xi), *Q = at<fe>(ws, o_Q), *z = at<fe>(ws, o_z);
+  g2_jac *S2 = at<g2_jac>(ws, o_S2);
+  g1_jac *HS = at<g1_jac>(ws, o_HS);
+
+  CK(hipMemsetAsync(err, 0, sizeof(int), st));
+  CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpyAsync(C, cm->C, sizeof(fp12), hipMemcpyDeviceToDevice, st));
+  CK(hipMemsetAsync(tree, 0, 32, st));  // heap node 0 is unused
+
+  // ---- Step 1: FC.BOpen for every block, all blocks in lockstep (Protocol 1, Eq. genFCBatchProof)
+  kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
+  kl::fc_chunks(Cj, K, b, nb, Hq, st);
+  kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
+  kl::fc_r(K, b, nb, sigma, B, st);
+  for (uint32_t j = 1; j <= lK; j++) {
+    uint64_t h = K >> j;
+    kl::oa_miller(A, V, K, nb, h, F, st);
+    kl::f12_reduce(F, 2 * nb, K / 2, h, st);
+    kl::final_exp(F, K, nb, Lgt + (j - 1), lK, st);
+    kl::final_exp(F + K / 2, K, nb, Rgt + (j - 1), lK, st);
+    kl::oa_g1terms(A, B, K, nb, h, S, st);
+    kl::g1_reduce(S, 2 * nb, K / 2, h, st);
+    kl::oa_transcript(S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
+    kl::oa_fold_g1(A, B, X, Xinv, K, nb, h, j, lK, st);
+    kl::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
+  }
+  CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
+  // faster verifier: KZG-style proof in G2 that v_l = f_v(beta) g2
+  kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, st);
+  kl::kzg_terms(pp->h, Q, K, nb, S2, st);
+  kl::g2_reduce(S2, nb, nq, nq, st);
+  kl::g2_to_aff(S2, nq, nb, piv, 1, st);
+
+  // ---- Step 2: Merkle tree (Fiat-Shamir), randomized folding tree, HyperEval on g*
+  kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
+  for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(tree, s, st);
+  kl::rho(C, tree, K, rho, st);
+  kl::ylevel0(cm->m, rho, M, N, Y, st);
+  for (uint32_t h = 1; h <= lK; h++) kl::ylevel(Y, M, K, h, st);
+  kl::g1_mul(Cj, 0, rho, K, D, st);
+  for (uint32_t h = 1; h <= lK; h++) kl::dlevel(D, K, h, st);
+  kl::hyper_terms(Y + (2 * K - 2) * M, pp->ek, M, lM, HS, st);
+  for (uint32_t d = 0; d < lM; d++) {
+    uint64_t half = M >> (d + 1);
+    g1_jac *base = HS + (uint64_t)d * (M / 2);
+    kl::g1_reduce(base, 1ull << d, half, half, st);
+    kl::g1_to_aff(base, half, 1ull << d, W + (1ull << d) - 1, 1, st);
+  }
+  CKL("vc_open_all launch");
+  int herr = 0;
+  CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (herr & VC_ERRBIT_CHALLENGE) { vc_proofs_free(pr); return VC_ECHALLENGE; }
+  *out = pr;
+  return VC_OK;
+}
+
+VC_API void vc_proofs_free(vc_proofs *pr) {
+  if (!pr) return;
+  hipSetDevice(pr->pp->device);
+  if (pr->mem) hipFree(pr->mem);
+  delete pr;
+}
+
+// ------------------------------------------------------------------ gathering / export
+namespace {
+
+// gather items (offsets in 32-byte units from base, encoding mode) as canonical BE bytes
+int gather(const void *base, const std::vector<uint64_t> &idx, const std::vector<int> &mode, std::vector<uint8_t> &outb) {
+  uint64_t n = idx.size();
+  outb.assign(n * 32, 0);
+  if (!n) return VC_OK;
+  void *d = nullptr;
+  Carve c;
+  size_t oi = c.take<uint64_t>(n), om = c.take<int>(n), oo = c.take<uint8_t>(n * 32);
+  CK(hipMalloc(&d, c.off));
+  hipError_t e = hipMemcpy(at<void>(d, oi), idx.data(), n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(at<void>(d, om), mode.data(), n * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    kl::gather_encode(static_cast<const fe *>(base), at<uint64_t>(d, oi), at<int>(d, om), n, at<uint8_t>(d, oo), nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(outb.data(), at<void>(d, oo), n * 32, hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "gather");
+  return VC_OK;
+}
+
+// contiguous run of n 32-byte items starting at byte offset off
+void push_run(std::vector<uint64_t> &idx, std::vector<int> &mode, size_t off, uint64_t n, int md) {
+  for (uint64_t q = 0; q < n; q++) {
+    idx.push_back(off / 32 + q);
+    mode.push_back(md);
+  }
+}
+
+const uint8_t P_HALF_BE[32] = {0x18, 0x32, 0x27, 0x39, 0x70, 0x98, 0xd0, 0x14, 0xdc, 0x28, 0x22, 0xdb, 0x40, 0xc0, 0xac, 0x2e,
+                               0xcb, 0xc0, 0xb5, 0x48, 0xb4, 0x38, 0xe5, 0x46, 0x9e, 0x10, 0x46, 0x0b, 0x6c, 0x3e, 0x7e, 0xa3};
+
+bool all_zero(const uint8_t *p, size_t n) {
+  for (size_t i = 0; i < n; i++)
+    if (p[i]) return false;
+  return true;
+}
+bool larger(const uint8_t *y) { return memcmp(y, P_HALF_BE, 32) > 0; }
+
+// compressed G1 from canonical x||y: x with flag bits (0x80 identity, 0x40 y > (p-1)/2)
+void compress_g1(uint8_t *o, const uint8_t *xy) {
+  if (all_zero(xy, 64)) { memset(o, 0, 32); o[0] = 0x80; return; }
+  memcpy(o, xy, 32);
+  if (larger(xy + 32)) o[0] |= 0x40;
+}
+// compressed G2 from x.c0||x.c1||y.c0||y.c1; the sign compares y.c1 first, then y.c0
+void compress_g2(uint8_t *o, const uint8_t *xy) {
+  if (all_zero(xy, 128)) { memset(o, 0, 64); o[0] = 0x80; return; }
+  memcpy(o, xy, 64);
+  bool big = all_zero(xy + 96, 32) ? larger(xy + 64) : larger(xy + 96);
+  if (big) o[0] |= 0x40;
+}
+
+}  // namespace
+
+VC_API int vc_proof_get(const vc_proofs *pr, uint64_t i, uint8_t *buf, size_t cap, size_t *len) {
+  if (!pr || !buf || !len) return VC_EINVAL;
+  const vc_params *pp = pr->pp;
+  const uint64_t N = pp->N, K = pp->K, M = pp->M;
+  const uint32_t lK = pp->lK, lM = pp->lM, L = pp->L;
+  if (i >= N) return VC_EINVAL;
+  uint64_t j = i / M, a = i % M, k = j / pr->b;
+  uint64_t lo = k * pr->b, hi = lo + pr->b < K ? lo + pr->b : K;
+  uint64_t need = vc_proof_len(L, (uint32_t)(hi - lo));
+  if (cap < need) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  std::vector<uint64_t> idx;
+  std::vector<int> mode;
+  for (uint64_t q = lo; q < hi; q++) push_run(idx, mode, pr->o_Cj + q * 64, 2, 0);
+  for (uint32_t r = 0; r < lK; r++) {
+    uint64_t s = k * lK + r;
+    push_run(idx, mode, pr->o_Lgt + s * 384, 12, 0);
+    push_run(idx, mode, pr->o_Lg1 + s * 64, 2, 0);
+    push_run(idx, mode, pr->o_Rgt + s * 384, 12, 0);
+    push_run(idx, mode, pr->o_Rg1 + s * 64, 2, 0);
+  }
+  push_run(idx, mode, pr->o_Al + k * 64, 2, 0);
+  push_run(idx, mode, pr->o_vl + k * 128, 4, 0);
+  push_run(idx, mode, pr->o_piv + k * 128, 4, 0);
+  for (uint32_t h = 0; h < lK; h++) {
+    uint64_t node = 2 * K - ((2 * K) >> h) + ((j >> h) ^ 1);
+    push_run(idx, mode, pr->o_D + node * 64, 2, 0);
+    push_run(idx, mode, pr->o_Y + (node * M + a) * 32, 1, 2);
+  }
+  for (uint32_t d = 0; d < lM; d++) push_run(idx, mode, pr->o_W + ((1ull << d) - 1 + (a >> (lM - d))) * 64, 2, 0);
+  for (uint32_t h = 0; h < L; h++) push_run(idx, mode, pr->o_tree + (((N + i) >> h) ^ 1) * 32, 1, 3);
+  std::vector<uint8_t> g;
+  int rc = gather(pr->mem, idx, mode, g);
+  if (rc) return rc;
+  const uint8_t *s = g.data();
+  uint8_t *q = buf;
+  for (uint64_t t = lo; t < hi; t++, s += 64, q += 32) compress_g1(q, s);
+  for (uint32_t r = 0; r < lK; r++) {
+    memcpy(q, s, 384); q += 384; s += 384;
+    compress_g1(q, s); q += 32; s += 64;
+    memcpy(q, s, 384); q += 384; s += 384;
+    compress_g1(q, s); q += 32; s += 64;
+  }
+  compress_g1(q, s); q += 32; s += 64;
+  compress_g2(q, s); q += 64; s += 128;
+  compress_g2(q, s); q += 64; s += 128;
+  for (uint32_t h = 0; h < lK; h++) {
+    compress_g1(q, s); q += 32; s += 64;
+    memcpy(q, s, 32); q += 32; s += 32;
+  }
+  for (uint32_t d = 0; d < lM; d++) { compress_g1(q, s); q += 32; s += 64; }
+  memcpy(q, s, 32ull * L);
+  q += 32ull * L;
+  *len = (size_t)(q - buf);
+  return *len == need ? VC_OK : VC_EDEVICE;
+}
+
+static int export_items(const void *base, const std::vector<uint64_t> &idx, const std::vector<int> &mode, void *dst,
+                        size_t cap, size_t *len) {
+  size_t need = idx.size() * 32;
+  if (len) *len = need;
+  if (!dst || cap < need) return VC_EINVAL;
+  std::vector<uint8_t> g;
+  int rc = gather(base, idx, mode, g);
+  if (rc) return rc;
+  memcpy(dst, g.data(), need);
+  return VC_OK;
+}
+
+VC_API int vc_params_export(const vc_params *pp, int what, uint32_t idx_, void *dst, size_t cap, size_t *len) {
+  if (!pp) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  std::vector<uint64_t> idx;
+  std::vector<int> mode;
+  size_t base = 0;
+  auto off = [&](const void *p) { return (size_t)(static_cast<const char *>(p) - static_cast<const char *>(pp->mem)); };
+  switch (what) {
+    case 0:
+      if (idx_ > pp->lM) return VC_EINVAL;
+      base = off(pp->ek + ((1ull << idx_) - 1));
+      push_run(idx, mode, base, 2ull << idx_, 0);
+      break;
+    case 1: push_run(idx, mode, off(pp->vk), 4ull * pp->lM, 0); break;
+    case 2: push_run(idx, mode, off(pp->h), 4 * (2 * pp->K - 1), 0); break;
+    case 3: push_run(idx, mode, off(pp->g1beta), 2, 0); break;
+    default: return VC_EINVAL;
+  }
+  return export_items(pp->mem, idx, mode, dst, cap, len);
+}
+
+VC_API int vc_commitment_export(const vc_commitment *cm, int what, void *dst, size_t cap, size_t *len) {
+  if (!cm) return VC_EINVAL;
+  CK(hipSetDevice(cm->pp->device));
+  std::vector<uint64_t> idx;
+  std::vector<int> mode;
+  auto off = [&](const void *p) { return (size_t)(static_cast<const char *>(p) - static_cast<const char *>(cm->mem)); };
+  if (what == 0) push_run(idx, mode, off(cm->Cj), 2 * cm->pp->K, 0);
+  else if (what == 1) push_run(idx, mode, off(cm->C), 12, 0);
+  else return VC_EINVAL;
+  return export_items(cm->mem, idx, mode, dst, cap, len);
+}
+
+VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst, size_t cap, size_t *len) {
+  if (!pr) return VC_EINVAL;
+  const vc_params *pp = pr->pp;
+  const uint64_t N = pp->N, K = pp->K, M = pp->M;
+  const uint32_t lK = pp->lK;
+  CK(hipSetDevice(pp->device));
+  if (what <= 2 && k >= pr->nb) return VC_EINVAL;
+  std::vector<uint64_t> idx;
+  std::vector<int> mode;
+  switch (what) {
+    case 0:
+      for (uint32_t r = 0; r < lK; r++) {
+        uint64_t s = k * lK + r;
+        push_run(idx, mode, pr->o_Lgt + s * 384, 12, 0);
+        push_run(idx, mode, pr->o_Lg1 + s * 64, 2, 0);
+        push_run(idx, mode, pr->o_Rgt + s * 384, 12, 0);
+        push_run(idx, mode, pr->o_Rg1 + s * 64, 2, 0);
+      }
+      break;
+    case 1:
+      push_run(idx, mode, pr->o_Al + k * 64, 2, 0);
+      push_run(idx, mode, pr->o_vl + k * 128, 4, 0);
+      push_run(idx, mode, pr->o_piv + k * 128, 4, 0);
+      break;
+    case 2: push_run(idx, mode, pr->o_X + k * lK * 32, lK, 1); break;
+    case 3: push_run(idx, mode, pr->o_tree, 2 * N, 3); break;
+    case 4: push_run(idx, mode, pr->o_rho, K, 1); break;
+    case 5: push_run(idx, mode, pr->o_Y, (2 * K - 1) * M, 2); break;
+    case 6: push_run(idx, mode, pr->o_D, 2 * (2 * K - 1), 0); break;
+    case 7: push_run(idx, mode, pr->o_W, 2 * (M - 1), 0); break;
+    default: return VC_EINVAL;
+  }
+  return export_items(pr->mem, idx, mode, dst, cap, len);
+}
+
+VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint32_t b, uint64_t i, const uint8_t m_i[32],
+                     const uint8_t *proof, size_t len) {
+  (void)pp; (void)C; (void)n; (void)b; (void)i; (void)m_i; (void)proof; (void)len;
+  return VC_ENOTIMPL;
+}
