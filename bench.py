@@ -1,0 +1,196 @@
+"""FlexProofs commit + OpenAll on one MI355X: benchmark.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extra]
+
+A step is one pass of the whole hot path over one seeded synthetic vector:
+VC.Commit (PST commitments of the K subvectors, FC commitment) and VC.OpenAll
+(all ceil(K/b) FC batch proofs, the Merkle tree, the randomized folding tree and
+HyperEval on g*).  The workload is N = 2^16 with b = log^2 N = 256 and uniform
+32-bit entries (the paper's headline all-proofs configuration); `value` is the
+median all-N-proofs (OpenAll) time in ms.  The N = 2^20, b = 400 full-width
+workload and the commitment MSM rate are reported under "extra".
+
+Per-kernel durations come from HIP events recorded by the library on its launch
+stream during the timed steps; the roofline object is for the kernel with the
+largest share of the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "all-N-proofs time (ms) at N=2^16,b=log²N and N=2^20; MSM points/s"
+PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32x32->64 multiply-adds, one per lane per clock: 39.32 TOP/s
+PEAK_HBM_GBS = 8000.0
+MADS_PER_FMUL = 136                        # 8x32-bit CIOS: 64 + 64 products + 8 reduction words
+
+
+def op_costs():
+    """Field multiplications per operation of the GPU path's formulas (host build count)."""
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_2601_03031_amd", "lib", "libvc_hostcheck.so"))
+    L.hc_count.restype = ctypes.c_uint64
+    names = ["miller", "final_exp", "g1_mul", "g2_mul", "g1_add", "g1_madd", "g2_add", "g2_madd",
+             "g1_dbl", "g2_dbl", "f12_mul", "g1_to_aff", "g2_to_aff"]
+    return {n: int(L.hc_count(i)) for i, n in enumerate(names)}
+
+
+def work_model(L, b, limbs, costs):
+    """Algorithmic field multiplications per kernel over one step (commit + open-all)."""
+    import numpy as np
+    lK, lM = L // 2, L - L // 2
+    K, M, N = 1 << lK, 1 << lM, 1 << L
+    nb = (K + b - 1) // b
+    rounds = [K >> j for j in range(1, lK + 1)]
+    nz_digits = int(np.count_nonzero(np.ascontiguousarray(limbs).view(np.uint8)))
+    S = min(M, 8192 // (4 if int(limbs[:, 1:].max()) == 0 else 32))
+    blocks = K * ((M + S - 1) // S)
+    w = {
+        "k_msm_slices": nz_digits * costs["g1_madd"] + blocks * 2048 * costs["g1_add"],
+        "k_miller": K * costs["miller"],
+        "k_oa_miller": sum(nb * 2 * h for h in rounds) * costs["miller"],
+        "k_final_exp": (2 * lK * nb + 1) * costs["final_exp"],
+        "k_oa_fold_g2": sum(nb * h for h in rounds) * (costs["g2_mul"] + costs["g2_madd"] + costs["g2_to_aff"]),
+        "k_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
+        "k_kzg_terms": nb * (2 * K - 2) * costs["g2_mul"],
+        "k_hyper_terms": lM * (M // 2) * costs["g1_mul"],
+    }
+    return w
+
+
+def hbm_model(L):
+    lK, lM = L // 2, L - L // 2
+    K, M, N = 1 << lK, 1 << lM, 1 << L
+    return {"k_ylevel0": 64 * N + 32 * K, "k_ylevel": sum(3 * (K >> h) * M * 32 for h in range(1, lK + 1))}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile=True):
+    import numpy as np
+    log("workload L=%d b=%d bits=%d seed=%d: setup" % (L, b, bits, seed))
+    from paper_2601_03031_amd import inputs as I
+    limbs = I.entries(1 << L, seed, bits)
+    if bits == 32:
+        m = torch.from_numpy(limbs[:, 0].astype(np.uint32).view(np.int32).copy()).cuda()
+    else:
+        m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+    pp = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        cm = V.vc_commit(pp, m, bits, stream)
+        pr = V.vc_open_all(pp, cm, b, stream)
+        del pr, cm
+    torch.cuda.synchronize()
+    log("warmup done; timing %d steps" % steps)
+    commit_ms, open_ms = [], []
+    if profile:
+        V.vc_profile_enable(True)
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        cm = V.vc_commit(pp, m, bits, stream)
+        t1 = time.perf_counter()
+        pr = V.vc_open_all(pp, cm, b, stream)
+        t2 = time.perf_counter()
+        commit_ms.append(1e3 * (t1 - t0))
+        open_ms.append(1e3 * (t2 - t1))
+        del pr, cm
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_all
+    prof = V.vc_profile_read() if profile else {}
+    V.vc_profile_enable(False)
+    return limbs, commit_ms, open_ms, prof, wall
+
+
+def cpu_baseline(L, b, bits, seed):
+    import oracle as O
+    log("cpu baseline (oracle) L=%d b=%d" % (L, b))
+    from paper_2601_03031_amd import inputs as I
+    limbs = I.entries(1 << L, seed, bits)
+    threads = O.max_threads()
+    pp = O.Params(L, I.TRAPDOOR_SEED)
+    t0 = time.perf_counter()
+    cm = O.Commitment(pp, I.limbs_to_bytes(limbs))
+    t1 = time.perf_counter()
+    op = O.Opening(cm, b)
+    t2 = time.perf_counter()
+    del op, cm, pp
+    return {"value": round(1e3 * (t2 - t1), 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": "the full N=2^%d, b=%d, %d-bit-entry workload: oracle OpenAll (all-N-proofs) time; "
+                      "oracle commit took %.1f ms" % (L, b, bits, 1e3 * (t1 - t0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the single-GPU path is the build's scope "
+              "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2601_03031_amd as V
+    V.lib()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    L, b, bits, seed = 16, 256, 32, 2
+    limbs, commit_ms, open_ms, prof, wall = run_workload(V, torch, L, b, bits, seed, a.steps, a.warmup)
+    costs = op_costs()
+    work = work_model(L, b, limbs, costs)
+    total_prof = sum(ms for _, ms in prof.values())
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    dname, (dcount, dms) = dom
+    roofline = None
+    if dname in work:
+        per_launch_fmul = work[dname] / (dcount / a.steps)
+        avg_s = dms / dcount / 1e3
+        achieved = per_launch_fmul * MADS_PER_FMUL / avg_s / 1e12
+        roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 4), "peak": round(PEAK_MAD_TOPS, 2),
+                    "unit": "TOP/s", "frac": round(achieved / PEAK_MAD_TOPS, 5), "traffic": None,
+                    "per_launch_field_mults": int(per_launch_fmul), "avg_launch_ms": round(dms / dcount, 4)}
+    kernels = {k: {"launches": c // a.steps, "ms_per_step": round(ms / a.steps, 4),
+                   "share": round(ms / total_prof, 4) if total_prof else None}
+               for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    msm_ms = (prof.get("k_msm_slices", (0, 0))[1] + prof.get("k_sum_g1", (0, 0))[1]) / a.steps
+    extra = {"commit_ms": round(statistics.median(commit_ms), 3),
+             "open_ms_all": [round(x, 3) for x in open_ms],
+             "open_ms_mean": round(statistics.mean(open_ms), 3),
+             "msm_points_per_s": round((1 << L) / (msm_ms / 1e3)) if msm_ms else None,
+             "kernels": kernels}
+    if not a.no_extra:
+        L2, b2 = 20, 400
+        _, c2, o2, p2, _ = run_workload(V, torch, L2, b2, 256, 3, max(1, min(a.steps, 2)), 1)
+        msm2 = (p2.get("k_msm_slices", (0, 0))[1] + p2.get("k_sum_g1", (0, 0))[1]) / max(1, min(a.steps, 2))
+        extra["n2^20_b400"] = {"all_proofs_ms": round(statistics.median(o2), 3), "commit_ms": round(statistics.median(c2), 3),
+                               "msm_points_per_s": round((1 << L2) / (msm2 / 1e3)) if msm2 else None}
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(L, b, bits, seed)
+    line = {"metric": METRIC, "value": round(statistics.median(open_ms), 3), "unit": "ms", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": round(statistics.median([c + o for c, o in zip(commit_ms, open_ms)]), 3),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "data": "synthetic", "config": {"workload": "N=2^16 commit + open-all, b=log^2 N=256, uniform 32-bit entries "
+                                            "(seed 2), BN254", "N": 1 << L, "b": b, "entry_bits": bits},
+            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

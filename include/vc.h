@@ -89,6 +89,14 @@ int vc_params_export(const vc_params *pp, int what, uint32_t idx, void *dst, siz
 int vc_commitment_export(const vc_commitment *cm, int what, void *dst, size_t cap, size_t *len);
 int vc_proofs_export(const vc_proofs *pr, int what, uint64_t idx, void *dst, size_t cap, size_t *len);
 
+/* Per-kernel timing for measurement: while enabled, every kernel launch of the
+ * library is bracketed by HIP events recorded on its own stream.
+ * vc_profile_read writes one line per kernel, "<name> <launches> <total_ms>\n", into
+ * buf (NUL-terminated, truncated to cap) and returns the size needed.
+ * vc_profile_enable(1) also clears previous records.  Not thread-safe. */
+void vc_profile_enable(int on);
+int vc_profile_read(char *buf, size_t cap);
+
 void vc_params_free(vc_params *pp);
 void vc_commitment_free(vc_commitment *cm);
 void vc_proofs_free(vc_proofs *pr);

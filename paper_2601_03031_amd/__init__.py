@@ -46,6 +46,8 @@ def lib():
         L.vc_proofs_export.argtypes = [vp, C.c_int, u64, vp, sz, C.POINTER(sz)]
         for f in ("vc_params_free", "vc_commitment_free", "vc_proofs_free"):
             getattr(L, f).argtypes = [vp]
+        L.vc_profile_enable.argtypes = [C.c_int]
+        L.vc_profile_read.argtypes = [C.c_char_p, sz]
         L.vc_strerror.restype = C.c_char_p
         L.vc_strerror.argtypes = [C.c_int]
         _lib = L
@@ -165,3 +167,19 @@ def vc_proof_get(pr: Proofs, i: int) -> bytes:
 def vc_verify(pp: Params, C_bytes: bytes, b: int, i: int, m_i: int, proof: bytes) -> int:
     return _check(lib().vc_verify(pp.ptr, C_bytes, pp.N, b, i, int(m_i).to_bytes(32, "little"), proof, len(proof)),
                   "vc_verify")
+
+
+def vc_profile_enable(on: bool = True) -> None:
+    lib().vc_profile_enable(1 if on else 0)
+
+
+def vc_profile_read() -> dict:
+    """{kernel name: (launches, total_ms)} for launches since vc_profile_enable(True)."""
+    n = lib().vc_profile_read(None, 0)
+    buf = C.create_string_buffer(n)
+    lib().vc_profile_read(buf, n)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.rsplit(" ", 2)
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -69,7 +69,7 @@ def build(incremental: bool = False, verbose: bool = False, jobs: int = 8) -> st
     link = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     subprocess.run(link, check=True, capture_output=not verbose)
     os.replace(LIB + ".tmp", LIB)
-    hc = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden", "-I" + CSRC,
+    hc = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden", "-DVC_COUNT_MULS", "-I" + CSRC,
           "-o", HOSTCHECK + ".tmp", os.path.join(CSRC, "hostcheck.cpp")]
     subprocess.run(hc, check=True)
     os.replace(HOSTCHECK + ".tmp", HOSTCHECK)

@@ -25,6 +25,17 @@ struct fe {
   uint32_t l[8];
 };
 
+// Host builds may count field multiplications (to state per-operation work exactly).
+#if !defined(__HIP_DEVICE_COMPILE__) && defined(VC_COUNT_MULS)
+inline uint64_t &fmul_counter() {
+  static thread_local uint64_t c = 0;
+  return c;
+}
+#define COUNT_FMUL() (fmul_counter()++)
+#else
+#define COUNT_FMUL()
+#endif
+
 struct FpP {
   static constexpr const uint32_t *M = bn::P_MOD;
   static constexpr uint32_t INV = bn::P_INV;
@@ -141,6 +152,7 @@ template <class F> DEV fe f_half(const fe &a) {
 
 // Montgomery product a b R^{-1} mod m (CIOS, one reduction word per operand word)
 template <class F> DEV fe f_mul(const fe &a, const fe &b) {
+  COUNT_FMUL();
   uint32_t t[10];
 #pragma unroll
   for (int j = 0; j < 10; j++) t[j] = 0;

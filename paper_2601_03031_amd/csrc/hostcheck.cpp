@@ -185,3 +185,52 @@ API void hc_merkle_node(const uint8_t l[32], const uint8_t r[32], uint8_t out[32
   sha::merkle_node(o, lw, rw);
   for (int i = 0; i < 8; i++) { out[4 * i] = o[i] >> 24; out[4 * i + 1] = o[i] >> 16; out[4 * i + 2] = o[i] >> 8; out[4 * i + 3] = o[i]; }
 }
+
+#ifdef VC_COUNT_MULS
+// Field multiplications (F_p or F_r, Montgomery) performed by one operation of the
+// GPU path's formulas: 0 Miller loop, 1 final exponentiation, 2 G1 scalar mul
+// (254-bit scalar), 3 G2 scalar mul, 4 G1 add, 5 G1 mixed add, 6 G2 add, 7 G2 mixed
+// add, 8 G1 doubling, 9 G2 doubling, 10 F_p12 mul, 11 Jacobian->affine G1 (excluding
+// the binary-GCD inversion), 12 Jacobian->affine G2.
+API uint64_t hc_count(int op) {
+  uint8_t gb1[64], gb2[128];
+  g1_aff G1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
+  g2_aff G2 = {{fe_const(bn::G2X0), fe_const(bn::G2X1)}, {fe_const(bn::G2Y0), fe_const(bn::G2Y1)}};
+  (void)gb1; (void)gb2;
+  uint32_t k[8] = {0x9e3779b9u, 0x7f4a7c15u, 0xf39cc060u, 0x5cedc834u, 0x1082276bu, 0xf3a27251u, 0xbe8e7a8bu, 0x2a9d0c3fu};
+  g1_jac P1 = jac_dbl(jac_from_aff(G1));
+  g2_jac P2 = jac_dbl(jac_from_aff(G2));
+  g1_aff A1 = jac_to_aff(P1);
+  g2_aff A2 = jac_to_aff(P2);
+  fp12 f = miller_loop(G1, G2);
+  uint64_t &c = fmul_counter();
+  c = 0;
+  switch (op) {
+    case 0: (void)miller_loop(A1, A2); break;
+    case 1: (void)f12_final_exp(f); break;
+    case 2: (void)scalar_mul(G1, k); break;
+    case 3: (void)scalar_mul(G2, k); break;
+    case 4: (void)jac_add(P1, jac_dbl(P1)); break;
+    case 5: (void)jac_madd(jac_dbl(P1), G1); break;
+    case 6: (void)jac_add(P2, jac_dbl(P2)); break;
+    case 7: (void)jac_madd(jac_dbl(P2), G2); break;
+    case 8: (void)jac_dbl(P1); break;
+    case 9: (void)jac_dbl(P2); break;
+    case 10: (void)f12_mul(f, f); break;
+    case 11: (void)jac_to_aff(P1); break;
+    case 12: (void)jac_to_aff(P2); break;
+    default: return 0;
+  }
+  uint64_t n = c;
+  // subtract the set-up work done inside the measured expression
+  c = 0;
+  switch (op) {
+    case 4: (void)jac_dbl(P1); break;
+    case 5: (void)jac_dbl(P1); break;
+    case 6: (void)jac_dbl(P2); break;
+    case 7: (void)jac_dbl(P2); break;
+    default: break;
+  }
+  return n - c;
+}
+#endif

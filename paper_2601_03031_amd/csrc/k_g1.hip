@@ -267,7 +267,7 @@ void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st) { L1(k_check_fr
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st) {
   uint64_t nslice = (M + S - 1) / S;
-  hipLaunchKernelGGL(k_msm_slices, dim3((unsigned)(K * nslice)), dim3(256), 0, st, scal, M, nwin, S, table, partial);
+  LAUNCH(k_msm_slices, dim3((unsigned)(K * nslice)), dim3(256), 0, scal, M, nwin, S, table, partial);
 }
 void sum_g1(const g1_jac *data, uint64_t nseg, uint64_t len, g1_aff *out, hipStream_t st) { L1(k_sum_g1, nseg, data, nseg, len, out); }
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {

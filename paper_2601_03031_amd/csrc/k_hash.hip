@@ -233,7 +233,7 @@ void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint
     (void)hipFuncSetAttribute((const void *)k_kzg_quotient, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (2 * KZG_T) * (int)sizeof(fe));
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_kzg_quotient, dim3((unsigned)nb), dim3(KZG_T), shm, st, Xinv, X, V, K, lK, Q, z);
+  LAUNCH(k_kzg_quotient, dim3((unsigned)nb), dim3(KZG_T), shm, Xinv, X, V, K, lK, Q, z);
 }
 void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st) {
   L1(k_merkle_leaves, N, m, Cj, M, N, tree);

@@ -51,4 +51,17 @@ __global__ void __launch_bounds__(TPB) k_jac_to_aff(const jac<O> *in, uint64_t s
   if (i >= n) return;
   out[i * ostride] = jac_to_aff(in[i * stride]);
 }
-#define L1(kern, n, ...) hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(TPB), 0, st, __VA_ARGS__)
+// optional per-kernel timing (HIP events on the launch stream), enabled through vc_profile_enable
+namespace prof {
+void begin(const char *name, hipStream_t st);
+void end(hipStream_t st);
+void name_last(const char *name);
+}
+#define LAUNCH(kern, grid, block, shm, ...)                                 \
+  do {                                                                     \
+    prof::begin(#kern, st);                                                \
+    hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);           \
+    prof::end(st);                                                         \
+    prof::name_last(#kern);                                                \
+  } while (0)
+#define L1(kern, n, ...) LAUNCH(kern, dim3(nblk(n)), dim3(TPB), 0, __VA_ARGS__)

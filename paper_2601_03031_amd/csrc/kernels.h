@@ -23,7 +23,8 @@ void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t 
 void sum_g1(const g1_jac *data, uint64_t nseg, uint64_t len, g1_aff *out, hipStream_t st);
 void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st);
 void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
-void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out, uint64_t ostride, hipStream_t st);
+// input s at in[s*stride]; output to (s odd ? out1 : out0)[(s >> 1) * ostride]
+void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void g2_reduce(g2_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st);

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 #include "kernels.h"
 #include "vc.h"
@@ -48,6 +49,36 @@ struct Carve {
 template <class T> T *at(void *base, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
 
 }  // namespace
+
+// ------------------------------------------------------------------ profiling hooks
+namespace {
+struct ProfRec {
+  const char *name;
+  hipEvent_t e0, e1;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_prof_recs;
+hipEvent_t g_prof_open = nullptr;
+}  // namespace
+
+namespace prof {
+void begin(const char *, hipStream_t st) {
+  if (!g_prof) return;
+  if (hipEventCreate(&g_prof_open) != hipSuccess) { g_prof_open = nullptr; return; }
+  (void)hipEventRecord(g_prof_open, st);
+}
+void end(hipStream_t st) {
+  if (!g_prof || !g_prof_open) return;
+  hipEvent_t e1;
+  if (hipEventCreate(&e1) != hipSuccess) return;
+  (void)hipEventRecord(e1, st);
+  g_prof_recs.push_back({nullptr, g_prof_open, e1});
+  g_prof_open = nullptr;
+}
+void name_last(const char *name) {
+  if (g_prof && !g_prof_recs.empty() && !g_prof_recs.back().name) g_prof_recs.back().name = name;
+}
+}  // namespace prof
 
 struct vc_params {
   int device;
@@ -211,7 +242,7 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   fp12 *F = at<fp12>(ws, o_F);
   kl::miller(cm->Cj, 1, pp->h, 2, K, F, st);
   kl::f12_reduce(F, 1, K, K, st);
-  kl::final_exp(F, 1, 1, cm->C, 1, st);
+  kl::final_exp(F, 1, 1, cm->C, nullptr, 1, st);
   uint8_t *enc = at<uint8_t>(ws, o_enc);
   kl::encode(reinterpret_cast<const fe *>(cm->C), 12, 0, enc, st);
   CKL("vc_commit launch");
@@ -311,8 +342,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     uint64_t h = K >> j;
     kl::oa_miller(A, V, K, nb, h, F, st);
     kl::f12_reduce(F, 2 * nb, K / 2, h, st);
-    kl::final_exp(F, K, nb, Lgt + (j - 1), lK, st);
-    kl::final_exp(F + K / 2, K, nb, Rgt + (j - 1), lK, st);
+    kl::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);  // segment 2k+side
     kl::oa_g1terms(A, B, K, nb, h, S, st);
     kl::g1_reduce(S, 2 * nb, K / 2, h, st);
     kl::oa_transcript(S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
@@ -557,4 +587,38 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
                      const uint8_t *proof, size_t len) {
   (void)pp; (void)C; (void)n; (void)b; (void)i; (void)m_i; (void)proof; (void)len;
   return VC_ENOTIMPL;
+}
+
+// ------------------------------------------------------------------ profiling C ABI
+VC_API void vc_profile_enable(int on) {
+  for (auto &r : g_prof_recs) { hipEventDestroy(r.e0); hipEventDestroy(r.e1); }
+  g_prof_recs.clear();
+  g_prof = on != 0;
+}
+
+// one line per kernel: "<name> <launches> <total_ms>\n"; returns bytes needed
+VC_API int vc_profile_read(char *buf, size_t cap) {
+  struct Agg { std::string name; uint64_t n; double ms; };
+  std::vector<Agg> agg;
+  for (auto &r : g_prof_recs) {
+    float ms = 0;
+    if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) continue;
+    std::string nm = r.name ? r.name : "?";
+    bool found = false;
+    for (auto &a : agg)
+      if (a.name == nm) { a.n++; a.ms += ms; found = true; break; }
+    if (!found) agg.push_back({nm, 1, ms});
+  }
+  std::string out;
+  char line[256];
+  for (auto &a : agg) {
+    snprintf(line, sizeof line, "%s %llu %.6f\n", a.name.c_str(), (unsigned long long)a.n, a.ms);
+    out += line;
+  }
+  if (buf && cap > 0) {
+    size_t n = out.size() < cap - 1 ? out.size() : cap - 1;
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return (int)out.size() + 1;
 }
