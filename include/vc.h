@@ -97,6 +97,12 @@ int vc_proofs_export(const vc_proofs *pr, int what, uint64_t idx, void *dst, siz
 void vc_profile_enable(int on);
 int vc_profile_read(char *buf, size_t cap);
 
+/* Self-test of the device field layer used by the proof rounds (8 lanes per
+ * element): one operation on n pairs of canonical 32-byte little-endian host inputs,
+ * results to out (n x 32 B).  op: 0 mul, 1 add, 2 sub, 3 halve, 4 inverse, 5 square;
+ * which: 0 = F_p, 1 = F_r.  Inputs must be < the modulus. */
+int vc_diag_field(int which, int op, uint64_t n, const void *a, const void *b, void *out);
+
 void vc_params_free(vc_params *pp);
 void vc_commitment_free(vc_commitment *cm);
 void vc_proofs_free(vc_proofs *pr);

@@ -21,21 +21,6 @@
 // large routines are kept out of line so every kernel does not carry its own copy
 #define NOINL __host__ __device__ __attribute__((noinline))
 
-struct fe {
-  uint32_t l[8];
-};
-
-// Host builds may count field multiplications (to state per-operation work exactly).
-#if !defined(__HIP_DEVICE_COMPILE__) && defined(VC_COUNT_MULS)
-inline uint64_t &fmul_counter() {
-  static thread_local uint64_t c = 0;
-  return c;
-}
-#define COUNT_FMUL() (fmul_counter()++)
-#else
-#define COUNT_FMUL()
-#endif
-
 struct FpP {
   static constexpr const uint32_t *M = bn::P_MOD;
   static constexpr uint32_t INV = bn::P_INV;
@@ -50,6 +35,24 @@ struct FpR {
   static constexpr const uint32_t *R2 = bn::R_R2;
   static constexpr const uint32_t *MINUS2 = bn::R_MINUS_2;
 };
+
+#ifdef VC_WIDE
+#include "field_wide.hpp"
+#else
+struct fe {
+  uint32_t l[8];
+};
+
+// Host builds may count field multiplications (to state per-operation work exactly).
+#if !defined(__HIP_DEVICE_COMPILE__) && defined(VC_COUNT_MULS)
+inline uint64_t &fmul_counter() {
+  static thread_local uint64_t c = 0;
+  return c;
+}
+#define COUNT_FMUL() (fmul_counter()++)
+#else
+#define COUNT_FMUL()
+#endif
 
 DEV fe fe_zero() {
   fe o;
@@ -240,18 +243,8 @@ DEV bool fe_lt_mod(const fe &a, const uint32_t *m) {
   return bw != 0;
 }
 
-#define fp_add f_add<FpP>
-#define fp_sub f_sub<FpP>
-#define fp_neg f_neg<FpP>
-#define fp_dbl f_dbl<FpP>
-#define fp_mul f_mul<FpP>
-#define fp_sqr f_sqr<FpP>
-#define fp_half f_half<FpP>
-#define fp_inv f_inv<FpP>
-#define fr_add f_add<FpR>
-#define fr_sub f_sub<FpR>
-#define fr_mul f_mul<FpR>
-#define fr_inv f_inv<FpR>
+DEV uint32_t fe_word(const fe &a, int i) { return a.l[i]; }
+DEV fe fe_from_words(const uint32_t *w) { return fe_const(w); }
 
 // Inverse by the binary extended Euclidean algorithm (variable time; the inputs
 // here are public).  Input and output in Montgomery form: the integer inverse of
@@ -291,5 +284,20 @@ template <class F> NOINL fe f_inv_binary(const fe &A, const uint32_t *R3) {
   fe r = is_one(u) ? x1 : x2;
   return f_mul<F>(r, fe_const(R3));
 }
+#endif  // VC_WIDE
+
+#define fp_add f_add<FpP>
+#define fp_sub f_sub<FpP>
+#define fp_neg f_neg<FpP>
+#define fp_dbl f_dbl<FpP>
+#define fp_mul f_mul<FpP>
+#define fp_sqr f_sqr<FpP>
+#define fp_half f_half<FpP>
+#define fp_inv f_inv<FpP>
+#define fr_add f_add<FpR>
+#define fr_sub f_sub<FpR>
+#define fr_mul f_mul<FpR>
+#define fr_inv f_inv<FpR>
+
 #define fp_inv_fast(a) f_inv_binary<FpP>(a, bn::P_R3)
 #define fr_inv_fast(a) f_inv_binary<FpR>(a, bn::R_R3)

@@ -110,7 +110,7 @@ struct Hasher {
   // canonical big-endian encoding of a Montgomery-form element
   template <class F> HD void field(const fe &a) {
     fe c = f_from_mont<F>(a);
-    for (int i = 7; i >= 0; i--) word(c.l[i]);
+    for (int i = 7; i >= 0; i--) word(fe_word(c, i));
   }
   HD void g1(const g1_aff &p) { field<FpP>(p.x); field<FpP>(p.y); }
   HD void g2(const g2_aff &p) {
@@ -169,10 +169,11 @@ inline NOINL fe xmd_finish_fr(Hasher &hs, const char *dst) {
   h2.byte((uint32_t)dlen);
   h2.final(b2);
   // uniform = b1 || b2[0..16): hi = b1 words 0..3, lo = b1 words 4..7 || b2 words 0..3
-  fe hi = fe_zero(), lo;
-  for (int i = 0; i < 4; i++) hi.l[i] = b1[3 - i];
-  for (int i = 0; i < 4; i++) lo.l[i] = b2[3 - i];
-  for (int i = 0; i < 4; i++) lo.l[4 + i] = b1[7 - i];
+  uint32_t hw[8], lw[8];
+  for (int i = 0; i < 4; i++) { hw[i] = b1[3 - i]; hw[4 + i] = 0; }
+  for (int i = 0; i < 4; i++) lw[i] = b2[3 - i];
+  for (int i = 0; i < 4; i++) lw[4 + i] = b1[7 - i];
+  fe hi = fe_from_words(hw), lo = fe_from_words(lw);
   // (hi 2^256 + lo) R mod r = mont(hi, R^3) + mont(lo, R^2)
   return fr_add(fr_mul(hi, fe_const(bn::R_R3)), fr_mul(lo, fe_const(bn::R_R2)));
 }

@@ -1,0 +1,296 @@
+// Kernels in the wide layout (field_wide.hpp): 8 lanes per field element, so one
+// 64-lane block serves 8 independent Miller loops, scalar multiplications or point
+// sums.  These are the dependent-chain kernels of the proof rounds, whose count of
+// independent items per launch is far below the lane count of the chip.
+//
+// Memory layouts are the same as everywhere else (32-byte little-endian field
+// elements, points as consecutive elements): lane g of a group loads limb g.
+#define VC_WIDE 1
+#include <hip/hip_runtime.h>
+#include "field.hpp"
+#include "tower.hpp"
+#include "curve.hpp"
+#include "pairing.hpp"
+#include "kernels.h"
+
+#define TPBW 64
+#define GPB (TPBW / 8)  // groups (elements) per block
+
+namespace prof {
+void begin(const char *name, hipStream_t st);
+void end(hipStream_t st);
+void name_last(const char *name);
+}  // namespace prof
+
+static inline unsigned nblkw(uint64_t n) { return (unsigned)((n + GPB - 1) / GPB); }
+__device__ __forceinline__ uint64_t wgid() { return (uint64_t)blockIdx.x * GPB + (threadIdx.x >> 3); }
+
+// element idx of a type made of n field elements, lane g taking limb g of each
+template <class T> __device__ __forceinline__ T wld(const void *base, uint64_t idx) {
+  constexpr int n = sizeof(T) / 4;
+  T r;
+  uint32_t *rv = reinterpret_cast<uint32_t *>(&r);
+  const uint32_t *src = static_cast<const uint32_t *>(base) + idx * (uint64_t)n * 8 + wg();
+#pragma unroll
+  for (int k = 0; k < n; k++) rv[k] = src[k * 8];
+  return r;
+}
+template <class T> __device__ __forceinline__ void wst(void *base, uint64_t idx, const T &v) {
+  constexpr int n = sizeof(T) / 4;
+  const uint32_t *rv = reinterpret_cast<const uint32_t *>(&v);
+  uint32_t *dst = static_cast<uint32_t *>(base) + idx * (uint64_t)n * 8 + wg();
+#pragma unroll
+  for (int k = 0; k < n; k++) dst[k * 8] = rv[k];
+}
+
+// canonical limbs of a scalar (every lane of the group gets all 8)
+__device__ __forceinline__ void wunpack(uint32_t k[8], const fe &c) {
+  k[0] = wbcast<0>(c.v); k[1] = wbcast<1>(c.v); k[2] = wbcast<2>(c.v); k[3] = wbcast<3>(c.v);
+  k[4] = wbcast<4>(c.v); k[5] = wbcast<5>(c.v); k[6] = wbcast<6>(c.v); k[7] = wbcast<7>(c.v);
+}
+__device__ __forceinline__ void wscalar(uint32_t k[8], const fe &mont) { wunpack(k, f_from_mont<FpR>(mont)); }
+__device__ __forceinline__ bool scalar_is_zero(const uint32_t k[8]) {
+  uint32_t t = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) t |= k[i];
+  return t == 0;
+}
+
+// ---------------------------------------------------------------- pairings
+__global__ void __launch_bounds__(TPBW) kw_miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n,
+                                                 void *out) {
+  uint64_t i = wgid();
+  if (i >= n) return;
+  wst(out, i, miller_loop(wld<g1_aff>(P, i * sp), wld<g2_aff>(Q, i * sq)));
+}
+
+// side 0 (L) pairs A[h+i] with V[i], side 1 (R) A[i] with V[h+i]; F[(2k+side) K/2 + i]
+__global__ void __launch_bounds__(TPBW) kw_oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h,
+                                                    void *F) {
+  uint64_t id = wgid();
+  if (id >= nb * 2 * h) return;
+  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
+  g1_aff P = wld<g1_aff>(A, side ? k * K + i : k * K + h + i);
+  g2_aff Q = wld<g2_aff>(V, side ? k * K + h + i : k * K + i);
+  wst(F, (k * 2 + side) * (K / 2) + i, miller_loop(P, Q));
+}
+
+// ---------------------------------------------------------------- scalar multiplications
+template <class O>
+__global__ void __launch_bounds__(TPBW) kw_mul(const void *P, int broadcast, const void *k, uint64_t n, void *out) {
+  uint64_t i = wgid();
+  if (i >= n) return;
+  uint32_t kk[8];
+  wscalar(kk, wld<fe>(k, i));
+  wst(out, i, jac_to_aff(scalar_mul(wld<aff<O>>(P, broadcast ? 0 : i), kk)));
+}
+
+// terms of <A_R, b_L> (side 0) and <A_L, b_R> (side 1), Jacobian
+__global__ void __launch_bounds__(TPBW) kw_oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h,
+                                                     void *S) {
+  uint64_t id = wgid();
+  if (id >= nb * 2 * h) return;
+  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
+  fe c = wld<fe>(B, side ? k * K + h + i : k * K + i);
+  g1_jac out = jac_inf<OpsG1>();
+  if (!fe_is_zero(c)) {
+    uint32_t kk[8];
+    wscalar(kk, c);
+    out = scalar_mul(wld<g1_aff>(A, side ? k * K + i : k * K + h + i), kk);
+  }
+  wst(S, (k * 2 + side) * (K / 2) + i, out);
+}
+
+// A_j = A_L o A_R^{x_j}, b_j = b_L + b_R / x_j
+__global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(void *A, void *B, const void *X, const void *Xinv, uint64_t K,
+                                                     uint64_t nb, uint64_t h, uint32_t j, uint32_t lK) {
+  uint64_t id = wgid();
+  if (id >= nb * h) return;
+  uint64_t k = id / h, i = id % h, slot = k * lK + (j - 1);
+  uint32_t kk[8];
+  wscalar(kk, wld<fe>(X, slot));
+  g1_jac t = scalar_mul(wld<g1_aff>(A, k * K + h + i), kk);
+  wst(A, k * K + i, jac_to_aff(jac_madd(t, wld<g1_aff>(A, k * K + i))));
+  fe bl = wld<fe>(B, k * K + i), br = wld<fe>(B, k * K + h + i);
+  wst(B, k * K + i, fr_add(bl, fr_mul(br, wld<fe>(Xinv, slot))));
+}
+
+// v_j = v_L o v_R^{1/x_j}
+__global__ void __launch_bounds__(TPBW) kw_oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h,
+                                                     uint32_t j, uint32_t lK) {
+  uint64_t id = wgid();
+  if (id >= nb * h) return;
+  uint64_t k = id / h, i = id % h;
+  uint32_t kk[8];
+  wscalar(kk, wld<fe>(Xinv, k * lK + (j - 1)));
+  g2_jac t = scalar_mul(wld<g2_aff>(V, k * K + h + i), kk);
+  wst(V, k * K + i, jac_to_aff(jac_madd(t, wld<g2_aff>(V, k * K + i))));
+}
+
+// terms q_m h_m of the KZG proof of v_l
+__global__ void __launch_bounds__(TPBW) kw_kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S) {
+  uint64_t n = 2 * K - 2;
+  uint64_t id = wgid();
+  if (id >= nb * n) return;
+  uint32_t kk[8];
+  wscalar(kk, wld<fe>(Q, id));
+  wst(S, id, scalar_mul(wld<g2_aff>(h, id % n), kk));
+}
+
+// HyperEval terms (canonical differences of the folded table times PST keys)
+__global__ void __launch_bounds__(TPBW) kw_hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S) {
+  uint64_t id = wgid();
+  uint64_t per = M / 2;
+  if (id >= lM * per) return;
+  uint32_t d = (uint32_t)(id / per);
+  uint64_t r = id % per;
+  uint32_t k = lM - d;
+  uint64_t half = 1ull << (k - 1);
+  uint64_t p = r / half, c = r % half;
+  fe q = fr_sub(wld<fe>(g, p * (2 * half) + half + c), wld<fe>(g, p * (2 * half) + c));
+  g1_jac out = jac_inf<OpsG1>();
+  if (!fe_is_zero(q)) {
+    uint32_t kk[8];
+    wunpack(kk, q);
+    out = scalar_mul(wld<g1_aff>(ek, (1ull << (k - 1)) - 1 + c), kk);
+  }
+  wst(S, id, out);
+}
+
+// ---------------------------------------------------------------- sums
+template <class O>
+__global__ void __launch_bounds__(TPBW) kw_jac_step(void *data, uint64_t nseg, uint64_t stride, uint64_t len, uint64_t s) {
+  uint64_t per = (len + 2 * s - 1) / (2 * s);
+  uint64_t id = wgid();
+  if (id >= nseg * per) return;
+  uint64_t g = id / per, q = id % per;
+  uint64_t a = 2 * s * q, b = a + s;
+  if (b >= len) return;
+  jac<O> x = wld<jac<O>>(data, g * stride + a), y = wld<jac<O>>(data, g * stride + b);
+  wst(data, g * stride + a, jac_add(x, y));
+}
+
+template <class O>
+__global__ void __launch_bounds__(TPBW) kw_jac_to_aff(const void *in, uint64_t stride, uint64_t n, void *out,
+                                                     uint64_t ostride) {
+  uint64_t i = wgid();
+  if (i >= n) return;
+  wst(out, i * ostride, jac_to_aff(wld<jac<O>>(in, i * stride)));
+}
+
+// out[s] = affine(sum_{q < len} data[s len + q])
+__global__ void __launch_bounds__(TPBW) kw_sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out) {
+  uint64_t s = wgid();
+  if (s >= nseg) return;
+  g1_jac acc = wld<g1_jac>(data, s * len);
+  for (uint64_t q = 1; q < len; q++) acc = jac_add(acc, wld<g1_jac>(data, s * len + q));
+  wst(out, s, jac_to_aff(acc));
+}
+
+__global__ void __launch_bounds__(TPBW) kw_dlevel(void *D, uint64_t K, uint32_t h) {
+  uint64_t w = wgid();
+  if (w >= (K >> h)) return;
+  uint64_t off = 2 * K - ((2 * K) >> h), offc = 2 * K - ((2 * K) >> (h - 1));
+  g1_aff l = wld<g1_aff>(D, offc + 2 * w), r = wld<g1_aff>(D, offc + 2 * w + 1);
+  wst(D, off + w, jac_to_aff(jac_madd(jac_from_aff(l), r)));
+}
+
+
+// ---------------------------------------------------------------- diagnostics
+// field operation on canonical inputs (limbs), for the layout self-test:
+// op 0 mul, 1 add, 2 sub, 3 half, 4 inverse, 5 square; F_p if which == 0 else F_r
+__global__ void __launch_bounds__(TPBW) kw_diag_field(int which, int op, const void *a, const void *b, uint64_t n,
+                                                     void *out) {
+  uint64_t i = wgid();
+  if (i >= n) return;
+  fe x = wld<fe>(a, i), y = wld<fe>(b, i), r;
+  if (which == 0) {
+    x = f_to_mont<FpP>(x);
+    y = f_to_mont<FpP>(y);
+    switch (op) {
+      case 0: r = fp_mul(x, y); break;
+      case 1: r = fp_add(x, y); break;
+      case 2: r = fp_sub(x, y); break;
+      case 3: r = fp_half(x); break;
+      case 4: r = fp_inv(x); break;
+      default: r = fp_sqr(x); break;
+    }
+    r = f_from_mont<FpP>(r);
+  } else {
+    x = f_to_mont<FpR>(x);
+    y = f_to_mont<FpR>(y);
+    switch (op) {
+      case 0: r = fr_mul(x, y); break;
+      case 1: r = fr_add(x, y); break;
+      case 2: r = fr_sub(x, y); break;
+      case 3: r = f_half<FpR>(x); break;
+      case 4: r = fr_inv(x); break;
+      default: r = f_sqr<FpR>(x); break;
+    }
+    r = f_from_mont<FpR>(r);
+  }
+  wst(out, i, r);
+}
+
+// ---------------------------------------------------------------- launchers
+namespace klw {
+#define LW(kern, n, ...)                                                                     \
+  do {                                                                                       \
+    prof::begin(#kern, st);                                                                  \
+    hipLaunchKernelGGL(kern, dim3(nblkw(n)), dim3(TPBW), 0, st, __VA_ARGS__);                \
+    prof::end(st);                                                                           \
+    prof::name_last(#kern);                                                                  \
+  } while (0)
+
+void miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n, void *out, hipStream_t st) {
+  if (n) LW(kw_miller, n, P, sp, Q, sq, n, out);
+}
+void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st) {
+  LW(kw_oa_miller, nb * 2 * h, A, V, K, nb, h, F);
+}
+void g1_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st) {
+  if (n) LW(kw_mul<OpsG1>, n, P, bc, k, n, out);
+}
+void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st) {
+  if (n) LW(kw_mul<OpsG2>, n, P, bc, k, n, out);
+}
+void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st) {
+  LW(kw_oa_g1terms, nb * 2 * h, A, B, K, nb, h, S);
+}
+void oa_fold_g1(void *A, void *B, const void *X, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+                uint32_t lK, hipStream_t st) {
+  LW(kw_oa_fold_g1, nb * h, A, B, X, Xinv, K, nb, h, j, lK);
+}
+void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
+  LW(kw_oa_fold_g2, nb * h, V, Xinv, K, nb, h, j, lK);
+}
+void kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S, hipStream_t st) {
+  LW(kw_kzg_terms, nb * (2 * K - 2), h, Q, K, nb, S);
+}
+void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st) {
+  LW(kw_hyper_terms, lM * (M / 2), g, ek, M, lM, S);
+}
+void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
+  for (uint64_t s = 1; s < len; s <<= 1) {
+    uint64_t per = (len + 2 * s - 1) / (2 * s);
+    LW(kw_jac_step<OpsG1>, nseg * per, data, nseg, stride, len, s);
+  }
+}
+void g2_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
+  for (uint64_t s = 1; s < len; s <<= 1) {
+    uint64_t per = (len + 2 * s - 1) / (2 * s);
+    LW(kw_jac_step<OpsG2>, nseg * per, data, nseg, stride, len, s);
+  }
+}
+void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st) {
+  LW(kw_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);
+}
+void g2_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st) {
+  LW(kw_jac_to_aff<OpsG2>, n, in, stride, n, out, ostride);
+}
+void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st) { LW(kw_sum_g1, nseg, data, nseg, len, out); }
+void dlevel(void *D, uint64_t K, uint32_t h, hipStream_t st) { LW(kw_dlevel, K >> h, D, K, h); }
+void diag_field(int which, int op, const void *a, const void *b, uint64_t n, void *out, hipStream_t st) {
+  LW(kw_diag_field, n, which, op, a, b, n, out);
+}
+}  // namespace klw

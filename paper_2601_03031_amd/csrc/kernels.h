@@ -53,3 +53,25 @@ void hyper_terms(const fe *g, const g1_aff *ek, uint64_t M, uint32_t lM, g1_jac 
 void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st);
 void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st);
 }  // namespace kl
+
+// Wide-layout kernels (k_wide.hip, 8 lanes per field element); same memory layouts
+// as above, passed untyped because the register types differ in that unit.
+namespace klw {
+void miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n, void *out, hipStream_t st);
+void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st);
+void g1_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
+void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
+void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st);
+void oa_fold_g1(void *A, void *B, const void *X, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+                uint32_t lK, hipStream_t st);
+void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
+void kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S, hipStream_t st);
+void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st);
+void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+void g2_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st);
+void g2_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st);
+void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st);
+void dlevel(void *D, uint64_t K, uint32_t h, hipStream_t st);
+void diag_field(int which, int op, const void *a, const void *b, uint64_t n, void *out, hipStream_t st);
+}  // namespace klw

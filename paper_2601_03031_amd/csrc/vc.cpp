@@ -179,11 +179,11 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   fe *s = at<fe>(ws, o_s), *beta = at<fe>(ws, o_beta), *w = at<fe>(ws, o_w), *pw = at<fe>(ws, o_pw);
   kl::trapdoor(at<uint8_t>(ws, o_seed), pp->lM, s, beta, st);
   kl::ek_weights(pp->lM, s, w, 2 * M - 1, st);
-  kl::g1_mul(pp->g1gen, 1, w, 2 * M - 1, pp->ek, st);
-  kl::g2_mul(pp->g2gen, 1, s, lM, pp->vk, st);
+  klw::g1_mul(pp->g1gen, 1, w, 2 * M - 1, pp->ek, st);
+  klw::g2_mul(pp->g2gen, 1, s, lM, pp->vk, st);
   kl::pow_table(beta, pw, 2 * K - 1, st);
-  kl::g2_mul(pp->g2gen, 1, pw, 2 * K - 1, pp->h, st);
-  kl::g1_mul(pp->g1gen, 1, beta, 1, pp->g1beta, st);
+  klw::g2_mul(pp->g2gen, 1, pw, 2 * K - 1, pp->h, st);
+  klw::g1_mul(pp->g1gen, 1, beta, 1, pp->g1beta, st);
   kl::msm_tables(pp->ek + (M - 1), M, NWIN, pp->table, st);
   CKL("vc_setup launch");
   CK(hipDeviceSynchronize());
@@ -237,10 +237,10 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   // PC.Commit for every subvector: K MSMs of M terms over the shared Lagrange keys
   g1_jac *part = at<g1_jac>(ws, o_part);
   kl::msm_slices(cm->m, K, M, nwin, S, pp->table, part, st);
-  kl::sum_g1(part, K, nslice, cm->Cj, st);
+  klw::sum_g1(part, K, nslice, cm->Cj, st);
   // FC.Commit: C = prod_j e(C_j, v[j]), v[j] = h[2j]
   fp12 *F = at<fp12>(ws, o_F);
-  kl::miller(cm->Cj, 1, pp->h, 2, K, F, st);
+  klw::miller(cm->Cj, 1, pp->h, 2, K, F, st);
   kl::f12_reduce(F, 1, K, K, st);
   kl::final_exp(F, 1, 1, cm->C, nullptr, 1, st);
   uint8_t *enc = at<uint8_t>(ws, o_enc);
@@ -340,22 +340,22 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   kl::fc_r(K, b, nb, sigma, B, st);
   for (uint32_t j = 1; j <= lK; j++) {
     uint64_t h = K >> j;
-    kl::oa_miller(A, V, K, nb, h, F, st);
+    klw::oa_miller(A, V, K, nb, h, F, st);
     kl::f12_reduce(F, 2 * nb, K / 2, h, st);
     kl::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);  // segment 2k+side
-    kl::oa_g1terms(A, B, K, nb, h, S, st);
-    kl::g1_reduce(S, 2 * nb, K / 2, h, st);
+    klw::oa_g1terms(A, B, K, nb, h, S, st);
+    klw::g1_reduce(S, 2 * nb, K / 2, h, st);
     kl::oa_transcript(S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
-    kl::oa_fold_g1(A, B, X, Xinv, K, nb, h, j, lK, st);
-    kl::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
+    klw::oa_fold_g1(A, B, X, Xinv, K, nb, h, j, lK, st);
+    klw::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
   }
   CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
   CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
   // faster verifier: KZG-style proof in G2 that v_l = f_v(beta) g2
   kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, st);
-  kl::kzg_terms(pp->h, Q, K, nb, S2, st);
-  kl::g2_reduce(S2, nb, nq, nq, st);
-  kl::g2_to_aff(S2, nq, nb, piv, 1, st);
+  klw::kzg_terms(pp->h, Q, K, nb, S2, st);
+  klw::g2_reduce(S2, nb, nq, nq, st);
+  klw::g2_to_aff(S2, nq, nb, piv, 1, st);
 
   // ---- Step 2: Merkle tree (Fiat-Shamir), randomized folding tree, HyperEval on g*
   kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
@@ -363,14 +363,14 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   kl::rho(C, tree, K, rho, st);
   kl::ylevel0(cm->m, rho, M, N, Y, st);
   for (uint32_t h = 1; h <= lK; h++) kl::ylevel(Y, M, K, h, st);
-  kl::g1_mul(Cj, 0, rho, K, D, st);
-  for (uint32_t h = 1; h <= lK; h++) kl::dlevel(D, K, h, st);
-  kl::hyper_terms(Y + (2 * K - 2) * M, pp->ek, M, lM, HS, st);
+  klw::g1_mul(Cj, 0, rho, K, D, st);
+  for (uint32_t h = 1; h <= lK; h++) klw::dlevel(D, K, h, st);
+  klw::hyper_terms(Y + (2 * K - 2) * M, pp->ek, M, lM, HS, st);
   for (uint32_t d = 0; d < lM; d++) {
     uint64_t half = M >> (d + 1);
     g1_jac *base = HS + (uint64_t)d * (M / 2);
-    kl::g1_reduce(base, 1ull << d, half, half, st);
-    kl::g1_to_aff(base, half, 1ull << d, W + (1ull << d) - 1, 1, st);
+    klw::g1_reduce(base, 1ull << d, half, half, st);
+    klw::g1_to_aff(base, half, 1ull << d, W + (1ull << d) - 1, 1, st);
   }
   CKL("vc_open_all launch");
   int herr = 0;
@@ -621,4 +621,24 @@ VC_API int vc_profile_read(char *buf, size_t cap) {
     buf[n] = 0;
   }
   return (int)out.size() + 1;
+}
+
+// ------------------------------------------------------------------ diagnostics
+// Runs one base-field operation on n pairs of canonical 32-byte little-endian inputs
+// (host buffers) in the 8-lanes-per-element layout: op 0 mul, 1 add, 2 sub, 3 half,
+// 4 inverse, 5 square; which 0 = F_p, 1 = F_r.
+VC_API int vc_diag_field(int which, int op, uint64_t n, const void *a, const void *b, void *out) {
+  if (!a || !b || !out || n == 0) return VC_EINVAL;
+  void *d = nullptr;
+  CK(hipMalloc(&d, 3 * n * 32));
+  hipError_t e = hipMemcpy(d, a, n * 32, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(static_cast<char *>(d) + n * 32, b, n * 32, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    klw::diag_field(which, op, d, static_cast<char *>(d) + n * 32, n, static_cast<char *>(d) + 2 * n * 32, nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, static_cast<char *>(d) + 2 * n * 32, n * 32, hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "vc_diag_field");
+  return VC_OK;
 }
