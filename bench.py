@@ -54,13 +54,14 @@ def work_model(L, b, limbs, costs):
     blocks = K * ((M + S - 1) // S)
     w = {
         "k_msm_slices": nz_digits * costs["g1_madd"] + blocks * 2048 * costs["g1_add"],
-        "k_miller": K * costs["miller"],
-        "k_oa_miller": sum(nb * 2 * h for h in rounds) * costs["miller"],
-        "k_final_exp": (2 * lK * nb + 1) * costs["final_exp"],
-        "k_oa_fold_g2": sum(nb * h for h in rounds) * (costs["g2_mul"] + costs["g2_madd"] + costs["g2_to_aff"]),
-        "k_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
-        "k_kzg_terms": nb * (2 * K - 2) * costs["g2_mul"],
-        "k_hyper_terms": lM * (M // 2) * costs["g1_mul"],
+        "kw_miller": K * costs["miller"],
+        "kw_oa_miller": sum(nb * 2 * h for h in rounds) * costs["miller"],
+        "k_final_exp_wave": (2 * lK * nb + 1) * costs["final_exp"],
+        "kw_oa_fold_g2": sum(nb * h for h in rounds) * (costs["g2_mul"] + costs["g2_madd"] + costs["g2_to_aff"]),
+        "kw_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
+        "kw_oa_g1terms": sum(nb * 2 * h for h in rounds) * costs["g1_mul"],
+        "kw_kzg_terms": nb * (2 * K - 2) * costs["g2_mul"],
+        "kw_hyper_terms": lM * (M // 2) * costs["g1_mul"],
     }
     return w
 

@@ -69,11 +69,18 @@ def build(incremental: bool = False, verbose: bool = False, jobs: int = 8) -> st
     link = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     subprocess.run(link, check=True, capture_output=not verbose)
     os.replace(LIB + ".tmp", LIB)
+    build_hostcheck()
+    return LIB
+
+
+def build_hostcheck() -> str:
+    """Host (g++) build of the device arithmetic headers, with field-multiplication counters."""
+    os.makedirs(LIBDIR, exist_ok=True)
     hc = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden", "-DVC_COUNT_MULS", "-I" + CSRC,
           "-o", HOSTCHECK + ".tmp", os.path.join(CSRC, "hostcheck.cpp")]
     subprocess.run(hc, check=True)
     os.replace(HOSTCHECK + ".tmp", HOSTCHECK)
-    return LIB
+    return HOSTCHECK
 
 
 if __name__ == "__main__":

@@ -21,7 +21,6 @@ void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st);
 void sum_g1(const g1_jac *data, uint64_t nseg, uint64_t len, g1_aff *out, hipStream_t st);
-void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st);
 void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 // input s at in[s*stride]; output to (s odd ? out1 : out0)[(s >> 1) * ostride]
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
@@ -33,7 +32,6 @@ void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff 
 void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st);
 void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
 void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st);
-void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st);
 void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st);
 void oa_transcript(const g1_jac *S, const fp12 *Lgt, const fp12 *Rgt, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK,
                    g1_aff *Lg1, g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);

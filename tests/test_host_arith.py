@@ -1,0 +1,163 @@
+"""The library's field, tower, curve, pairing and hash formulas, compiled for the host
+(lib/libvc_hostcheck.so: the same headers the gfx950 kernels use, one lane per
+element), checked against the CPU oracle on seeded random inputs.  This runs without
+a GPU and catches formula mistakes before any kernel is launched."""
+import ctypes as C
+import hashlib
+import os
+import random
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HC_PATH = os.path.join(ROOT, "paper_2601_03031_amd", "lib", "libvc_hostcheck.so")
+P, R = O.P, O.R
+
+
+@pytest.fixture(scope="module")
+def hc():
+    if not os.path.exists(HC_PATH):
+        from paper_2601_03031_amd import build as B
+        B.build_hostcheck()
+    L = C.CDLL(HC_PATH)
+    L.hc_h2f.argtypes = [C.c_char_p, C.c_char_p, C.c_uint64, C.c_void_p]
+    L.hc_sha256.argtypes = [C.c_char_p, C.c_uint64, C.c_void_p]
+    L.hc_count.restype = C.c_uint64
+    return L
+
+
+def buf(n):
+    return C.create_string_buffer(n)
+
+
+@pytest.mark.parametrize("which,mod", [(0, P), (1, R)])
+def test_field_ops(hc, which, mod):
+    rng = random.Random(100 + which)
+    vals = [0, 1, 2, mod - 1, mod - 2, (mod + 1) // 2] + [rng.randrange(mod) for _ in range(150)]
+    for a in vals:
+        b = rng.randrange(mod)
+        want = {0: (a + b) % mod, 1: (a - b) % mod, 2: a * b % mod, 5: a * pow(2, -1, mod) % mod}
+        if a:
+            want[3] = want[4] = pow(a, -1, mod)
+        for op, w in want.items():
+            o = buf(32)
+            assert hc.hc_field(which, op, O.be32(a), O.be32(b), o) == 0
+            assert int.from_bytes(o.raw, "big") == w, (which, op, a, b)
+
+
+def test_fp2_ops(hc):
+    rng = random.Random(7)
+    for _ in range(40):
+        a = (rng.randrange(P), rng.randrange(P))
+        b = (rng.randrange(P), rng.randrange(P))
+        want = {0: O.fp2_op("mul", a, b), 1: O.fp2_op("mul", a, a), 2: O.fp2_op("inv", a),
+                3: O.fp2_op("mul", a, (9, 1))}  # xi = 9 + i
+        for op, w in want.items():
+            o = buf(64)
+            assert hc.hc_fp2(op, O.be32(a[0]) + O.be32(a[1]), O.be32(b[0]) + O.be32(b[1]), o) == 0
+            assert (int.from_bytes(o.raw[:32], "big"), int.from_bytes(o.raw[32:], "big")) == w, oop
+
+
+def rand12(rng):
+    return b"".join(O.be32(rng.randrange(P)) for _ in range(12))
+
+
+def frob(f):
+    """f^p by generic powers: p = (r - 1) + 1 + 6u^2, each exponent below r"""
+    u = 0x44E992B44A6909F1
+    t = O.fp12_op("mul", O.fp12_op("pow", f, O.be32(R - 1)), f)
+    return O.fp12_op("mul", t, O.fp12_op("pow", f, O.be32(6 * u * u)))
+
+
+def test_fp12_ops(hc):
+    rng = random.Random(8)
+    for _ in range(4):
+        f, g = rand12(rng), rand12(rng)
+        f1 = frob(f)
+        f2 = frob(f1)
+        want = {0: O.fp12_op("mul", f, g), 2: O.fp12_op("inv", f), 4: f1, 5: f2, 6: frob(f2)}
+        for op, w in want.items():
+            o = buf(384)
+            assert hc.hc_fp12(op, f, g, o) == 0
+            assert o.raw == w, op
+        o = buf(384)
+        hc.hc_fp12(1, f, g, o)
+        assert o.raw == O.fp12_op("mul", f, f)
+    f = rand12(rng)
+    o = buf(384)
+    hc.hc_fp12(3, f, f, o)
+    assert o.raw == O.fp12_op("final_exp", f)
+
+
+def test_cyclotomic_ops(hc):
+    """Granger-Scott squaring and f^u agree with generic arithmetic on cyclotomic elements."""
+    rng = random.Random(9)
+    g = O.fp12_op("final_exp", rand12(rng))  # an element of order r lies in the cyclotomic subgroup
+    o = buf(384)
+    hc.hc_fp12(7, g, g, o)
+    assert o.raw == O.fp12_op("mul", g, g)
+    o = buf(384)
+    hc.hc_fp12(8, g, g, o)
+    u = 0x44E992B44A6909F1
+    assert o.raw == O.fp12_op("pow", g, O.be32(u))
+
+
+def test_group_ops(hc):
+    rng = random.Random(10)
+    g1, g2 = O.generators()
+    for _ in range(4):
+        k = rng.randrange(R)
+        o = buf(64)
+        hc.hc_g1(2, g1, O.be32(k), o)
+        assert o.raw == O.g1_op("mul", g1, O.be32(k))
+        o = buf(128)
+        hc.hc_g2(2, g2, O.be32(k), o)
+        assert o.raw == O.g2_op("mul", g2, O.be32(k))
+    A, B = O.g1_op("mul", g1, O.be32(5)), O.g1_op("mul", g1, O.be32(7))
+    A2, B2 = O.g2_op("mul", g2, O.be32(5)), O.g2_op("mul", g2, O.be32(7))
+    for op in (0, 3):
+        for X, Y in ((A, B), (A, A), (A, O.g1_op("neg", A))):
+            o = buf(64)
+            hc.hc_g1(op, X, Y, o)
+            assert o.raw == O.g1_op("add", X, Y)
+        for X, Y in ((A2, B2), (A2, A2), (A2, O.g2_op("neg", A2))):
+            o = buf(128)
+            hc.hc_g2(op, X, Y, o)
+            assert o.raw == O.g2_op("add", X, Y)
+    o = buf(64)
+    hc.hc_g1(1, A, A, o)
+    assert o.raw == O.g1_op("add", A, A)
+    o = buf(128)
+    hc.hc_g2(4, A2, A2, o)
+    assert o.raw == O.g2_op("frobenius", A2)
+
+
+def test_pairing(hc):
+    g1, g2 = O.generators()
+    A = O.g1_op("mul", g1, O.be32(1234567))
+    B = O.g2_op("mul", g2, O.be32(7654321))
+    o = buf(384)
+    hc.hc_pairing(A, B, o)
+    assert o.raw == O.pairing([A], [B])
+
+
+def test_hashes(hc):
+    rng = random.Random(11)
+    for n in (0, 1, 3, 55, 56, 63, 64, 65, 200, 1000):
+        msg = bytes(rng.randrange(256) for _ in range(n))
+        o = buf(32)
+        hc.hc_sha256(msg, len(msg), o)
+        assert o.raw == hashlib.sha256(msg).digest()
+        for dst in ("FLEXPROOFS-V1-FC-X", "FLEXPROOFS-V1-RHO"):
+            o = buf(32)
+            hc.hc_h2f(dst.encode(), msg, len(msg), o)
+            assert int.from_bytes(o.raw, "big") == O.hash_to_fr(dst, msg)
+    m, c = bytes(range(32)), bytes(range(64, 128))
+    o = buf(32)
+    hc.hc_merkle_leaf(m, c, o)
+    assert o.raw == hashlib.sha256(b"\x00" + m + c).digest()
+    o = buf(32)
+    hc.hc_merkle_node(m, c[:32], o)
+    assert o.raw == hashlib.sha256(b"\x01" + m + c[:32]).digest()
