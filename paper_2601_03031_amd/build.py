@@ -24,7 +24,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(LIBDIR, "libvc.so")
 HOSTCHECK = os.path.join(LIBDIR, "libvc_hostcheck.so")
 
-UNITS = ["k_pair.hip", "k_wide.hip", "k_g1.hip", "k_g2.hip", "k_hash.hip", "vc.cpp"]
+UNITS = ["k_slp.hip", "k_pair.hip", "k_wide.hip", "k_g1.hip", "k_g2.hip", "k_hash.hip", "vc.cpp"]
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I" + INCLUDE, "-I" + CSRC]
 
@@ -57,9 +57,23 @@ def _compile(unit: str, incremental: bool, verbose: bool):
     return unit, time.time() - t0, " ".join(cmd) if verbose else ""
 
 
+def generate() -> None:
+    """Write the generated headers: curve constants and the engine's programs."""
+    for script, out in (("gen_constants.py", "constants.hpp"), ("gen_slp.py", "slp_progs.hpp")):
+        dst = os.path.join(CSRC, out)
+        src = os.path.join(CSRC, script)
+        if os.path.exists(dst) and os.path.getmtime(dst) >= os.path.getmtime(src):
+            continue
+        text = subprocess.run([sys.executable, src], capture_output=True, text=True, check=True).stdout
+        with open(dst + ".tmp", "w") as f:
+            f.write(text)
+        os.replace(dst + ".tmp", dst)
+
+
 def build(incremental: bool = False, verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
+    generate()
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         results = list(ex.map(lambda u: _compile(u, incremental, verbose), UNITS))
     for unit, dt, cmd in results:

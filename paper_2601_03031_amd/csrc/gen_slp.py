@@ -1,0 +1,1245 @@
+"""Generate slp_progs.hpp: straight-line programs (SLPs) over F_p for the
+wave-cooperative engine in slp.hpp.
+
+A program is a dataflow graph of base-field operations, produced by running the
+formulas of the BN254 tower, the twist and the pairing on tracer values.  The
+scheduler packs it into levels of at most 64 independent operations; one wavefront
+executes a level per step, lane t doing the t-th operation of the level.
+Operations:
+  MUL  dst = a * b                                  (Montgomery product)
+  LIN  dst = ka * a + sb * b + sc * c  (mod p)      ka in [-15, 15], sb, sc in {-1, 0, 1}
+Linear combinations are kept symbolic by the tracer and materialised only where a
+product or an output needs them, so chains of additions fuse into few LIN operations.
+Slots are 32-byte field elements in LDS.  An operand field holds a 3-bit segment and
+a 9-bit offset: segment 0 is absolute, segments 1..7 are bases the caller sets before
+running a relocatable program.
+
+Programs:
+  * Miller-loop bodies for the optimal ate pairing, software-pipelined: the T-chain
+    (doubling / addition of the twist point, with line coefficients) runs one step
+    ahead of the f-chain (squaring of the accumulator times the pending lines).  The
+    loop follows the non-adjacent form of 6u + 2; the closing additions use pi(Q)
+    and -pi^2(Q);
+  * F_p12 operations for the final exponentiation (relocatable: X in segment 1, Y in
+    segment 2, D in segment 3): product, Granger-Scott cyclotomic square, Frobenius
+    powers, conjugate, the norm down to F_p and the easy part from the inverse norm.
+
+Run:  python gen_slp.py > slp_progs.hpp      (the build does this)
+      python gen_slp.py --check              (run every program on random inputs
+                                              against plain polynomial arithmetic)
+"""
+from __future__ import annotations
+
+import random
+import sys
+
+U = 0x44E992B44A6909F1
+P = 36 * U**4 + 36 * U**3 + 24 * U**2 + 6 * U + 1
+R = 36 * U**4 + 36 * U**3 + 18 * U**2 + 6 * U + 1
+RMONT = 1 << 256
+LANES = 64
+KMAX = 15
+
+OP_NOP, OP_MUL, OP_LIN = 0, 1, 2
+
+
+# ============================================================================ tracer
+NTERM = 6       # operands per op (a product splits them between its two factors)
+
+
+class Prog:
+    """SSA values: ('in', name) | ('const', x) | ('lin', terms) | ('mul', termsA, termsB);
+    terms are tuples of (value id, small integer coefficient)"""
+
+    def __init__(self, name):
+        self.name = name
+        self.vals = []
+        self.inputs = {}
+        self.outputs = {}
+        self.consts = {}
+        self.memo = {}
+        self.zero = self.const(0)
+
+    def new(self, node):
+        key = node if node[0] in ("lin", "mul") else None
+        if key is not None and key in self.memo:
+            return self.memo[key]
+        self.vals.append(node)
+        v = len(self.vals) - 1
+        if key is not None:
+            self.memo[key] = v
+        return v
+
+    def inp(self, name):
+        v = self.new(("in", name))
+        self.inputs[name] = v
+        return F(self, {v: 1})
+
+    def const(self, x):
+        x %= P
+        if x not in self.consts:
+            self.consts[x] = self.new(("const", x))
+        return self.consts[x]
+
+    def fconst(self, x):
+        return F(self, {self.const(x): 1})
+
+    def out(self, name, f):
+        self.outputs[name] = f.atom()
+
+
+def canon(terms):
+    return tuple(sorted((k, c) for k, c in terms.items() if c != 0))
+
+
+class F:
+    """a base-field value: a small-integer linear combination of atoms (value ids)"""
+    __slots__ = ("p", "t")
+
+    def __init__(self, p, terms):
+        self.p = p
+        self.t = {k: c for k, c in terms.items() if c != 0}
+
+    def _lin(self, o, s):
+        t = dict(self.t)
+        for k, c in o.t.items():
+            t[k] = t.get(k, 0) + s * c
+        return F(self.p, t)
+
+    def __add__(self, o):
+        return self._lin(o, 1)
+
+    def __sub__(self, o):
+        return self._lin(o, -1)
+
+    def __neg__(self):
+        return F(self.p, {k: -c for k, c in self.t.items()})
+
+    def scale(self, k):
+        return F(self.p, {a: c * k for a, c in self.t.items()})
+
+    def __mul__(self, o):
+        if not self.t or not o.t:
+            return F(self.p, {})
+        A, B = operand_terms(self.p, self.t), operand_terms(self.p, o.t)
+        while len(A) + len(B) > NTERM:
+            if len(A) >= len(B):
+                A = {materialise(self.p, A): 1}
+            else:
+                B = {materialise(self.p, B): 1}
+        a, b = canon(A), canon(B)
+        if b < a:
+            a, b = b, a
+        return F(self.p, {self.p.new(("mul", a, b)): 1})
+
+    def atom(self):
+        if not self.t:
+            return self.p.zero
+        if len(self.t) == 1:
+            (k, c), = self.t.items()
+            if c == 1:
+                return k
+        a = materialise(self.p, self.t)
+        self.t = {a: 1}
+        return a
+
+
+def operand_terms(p, t):
+    """a factor of a product: coefficients within [-KMAX, KMAX], at most NTERM - 1 terms"""
+    t = fit_coeffs(p, dict(t))
+    if len(t) > NTERM - 1:
+        t = {materialise(p, t): 1}
+    return t
+
+
+def fit_coeffs(p, t):
+    """rewrite terms whose coefficient exceeds KMAX through an intermediate LIN"""
+    for k, c in list(t.items()):
+        if abs(c) > KMAX:
+            s = 1 if c > 0 else -1
+            a = abs(c)
+            f1 = next((d for d in range(KMAX, 1, -1) if a % d == 0 and a // d <= KMAX), None)
+            del t[k]
+            if f1:
+                v = p.new(("lin", ((k, f1),)))
+                t[v] = t.get(v, 0) + s * (a // f1)
+            else:
+                v = p.new(("lin", ((k, KMAX),)))
+                t[v] = t.get(v, 0) + s * (a // KMAX)
+                if a % KMAX:
+                    t[k] = t.get(k, 0) + s * (a % KMAX)
+            return fit_coeffs(p, {kk: cc for kk, cc in t.items() if cc})
+    return t
+
+
+def materialise(p, terms):
+    """LIN operations computing sum c_k x_k, NTERM terms per operation, shallow tree"""
+    t = fit_coeffs(p, {k: c for k, c in terms.items() if c != 0})
+    if not t:
+        return p.zero
+    if len(t) == 1:
+        (k, c), = t.items()
+        if c == 1:
+            return k
+    items = sorted(t.items(), key=lambda kc: (-abs(kc[1]), kc[0]))
+    if len(items) <= NTERM:
+        return p.new(("lin", canon(dict(items))))
+    n = len(items)
+    g = -(-(n - NTERM) // (NTERM - 1))          # sub-sums needed
+    raw = items[:NTERM - g]
+    rest = items[NTERM - g:]
+    subs = []
+    per = -(-len(rest) // g)
+    for i in range(0, len(rest), per):
+        subs.append((materialise(p, dict(rest[i:i + per])), 1))
+    return p.new(("lin", canon(dict(raw + subs))))
+
+
+# ============================================================================ tower
+def zero2(p):
+    return F2(F(p, {}), F(p, {}))
+
+
+class F2:
+    __slots__ = ("c0", "c1")
+
+    def __init__(self, c0, c1):
+        self.c0, self.c1 = c0, c1
+
+    def __add__(s, o):
+        return F2(s.c0 + o.c0, s.c1 + o.c1)
+
+    def __sub__(s, o):
+        return F2(s.c0 - o.c0, s.c1 - o.c1)
+
+    def __neg__(s):
+        return F2(-s.c0, -s.c1)
+
+    def scale(s, k):
+        return F2(s.c0.scale(k), s.c1.scale(k))
+
+    def is_zero(s):
+        return not s.c0.t and not s.c1.t
+
+    def mul(s, o, kara=False):
+        if s.is_zero() or o.is_zero():
+            return zero2(s.c0.p)
+        a0, a1, b0, b1 = s.c0, s.c1, o.c0, o.c1
+        if kara:
+            v0, v1 = a0 * b0, a1 * b1
+            return F2(v0 - v1, (a0 + a1) * (b0 + b1) - v0 - v1)
+        return F2(a0 * b0 - a1 * b1, a0 * b1 + a1 * b0)
+
+    def sqr(s):
+        a0, a1 = s.c0, s.c1
+        return F2((a0 + a1) * (a0 - a1), (a0 * a1).scale(2))
+
+    def mul_fp(s, x):
+        return F2(s.c0 * x, s.c1 * x)
+
+    def mul_xi(s):  # (9 + i)(a0 + a1 i) = (9 a0 - a1) + (a0 + 9 a1) i
+        return F2(s.c0.scale(9) - s.c1, s.c0 + s.c1.scale(9))
+
+    def conj(s):
+        return F2(s.c0, -s.c1)
+
+    def mul_const(s, c):
+        p = s.c0.p
+        k0, k1 = c[0] % P, c[1] % P
+        r0, r1 = F(p, {}), F(p, {})
+        if k0:
+            g = p.fconst(k0)
+            r0 = r0 + s.c0 * g
+            r1 = r1 + s.c1 * g
+        if k1:
+            g = p.fconst(k1)
+            r0 = r0 - s.c1 * g
+            r1 = r1 + s.c0 * g
+        return F2(r0, r1)
+
+
+class F6:
+    __slots__ = ("c",)
+
+    def __init__(self, c0, c1, c2):
+        self.c = (c0, c1, c2)
+
+    def __add__(s, o):
+        return F6(*(x + y for x, y in zip(s.c, o.c)))
+
+    def __sub__(s, o):
+        return F6(*(x - y for x, y in zip(s.c, o.c)))
+
+    def __neg__(s):
+        return F6(*(-x for x in s.c))
+
+    def mul(s, o, kara2=True):
+        a0, a1, a2 = s.c
+        b0, b1, b2 = o.c
+        v0, v1, v2 = a0.mul(b0, kara2), a1.mul(b1, kara2), a2.mul(b2, kara2)
+        c0 = v0 + ((a1 + a2).mul(b1 + b2, kara2) - v1 - v2).mul_xi()
+        c1 = (a0 + a1).mul(b0 + b1, kara2) - v0 - v1 + v2.mul_xi()
+        c2 = (a0 + a2).mul(b0 + b2, kara2) - v0 + v1 - v2
+        return F6(c0, c1, c2)
+
+    def mul_v(s):  # v (c0 + c1 v + c2 v^2) = xi c2 + c0 v + c1 v^2
+        return F6(s.c[2].mul_xi(), s.c[0], s.c[1])
+
+
+class F12:
+    __slots__ = ("a", "b")
+
+    def __init__(self, a, b):
+        self.a, self.b = a, b
+
+    def coeffs(self):  # memory order c0.c0.c0, c0.c0.c1, ..., c1.c2.c1
+        out = []
+        for h in (self.a, self.b):
+            for q in h.c:
+                out += [q.c0, q.c1]
+        return out
+
+    @staticmethod
+    def of(cs):
+        f2 = [F2(cs[2 * j], cs[2 * j + 1]) for j in range(6)]
+        return F12(F6(*f2[:3]), F6(*f2[3:]))
+
+    def mul(s, o, kara2=True):
+        t0, t1 = s.a.mul(o.a, kara2), s.b.mul(o.b, kara2)
+        c1 = (s.a + s.b).mul(o.a + o.b, kara2) - t0 - t1
+        return F12(t0 + t1.mul_v(), c1)
+
+    def sqr(s, kara2=True):
+        # complex squaring over F_p6: t = a b, c0 = (a + b)(a + v b) - t - v t, c1 = 2t
+        a, b = s.a, s.b
+        t = a.mul(b, kara2)
+        m = (a + b).mul(a + b.mul_v(), kara2)
+        return F12(m - t - t.mul_v(), t + t)
+
+    def conj(s):
+        return F12(s.a, -s.b)
+
+
+# ============================================================================ constants
+def f2mul_int(a, b):
+    return ((a[0] * b[0] - a[1] * b[1]) % P, (a[0] * b[1] + a[1] * b[0]) % P)
+
+
+def f2pow_int(a, e):
+    r = (1, 0)
+    while e:
+        if e & 1:
+            r = f2mul_int(r, a)
+        a = f2mul_int(a, a)
+        e >>= 1
+    return r
+
+
+def f2inv_int(a):
+    n = pow(a[0] * a[0] + a[1] * a[1], -1, P)
+    return (a[0] * n % P, -a[1] * n % P)
+
+
+XI = (9, 1)
+TWIST_B = f2mul_int((3, 0), f2inv_int(XI))     # b' = 3 / xi
+B3 = f2mul_int((3, 0), TWIST_B)                # 3 b'
+B9 = f2mul_int((9, 0), TWIST_B)                # 9 b'
+GAM1 = [f2pow_int(XI, k * (P - 1) // 6) for k in range(6)]
+GAM2 = [f2pow_int(XI, k * (P * P - 1) // 6) for k in range(6)]
+GAM3 = [f2pow_int(XI, k * (P**3 - 1) // 6) for k in range(6)]
+assert all(g[1] == 0 for g in GAM2)
+FROB_TX, FROB_TY = GAM1[2], GAM1[3]            # twist Frobenius: (conj(x) tx, conj(y) ty)
+FROB2_TX = f2pow_int(XI, (P * P - 1) // 3)
+FROB2_TY = f2pow_int(XI, (P * P - 1) // 2)
+assert FROB2_TX[1] == 0 and FROB2_TY[1] == 0
+
+
+def frob12(f, e):
+    """f^{p^e}, e = 1, 2, 3: the F_p2 coefficient of w^k (k = 2q + h) maps to conj^e(c) gamma_e[k]"""
+    p = f.a.c[0].c0.p
+    out = []
+    for h, half in enumerate((f.a, f.b)):
+        for q, c in enumerate(half.c):
+            k = 2 * q + h
+            if e & 1:
+                c = c.conj()
+            if k == 0:
+                out.append(c)
+            elif e == 2:
+                g = p.fconst(GAM2[k][0])
+                out.append(F2(c.c0 * g, c.c1 * g))
+            else:
+                out.append(c.mul_const(GAM1[k] if e == 1 else GAM3[k]))
+    return F12(F6(*out[:3]), F6(*out[3:]))
+
+
+# ============================================================================ pairing formulas
+def line_dbl(T, xP, yP):
+    """T = (X, Y, Z) homogeneous projective on y^2 = x^3 + b'.  Returns 2T (scaled by 4)
+    and the tangent at T evaluated at P up to an F_p2 factor, as (l0, l1, l3) meaning
+    l0 + l1 w + l3 w^3:  l0 = 2YZ yP, l1 = -3X^2 xP, l3 = Y^2 - 3b'Z^2."""
+    X, Y, Z = T
+    XX, YY, ZZ = X.sqr(), Y.sqr(), Z.sqr()
+    XY, YZ = X.mul(Y), Y.mul(Z)
+    F9 = ZZ.mul_const(B9)                  # 9 b' Z^2
+    E = ZZ.mul_const(B3)                   # 3 b' Z^2
+    X3 = XY.mul(YY - F9).scale(2)          # 2 XY (Y^2 - 9b'Z^2)
+    Y3 = (YY + F9).sqr() - E.sqr().scale(12)
+    Z3 = YY.mul(YZ).scale(8)               # 8 Y^3 Z
+    l0 = YZ.scale(2).mul_fp(yP)
+    l1 = XX.scale(-3).mul_fp(xP)
+    l3 = YY - E
+    return (X3, Y3, Z3), (l0, l1, l3)
+
+
+def line_add(T, Q, xP, yP):
+    """T projective, Q = (xQ, yQ) affine: T + Q and the line through T and Q at P:
+    l0 = lam yP, l1 = -theta xP, l3 = theta xQ - lam yQ  (theta = Y - yQ Z, lam = X - xQ Z)."""
+    X, Y, Z = T
+    xQ, yQ = Q
+    th = Y - yQ.mul(Z)
+    la = X - xQ.mul(Z)
+    C, D = th.sqr(), la.sqr()
+    E2 = la.mul(D)
+    F2_ = Z.mul(C)
+    G2 = X.mul(D)
+    H2 = E2 + F2_ - G2.scale(2)
+    X3 = la.mul(H2)
+    Y3 = th.mul(G2 - H2) - Y.mul(E2)
+    Z3 = Z.mul(E2)
+    l0 = la.mul_fp(yP)
+    l1 = (-th).mul_fp(xP)
+    l3 = th.mul(xQ) - la.mul(yQ)
+    return (X3, Y3, Z3), (l0, l1, l3)
+
+
+def line_to_f12(l):
+    """l0 + l1 w + l3 w^3 = (l0, 0, 0) + (l1, l3, 0) w"""
+    l0, l1, l3 = l
+    z = zero2(l0.c0.p)
+    return F12(F6(l0, z, z), F6(l1, l3, z))
+
+
+def sparse01(x, b0, b1, kara2=True):
+    """(x0 + x1 v + x2 v^2)(b0 + b1 v)"""
+    x0, x1, x2 = x.c
+    v0, v1 = x0.mul(b0, kara2), x1.mul(b1, kara2)
+    c0 = v0 + x2.mul(b1, kara2).mul_xi()
+    c1 = (x0 + x1).mul(b0 + b1, kara2) - v0 - v1
+    c2 = x2.mul(b0, kara2) + v1
+    return F6(c0, c1, c2)
+
+
+def mul_by_line(f, l, kara2=True):
+    """f (a + b w) with a = (l0, 0, 0), b = (l1, l3, 0)"""
+    l0, l1, l3 = l
+    f0, f1 = f.a, f.b
+    t0 = F6(*(c.mul(l0, kara2) for c in f0.c))
+    t1 = sparse01(f1, l1, l3, kara2)
+    m = sparse01(f0 + f1, l0 + l1, l3, kara2)
+    return F12(t0 + t1.mul_v(), m - t0 - t1)
+
+
+def line_mul_line(la, lb):
+    """(a0 + a1 w + a3 w^3)(b0 + b1 w + b3 w^3), w^6 = xi:
+    w^0: a0b0; w^1: a0b1 + a1b0; w^2: a1b1; w^3: a0b3 + a3b0; w^4: a1b3 + a3b1; w^6 -> xi: a3b3"""
+    a0, a1, a3 = la
+    b0, b1, b3 = lb
+    p = a0.c0.p
+    z = zero2(p)
+    t00, t11, t33 = a0.mul(b0), a1.mul(b1), a3.mul(b3)
+    c = {0: t00 + t33.mul_xi(), 1: a0.mul(b1) + a1.mul(b0), 2: t11, 3: a0.mul(b3) + a3.mul(b0),
+         4: a1.mul(b3) + a3.mul(b1), 5: z}
+    # w^k, k = 2q + h  ->  (h, q)
+    h0 = F6(c[0], c[2], c[4])
+    h1 = F6(c[1], c[3], c[5])
+    return F12(h0, h1)
+
+
+def twist_frob(Q):
+    xQ, yQ = Q
+    return (xQ.conj().mul_const(FROB_TX), yQ.conj().mul_const(FROB_TY))
+
+
+def twist_frob2_neg(Q):
+    xQ, yQ = Q
+    p = xQ.c0.p
+    gx, gy = p.fconst(FROB2_TX[0]), p.fconst(-FROB2_TY[0])
+    return (F2(xQ.c0 * gx, xQ.c1 * gx), F2(yQ.c0 * gy, yQ.c1 * gy))
+
+
+def naf(k):
+    d = []
+    while k:
+        if k & 1:
+            z = 2 - (k % 4)
+            k -= z
+        else:
+            z = 0
+        d.append(z)
+        k //= 2
+    return d[::-1]
+
+
+ATE = 6 * U + 2
+ATE_NAF = naf(ATE)          # most significant first, leading digit 1
+
+
+# ============================================================================ programs
+def f2_in(p, name):
+    return F2(p.inp(name + ".0"), p.inp(name + ".1"))
+
+
+def f12_in(p, name):
+    return F12.of([p.inp("%s.%d" % (name, k)) for k in range(12)])
+
+
+def f2_out(p, name, v):
+    p.out(name + ".0", v.c0)
+    p.out(name + ".1", v.c1)
+
+
+def f12_out(p, name, f):
+    for k, c in enumerate(f.coeffs()):
+        p.out("%s.%d" % (name, k), c)
+
+
+def line_in(p, name):
+    return tuple(f2_in(p, "%s.%d" % (name, k)) for k in range(3))
+
+
+def line_out(p, name, l):
+    for k, c in enumerate(l):
+        f2_out(p, "%s.%d" % (name, k), c)
+
+
+def pt_in(p, name):
+    return tuple(f2_in(p, "%s.%s" % (name, c)) for c in "XYZ")
+
+
+def pt_out(p, name, T):
+    for c, v in zip("XYZ", T):
+        f2_out(p, "%s.%s" % (name, c), v)
+
+
+def miller_programs():
+    """Bodies of the pipelined Miller loop over the NAF digits d_1 .. d_n of 6u + 2
+    (d_0 = 1 is the starting T = Q).  State: f, T, pending lines L1 (and L2 when an
+    addition followed the doubling), P = (xP, yP), Q = (xQ, yQ), nyQ = -yQ.
+
+      ml_start<a>    : (T, L1) = dbl(Q); addition step a (0, +1, -1) gives L2
+      ml_body<n><a>  : f = f^2 * pending (f = pending on the first body);
+                       (T, L1) = dbl(T); addition step a gives L2
+      ml_final<n>    : f = f^2 * pending, times the lines of T + pi(Q) and of
+                       (T + pi(Q)) - pi^2(Q)
+    n is the number of pending lines (1 or 2)."""
+    progs = {}
+
+    def common(p):
+        xP, yP = p.inp("xP"), p.inp("yP")
+        xQ, yQ = f2_in(p, "xQ"), f2_in(p, "yQ")
+        return xP, yP, (xQ, yQ)
+
+    def add_step(p, T, Q, a, xP, yP):
+        if a == 1:
+            return line_add(T, Q, xP, yP)
+        return line_add(T, (Q[0], -Q[1]), xP, yP)
+
+    for a in (0, 1, -1):
+        p = Prog("ml_start%s" % "0pm"[a])
+        xP, yP, Q = common(p)
+        one = F2(p.fconst(1), p.fconst(0))
+        T, l1 = line_dbl((Q[0], Q[1], one), xP, yP)
+        if a:
+            T, l2 = add_step(p, T, Q, a, xP, yP)
+        pt_out(p, "T", T)
+        line_out(p, "L1", l1)
+        if a:
+            line_out(p, "L2", l2)
+        progs[p.name] = p
+    for npend in (1, 2):
+        for a in (0, 1, -1):
+            for first in (0, 1):
+                p = Prog("ml_body%d%s%s" % (npend, "0pm"[a], "_first" if first else ""))
+                xP, yP, Q = common(p)
+                L1 = line_in(p, "L1")
+                L2 = line_in(p, "L2") if npend == 2 else None
+                if first:
+                    f = line_to_f12(L1) if npend == 1 else line_mul_line(L1, L2)
+                else:
+                    f = f12_in(p, "f").sqr()
+                    f = mul_by_line(f, L1) if npend == 1 else f.mul(line_mul_line(L1, L2))
+                f12_out(p, "f", f)
+                T, l1 = line_dbl(pt_in(p, "T"), xP, yP)
+                if a:
+                    T, l2 = add_step(p, T, Q, a, xP, yP)
+                pt_out(p, "T", T)
+                line_out(p, "L1", l1)
+                if a:
+                    line_out(p, "L2", l2)
+                progs[p.name] = p
+    for npend in (1, 2):
+        p = Prog("ml_final%d" % npend)
+        xP, yP, Q = common(p)
+        L1 = line_in(p, "L1")
+        L2 = line_in(p, "L2") if npend == 2 else None
+        f = f12_in(p, "f").sqr()
+        f = mul_by_line(f, L1) if npend == 1 else f.mul(line_mul_line(L1, L2))
+        T = pt_in(p, "T")
+        T, la = line_add(T, twist_frob(Q), xP, yP)
+        _, lb = line_add(T, twist_frob2_neg(Q), xP, yP)
+        f12_out(p, "f", f.mul(line_mul_line(la, lb)))
+        progs[p.name] = p
+    return progs
+
+
+def miller_sequence():
+    d = ATE_NAF
+    assert d[0] == 1
+    seq = ["ml_start%s" % "0pm"[d[1]]]
+    pend = 2 if d[1] else 1
+    for i in range(2, len(d)):
+        seq.append("ml_body%d%s%s" % (pend, "0pm"[d[i]], "_first" if i == 2 else ""))
+        pend = 2 if d[i] else 1
+    seq.append("ml_final%d" % pend)
+    return seq
+
+
+MILLER_STATE = (["xP", "yP", "xQ.0", "xQ.1", "yQ.0", "yQ.1"] + ["f.%d" % k for k in range(12)]
+                + ["T.%s.%d" % (c, k) for c in "XYZ" for k in (0, 1)]
+                + ["L%d.%d.%d" % (n, j, k) for n in (1, 2) for j in range(3) for k in (0, 1)])
+
+
+def cyclo_sqr(X):
+    """Granger-Scott squaring of a cyclotomic element over the three F_p4 pairs
+    (w^0, w^3), (w^1, w^4), (w^2, w^5), with s = w^3, s^2 = xi."""
+    a, b = X.a, X.b
+    g = {0: a.c[0], 2: a.c[1], 4: a.c[2], 1: b.c[0], 3: b.c[1], 5: b.c[2]}   # by power of w
+
+    def fp4_sqr(x, y):  # (x + y s)^2 with s^2 = xi: (x^2 + xi y^2, 2xy)
+        t0, t1 = x.sqr(), y.sqr()
+        return t0 + t1.mul_xi(), (x + y).sqr() - t0 - t1
+
+    z0, z1 = g[0], g[3]
+    z2, z3 = g[1], g[4]
+    z4, z5 = g[2], g[5]
+    t0, t1 = fp4_sqr(z0, z1)
+    n0 = (t0 - z0).scale(2) + t0
+    n1 = (t1 + z1).scale(2) + t1
+    t0, t1 = fp4_sqr(z2, z3)
+    t2, t3 = fp4_sqr(z4, z5)
+    n4 = (t0 - z4).scale(2) + t0
+    n5 = (t1 + z5).scale(2) + t1
+    t0 = t3.mul_xi()
+    n2 = (t0 + z2).scale(2) + t0
+    n3 = (t2 - z3).scale(2) + t2
+    h = {0: n0, 3: n1, 1: n2, 4: n3, 2: n4, 5: n5}
+    return F12(F6(h[0], h[2], h[4]), F6(h[1], h[3], h[5]))
+
+
+def fe_programs():
+    progs = {}
+
+    def mk(name, fn, n_in):
+        p = Prog(name)
+        X = f12_in(p, "X")
+        args = [X] + ([f12_in(p, "Y")] if n_in == 2 else [])
+        f12_out(p, "D", fn(*args))
+        progs[name] = p
+
+    mk("f12_mul", lambda X, Y: X.mul(Y), 2)
+    mk("f12_csqr", cyclo_sqr, 1)
+    mk("f12_csqr_mul", lambda X, Y: cyclo_sqr(X).mul(Y), 2)
+    mk("f12_frob1", lambda X: frob12(X, 1), 1)
+    mk("f12_frob2", lambda X: frob12(X, 2), 1)
+    mk("f12_frob3", lambda X: frob12(X, 3), 1)
+    mk("f12_conj", lambda X: X.conj(), 1)
+    mk("f12_conj_mul", lambda X, Y: X.conj().mul(Y), 2)
+    mk("f12_frob2_mul", lambda X, Y: frob12(X, 2).mul(Y), 2)
+    # norm: n6 = X conj(X) = a^2 - v b^2 in F_p6; the F_p6 inverse of n6 is (A, B, C) / n2
+    # with A = c0^2 - xi c1 c2, B = xi c2^2 - c0 c1, C = c1^2 - c0 c2,
+    # n2 = c0 A + xi (c2 B + c1 C); t = n2 conj(n2) in F_p
+    p = Prog("fe_norm")
+    X = f12_in(p, "X")
+    n6 = X.a.mul(X.a) - X.b.mul(X.b).mul_v()
+    c0, c1, c2 = n6.c
+    A = c0.sqr() - c1.mul(c2).mul_xi()
+    B = c2.sqr().mul_xi() - c0.mul(c1)
+    C = c1.sqr() - c0.mul(c2)
+    n2 = c0.mul(A) + (c2.mul(B) + c1.mul(C)).mul_xi()
+    for nm, v in (("nA", A), ("nB", B), ("nC", C), ("n2", n2)):
+        f2_out(p, nm, v)
+    p.out("t", n2.c0 * n2.c0 + n2.c1 * n2.c1)
+    progs[p.name] = p
+    # easy part from tinv = t^{-1}: n6^{-1} = (A, B, C) conj(n2) tinv and
+    # conj(X) X^{-1} = conj(X)^2 n6^{-1}
+    p = Prog("fe_easy")
+    X = f12_in(p, "X")
+    A, B, C, n2 = (f2_in(p, nm) for nm in ("nA", "nB", "nC", "n2"))
+    ti = p.inp("tinv")
+    n2i = n2.conj().mul_fp(ti)
+    n6i = F6(A.mul(n2i), B.mul(n2i), C.mul(n2i))
+    cx2 = X.conj().sqr()
+    f12_out(p, "D", F12(cx2.a.mul(n6i), cx2.b.mul(n6i)))
+    progs[p.name] = p
+    return progs
+
+
+UNAF = naf(U)
+
+
+def fe_sequence():
+    """Final exponentiation f^((p^12 - 1)/r) as calls of the F_p12 programs on buffers of
+    12 slots: easy part conj(f) f^{-1}, then (.)^{p^2} (.); hard part through f^u, f^{u^2},
+    f^{u^3} and the p-power split (p^4 - p^2 + 1)/r = l0 + l1 p + l2 p^2 + l3 p^3 with
+    l3 = 1, l2 = 6u^2 + 1, l1 = -36u^3 - 18u^2 - 12u + 1, l0 = -36u^3 - 30u^2 - 18u - 2.
+    Entries are (program, X, Y, D) buffer numbers; "INV" inverts the norm on one lane.
+    Buffer 0 holds the input; the result is left in the buffer returned."""
+    seq = []
+    nbuf = [1]
+    free = []
+
+    def alloc():
+        if free:
+            return free.pop()
+        nbuf[0] += 1
+        return nbuf[0] - 1
+
+    def call(prog, X, Y=None):
+        D = alloc()
+        seq.append((prog, X, X if Y is None else Y, D))
+        return D
+
+    def release(*bs):
+        for b in bs:
+            free.append(b)
+
+    seq.append(("fe_norm", 0, 0, 0))
+    seq.append(("INV", 0, 0, 0))
+    f1 = call("fe_easy", 0)
+    f = call("f12_frob2_mul", f1, f1)
+    release(f1)
+
+    def pow_u(x):
+        xc = call("f12_conj", x)
+        acc = x
+        for d in UNAF[1:]:
+            if d == 0:
+                nxt = call("f12_csqr", acc)
+            else:
+                nxt = call("f12_csqr_mul", acc, x if d == 1 else xc)
+            if acc != x:
+                release(acc)
+            acc = nxt
+        release(xc)
+        return acc
+
+    a = pow_u(f)
+    b = pow_u(a)
+    c = pow_u(b)
+    c2 = call("f12_csqr", c)
+    c4 = call("f12_csqr", c2)
+    release(c2)
+    c8 = call("f12_csqr", c4)
+    release(c4)
+    c9 = call("f12_mul", c8, c)
+    release(c8, c)
+    c18 = call("f12_csqr", c9)
+    release(c9)
+    c36 = call("f12_csqr", c18)
+    release(c18)
+    b2 = call("f12_csqr", b)
+    b3 = call("f12_mul", b2, b)
+    release(b2, b)
+    b6 = call("f12_csqr", b3)
+    release(b3)
+    b12 = call("f12_csqr", b6)
+    b18 = call("f12_mul", b12, b6)
+    b30 = call("f12_mul", b18, b12)
+    release(b12)
+    a2 = call("f12_csqr", a)
+    a3 = call("f12_mul", a2, a)
+    release(a2, a)
+    a6 = call("f12_csqr", a3)
+    release(a3)
+    a12 = call("f12_csqr", a6)
+    a18 = call("f12_mul", a12, a6)
+    release(a6)
+    f2 = call("f12_csqr", f)
+    t = call("f12_mul", c36, b30)
+    release(b30)
+    u_ = call("f12_mul", a18, f2)
+    release(a18, f2)
+    t0n = call("f12_mul", t, u_)                 # conj(t0n) = f^{l0}
+    release(t, u_)
+    v = call("f12_mul", c36, b18)
+    release(c36, b18)
+    v2 = call("f12_mul", v, a12)
+    release(v, a12)
+    t1 = call("f12_conj_mul", v2, f)             # f^{l1}
+    release(v2)
+    t2 = call("f12_mul", b6, f)                  # f^{l2}
+    release(b6)
+    ft1 = call("f12_frob1", t1)
+    release(t1)
+    r1 = call("f12_conj_mul", t0n, ft1)          # f^{l0} (f^{l1})^p
+    release(t0n, ft1)
+    f3 = call("f12_frob3", f)
+    release(f)
+    r2 = call("f12_frob2_mul", t2, f3)           # (f^{l2})^{p^2} f^{p^3}
+    release(t2, f3)
+    res = call("f12_mul", r1, r2)
+    return seq, res, nbuf[0]
+
+
+# ============================================================================ scheduling
+def operands(v):
+    if v[0] == "mul":
+        return tuple(k for k, _ in v[1]) + tuple(k for k, _ in v[2])
+    if v[0] == "lin":
+        return tuple(k for k, _ in v[1])
+    return ()
+
+
+def schedule(p, lanes=LANES):
+    """Stage scheduling: a product's stage is its multiplicative depth (products on the
+    longest path from the inputs), so all products of one depth share one level (split
+    only beyond the lane count).  Additions run in the phase after the products they
+    depend on, levelised by their depth within the phase."""
+    vals = p.vals
+    n = len(vals)
+    live = [False] * n
+    stack = list(p.outputs.values())
+    while stack:
+        i = stack.pop()
+        if live[i]:
+            continue
+        live[i] = True
+        stack.extend(operands(vals[i]))
+    is_op = [live[i] and vals[i][0] in ("mul", "lin") for i in range(n)]
+    md = [0] * n      # multiplicative depth
+    ld = [0] * n      # depth in additions since the last product
+    for i in range(n):
+        if not is_op[i]:
+            continue
+        ops_ = [a for a in operands(vals[i]) if is_op[a]]
+        if vals[i][0] == "mul":
+            md[i] = 1 + max([md[a] for a in ops_] + [0])
+            ld[i] = 0
+        else:
+            m = max([md[a] for a in ops_] + [0])
+            md[i] = m
+            ld[i] = 1 + max([ld[a] for a in ops_ if md[a] == m] + [0])
+    # a product at depth k must follow the additions of phase k-1 that feed it
+    maxd = max([md[i] for i in range(n) if is_op[i]] + [0])
+    phase_len = [0] * (maxd + 1)
+    for i in range(n):
+        if is_op[i] and vals[i][0] == "lin":
+            phase_len[md[i]] = max(phase_len[md[i]], ld[i])
+    buckets = {}
+    for i in range(n):
+        if not is_op[i]:
+            continue
+        if vals[i][0] == "mul":
+            key = (md[i] - 1, 1 << 20)          # after phase md-1 additions
+        else:
+            key = (md[i], ld[i])
+        buckets.setdefault(key, []).append(i)
+    levels = []
+    level_of = [-1] * n
+    for key in sorted(buckets):
+        ops_ = sorted(buckets[key])
+        for k in range(0, len(ops_), lanes):
+            L = len(levels)
+            levels.append(ops_[k:k + lanes])
+            for i in ops_[k:k + lanes]:
+                level_of[i] = L
+    return levels, level_of, live
+
+
+def compile_prog(p, io_slot, const_slot, temp_base, temp_limit, lanes=LANES):
+    """Schedule p and assign slots.  io_slot(name) gives the encoded slot of an input or
+    output name (an output with the name of an input replaces it), const_slot(x) the slot
+    of a constant.  Returns (levels of encoded op tuples, highest temp slot used + 1)."""
+    levels, level_of, live = schedule(p, lanes)
+    vals = p.vals
+    n = len(vals)
+    nlev = len(levels)
+    slot = [None] * n
+    for name, v in p.inputs.items():
+        slot[v] = io_slot(name)
+    for x, v in p.consts.items():
+        slot[v] = const_slot(x)
+    last = [-1] * n
+    for i in range(n):
+        if level_of[i] >= 0:
+            for a in operands(vals[i]):
+                last[a] = max(last[a], level_of[i])
+    outs = {}
+    for name, v in p.outputs.items():
+        outs.setdefault(v, []).append(name)
+    for v in outs:
+        last[v] = nlev
+    # last read of the value held in each io slot at entry
+    held_read = {}
+    for name, v in p.inputs.items():
+        held_read[io_slot(name)] = last[v]
+    free = list(range(temp_limit - 1, temp_base - 1, -1))
+    busy = []
+    used = temp_base
+    copies = []
+    for i in sorted((i for i in range(n) if level_of[i] >= 0), key=lambda i: (level_of[i], i)):
+        L = level_of[i]
+        keep = []
+        for rl, s in busy:
+            (free if rl <= L else keep).append(s if rl <= L else (rl, s))
+        busy = keep
+        names = outs.get(i, [])
+        # write in place when this is the only output of the value and the slot's entry
+        # value is not read after this level
+        if len(names) == 1 and held_read.get(io_slot(names[0]), -1) <= L:
+            slot[i] = io_slot(names[0])
+            continue
+        if not free:
+            raise RuntimeError("%s: out of temp slots" % p.name)
+        s = free.pop()
+        used = max(used, s + 1)
+        slot[i] = s
+        busy.append((last[i], s))
+        for nm in names:
+            copies.append((nm, i))
+    # outputs that are inputs or constants of the program, or that share a value
+    for v, names in outs.items():
+        if level_of[v] < 0:
+            for nm in names:
+                if slot[v] != io_slot(nm):
+                    copies.append((nm, v))
+    enc = []
+    for ops in levels:
+        row = []
+        for i in ops:
+            v = vals[i]
+            if v[0] == "mul":
+                row.append((OP_MUL, slot[i], len(v[1]), tuple((slot[k], c) for k, c in v[1] + v[2])))
+            else:
+                row.append((OP_LIN, slot[i], len(v[1]), tuple((slot[k], c) for k, c in v[1])))
+        enc.append(row)
+    if copies:
+        row = [(OP_LIN, io_slot(nm), 1, ((slot[v], 1),)) for nm, v in copies]
+        for k in range(0, len(row), lanes):
+            enc.append(row[k:k + lanes])
+    return enc, used
+
+
+# ============================================================================ kernels
+class Kernel:
+    """programs that share one LDS slot map: named state slots, constants, temps"""
+
+    def __init__(self, name, progs, state, segs=None, lanes=LANES):
+        self.name = name
+        self.state = {nm: i for i, nm in enumerate(state)}
+        self.segs = segs or {}
+        consts = sorted(set(x for p in progs.values() for x in p.consts) | {0, 1})
+        self.cbase = len(state)
+        self.cslot = {x: self.cbase + k for k, x in enumerate(consts)}
+        self.consts = consts
+        self.tbase = self.cbase + len(consts)
+        self.progs = {}
+        self.ntemps = self.tbase
+        for nm, p in progs.items():
+            enc, used = compile_prog(p, self.io_slot, lambda x: self.cslot[x % P], self.tbase, 512, lanes)
+            self.progs[nm] = enc
+            self.ntemps = max(self.ntemps, used)
+        self.nslots = self.ntemps
+
+    def io_slot(self, name):
+        head = name.split(".")[0]
+        if head in self.segs:
+            seg = self.segs[head]
+            off = int(name.split(".")[1])
+            return (seg << 9) | off
+        return self.state[name]
+
+
+def encode_op(op):
+    """128-bit op: kind (2) | dst (12) | na (3) | 6 x (slot 12 | coefficient 5, two's complement);
+    a product multiplies the sum of terms [0, na) by the sum of terms [na, 6); unused
+    terms have coefficient 0"""
+    kind, dst, na, terms = op
+    assert 0 <= dst < 4096 and len(terms) <= NTERM and 0 <= na <= NTERM
+    x = kind | (dst << 2) | (na << 14)
+    for i, (s, c) in enumerate(terms):
+        assert 0 <= s < 4096 and -KMAX <= c <= KMAX
+        x |= ((s | ((c & 31) << 12)) << (17 + 17 * i))
+    return x
+
+
+def build_all():
+    mk = Kernel("ml", miller_programs(), MILLER_STATE)
+    fe_state = ["t", "tinv"] + ["%s.%d" % (nm, k) for nm in ("nA", "nB", "nC", "n2") for k in (0, 1)]
+    fk = Kernel("fe", fe_programs(), fe_state, segs={"X": 1, "Y": 2, "D": 3})
+    return mk, fk
+
+
+# ============================================================================ emission
+def limbs(x):
+    return [(x >> (32 * i)) & 0xFFFFFFFF for i in range(8)]
+
+
+def emit(kernels):
+    o = []
+    w = o.append
+    w("// Generated by gen_slp.py -- straight-line programs for the wave-cooperative engine.")
+    w("#pragma once")
+    w("#include <cstdint>")
+    w("namespace slp {")
+    allops = []
+    descs = []
+    for k in kernels:
+        w("// kernel %s: %d slots (%d state, %d constants)" % (k.name, k.nslots, len(k.state), len(k.consts)))
+        w("static constexpr int %s_NSLOT = %d;" % (k.name.upper(), k.nslots))
+        w("static constexpr int %s_CBASE = %d;" % (k.name.upper(), k.cbase))
+        w("static constexpr int %s_NCONST = %d;" % (k.name.upper(), len(k.consts)))
+        for nm, s in k.state.items():
+            w("static constexpr int %s_%s = %d;" % (k.name.upper(), nm.replace(".", "_"), s))
+        for nm, enc in k.progs.items():
+            width = max(1, max(len(r) for r in enc))
+            descs.append((k.name, nm, len(allops), len(enc), width))
+            w("static constexpr int PROG_%s = %d;" % (nm.upper(), len(descs) - 1))
+            for row in enc:
+                allops += [encode_op(op) for op in row] + [0] * (width - len(row))
+    w("struct ProgDesc { uint32_t off; uint16_t nlev; uint16_t width; };")
+    w("__device__ const ProgDesc PROGS[%d] = {" % len(descs))
+    for kn, nm, off, nlev, width in descs:
+        w("  {%du, %du, %du},  // %s" % (off, nlev, width, nm))
+    w("};")
+    w("__device__ const uint64_t OPS[%d][2] = {" % len(allops))
+    for i in range(0, len(allops), 3):
+        w("  " + ", ".join("{0x%016xull, 0x%016xull}" % (x & (2**64 - 1), x >> 64) for x in allops[i:i + 3]) + ",")
+    w("};")
+    for k in kernels:
+        w("__device__ const uint32_t %s_CONSTS[%d][8] = {" % (k.name.upper(), len(k.consts)))
+        for x in k.consts:
+            w("  {%s}," % ", ".join("0x%08xu" % v for v in limbs(x * RMONT % P)))
+        w("};")
+    mk = kernels[0]
+    seq = miller_sequence()
+    w("static constexpr int ML_SEQ_LEN = %d;" % len(seq))
+    w("__device__ const uint8_t ML_SEQ[%d] = {%s};" % (len(seq), ", ".join("PROG_%s" % s.upper() for s in seq)))
+    seqf, res_buf, nb = fe_sequence()
+    w("static constexpr int FE_NBUF = %d;" % nb)
+    w("static constexpr int FE_RESULT = %d;" % res_buf)
+    w("static constexpr int FE_SEQ_LEN = %d;" % len(seqf))
+    w("static constexpr int PROG_INV = 255;")
+    w("__device__ const uint8_t FE_SEQ[%d][4] = {" % len(seqf))
+    for prog, X, Y, D in seqf:
+        w("  {%s, %d, %d, %d}," % ("PROG_INV" if prog == "INV" else "PROG_%s" % prog.upper(), X, Y, D))
+    w("};")
+    w("}  // namespace slp")
+    return "\n".join(o) + "\n"
+
+
+# ============================================================================ checks
+def run_levels(levels, S, segbase=(0, 0, 0, 0, 0, 0, 0, 0)):
+    def res(x):
+        return segbase[x >> 9] + (x & 511) if x >> 9 else x
+    for row in levels:
+        out = []
+        for kind, dst, na, terms in row:
+            if kind == OP_MUL:
+                a = sum(c * S[res(s)] for s, c in terms[:na])
+                b = sum(c * S[res(s)] for s, c in terms[na:])
+                out.append((res(dst), a * b % P))
+            else:
+                out.append((res(dst), sum(c * S[res(s)] for s, c in terms) % P))
+        for d, v in out:
+            S[d] = v
+
+
+# plain reference: F_p12 as F_p2[w] / (w^6 - xi); coefficient j = 3h + q is w^{2q + h}
+def ref_from_mem(cs):
+    poly = [None] * 6
+    for j in range(6):
+        h, q = divmod(j, 3)
+        poly[2 * q + h] = (cs[2 * j] % P, cs[2 * j + 1] % P)
+    return poly
+
+
+def ref_to_mem(poly):
+    cs = [0] * 12
+    for k in range(6):
+        q, h = divmod(k, 2)
+        j = 3 * h + q
+        cs[2 * j], cs[2 * j + 1] = poly[k]
+    return cs
+
+
+def ref_mul(a, b):
+    acc = [(0, 0)] * 11
+    for i in range(6):
+        for j in range(6):
+            t = f2mul_int(a[i], b[j])
+            acc[i + j] = ((acc[i + j][0] + t[0]) % P, (acc[i + j][1] + t[1]) % P)
+    out = list(acc[:6])
+    for k in range(6, 11):
+        t = f2mul_int(acc[k], XI)
+        out[k - 6] = ((out[k - 6][0] + t[0]) % P, (out[k - 6][1] + t[1]) % P)
+    return out
+
+
+def ref_pow(a, e):
+    r = [(1, 0)] + [(0, 0)] * 5
+    while e:
+        if e & 1:
+            r = ref_mul(r, a)
+        a = ref_mul(a, a)
+        e >>= 1
+    return r
+
+
+def ref_conj(a):  # w -> -w
+    return [(c[0], c[1]) if k % 2 == 0 else ((-c[0]) % P, (-c[1]) % P) for k, c in enumerate(a)]
+
+
+def ref_frob(a):
+    """x -> x^p: coefficient k gets conj(c) gamma1[k]"""
+    return [f2mul_int((c[0], (-c[1]) % P), GAM1[k]) for k, c in enumerate(a)]
+
+
+def ref_inv(a):
+    return ref_pow(a, P**12 - 2)
+
+
+def ref_miller(xP, yP, Q):
+    """affine Miller loop of the optimal ate pairing, lines in the w-polynomial form"""
+    def add_aff(T, S):
+        (x1, y1), (x2, y2) = T, S
+        if T == S:
+            lam = f2mul_int(f2mul_int((3, 0), f2mul_int(x1, x1)), f2inv_int(f2mul_int((2, 0), y1)))
+        else:
+            lam = f2mul_int(((y2[0] - y1[0]) % P, (y2[1] - y1[1]) % P), f2inv_int(((x2[0] - x1[0]) % P, (x2[1] - x1[1]) % P)))
+        x3 = ((f2mul_int(lam, lam)[0] - x1[0] - x2[0]) % P, (f2mul_int(lam, lam)[1] - x1[1] - x2[1]) % P)
+        t = f2mul_int(lam, ((x1[0] - x3[0]) % P, (x1[1] - x3[1]) % P))
+        y3 = ((t[0] - y1[0]) % P, (t[1] - y1[1]) % P)
+        # line yP - lam xP w + (lam x1 - y1) w^3
+        l = [(0, 0)] * 6
+        l[0] = (yP, 0)
+        lx = f2mul_int(lam, (xP, 0))
+        l[1] = ((-lx[0]) % P, (-lx[1]) % P)
+        m = f2mul_int(lam, x1)
+        l[3] = ((m[0] - y1[0]) % P, (m[1] - y1[1]) % P)
+        return (x3, y3), l
+    f = [(1, 0)] + [(0, 0)] * 5
+    T = Q
+    negQ = (Q[0], (0, 0) if Q[1] == (0, 0) else ((-Q[1][0]) % P, (-Q[1][1]) % P))
+    for d in ATE_NAF[1:]:
+        f = ref_mul(f, f)
+        T, l = add_aff(T, T)
+        f = ref_mul(f, l)
+        if d:
+            T, l = add_aff(T, Q if d == 1 else negQ)
+            f = ref_mul(f, l)
+    Q1 = (f2mul_int((Q[0][0], (-Q[0][1]) % P), FROB_TX), f2mul_int((Q[1][0], (-Q[1][1]) % P), FROB_TY))
+    Q2 = (f2mul_int(Q[0], FROB2_TX), f2mul_int(Q[1], ((-FROB2_TY[0]) % P, 0)))
+    T, l = add_aff(T, Q1)
+    f = ref_mul(f, l)
+    T, l = add_aff(T, Q2)
+    f = ref_mul(f, l)
+    return f
+
+
+def check():
+    rng = random.Random(5)
+    mk, fk = build_all()
+    for k in (mk, fk):
+        for nm, enc in k.progs.items():
+            nmul = sum(1 for r in enc for op in r if op[0] == OP_MUL)
+            nmlev = sum(1 for r in enc if any(op[0] == OP_MUL for op in r))
+            print("%-22s levels %4d  mul-levels %3d  MUL %5d  LIN %5d  width %2d" %
+                  (nm, len(enc), nmlev, nmul, sum(len(r) for r in enc) - nmul, max(len(r) for r in enc)),
+                  file=sys.stderr)
+        print("kernel %s: %d slots" % (k.name, k.nslots), file=sys.stderr)
+    # F_p12 programs against the polynomial reference
+    fprogs = fe_programs()
+    base = {"X": fk.nslots, "Y": fk.nslots + 12, "D": fk.nslots + 24}
+    seg = (0, base["X"], base["Y"], base["D"], 0, 0, 0, 0)
+    for trial in range(3):
+        S = [rng.randrange(P) for _ in range(fk.nslots + 36)]
+        for x, s in fk.cslot.items():
+            S[s] = x
+        X = S[base["X"]:base["X"] + 12]
+        Y = S[base["Y"]:base["Y"] + 12]
+        rx, ry = ref_from_mem(X), ref_from_mem(Y)
+        cyc = ref_mul(ref_conj(rx), ref_inv(rx))
+        cyc = ref_mul(ref_frob(ref_frob(cyc)), cyc)        # cyclotomic element
+        want = {"f12_mul": ref_mul(rx, ry), "f12_frob1": ref_frob(rx), "f12_frob2": ref_frob(ref_frob(rx)),
+                "f12_frob3": ref_frob(ref_frob(ref_frob(rx))), "f12_conj": ref_conj(rx),
+                "f12_conj_mul": ref_mul(ref_conj(rx), ry), "f12_frob2_mul": ref_mul(ref_frob(ref_frob(rx)), ry)}
+        for nm, wv in want.items():
+            S2 = list(S)
+            run_levels(fk.progs[nm], S2, seg)
+            got = S2[base["D"]:base["D"] + 12]
+            assert got == ref_to_mem(wv), nm
+        # cyclotomic squaring on a cyclotomic input
+        S2 = list(S)
+        S2[base["X"]:base["X"] + 12] = ref_to_mem(cyc)
+        run_levels(fk.progs["f12_csqr"], S2, seg)
+        assert S2[base["D"]:base["D"] + 12] == ref_to_mem(ref_mul(cyc, cyc)), "csqr"
+        S2 = list(S)
+        S2[base["X"]:base["X"] + 12] = ref_to_mem(cyc)
+        run_levels(fk.progs["f12_csqr_mul"], S2, seg)
+        assert S2[base["D"]:base["D"] + 12] == ref_to_mem(ref_mul(ref_mul(cyc, cyc), ry)), "csqr_mul"
+        # norm + easy part
+        S2 = list(S)
+        run_levels(fk.progs["fe_norm"], S2, seg)
+        t = S2[fk.state["t"]]
+        S2[fk.state["tinv"]] = pow(t, -1, P)
+        run_levels(fk.progs["fe_easy"], S2, seg)
+        assert S2[base["D"]:base["D"] + 12] == ref_to_mem(ref_mul(ref_conj(rx), ref_inv(rx))), "easy part"
+    print("F_p12 programs ok", file=sys.stderr)
+    seqf, res_buf, nb = fe_sequence()
+    print("final exponentiation: %d calls, %d buffers, %d levels (%d with products)" % (
+        len(seqf), nb, sum(len(fk.progs[c[0]]) for c in seqf if c[0] != "INV"),
+        sum(1 for c in seqf if c[0] != "INV" for r in fk.progs[c[0]] if any(op[0] == OP_MUL for op in r))),
+        file=sys.stderr)
+    bufbase = fk.nslots
+    S = [0] * (bufbase + 12 * nb)
+    for x, sl in fk.cslot.items():
+        S[sl] = x
+    fin = [rng.randrange(P) for _ in range(12)]
+    S[bufbase:bufbase + 12] = fin
+    for prog, X, Y, D in seqf:
+        if prog == "INV":
+            S[fk.state["tinv"]] = pow(S[fk.state["t"]], -1, P)
+            continue
+        run_levels(fk.progs[prog], S, (0, bufbase + 12 * X, bufbase + 12 * Y, bufbase + 12 * D, 0, 0, 0, 0))
+    got = S[bufbase + 12 * res_buf:bufbase + 12 * res_buf + 12]
+    assert got == ref_to_mem(ref_pow(ref_from_mem(fin), (P**12 - 1) // R)), "final exponentiation"
+    print("final exponentiation ok", file=sys.stderr)
+    # Miller loop: pipelined programs vs the affine reference, compared after the
+    # final exponentiation (the two differ by factors in proper subfields)
+    g2 = ((10857046999023057135944570762232829481370756359578518086990519993285655852781,
+           11559732032986387107991004021392285783925812861821192530917403151452391805634),
+          (8495653923123431417604973247489272438418190587263600148770280649306958101930,
+           4082367875863433681332203403145435568316851327593401208105741076214120093531))
+    xP, yP = 1, 2
+    S = [0] * mk.nslots
+    for x, s in mk.cslot.items():
+        S[s] = x
+    st = mk.state
+    S[st["xP"]], S[st["yP"]] = xP, yP
+    S[st["xQ.0"]], S[st["xQ.1"]], S[st["yQ.0"]], S[st["yQ.1"]] = g2[0][0], g2[0][1], g2[1][0], g2[1][1]
+    for nm in miller_sequence():
+        run_levels(mk.progs[nm], S)
+    f = ref_from_mem([S[st["f.%d" % k]] for k in range(12)])
+    g = ref_miller(xP, yP, g2)
+    e = (P**12 - 1) // R
+    assert ref_pow(f, e) == ref_pow(g, e), "Miller loop"
+    print("Miller loop ok (%d bodies)" % len(miller_sequence()), file=sys.stderr)
+
+
+if __name__ == "__main__":
+    if "--check" in sys.argv:
+        check()
+    else:
+        sys.stdout.write(emit(list(build_all())))

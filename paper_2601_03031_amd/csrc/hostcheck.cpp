@@ -8,6 +8,7 @@
 #include "curve.hpp"
 #include "pairing.hpp"
 #include "hash.hpp"
+#include "slp.hpp"
 
 #define API extern "C" __attribute__((visibility("default")))
 
@@ -184,6 +185,55 @@ API void hc_merkle_node(const uint8_t l[32], const uint8_t r[32], uint8_t out[32
   }
   sha::merkle_node(o, lw, rw);
   for (int i = 0; i < 8; i++) { out[4 * i] = o[i] >> 24; out[4 * i + 1] = o[i] >> 16; out[4 * i + 2] = o[i] >> 8; out[4 * i + 3] = o[i]; }
+}
+
+
+// ---- the wave-cooperative engine's programs through the host model of the interpreter
+static void ld_consts(fe *S, int base, const uint32_t (*C)[8], int n) {
+  for (int c = 0; c < n; c++) S[base + c] = fe_const(C[c]);
+}
+
+// Miller loop of the engine (before the final exponentiation)
+API int hc_slp_miller(const uint8_t *P, const uint8_t *Q, uint8_t *out) {
+  static fe S[slp::ML_NSLOT];
+  g1_aff p = rdg1(P);
+  g2_aff q = rdg2(Q);
+  S[slp::ML_xP] = p.x; S[slp::ML_xP + 1] = p.y;
+  S[slp::ML_xP + 2] = q.x.c0; S[slp::ML_xP + 3] = q.x.c1; S[slp::ML_xP + 4] = q.y.c0; S[slp::ML_xP + 5] = q.y.c1;
+  ld_consts(S, slp::ML_CBASE, slp::ML_CONSTS, slp::ML_NCONST);
+  for (int s = 0; s < slp::ML_SEQ_LEN; s++) slp::run_host(S, slp::ML_SEQ[s], 0, 0, 0);
+  fp12 f;
+  fe *fw = reinterpret_cast<fe *>(&f);
+  for (int k = 0; k < 12; k++) fw[k] = S[slp::ML_f_0 + k];
+  wr12(out, f);
+  return 0;
+}
+
+// final exponentiation (op 0) or F_p12 product of a and b (op 1) on the engine
+API int hc_slp_f12(int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
+  static fe S[slp::FE_NSLOT + 12 * slp::FE_NBUF];
+  auto buf = [](int k) { return slp::FE_NSLOT + 12 * k; };
+  fp12 x = rd12(a), y = rd12(b);
+  const fe *xw = reinterpret_cast<const fe *>(&x), *yw = reinterpret_cast<const fe *>(&y);
+  for (int k = 0; k < 12; k++) { S[buf(0) + k] = xw[k]; S[buf(1) + k] = yw[k]; }
+  ld_consts(S, slp::FE_CBASE, slp::FE_CONSTS, slp::FE_NCONST);
+  int res;
+  if (op == 1) {
+    slp::run_host(S, slp::PROG_F12_MUL, buf(0), buf(1), buf(2));
+    res = 2;
+  } else {
+    for (int e = 0; e < slp::FE_SEQ_LEN; e++) {
+      int prog = slp::FE_SEQ[e][0];
+      if (prog == slp::PROG_INV) { S[slp::FE_tinv] = fp_inv_fast(S[slp::FE_t]); continue; }
+      slp::run_host(S, prog, buf(slp::FE_SEQ[e][1]), buf(slp::FE_SEQ[e][2]), buf(slp::FE_SEQ[e][3]));
+    }
+    res = slp::FE_RESULT;
+  }
+  fp12 f;
+  fe *fw = reinterpret_cast<fe *>(&f);
+  for (int k = 0; k < 12; k++) fw[k] = S[buf(res) + k];
+  wr12(out, f);
+  return 0;
 }
 
 #ifdef VC_COUNT_MULS

@@ -1,0 +1,126 @@
+// Kernels on the wave-cooperative engine (slp.hpp): Miller loops, F_p12 product trees
+// and the final exponentiation, one 64-lane workgroup per pairing / product / element.
+#include "kcommon.hpp"
+#include "slp.hpp"
+
+#define SLP_T 64
+
+namespace {
+
+__device__ __forceinline__ bool g1_inf(const g1_aff &P) { return fe_is_zero(P.x) && fe_is_zero(P.y); }
+__device__ __forceinline__ bool g2_inf(const g2_aff &Q) {
+  return fe_is_zero(Q.x.c0) && fe_is_zero(Q.x.c1) && fe_is_zero(Q.y.c0) && fe_is_zero(Q.y.c1);
+}
+
+template <int NCONST>
+__device__ __forceinline__ void load_consts(fe *S, int base, const uint32_t (*C)[8]) {
+  for (int c = threadIdx.x; c < NCONST; c += SLP_T) S[base + c] = fe_const(C[c]);
+}
+
+// Miller loop of e(P, Q) into dst (12 coefficients); identity inputs give 1.
+__device__ void miller_one(fe *S, const g1_aff *P, const g2_aff *Q, fp12 *dst) {
+  const int t = threadIdx.x;
+  fe *out = reinterpret_cast<fe *>(dst);
+  if (g1_inf(*P) || g2_inf(*Q)) {
+    if (t < 12) out[t] = t == 0 ? f_one<FpP>() : fe_zero();
+    return;
+  }
+  if (t < 2) S[slp::ML_xP + t] = t ? P->y : P->x;
+  else if (t < 6) {
+    const fe *q = reinterpret_cast<const fe *>(Q);
+    S[slp::ML_xP + t] = q[t - 2];  // xQ.0, xQ.1, yQ.0, yQ.1
+  }
+  load_consts<slp::ML_NCONST>(S, slp::ML_CBASE, slp::ML_CONSTS);
+  __syncthreads();
+  for (int s = 0; s < slp::ML_SEQ_LEN; s++) slp::run(S, slp::ML_SEQ[s], 0, 0, 0);
+  if (t < 12) out[t] = S[slp::ML_f_0 + t];
+}
+
+}  // namespace
+
+// out[i] = Miller(P[i sp], Q[i sq])
+__global__ void __launch_bounds__(SLP_T) ks_miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n,
+                                                  fp12 *out) {
+  __shared__ fe S[slp::ML_NSLOT];
+  uint64_t i = blockIdx.x;
+  if (i >= n) return;
+  miller_one(S, P + i * sp, Q + i * sq, out + i);
+}
+
+// side 0 (L) pairs A[h+i] with V[i], side 1 (R) A[i] with V[h+i]; F[(2k+side) K/2 + i]
+__global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h,
+                                                     fp12 *F) {
+  __shared__ fe S[slp::ML_NSLOT];
+  uint64_t id = blockIdx.x;
+  if (id >= nb * 2 * h) return;
+  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
+  const g1_aff *P = A + (side ? k * K + i : k * K + h + i);
+  const g2_aff *Q = V + (side ? k * K + h + i : k * K + i);
+  miller_one(S, P, Q, F + (k * 2 + side) * (K / 2) + i);
+}
+
+#define FE_SLOTS (slp::FE_NSLOT + 12 * slp::FE_NBUF)
+#define FE_BUF(b) (slp::FE_NSLOT + 12 * (b))
+
+// one tree step, a workgroup per product: data[g stride + 2 s q] *= data[g stride + 2 s q + s]
+__global__ void __launch_bounds__(SLP_T) ks_f12_step(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint64_t s) {
+  __shared__ fe S[slp::FE_NSLOT + 36];
+  uint64_t per = (len + 2 * s - 1) / (2 * s);
+  uint64_t id = blockIdx.x;
+  if (id >= nseg * per) return;
+  uint64_t g = id / per, q = id % per;
+  uint64_t a = 2 * s * q, b = a + s;
+  if (b >= len) return;
+  fe *da = reinterpret_cast<fe *>(data + g * stride + a);
+  const fe *db = reinterpret_cast<const fe *>(data + g * stride + b);
+  int t = threadIdx.x;
+  if (t < 12) { S[slp::FE_NSLOT + t] = da[t]; S[slp::FE_NSLOT + 12 + t] = db[t]; }
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  slp::run(S, slp::PROG_F12_MUL, slp::FE_NSLOT, slp::FE_NSLOT + 12, slp::FE_NSLOT + 24);
+  if (t < 12) da[t] = S[slp::FE_NSLOT + 24 + t];
+}
+
+// f^((p^12 - 1)/r), a workgroup per input; input s at in[s in_stride], output to
+// (s odd ? out1 : out0)[(s >> 1) ostride]
+__global__ void __launch_bounds__(SLP_T) ks_final_exp(const fp12 *in, uint64_t in_stride, uint64_t n, fp12 *out0, fp12 *out1,
+                                                     uint64_t ostride) {
+  __shared__ fe S[FE_SLOTS];
+  uint64_t s = blockIdx.x;
+  if (s >= n) return;
+  int t = threadIdx.x;
+  const fe *src = reinterpret_cast<const fe *>(in + s * in_stride);
+  if (t < 12) S[FE_BUF(0) + t] = src[t];
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  for (int e = 0; e < slp::FE_SEQ_LEN; e++) {
+    int prog = slp::FE_SEQ[e][0];
+    if (prog == slp::PROG_INV) {
+      if (t == 0) S[slp::FE_tinv] = fp_inv_fast(S[slp::FE_t]);
+      __syncthreads();
+      continue;
+    }
+    slp::run(S, prog, FE_BUF(slp::FE_SEQ[e][1]), FE_BUF(slp::FE_SEQ[e][2]), FE_BUF(slp::FE_SEQ[e][3]));
+  }
+  fp12 *o = (s & 1) ? out1 : out0;
+  fe *dst = reinterpret_cast<fe *>(o + (s >> 1) * ostride);
+  if (t < 12) dst[t] = S[FE_BUF(slp::FE_RESULT) + t];
+}
+
+namespace ks {
+void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st) {
+  if (n) LAUNCH(ks_miller, dim3((unsigned)n), dim3(SLP_T), 0, P, sp, Q, sq, n, out);
+}
+void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st) {
+  LAUNCH(ks_oa_miller, dim3((unsigned)(nb * 2 * h)), dim3(SLP_T), 0, A, V, K, nb, h, F);
+}
+void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
+  for (uint64_t s = 1; s < len; s <<= 1) {
+    uint64_t per = (len + 2 * s - 1) / (2 * s);
+    LAUNCH(ks_f12_step, dim3((unsigned)(nseg * per)), dim3(SLP_T), 0, data, nseg, stride, len, s);
+  }
+}
+void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st) {
+  if (n) LAUNCH(ks_final_exp, dim3((unsigned)n), dim3(SLP_T), 0, in, stride, n, out0, out1, ostride);
+}
+}  // namespace ks

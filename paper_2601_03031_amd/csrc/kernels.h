@@ -73,3 +73,11 @@ void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_
 void dlevel(void *D, uint64_t K, uint32_t h, hipStream_t st);
 void diag_field(int which, int op, const void *a, const void *b, uint64_t n, void *out, hipStream_t st);
 }  // namespace klw
+
+// wave-cooperative engine (k_slp.hip): a 64-lane workgroup per pairing / product / element
+namespace ks {
+void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st);
+void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st);
+void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
+}  // namespace ks

@@ -89,7 +89,17 @@ struct vc_params {
   g2_aff *vk, *h, *g2gen;
   void *ws = nullptr;       // grow-only scratch shared by calls on these params
   size_t ws_size = 0;
+  // side streams (default priority) and fork/join events for independent phases
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev[8] = {};
 };
+
+// fork: `to` waits for the work issued so far on `from`
+static int stream_wait(vc_params *pp, int slot, hipStream_t from, hipStream_t to) {
+  CK(hipEventRecord(pp->ev[slot], from));
+  CK(hipStreamWaitEvent(to, pp->ev[slot], 0));
+  return VC_OK;
+}
 
 struct vc_commitment {
   const vc_params *pp;
@@ -143,6 +153,14 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   CK(hipSetDevice(device));
   vc_params *pp = new vc_params();
   pp->device = device;
+  for (auto &sd : pp->side) {
+    hipError_t e = hipStreamCreateWithFlags(&sd, hipStreamNonBlocking);
+    if (e != hipSuccess) { vc_params_free(pp); return hip_fail(e, "vc_setup stream"); }
+  }
+  for (auto &ev : pp->ev) {
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) { vc_params_free(pp); return hip_fail(e, "vc_setup event"); }
+  }
   pp->L = log_n;
   pp->lK = log_n / 2;
   pp->lM = log_n - pp->lK;
@@ -196,6 +214,10 @@ VC_API void vc_params_free(vc_params *pp) {
   hipSetDevice(pp->device);
   if (pp->mem) hipFree(pp->mem);
   if (pp->ws) hipFree(pp->ws);
+  for (auto sd : pp->side)
+    if (sd) hipStreamDestroy(sd);
+  for (auto ev : pp->ev)
+    if (ev) hipEventDestroy(ev);
   delete pp;
 }
 
@@ -240,9 +262,9 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   klw::sum_g1(part, K, nslice, cm->Cj, st);
   // FC.Commit: C = prod_j e(C_j, v[j]), v[j] = h[2j]
   fp12 *F = at<fp12>(ws, o_F);
-  klw::miller(cm->Cj, 1, pp->h, 2, K, F, st);
-  kl::f12_reduce(F, 1, K, K, st);
-  kl::final_exp(F, 1, 1, cm->C, nullptr, 1, st);
+  ks::miller(cm->Cj, 1, pp->h, 2, K, F, st);
+  ks::f12_reduce(F, 1, K, K, st);
+  ks::final_exp(F, 1, 1, cm->C, nullptr, 1, st);
   uint8_t *enc = at<uint8_t>(ws, o_enc);
   kl::encode(reinterpret_cast<const fe *>(cm->C), 12, 0, enc, st);
   CKL("vc_commit launch");
@@ -333,21 +355,52 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   CK(hipMemcpyAsync(C, cm->C, sizeof(fp12), hipMemcpyDeviceToDevice, st));
   CK(hipMemsetAsync(tree, 0, 32, st));  // heap node 0 is unused
 
-  // ---- Step 1: FC.BOpen for every block, all blocks in lockstep (Protocol 1, Eq. genFCBatchProof)
+  // ---- Step 2 runs on side stream 1, concurrently with Step 1: Merkle tree (Fiat-Shamir),
+  // randomized folding tree, HyperEval on g* (Protocol 1 Step 2 and its Sub-protocol)
+  hipStream_t s1 = pp->side[0], s2 = pp->side[1];
+  if (int rc2 = stream_wait(pp, 0, st, s1)) return rc2;
+  {
+    hipStream_t st_main = st;
+    hipStream_t st = s1;  // launches below go to side stream 1
+    kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
+    for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(tree, s, st);
+    kl::rho(C, tree, K, rho, st);
+    kl::ylevel0(cm->m, rho, M, N, Y, st);
+    for (uint32_t h = 1; h <= lK; h++) kl::ylevel(Y, M, K, h, st);
+    klw::g1_mul(Cj, 0, rho, K, D, st);
+    for (uint32_t h = 1; h <= lK; h++) klw::dlevel(D, K, h, st);
+    klw::hyper_terms(Y + (2 * K - 2) * M, pp->ek, M, lM, HS, st);
+    for (uint32_t d = 0; d < lM; d++) {
+      uint64_t half = M >> (d + 1);
+      g1_jac *base = HS + (uint64_t)d * (M / 2);
+      klw::g1_reduce(base, 1ull << d, half, half, st);
+      klw::g1_to_aff(base, half, 1ull << d, W + (1ull << d) - 1, 1, st);
+    }
+    (void)st_main;
+  }
+
+  // ---- Step 1: FC.BOpen for every block, all blocks in lockstep (Protocol 1, Eq. genFCBatchProof).
+  // Per round the pairing chain (Miller loops, product tree, final exponentiation) runs on the
+  // caller's stream while the G1 parts of L_j, R_j run on side stream 2; after the transcript
+  // the G1 fold runs on side stream 2 beside the G2 fold.
   kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
   kl::fc_chunks(Cj, K, b, nb, Hq, st);
   kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
   kl::fc_r(K, b, nb, sigma, B, st);
   for (uint32_t j = 1; j <= lK; j++) {
     uint64_t h = K >> j;
-    klw::oa_miller(A, V, K, nb, h, F, st);
-    kl::f12_reduce(F, 2 * nb, K / 2, h, st);
-    kl::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);  // segment 2k+side
-    klw::oa_g1terms(A, B, K, nb, h, S, st);
-    klw::g1_reduce(S, 2 * nb, K / 2, h, st);
+    if (int rc2 = stream_wait(pp, 1, st, s2)) return rc2;
+    klw::oa_g1terms(A, B, K, nb, h, S, s2);
+    klw::g1_reduce(S, 2 * nb, K / 2, h, s2);
+    ks::oa_miller(A, V, K, nb, h, F, st);
+    ks::f12_reduce(F, 2 * nb, K / 2, h, st);
+    ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
+    if (int rc2 = stream_wait(pp, 2, s2, st)) return rc2;
     kl::oa_transcript(S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
-    klw::oa_fold_g1(A, B, X, Xinv, K, nb, h, j, lK, st);
+    if (int rc2 = stream_wait(pp, 3, st, s2)) return rc2;
+    klw::oa_fold_g1(A, B, X, Xinv, K, nb, h, j, lK, s2);
     klw::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
+    if (int rc2 = stream_wait(pp, 4, s2, st)) return rc2;
   }
   CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
   CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
@@ -356,22 +409,8 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   klw::kzg_terms(pp->h, Q, K, nb, S2, st);
   klw::g2_reduce(S2, nb, nq, nq, st);
   klw::g2_to_aff(S2, nq, nb, piv, 1, st);
-
-  // ---- Step 2: Merkle tree (Fiat-Shamir), randomized folding tree, HyperEval on g*
-  kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
-  for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(tree, s, st);
-  kl::rho(C, tree, K, rho, st);
-  kl::ylevel0(cm->m, rho, M, N, Y, st);
-  for (uint32_t h = 1; h <= lK; h++) kl::ylevel(Y, M, K, h, st);
-  klw::g1_mul(Cj, 0, rho, K, D, st);
-  for (uint32_t h = 1; h <= lK; h++) klw::dlevel(D, K, h, st);
-  klw::hyper_terms(Y + (2 * K - 2) * M, pp->ek, M, lM, HS, st);
-  for (uint32_t d = 0; d < lM; d++) {
-    uint64_t half = M >> (d + 1);
-    g1_jac *base = HS + (uint64_t)d * (M / 2);
-    klw::g1_reduce(base, 1ull << d, half, half, st);
-    klw::g1_to_aff(base, half, 1ull << d, W + (1ull << d) - 1, 1, st);
-  }
+  // join Step 2
+  if (int rc2 = stream_wait(pp, 5, s1, st)) return rc2;
   CKL("vc_open_all launch");
   int herr = 0;
   CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -161,3 +161,25 @@ def test_hashes(hc):
     o = buf(32)
     hc.hc_merkle_node(m, c[:32], o)
     assert o.raw == hashlib.sha256(b"\x01" + m + c[:32]).digest()
+
+
+def test_engine_programs_on_host(hc):
+    """The engine's generated programs, run through the host model of its interpreter
+    (same operation decoder and arithmetic as the GPU kernels): Miller loop then the
+    oracle's final exponentiation equals the oracle's pairing; the engine's final
+    exponentiation and F_p12 product equal the oracle's."""
+    rng = random.Random(12)
+    g1, g2 = O.generators()
+    for _ in range(2):
+        A = O.g1_op("mul", g1, O.be32(rng.randrange(1, R)))
+        B = O.g2_op("mul", g2, O.be32(rng.randrange(1, R)))
+        f = buf(384)
+        assert hc.hc_slp_miller(A, B, f) == 0
+        assert O.fp12_op("final_exp", f.raw) == O.pairing([A], [B])
+    for _ in range(3):
+        x, y = rand12(rng), rand12(rng)
+        o = buf(384)
+        hc.hc_slp_f12(1, x, y, o)
+        assert o.raw == O.fp12_op("mul", x, y)
+        hc.hc_slp_f12(0, x, y, o)
+        assert o.raw == O.fp12_op("final_exp", x)
