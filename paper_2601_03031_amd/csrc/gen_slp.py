@@ -986,6 +986,28 @@ def limbs(x):
     return [(x >> (32 * i)) & 0xFFFFFFFF for i in range(8)]
 
 
+M29 = (1 << 29) - 1
+OFF_MULT = 5760           # offset multiple of p added to every linear combination
+
+
+def limbs29(x):
+    return [(x >> (29 * i)) & M29 for i in range(9)]
+
+
+def emit_radix():
+    """constants of the radix-2^29 lane arithmetic"""
+    o = []
+    o.append("static constexpr uint32_t P29[9] = {%s};" % ", ".join("0x%08xu" % v for v in limbs29(P)))
+    o.append("static constexpr uint32_t PINV29 = 0x%08xu;  // -p^{-1} mod 2^29" % ((-pow(P, -1, 1 << 29)) % (1 << 29)))
+    off = OFF_MULT * P
+    ol = [(off >> (29 * i)) & M29 for i in range(8)] + [off >> 232]
+    o.append("static constexpr int64_t OFF29[9] = {%s};  // %d p: limbs 0..7, then everything from bit 232" % (
+        ", ".join("%dll" % v for v in ol), OFF_MULT))
+    assert P >> 232 < (1 << 29)
+    o.append("static constexpr double INVP232 = %r;  // 2^232 / p" % (float(2**232) / P))
+    return o
+
+
 def emit(kernels):
     o = []
     w = o.append
@@ -993,6 +1015,8 @@ def emit(kernels):
     w("#pragma once")
     w("#include <cstdint>")
     w("namespace slp {")
+    for line in emit_radix():
+        w(line)
     allops = []
     descs = []
     for k in kernels:
@@ -1018,14 +1042,15 @@ def emit(kernels):
         w("  " + ", ".join("{0x%016xull, 0x%016xull}" % (x & (2**64 - 1), x >> 64) for x in allops[i:i + 3]) + ",")
     w("};")
     for k in kernels:
-        w("__device__ const uint32_t %s_CONSTS[%d][8] = {" % (k.name.upper(), len(k.consts)))
+        w("__device__ const uint32_t %s_CONSTS[%d][9] = {" % (k.name.upper(), len(k.consts)))
         for x in k.consts:
-            w("  {%s}," % ", ".join("0x%08xu" % v for v in limbs(x * RMONT % P)))
+            w("  {%s}," % ", ".join("0x%08xu" % v for v in limbs29(x * RMONT % P)))
         w("};")
     mk = kernels[0]
     seq = miller_sequence()
     w("static constexpr int ML_SEQ_LEN = %d;" % len(seq))
-    w("__device__ const uint8_t ML_SEQ[%d] = {%s};" % (len(seq), ", ".join("PROG_%s" % s.upper() for s in seq)))
+    w("__device__ const uint8_t ML_SEQ[%d][1] = {%s};" % (len(seq), ", ".join("{PROG_%s}" % s.upper() for s in seq)))
+    w("__device__ const uint8_t F12_MUL_CALL[1][4] = {{PROG_F12_MUL, 0, 1, 2}};")
     seqf, res_buf, nb = fe_sequence()
     w("static constexpr int FE_NBUF = %d;" % nb)
     w("static constexpr int FE_RESULT = %d;" % res_buf)

@@ -189,33 +189,36 @@ API void hc_merkle_node(const uint8_t l[32], const uint8_t r[32], uint8_t out[32
 
 
 // ---- the wave-cooperative engine's programs through the host model of the interpreter
-static void ld_consts(fe *S, int base, const uint32_t (*C)[8], int n) {
-  for (int c = 0; c < n; c++) S[base + c] = fe_const(C[c]);
+static void ld_consts(slp::f29 *S, int base, const uint32_t (*C)[9], int n) {
+  for (int c = 0; c < n; c++) {
+    for (int j = 0; j < 9; j++) S[base + c].l[j] = C[c][j];
+    S[base + c].l[9] = S[base + c].l[10] = S[base + c].l[11] = 0;
+  }
 }
 
 // Miller loop of the engine (before the final exponentiation)
 API int hc_slp_miller(const uint8_t *P, const uint8_t *Q, uint8_t *out) {
-  static fe S[slp::ML_NSLOT];
+  static slp::f29 S[slp::ML_NSLOT];
   g1_aff p = rdg1(P);
   g2_aff q = rdg2(Q);
-  S[slp::ML_xP] = p.x; S[slp::ML_xP + 1] = p.y;
-  S[slp::ML_xP + 2] = q.x.c0; S[slp::ML_xP + 3] = q.x.c1; S[slp::ML_xP + 4] = q.y.c0; S[slp::ML_xP + 5] = q.y.c1;
+  const fe in[6] = {p.x, p.y, q.x.c0, q.x.c1, q.y.c0, q.y.c1};
+  for (int k = 0; k < 6; k++) S[slp::ML_xP + k] = slp::to29(in[k]);
   ld_consts(S, slp::ML_CBASE, slp::ML_CONSTS, slp::ML_NCONST);
-  for (int s = 0; s < slp::ML_SEQ_LEN; s++) slp::run_host(S, slp::ML_SEQ[s], 0, 0, 0);
+  for (int s = 0; s < slp::ML_SEQ_LEN; s++) slp::run_host(S, slp::ML_SEQ[s][0], 0, 0, 0);
   fp12 f;
   fe *fw = reinterpret_cast<fe *>(&f);
-  for (int k = 0; k < 12; k++) fw[k] = S[slp::ML_f_0 + k];
+  for (int k = 0; k < 12; k++) fw[k] = slp::from29(slp::canon29(S[slp::ML_f_0 + k]));
   wr12(out, f);
   return 0;
 }
 
 // final exponentiation (op 0) or F_p12 product of a and b (op 1) on the engine
 API int hc_slp_f12(int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
-  static fe S[slp::FE_NSLOT + 12 * slp::FE_NBUF];
+  static slp::f29 S[slp::FE_NSLOT + 12 * slp::FE_NBUF];
   auto buf = [](int k) { return slp::FE_NSLOT + 12 * k; };
   fp12 x = rd12(a), y = rd12(b);
   const fe *xw = reinterpret_cast<const fe *>(&x), *yw = reinterpret_cast<const fe *>(&y);
-  for (int k = 0; k < 12; k++) { S[buf(0) + k] = xw[k]; S[buf(1) + k] = yw[k]; }
+  for (int k = 0; k < 12; k++) { S[buf(0) + k] = slp::to29(xw[k]); S[buf(1) + k] = slp::to29(yw[k]); }
   ld_consts(S, slp::FE_CBASE, slp::FE_CONSTS, slp::FE_NCONST);
   int res;
   if (op == 1) {
@@ -224,15 +227,48 @@ API int hc_slp_f12(int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
   } else {
     for (int e = 0; e < slp::FE_SEQ_LEN; e++) {
       int prog = slp::FE_SEQ[e][0];
-      if (prog == slp::PROG_INV) { S[slp::FE_tinv] = fp_inv_fast(S[slp::FE_t]); continue; }
+      if (prog == slp::PROG_INV) { S[slp::FE_tinv] = slp::to29(fp_inv_fast(slp::from29(slp::canon29(S[slp::FE_t])))); continue; }
       slp::run_host(S, prog, buf(slp::FE_SEQ[e][1]), buf(slp::FE_SEQ[e][2]), buf(slp::FE_SEQ[e][3]));
     }
     res = slp::FE_RESULT;
   }
   fp12 f;
   fe *fw = reinterpret_cast<fe *>(&f);
-  for (int k = 0; k < 12; k++) fw[k] = S[buf(res) + k];
+  for (int k = 0; k < 12; k++) fw[k] = slp::from29(slp::canon29(S[buf(res) + k]));
   wr12(out, f);
+  return 0;
+}
+
+
+// radix-2^29 lane arithmetic on raw integers (big-endian 32 bytes, below 2p):
+// op 0: sum_i k_i x_i mod p (reduced to [0, 2p), then canonical); op 1: Montgomery
+// product a b 2^{-261} (canonical); op 2: the raw almost-reduced linear combination
+static fe rd_raw(const uint8_t *b) {
+  fe a;
+  for (int i = 0; i < 8; i++)
+    a.l[7 - i] = ((uint32_t)b[4 * i] << 24) | ((uint32_t)b[4 * i + 1] << 16) | ((uint32_t)b[4 * i + 2] << 8) | b[4 * i + 3];
+  return a;
+}
+static void wr_raw(uint8_t *b, const fe &a) {
+  for (int i = 0; i < 8; i++) {
+    uint32_t w = a.l[7 - i];
+    b[4 * i] = w >> 24; b[4 * i + 1] = w >> 16; b[4 * i + 2] = w >> 8; b[4 * i + 3] = w;
+  }
+}
+API int hc_slp_lane(int op, int n, const int *k, const uint8_t *xs, uint8_t *out) {
+  if (op == 1) {
+    slp::f29 r = slp::canon29(slp::mont29(slp::to29(rd_raw(xs)), slp::to29(rd_raw(xs + 32))));
+    wr_raw(out, slp::from29(r));
+    return 0;
+  }
+  int64_t acc[9];
+  for (int j = 0; j < 9; j++) acc[j] = slp::OFF29[j];
+  for (int i = 0; i < n; i++) {
+    slp::f29 x = slp::to29(rd_raw(xs + 32 * i));
+    for (int j = 0; j < 9; j++) acc[j] += (int64_t)k[i] * (int32_t)x.l[j];
+  }
+  slp::f29 r = slp::red29(acc);
+  wr_raw(out, slp::from29(op == 2 ? r : slp::canon29(r)));
   return 0;
 }
 

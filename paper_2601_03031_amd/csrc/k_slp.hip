@@ -12,28 +12,36 @@ __device__ __forceinline__ bool g2_inf(const g2_aff &Q) {
   return fe_is_zero(Q.x.c0) && fe_is_zero(Q.x.c1) && fe_is_zero(Q.y.c0) && fe_is_zero(Q.y.c1);
 }
 
+using slp::f29;
+
 template <int NCONST>
-__device__ __forceinline__ void load_consts(fe *S, int base, const uint32_t (*C)[8]) {
-  for (int c = threadIdx.x; c < NCONST; c += SLP_T) S[base + c] = fe_const(C[c]);
+__device__ __forceinline__ void load_consts(f29 *S, int base, const uint32_t (*C)[9]) {
+  for (int c = threadIdx.x; c < NCONST; c += SLP_T) {
+    f29 v;
+#pragma unroll
+    for (int j = 0; j < 9; j++) v.l[j] = C[c][j];
+    v.l[9] = v.l[10] = v.l[11] = 0;
+    S[base + c] = v;
+  }
 }
 
 // Miller loop of e(P, Q) into dst (12 coefficients); identity inputs give 1.
-__device__ void miller_one(fe *S, const g1_aff *P, const g2_aff *Q, fp12 *dst) {
+__device__ void miller_one(f29 *S, const g1_aff *P, const g2_aff *Q, fp12 *dst) {
   const int t = threadIdx.x;
   fe *out = reinterpret_cast<fe *>(dst);
   if (g1_inf(*P) || g2_inf(*Q)) {
     if (t < 12) out[t] = t == 0 ? f_one<FpP>() : fe_zero();
     return;
   }
-  if (t < 2) S[slp::ML_xP + t] = t ? P->y : P->x;
+  if (t < 2) S[slp::ML_xP + t] = slp::to29(t ? P->y : P->x);
   else if (t < 6) {
     const fe *q = reinterpret_cast<const fe *>(Q);
-    S[slp::ML_xP + t] = q[t - 2];  // xQ.0, xQ.1, yQ.0, yQ.1
+    S[slp::ML_xP + t] = slp::to29(q[t - 2]);  // xQ.0, xQ.1, yQ.0, yQ.1
   }
   load_consts<slp::ML_NCONST>(S, slp::ML_CBASE, slp::ML_CONSTS);
   __syncthreads();
-  for (int s = 0; s < slp::ML_SEQ_LEN; s++) slp::run(S, slp::ML_SEQ[s], 0, 0, 0);
-  if (t < 12) out[t] = S[slp::ML_f_0 + t];
+  slp::run_seq<1>(S, slp::ML_SEQ, slp::ML_SEQ_LEN, 0, 0, 0);
+  if (t < 12) out[t] = slp::from29(slp::canon29(S[slp::ML_f_0 + t]));
 }
 
 }  // namespace
@@ -41,7 +49,7 @@ __device__ void miller_one(fe *S, const g1_aff *P, const g2_aff *Q, fp12 *dst) {
 // out[i] = Miller(P[i sp], Q[i sq])
 __global__ void __launch_bounds__(SLP_T) ks_miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n,
                                                   fp12 *out) {
-  __shared__ fe S[slp::ML_NSLOT];
+  __shared__ f29 S[slp::ML_NSLOT];
   uint64_t i = blockIdx.x;
   if (i >= n) return;
   miller_one(S, P + i * sp, Q + i * sq, out + i);
@@ -50,7 +58,7 @@ __global__ void __launch_bounds__(SLP_T) ks_miller(const g1_aff *P, uint64_t sp,
 // side 0 (L) pairs A[h+i] with V[i], side 1 (R) A[i] with V[h+i]; F[(2k+side) K/2 + i]
 __global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h,
                                                      fp12 *F) {
-  __shared__ fe S[slp::ML_NSLOT];
+  __shared__ f29 S[slp::ML_NSLOT];
   uint64_t id = blockIdx.x;
   if (id >= nb * 2 * h) return;
   uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
@@ -64,7 +72,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_
 
 // one tree step, a workgroup per product: data[g stride + 2 s q] *= data[g stride + 2 s q + s]
 __global__ void __launch_bounds__(SLP_T) ks_f12_step(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint64_t s) {
-  __shared__ fe S[slp::FE_NSLOT + 36];
+  __shared__ f29 S[slp::FE_NSLOT + 36];
   uint64_t per = (len + 2 * s - 1) / (2 * s);
   uint64_t id = blockIdx.x;
   if (id >= nseg * per) return;
@@ -74,37 +82,29 @@ __global__ void __launch_bounds__(SLP_T) ks_f12_step(fp12 *data, uint64_t nseg, 
   fe *da = reinterpret_cast<fe *>(data + g * stride + a);
   const fe *db = reinterpret_cast<const fe *>(data + g * stride + b);
   int t = threadIdx.x;
-  if (t < 12) { S[slp::FE_NSLOT + t] = da[t]; S[slp::FE_NSLOT + 12 + t] = db[t]; }
+  if (t < 12) { S[slp::FE_NSLOT + t] = slp::to29(da[t]); S[slp::FE_NSLOT + 12 + t] = slp::to29(db[t]); }
   load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
   __syncthreads();
-  slp::run(S, slp::PROG_F12_MUL, slp::FE_NSLOT, slp::FE_NSLOT + 12, slp::FE_NSLOT + 24);
-  if (t < 12) da[t] = S[slp::FE_NSLOT + 24 + t];
+  slp::run_seq<4>(S, slp::F12_MUL_CALL, 1, slp::FE_NSLOT, 0, 0);
+  if (t < 12) da[t] = slp::from29(slp::canon29(S[slp::FE_NSLOT + 24 + t]));
 }
 
 // f^((p^12 - 1)/r), a workgroup per input; input s at in[s in_stride], output to
 // (s odd ? out1 : out0)[(s >> 1) ostride]
 __global__ void __launch_bounds__(SLP_T) ks_final_exp(const fp12 *in, uint64_t in_stride, uint64_t n, fp12 *out0, fp12 *out1,
                                                      uint64_t ostride) {
-  __shared__ fe S[FE_SLOTS];
+  __shared__ f29 S[FE_SLOTS];
   uint64_t s = blockIdx.x;
   if (s >= n) return;
   int t = threadIdx.x;
   const fe *src = reinterpret_cast<const fe *>(in + s * in_stride);
-  if (t < 12) S[FE_BUF(0) + t] = src[t];
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
   load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
   __syncthreads();
-  for (int e = 0; e < slp::FE_SEQ_LEN; e++) {
-    int prog = slp::FE_SEQ[e][0];
-    if (prog == slp::PROG_INV) {
-      if (t == 0) S[slp::FE_tinv] = fp_inv_fast(S[slp::FE_t]);
-      __syncthreads();
-      continue;
-    }
-    slp::run(S, prog, FE_BUF(slp::FE_SEQ[e][1]), FE_BUF(slp::FE_SEQ[e][2]), FE_BUF(slp::FE_SEQ[e][3]));
-  }
+  slp::run_seq<4>(S, slp::FE_SEQ, slp::FE_SEQ_LEN, slp::FE_NSLOT, slp::FE_t, slp::FE_tinv);
   fp12 *o = (s & 1) ? out1 : out0;
   fe *dst = reinterpret_cast<fe *>(o + (s >> 1) * ostride);
-  if (t < 12) dst[t] = S[FE_BUF(slp::FE_RESULT) + t];
+  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(slp::FE_RESULT) + t]));
 }
 
 namespace ks {

@@ -183,3 +183,33 @@ def test_engine_programs_on_host(hc):
         assert o.raw == O.fp12_op("mul", x, y)
         hc.hc_slp_f12(0, x, y, o)
         assert o.raw == O.fp12_op("final_exp", x)
+
+
+def test_engine_lane_arithmetic(hc):
+    """Radix-2^29 lane arithmetic of the engine on edge and random inputs below 2p
+    (slot values are almost reduced): linear combinations with coefficients up to the
+    product-operand scale (32 x 15) and Montgomery products with R = 2^261."""
+    rng = random.Random(13)
+    edge = [0, 1, P - 1, P, P + 1, 2 * P - 1, (1 << 254) - 1 if (1 << 254) - 1 < 2 * P else 2 * P - 2]
+    for trial in range(3000):
+        n = rng.randrange(1, 7)
+        kmax = 480 if trial % 2 else 15
+        ks = [rng.randrange(-kmax, kmax + 1) for _ in range(n)]
+        if trial % 7 == 0:
+            ks = [rng.choice([-kmax, kmax]) for _ in range(n)]
+        xs = [rng.choice(edge) if rng.random() < 0.3 else rng.randrange(2 * P) for _ in range(n)]
+        karr = (C.c_int * 6)(*ks)
+        blob = b"".join(x.to_bytes(32, "big") for x in xs)
+        o = buf(32)
+        hc.hc_slp_lane(0, n, karr, blob, o)
+        assert int.from_bytes(o.raw, "big") == sum(k * x for k, x in zip(ks, xs)) % P, (ks, xs)
+        hc.hc_slp_lane(2, n, karr, blob, o)
+        raw = int.from_bytes(o.raw, "big")
+        assert raw < 2 * P and raw % P == sum(k * x for k, x in zip(ks, xs)) % P
+    rinv = pow(1 << 261, -1, P)
+    for trial in range(2000):
+        a = rng.choice(edge) if trial % 5 == 0 else rng.randrange(2 * P)
+        b = rng.choice(edge) if trial % 3 == 0 else rng.randrange(2 * P)
+        o = buf(32)
+        hc.hc_slp_lane(1, 2, None, a.to_bytes(32, "big") + b.to_bytes(32, "big"), o)
+        assert int.from_bytes(o.raw, "big") == a * b * rinv % P, (a, b)
