@@ -792,6 +792,160 @@ def fe_sequence():
     return seq, res, nbuf[0]
 
 
+# ============================================================================ G2 scalar multiplication (GLS)
+# psi(x, y) = (conj(x) tx, conj(y) ty) acts on G2 as multiplication by lam = p mod r = 6u^2.
+# A scalar k is split as k = sum_j k_j lam^j (mod r), |k_j| < 2^65, with the reduced lattice
+# basis below (rows b satisfy b0 + b1 lam + b2 lam^2 + b3 lam^3 = 0 mod r) and Babai rounding
+# with the constants G (c_i = floor(k G_i / 2^256), k_j = [j = 0] k - sum_i c_i b_ij).
+GLS_B = [[2 * U + 1, 0, 2 * U, 1], [2 * U, U + 1, -U, U], [U + 1, U, U, -2 * U], [2 * U + 1, -U, -(U + 1), -U]]
+
+
+def gls_constants():
+    from fractions import Fraction
+    n = 4
+    M = [[Fraction(x) for x in row] + [Fraction(int(i == j)) for j in range(n)] for i, row in enumerate(GLS_B)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[piv] = M[piv], M[c]
+        pv = M[c][c]
+        M[c] = [x / pv for x in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c]
+                M[r] = [a - f * b for a, b in zip(M[r], M[c])]
+    alpha = M[0][n:]
+    G = [round(a * 2**256) for a in alpha]
+    assert all(0 <= g < 2**192 for g in G)
+    return G
+
+
+def gls_decompose(k):
+    G = gls_constants()
+    c = [(k * g) >> 256 for g in G]
+    return [(k if j == 0 else 0) - sum(c[i] * GLS_B[i][j] for i in range(4)) for j in range(4)]
+
+
+def j_dbl(T):
+    X, Y, Z = T
+    A, B = X.sqr(), Y.sqr()
+    C = B.sqr()
+    D = ((X + B).sqr() - A - C).scale(2)
+    E = A.scale(3)
+    X3 = E.sqr() - D.scale(2)
+    Y3 = E.mul(D - X3) - C.scale(8)
+    Z3 = Y.mul(Z).scale(2)
+    return (X3, Y3, Z3)
+
+
+def j_add(T1, T2):
+    """add-2007-bl; returns the sum and (H, r): H = 0 means equal x, then r = 0 means equal points"""
+    X1, Y1, Z1 = T1
+    X2, Y2, Z2 = T2
+    Z1Z1, Z2Z2 = Z1.sqr(), Z2.sqr()
+    U1, U2 = X1.mul(Z2Z2), X2.mul(Z1Z1)
+    S1, S2 = Y1.mul(Z2).mul(Z2Z2), Y2.mul(Z1).mul(Z1Z1)
+    H = U2 - U1
+    I = H.scale(2).sqr()
+    J = H.mul(I)
+    rr = (S2 - S1).scale(2)
+    V = U1.mul(I)
+    X3 = rr.sqr() - J - V.scale(2)
+    Y3 = rr.mul(V - X3) - S1.mul(J).scale(2)
+    Z3 = ((Z1 + Z2).sqr() - Z1Z1 - Z2Z2).mul(H)
+    return (X3, Y3, Z3), H, S2 - S1
+
+
+def j_madd(T1, A):
+    """madd-2007-bl: T1 Jacobian plus A = (x2, y2) affine"""
+    X1, Y1, Z1 = T1
+    x2, y2 = A
+    Z1Z1 = Z1.sqr()
+    U2 = x2.mul(Z1Z1)
+    S2 = y2.mul(Z1).mul(Z1Z1)
+    H = U2 - X1
+    HH = H.sqr()
+    I = HH.scale(4)
+    J = H.mul(I)
+    rr = (S2 - Y1).scale(2)
+    V = X1.mul(I)
+    X3 = rr.sqr() - J - V.scale(2)
+    Y3 = rr.mul(V - X3) - Y1.mul(J).scale(2)
+    Z3 = (Z1 + H).sqr() - Z1Z1 - HH
+    return (X3, Y3, Z3), H, S2 - Y1
+
+
+def jac_in(p, name):
+    return tuple(F2(p.inp("%s.%d" % (name, 2 * c)), p.inp("%s.%d" % (name, 2 * c + 1))) for c in range(3))
+
+
+def jac_out(p, name, T):
+    for c, v in enumerate(T):
+        p.out("%s.%d" % (name, 2 * c), v.c0)
+        p.out("%s.%d" % (name, 2 * c + 1), v.c1)
+
+
+def g2_programs():
+    progs = {}
+    # psi images of Q (B0 = Q)
+    p = Prog("g2_psi")
+    Q = (f2_in(p, "xQ"), f2_in(p, "yQ"))
+    Bj = Q
+    for j in (1, 2, 3):
+        Bj = twist_frob(Bj)
+        f2_out(p, "B%d.x" % j, Bj[0])
+        f2_out(p, "B%d.y" % j, Bj[1])
+    progs[p.name] = p
+    # table TB[d] = sum_{j in d} B_j (Jacobian), the single-bit entries with Z = 1
+    p = Prog("g2_table")
+    one = F2(p.fconst(1), p.fconst(0))
+    B = [(f2_in(p, "xQ"), f2_in(p, "yQ"))] + [(f2_in(p, "B%d.x" % j), f2_in(p, "B%d.y" % j)) for j in range(1, 4)]
+    TB = {}
+    for j in range(4):
+        TB[1 << j] = (B[j][0], B[j][1], one)
+    for d in range(1, 16):
+        if d & (d - 1) == 0:
+            continue
+        lo = d & -d
+        TB[d], _, _ = j_add(TB[d - lo], TB[lo])
+    for d in range(1, 16):
+        jac_out(p, "TB%d" % d, TB[d])
+    progs[p.name] = p
+    p = Prog("g2_dbl")
+    jac_out(p, "T", j_dbl(jac_in(p, "T")))
+    progs[p.name] = p
+    p = Prog("g2_add")
+    T, H, r = j_add(jac_in(p, "T"), jac_in(p, "A"))
+    jac_out(p, "T", T)
+    f2_out(p, "H", H)
+    f2_out(p, "RR", r)
+    progs[p.name] = p
+    p = Prog("g2_madd")
+    T, H, r = j_madd(jac_in(p, "T"), (F2(p.inp("A.0"), p.inp("A.1")), F2(p.inp("A.2"), p.inp("A.3"))))
+    jac_out(p, "T", T)
+    f2_out(p, "H", H)
+    f2_out(p, "RR", r)
+    progs[p.name] = p
+    # to affine: t = N(Z); then Zi = conj(Z) / t, x = X Zi^2, y = Y Zi^3
+    p = Prog("g2_norm")
+    Z = F2(p.inp("T.4"), p.inp("T.5"))
+    p.out("t", Z.c0 * Z.c0 + Z.c1 * Z.c1)
+    progs[p.name] = p
+    p = Prog("g2_aff")
+    X, Y, Z = jac_in(p, "T")
+    Zi = Z.conj().mul_fp(p.inp("tinv"))
+    Zi2 = Zi.sqr()
+    f2_out(p, "ax", X.mul(Zi2))
+    f2_out(p, "ay", Y.mul(Zi2.mul(Zi)))
+    progs[p.name] = p
+    return progs
+
+
+G2_STATE = (["T.%d" % k for k in range(6)] + ["xQ.0", "xQ.1", "yQ.0", "yQ.1"]
+            + ["B%d.%s.%d" % (j, c, k) for j in range(1, 4) for c in "xy" for k in (0, 1)]
+            + ["TB%d.%d" % (d, k) for d in range(1, 16) for k in range(6)]
+            + ["H.0", "H.1", "RR.0", "RR.1", "t", "tinv", "ax.0", "ax.1", "ay.0", "ay.1"])
+
+
 # ============================================================================ scheduling
 def operands(v):
     if v[0] == "mul":
@@ -978,7 +1132,8 @@ def build_all():
     mk = Kernel("ml", miller_programs(), MILLER_STATE)
     fe_state = ["t", "tinv"] + ["%s.%d" % (nm, k) for nm in ("nA", "nB", "nC", "n2") for k in (0, 1)]
     fk = Kernel("fe", fe_programs(), fe_state, segs={"X": 1, "Y": 2, "D": 3})
-    return mk, fk
+    gk = Kernel("g2", g2_programs(), G2_STATE, segs={"A": 2})
+    return mk, fk, gk
 
 
 # ============================================================================ emission
@@ -1060,6 +1215,14 @@ def emit(kernels):
     for prog, X, Y, D in seqf:
         w("  {%s, %d, %d, %d}," % ("PROG_INV" if prog == "INV" else "PROG_%s" % prog.upper(), X, Y, D))
     w("};")
+    G = gls_constants()
+    w("// GLS decomposition on G2: lattice basis rows (signed) and rounding constants G_i")
+    w("static constexpr int64_t GLS_B_NEG[4][4] = {%s};" % ", ".join(
+        "{%s}" % ", ".join("%d" % (1 if x < 0 else 0) for x in row) for row in GLS_B))
+    w("static constexpr uint64_t GLS_B_ABS[4][4] = {%s};" % ", ".join(
+        "{%s}" % ", ".join("0x%xull" % abs(x) for x in row) for row in GLS_B))
+    w("static constexpr uint32_t GLS_G[4][6] = {%s};" % ", ".join(
+        "{%s}" % ", ".join("0x%08xu" % ((g >> (32 * i)) & 0xFFFFFFFF) for i in range(6)) for g in G))
     w("}  // namespace slp")
     return "\n".join(o) + "\n"
 
@@ -1175,8 +1338,8 @@ def ref_miller(xP, yP, Q):
 
 def check():
     rng = random.Random(5)
-    mk, fk = build_all()
-    for k in (mk, fk):
+    mk, fk, gk = build_all()
+    for k in (mk, fk, gk):
         for nm, enc in k.progs.items():
             nmul = sum(1 for r in enc for op in r if op[0] == OP_MUL)
             nmlev = sum(1 for r in enc if any(op[0] == OP_MUL for op in r))
@@ -1261,6 +1424,107 @@ def check():
     e = (P**12 - 1) // R
     assert ref_pow(f, e) == ref_pow(g, e), "Miller loop"
     print("Miller loop ok (%d bodies)" % len(miller_sequence()), file=sys.stderr)
+    check_g2(gk, rng)
+
+
+def f2add(a, b):
+    return ((a[0] + b[0]) % P, (a[1] + b[1]) % P)
+
+
+def f2sub(a, b):
+    return ((a[0] - b[0]) % P, (a[1] - b[1]) % P)
+
+
+def aff_add(A, B):
+    """affine addition on the twist (None = identity)"""
+    if A is None:
+        return B
+    if B is None:
+        return A
+    if A[0] == B[0]:
+        if f2add(A[1], B[1]) == (0, 0):
+            return None
+        lam = f2mul_int(f2mul_int((3, 0), f2mul_int(A[0], A[0])), f2inv_int(f2mul_int((2, 0), A[1])))
+    else:
+        lam = f2mul_int(f2sub(B[1], A[1]), f2inv_int(f2sub(B[0], A[0])))
+    x3 = f2sub(f2sub(f2mul_int(lam, lam), A[0]), B[0])
+    return (x3, f2sub(f2mul_int(lam, f2sub(A[0], x3)), A[1]))
+
+
+def aff_mul(A, k):
+    R_ = None
+    for bit in bin(k)[2:]:
+        R_ = aff_add(R_, R_)
+        if bit == "1":
+            R_ = aff_add(R_, A)
+    return R_
+
+
+G2GEN = ((10857046999023057135944570762232829481370756359578518086990519993285655852781,
+          11559732032986387107991004021392285783925812861821192530917403151452391805634),
+         (8495653923123431417604973247489272438418190587263600148770280649306958101930,
+          4082367875863433681332203403145435568316851327593401208105741076214120093531))
+
+
+def check_g2(gk, rng):
+    lam = P % R
+    st = gk.state
+    def setpt(S, name, pt):  # Jacobian with Z = 1 from affine
+        (x0, x1), (y0, y1) = pt
+        for k, v in enumerate((x0, x1, y0, y1, 1, 0)):
+            S[st["%s.%d" % (name, k)]] = v
+    def getaff(S, name):
+        v = [S[st["%s.%d" % (name, k)]] for k in range(6)]
+        X, Y, Z = (v[0], v[1]), (v[2], v[3]), (v[4], v[5])
+        if Z == (0, 0):
+            return None
+        zi = f2inv_int(Z)
+        zi2 = f2mul_int(zi, zi)
+        return (f2mul_int(X, zi2), f2mul_int(Y, f2mul_int(zi2, zi)))
+    for trial in range(2):
+        Q = aff_mul(G2GEN, rng.randrange(1, R))
+        S = [0] * gk.nslots
+        for x, sl in gk.cslot.items():
+            S[sl] = x
+        S[st["xQ.0"]], S[st["xQ.1"]], S[st["yQ.0"]], S[st["yQ.1"]] = Q[0][0], Q[0][1], Q[1][0], Q[1][1]
+        run_levels(gk.progs["g2_psi"], S)
+        for j in (1, 2, 3):
+            got = ((S[st["B%d.x.0" % j]], S[st["B%d.x.1" % j]]), (S[st["B%d.y.0" % j]], S[st["B%d.y.1" % j]]))
+            assert got == aff_mul(Q, pow(lam, j, R)), "psi"
+        run_levels(gk.progs["g2_table"], S)
+        for d in range(1, 16):
+            want = None
+            for j in range(4):
+                if d >> j & 1:
+                    want = aff_add(want, aff_mul(Q, pow(lam, j, R)))
+            assert getaff(S, "TB%d" % d) == want, ("table", d)
+        # doubling, addition (with a Jacobian operand at segment 2), mixed addition, to affine
+        A = aff_mul(G2GEN, rng.randrange(1, R))
+        setpt(S, "T", Q)
+        run_levels(gk.progs["g2_dbl"], S)
+        assert getaff(S, "T") == aff_add(Q, Q), "dbl"
+        T2 = aff_add(Q, Q)
+        base = st["TB5.0"]
+        run_levels(gk.progs["g2_add"], S, (0, 0, base, 0, 0, 0, 0, 0))
+        assert getaff(S, "T") == aff_add(T2, getaff(S, "TB5")), "add"
+        T3 = getaff(S, "T")
+        Sa = list(S) + [A[0][0], A[0][1], A[1][0], A[1][1]]
+        run_levels(gk.progs["g2_madd"], Sa, (0, 0, len(S), 0, 0, 0, 0, 0))
+        assert getaff(Sa, "T") == aff_add(T3, A), "madd"
+        run_levels(gk.progs["g2_norm"], Sa)
+        Sa[st["tinv"]] = pow(Sa[st["t"]], -1, P)
+        run_levels(gk.progs["g2_aff"], Sa)
+        assert ((Sa[st["ax.0"]], Sa[st["ax.1"]]), (Sa[st["ay.0"]], Sa[st["ay.1"]])) == aff_add(T3, A), "aff"
+        # degenerate addition reports H = 0 and r = 0
+        setpt(S, "T", Q)
+        setpt(S, "TB1", Q)
+        run_levels(gk.progs["g2_add"], S, (0, 0, st["TB1.0"], 0, 0, 0, 0, 0))
+        assert S[st["H.0"]] % P == 0 and S[st["H.1"]] % P == 0 and S[st["RR.0"]] % P == 0 and S[st["RR.1"]] % P == 0
+    # decomposition
+    for k in [0, 1, R - 1] + [rng.randrange(R) for _ in range(2000)]:
+        kj = gls_decompose(k)
+        assert (sum(kj[j] * pow(lam, j, R) for j in range(4)) - k) % R == 0 and max(abs(x) for x in kj) < 2**65
+    print("G2 programs and GLS decomposition ok", file=sys.stderr)
 
 
 if __name__ == "__main__":

@@ -9,6 +9,8 @@
 #include "pairing.hpp"
 #include "hash.hpp"
 #include "slp.hpp"
+#include "gls.hpp"
+#include "g2mul.hpp"
 
 #define API extern "C" __attribute__((visibility("default")))
 
@@ -269,6 +271,55 @@ API int hc_slp_lane(int op, int n, const int *k, const uint8_t *xs, uint8_t *out
   }
   slp::f29 r = slp::red29(acc);
   wr_raw(out, slp::from29(op == 2 ? r : slp::canon29(r)));
+  return 0;
+}
+
+
+// GLS decomposition of a canonical scalar (big-endian 32 bytes): out = 4 signed 128-bit
+// two's-complement values (little-endian 16 bytes each) and the bit length
+API int hc_gls(const uint8_t *kb, uint8_t *out, uint32_t *nbits) {
+  fe k = rd_raw(kb);
+  gls::Dec d = gls::decompose(k.l);
+  for (int j = 0; j < 4; j++) {
+    uint32_t m[4] = {d.mag[j][0], d.mag[j][1], d.mag[j][2], 0};
+    if (d.neg >> j & 1) {
+      uint64_t cy = 1;
+      for (int w = 0; w < 4; w++) { uint64_t t = (uint64_t)(uint32_t)~m[w] + cy; m[w] = (uint32_t)t; cy = t >> 32; }
+    }
+    for (int w = 0; w < 4; w++)
+      for (int b = 0; b < 4; b++) out[16 * j + 4 * w + b] = (uint8_t)(m[w] >> (8 * b));
+  }
+  *nbits = d.nbits;
+  return 0;
+}
+
+
+// k Q + A on the engine's host model (A may be null); out affine (128 bytes, zeros = identity)
+API int hc_g2_mul(const uint8_t *Qb, const uint8_t *kb, const uint8_t *Ab, uint8_t *out) {
+  static slp::f29 S[slp::G2_NSLOT + 4];
+  g2_aff Q = rdg2(Qb);
+  const fe *q = reinterpret_cast<const fe *>(&Q);
+  for (int i = 0; i < 4; i++) S[slp::G2_xQ_0 + i] = slp::to29(q[i]);
+  bool has_a = false;
+  if (Ab) {
+    g2_aff A = rdg2(Ab);
+    const fe *a = reinterpret_cast<const fe *>(&A);
+    for (int i = 0; i < 4; i++) S[slp::G2_NSLOT + i] = slp::to29(a[i]);
+    has_a = !aff_is_inf(A);
+  }
+  ld_consts(S, slp::G2_CBASE, slp::G2_CONSTS, slp::G2_NCONST);
+  fe k = rd_raw(kb);
+  gls::Dec dec = gls::decompose(k.l);
+  slp::HostCtx c{S};
+  bool inf = g2m::mul_add(c, dec, aff_is_inf(Q), has_a, slp::G2_NSLOT, S[slp::G2_CBASE + 1], S[slp::G2_CBASE]);
+  if (inf) { memset(out, 0, 128); return 0; }
+  c.run(slp::PROG_G2_NORM, 0, 0, 0);
+  S[slp::G2_tinv] = slp::to29(fp_inv_fast(slp::from29(slp::canon29(S[slp::G2_t]))));
+  c.run(slp::PROG_G2_AFF, 0, 0, 0);
+  g2_aff r;
+  fe *rw = reinterpret_cast<fe *>(&r);
+  for (int i = 0; i < 4; i++) rw[i] = slp::from29(slp::canon29(S[slp::G2_ax_0 + i]));
+  wrg2(out, r);
   return 0;
 }
 

@@ -2,6 +2,7 @@
 // and the final exponentiation, one 64-lane workgroup per pairing / product / element.
 #include "kcommon.hpp"
 #include "slp.hpp"
+#include "g2mul.hpp"
 
 #define SLP_T 64
 
@@ -107,6 +108,66 @@ __global__ void __launch_bounds__(SLP_T) ks_final_exp(const fp12 *in, uint64_t i
   if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(slp::FE_RESULT) + t]));
 }
 
+
+// ---------------------------------------------------------------- G2 scalar multiplications
+#define G2_SLOTS (slp::G2_NSLOT + 4)
+#define G2_ABASE slp::G2_NSLOT
+
+// out = k Q + A on the engine (A optional); results written as affine (oaff) or Jacobian (ojac)
+__device__ void g2_job(f29 *S, gls::Dec *dec, const g2_aff *Q, const fe *k_mont, const g2_aff *A, g2_aff *oaff,
+                       g2_jac *ojac) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    fe kc = f_from_mont<FpR>(*k_mont);
+    *dec = gls::decompose(kc.l);
+  }
+  const fe *q = reinterpret_cast<const fe *>(Q);
+  if (t < 4) S[slp::G2_xQ_0 + t] = slp::to29(q[t]);
+  if (A && t >= 4 && t < 8) S[G2_ABASE + t - 4] = slp::to29(reinterpret_cast<const fe *>(A)[t - 4]);
+  load_consts<slp::G2_NCONST>(S, slp::G2_CBASE, slp::G2_CONSTS);
+  __syncthreads();
+  bool qinf = g2_inf(*Q), has_a = A && !g2_inf(*A);
+  slp::DevCtx c{S};
+  const f29 one = S[slp::G2_CBASE + 1], zero = S[slp::G2_CBASE];
+  bool inf = g2m::mul_add(c, *dec, qinf, has_a, G2_ABASE, one, zero);
+  if (ojac) {
+    fe *o = reinterpret_cast<fe *>(ojac);
+    if (t < 6) o[t] = inf ? ((t == 0 || t == 2) ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::G2_T_0 + t]));
+    return;
+  }
+  fe *o = reinterpret_cast<fe *>(oaff);
+  if (inf) {
+    if (t < 4) o[t] = fe_zero();
+    return;
+  }
+  c.run(slp::PROG_G2_NORM, 0, 0, 0);
+  if (t == 0) S[slp::G2_tinv] = slp::to29(f_inv_binary<FpP>(slp::from29(slp::canon29(S[slp::G2_t])), bn::P_R3));
+  __syncthreads();
+  c.run(slp::PROG_G2_AFF, 0, 0, 0);
+  if (t < 4) o[t] = slp::from29(slp::canon29(S[slp::G2_ax_0 + t]));
+}
+
+// v[i] = v[i] + x^{-1} v[h + i] for every batch k (Eq. folding)
+__global__ void __launch_bounds__(SLP_T) ks_oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+                                                      uint32_t lK) {
+  __shared__ f29 S[G2_SLOTS];
+  __shared__ gls::Dec dec;
+  uint64_t id = blockIdx.x;
+  if (id >= nb * h) return;
+  uint64_t k = id / h, i = id % h;
+  g2_job(S, &dec, V + k * K + h + i, Xinv + k * lK + (j - 1), V + k * K + i, V + k * K + i, nullptr);
+}
+
+// terms q_m h_m of the KZG proof of v_l (Jacobian)
+__global__ void __launch_bounds__(SLP_T) ks_kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2) {
+  __shared__ f29 S[G2_SLOTS];
+  __shared__ gls::Dec dec;
+  uint64_t n = 2 * K - 2;
+  uint64_t id = blockIdx.x;
+  if (id >= nb * n) return;
+  g2_job(S, &dec, h + id % n, Qc + id, nullptr, nullptr, S2 + id);
+}
+
 namespace ks {
 void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st) {
   if (n) LAUNCH(ks_miller, dim3((unsigned)n), dim3(SLP_T), 0, P, sp, Q, sq, n, out);
@@ -122,5 +183,11 @@ void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStr
 }
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st) {
   if (n) LAUNCH(ks_final_exp, dim3((unsigned)n), dim3(SLP_T), 0, in, stride, n, out0, out1, ostride);
+}
+void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
+  LAUNCH(ks_oa_fold_g2, dim3((unsigned)(nb * h)), dim3(SLP_T), 0, V, Xinv, K, nb, h, j, lK);
+}
+void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st) {
+  LAUNCH(ks_kzg_terms, dim3((unsigned)(nb * (2 * K - 2))), dim3(SLP_T), 0, h, Qc, K, nb, S2);
 }
 }  // namespace ks

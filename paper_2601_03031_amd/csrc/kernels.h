@@ -80,4 +80,6 @@ void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t
 void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st);
 void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
+void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
+void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
 }  // namespace ks

@@ -399,14 +399,14 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     kl::oa_transcript(S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
     if (int rc2 = stream_wait(pp, 3, st, s2)) return rc2;
     klw::oa_fold_g1(A, B, X, Xinv, K, nb, h, j, lK, s2);
-    klw::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
+    ks::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
     if (int rc2 = stream_wait(pp, 4, s2, st)) return rc2;
   }
   CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
   CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
   // faster verifier: KZG-style proof in G2 that v_l = f_v(beta) g2
   kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, st);
-  klw::kzg_terms(pp->h, Q, K, nb, S2, st);
+  ks::kzg_terms(pp->h, Q, K, nb, S2, st);
   klw::g2_reduce(S2, nb, nq, nq, st);
   klw::g2_to_aff(S2, nq, nb, piv, 1, st);
   // join Step 2

@@ -213,3 +213,46 @@ def test_engine_lane_arithmetic(hc):
         o = buf(32)
         hc.hc_slp_lane(1, 2, None, a.to_bytes(32, "big") + b.to_bytes(32, "big"), o)
         assert int.from_bytes(o.raw, "big") == a * b * rinv % P, (a, b)
+
+
+def test_gls_decomposition(hc):
+    """k = sum_j k_j lam^j (mod r) with lam = p mod r (the eigenvalue of the twist
+    Frobenius on G2, pinned against the oracle's Frobenius) and |k_j| < 2^65."""
+    g1, g2 = O.generators()
+    lam = P % R
+    Q = O.g2_op("mul", g2, O.be32(777))
+    assert O.g2_op("frobenius", Q) == O.g2_op("mul", Q, O.be32(lam))
+    rng = random.Random(14)
+    for k in [0, 1, 2, R - 1, R - 2, (R - 1) // 2, 1 << 200] + [rng.randrange(R) for _ in range(3000)]:
+        o = buf(64)
+        nb = C.c_uint32()
+        hc.hc_gls(k.to_bytes(32, "big"), o, C.byref(nb))
+        kj = [int.from_bytes(o.raw[16 * j:16 * j + 16], "little", signed=True) for j in range(4)]
+        assert (sum(kj[j] * pow(lam, j, R) for j in range(4)) - k) % R == 0, k
+        assert max(abs(x) for x in kj) < 2**65
+        assert nb.value == max(abs(x) for x in kj).bit_length()
+
+
+def test_g2_scalar_mul_engine(hc):
+    """k Q + A through the engine's host model (GLS split, signed table, exact handling
+    of equal and opposite points) against the oracle's group law."""
+    g1, g2 = O.generators()
+    rng = random.Random(15)
+    ident = bytes(128)
+    cases = []
+    for _ in range(4):
+        Q = O.g2_op("mul", g2, O.be32(rng.randrange(1, R)))
+        A = O.g2_op("mul", g2, O.be32(rng.randrange(1, R)))
+        cases.append((Q, rng.randrange(R), A))
+    Q = O.g2_op("mul", g2, O.be32(12345))
+    k = rng.randrange(1, R)
+    kQ = O.g2_op("mul", Q, O.be32(k))
+    cases += [(Q, 0, None), (Q, 1, None), (Q, R - 1, None), (ident, 5, None), (Q, k, ident),
+              (Q, k, kQ), (Q, k, O.g2_op("neg", kQ)), (Q, 0, kQ), (Q, k, None)]
+    for Qb, k, Ab in cases:
+        o = buf(128)
+        assert hc.hc_g2_mul(Qb, k.to_bytes(32, "big"), Ab, o) == 0
+        want = O.g2_op("mul", Qb, O.be32(k)) if Qb != ident else ident
+        if Ab is not None:
+            want = O.g2_op("add", want, Ab)
+        assert o.raw == want, (k,)
