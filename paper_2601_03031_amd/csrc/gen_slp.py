@@ -38,13 +38,13 @@ P = 36 * U**4 + 36 * U**3 + 24 * U**2 + 6 * U + 1
 R = 36 * U**4 + 36 * U**3 + 18 * U**2 + 6 * U + 1
 RMONT = 1 << 256
 LANES = 64
-KMAX = 15
+KMAX = 127
 
 OP_NOP, OP_MUL, OP_LIN = 0, 1, 2
 
 
 # ============================================================================ tracer
-NTERM = 6       # operands per op (a product splits them between its two factors)
+NTERM = 8       # operands per op (a product splits them between its two factors)
 
 
 class Prog:
@@ -122,11 +122,6 @@ class F:
         if not self.t or not o.t:
             return F(self.p, {})
         A, B = operand_terms(self.p, self.t), operand_terms(self.p, o.t)
-        while len(A) + len(B) > NTERM:
-            if len(A) >= len(B):
-                A = {materialise(self.p, A): 1}
-            else:
-                B = {materialise(self.p, B): 1}
         a, b = canon(A), canon(B)
         if b < a:
             a, b = b, a
@@ -144,10 +139,13 @@ class F:
         return a
 
 
+SIDE = NTERM // 2   # terms per factor of a product (terms 0..3 and 4..7 of the operation)
+
+
 def operand_terms(p, t):
-    """a factor of a product: coefficients within [-KMAX, KMAX], at most NTERM - 1 terms"""
+    """a factor of a product: coefficients within [-KMAX, KMAX], at most SIDE terms"""
     t = fit_coeffs(p, dict(t))
-    if len(t) > NTERM - 1:
+    if len(t) > SIDE:
         t = {materialise(p, t): 1}
     return t
 
@@ -1074,7 +1072,9 @@ def compile_prog(p, io_slot, const_slot, temp_base, temp_limit, lanes=LANES):
         for i in ops:
             v = vals[i]
             if v[0] == "mul":
-                row.append((OP_MUL, slot[i], len(v[1]), tuple((slot[k], c) for k, c in v[1] + v[2])))
+                za = (const_slot(0), 0)
+                ta = tuple((slot[k], c) for k, c in v[1]) + (za,) * (SIDE - len(v[1]))
+                row.append((OP_MUL, slot[i], SIDE, ta + tuple((slot[k], c) for k, c in v[2])))
             else:
                 row.append((OP_LIN, slot[i], len(v[1]), tuple((slot[k], c) for k, c in v[1])))
         enc.append(row)
@@ -1116,15 +1116,15 @@ class Kernel:
 
 
 def encode_op(op):
-    """128-bit op: kind (2) | dst (12) | na (3) | 6 x (slot 12 | coefficient 5, two's complement);
-    a product multiplies the sum of terms [0, na) by the sum of terms [na, 6); unused
+    """192-bit op: kind (2) | dst (12) | na (4) | 8 x (slot 12 | coefficient 8, two's complement);
+    a product multiplies the sum of terms [0, na) by the sum of terms [na, 8); unused
     terms have coefficient 0"""
     kind, dst, na, terms = op
     assert 0 <= dst < 4096 and len(terms) <= NTERM and 0 <= na <= NTERM
     x = kind | (dst << 2) | (na << 14)
     for i, (s, c) in enumerate(terms):
         assert 0 <= s < 4096 and -KMAX <= c <= KMAX
-        x |= ((s | ((c & 31) << 12)) << (17 + 17 * i))
+        x |= ((s | ((c & 255) << 12)) << (18 + 20 * i))
     return x
 
 
@@ -1142,7 +1142,7 @@ def limbs(x):
 
 
 M29 = (1 << 29) - 1
-OFF_MULT = 5760           # offset multiple of p added to every linear combination
+OFF_MULT = 65536          # offset multiple of p added to every linear combination
 
 
 def limbs29(x):
@@ -1174,6 +1174,7 @@ def emit(kernels):
         w(line)
     allops = []
     descs = []
+    levn = []
     for k in kernels:
         w("// kernel %s: %d slots (%d state, %d constants)" % (k.name, k.nslots, len(k.state), len(k.consts)))
         w("static constexpr int %s_NSLOT = %d;" % (k.name.upper(), k.nslots))
@@ -1183,18 +1184,22 @@ def emit(kernels):
             w("static constexpr int %s_%s = %d;" % (k.name.upper(), nm.replace(".", "_"), s))
         for nm, enc in k.progs.items():
             width = max(1, max(len(r) for r in enc))
-            descs.append((k.name, nm, len(allops), len(enc), width))
+            descs.append((k.name, nm, len(allops), len(enc), width, len(levn)))
             w("static constexpr int PROG_%s = %d;" % (nm.upper(), len(descs) - 1))
             for row in enc:
                 allops += [encode_op(op) for op in row] + [0] * (width - len(row))
-    w("struct ProgDesc { uint32_t off; uint16_t nlev; uint16_t width; };")
+                # terms in use: the highest term position with a nonzero coefficient, plus one
+                levn.append(max([max([i + 1 for i, (_, c) in enumerate(op[3]) if c] + [0]) for op in row] + [0]))
+    w("struct ProgDesc { uint32_t off; uint16_t nlev; uint16_t width; uint32_t moff; };")
     w("__device__ const ProgDesc PROGS[%d] = {" % len(descs))
-    for kn, nm, off, nlev, width in descs:
-        w("  {%du, %du, %du},  // %s" % (off, nlev, width, nm))
+    for kn, nm, off, nlev, width, moff in descs:
+        w("  {%du, %du, %du, %du},  // %s" % (off, nlev, width, moff, nm))
     w("};")
-    w("__device__ const uint64_t OPS[%d][2] = {" % len(allops))
-    for i in range(0, len(allops), 3):
-        w("  " + ", ".join("{0x%016xull, 0x%016xull}" % (x & (2**64 - 1), x >> 64) for x in allops[i:i + 3]) + ",")
+    w("__device__ const uint8_t LEVN[%d] = {%s};" % (len(levn), ", ".join(str(x) for x in levn)))
+    w("__device__ const uint64_t OPS[%d][3] = {" % len(allops))
+    for i in range(0, len(allops), 2):
+        w("  " + ", ".join("{0x%016xull, 0x%016xull, 0x%016xull}" % (x & (2**64 - 1), (x >> 64) & (2**64 - 1), x >> 128)
+                           for x in allops[i:i + 2]) + ",")
     w("};")
     for k in kernels:
         w("__device__ const uint32_t %s_CONSTS[%d][9] = {" % (k.name.upper(), len(k.consts)))
