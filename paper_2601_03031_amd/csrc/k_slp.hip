@@ -168,6 +168,46 @@ __global__ void __launch_bounds__(SLP_T) ks_kzg_terms(const g2_aff *h, const fe 
   g2_job(S, &dec, h + id % n, Qc + id, nullptr, nullptr, S2 + id);
 }
 
+// ---------------------------------------------------------------- G_T exponentiation
+// out[s] = in[s]^k_s (k in Montgomery F_r form), square-and-multiply with the engine's
+// F_p12 product (inputs need not lie in the cyclotomic subgroup)
+__global__ void __launch_bounds__(SLP_T) ks_gt_pow(const fp12 *in, const fe *k_mont, uint64_t n, fp12 *out) {
+  __shared__ f29 S[slp::FE_NSLOT + 36];
+  __shared__ uint32_t kc[8];
+  uint64_t s = blockIdx.x;
+  if (s >= n) return;
+  const int t = threadIdx.x;
+  const fe *src = reinterpret_cast<const fe *>(in + s);
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
+  if (t == 0) {
+    fe kcan = f_from_mont<FpR>(k_mont[s]);
+    for (int w = 0; w < 8; w++) kc[w] = kcan.l[w];
+  }
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  int top = -1;
+  for (int b = 255; b >= 0; b--)
+    if ((kc[b >> 5] >> (b & 31)) & 1) { top = b; break; }
+  fe *dst = reinterpret_cast<fe *>(out + s);
+  if (top < 0) {
+    if (t < 12) dst[t] = t == 0 ? f_one<FpP>() : fe_zero();
+    return;
+  }
+  // accumulator alternates between buffers 1 and 2; buffer 0 holds the base
+  if (t < 12) S[FE_BUF(1) + t] = S[FE_BUF(0) + t];
+  __syncthreads();
+  int acc = 1;
+  for (int b = top - 1; b >= 0; b--) {
+    slp::run1(S, slp::PROG_F12_MUL, FE_BUF(acc), FE_BUF(acc), FE_BUF(3 - acc));
+    acc = 3 - acc;
+    if ((kc[b >> 5] >> (b & 31)) & 1) {
+      slp::run1(S, slp::PROG_F12_MUL, FE_BUF(acc), FE_BUF(0), FE_BUF(3 - acc));
+      acc = 3 - acc;
+    }
+  }
+  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(acc) + t]));
+}
+
 namespace ks {
 void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st) {
   if (n) LAUNCH(ks_miller, dim3((unsigned)n), dim3(SLP_T), 0, P, sp, Q, sq, n, out);
@@ -189,5 +229,8 @@ void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, 
 }
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st) {
   LAUNCH(ks_kzg_terms, dim3((unsigned)(nb * (2 * K - 2))), dim3(SLP_T), 0, h, Qc, K, nb, S2);
+}
+void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st) {
+  if (n) LAUNCH(ks_gt_pow, dim3((unsigned)n), dim3(SLP_T), 0, in, k, n, out);
 }
 }  // namespace ks

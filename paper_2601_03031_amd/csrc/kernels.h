@@ -82,4 +82,5 @@ void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStr
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
 void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
+void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st);
 }  // namespace ks

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 #include "kernels.h"
+#include "verify.h"
 #include "vc.h"
 
 #define VC_API extern "C" __attribute__((visibility("default")))
@@ -622,10 +623,73 @@ VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst
   return export_items(pr->mem, idx, mode, dst, cap, len);
 }
 
+// VC.Verify (appendix C): FC.BVerify on the proof's block with the faster verifier,
+// the Merkle path to rho_j, the fold-up of D* and y*, and the PST check at Bin(a).
 VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint32_t b, uint64_t i, const uint8_t m_i[32],
                      const uint8_t *proof, size_t len) {
-  (void)pp; (void)C; (void)n; (void)b; (void)i; (void)m_i; (void)proof; (void)len;
-  return VC_ENOTIMPL;
+  if (!pp || !C || !m_i || !proof || n != pp->N || i >= n || b < 1 || b > pp->K) return VC_EINVAL;
+  const uint64_t K = pp->K, M = pp->M;
+  const uint32_t lK = pp->lK, lM = pp->lM;
+  const uint64_t j = i / M, a = i % M, k = j / b, lo = k * b, hi = lo + b < K ? lo + b : K;
+  const uint32_t t = (uint32_t)(hi - lo);
+  if (len != vc_proof_len(pp->L, t)) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  hipStream_t st = pp->side[0];
+  const uint32_t nmul = t + 2 * lK + 4, npair = 4 + lM;
+  Carve c;
+  size_t o_pf = c.take<uint8_t>(len), o_C = c.take<uint8_t>(384), o_m = c.take<uint8_t>(32);
+  size_t o_blk = c.take<g1_aff>(t), o_Lg1 = c.take<g1_aff>(lK), o_Rg1 = c.take<g1_aff>(lK), o_Al = c.take<g1_aff>(1);
+  size_t o_D = c.take<g1_aff>(lK), o_W = c.take<g1_aff>(lM), o_Lgt = c.take<fp12>(lK), o_Rgt = c.take<fp12>(lK);
+  size_t o_Cgt = c.take<fp12>(1), o_vl = c.take<g2_aff>(1), o_piv = c.take<g2_aff>(1), o_ys = c.take<fe>(lK);
+  size_t o_mi = c.take<fe>(1), o_r = c.take<fe>(t), o_x = c.take<fe>(lK), o_xi = c.take<fe>(lK), o_ms = c.take<fe>(nmul);
+  size_t o_fz = c.take<fe>(1), o_gts = c.take<fe>(2 * lK), o_mb = c.take<g1_aff>(nmul), o_mo = c.take<g1_aff>(nmul);
+  size_t o_fzg2 = c.take<g2_aff>(1), o_gtb = c.take<fp12>(2 * lK), o_gto = c.take<fp12>(2 * lK + 1);
+  size_t o_Cg1 = c.take<g1_aff>(1), o_bA = c.take<g1_aff>(1), o_pp = c.take<g1_aff>(npair), o_pq = c.take<g2_aff>(npair);
+  size_t o_F = c.take<fp12>(npair), o_E = c.take<fp12>(3), o_fl = c.take<int>(1);
+  void *d = nullptr;
+  CK(hipMalloc(&d, c.off));
+  VCtx x;
+  x.t = t; x.lK = lK; x.lM = lM; x.L = pp->L;
+  x.N = pp->N; x.i = i; x.j = j; x.a = a; x.lo = lo;
+  x.proof = at<uint8_t>(d, o_pf); x.Cb = at<uint8_t>(d, o_C); x.mib = at<uint8_t>(d, o_m);
+  x.mpath = x.proof + (len - 32ull * pp->L);
+  x.blk = at<g1_aff>(d, o_blk); x.Lg1 = at<g1_aff>(d, o_Lg1); x.Rg1 = at<g1_aff>(d, o_Rg1); x.Al = at<g1_aff>(d, o_Al);
+  x.Dsib = at<g1_aff>(d, o_D); x.Wp = at<g1_aff>(d, o_W); x.Lgt = at<fp12>(d, o_Lgt); x.Rgt = at<fp12>(d, o_Rgt);
+  x.C = at<fp12>(d, o_Cgt); x.vl = at<g2_aff>(d, o_vl); x.piv = at<g2_aff>(d, o_piv); x.ysib = at<fe>(d, o_ys);
+  x.mi = at<fe>(d, o_mi); x.r = at<fe>(d, o_r); x.x = at<fe>(d, o_x); x.xinv = at<fe>(d, o_xi); x.ms = at<fe>(d, o_ms);
+  x.fz = at<fe>(d, o_fz); x.gts = at<fe>(d, o_gts); x.mb = at<g1_aff>(d, o_mb); x.mo = at<g1_aff>(d, o_mo);
+  x.fzg2 = at<g2_aff>(d, o_fzg2); x.gtb = at<fp12>(d, o_gtb); x.gto = at<fp12>(d, o_gto);
+  x.Cg1 = at<g1_aff>(d, o_Cg1); x.bA = at<g1_aff>(d, o_bA); x.pp = at<g1_aff>(d, o_pp); x.pq = at<g2_aff>(d, o_pq);
+  x.F = at<fp12>(d, o_F); x.E = at<fp12>(d, o_E); x.g1beta = pp->g1beta; x.vk = pp->vk; x.flags = at<int>(d, o_fl);
+  int flags = 0;
+  hipError_t e = hipMemcpyAsync(at<void>(d, o_pf), proof, len, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(at<void>(d, o_C), C, 384, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(at<void>(d, o_m), m_i, 32, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(x.flags, 0, sizeof(int), st);
+  if (e == hipSuccess) {
+    kv::decode(x, st);
+    kv::transcript(x, st);
+    klw::g1_mul(x.mb, 0, x.ms, nmul, x.mo, st);
+    klw::g2_mul(pp->g2gen, 1, x.fz, 1, x.fzg2, st);
+    ks::gt_pow(x.gtb, x.gts, 2 * lK, x.gto, st);
+    kv::assemble(x, st);
+    ks::f12_reduce(x.gto, 1, 2 * lK + 1, 2 * lK + 1, st);
+    ks::miller(x.pp, 1, x.pq, 1, npair, x.F, st);
+    ks::f12_reduce(x.F + 1, 1, 2, 2, st);
+    ks::f12_reduce(x.F + 3, 1, npair - 3, npair - 3, st);
+    ks::final_exp(x.F, 1, 1, x.E, nullptr, 1, st);
+    ks::final_exp(x.F + 1, 1, 1, x.E + 1, nullptr, 1, st);
+    ks::final_exp(x.F + 3, 1, 1, x.E + 2, nullptr, 1, st);
+    kv::compare(x, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, x.flags, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "vc_verify");
+  if (flags & VFLAG_BAD_INPUT) return VC_EINVAL;
+  if (flags & VFLAG_BAD_PROOF) return 0;
+  return (flags & VFLAG_ACCEPT) ? 1 : 0;
 }
 
 // ------------------------------------------------------------------ profiling C ABI
