@@ -21,6 +21,10 @@ void begin(const char *name, hipStream_t st);
 void end(hipStream_t st);
 void name_last(const char *name);
 }  // namespace prof
+namespace dbg {
+bool on();
+void check(const char *name, hipStream_t st);
+}  // namespace dbg
 
 static inline unsigned nblkw(uint64_t n) { return (unsigned)((n + GPB - 1) / GPB); }
 __device__ __forceinline__ uint64_t wgid() { return (uint64_t)blockIdx.x * GPB + (threadIdx.x >> 3); }
@@ -240,6 +244,7 @@ namespace klw {
     hipLaunchKernelGGL(kern, dim3(nblkw(n)), dim3(TPBW), 0, st, __VA_ARGS__);                \
     prof::end(st);                                                                           \
     prof::name_last(#kern);                                                                  \
+    if (dbg::on()) dbg::check(#kern, st);                                                    \
   } while (0)
 
 void miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n, void *out, hipStream_t st) {

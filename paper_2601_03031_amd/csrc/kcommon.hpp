@@ -57,11 +57,18 @@ void begin(const char *name, hipStream_t st);
 void end(hipStream_t st);
 void name_last(const char *name);
 }
+namespace dbg {
+// VC_DEBUG_SYNC=1 in the environment: synchronize after every launch and report the
+// first failing kernel on stderr (diagnostics only)
+bool on();
+void check(const char *name, hipStream_t st);
+}  // namespace dbg
 #define LAUNCH(kern, grid, block, shm, ...)                                 \
   do {                                                                     \
     prof::begin(#kern, st);                                                \
     hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);           \
     prof::end(st);                                                         \
     prof::name_last(#kern);                                                \
+    if (dbg::on()) dbg::check(#kern, st);                                  \
   } while (0)
 #define L1(kern, n, ...) LAUNCH(kern, dim3(nblk(n)), dim3(TPB), 0, __VA_ARGS__)

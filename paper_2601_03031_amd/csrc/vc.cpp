@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <string>
 #include <vector>
 #include "kernels.h"
@@ -61,6 +62,25 @@ bool g_prof = false;
 std::vector<ProfRec> g_prof_recs;
 hipEvent_t g_prof_open = nullptr;
 }  // namespace
+
+namespace dbg {
+bool on() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("VC_DEBUG_SYNC");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+void check(const char *name, hipStream_t st) {
+  hipError_t e0 = hipGetLastError();
+  hipError_t e1 = hipStreamSynchronize(st);
+  hipError_t e2 = hipGetLastError();
+  if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess)
+    fprintf(stderr, "[vc debug] after %s: %s / %s / %s\n", name, hipGetErrorString(e0), hipGetErrorString(e1),
+            hipGetErrorString(e2));
+}
+}  // namespace dbg
 
 namespace prof {
 void begin(const char *, hipStream_t st) {
@@ -149,6 +169,7 @@ VC_API const char *vc_strerror(int code) {
 
 // ------------------------------------------------------------------ setup
 VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!out || !seed || log_n < 2 || log_n > 20) return VC_EINVAL;
   *out = nullptr;
   CK(hipSetDevice(device));
@@ -211,6 +232,7 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
 }
 
 VC_API void vc_params_free(vc_params *pp) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pp) return;
   hipSetDevice(pp->device);
   if (pp->mem) hipFree(pp->mem);
@@ -225,6 +247,7 @@ VC_API void vc_params_free(vc_params *pp) {
 // ------------------------------------------------------------------ commit
 VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
                      vc_commitment **out, uint8_t C_out[384]) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!cpp || !m_dev || !out || n != cpp->N || (entry_bits != 32 && entry_bits != 256)) return VC_EINVAL;
   vc_params *pp = const_cast<vc_params *>(cpp);
   *out = nullptr;
@@ -279,6 +302,7 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
 }
 
 VC_API void vc_commitment_free(vc_commitment *cm) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!cm) return;
   hipSetDevice(cm->pp->device);
   if (cm->mem) hipFree(cm->mem);
@@ -287,6 +311,7 @@ VC_API void vc_commitment_free(vc_commitment *cm) {
 
 // ------------------------------------------------------------------ open-all
 VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!cpp || !cm || !out || cm->pp != cpp || b < 1 || b > cpp->K) return VC_EINVAL;
   vc_params *pp = const_cast<vc_params *>(cpp);
   *out = nullptr;
@@ -422,6 +447,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
 }
 
 VC_API void vc_proofs_free(vc_proofs *pr) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pr) return;
   hipSetDevice(pr->pp->device);
   if (pr->mem) hipFree(pr->mem);
@@ -487,6 +513,7 @@ void compress_g2(uint8_t *o, const uint8_t *xy) {
 }  // namespace
 
 VC_API int vc_proof_get(const vc_proofs *pr, uint64_t i, uint8_t *buf, size_t cap, size_t *len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pr || !buf || !len) return VC_EINVAL;
   const vc_params *pp = pr->pp;
   const uint64_t N = pp->N, K = pp->K, M = pp->M;
@@ -556,6 +583,7 @@ static int export_items(const void *base, const std::vector<uint64_t> &idx, cons
 }
 
 VC_API int vc_params_export(const vc_params *pp, int what, uint32_t idx_, void *dst, size_t cap, size_t *len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pp) return VC_EINVAL;
   CK(hipSetDevice(pp->device));
   std::vector<uint64_t> idx;
@@ -577,6 +605,7 @@ VC_API int vc_params_export(const vc_params *pp, int what, uint32_t idx_, void *
 }
 
 VC_API int vc_commitment_export(const vc_commitment *cm, int what, void *dst, size_t cap, size_t *len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!cm) return VC_EINVAL;
   CK(hipSetDevice(cm->pp->device));
   std::vector<uint64_t> idx;
@@ -589,6 +618,7 @@ VC_API int vc_commitment_export(const vc_commitment *cm, int what, void *dst, si
 }
 
 VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst, size_t cap, size_t *len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pr) return VC_EINVAL;
   const vc_params *pp = pr->pp;
   const uint64_t N = pp->N, K = pp->K, M = pp->M;
@@ -627,6 +657,7 @@ VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst
 // the Merkle path to rho_j, the fold-up of D* and y*, and the PST check at Bin(a).
 VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint32_t b, uint64_t i, const uint8_t m_i[32],
                      const uint8_t *proof, size_t len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pp || !C || !m_i || !proof || n != pp->N || i >= n || b < 1 || b > pp->K) return VC_EINVAL;
   const uint64_t K = pp->K, M = pp->M;
   const uint32_t lK = pp->lK, lM = pp->lM;
@@ -731,6 +762,7 @@ VC_API int vc_profile_read(char *buf, size_t cap) {
 // (host buffers) in the 8-lanes-per-element layout: op 0 mul, 1 add, 2 sub, 3 half,
 // 4 inverse, 5 square; which 0 = F_p, 1 = F_r.
 VC_API int vc_diag_field(int which, int op, uint64_t n, const void *a, const void *b, void *out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!a || !b || !out || n == 0) return VC_EINVAL;
   void *d = nullptr;
   CK(hipMalloc(&d, 3 * n * 32));

@@ -123,3 +123,52 @@ def test_rejects_bad_input(vc):
         with pytest.raises(vc.VCError) as e:
             vc.vc_open_all(pp, cm, b)
         assert e.value.code == vc.VC_EINVAL
+
+
+def sample_indices(N, M, b, seed, extra=()):
+    """edges of the first and last batch and block, plus seeded random positions"""
+    rng = np.random.default_rng(seed)
+    K = N // M
+    base = {0, 1, M - 1, M, N - 1, N - M, min(b, K - 1) * M, ((K - 1) // b) * b * M}
+    base |= set(int(x) for x in rng.integers(0, N, 24))
+    return sorted(i for i in base | set(extra) if 0 <= i < N)
+
+
+def test_full_n16_b256_u32(vc):
+    """The benchmark workload (N = 2^16, b = log^2 N = 256, uniform 32-bit entries, seed 2):
+    every exported array, and sampled serialized proofs, byte for byte."""
+    cs = Case(vc, 16, 256, seed=2, bits=32)
+    compare_all(vc, cs, proofs=sample_indices(1 << 16, 256, 256, 2))
+
+
+def test_n16_b16_u32(vc):
+    cs = Case(vc, 16, 16, seed=2, bits=32)
+    compare_all(vc, cs, proofs=sample_indices(1 << 16, 256, 16, 3))
+
+
+def test_full_n20_b400(vc):
+    """N = 2^20, b = log^2 N = 400 (3 batches, the last with 224 entries), full-width entries
+    (seed 3): every exported array and sampled proofs."""
+    cs = Case(vc, 20, 400, seed=3, bits=256)
+    compare_all(vc, cs, proofs=sample_indices(1 << 20, 1024, 400, 4))
+
+
+def test_n20_b1_sampled(vc):
+    """N = 2^20, b = 1 (1024 FC batches) is beyond the oracle's full OpenAll here; sampled
+    proofs are checked against the oracle's one-proof-at-a-time construction (no shared
+    work) and its verifier."""
+    L, b = 20, 1
+    say("case L=20 b=1 (sampled)")
+    limbs = I.entries(1 << L, 3, 256)
+    ints = I.limbs_to_ints(limbs)
+    gpp = vc.vc_setup(L, SEED, 0)
+    gcm = vc.vc_commit(gpp, dev_entries(limbs), 256)
+    gpr = vc.vc_open_all(gpp, gcm, b)
+    torch.cuda.synchronize()
+    say("  GPU done")
+    opp = O.Params(L, SEED)
+    m_le = I.limbs_to_bytes(limbs)
+    for i in (0, 777777):
+        proof = vc.vc_proof_get(gpr, i)
+        assert proof == O.naive_proof(opp, m_le, b, i), i
+        assert O.verify(opp, gcm.C, b, i, ints[i], proof) == 1, i
