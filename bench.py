@@ -28,18 +28,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "all-N-proofs time (ms) at N=2^16,b=log²N and N=2^20; MSM points/s"
-PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32x32->64 multiply-adds, one per lane per clock: 39.32 TOP/s
+PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12   # v_mad_u64_u32 issues at half rate: 19.66 T multiply-adds/s
 PEAK_HBM_GBS = 8000.0
 MADS_PER_FMUL = 136                        # 8x32-bit CIOS: 64 + 64 products + 8 reduction words
 
 
 def op_costs():
-    """Field multiplications per operation of the GPU path's formulas (host build count)."""
+    """Field multiplications per operation: formulas of the one-lane and eight-lane layouts
+    (host build count) and the engine's programs (Montgomery products in the tables)."""
     L = ctypes.CDLL(os.path.join(ROOT, "paper_2601_03031_amd", "lib", "libvc_hostcheck.so"))
     L.hc_count.restype = ctypes.c_uint64
+    L.hc_engine_muls.restype = ctypes.c_uint64
     names = ["miller", "final_exp", "g1_mul", "g2_mul", "g1_add", "g1_madd", "g2_add", "g2_madd",
              "g1_dbl", "g2_dbl", "f12_mul", "g1_to_aff", "g2_to_aff"]
-    return {n: int(L.hc_count(i)) for i, n in enumerate(names)}
+    c = {n: int(L.hc_count(i)) for i, n in enumerate(names)}
+    e = [int(L.hc_engine_muls(i)) for i in range(9)]
+    c["e_miller"], c["e_final_exp"], c["e_f12_mul"] = e[0], e[1], e[8]
+    # GLS scalar multiplication on G2: psi images, table, then per bit of the 65-bit
+    # split scalars one doubling and (with probability 15/16) one table addition
+    c["e_g2_mul"] = e[2] + e[3] + 64 * e[4] + 60 * e[5]
+    c["e_g2_madd"], c["e_g2_to_aff"] = e[6], e[7]
+    return c
 
 
 def work_model(L, b, limbs, costs):
@@ -54,13 +63,14 @@ def work_model(L, b, limbs, costs):
     blocks = K * ((M + S - 1) // S)
     w = {
         "k_msm_slices": nz_digits * costs["g1_madd"] + blocks * 2048 * costs["g1_add"],
-        "kw_miller": K * costs["miller"],
-        "kw_oa_miller": sum(nb * 2 * h for h in rounds) * costs["miller"],
-        "k_final_exp_wave": (2 * lK * nb + 1) * costs["final_exp"],
-        "kw_oa_fold_g2": sum(nb * h for h in rounds) * (costs["g2_mul"] + costs["g2_madd"] + costs["g2_to_aff"]),
+        "ks_miller": K * costs["e_miller"],
+        "ks_oa_miller": sum(nb * 2 * h for h in rounds) * costs["e_miller"],
+        "ks_final_exp": (2 * lK * nb + 1) * costs["e_final_exp"],
+        "ks_f12_step": (K - 1 + sum(2 * nb * (h - 1) for h in rounds)) * costs["e_f12_mul"],
+        "ks_oa_fold_g2": sum(nb * h for h in rounds) * (costs["e_g2_mul"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]),
+        "ks_kzg_terms": nb * (2 * K - 2) * costs["e_g2_mul"],
         "kw_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
         "kw_oa_g1terms": sum(nb * 2 * h for h in rounds) * costs["g1_mul"],
-        "kw_kzg_terms": nb * (2 * K - 2) * costs["g2_mul"],
         "kw_hyper_terms": lM * (M // 2) * costs["g1_mul"],
     }
     return w
@@ -168,7 +178,7 @@ def main():
     kernels = {k: {"launches": c // a.steps, "ms_per_step": round(ms / a.steps, 4),
                    "share": round(ms / total_prof, 4) if total_prof else None}
                for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
-    msm_ms = (prof.get("k_msm_slices", (0, 0))[1] + prof.get("k_sum_g1", (0, 0))[1]) / a.steps
+    msm_ms = (prof.get("k_msm_slices", (0, 0))[1] + prof.get("kw_sum_g1", (0, 0))[1]) / a.steps
     extra = {"commit_ms": round(statistics.median(commit_ms), 3),
              "open_ms_all": [round(x, 3) for x in open_ms],
              "open_ms_mean": round(statistics.mean(open_ms), 3),
@@ -177,9 +187,15 @@ def main():
     if not a.no_extra:
         L2, b2 = 20, 400
         _, c2, o2, p2, _ = run_workload(V, torch, L2, b2, 256, 3, max(1, min(a.steps, 2)), 1)
-        msm2 = (p2.get("k_msm_slices", (0, 0))[1] + p2.get("k_sum_g1", (0, 0))[1]) / max(1, min(a.steps, 2))
+        msm2 = (p2.get("k_msm_slices", (0, 0))[1] + p2.get("kw_sum_g1", (0, 0))[1]) / max(1, min(a.steps, 2))
         extra["n2^20_b400"] = {"all_proofs_ms": round(statistics.median(o2), 3), "commit_ms": round(statistics.median(c2), 3),
                                "msm_points_per_s": round((1 << L2) / (msm2 / 1e3)) if msm2 else None}
+        # batch-size sweep (one timed step each): all-N-proofs ms
+        sweep = {}
+        for (Ls, bs, bits_s, seed_s) in ((16, 1, 32, 2), (16, 16, 32, 2), (20, 20, 256, 3), (20, 1, 256, 3)):
+            _, cs_, os_, _, _ = run_workload(V, torch, Ls, bs, bits_s, seed_s, 1, 1, profile=False)
+            sweep["n2^%d_b%d" % (Ls, bs)] = round(os_[0], 3)
+        extra["b_sweep_all_proofs_ms"] = sweep
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(L, b, bits, seed)

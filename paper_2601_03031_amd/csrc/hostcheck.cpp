@@ -323,6 +323,36 @@ API int hc_g2_mul(const uint8_t *Qb, const uint8_t *kb, const uint8_t *Ab, uint8
   return 0;
 }
 
+
+// Montgomery products (MUL operations) in the engine's programs, for the work model:
+// 0 Miller loop (whole sequence), 1 final exponentiation (whole sequence, without the
+// one-lane inversion), 2 G2 psi images, 3 G2 table, 4 G2 doubling, 5 G2 addition,
+// 6 G2 mixed addition, 7 G2 to affine (norm + affine), 8 F_p12 product
+static uint64_t prog_muls(int prog) {
+  const slp::ProgDesc d = slp::PROGS[prog];
+  uint64_t n = 0;
+  for (uint32_t i = 0; i < (uint32_t)d.nlev * d.width; i++) n += (slp::OPS[d.off + i][0] & 3) == 1;
+  return n;
+}
+API uint64_t hc_engine_muls(int which) {
+  uint64_t n = 0;
+  switch (which) {
+    case 0: for (int s = 0; s < slp::ML_SEQ_LEN; s++) n += prog_muls(slp::ML_SEQ[s][0]); return n;
+    case 1:
+      for (int e = 0; e < slp::FE_SEQ_LEN; e++)
+        if (slp::FE_SEQ[e][0] != slp::PROG_INV) n += prog_muls(slp::FE_SEQ[e][0]);
+      return n;
+    case 2: return prog_muls(slp::PROG_G2_PSI);
+    case 3: return prog_muls(slp::PROG_G2_TABLE);
+    case 4: return prog_muls(slp::PROG_G2_DBL);
+    case 5: return prog_muls(slp::PROG_G2_ADD);
+    case 6: return prog_muls(slp::PROG_G2_MADD);
+    case 7: return prog_muls(slp::PROG_G2_NORM) + prog_muls(slp::PROG_G2_AFF);
+    case 8: return prog_muls(slp::PROG_F12_MUL);
+  }
+  return 0;
+}
+
 #ifdef VC_COUNT_MULS
 // Field multiplications (F_p or F_r, Montgomery) performed by one operation of the
 // GPU path's formulas: 0 Miller loop, 1 final exponentiation, 2 G1 scalar mul
