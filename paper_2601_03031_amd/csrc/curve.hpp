@@ -155,6 +155,36 @@ template <class O> NOINL jac<O> scalar_mul(const aff<O> &P, const uint32_t k[8])
   return acc;
 }
 
+#include "glv.hpp"
+
+// k P on G1 with the GLV split k = k_0 + k_1 lam: bases B0 = sign(k_0) P and
+// B1 = sign(k_1) phi(P), phi(x, y) = (beta x, y); joint 2-bit windows d0 + 4 d1 over the
+// table d0 B0 + d1 B1 (Jacobian), two doublings and at most one addition per window
+inline NOINL g1_jac g1_mul_glv(const g1_aff &P, const glv::Dec &d) {
+  if (aff_is_inf(P) || d.nbits == 0) return jac_inf<OpsG1>();
+  g1_aff B0 = P, B1 = {fp_mul(P.x, fe_const(bn::GLV_BETA)), P.y};
+  if (d.neg & 1) B0 = aff_neg(B0);
+  if (d.neg & 2) B1 = aff_neg(B1);
+  g1_jac T[16];
+  T[0] = jac_inf<OpsG1>();
+  T[1] = jac_from_aff(B0);
+  T[2] = jac_dbl(T[1]);
+  T[3] = jac_madd(T[2], B0);
+  T[4] = jac_from_aff(B1);
+  T[8] = jac_dbl(T[4]);
+  T[12] = jac_madd(T[8], B1);
+  for (int d1 = 1; d1 < 4; d1++)
+    for (int d0 = 1; d0 < 4; d0++) T[d0 + 4 * d1] = jac_add(T[4 * d1], T[d0]);
+  int nw = (int)(d.nbits + 1) / 2;
+  g1_jac acc = T[glv::digit2(d, (uint32_t)(nw - 1))];
+  for (int w = nw - 2; w >= 0; w--) {
+    acc = jac_dbl(jac_dbl(acc));
+    uint32_t dg = glv::digit2(d, (uint32_t)w);
+    if (dg) acc = jac_add(acc, T[dg]);
+  }
+  return acc;
+}
+
 template <class O> DEV bool aff_on_curve(const aff<O> &p) {
   if (aff_is_inf(p)) return true;
   typename O::T l = O::sqr(p.y), r = O::add(O::mul(O::sqr(p.x), p.x), O::b());

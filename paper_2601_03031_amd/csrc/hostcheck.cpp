@@ -353,6 +353,16 @@ API uint64_t hc_engine_muls(int which) {
   return 0;
 }
 
+
+// k P on G1 through the GLV split (host build of the device formulas); P, out affine BE
+API int hc_g1_mul_glv(const uint8_t *Pb, const uint8_t *kb, uint8_t *out, uint8_t *dec_out) {
+  fe k = rd_raw(kb);
+  glv::Dec d = glv::decompose(k.l);
+  if (dec_out) memcpy(dec_out, &d, sizeof d);
+  wrg1(out, jac_to_aff(g1_mul_glv(rdg1(Pb), d)));
+  return 0;
+}
+
 #ifdef VC_COUNT_MULS
 // Field multiplications (F_p or F_r, Montgomery) performed by one operation of the
 // GPU path's formulas: 0 Miller loop, 1 final exponentiation, 2 G1 scalar mul

@@ -257,6 +257,15 @@ __global__ void __launch_bounds__(TPB) k_gather_encode(const fe *base, const uin
   }
 }
 
+
+// GLV split of the round challenge x_j of every batch (one thread per batch)
+__global__ void __launch_bounds__(TPB) k_glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out) {
+  uint64_t k = gtid();
+  if (k >= nb) return;
+  fe c = f_from_mont<FpR>(X[k * lK + (j - 1)]);
+  out[k] = glv::decompose(c.l);
+}
+
 namespace kl {
 void ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n, hipStream_t st) { L1(k_ek_weights, n, lM, s, w, n); }
 void pow_table(const fe *beta, fe *out, uint64_t n, hipStream_t st) { L1(k_pow_table, n, beta, out, n); }
@@ -288,6 +297,9 @@ void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t 
 void oa_fold_g1(g1_aff *A, fe *B, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st) {
   L1(k_oa_fold_g1, nb * h, A, B, X, Xinv, K, nb, h, j, lK);
+}
+void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st) {
+  L1(k_glv_dec, nb, X, nb, j, lK, out);
 }
 void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_t st) { L1(k_ylevel0, N, m, r, M, N, Y); }
 void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st) { L1(k_ylevel, (K >> h) * M, Y, M, K, h); }

@@ -72,23 +72,30 @@ __global__ void __launch_bounds__(TPB) k_fc_r(uint64_t K, uint32_t b, uint64_t n
   B[k * K + a] = sha::xmd_finish_fr(hs, DSTR_FC_R);
 }
 
-// per batch: finish L_j, R_j (affine G1 parts), hash them into x_j, keep x_j and 1/x_j
-__global__ void __launch_bounds__(TPB) k_oa_transcript(const g1_jac *S, const fp12 *Lgt, const fp12 *Rgt, uint64_t K, uint64_t nb,
-                                uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, fe *X, fe *Xinv, int *err) {
+// affine G1 parts of L_j, R_j from the reduced term sums, one thread per (batch, side)
+__global__ void __launch_bounds__(TPB) k_oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK,
+                                                   g1_aff *Lg1, g1_aff *Rg1) {
+  uint64_t id = gtid();
+  if (id >= 2 * nb) return;
+  uint64_t k = id / 2, side = id % 2;
+  g1_aff a = jac_to_aff(S[(k * 2 + side) * (K / 2)]);
+  (side ? Rg1 : Lg1)[k * lK + (j - 1)] = a;
+}
+
+// per batch: hash L_j, R_j into x_j, keep x_j and 1/x_j
+__global__ void __launch_bounds__(TPB) k_oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j,
+                                                       uint32_t lK, const g1_aff *Lg1, const g1_aff *Rg1, fe *X, fe *Xinv,
+                                                       int *err) {
   uint64_t k = gtid();
   if (k >= nb) return;
   uint64_t slot = k * lK + (j - 1);
-  g1_aff l = jac_to_aff(S[(k * 2 + 0) * (K / 2)]);
-  g1_aff r = jac_to_aff(S[(k * 2 + 1) * (K / 2)]);
-  Lg1[slot] = l;
-  Rg1[slot] = r;
   sha::Hasher hs;
   sha::xmd_begin(hs);
   if (j > 1) hs.field<FpR>(X[slot - 1]);
   hs.gt(Lgt[slot]);
-  hs.g1(l);
+  hs.g1(Lg1[slot]);
   hs.gt(Rgt[slot]);
-  hs.g1(r);
+  hs.g1(Rg1[slot]);
   fe x = sha::xmd_finish_fr(hs, DSTR_FC_X);
   if (fe_is_zero(x)) atomicOr(err, VC_ERRBIT_CHALLENGE);
   X[slot] = x;
@@ -221,9 +228,12 @@ void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t
   L1(k_fc_sigma, nb, C, K, b, nb, Hq, sigma);
 }
 void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st) { L1(k_fc_r, nb * b, K, b, nb, sigma, B); }
-void oa_transcript(const g1_jac *S, const fp12 *Lgt, const fp12 *Rgt, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK,
-                   g1_aff *Lg1, g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st) {
-  L1(k_oa_transcript, nb, S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err);
+void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st) {
+  L1(k_oa_lr_aff, 2 * nb, S, K, nb, j, lK, Lg1, Rg1);
+}
+void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
+                   const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st) {
+  L1(k_oa_transcript, nb, Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err);
 }
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   hipStream_t st) {

@@ -60,6 +60,10 @@ __device__ __forceinline__ bool scalar_is_zero(const uint32_t k[8]) {
   return t == 0;
 }
 
+// scalar multiplication by a canonical scalar: GLV split on G1, fixed windows on G2
+__device__ __forceinline__ g1_jac mul_any(const g1_aff &P, const uint32_t kk[8]) { return g1_mul_glv(P, glv::decompose(kk)); }
+__device__ __forceinline__ g2_jac mul_any(const g2_aff &P, const uint32_t kk[8]) { return scalar_mul(P, kk); }
+
 // ---------------------------------------------------------------- pairings
 __global__ void __launch_bounds__(TPBW) kw_miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n,
                                                  void *out) {
@@ -86,7 +90,7 @@ __global__ void __launch_bounds__(TPBW) kw_mul(const void *P, int broadcast, con
   if (i >= n) return;
   uint32_t kk[8];
   wscalar(kk, wld<fe>(k, i));
-  wst(out, i, jac_to_aff(scalar_mul(wld<aff<O>>(P, broadcast ? 0 : i), kk)));
+  wst(out, i, jac_to_aff(mul_any(wld<aff<O>>(P, broadcast ? 0 : i), kk)));
 }
 
 // terms of <A_R, b_L> (side 0) and <A_L, b_R> (side 1), Jacobian
@@ -100,20 +104,19 @@ __global__ void __launch_bounds__(TPBW) kw_oa_g1terms(const void *A, const void 
   if (!fe_is_zero(c)) {
     uint32_t kk[8];
     wscalar(kk, c);
-    out = scalar_mul(wld<g1_aff>(A, side ? k * K + i : k * K + h + i), kk);
+    out = mul_any(wld<g1_aff>(A, side ? k * K + i : k * K + h + i), kk);
   }
   wst(S, (k * 2 + side) * (K / 2) + i, out);
 }
 
-// A_j = A_L o A_R^{x_j}, b_j = b_L + b_R / x_j
-__global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(void *A, void *B, const void *X, const void *Xinv, uint64_t K,
+// A_j = A_L o A_R^{x_j}, b_j = b_L + b_R / x_j; x_j enters through its GLV split (per batch)
+__global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(void *A, void *B, const void *Xinv, const glv::Dec *dec, uint64_t K,
                                                      uint64_t nb, uint64_t h, uint32_t j, uint32_t lK) {
   uint64_t id = wgid();
   if (id >= nb * h) return;
   uint64_t k = id / h, i = id % h, slot = k * lK + (j - 1);
-  uint32_t kk[8];
-  wscalar(kk, wld<fe>(X, slot));
-  g1_jac t = scalar_mul(wld<g1_aff>(A, k * K + h + i), kk);
+  glv::Dec d = dec[k];
+  g1_jac t = g1_mul_glv(wld<g1_aff>(A, k * K + h + i), d);
   wst(A, k * K + i, jac_to_aff(jac_madd(t, wld<g1_aff>(A, k * K + i))));
   fe bl = wld<fe>(B, k * K + i), br = wld<fe>(B, k * K + h + i);
   wst(B, k * K + i, fr_add(bl, fr_mul(br, wld<fe>(Xinv, slot))));
@@ -156,7 +159,7 @@ __global__ void __launch_bounds__(TPBW) kw_hyper_terms(const void *g, const void
   if (!fe_is_zero(q)) {
     uint32_t kk[8];
     wunpack(kk, q);
-    out = scalar_mul(wld<g1_aff>(ek, (1ull << (k - 1)) - 1 + c), kk);
+    out = mul_any(wld<g1_aff>(ek, (1ull << (k - 1)) - 1 + c), kk);
   }
   wst(S, id, out);
 }
@@ -262,9 +265,9 @@ void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStre
 void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st) {
   LW(kw_oa_g1terms, nb * 2 * h, A, B, K, nb, h, S);
 }
-void oa_fold_g1(void *A, void *B, const void *X, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+void oa_fold_g1(void *A, void *B, const void *Xinv, const void *dec, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
                 uint32_t lK, hipStream_t st) {
-  LW(kw_oa_fold_g1, nb * h, A, B, X, Xinv, K, nb, h, j, lK);
+  LW(kw_oa_fold_g1, nb * h, A, B, Xinv, static_cast<const glv::Dec *>(dec), K, nb, h, j, lK);
 }
 void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
   LW(kw_oa_fold_g2, nb * h, V, Xinv, K, nb, h, j, lK);

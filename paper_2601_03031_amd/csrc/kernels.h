@@ -33,8 +33,9 @@ void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *
 void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
 void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st);
 void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st);
-void oa_transcript(const g1_jac *S, const fp12 *Lgt, const fp12 *Rgt, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK,
-                   g1_aff *Lg1, g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
+void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st);
+void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
+                   const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
 void oa_fold_g1(g1_aff *A, fe *B, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st);
 void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
@@ -44,6 +45,7 @@ void kzg_terms(const g2_aff *h, const fe *Q, uint64_t K, uint64_t nb, g2_jac *S,
 void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st);
 void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st);
 void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st);
+void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st);
 void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_t st);
 void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st);
 void dlevel(g1_aff *D, uint64_t K, uint32_t h, hipStream_t st);
@@ -60,7 +62,7 @@ void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h
 void g1_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
 void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
 void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st);
-void oa_fold_g1(void *A, void *B, const void *X, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+void oa_fold_g1(void *A, void *B, const void *Xinv, const void *dec, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
                 uint32_t lK, hipStream_t st);
 void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S, hipStream_t st);

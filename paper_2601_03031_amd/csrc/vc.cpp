@@ -361,7 +361,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   size_t o_err = t.take<int>(1), o_A = t.take<g1_aff>(nb * K), o_V = t.take<g2_aff>(nb * K), o_B = t.take<fe>(nb * K);
   size_t o_F = t.take<fp12>(nb * K), o_S = t.take<g1_jac>(nb * K), o_Hq = t.take<uint32_t>(nb * qmax * 8);
   size_t o_sig = t.take<uint32_t>(nb * 8), o_Xi = t.take<fe>(nb * lK), o_Q = t.take<fe>(nb * nq), o_z = t.take<fe>(nb);
-  size_t o_S2 = t.take<g2_jac>(nb * nq), o_HS = t.take<g1_jac>(lM * (M / 2));
+  size_t o_S2 = t.take<g2_jac>(nb * nq), o_HS = t.take<g1_jac>(lM * (M / 2)), o_dec = t.take<glv::Dec>(nb);
   int rc = ensure_ws(pp, t.off);
   if (rc) { vc_proofs_free(pr); return rc; }
   void *ws = pp->ws;
@@ -375,6 +375,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   fe *Xinv = at<fe>(ws, o_Xi), *Q = at<fe>(ws, o_Q), *z = at<fe>(ws, o_z);
   g2_jac *S2 = at<g2_jac>(ws, o_S2);
   g1_jac *HS = at<g1_jac>(ws, o_HS);
+  glv::Dec *gdec = at<glv::Dec>(ws, o_dec);
 
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
@@ -418,13 +419,15 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     if (int rc2 = stream_wait(pp, 1, st, s2)) return rc2;
     klw::oa_g1terms(A, B, K, nb, h, S, s2);
     klw::g1_reduce(S, 2 * nb, K / 2, h, s2);
+    kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, s2);
     ks::oa_miller(A, V, K, nb, h, F, st);
     ks::f12_reduce(F, 2 * nb, K / 2, h, st);
     ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
     if (int rc2 = stream_wait(pp, 2, s2, st)) return rc2;
-    kl::oa_transcript(S, Lgt, Rgt, K, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
+    kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
     if (int rc2 = stream_wait(pp, 3, st, s2)) return rc2;
-    klw::oa_fold_g1(A, B, X, Xinv, K, nb, h, j, lK, s2);
+    kl::glv_dec(X, nb, j, lK, gdec, s2);
+    klw::oa_fold_g1(A, B, Xinv, gdec, K, nb, h, j, lK, s2);
     ks::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
     if (int rc2 = stream_wait(pp, 4, s2, st)) return rc2;
   }

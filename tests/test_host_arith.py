@@ -256,3 +256,29 @@ def test_g2_scalar_mul_engine(hc):
         if Ab is not None:
             want = O.g2_op("add", want, Ab)
         assert o.raw == want, (k,)
+
+
+def test_g1_glv(hc):
+    """phi(x, y) = (beta x, y) is multiplication by the chosen cube root of unity lam on
+    G1 (pinned against the oracle); k = k_0 + k_1 lam with |k_j| < 2^128; k P through the
+    split equals the oracle's k P, including k = 0, 1, r - 1 and the identity."""
+    g1, g2 = O.generators()
+    beta = 0x59E26BCEA0D48BACD4F263F1ACDB5C4F5763473177FFFFFE
+    lam = 0xB3C4D79D41A917585BFC41088D8DAAA78B17EA66B99C90DD
+    x, y = int.from_bytes(g1[:32], "big"), int.from_bytes(g1[32:], "big")
+    assert O.g1_op("mul", g1, O.be32(lam)) == O.be32(beta * x % P) + O.be32(y)
+    rng = random.Random(16)
+    for k in [0, 1, 2, R - 1, R - 2, (R - 1) // 2] + [rng.randrange(R) for _ in range(60)]:
+        Pt = O.g1_op("mul", g1, O.be32(rng.randrange(1, R)))
+        o, dec = buf(64), buf(40)
+        hc.hc_g1_mul_glv(Pt, k.to_bytes(32, "big"), o, dec)
+        assert o.raw == O.g1_op("mul", Pt, O.be32(k)), k
+        w = [int.from_bytes(dec.raw[4 * i:4 * i + 4], "little") for i in range(10)]
+        k0 = w[0] | w[1] << 32 | w[2] << 64 | w[3] << 96
+        k1 = w[4] | w[5] << 32 | w[6] << 64 | w[7] << 96
+        k0 = -k0 if w[8] & 1 else k0
+        k1 = -k1 if w[8] & 2 else k1
+        assert (k0 + k1 * lam - k) % R == 0 and max(abs(k0), abs(k1)) < 2**128
+    o = buf(64)
+    hc.hc_g1_mul_glv(bytes(64), (12345).to_bytes(32, "big"), o, None)
+    assert o.raw == bytes(64)
