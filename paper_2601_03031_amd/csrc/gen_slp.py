@@ -1117,8 +1117,9 @@ class Kernel:
 
 def encode_op(op):
     """192-bit op: kind (2) | dst (12) | na (4) | 8 x (slot 12 | coefficient 8, two's complement);
-    a product multiplies the sum of terms [0, na) by the sum of terms [na, 8); unused
-    terms have coefficient 0"""
+    a product multiplies the sum of terms [0, SIDE) by the sum of terms [SIDE, 8); unused
+    terms have coefficient 0.  In the emitted tables na is the number of leading term
+    positions that any operation of the level uses (uniform over the level)."""
     kind, dst, na, terms = op
     assert 0 <= dst < 4096 and len(terms) <= NTERM and 0 <= na <= NTERM
     x = kind | (dst << 2) | (na << 14)
@@ -1174,7 +1175,6 @@ def emit(kernels):
         w(line)
     allops = []
     descs = []
-    levn = []
     for k in kernels:
         w("// kernel %s: %d slots (%d state, %d constants)" % (k.name, k.nslots, len(k.state), len(k.consts)))
         w("static constexpr int %s_NSLOT = %d;" % (k.name.upper(), k.nslots))
@@ -1184,18 +1184,20 @@ def emit(kernels):
             w("static constexpr int %s_%s = %d;" % (k.name.upper(), nm.replace(".", "_"), s))
         for nm, enc in k.progs.items():
             width = max(1, max(len(r) for r in enc))
-            descs.append((k.name, nm, len(allops), len(enc), width, len(levn)))
+            descs.append((k.name, nm, len(allops), len(enc), width))
             w("static constexpr int PROG_%s = %d;" % (nm.upper(), len(descs) - 1))
             for row in enc:
-                allops += [encode_op(op) for op in row] + [0] * (width - len(row))
-                # terms in use: the highest term position with a nonzero coefficient, plus one
-                levn.append(max([max([i + 1 for i, (_, c) in enumerate(op[3]) if c] + [0]) for op in row] + [0]))
-    w("struct ProgDesc { uint32_t off; uint16_t nlev; uint16_t width; uint32_t moff; };")
+                # terms in use by the level: the highest term position with a nonzero
+                # coefficient, plus one; it replaces the na field of every operation of the
+                # level (products split their terms at the fixed position SIDE)
+                nt = max([max([i + 1 for i, (_, c) in enumerate(op[3]) if c] + [0]) for op in row] + [0])
+                assert all(op[0] != OP_MUL or op[2] == SIDE for op in row)
+                allops += [encode_op((op[0], op[1], nt, op[3])) for op in row] + [0] * (width - len(row))
+    w("struct ProgDesc { uint32_t off; uint16_t nlev; uint16_t width; };")
     w("__device__ const ProgDesc PROGS[%d] = {" % len(descs))
-    for kn, nm, off, nlev, width, moff in descs:
-        w("  {%du, %du, %du, %du},  // %s" % (off, nlev, width, moff, nm))
+    for kn, nm, off, nlev, width in descs:
+        w("  {%du, %du, %du},  // %s" % (off, nlev, width, nm))
     w("};")
-    w("__device__ const uint8_t LEVN[%d] = {%s};" % (len(levn), ", ".join(str(x) for x in levn)))
     w("__device__ const uint64_t OPS[%d][3] = {" % len(allops))
     for i in range(0, len(allops), 2):
         w("  " + ", ".join("{0x%016xull, 0x%016xull, 0x%016xull}" % (x & (2**64 - 1), (x >> 64) & (2**64 - 1), x >> 128)
