@@ -44,7 +44,11 @@ OP_NOP, OP_MUL, OP_LIN = 0, 1, 2
 
 
 # ============================================================================ tracer
-NTERM = 8       # operands per op (a product splits them between its two factors)
+ENC_NTERM = 16  # term positions of an encoded operation
+ENC_SIDE = 8    # a product's second factor starts at this term position
+# Trace-time limits (set per program by build_all from TRACE_LIMITS): terms of a linear
+# operation and terms of one factor of a product
+NTERM = 16
 
 
 class Prog:
@@ -139,7 +143,7 @@ class F:
         return a
 
 
-SIDE = NTERM // 2   # terms per factor of a product (terms 0..3 and 4..7 of the operation)
+SIDE = 8
 
 
 def operand_terms(p, t):
@@ -953,11 +957,46 @@ def operands(v):
     return ()
 
 
+# Cost of a level in cycles of the interpreter (one wavefront): a fixed part, a part per
+# group of four term positions loaded (the union over the level's operations) and the
+# Montgomery product of a level with products (measured on gfx950).
+LEVEL_BASE, LEVEL_GROUP, LEVEL_MUL = 880, 430, 1310
+
+
+def op_groups(v):
+    """term groups an operation's encoding uses (see encode_op)"""
+    if v[0] == "mul":
+        na, nb = len(v[1]), len(v[2])
+        return ((1 << -(-na // 4)) - 1) | (((1 << -(-nb // 4)) - 1) << 2)
+    return (1 << -(-len(v[1]) // 4)) - 1
+
+
+def levels_cost(p, levels):
+    c = 0
+    for ops in levels:
+        gm = 0
+        mul = False
+        for i in ops:
+            gm |= op_groups(p.vals[i])
+            mul = mul or p.vals[i][0] == "mul"
+        c += LEVEL_BASE + LEVEL_GROUP * bin(gm).count("1") + (LEVEL_MUL if mul else 0)
+    return c
+
+
 def schedule(p, lanes=LANES):
+    """The cheaper of the two stage schedules below (as early / as late as possible)."""
+    a = schedule_phases(p, lanes, late=False)
+    b = schedule_phases(p, lanes, late=True)
+    return b if levels_cost(p, b[0]) <= levels_cost(p, a[0]) else a
+
+
+def schedule_phases(p, lanes=LANES, late=False):
     """Stage scheduling: a product's stage is its multiplicative depth (products on the
     longest path from the inputs), so all products of one depth share one level (split
-    only beyond the lane count).  Additions run in the phase after the products they
-    depend on, levelised by their depth within the phase."""
+    only beyond the lane count).  Additions run in a phase between two product levels,
+    levelised by their depth within the phase: the phase right after the products they
+    depend on, or (late) the last phase before their first use, so that additions that
+    only feed outputs or later products share levels that exist anyway."""
     vals = p.vals
     n = len(vals)
     live = [False] * n
@@ -984,10 +1023,26 @@ def schedule(p, lanes=LANES):
             ld[i] = 1 + max([ld[a] for a in ops_ if md[a] == m] + [0])
     # a product at depth k must follow the additions of phase k-1 that feed it
     maxd = max([md[i] for i in range(n) if is_op[i]] + [0])
-    phase_len = [0] * (maxd + 1)
-    for i in range(n):
-        if is_op[i] and vals[i][0] == "lin":
-            phase_len[md[i]] = max(phase_len[md[i]], ld[i])
+    phase = list(md)
+    if late:
+        users = [[] for _ in range(n)]
+        for i in range(n):
+            if is_op[i]:
+                for a in set(operands(vals[i])):
+                    users[a].append(i)
+        outset = set(p.outputs.values())
+        for i in reversed(range(n)):
+            if not (is_op[i] and vals[i][0] == "lin"):
+                continue
+            lim = maxd if i in outset else 1 << 30
+            for c in users[i]:
+                lim = min(lim, md[c] - 1 if vals[c][0] == "mul" else phase[c])
+            assert md[i] <= lim < 1 << 30
+            phase[i] = lim
+        for i in range(n):
+            if is_op[i] and vals[i][0] == "lin":
+                ld[i] = 1 + max([ld[a] for a in operands(vals[i])
+                                 if is_op[a] and vals[a][0] == "lin" and phase[a] == phase[i]] + [0])
     buckets = {}
     for i in range(n):
         if not is_op[i]:
@@ -995,7 +1050,7 @@ def schedule(p, lanes=LANES):
         if vals[i][0] == "mul":
             key = (md[i] - 1, 1 << 20)          # after phase md-1 additions
         else:
-            key = (md[i], ld[i])
+            key = (phase[i], ld[i])
         buckets.setdefault(key, []).append(i)
     levels = []
     level_of = [-1] * n
@@ -1073,8 +1128,8 @@ def compile_prog(p, io_slot, const_slot, temp_base, temp_limit, lanes=LANES):
             v = vals[i]
             if v[0] == "mul":
                 za = (const_slot(0), 0)
-                ta = tuple((slot[k], c) for k, c in v[1]) + (za,) * (SIDE - len(v[1]))
-                row.append((OP_MUL, slot[i], SIDE, ta + tuple((slot[k], c) for k, c in v[2])))
+                ta = tuple((slot[k], c) for k, c in v[1]) + (za,) * (ENC_SIDE - len(v[1]))
+                row.append((OP_MUL, slot[i], ENC_SIDE, ta + tuple((slot[k], c) for k, c in v[2])))
             else:
                 row.append((OP_LIN, slot[i], len(v[1]), tuple((slot[k], c) for k, c in v[1])))
         enc.append(row)
@@ -1116,25 +1171,68 @@ class Kernel:
 
 
 def encode_op(op):
-    """192-bit op: kind (2) | dst (12) | na (4) | 8 x (slot 12 | coefficient 8, two's complement);
-    a product multiplies the sum of terms [0, SIDE) by the sum of terms [SIDE, 8); unused
-    terms have coefficient 0.  In the emitted tables na is the number of leading term
-    positions that any operation of the level uses (uniform over the level)."""
-    kind, dst, na, terms = op
-    assert 0 <= dst < 4096 and len(terms) <= NTERM and 0 <= na <= NTERM
-    x = kind | (dst << 2) | (na << 14)
+    """384-bit op: kind (2) | dst (12) | group mask (4) | 16 x (slot 12 | coefficient 8,
+    two's complement); a product multiplies the sum of terms [0, 8) by the sum of terms
+    [8, 16); unused terms have slot 0 and coefficient 0.  The mask has bit g set when
+    some operation of the level uses a term in positions 4g .. 4g + 3 (uniform over the
+    level)."""
+    kind, dst, gmask, terms = op
+    assert 0 <= dst < 4096 and len(terms) <= ENC_NTERM and 0 <= gmask < 16
+    # the interpreter adds 65536 p to each factor (or the sum): the scaled coefficient
+    # magnitudes must stay below 32768 so that the sum is positive (slots are below 2p)
+    if kind == OP_MUL:
+        assert 32 * sum(abs(c) for _, c in terms[:ENC_SIDE]) < 32768 and sum(abs(c) for _, c in terms[ENC_SIDE:]) < 32768
+    else:
+        assert sum(abs(c) for _, c in terms) < 32768
+    x = kind | (dst << 2) | (gmask << 14)
     for i, (s, c) in enumerate(terms):
         assert 0 <= s < 4096 and -KMAX <= c <= KMAX
         x |= ((s | ((c & 255) << 12)) << (18 + 20 * i))
     return x
 
 
+def term_groups(op):
+    """bit g set when op has a nonzero coefficient in term positions 4g .. 4g + 3"""
+    m = 0
+    for i, (_, c) in enumerate(op[3]):
+        if c:
+            m |= 1 << (i // 4)
+    return m
+
+
+OP_WORDS = 6
+
+
+TRACE_LIMITS = ((8, 4), (12, 4), (16, 4), (8, 8), (12, 8), (16, 8))
+
+
+def cheapest(make):
+    """trace every program under each (NTERM, SIDE) limit and keep, per program, the trace
+    whose schedule costs least"""
+    global NTERM, SIDE
+    best = {}
+    saved = NTERM, SIDE
+    for nt, sd in TRACE_LIMITS:
+        NTERM, SIDE = nt, sd
+        for nm, p in make().items():
+            c = levels_cost(p, schedule(p)[0])
+            if nm not in best or c < best[nm][0]:
+                best[nm] = (c, p)
+    NTERM, SIDE = saved
+    return {nm: p for nm, (c, p) in best.items()}
+
+
+_BUILT = []
+
+
 def build_all():
-    mk = Kernel("ml", miller_programs(), MILLER_STATE)
-    fe_state = ["t", "tinv"] + ["%s.%d" % (nm, k) for nm in ("nA", "nB", "nC", "n2") for k in (0, 1)]
-    fk = Kernel("fe", fe_programs(), fe_state, segs={"X": 1, "Y": 2, "D": 3})
-    gk = Kernel("g2", g2_programs(), G2_STATE, segs={"A": 2})
-    return mk, fk, gk
+    if not _BUILT:
+        mk = Kernel("ml", cheapest(miller_programs), MILLER_STATE)
+        fe_state = ["t", "tinv"] + ["%s.%d" % (nm, k) for nm in ("nA", "nB", "nC", "n2") for k in (0, 1)]
+        fk = Kernel("fe", cheapest(fe_programs), fe_state, segs={"X": 1, "Y": 2, "D": 3})
+        gk = Kernel("g2", cheapest(g2_programs), G2_STATE, segs={"A": 2})
+        _BUILT.append((mk, fk, gk))
+    return _BUILT[0]
 
 
 # ============================================================================ emission
@@ -1187,21 +1285,22 @@ def emit(kernels):
             descs.append((k.name, nm, len(allops), len(enc), width))
             w("static constexpr int PROG_%s = %d;" % (nm.upper(), len(descs) - 1))
             for row in enc:
-                # terms in use by the level: the highest term position with a nonzero
-                # coefficient, plus one; it replaces the na field of every operation of the
-                # level (products split their terms at the fixed position SIDE)
-                nt = max([max([i + 1 for i, (_, c) in enumerate(op[3]) if c] + [0]) for op in row] + [0])
-                assert all(op[0] != OP_MUL or op[2] == SIDE for op in row)
-                allops += [encode_op((op[0], op[1], nt, op[3])) for op in row] + [0] * (width - len(row))
+                # term groups in use by the level (products split their terms at ENC_SIDE)
+                gm = 0
+                for op in row:
+                    gm |= term_groups(op)
+                assert all(op[0] != OP_MUL or op[2] == ENC_SIDE for op in row)
+                allops += [encode_op((op[0], op[1], gm, op[3])) for op in row] + [0] * (width - len(row))
     w("struct ProgDesc { uint32_t off; uint16_t nlev; uint16_t width; };")
     w("__device__ const ProgDesc PROGS[%d] = {" % len(descs))
     for kn, nm, off, nlev, width in descs:
         w("  {%du, %du, %du},  // %s" % (off, nlev, width, nm))
     w("};")
-    w("__device__ const uint64_t OPS[%d][3] = {" % len(allops))
-    for i in range(0, len(allops), 2):
-        w("  " + ", ".join("{0x%016xull, 0x%016xull, 0x%016xull}" % (x & (2**64 - 1), (x >> 64) & (2**64 - 1), x >> 128)
-                           for x in allops[i:i + 2]) + ",")
+    w("static constexpr int OP_WORDS = %d;" % OP_WORDS)
+    w("__device__ const uint64_t OPS[%d][%d] = {" % (len(allops), OP_WORDS))
+    for x in allops:
+        assert x >> (64 * OP_WORDS) == 0
+        w("  {%s}," % ", ".join("0x%xull" % ((x >> (64 * k)) & (2**64 - 1)) for k in range(OP_WORDS)))
     w("};")
     for k in kernels:
         w("__device__ const uint32_t %s_CONSTS[%d][9] = {" % (k.name.upper(), len(k.consts)))
