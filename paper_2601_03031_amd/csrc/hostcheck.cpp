@@ -54,6 +54,22 @@ static void canon_scalar(uint32_t k[8], const uint8_t *b) {
     k[7 - i] = ((uint32_t)b[4 * i] << 24) | ((uint32_t)b[4 * i + 1] << 16) | ((uint32_t)b[4 * i + 2] << 8) | b[4 * i + 3];
 }
 
+// batched binary GCD on a canonical integer 0 < x < m (which 0: p, 1: r): x^{-1} mod m
+// (big-endian 32 bytes) and the number of outer rounds; returns 1 if it converged
+API int hc_bingcd(int which, const uint8_t *x, uint8_t *out, int *rounds) {
+  fe a, r;
+  for (int i = 0; i < 8; i++) {
+    const uint8_t *q = x + 28 - 4 * i;
+    a.l[i] = (uint32_t)q[0] << 24 | (uint32_t)q[1] << 16 | (uint32_t)q[2] << 8 | q[3];
+  }
+  bool ok = which == 0 ? bingcd::inverse<FpP>(a, r, rounds) : bingcd::inverse<FpR>(a, r, rounds);
+  for (int i = 0; i < 8; i++) {
+    uint8_t *q = out + 28 - 4 * i;
+    q[0] = (uint8_t)(r.l[i] >> 24); q[1] = (uint8_t)(r.l[i] >> 16); q[2] = (uint8_t)(r.l[i] >> 8); q[3] = (uint8_t)r.l[i];
+  }
+  return ok ? 1 : 0;
+}
+
 // op: 0 add 1 sub 2 mul 3 inv(Fermat) 4 inv(binary) 5 half
 API int hc_field(int which, int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
   if (which == 0) {

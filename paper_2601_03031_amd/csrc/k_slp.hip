@@ -141,7 +141,10 @@ __device__ void g2_job(f29 *S, gls::Dec *dec, const g2_aff *Q, const fe *k_mont,
     return;
   }
   c.run(slp::PROG_G2_NORM, 0, 0, 0);
-  if (t == 0) S[slp::G2_tinv] = slp::to29(f_inv_binary<FpP>(slp::from29(slp::canon29(S[slp::G2_t])), bn::P_R3));
+  {
+    fe ti = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G2_t])), bn::P_R3);
+    if (t == 0) S[slp::G2_tinv] = slp::to29(ti);
+  }
   __syncthreads();
   c.run(slp::PROG_G2_AFF, 0, 0, 0);
   if (t < 4) o[t] = slp::from29(slp::canon29(S[slp::G2_ax_0 + t]));

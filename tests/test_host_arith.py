@@ -282,3 +282,20 @@ def test_g1_glv(hc):
     o = buf(64)
     hc.hc_g1_mul_glv(bytes(64), (12345).to_bytes(32, "big"), o, None)
     assert o.raw == bytes(64)
+
+
+@pytest.mark.parametrize("which,mod", [(0, P), (1, R)])
+def test_bingcd_inverse(hc, which, mod):
+    """The batched binary GCD itself (without the exponentiation fallback) against
+    Python's modular inverse, with its round count within the 2 len(m) - 1 step bound."""
+    rng = random.Random(300 + which)
+    vals = [1, 2, 3, mod - 1, mod - 2, (mod + 1) // 2, 1 << 200, (1 << 253) + 1, (1 << 64) - 1, 1 << 64]
+    vals += [rng.randrange(1, mod) for _ in range(400)] + [rng.randrange(1, 1 << 70) for _ in range(50)]
+    rounds = C.c_int(0)
+    worst = 0
+    for x in vals:
+        o = buf(32)
+        assert hc.hc_bingcd(which, O.be32(x), o, C.byref(rounds)) == 1, x
+        assert int.from_bytes(o.raw, "big") == pow(x, -1, mod), x
+        worst = max(worst, rounds.value)
+    assert worst <= -(-(2 * mod.bit_length() - 1) // 30), worst
