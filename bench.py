@@ -86,7 +86,8 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile=True):
+def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile="all"):
+    """profile: None, "all" (every kernel launch bracketed by events) or one kernel name"""
     import numpy as np
     log("workload L=%d b=%d bits=%d seed=%d: setup" % (L, b, bits, seed))
     from paper_2601_03031_amd import inputs as I
@@ -105,6 +106,7 @@ def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile=True):
     log("warmup done; timing %d steps" % steps)
     commit_ms, open_ms = [], []
     if profile:
+        V.vc_profile_only(None if profile == "all" else profile)
         V.vc_profile_enable(True)
     t_all = time.perf_counter()
     for _ in range(steps):
@@ -120,6 +122,7 @@ def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile=True):
     wall = time.perf_counter() - t_all
     prof = V.vc_profile_read() if profile else {}
     V.vc_profile_enable(False)
+    V.vc_profile_only(None)
     return limbs, commit_ms, open_ms, prof, wall
 
 
@@ -161,24 +164,29 @@ def main():
         sys.exit(1)
 
     L, b, bits, seed = 16, 256, 32, 2
-    limbs, commit_ms, open_ms, prof, wall = run_workload(V, torch, L, b, bits, seed, a.steps, a.warmup)
+    # per-kernel table from a separate pass with every launch bracketed by events (the
+    # events cost host time and would perturb the timed steps); it names the dominant kernel
+    psteps = 2
+    limbs, _, _, prof, _ = run_workload(V, torch, L, b, bits, seed, psteps, a.warmup)
+    total_prof = sum(ms for _, ms in prof.values())
+    dname = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    # timed steps: only the dominant kernel's launches carry events (its average duration)
+    _, commit_ms, open_ms, pdom, wall = run_workload(V, torch, L, b, bits, seed, a.steps, a.warmup, profile=dname)
+    dcount, dms = pdom.get(dname, (0, 0.0))
     costs = op_costs()
     work = work_model(L, b, limbs, costs)
-    total_prof = sum(ms for _, ms in prof.values())
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    dname, (dcount, dms) = dom
     roofline = None
-    if dname in work:
+    if dname in work and dcount:
         per_launch_fmul = work[dname] / (dcount / a.steps)
         avg_s = dms / dcount / 1e3
         achieved = per_launch_fmul * MADS_PER_FMUL / avg_s / 1e12
         roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 4), "peak": round(PEAK_MAD_TOPS, 2),
                     "unit": "TOP/s", "frac": round(achieved / PEAK_MAD_TOPS, 5), "traffic": None,
                     "per_launch_field_mults": int(per_launch_fmul), "avg_launch_ms": round(dms / dcount, 4)}
-    kernels = {k: {"launches": c // a.steps, "ms_per_step": round(ms / a.steps, 4),
+    kernels = {k: {"launches": c // psteps, "ms_per_step": round(ms / psteps, 4),
                    "share": round(ms / total_prof, 4) if total_prof else None}
                for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
-    msm_ms = (prof.get("k_msm_slices", (0, 0))[1] + prof.get("kw_sum_g1", (0, 0))[1]) / a.steps
+    msm_ms = (prof.get("k_msm_slices", (0, 0))[1] + prof.get("kw_sum_g1", (0, 0))[1]) / psteps
     extra = {"commit_ms": round(statistics.median(commit_ms), 3),
              "open_ms_all": [round(x, 3) for x in open_ms],
              "open_ms_mean": round(statistics.mean(open_ms), 3),
@@ -186,8 +194,10 @@ def main():
              "kernels": kernels}
     if not a.no_extra:
         L2, b2 = 20, 400
-        _, c2, o2, p2, _ = run_workload(V, torch, L2, b2, 256, 3, max(1, min(a.steps, 2)), 1)
-        msm2 = (p2.get("k_msm_slices", (0, 0))[1] + p2.get("kw_sum_g1", (0, 0))[1]) / max(1, min(a.steps, 2))
+        n2 = max(1, min(a.steps, 2))
+        _, _, _, p2, _ = run_workload(V, torch, L2, b2, 256, 3, 1, 1)
+        _, c2, o2, _, _ = run_workload(V, torch, L2, b2, 256, 3, n2, 1, profile=None)
+        msm2 = p2.get("k_msm_slices", (0, 0))[1] + p2.get("kw_sum_g1", (0, 0))[1]
         extra["n2^20_b400"] = {"all_proofs_ms": round(statistics.median(o2), 3), "commit_ms": round(statistics.median(c2), 3),
                                "msm_points_per_s": round((1 << L2) / (msm2 / 1e3)) if msm2 else None}
         # batch-size sweep (one timed step each): all-N-proofs ms

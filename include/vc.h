@@ -90,11 +90,15 @@ int vc_commitment_export(const vc_commitment *cm, int what, void *dst, size_t ca
 int vc_proofs_export(const vc_proofs *pr, int what, uint64_t idx, void *dst, size_t cap, size_t *len);
 
 /* Per-kernel timing for measurement: while enabled, every kernel launch of the
- * library is bracketed by HIP events recorded on its own stream.
+ * library (or, after vc_profile_only(name), only launches of the kernel with that
+ * name; NULL selects all again) is bracketed by HIP events recorded on its own stream.
  * vc_profile_read writes one line per kernel, "<name> <launches> <total_ms>\n", into
  * buf (NUL-terminated, truncated to cap) and returns the size needed.
- * vc_profile_enable(1) also clears previous records.  Not thread-safe. */
+ * vc_profile_enable also clears previous records (waiting for the device first if
+ * there are any).  The events come from a pool kept until the process ends.  Not
+ * thread-safe. */
 void vc_profile_enable(int on);
+void vc_profile_only(const char *kernel);
 int vc_profile_read(char *buf, size_t cap);
 
 /* Self-test of the device field layer used by the proof rounds (8 lanes per

@@ -47,6 +47,7 @@ def lib():
         for f in ("vc_params_free", "vc_commitment_free", "vc_proofs_free"):
             getattr(L, f).argtypes = [vp]
         L.vc_profile_enable.argtypes = [C.c_int]
+        L.vc_profile_only.argtypes = [C.c_char_p]
         L.vc_profile_read.argtypes = [C.c_char_p, sz]
         L.vc_strerror.restype = C.c_char_p
         L.vc_strerror.argtypes = [C.c_int]
@@ -171,6 +172,11 @@ def vc_verify(pp: Params, C_bytes: bytes, b: int, i: int, m_i: int, proof: bytes
 
 def vc_profile_enable(on: bool = True) -> None:
     lib().vc_profile_enable(1 if on else 0)
+
+
+def vc_profile_only(kernel=None) -> None:
+    """Restrict profiling to launches of one kernel (None: every kernel)."""
+    lib().vc_profile_only(kernel.encode() if kernel else None)
 
 
 def vc_profile_read() -> dict:

@@ -131,6 +131,12 @@ class F:
             a, b = b, a
         return F(self.p, {self.p.new(("mul", a, b)): 1})
 
+    def sqr(self):
+        return self * self
+
+    def mul(self, o):
+        return self * o
+
     def atom(self):
         if not self.t:
             return self.p.zero
@@ -942,6 +948,75 @@ def g2_programs():
     return progs
 
 
+# G1 (y^2 = x^3 + 3 over F_p) on the engine: GLV with phi(x, y) = (beta x, y)
+GLV_BETA = 0x59E26BCEA0D48BACD4F263F1ACDB5C4F5763473177FFFFFE
+GLV_LAM = 0xB3C4D79D41A917585BFC41088D8DAAA78B17EA66B99C90DD
+
+
+def g1_jin(p, name):
+    return tuple(p.inp("%s.%d" % (name, c)) for c in range(3))
+
+
+def g1_jout(p, name, T):
+    for c, v in enumerate(T):
+        p.out("%s.%d" % (name, c), v)
+
+
+def g1_programs():
+    progs = {}
+    p = Prog("g1_phi")
+    p.out("B1.x", p.inp("xP") * p.fconst(GLV_BETA))
+    progs[p.name] = p
+    # table TB[d0 + 4 d1] = d0 B0 + d1 B1 (Jacobian) for the joint 2-bit windows; B0 in
+    # (xP, yP), B1 in (B1.x, B1.y), signs applied by the caller
+    p = Prog("g1_table")
+    one = p.fconst(1)
+    B0 = (p.inp("xP"), p.inp("yP"))
+    B1 = (p.inp("B1.x"), p.inp("B1.y"))
+    TB = {1: (B0[0], B0[1], one), 4: (B1[0], B1[1], one)}
+    TB[2] = j_dbl(TB[1])
+    TB[3], _, _ = j_madd(TB[2], B0)
+    TB[8] = j_dbl(TB[4])
+    TB[12], _, _ = j_madd(TB[8], B1)
+    for d1 in (1, 2, 3):
+        for d0 in (1, 2, 3):
+            TB[d0 + 4 * d1], _, _ = j_add(TB[4 * d1], TB[d0])
+    for d in range(1, 16):
+        g1_jout(p, "TB%d" % d, TB[d])
+    progs[p.name] = p
+    p = Prog("g1_dbl")
+    g1_jout(p, "T", j_dbl(g1_jin(p, "T")))
+    progs[p.name] = p
+    p = Prog("g1_dbl2")
+    g1_jout(p, "T", j_dbl(j_dbl(g1_jin(p, "T"))))
+    progs[p.name] = p
+    p = Prog("g1_dbl2_add")
+    T, H, r = j_add(j_dbl(j_dbl(g1_jin(p, "T"))), g1_jin(p, "A"))
+    g1_jout(p, "T", T)
+    p.out("H", H)
+    p.out("RR", r)
+    progs[p.name] = p
+    p = Prog("g1_madd")
+    T, H, r = j_madd(g1_jin(p, "T"), (p.inp("A.0"), p.inp("A.1")))
+    g1_jout(p, "T", T)
+    p.out("H", H)
+    p.out("RR", r)
+    progs[p.name] = p
+    p = Prog("g1_aff")
+    X, Y, Z = g1_jin(p, "T")
+    zi = p.inp("tinv")
+    zi2 = zi * zi
+    p.out("ax", X * zi2)
+    p.out("ay", Y * (zi2 * zi))
+    progs[p.name] = p
+    return progs
+
+
+G1_STATE = (["T.%d" % k for k in range(3)] + ["xP", "yP", "B1.x", "B1.y"]
+            + ["TB%d.%d" % (d, k) for d in range(1, 16) for k in range(3)]
+            + ["H", "RR", "tinv", "ax", "ay"])
+
+
 G2_STATE = (["T.%d" % k for k in range(6)] + ["xQ.0", "xQ.1", "yQ.0", "yQ.1"]
             + ["B%d.%s.%d" % (j, c, k) for j in range(1, 4) for c in "xy" for k in (0, 1)]
             + ["TB%d.%d" % (d, k) for d in range(1, 16) for k in range(6)]
@@ -1231,7 +1306,8 @@ def build_all():
         fe_state = ["t", "tinv"] + ["%s.%d" % (nm, k) for nm in ("nA", "nB", "nC", "n2") for k in (0, 1)]
         fk = Kernel("fe", cheapest(fe_programs), fe_state, segs={"X": 1, "Y": 2, "D": 3})
         gk = Kernel("g2", cheapest(g2_programs), G2_STATE, segs={"A": 2})
-        _BUILT.append((mk, fk, gk))
+        g1k = Kernel("g1", cheapest(g1_programs), G1_STATE, segs={"A": 2})
+        _BUILT.append((mk, fk, gk, g1k))
     return _BUILT[0]
 
 
@@ -1444,8 +1520,8 @@ def ref_miller(xP, yP, Q):
 
 def check():
     rng = random.Random(5)
-    mk, fk, gk = build_all()
-    for k in (mk, fk, gk):
+    mk, fk, gk, g1k = build_all()
+    for k in (mk, fk, gk, g1k):
         for nm, enc in k.progs.items():
             nmul = sum(1 for r in enc for op in r if op[0] == OP_MUL)
             nmlev = sum(1 for r in enc if any(op[0] == OP_MUL for op in r))
@@ -1531,6 +1607,7 @@ def check():
     assert ref_pow(f, e) == ref_pow(g, e), "Miller loop"
     print("Miller loop ok (%d bodies)" % len(miller_sequence()), file=sys.stderr)
     check_g2(gk, rng)
+    check_g1(g1k, rng)
 
 
 def f2add(a, b):
@@ -1631,6 +1708,79 @@ def check_g2(gk, rng):
         kj = gls_decompose(k)
         assert (sum(kj[j] * pow(lam, j, R) for j in range(4)) - k) % R == 0 and max(abs(x) for x in kj) < 2**65
     print("G2 programs and GLS decomposition ok", file=sys.stderr)
+
+
+def g1_aff_add(A, B):
+    if A is None:
+        return B
+    if B is None:
+        return A
+    if A[0] == B[0]:
+        if (A[1] + B[1]) % P == 0:
+            return None
+        l = 3 * A[0] * A[0] * pow(2 * A[1], -1, P) % P
+    else:
+        l = (B[1] - A[1]) * pow(B[0] - A[0], -1, P) % P
+    x = (l * l - A[0] - B[0]) % P
+    return (x, (l * (A[0] - x) - A[1]) % P)
+
+
+def g1_aff_mul(A, k):
+    R_ = None
+    for bit in bin(k)[2:]:
+        R_ = g1_aff_add(R_, R_)
+        if bit == "1":
+            R_ = g1_aff_add(R_, A)
+    return R_
+
+
+def check_g1(g1k, rng):
+    st = g1k.state
+    def setj(S, name, pt):
+        S[st[name + ".0"]], S[st[name + ".1"]], S[st[name + ".2"]] = pt[0], pt[1], 1
+    def getj(S, name):
+        X, Y, Z = (S[st["%s.%d" % (name, k)]] % P for k in range(3))
+        if Z == 0:
+            return None
+        zi = pow(Z, -1, P)
+        return (X * zi * zi % P, Y * zi * zi * zi % P)
+    for trial in range(3):
+        Pt = g1_aff_mul((1, 2), rng.randrange(1, R))
+        S = [0] * g1k.nslots
+        for x, sl in g1k.cslot.items():
+            S[sl] = x
+        S[st["xP"]], S[st["yP"]] = Pt
+        run_levels(g1k.progs["g1_phi"], S)
+        assert (S[st["B1.x"]] % P, Pt[1]) == g1_aff_mul(Pt, GLV_LAM), "phi"
+        S[st["B1.y"]] = Pt[1]
+        run_levels(g1k.progs["g1_table"], S)
+        for d in range(1, 16):
+            want = g1_aff_add(g1_aff_mul(Pt, d & 3), g1_aff_mul(Pt, (d >> 2) * GLV_LAM % R)) if d & 3 else \
+                g1_aff_mul(Pt, (d >> 2) * GLV_LAM % R)
+            assert getj(S, "TB%d" % d) == want, ("table", d)
+        setj(S, "T", Pt)
+        run_levels(g1k.progs["g1_dbl"], S)
+        assert getj(S, "T") == g1_aff_mul(Pt, 2), "dbl"
+        run_levels(g1k.progs["g1_dbl2"], S)
+        assert getj(S, "T") == g1_aff_mul(Pt, 8), "dbl2"
+        run_levels(g1k.progs["g1_dbl2_add"], S, (0, 0, st["TB7.0"], 0, 0, 0, 0, 0))
+        T32 = g1_aff_add(g1_aff_mul(Pt, 32), getj(S, "TB7"))
+        assert getj(S, "T") == T32, "dbl2_add"
+        A = g1_aff_mul((1, 2), rng.randrange(1, R))
+        Sa = list(S) + [A[0], A[1]]
+        run_levels(g1k.progs["g1_madd"], Sa, (0, 0, len(S), 0, 0, 0, 0, 0))
+        assert getj(Sa, "T") == g1_aff_add(T32, A), "madd"
+        Z = Sa[st["T.2"]] % P
+        Sa[st["tinv"]] = pow(Z, -1, P)
+        run_levels(g1k.progs["g1_aff"], Sa)
+        assert (Sa[st["ax"]] % P, Sa[st["ay"]] % P) == g1_aff_add(T32, A), "aff"
+        # degenerate: 4T + A with A = 4T reports H = 0 and r = 0
+        setj(S, "T", Pt)
+        Tq = g1_aff_mul(Pt, 4)
+        setj(S, "TB1", Tq)
+        run_levels(g1k.progs["g1_dbl2_add"], S, (0, 0, st["TB1.0"], 0, 0, 0, 0, 0))
+        assert S[st["H"]] % P == 0 and S[st["RR"]] % P == 0, "degenerate"
+    print("G1 programs ok", file=sys.stderr)
 
 
 if __name__ == "__main__":

@@ -11,6 +11,8 @@
 #include "slp.hpp"
 #include "gls.hpp"
 #include "g2mul.hpp"
+#include "gtpow.hpp"
+#include "g1mul.hpp"
 
 #define API extern "C" __attribute__((visibility("default")))
 
@@ -339,6 +341,52 @@ API int hc_g2_mul(const uint8_t *Qb, const uint8_t *kb, const uint8_t *Ab, uint8
   return 0;
 }
 
+
+// k P (+ A) on the engine (host model), affine result; k canonical 32 bytes big-endian
+API int hc_g1_mul_engine(const uint8_t *Pb, const uint8_t *kb, const uint8_t *Ab, uint8_t *out) {
+  static slp::f29 S[slp::G1_NSLOT + 2];
+  g1_aff P = rdg1(Pb);
+  S[slp::G1_xP] = slp::to29(P.x);
+  S[slp::G1_yP] = slp::to29(P.y);
+  bool has_a = false;
+  if (Ab) {
+    g1_aff A = rdg1(Ab);
+    S[slp::G1_NSLOT] = slp::to29(A.x);
+    S[slp::G1_NSLOT + 1] = slp::to29(A.y);
+    has_a = !aff_is_inf(A);
+  }
+  ld_consts(S, slp::G1_CBASE, slp::G1_CONSTS, slp::G1_NCONST);
+  fe k = rd_raw(kb);
+  glv::Dec dec = glv::decompose(k.l);
+  slp::HostCtx c{S};
+  bool inf = g1m::mul_add(c, dec, aff_is_inf(P), has_a, slp::G1_NSLOT, S[slp::G1_CBASE + 1]);
+  if (inf) { memset(out, 0, 64); return 0; }
+  S[slp::G1_tinv] = slp::to29(fp_inv_fast(slp::from29(slp::canon29(S[slp::G1_T_2]))));
+  c.run(slp::PROG_G1_AFF, 0, 0, 0);
+  g1_aff r{slp::from29(slp::canon29(S[slp::G1_ax])), slp::from29(slp::canon29(S[slp::G1_ay]))};
+  wrg1(out, r);
+  return 0;
+}
+
+// g^k on the engine (host model) for g in the cyclotomic subgroup, k canonical (32 bytes
+// big-endian) through the 4-dimensional Frobenius split
+API int hc_gt_pow_cyc(const uint8_t *gb, const uint8_t *kb, uint8_t *out) {
+  static slp::f29 S[slp::FE_NSLOT + 12 * gtp::NBUF];
+  fp12 g = rd12(gb);
+  const fe *gw = reinterpret_cast<const fe *>(&g);
+  for (int i = 0; i < 12; i++) S[slp::FE_NSLOT + i] = slp::to29(gw[i]);
+  ld_consts(S, slp::FE_CBASE, slp::FE_CONSTS, slp::FE_NCONST);
+  fe k = rd_raw(kb);
+  gls::Dec dec = gls::decompose(k.l);
+  slp::HostCtx c{S};
+  int r = gtp::pow_cyc(c, dec, slp::FE_NSLOT);
+  fp12 f;
+  fe *fw = reinterpret_cast<fe *>(&f);
+  for (int i = 0; i < 12; i++)
+    fw[i] = r < 0 ? (i == 0 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::FE_NSLOT + 12 * r + i]));
+  wr12(out, f);
+  return 0;
+}
 
 // Montgomery products (MUL operations) in the engine's programs, for the work model:
 // 0 Miller loop (whole sequence), 1 final exponentiation (whole sequence, without the

@@ -82,6 +82,17 @@ __global__ void __launch_bounds__(TPB) k_oa_lr_aff(const g1_jac *S, uint64_t K, 
   (side ? Rg1 : Lg1)[k * lK + (j - 1)] = a;
 }
 
+// (side ? R : L)[k lK] = U[2k + side] + P[4k + 2 side] + P[4k + 2 side + 1] (affine): the next
+// round's G1 parts from the groups of oa_terms.hpp (P holding x X and x^{-1} Y, Jacobian)
+__global__ void __launch_bounds__(TPB) k_oa_g1_combine(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R,
+                                                      uint64_t lK) {
+  uint64_t id = gtid();
+  if (id >= 2 * nb) return;
+  uint64_t k = id / 2, side = id % 2;
+  g1_jac t = jac_madd(jac_add(P[4 * k + 2 * side], P[4 * k + 2 * side + 1]), U[id]);
+  (side ? R : L)[k * lK] = jac_to_aff(t);
+}
+
 // per batch: hash L_j, R_j into x_j, keep x_j and 1/x_j
 __global__ void __launch_bounds__(TPB) k_oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j,
                                                        uint32_t lK, const g1_aff *Lg1, const g1_aff *Rg1, fe *X, fe *Xinv,
@@ -230,6 +241,9 @@ void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t
 void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st) { L1(k_fc_r, nb * b, K, b, nb, sigma, B); }
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st) {
   L1(k_oa_lr_aff, 2 * nb, S, K, nb, j, lK, Lg1, Rg1);
+}
+void oa_g1_combine(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st) {
+  L1(k_oa_g1_combine, 2 * nb, U, P, nb, L, R, lK);
 }
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st) {

@@ -3,6 +3,9 @@
 #include "kcommon.hpp"
 #include "slp.hpp"
 #include "g2mul.hpp"
+#include "gtpow.hpp"
+#include "g1mul.hpp"
+#include "oa_terms.hpp"
 
 #define SLP_T 64
 
@@ -66,6 +69,16 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_
   const g1_aff *P = A + (side ? k * K + i : k * K + h + i);
   const g2_aff *Q = V + (side ? k * K + h + i : k * K + i);
   miller_one(S, P, Q, F + (k * 2 + side) * (K / 2) + i);
+}
+
+// Miller loops of the terms of the next round (oa_terms.hpp) into F[term.out]
+__global__ void __launch_bounds__(SLP_T) ks_oa_pmiller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q,
+                                                      fp12 *F) {
+  __shared__ f29 S[slp::ML_NSLOT];
+  uint64_t id = blockIdx.x;
+  if (id >= nb * 8 * q) return;
+  oat::Term tm = oat::term(id, K, nb, q);
+  miller_one(S, A + tm.a, V + tm.v, F + tm.out);
 }
 
 #define FE_SLOTS (slp::FE_NSLOT + 12 * slp::FE_NBUF)
@@ -150,15 +163,15 @@ __device__ void g2_job(f29 *S, gls::Dec *dec, const g2_aff *Q, const fe *k_mont,
   if (t < 4) o[t] = slp::from29(slp::canon29(S[slp::G2_ax_0 + t]));
 }
 
-// v[i] = v[i] + x^{-1} v[h + i] for every batch k (Eq. folding)
-__global__ void __launch_bounds__(SLP_T) ks_oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
-                                                      uint32_t lK) {
+// Vout[i] = Vin[i] + x^{-1} Vin[h + i] for every batch k (Eq. folding); Vout may be Vin
+__global__ void __launch_bounds__(SLP_T) ks_oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb,
+                                                      uint64_t h, uint32_t j, uint32_t lK) {
   __shared__ f29 S[G2_SLOTS];
   __shared__ gls::Dec dec;
   uint64_t id = blockIdx.x;
   if (id >= nb * h) return;
   uint64_t k = id / h, i = id % h;
-  g2_job(S, &dec, V + k * K + h + i, Xinv + k * lK + (j - 1), V + k * K + i, V + k * K + i, nullptr);
+  g2_job(S, &dec, Vin + k * K + h + i, Xinv + k * lK + (j - 1), Vin + k * K + i, Vout + k * K + i, nullptr);
 }
 
 // terms q_m h_m of the KZG proof of v_l (Jacobian)
@@ -211,6 +224,185 @@ __global__ void __launch_bounds__(SLP_T) ks_gt_pow(const fp12 *in, const fe *k_m
   if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(acc) + t]));
 }
 
+// ---------------------------------------------------------------- G1 scalar multiplications
+#define G1_SLOTS (slp::G1_NSLOT + 2)
+#define G1_ABASE slp::G1_NSLOT
+
+// out = k P + A on the engine (A optional); results written as affine (oaff) or Jacobian (ojac)
+__device__ void g1_job(f29 *S, glv::Dec *dec, const g1_aff *P, const fe *k_mont, const g1_aff *A, g1_aff *oaff,
+                       g1_jac *ojac) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    fe kc = f_from_mont<FpR>(*k_mont);
+    *dec = glv::decompose(kc.l);
+  }
+  if (t < 2) S[slp::G1_xP + t] = slp::to29(t ? P->y : P->x);
+  if (A && t >= 2 && t < 4) S[G1_ABASE + t - 2] = slp::to29(t == 3 ? A->y : A->x);
+  load_consts<slp::G1_NCONST>(S, slp::G1_CBASE, slp::G1_CONSTS);
+  __syncthreads();
+  bool pinf = g1_inf(*P), has_a = A && !g1_inf(*A);
+  slp::DevCtx c{S};
+  bool inf = g1m::mul_add(c, *dec, pinf, has_a, G1_ABASE, S[slp::G1_CBASE + 1]);
+  if (ojac) {
+    fe *o = reinterpret_cast<fe *>(ojac);
+    if (t < 3) o[t] = inf ? (t < 2 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::G1_T_0 + t]));
+    return;
+  }
+  fe *o = reinterpret_cast<fe *>(oaff);
+  if (inf) {
+    if (t < 2) o[t] = fe_zero();
+    return;
+  }
+  {
+    fe zi = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G1_T_2])), bn::P_R3);
+    if (t == 0) S[slp::G1_tinv] = slp::to29(zi);
+  }
+  __syncthreads();
+  c.run(slp::PROG_G1_AFF, 0, 0, 0);
+  if (t < 2) o[t] = slp::from29(slp::canon29(S[t ? slp::G1_ay : slp::G1_ax]));
+}
+
+// ---------------------------------------------------------------- Step 1 rounds, fused
+template <int A_, int B_> struct imax { static constexpr int v = A_ > B_ ? A_ : B_; };
+
+// The fold of round j (Eq. folding) for every batch: blocks [0, nb h) fold G1 and b,
+// blocks [nb h, 2 nb h) fold G2.  Aout[i] = Ain[i] + x Ain[h + i], Bout[i] = Bin[i] +
+// x^{-1} Bin[h + i], Vout[i] = Vin[i] + x^{-1} Vin[h + i].
+__global__ void __launch_bounds__(SLP_T) ks_oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin,
+                                                   g2_aff *Vout, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb,
+                                                   uint64_t h, uint32_t j, uint32_t lK) {
+  __shared__ f29 S[imax<G1_SLOTS, G2_SLOTS>::v];
+  __shared__ glv::Dec d1;
+  __shared__ gls::Dec d2;
+  uint64_t id = blockIdx.x;
+  if (id >= 2 * nb * h) return;
+  bool g2 = id >= nb * h;
+  if (g2) id -= nb * h;
+  uint64_t k = id / h, i = id % h, slot = k * lK + (j - 1);
+  if (g2) {
+    g2_job(S, &d2, Vin + k * K + h + i, Xinv + slot, Vin + k * K + i, Vout + k * K + i, nullptr);
+    return;
+  }
+  if (threadIdx.x == 32) Bout[k * K + i] = fr_add(Bin[k * K + i], fr_mul(Bin[k * K + h + i], Xinv[slot]));
+  g1_job(S, &d1, Ain + k * K + h + i, X + slot, Ain + k * K + i, Aout + k * K + i, nullptr);
+}
+
+// The next round's terms (oa_terms.hpp): blocks [0, nb 8q) run the Miller loops into
+// F[out], blocks [nb 8q, 2 nb 8q) the G1 terms b[v] A[a] into S1[out] (Jacobian).
+__global__ void __launch_bounds__(SLP_T) ks_oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64_t nb,
+                                                     uint64_t q, fp12 *F, g1_jac *S1) {
+  __shared__ f29 S[imax<slp::ML_NSLOT, G1_SLOTS>::v];
+  __shared__ glv::Dec d1;
+  uint64_t id = blockIdx.x, n = nb * 8 * q;
+  if (id >= 2 * n) return;
+  if (id < n) {
+    oat::Term tm = oat::term(id, K, nb, q);
+    miller_one(S, A + tm.a, V + tm.v, F + tm.out);
+    return;
+  }
+  oat::Term tm = oat::term(id - n, K, nb, q);
+  g1_job(S, &d1, A + tm.a, B + tm.v, nullptr, nullptr, S1 + tm.out);
+}
+
+// ---------------------------------------------------------------- cyclotomic G_T powers
+#define GTP_SLOTS (slp::FE_NSLOT + 12 * gtp::NBUF)
+
+// out[s] = in[s]^k for in[s] in the cyclotomic subgroup, k = (s odd ? k_odd : k_even)[(s >> 2)
+// kstride] (Montgomery F_r form), through the 4-dimensional Frobenius split (gtpow.hpp)
+__global__ void __launch_bounds__(SLP_T) ks_gt_pow_cyc(const fp12 *in, const fe *k_even, const fe *k_odd, uint64_t kstride,
+                                                      uint64_t n, fp12 *out) {
+  __shared__ f29 S[GTP_SLOTS];
+  __shared__ gls::Dec dec;
+  uint64_t s = blockIdx.x;
+  if (s >= n) return;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    fe kc = f_from_mont<FpR>((s & 1 ? k_odd : k_even)[(s >> 2) * kstride]);
+    dec = gls::decompose(kc.l);
+  }
+  const fe *src = reinterpret_cast<const fe *>(in + s);
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  slp::DevCtx c{S};
+  int r = gtp::pow_cyc(c, dec, slp::FE_NSLOT);
+  fe *dst = reinterpret_cast<fe *>(out + s);
+  if (t < 12) dst[t] = r < 0 ? (t == 0 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[FE_BUF(r) + t]));
+}
+
+// The x-dependent part of a round taken ahead: blocks [0, 4 nb) raise PX[s] (cyclotomic)
+// to k_s, blocks [4 nb, 8 nb) multiply PX1[s] (G1) by k_s, with k_s = (s odd ? k_odd :
+// k_even)[(s >> 2) kstride]; outputs PE[s] and PM[s] (Jacobian).
+__global__ void __launch_bounds__(SLP_T) ks_oa_combine_pow(const fp12 *PX, const g1_aff *PX1, const fe *k_even,
+                                                          const fe *k_odd, uint64_t kstride, uint64_t nb, fp12 *PE,
+                                                          g1_jac *PM) {
+  __shared__ f29 S[imax<GTP_SLOTS, G1_SLOTS>::v];
+  __shared__ gls::Dec dec;
+  __shared__ glv::Dec d1;
+  uint64_t id = blockIdx.x;
+  if (id >= 8 * nb) return;
+  const int t = threadIdx.x;
+  if (id >= 4 * nb) {
+    uint64_t s = id - 4 * nb;
+    g1_job(S, &d1, PX1 + s, (s & 1 ? k_odd : k_even) + (s >> 2) * kstride, nullptr, nullptr, PM + s);
+    return;
+  }
+  uint64_t s = id;
+  if (t == 0) {
+    fe kc = f_from_mont<FpR>((s & 1 ? k_odd : k_even)[(s >> 2) * kstride]);
+    dec = gls::decompose(kc.l);
+  }
+  const fe *src = reinterpret_cast<const fe *>(PX + s);
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  slp::DevCtx c{S};
+  int r = gtp::pow_cyc(c, dec, slp::FE_NSLOT);
+  fe *dst = reinterpret_cast<fe *>(PE + s);
+  if (t < 12) dst[t] = r < 0 ? (t == 0 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[FE_BUF(r) + t]));
+}
+
+// final exponentiations of two strided lists: job s < n0 takes in0[s st0] to out0[s], the
+// others in1[(s - n0) st1] to out1[s - n0]
+__global__ void __launch_bounds__(SLP_T) ks_final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1,
+                                                      uint64_t st1, uint64_t n1, fp12 *out1) {
+  __shared__ f29 S[FE_SLOTS];
+  uint64_t s = blockIdx.x;
+  if (s >= n0 + n1) return;
+  int t = threadIdx.x;
+  const fe *src = reinterpret_cast<const fe *>(s < n0 ? in0 + s * st0 : in1 + (s - n0) * st1);
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  slp::run_seq<4>(S, slp::FE_SEQ, slp::FE_SEQ_LEN, slp::FE_NSLOT, slp::FE_t, slp::FE_tinv);
+  fe *dst = reinterpret_cast<fe *>(s < n0 ? out0 + s : out1 + (s - n0));
+  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(slp::FE_RESULT) + t]));
+}
+
+// (side ? R : L)[k lK] = U[2k + side] P[4k + 2 side] P[4k + 2 side + 1]: the next round's
+// G_T parts from the groups of oa_terms.hpp (P holding X^x and Y^{1/x})
+__global__ void __launch_bounds__(SLP_T) ks_oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R,
+                                                         uint64_t lK) {
+  __shared__ f29 S[slp::FE_NSLOT + 48];
+  uint64_t id = blockIdx.x;
+  if (id >= 2 * nb) return;
+  uint64_t k = id / 2, side = id % 2;
+  const int t = threadIdx.x;
+  const fe *u = reinterpret_cast<const fe *>(U + id), *p0 = reinterpret_cast<const fe *>(P + 4 * k + 2 * side),
+           *p1 = reinterpret_cast<const fe *>(P + 4 * k + 2 * side + 1);
+  if (t < 12) {
+    S[FE_BUF(0) + t] = slp::to29(u[t]);
+    S[FE_BUF(1) + t] = slp::to29(p0[t]);
+    S[FE_BUF(2) + t] = slp::to29(p1[t]);
+  }
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  slp::run1(S, slp::PROG_F12_MUL, FE_BUF(0), FE_BUF(1), FE_BUF(3));
+  slp::run1(S, slp::PROG_F12_MUL, FE_BUF(3), FE_BUF(2), FE_BUF(0));
+  fe *dst = reinterpret_cast<fe *>((side ? R : L) + k * lK);
+  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(0) + t]));
+}
+
 namespace ks {
 void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st) {
   if (n) LAUNCH(ks_miller, dim3((unsigned)n), dim3(SLP_T), 0, P, sp, Q, sq, n, out);
@@ -227,8 +419,34 @@ void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStr
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st) {
   if (n) LAUNCH(ks_final_exp, dim3((unsigned)n), dim3(SLP_T), 0, in, stride, n, out0, out1, ostride);
 }
-void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
-  LAUNCH(ks_oa_fold_g2, dim3((unsigned)(nb * h)), dim3(SLP_T), 0, V, Xinv, K, nb, h, j, lK);
+void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
+                hipStream_t st) {
+  LAUNCH(ks_oa_fold_g2, dim3((unsigned)(nb * h)), dim3(SLP_T), 0, Vin, Vout, Xinv, K, nb, h, j, lK);
+}
+void oa_pmiller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, hipStream_t st) {
+  LAUNCH(ks_oa_pmiller, dim3((unsigned)(nb * 8 * q)), dim3(SLP_T), 0, A, V, K, nb, q, F);
+}
+void gt_pow_cyc(const fp12 *in, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t n, fp12 *out, hipStream_t st) {
+  if (n) LAUNCH(ks_gt_pow_cyc, dim3((unsigned)n), dim3(SLP_T), 0, in, k_even, k_odd, kstride, n, out);
+}
+void oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st) {
+  LAUNCH(ks_oa_gt_combine, dim3((unsigned)(2 * nb)), dim3(SLP_T), 0, U, P, nb, L, R, lK);
+}
+void oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
+             const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
+  LAUNCH(ks_oa_fold, dim3((unsigned)(2 * nb * h)), dim3(SLP_T), 0, Ain, Bin, Aout, Bout, Vin, Vout, X, Xinv, K, nb, h, j, lK);
+}
+void oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, g1_jac *S1,
+               hipStream_t st) {
+  LAUNCH(ks_oa_pterms, dim3((unsigned)(2 * nb * 8 * q)), dim3(SLP_T), 0, A, V, B, K, nb, q, F, S1);
+}
+void oa_combine_pow(const fp12 *PX, const g1_aff *PX1, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t nb,
+                    fp12 *PE, g1_jac *PM, hipStream_t st) {
+  LAUNCH(ks_oa_combine_pow, dim3((unsigned)(8 * nb)), dim3(SLP_T), 0, PX, PX1, k_even, k_odd, kstride, nb, PE, PM);
+}
+void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1, uint64_t st1, uint64_t n1, fp12 *out1,
+                hipStream_t st) {
+  if (n0 + n1) LAUNCH(ks_final_exp2, dim3((unsigned)(n0 + n1)), dim3(SLP_T), 0, in0, st0, n0, out0, in1, st1, n1, out1);
 }
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st) {
   LAUNCH(ks_kzg_terms, dim3((unsigned)(nb * (2 * K - 2))), dim3(SLP_T), 0, h, Qc, K, nb, S2);

@@ -12,6 +12,7 @@
 #include "curve.hpp"
 #include "pairing.hpp"
 #include "kernels.h"
+#include "oa_terms.hpp"
 
 #define TPBW 64
 #define GPB (TPBW / 8)  // groups (elements) per block
@@ -109,17 +110,47 @@ __global__ void __launch_bounds__(TPBW) kw_oa_g1terms(const void *A, const void 
   wst(S, (k * 2 + side) * (K / 2) + i, out);
 }
 
-// A_j = A_L o A_R^{x_j}, b_j = b_L + b_R / x_j; x_j enters through its GLV split (per batch)
-__global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(void *A, void *B, const void *Xinv, const glv::Dec *dec, uint64_t K,
-                                                     uint64_t nb, uint64_t h, uint32_t j, uint32_t lK) {
+// A_j = A_L o A_R^{x_j}, b_j = b_L + b_R / x_j; x_j enters through its GLV split (per batch);
+// the folded arrays go to Aout, Bout (which may be Ain, Bin)
+__global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv,
+                                                     const glv::Dec *dec, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+                                                     uint32_t lK) {
   uint64_t id = wgid();
   if (id >= nb * h) return;
   uint64_t k = id / h, i = id % h, slot = k * lK + (j - 1);
   glv::Dec d = dec[k];
-  g1_jac t = g1_mul_glv(wld<g1_aff>(A, k * K + h + i), d);
-  wst(A, k * K + i, jac_to_aff(jac_madd(t, wld<g1_aff>(A, k * K + i))));
-  fe bl = wld<fe>(B, k * K + i), br = wld<fe>(B, k * K + h + i);
-  wst(B, k * K + i, fr_add(bl, fr_mul(br, wld<fe>(Xinv, slot))));
+  g1_jac t = g1_mul_glv(wld<g1_aff>(Ain, k * K + h + i), d);
+  g1_aff a = jac_to_aff(jac_madd(t, wld<g1_aff>(Ain, k * K + i)));
+  fe bl = wld<fe>(Bin, k * K + i), br = wld<fe>(Bin, k * K + h + i);
+  fe b = fr_add(bl, fr_mul(br, wld<fe>(Xinv, slot)));
+  wst(Aout, k * K + i, a);
+  wst(Bout, k * K + i, b);
+}
+
+// G1 terms b[v] A[a] of the next round (oa_terms.hpp) into S[term.out], Jacobian
+__global__ void __launch_bounds__(TPBW) kw_oa_pg1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t q,
+                                                      void *S) {
+  uint64_t id = wgid();
+  if (id >= nb * 8 * q) return;
+  oat::Term tm = oat::term(id, K, nb, q);
+  fe c = wld<fe>(B, tm.v);
+  g1_jac out = jac_inf<OpsG1>();
+  if (!fe_is_zero(c)) {
+    uint32_t kk[8];
+    wscalar(kk, c);
+    out = mul_any(wld<g1_aff>(A, tm.a), kk);
+  }
+  wst(S, tm.out, out);
+}
+
+// out[s] = k P[s] (Jacobian), k = (s odd ? k_odd : k_even)[(s >> 2) kstride] (Montgomery F_r)
+__global__ void __launch_bounds__(TPBW) kw_oa_cmul(const void *P, const void *k_even, const void *k_odd, uint64_t kstride,
+                                                  uint64_t n, void *out) {
+  uint64_t s = wgid();
+  if (s >= n) return;
+  uint32_t kk[8];
+  wscalar(kk, wld<fe>(s & 1 ? k_odd : k_even, (s >> 2) * kstride));
+  wst(out, s, mul_any(wld<g1_aff>(P, s), kk));
 }
 
 // v_j = v_L o v_R^{1/x_j}
@@ -265,9 +296,15 @@ void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStre
 void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st) {
   LW(kw_oa_g1terms, nb * 2 * h, A, B, K, nb, h, S);
 }
-void oa_fold_g1(void *A, void *B, const void *Xinv, const void *dec, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
-                uint32_t lK, hipStream_t st) {
-  LW(kw_oa_fold_g1, nb * h, A, B, Xinv, static_cast<const glv::Dec *>(dec), K, nb, h, j, lK);
+void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv, const void *dec, uint64_t K,
+                uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
+  LW(kw_oa_fold_g1, nb * h, Ain, Bin, Aout, Bout, Xinv, static_cast<const glv::Dec *>(dec), K, nb, h, j, lK);
+}
+void oa_pg1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t q, void *S, hipStream_t st) {
+  LW(kw_oa_pg1terms, nb * 8 * q, A, B, K, nb, q, S);
+}
+void oa_cmul(const void *P, const void *k_even, const void *k_odd, uint64_t kstride, uint64_t n, void *out, hipStream_t st) {
+  if (n) LW(kw_oa_cmul, n, P, k_even, k_odd, kstride, n, out);
 }
 void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
   LW(kw_oa_fold_g2, nb * h, V, Xinv, K, nb, h, j, lK);

@@ -36,6 +36,8 @@ void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t 
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st);
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
+// L[k lK], R[k lK] = U[2k + side] + P[4k + 2 side] + P[4k + 2 side + 1] (affine)
+void oa_g1_combine(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st);
 void oa_fold_g1(g1_aff *A, fe *B, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st);
 void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
@@ -62,8 +64,12 @@ void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h
 void g1_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
 void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
 void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st);
-void oa_fold_g1(void *A, void *B, const void *Xinv, const void *dec, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
-                uint32_t lK, hipStream_t st);
+void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv, const void *dec, uint64_t K,
+                uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
+// next-round G1 terms (oa_terms.hpp), Jacobian; out[s] = k P[s] with k from k_even (s even)
+// or k_odd (s odd) at (s >> 2) kstride, Jacobian
+void oa_pg1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t q, void *S, hipStream_t st);
+void oa_cmul(const void *P, const void *k_even, const void *k_odd, uint64_t kstride, uint64_t n, void *out, hipStream_t st);
 void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S, hipStream_t st);
 void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st);
@@ -82,7 +88,23 @@ void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t
 void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st);
 void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
-void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
+void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
+                hipStream_t st);
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
 void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st);
+// next-round terms (oa_terms.hpp): Miller loops; cyclotomic powers in[s]^{k}, k from k_even
+// (s even) or k_odd (s odd) at (s >> 2) kstride; L[k lK], R[k lK] = U[2k + side] P[4k + 2 side] P[4k + 2 side + 1]
+void oa_pmiller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, hipStream_t st);
+void gt_pow_cyc(const fp12 *in, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t n, fp12 *out, hipStream_t st);
+void oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st);
+// fused round kernels: G1 + G2 fold; Miller loops + G1 terms of the next round; G_T powers
+// + G1 multiples by x, x^{-1}; final exponentiations of two strided lists
+void oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
+             const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
+void oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, g1_jac *S1,
+               hipStream_t st);
+void oa_combine_pow(const fp12 *PX, const g1_aff *PX1, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t nb,
+                    fp12 *PE, g1_jac *PM, hipStream_t st);
+void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1, uint64_t st1, uint64_t n1, fp12 *out1,
+                hipStream_t st);
 }  // namespace ks

@@ -59,8 +59,20 @@ struct ProfRec {
   hipEvent_t e0, e1;
 };
 bool g_prof = false;
+std::string g_prof_only;          // empty: every kernel
 std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;  // timing events, reused across profiling runs
+size_t g_prof_next = 0;
 hipEvent_t g_prof_open = nullptr;
+
+hipEvent_t prof_event() {
+  if (g_prof_next == g_prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof_pool.push_back(e);
+  }
+  return g_prof_pool[g_prof_next++];
+}
 }  // namespace
 
 namespace dbg {
@@ -83,15 +95,16 @@ void check(const char *name, hipStream_t st) {
 }  // namespace dbg
 
 namespace prof {
-void begin(const char *, hipStream_t st) {
-  if (!g_prof) return;
-  if (hipEventCreate(&g_prof_open) != hipSuccess) { g_prof_open = nullptr; return; }
-  (void)hipEventRecord(g_prof_open, st);
+void begin(const char *name, hipStream_t st) {
+  g_prof_open = nullptr;
+  if (!g_prof || (!g_prof_only.empty() && g_prof_only != name)) return;
+  g_prof_open = prof_event();
+  if (g_prof_open) (void)hipEventRecord(g_prof_open, st);
 }
 void end(hipStream_t st) {
   if (!g_prof || !g_prof_open) return;
-  hipEvent_t e1;
-  if (hipEventCreate(&e1) != hipSuccess) return;
+  hipEvent_t e1 = prof_event();
+  if (!e1) { g_prof_open = nullptr; return; }
   (void)hipEventRecord(e1, st);
   g_prof_recs.push_back({nullptr, g_prof_open, e1});
   g_prof_open = nullptr;
@@ -111,13 +124,27 @@ struct vc_params {
   void *ws = nullptr;       // grow-only scratch shared by calls on these params
   size_t ws_size = 0;
   // side streams (default priority) and fork/join events for independent phases
-  hipStream_t side[2] = {nullptr, nullptr};
-  hipEvent_t ev[8] = {};
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[16] = {};
 };
+
+// Step 1 takes the next round's terms ahead (oa_terms.hpp) when the batches leave the
+// device mostly idle: at most this many (batch, index) pairs per round.  Beyond it the
+// doubled Miller-loop count of that scheme costs more than the shorter chain saves.
+static constexpr uint64_t AHEAD_MAX_PAIRS = 4096;
 
 // fork: `to` waits for the work issued so far on `from`
 static int stream_wait(vc_params *pp, int slot, hipStream_t from, hipStream_t to) {
   CK(hipEventRecord(pp->ev[slot], from));
+  CK(hipStreamWaitEvent(to, pp->ev[slot], 0));
+  return VC_OK;
+}
+// the same split in two: mark the work issued so far on a stream, wait for the mark later
+static int ev_mark(vc_params *pp, int slot, hipStream_t from) {
+  CK(hipEventRecord(pp->ev[slot], from));
+  return VC_OK;
+}
+static int ev_wait(vc_params *pp, int slot, hipStream_t to) {
   CK(hipStreamWaitEvent(to, pp->ev[slot], 0));
   return VC_OK;
 }
@@ -362,6 +389,14 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   size_t o_F = t.take<fp12>(nb * K), o_S = t.take<g1_jac>(nb * K), o_Hq = t.take<uint32_t>(nb * qmax * 8);
   size_t o_sig = t.take<uint32_t>(nb * 8), o_Xi = t.take<fe>(nb * lK), o_Q = t.take<fe>(nb * nq), o_z = t.take<fe>(nb);
   size_t o_S2 = t.take<g2_jac>(nb * nq), o_HS = t.take<g1_jac>(lM * (M / 2)), o_dec = t.take<glv::Dec>(nb);
+  // Step 1 arrays of alternate rounds, and the terms taken one round ahead (oa_terms.hpp)
+  const bool ahead = lK >= 2 && nb * K <= AHEAD_MAX_PAIRS;
+  const uint64_t nterm = ahead ? 2 * nb * K : 0;
+  size_t o_A2 = t.take<g1_aff>(nb * K), o_V2 = t.take<g2_aff>(nb * K), o_B2 = t.take<fe>(nb * K);
+  size_t o_F2 = t.take<fp12>(nterm), o_PS = t.take<g1_jac>(nterm);
+  size_t o_PU = t.take<fp12>(ahead ? 4 * nb : 0), o_PX = t.take<fp12>(ahead ? 8 * nb : 0), o_PE = t.take<fp12>(ahead ? 4 * nb : 0);
+  size_t o_PU1 = t.take<g1_aff>(ahead ? 4 * nb : 0), o_PX1 = t.take<g1_aff>(ahead ? 8 * nb : 0);
+  size_t o_PM = t.take<g1_jac>(ahead ? 4 * nb : 0);
   int rc = ensure_ws(pp, t.off);
   if (rc) { vc_proofs_free(pr); return rc; }
   void *ws = pp->ws;
@@ -376,6 +411,17 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   g2_jac *S2 = at<g2_jac>(ws, o_S2);
   g1_jac *HS = at<g1_jac>(ws, o_HS);
   glv::Dec *gdec = at<glv::Dec>(ws, o_dec);
+  g1_aff *Ab[2] = {A, at<g1_aff>(ws, o_A2)};
+  g2_aff *Vb[2] = {V, at<g2_aff>(ws, o_V2)};
+  fe *Bb[2] = {B, at<fe>(ws, o_B2)};
+  fp12 *F2 = at<fp12>(ws, o_F2);
+  g1_jac *PS = at<g1_jac>(ws, o_PS);
+  fp12 *PU[2] = {at<fp12>(ws, o_PU), at<fp12>(ws, o_PU) + 2 * nb};
+  fp12 *PX[2] = {at<fp12>(ws, o_PX), at<fp12>(ws, o_PX) + 4 * nb};
+  fp12 *PE = at<fp12>(ws, o_PE);
+  g1_aff *PU1[2] = {at<g1_aff>(ws, o_PU1), at<g1_aff>(ws, o_PU1) + 2 * nb};
+  g1_aff *PX1[2] = {at<g1_aff>(ws, o_PX1), at<g1_aff>(ws, o_PX1) + 4 * nb};
+  g1_jac *PM = at<g1_jac>(ws, o_PM);
 
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
@@ -407,30 +453,82 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   }
 
   // ---- Step 1: FC.BOpen for every block, all blocks in lockstep (Protocol 1, Eq. genFCBatchProof).
-  // Per round the pairing chain (Miller loops, product tree, final exponentiation) runs on the
-  // caller's stream while the G1 parts of L_j, R_j run on side stream 2; after the transcript
-  // the G1 fold runs on side stream 2 beside the G2 fold.
+  // Round j works on the arrays A, V, b of buffer (j - 1) & 1; its fold writes buffer j & 1.
+  // Round 1 (and every round when the batches alone fill the device) computes L_j, R_j
+  // directly: Miller loops, product tree and final exponentiation on the caller's stream,
+  // the G1 parts on side stream 2, the folds on side streams 2 (G1) and 3 (G2).
+  // Otherwise (ahead) the terms of round j + 1 are computed from the arrays of round j - 1
+  // while x_{j-1} and x_j are derived (oa_terms.hpp), and round j + 1 only raises them to
+  // x_j, x_j^{-1} and multiplies: the Miller loops and final exponentiations leave the
+  // chain of dependent rounds.  Then side stream 2 runs the fused folds and side stream 3
+  // the terms; each launch pairs the G1 and the pairing-side work of its step.
+  hipStream_t sg = s2, sf = pp->side[2];
   kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
   kl::fc_chunks(Cj, K, b, nb, Hq, st);
   kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
   kl::fc_r(K, b, nb, sigma, B, st);
+  if (int rc2 = stream_wait(pp, 1, st, sg)) return rc2;
+  if (int rc2 = stream_wait(pp, 2, st, sf)) return rc2;
+  // terms of round jn >= 2 from the arrays of round jn - 1, on side stream 3
+  auto launch_terms = [&](uint32_t jn) -> int {
+    uint64_t q = K >> jn;
+    int par = jn & 1, src = (jn - 2) & 1;
+    ks::oa_pterms(Ab[src], Vb[src], Bb[src], K, nb, q, F2, PS, sf);
+    kl::g1_reduce(PS, 2 * nb, 2 * q, 2 * q, sf);
+    kl::g1_reduce(PS + nb * 4 * q, 4 * nb, q, q, sf);
+    kl::g1_to_aff(PS, 2 * q, 2 * nb, PU1[par], 1, sf);
+    kl::g1_to_aff(PS + nb * 4 * q, q, 4 * nb, PX1[par], 1, sf);
+    ks::f12_reduce(F2, 2 * nb, 2 * q, 2 * q, sf);
+    ks::f12_reduce(F2 + nb * 4 * q, 4 * nb, q, q, sf);
+    ks::final_exp2(F2, 2 * q, 2 * nb, PU[par], F2 + nb * 4 * q, q, 4 * nb, PX[par], sf);
+    return ev_mark(pp, 6 + par, sf);
+  };
   for (uint32_t j = 1; j <= lK; j++) {
-    uint64_t h = K >> j;
-    if (int rc2 = stream_wait(pp, 1, st, s2)) return rc2;
-    klw::oa_g1terms(A, B, K, nb, h, S, s2);
-    klw::g1_reduce(S, 2 * nb, K / 2, h, s2);
-    kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, s2);
-    ks::oa_miller(A, V, K, nb, h, F, st);
-    ks::f12_reduce(F, 2 * nb, K / 2, h, st);
-    ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
-    if (int rc2 = stream_wait(pp, 2, s2, st)) return rc2;
+    const uint64_t h = K >> j;
+    const int cur = (j - 1) & 1, nxt = j & 1;
+    if (j == 1 || !ahead) {
+      klw::oa_g1terms(Ab[cur], Bb[cur], K, nb, h, S, sg);
+      klw::g1_reduce(S, 2 * nb, K / 2, h, sg);
+      kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
+      if (int rc2 = ev_mark(pp, 3, sg)) return rc2;
+      if (ahead)
+        if (int rc2 = launch_terms(2)) return rc2;
+      ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
+      ks::f12_reduce(F, 2 * nb, K / 2, h, st);
+      ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
+      if (int rc2 = ev_wait(pp, 3, st)) return rc2;
+    } else {
+      // L_j, R_j from the terms taken from the arrays of round j - 1 and x_{j-1}
+      const int par = j & 1;
+      if (int rc2 = ev_wait(pp, 6 + par, st)) return rc2;
+      ks::oa_combine_pow(PX[par], PX1[par], X + (j - 2), Xinv + (j - 2), lK, nb, PE, PM, st);
+      ks::oa_gt_combine(PU[par], PE, nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
+      kl::oa_g1_combine(PU1[par], PM, nb, Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
+    }
     kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
-    if (int rc2 = stream_wait(pp, 3, st, s2)) return rc2;
-    kl::glv_dec(X, nb, j, lK, gdec, s2);
-    klw::oa_fold_g1(A, B, Xinv, gdec, K, nb, h, j, lK, s2);
-    ks::oa_fold_g2(V, Xinv, K, nb, h, j, lK, st);
-    if (int rc2 = stream_wait(pp, 4, s2, st)) return rc2;
+    // fold with x_j into the other buffer
+    if (ahead) {
+      if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
+      ks::oa_fold(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, K, nb, h, j, lK, sg);
+      // terms of round j + 2 from the arrays of round j + 1 (just folded)
+      if (j + 2 <= lK) {
+        if (int rc2 = stream_wait(pp, 10, sg, sf)) return rc2;
+        if (int rc2 = launch_terms(j + 2)) return rc2;
+      }
+    } else {
+      if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
+      kl::glv_dec(X, nb, j, lK, gdec, sg);
+      klw::oa_fold_g1(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Xinv, gdec, K, nb, h, j, lK, sg);
+      if (int rc2 = stream_wait(pp, 5, st, sf)) return rc2;
+      ks::oa_fold_g2(Vb[cur], Vb[nxt], Xinv, K, nb, h, j, lK, sf);
+      if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
+      if (int rc2 = stream_wait(pp, 12, sf, st)) return rc2;
+    }
   }
+  if (ahead)
+    if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
+  A = Ab[lK & 1];
+  V = Vb[lK & 1];
   CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
   CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
   // faster verifier: KZG-style proof in G2 that v_l = f_v(beta) g2
@@ -439,7 +537,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   klw::g2_reduce(S2, nb, nq, nq, st);
   klw::g2_to_aff(S2, nq, nb, piv, 1, st);
   // join Step 2
-  if (int rc2 = stream_wait(pp, 5, s1, st)) return rc2;
+  if (int rc2 = stream_wait(pp, 13, s1, st)) return rc2;
   CKL("vc_open_all launch");
   int herr = 0;
   CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -728,10 +826,13 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
 
 // ------------------------------------------------------------------ profiling C ABI
 VC_API void vc_profile_enable(int on) {
-  for (auto &r : g_prof_recs) { hipEventDestroy(r.e0); hipEventDestroy(r.e1); }
+  if (!g_prof_recs.empty()) (void)hipDeviceSynchronize();  // recorded events may still be pending
   g_prof_recs.clear();
+  g_prof_next = 0;
   g_prof = on != 0;
 }
+
+VC_API void vc_profile_only(const char *kernel) { g_prof_only = kernel ? kernel : ""; }
 
 // one line per kernel: "<name> <launches> <total_ms>\n"; returns bytes needed
 VC_API int vc_profile_read(char *buf, size_t cap) {

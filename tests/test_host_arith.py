@@ -299,3 +299,45 @@ def test_bingcd_inverse(hc, which, mod):
         assert int.from_bytes(o.raw, "big") == pow(x, -1, mod), x
         worst = max(worst, rounds.value)
     assert worst <= -(-(2 * mod.bit_length() - 1) // 30), worst
+
+
+def test_gt_pow_cyc(hc):
+    """g^k on the engine through k = sum_j k_j lam^j and the Frobenius powers of g equals
+    the oracle's g^k for pairing values g (of order r), including k = 0, 1, r - 1."""
+    g1, g2 = O.generators()
+    rng = random.Random(23)
+    for trial in range(4):
+        Pt = O.g1_op("mul", g1, O.be32(rng.randrange(1, R)))
+        Qt = O.g2_op("mul", g2, O.be32(rng.randrange(1, R)))
+        g = O.pairing([Pt], [Qt])
+        ks = [0, 1, R - 1, 2] if trial == 0 else [rng.randrange(R) for _ in range(5)]
+        for k in ks:
+            o = buf(384)
+            assert hc.hc_gt_pow_cyc(g, k.to_bytes(32, "big"), o) == 0
+            assert o.raw == O.fp12_op("pow", g, O.be32(k)), k
+
+
+def test_g1_scalar_mul_engine(hc):
+    """k P + A through the engine's host model (GLV split, signed table, exact handling of
+    equal and opposite points, also inside the window loop) against the oracle's group law."""
+    g1, g2 = O.generators()
+    rng = random.Random(25)
+    ident = bytes(64)
+    cases = []
+    for _ in range(6):
+        Pt = O.g1_op("mul", g1, O.be32(rng.randrange(1, R)))
+        A = O.g1_op("mul", g1, O.be32(rng.randrange(1, R)))
+        cases.append((Pt, rng.randrange(R), A))
+        cases.append((Pt, rng.randrange(R), None))
+    Pt = O.g1_op("mul", g1, O.be32(777))
+    k = rng.randrange(1, R)
+    kP = O.g1_op("mul", Pt, O.be32(k))
+    cases += [(Pt, 0, None), (Pt, 1, None), (Pt, 2, None), (Pt, R - 1, None), (ident, 5, None), (Pt, k, ident),
+              (Pt, k, kP), (Pt, k, O.g1_op("neg", kP)), (Pt, 0, kP), (Pt, 5, None), (Pt, 16, None)]
+    for Pb, k, Ab in cases:
+        o = buf(64)
+        assert hc.hc_g1_mul_engine(Pb, k.to_bytes(32, "big"), Ab, o) == 0
+        want = O.g1_op("mul", Pb, O.be32(k)) if Pb != ident else ident
+        if Ab is not None:
+            want = O.g1_op("add", want, Ab)
+        assert o.raw == want, (k,)
