@@ -31,6 +31,7 @@ METRIC = "all-N-proofs time (ms) at N=2^16,b=log²N and N=2^20; MSM points/s"
 PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12   # v_mad_u64_u32 issues at half rate: 19.66 T multiply-adds/s
 PEAK_HBM_GBS = 8000.0
 MADS_PER_FMUL = 136                        # 8x32-bit CIOS: 64 + 64 products + 8 reduction words
+AHEAD_MAX_PAIRS = 4096                     # the library's switch to next-round terms (batches x K)
 
 
 def op_costs():
@@ -42,12 +43,19 @@ def op_costs():
     names = ["miller", "final_exp", "g1_mul", "g2_mul", "g1_add", "g1_madd", "g2_add", "g2_madd",
              "g1_dbl", "g2_dbl", "f12_mul", "g1_to_aff", "g2_to_aff"]
     c = {n: int(L.hc_count(i)) for i, n in enumerate(names)}
-    e = [int(L.hc_engine_muls(i)) for i in range(9)]
+    e = [int(L.hc_engine_muls(i)) for i in range(16)]
     c["e_miller"], c["e_final_exp"], c["e_f12_mul"] = e[0], e[1], e[8]
     # GLS scalar multiplication on G2: psi images, table, then per bit of the 65-bit
     # split scalars one doubling and (with probability 15/16) one table addition
     c["e_g2_mul"] = e[2] + e[3] + 64 * e[4] + 60 * e[5]
     c["e_g2_madd"], c["e_g2_to_aff"] = e[6], e[7]
+    # GLV scalar multiplication on G1 (128-bit split scalars in 2-bit joint windows): table,
+    # then per window two doublings and (with probability 15/16) an addition
+    c["e_g1_mul"] = e[9] + 60 * e[10] + 4 * e[11]
+    c["e_g1_madd"], c["e_g1_to_aff"] = e[12], e[13]
+    # G_T power through the 4-dimensional split (65-bit): Frobenius images, 11 table
+    # products, then per bit one cyclotomic squaring and (15/16) one product
+    c["e_gt_pow"] = e[15] + 11 * e[8] + 64 * e[14] + 60 * e[8]
     return c
 
 
@@ -61,18 +69,38 @@ def work_model(L, b, limbs, costs):
     nz_digits = int(np.count_nonzero(np.ascontiguousarray(limbs).view(np.uint8)))
     S = min(M, 8192 // (4 if int(limbs[:, 1:].max()) == 0 else 32))
     blocks = K * ((M + S - 1) // S)
+    g2_fold = costs["e_g2_mul"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]
     w = {
         "k_msm_slices": nz_digits * costs["g1_madd"] + blocks * 2048 * costs["g1_add"],
         "ks_miller": K * costs["e_miller"],
-        "ks_oa_miller": sum(nb * 2 * h for h in rounds) * costs["e_miller"],
-        "ks_final_exp": (2 * lK * nb + 1) * costs["e_final_exp"],
-        "ks_f12_step": (K - 1 + sum(2 * nb * (h - 1) for h in rounds)) * costs["e_f12_mul"],
-        "ks_oa_fold_g2": sum(nb * h for h in rounds) * (costs["e_g2_mul"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]),
         "ks_kzg_terms": nb * (2 * K - 2) * costs["e_g2_mul"],
-        "kw_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
-        "kw_oa_g1terms": sum(nb * 2 * h for h in rounds) * costs["g1_mul"],
         "kw_hyper_terms": lM * (M // 2) * costs["g1_mul"],
     }
+    if lK >= 2 and nb * K <= AHEAD_MAX_PAIRS:
+        # round 1 direct; rounds j >= 2 from terms of the arrays of round j - 1 (q = K >> j)
+        qs = [K >> j for j in range(2, lK + 1)]
+        g1_fold = costs["e_g1_mul"] + costs["e_g1_madd"] + costs["e_g1_to_aff"]
+        w.update({
+            "ks_oa_miller": nb * 2 * rounds[0] * costs["e_miller"],
+            "kw_oa_g1terms": nb * 2 * rounds[0] * costs["g1_mul"],
+            "ks_final_exp": (2 * nb + 1) * costs["e_final_exp"],
+            "ks_f12_step": (K - 1 + 2 * nb * (rounds[0] - 1)
+                            + sum(2 * nb * (2 * q - 1) + 4 * nb * (q - 1) for q in qs)) * costs["e_f12_mul"],
+            "ks_oa_fold": sum(nb * h for h in rounds) * (g1_fold + g2_fold),
+            "ks_oa_pterms": sum(nb * 8 * q for q in qs) * (costs["e_miller"] + costs["e_g1_mul"]),
+            "ks_final_exp2": len(qs) * 6 * nb * costs["e_final_exp"],
+            "ks_oa_combine_pow": len(qs) * 4 * nb * (costs["e_gt_pow"] + costs["e_g1_mul"]),
+            "ks_oa_gt_combine": len(qs) * 2 * nb * 2 * costs["e_f12_mul"],
+        })
+    else:
+        w.update({
+            "ks_oa_miller": sum(nb * 2 * h for h in rounds) * costs["e_miller"],
+            "ks_final_exp": (2 * lK * nb + 1) * costs["e_final_exp"],
+            "ks_f12_step": (K - 1 + sum(2 * nb * (h - 1) for h in rounds)) * costs["e_f12_mul"],
+            "ks_oa_fold_g2": sum(nb * h for h in rounds) * g2_fold,
+            "kw_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
+            "kw_oa_g1terms": sum(nb * 2 * h for h in rounds) * costs["g1_mul"],
+        })
     return w
 
 

@@ -24,7 +24,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(LIBDIR, "libvc.so")
 HOSTCHECK = os.path.join(LIBDIR, "libvc_hostcheck.so")
 
-UNITS = ["k_slp.hip", "k_verify.hip", "k_pair.hip", "k_wide.hip", "k_g1.hip", "k_g2.hip", "k_hash.hip", "vc.cpp"]
+UNITS = ["k_slp.hip", "k_verify.hip", "k_wide.hip", "k_g1.hip", "k_hash.hip", "vc.cpp"]
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I" + INCLUDE, "-I" + CSRC]
 

@@ -388,7 +388,9 @@ API int hc_gt_pow_cyc(const uint8_t *gb, const uint8_t *kb, uint8_t *out) {
   return 0;
 }
 
-// Montgomery products (MUL operations) in the engine's programs, for the work model:
+// Montgomery products (MUL operations) in the engine's programs, for the work model
+// (9.. : G1 phi + table, two doublings + addition, two doublings, mixed addition, to affine;
+// cyclotomic squaring; the three Frobenius maps):
 // 0 Miller loop (whole sequence), 1 final exponentiation (whole sequence, without the
 // one-lane inversion), 2 G2 psi images, 3 G2 table, 4 G2 doubling, 5 G2 addition,
 // 6 G2 mixed addition, 7 G2 to affine (norm + affine), 8 F_p12 product
@@ -413,6 +415,13 @@ API uint64_t hc_engine_muls(int which) {
     case 6: return prog_muls(slp::PROG_G2_MADD);
     case 7: return prog_muls(slp::PROG_G2_NORM) + prog_muls(slp::PROG_G2_AFF);
     case 8: return prog_muls(slp::PROG_F12_MUL);
+    case 9: return prog_muls(slp::PROG_G1_PHI) + prog_muls(slp::PROG_G1_TABLE);
+    case 10: return prog_muls(slp::PROG_G1_DBL2_ADD);
+    case 11: return prog_muls(slp::PROG_G1_DBL2);
+    case 12: return prog_muls(slp::PROG_G1_MADD);
+    case 13: return prog_muls(slp::PROG_G1_AFF);
+    case 14: return prog_muls(slp::PROG_F12_CSQR);
+    case 15: return prog_muls(slp::PROG_F12_FROB1) + prog_muls(slp::PROG_F12_FROB2) + prog_muls(slp::PROG_F12_FROB3);
   }
   return 0;
 }

@@ -29,15 +29,6 @@ __global__ void __launch_bounds__(TPB) k_pow_table(const fe *beta, fe *out, uint
   out[k] = acc;
 }
 
-// out[i] = k_i P_i (or k_i P_0 when broadcast), scalars in Montgomery F_r, result affine
-__global__ void __launch_bounds__(TPB) k_g1_mul(const g1_aff *P, int broadcast, const fe *k, uint64_t n, g1_aff *out) {
-  uint64_t i = gtid();
-  if (i >= n) return;
-  uint32_t kk[8];
-  canon_scalar(kk, k[i]);
-  out[i] = jac_to_aff(scalar_mul(P[broadcast ? 0 : i], kk));
-}
-
 // table[w M + a] = 2^{8w} base[a] for w < nwin
 __global__ void __launch_bounds__(TPB) k_msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table) {
   uint64_t a = gtid();
@@ -130,15 +121,6 @@ __global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, 
   if (t == 0) partial[blockIdx.x] = red[0];
 }
 
-// out[s] = affine(sum_{q < len} data[s*len + q])
-__global__ void __launch_bounds__(TPB) k_sum_g1(const g1_jac *data, uint64_t nseg, uint64_t len, g1_aff *out) {
-  uint64_t s = gtid();
-  if (s >= nseg) return;
-  g1_jac acc = data[s * len];
-  for (uint64_t q = 1; q < len; q++) acc = jac_add(acc, data[s * len + q]);
-  out[s] = jac_to_aff(acc);
-}
-
 // ================================================================ open-all, step 1
 __global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B) {
   uint64_t id = gtid();
@@ -147,36 +129,6 @@ __global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff 
   A[id] = Cj[i];
   V[id] = h[2 * i];
   B[id] = fe_zero();
-}
-
-// terms of <A_R, b_L> (side 0) and <A_L, b_R> (side 1); zero coefficients give the identity
-__global__ void __launch_bounds__(TPB) k_oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S) {
-  uint64_t id = gtid();
-  if (id >= nb * 2 * h) return;
-  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
-  const g1_aff &P = side ? A[k * K + i] : A[k * K + h + i];
-  const fe &c = side ? B[k * K + h + i] : B[k * K + i];
-  g1_jac out = jac_inf<OpsG1>();
-  if (!fe_is_zero(c)) {
-    uint32_t kk[8];
-    canon_scalar(kk, c);
-    out = scalar_mul(P, kk);
-  }
-  S[(k * 2 + side) * (K / 2) + i] = out;
-}
-
-// A_j = A_L o A_R^{x_j}, b_j = b_L + b_R / x_j
-__global__ void __launch_bounds__(TPB) k_oa_fold_g1(g1_aff *A, fe *B, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h,
-                             uint32_t j, uint32_t lK) {
-  uint64_t id = gtid();
-  if (id >= nb * h) return;
-  uint64_t k = id / h, i = id % h;
-  uint64_t slot = k * lK + (j - 1);
-  uint32_t kk[8];
-  canon_scalar(kk, X[slot]);
-  g1_jac t = scalar_mul(A[k * K + h + i], kk);
-  A[k * K + i] = jac_to_aff(jac_madd(t, A[k * K + i]));
-  B[k * K + i] = fr_add(B[k * K + i], fr_mul(B[k * K + h + i], Xinv[slot]));
 }
 
 // fold rows, canonical F_r: y[0][j][a] = rho_j m[jM+a]; the Montgomery product of a
@@ -195,33 +147,6 @@ __global__ void __launch_bounds__(TPB) k_ylevel(fe *Y, uint64_t M, uint64_t K, u
   uint64_t w = id / M, a = id % M;
   uint64_t off = 2 * K - ((2 * K) >> h), offc = 2 * K - ((2 * K) >> (h - 1));
   Y[(off + w) * M + a] = fr_add(Y[(offc + 2 * w) * M + a], Y[(offc + 2 * w + 1) * M + a]);
-}
-
-__global__ void __launch_bounds__(TPB) k_dlevel(g1_aff *D, uint64_t K, uint32_t h) {
-  uint64_t w = gtid();
-  if (w >= (K >> h)) return;
-  uint64_t off = 2 * K - ((2 * K) >> h), offc = 2 * K - ((2 * K) >> (h - 1));
-  D[off + w] = jac_to_aff(jac_madd(jac_from_aff(D[offc + 2 * w]), D[offc + 2 * w + 1]));
-}
-
-// HyperEval terms: depth d, prefix p, c < half = 2^{lM-d-1}:
-// (g*[p 2^{k} + half + c] - g*[p 2^{k} + c]) ek_{k-1}[c], k = lM - d; term index d (M/2) + p half + c
-__global__ void __launch_bounds__(TPB) k_hyper_terms(const fe *g, const g1_aff *ek, uint64_t M, uint32_t lM, g1_jac *S) {
-  uint64_t id = gtid();
-  uint64_t per = M / 2;
-  if (id >= lM * per) return;
-  uint32_t d = (uint32_t)(id / per);
-  uint64_t r = id % per;
-  uint32_t k = lM - d;
-  uint64_t half = 1ull << (k - 1);
-  uint64_t p = r / half, c = r % half;
-  fe q = fr_sub(g[p * (2 * half) + half + c], g[p * (2 * half) + c]);  // canonical difference
-  g1_jac out = jac_inf<OpsG1>();
-  if (!fe_is_zero(q)) {
-    const g1_aff &base = ek[(1ull << (k - 1)) - 1 + c];
-    out = scalar_mul(base, q.l);
-  }
-  S[id] = out;
 }
 
 // ================================================================ export
@@ -269,7 +194,6 @@ __global__ void __launch_bounds__(TPB) k_glv_dec(const fe *X, uint64_t nb, uint3
 namespace kl {
 void ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n, hipStream_t st) { L1(k_ek_weights, n, lM, s, w, n); }
 void pow_table(const fe *beta, fe *out, uint64_t n, hipStream_t st) { L1(k_pow_table, n, beta, out, n); }
-void g1_mul(const g1_aff *P, int bc, const fe *k, uint64_t n, g1_aff *out, hipStream_t st) { if (n) L1(k_g1_mul, n, P, bc, k, n, out); }
 void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hipStream_t st) { L1(k_msm_tables, M, base, M, nwin, table); }
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st) { L1(k_lift_u32, n, in, n, out); }
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st) { L1(k_check_fr, n, m, n, err); }
@@ -278,7 +202,6 @@ void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t 
   uint64_t nslice = (M + S - 1) / S;
   LAUNCH(k_msm_slices, dim3((unsigned)(K * nslice)), dim3(256), 0, scal, M, nwin, S, table, partial);
 }
-void sum_g1(const g1_jac *data, uint64_t nseg, uint64_t len, g1_aff *out, hipStream_t st) { L1(k_sum_g1, nseg, data, nseg, len, out); }
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
   for (uint64_t s = 1; s < len; s <<= 1) {
     uint64_t per = (len + 2 * s - 1) / (2 * s);
@@ -291,22 +214,11 @@ void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint6
 void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st) {
   L1(k_oa_init, nb * K, Cj, h, K, nb, A, V, B);
 }
-void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st) {
-  L1(k_oa_g1terms, nb * 2 * h, A, B, K, nb, h, S);
-}
-void oa_fold_g1(g1_aff *A, fe *B, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
-                hipStream_t st) {
-  L1(k_oa_fold_g1, nb * h, A, B, X, Xinv, K, nb, h, j, lK);
-}
 void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st) {
   L1(k_glv_dec, nb, X, nb, j, lK, out);
 }
 void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_t st) { L1(k_ylevel0, N, m, r, M, N, Y); }
 void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st) { L1(k_ylevel, (K >> h) * M, Y, M, K, h); }
-void dlevel(g1_aff *D, uint64_t K, uint32_t h, hipStream_t st) { L1(k_dlevel, K >> h, D, K, h); }
-void hyper_terms(const fe *g, const g1_aff *ek, uint64_t M, uint32_t lM, g1_jac *S, hipStream_t st) {
-  L1(k_hyper_terms, lM * (M / 2), g, ek, M, lM, S);
-}
 void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st) { if (n) L1(k_encode, n, in, n, mode, out); }
 void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st) {
   if (n) L1(k_gather_encode, n, base, idx, mode, n, out);

@@ -71,16 +71,6 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_
   miller_one(S, P, Q, F + (k * 2 + side) * (K / 2) + i);
 }
 
-// Miller loops of the terms of the next round (oa_terms.hpp) into F[term.out]
-__global__ void __launch_bounds__(SLP_T) ks_oa_pmiller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q,
-                                                      fp12 *F) {
-  __shared__ f29 S[slp::ML_NSLOT];
-  uint64_t id = blockIdx.x;
-  if (id >= nb * 8 * q) return;
-  oat::Term tm = oat::term(id, K, nb, q);
-  miller_one(S, A + tm.a, V + tm.v, F + tm.out);
-}
-
 #define FE_SLOTS (slp::FE_NSLOT + 12 * slp::FE_NBUF)
 #define FE_BUF(b) (slp::FE_NSLOT + 12 * (b))
 
@@ -307,29 +297,6 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_pterms(const g1_aff *A, const g2_
 // ---------------------------------------------------------------- cyclotomic G_T powers
 #define GTP_SLOTS (slp::FE_NSLOT + 12 * gtp::NBUF)
 
-// out[s] = in[s]^k for in[s] in the cyclotomic subgroup, k = (s odd ? k_odd : k_even)[(s >> 2)
-// kstride] (Montgomery F_r form), through the 4-dimensional Frobenius split (gtpow.hpp)
-__global__ void __launch_bounds__(SLP_T) ks_gt_pow_cyc(const fp12 *in, const fe *k_even, const fe *k_odd, uint64_t kstride,
-                                                      uint64_t n, fp12 *out) {
-  __shared__ f29 S[GTP_SLOTS];
-  __shared__ gls::Dec dec;
-  uint64_t s = blockIdx.x;
-  if (s >= n) return;
-  const int t = threadIdx.x;
-  if (t == 0) {
-    fe kc = f_from_mont<FpR>((s & 1 ? k_odd : k_even)[(s >> 2) * kstride]);
-    dec = gls::decompose(kc.l);
-  }
-  const fe *src = reinterpret_cast<const fe *>(in + s);
-  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
-  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
-  __syncthreads();
-  slp::DevCtx c{S};
-  int r = gtp::pow_cyc(c, dec, slp::FE_NSLOT);
-  fe *dst = reinterpret_cast<fe *>(out + s);
-  if (t < 12) dst[t] = r < 0 ? (t == 0 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[FE_BUF(r) + t]));
-}
-
 // The x-dependent part of a round taken ahead: blocks [0, 4 nb) raise PX[s] (cyclotomic)
 // to k_s, blocks [4 nb, 8 nb) multiply PX1[s] (G1) by k_s, with k_s = (s odd ? k_odd :
 // k_even)[(s >> 2) kstride]; outputs PE[s] and PM[s] (Jacobian).
@@ -422,12 +389,6 @@ void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *ou
 void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st) {
   LAUNCH(ks_oa_fold_g2, dim3((unsigned)(nb * h)), dim3(SLP_T), 0, Vin, Vout, Xinv, K, nb, h, j, lK);
-}
-void oa_pmiller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, hipStream_t st) {
-  LAUNCH(ks_oa_pmiller, dim3((unsigned)(nb * 8 * q)), dim3(SLP_T), 0, A, V, K, nb, q, F);
-}
-void gt_pow_cyc(const fp12 *in, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t n, fp12 *out, hipStream_t st) {
-  if (n) LAUNCH(ks_gt_pow_cyc, dim3((unsigned)n), dim3(SLP_T), 0, in, k_even, k_odd, kstride, n, out);
 }
 void oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st) {
   LAUNCH(ks_oa_gt_combine, dim3((unsigned)(2 * nb)), dim3(SLP_T), 0, U, P, nb, L, R, lK);

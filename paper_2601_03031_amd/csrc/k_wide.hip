@@ -65,25 +65,6 @@ __device__ __forceinline__ bool scalar_is_zero(const uint32_t k[8]) {
 __device__ __forceinline__ g1_jac mul_any(const g1_aff &P, const uint32_t kk[8]) { return g1_mul_glv(P, glv::decompose(kk)); }
 __device__ __forceinline__ g2_jac mul_any(const g2_aff &P, const uint32_t kk[8]) { return scalar_mul(P, kk); }
 
-// ---------------------------------------------------------------- pairings
-__global__ void __launch_bounds__(TPBW) kw_miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n,
-                                                 void *out) {
-  uint64_t i = wgid();
-  if (i >= n) return;
-  wst(out, i, miller_loop(wld<g1_aff>(P, i * sp), wld<g2_aff>(Q, i * sq)));
-}
-
-// side 0 (L) pairs A[h+i] with V[i], side 1 (R) A[i] with V[h+i]; F[(2k+side) K/2 + i]
-__global__ void __launch_bounds__(TPBW) kw_oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h,
-                                                    void *F) {
-  uint64_t id = wgid();
-  if (id >= nb * 2 * h) return;
-  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
-  g1_aff P = wld<g1_aff>(A, side ? k * K + i : k * K + h + i);
-  g2_aff Q = wld<g2_aff>(V, side ? k * K + h + i : k * K + i);
-  wst(F, (k * 2 + side) * (K / 2) + i, miller_loop(P, Q));
-}
-
 // ---------------------------------------------------------------- scalar multiplications
 template <class O>
 __global__ void __launch_bounds__(TPBW) kw_mul(const void *P, int broadcast, const void *k, uint64_t n, void *out) {
@@ -125,54 +106,6 @@ __global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(const void *Ain, const voi
   fe b = fr_add(bl, fr_mul(br, wld<fe>(Xinv, slot)));
   wst(Aout, k * K + i, a);
   wst(Bout, k * K + i, b);
-}
-
-// G1 terms b[v] A[a] of the next round (oa_terms.hpp) into S[term.out], Jacobian
-__global__ void __launch_bounds__(TPBW) kw_oa_pg1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t q,
-                                                      void *S) {
-  uint64_t id = wgid();
-  if (id >= nb * 8 * q) return;
-  oat::Term tm = oat::term(id, K, nb, q);
-  fe c = wld<fe>(B, tm.v);
-  g1_jac out = jac_inf<OpsG1>();
-  if (!fe_is_zero(c)) {
-    uint32_t kk[8];
-    wscalar(kk, c);
-    out = mul_any(wld<g1_aff>(A, tm.a), kk);
-  }
-  wst(S, tm.out, out);
-}
-
-// out[s] = k P[s] (Jacobian), k = (s odd ? k_odd : k_even)[(s >> 2) kstride] (Montgomery F_r)
-__global__ void __launch_bounds__(TPBW) kw_oa_cmul(const void *P, const void *k_even, const void *k_odd, uint64_t kstride,
-                                                  uint64_t n, void *out) {
-  uint64_t s = wgid();
-  if (s >= n) return;
-  uint32_t kk[8];
-  wscalar(kk, wld<fe>(s & 1 ? k_odd : k_even, (s >> 2) * kstride));
-  wst(out, s, mul_any(wld<g1_aff>(P, s), kk));
-}
-
-// v_j = v_L o v_R^{1/x_j}
-__global__ void __launch_bounds__(TPBW) kw_oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h,
-                                                     uint32_t j, uint32_t lK) {
-  uint64_t id = wgid();
-  if (id >= nb * h) return;
-  uint64_t k = id / h, i = id % h;
-  uint32_t kk[8];
-  wscalar(kk, wld<fe>(Xinv, k * lK + (j - 1)));
-  g2_jac t = scalar_mul(wld<g2_aff>(V, k * K + h + i), kk);
-  wst(V, k * K + i, jac_to_aff(jac_madd(t, wld<g2_aff>(V, k * K + i))));
-}
-
-// terms q_m h_m of the KZG proof of v_l
-__global__ void __launch_bounds__(TPBW) kw_kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S) {
-  uint64_t n = 2 * K - 2;
-  uint64_t id = wgid();
-  if (id >= nb * n) return;
-  uint32_t kk[8];
-  wscalar(kk, wld<fe>(Q, id));
-  wst(S, id, scalar_mul(wld<g2_aff>(h, id % n), kk));
 }
 
 // HyperEval terms (canonical differences of the folded table times PST keys)
@@ -281,12 +214,6 @@ namespace klw {
     if (dbg::on()) dbg::check(#kern, st);                                                    \
   } while (0)
 
-void miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n, void *out, hipStream_t st) {
-  if (n) LW(kw_miller, n, P, sp, Q, sq, n, out);
-}
-void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st) {
-  LW(kw_oa_miller, nb * 2 * h, A, V, K, nb, h, F);
-}
 void g1_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st) {
   if (n) LW(kw_mul<OpsG1>, n, P, bc, k, n, out);
 }
@@ -299,18 +226,6 @@ void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t 
 void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv, const void *dec, uint64_t K,
                 uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
   LW(kw_oa_fold_g1, nb * h, Ain, Bin, Aout, Bout, Xinv, static_cast<const glv::Dec *>(dec), K, nb, h, j, lK);
-}
-void oa_pg1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t q, void *S, hipStream_t st) {
-  LW(kw_oa_pg1terms, nb * 8 * q, A, B, K, nb, q, S);
-}
-void oa_cmul(const void *P, const void *k_even, const void *k_odd, uint64_t kstride, uint64_t n, void *out, hipStream_t st) {
-  if (n) LW(kw_oa_cmul, n, P, k_even, k_odd, kstride, n, out);
-}
-void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
-  LW(kw_oa_fold_g2, nb * h, V, Xinv, K, nb, h, j, lK);
-}
-void kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S, hipStream_t st) {
-  LW(kw_kzg_terms, nb * (2 * K - 2), h, Q, K, nb, S);
 }
 void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st) {
   LW(kw_hyper_terms, lM * (M / 2), g, ek, M, lM, S);

@@ -1,4 +1,5 @@
-// Host-side declarations of the kernel launchers in kernels.hip.
+// Host-side declarations of the kernel launchers (k_g1.hip, k_hash.hip, k_verify.hip: one
+// lane per element; k_wide.hip: eight lanes per element; k_slp.hip: the engine).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -13,45 +14,31 @@ namespace kl {
 void trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta, hipStream_t st);
 void ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n, hipStream_t st);
 void pow_table(const fe *beta, fe *out, uint64_t n, hipStream_t st);
-void g1_mul(const g1_aff *P, int bc, const fe *k, uint64_t n, g1_aff *out, hipStream_t st);
-void g2_mul(const g2_aff *P, int bc, const fe *k, uint64_t n, g2_aff *out, hipStream_t st);
 void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hipStream_t st);
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st);
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st);
-void sum_g1(const g1_jac *data, uint64_t nseg, uint64_t len, g1_aff *out, hipStream_t st);
-void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 // input s at in[s*stride]; output to (s odd ? out1 : out0)[(s >> 1) * ostride]
-void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
-void g2_reduce(g2_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st);
-void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint64_t ostride, hipStream_t st);
 void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st);
 void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st);
 void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
 void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st);
-void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st);
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st);
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
 // L[k lK], R[k lK] = U[2k + side] + P[4k + 2 side] + P[4k + 2 side + 1] (affine)
 void oa_g1_combine(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st);
-void oa_fold_g1(g1_aff *A, fe *B, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
-                hipStream_t st);
-void oa_fold_g2(g2_aff *V, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   hipStream_t st);
-void kzg_terms(const g2_aff *h, const fe *Q, uint64_t K, uint64_t nb, g2_jac *S, hipStream_t st);
 void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st);
 void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st);
 void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st);
 void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st);
 void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_t st);
 void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st);
-void dlevel(g1_aff *D, uint64_t K, uint32_t h, hipStream_t st);
-void hyper_terms(const fe *g, const g1_aff *ek, uint64_t M, uint32_t lM, g1_jac *S, hipStream_t st);
 void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st);
 void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st);
 }  // namespace kl
@@ -59,19 +46,11 @@ void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_
 // Wide-layout kernels (k_wide.hip, 8 lanes per field element); same memory layouts
 // as above, passed untyped because the register types differ in that unit.
 namespace klw {
-void miller(const void *P, uint64_t sp, const void *Q, uint64_t sq, uint64_t n, void *out, hipStream_t st);
-void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st);
 void g1_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
 void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStream_t st);
 void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st);
 void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv, const void *dec, uint64_t K,
                 uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
-// next-round G1 terms (oa_terms.hpp), Jacobian; out[s] = k P[s] with k from k_even (s even)
-// or k_odd (s odd) at (s >> 2) kstride, Jacobian
-void oa_pg1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t q, void *S, hipStream_t st);
-void oa_cmul(const void *P, const void *k_even, const void *k_odd, uint64_t kstride, uint64_t n, void *out, hipStream_t st);
-void oa_fold_g2(void *V, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
-void kzg_terms(const void *h, const void *Q, uint64_t K, uint64_t nb, void *S, hipStream_t st);
 void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st);
 void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void g2_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
@@ -92,10 +71,7 @@ void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uin
                 hipStream_t st);
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
 void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st);
-// next-round terms (oa_terms.hpp): Miller loops; cyclotomic powers in[s]^{k}, k from k_even
-// (s even) or k_odd (s odd) at (s >> 2) kstride; L[k lK], R[k lK] = U[2k + side] P[4k + 2 side] P[4k + 2 side + 1]
-void oa_pmiller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, hipStream_t st);
-void gt_pow_cyc(const fp12 *in, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t n, fp12 *out, hipStream_t st);
+// L[k lK], R[k lK] = U[2k + side] P[4k + 2 side] P[4k + 2 side + 1] (next-round terms, oa_terms.hpp)
 void oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st);
 // fused round kernels: G1 + G2 fold; Miller loops + G1 terms of the next round; G_T powers
 // + G1 multiples by x, x^{-1}; final exponentiations of two strided lists

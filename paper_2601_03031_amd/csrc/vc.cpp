@@ -429,11 +429,12 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   CK(hipMemsetAsync(tree, 0, 32, st));  // heap node 0 is unused
 
   // ---- Step 2 runs on side stream 1, concurrently with Step 1: Merkle tree (Fiat-Shamir),
-  // randomized folding tree, HyperEval on g* (Protocol 1 Step 2 and its Sub-protocol)
+  // randomized folding tree, HyperEval on g* (Protocol 1 Step 2 and its Sub-protocol).  Its
+  // launches are issued after those of the first Step 1 round, which is on the critical path.
   hipStream_t s1 = pp->side[0], s2 = pp->side[1];
-  if (int rc2 = stream_wait(pp, 0, st, s1)) return rc2;
-  {
-    hipStream_t st_main = st;
+  if (int rc2 = ev_mark(pp, 0, st)) return rc2;
+  auto launch_step2 = [&]() -> int {
+    if (int rc2 = ev_wait(pp, 0, s1)) return rc2;
     hipStream_t st = s1;  // launches below go to side stream 1
     kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
     for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(tree, s, st);
@@ -449,8 +450,8 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       klw::g1_reduce(base, 1ull << d, half, half, st);
       klw::g1_to_aff(base, half, 1ull << d, W + (1ull << d) - 1, 1, st);
     }
-    (void)st_main;
-  }
+    return VC_OK;
+  };
 
   // ---- Step 1: FC.BOpen for every block, all blocks in lockstep (Protocol 1, Eq. genFCBatchProof).
   // Round j works on the arrays A, V, b of buffer (j - 1) & 1; its fold writes buffer j & 1.
@@ -506,6 +507,8 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       kl::oa_g1_combine(PU1[par], PM, nb, Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
     }
     kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
+    if (j == 1)
+      if (int rc2 = launch_step2()) return rc2;
     // fold with x_j into the other buffer
     if (ahead) {
       if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
