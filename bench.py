@@ -56,6 +56,7 @@ def op_costs():
     # G_T power through the 4-dimensional split (65-bit): Frobenius images, 11 table
     # products, then per bit one cyclotomic squaring and (15/16) one product
     c["e_gt_pow"] = e[15] + 11 * e[8] + 64 * e[14] + 60 * e[8]
+    c["e_g1_tab"], c["e_g1_dbl2"], c["e_csqr"], c["e_gt_tab"] = e[9], e[11], e[14], e[15] + 11 * e[8]
     return c
 
 
@@ -89,8 +90,12 @@ def work_model(L, b, limbs, costs):
             "ks_oa_fold": sum(nb * h for h in rounds) * (g1_fold + g2_fold),
             "ks_oa_pterms": sum(nb * 8 * q for q in qs) * (costs["e_miller"] + costs["e_g1_mul"]),
             "ks_final_exp2": len(qs) * 6 * nb * costs["e_final_exp"],
-            "ks_oa_combine_pow": len(qs) * 4 * nb * (costs["e_gt_pow"] + costs["e_g1_mul"]),
-            "ks_oa_gt_combine": len(qs) * 2 * nb * 2 * costs["e_f12_mul"],
+            # four-part split multiplications: the whole work plus three more tables each
+            "ks_oa_combine_split": len(qs) * 4 * nb * (costs["e_gt_pow"] + 3 * costs["e_gt_tab"]
+                                                       + costs["e_g1_mul"] + 3 * costs["e_g1_tab"]),
+            "ks_oa_gt_combine8": len(qs) * 2 * nb * 8 * costs["e_f12_mul"],
+            "ks_gt_sqr_mults": len(qs) * 4 * nb * 96 * costs["e_csqr"],
+            "ks_g1_dbl_mults": len(qs) * 4 * nb * (48 * costs["e_g1_dbl2"] + 3 * costs["e_g1_to_aff"]),
         })
     else:
         w.update({

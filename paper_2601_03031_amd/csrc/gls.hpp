@@ -88,6 +88,25 @@ __host__ __device__ inline Dec decompose(const uint32_t *k) {
   return d;
 }
 
+// The part of the split with bits [lo, lo + width) of each |k_j| (signs kept), width <= 32:
+// with g_lo = g^{2^lo} (or 2^lo Q), the parts over consecutive ranges multiply (add) to the whole.
+__host__ __device__ inline Dec chunk(const Dec &d, int lo, int width) {
+  Dec c;
+  uint32_t top = 0;
+  for (int j = 0; j < 4; j++) {
+    int w = lo >> 5, s = lo & 31;
+    uint64_t v = d.mag[j][w] >> s;
+    if (s && w + 1 < 3) v |= (uint64_t)d.mag[j][w + 1] << (32 - s);
+    v &= width == 32 ? 0xffffffffull : ((1ull << width) - 1);
+    c.mag[j][0] = (uint32_t)v;
+    c.mag[j][1] = c.mag[j][2] = 0;
+    top |= c.mag[j][0];
+  }
+  c.neg = d.neg;
+  c.nbits = (d.nbits == 0 || top == 0) ? 0 : 32 - __builtin_clz(top);
+  return c;
+}
+
 // digit of bit position t: bit j is bit t of |k_j|
 __host__ __device__ inline uint32_t digit(const Dec &d, uint32_t t) {
   uint32_t r = 0;

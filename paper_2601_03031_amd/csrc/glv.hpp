@@ -80,6 +80,27 @@ __host__ __device__ inline Dec decompose(const uint32_t *k) {
 }
 
 // joint 2-bit digit of window w: d0 + 4 d1 with d_j the bits 2w, 2w+1 of |k_j|
+// bit length of a little-endian magnitude of n words
+__host__ __device__ inline uint32_t mag_bits(const uint32_t *m, int n) {
+  for (int w = n - 1; w >= 0; w--)
+    if (m[w]) return 32 * w + 32 - __builtin_clz(m[w]);
+  return 0;
+}
+
+// The part of the split with bits [32 t, 32 t + 32) of each |k_j| (signs kept): with
+// P_t = 2^{32 t} P, k P = sum_{t < 4} chunk_t(k) P_t.
+__host__ __device__ inline Dec chunk(const Dec &d, int t) {
+  Dec c;
+  for (int j = 0; j < 2; j++) {
+    c.mag[j][0] = d.mag[j][t];
+    c.mag[j][1] = c.mag[j][2] = c.mag[j][3] = 0;
+  }
+  c.neg = d.neg;
+  uint32_t a = mag_bits(c.mag[0], 1), b = mag_bits(c.mag[1], 1);
+  c.nbits = d.nbits == 0 ? 0 : (a > b ? a : b);
+  return c;
+}
+
 __host__ __device__ inline uint32_t digit2(const Dec &d, uint32_t w) {
   uint32_t b = 2 * w;
   uint32_t d0 = (d.mag[0][b >> 5] >> (b & 31)) & 3u, d1 = (d.mag[1][b >> 5] >> (b & 31)) & 3u;

@@ -178,6 +178,131 @@ inline NOINL fe xmd_finish_fr(Hasher &hs, const char *dst) {
   return fr_add(fr_mul(hi, fe_const(bn::R_R3)), fr_mul(lo, fe_const(bn::R_R2)));
 }
 
+// ---- the same hashes for a message that every lane of the wavefront holds (word-aligned
+// prefix in LDS plus a short byte tail): on the device the values are made explicitly
+// uniform so that the compression runs on the scalar unit
+#ifdef __HIP_DEVICE_COMPILE__
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+#else
+HD inline uint32_t uni32(uint32_t x) { return x; }
+#endif
+
+HD inline void compress_u(uint32_t h[8], const uint32_t blk[16]) {
+  uint32_t w[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) w[i] = blk[i];
+  uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
+#pragma unroll
+  for (int i = 0; i < 64; i++) {
+    uint32_t wi;
+    if (i < 16) {
+      wi = w[i];
+    } else {
+      uint32_t w15 = w[(i - 15) & 15], w2 = w[(i - 2) & 15];
+      uint32_t s0 = rotr(w15, 7) ^ rotr(w15, 18) ^ (w15 >> 3);
+      uint32_t s1 = rotr(w2, 17) ^ rotr(w2, 19) ^ (w2 >> 10);
+      wi = w[i & 15] + s0 + w[(i - 7) & 15] + s1;
+      w[i & 15] = wi;
+    }
+    uint32_t S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
+    uint32_t ch = (e & f) ^ (~e & g);
+    uint32_t t1 = hh + S1 + ch + K[i] + wi;
+    uint32_t S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
+    uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
+    hh = g;
+    g = f;
+    f = e;
+    e = d + t1;
+    d = c;
+    c = b;
+    b = a;
+    a = t1 + S0 + mj;
+  }
+  h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
+}
+
+// SHA-256 of (words[0 .. nw) as big-endian words, in LDS) || tail[0 .. tlen) (tlen < 64);
+// every lane calls it with the same arguments; tlen <= 64 + 4 (nw mod 16) - 9
+HD inline void sha_words_u(const uint32_t *words, int nw, const uint8_t *tail, int tlen, uint32_t out[8]) {
+  uint32_t h[8], blk[16];
+#pragma unroll
+  for (int i = 0; i < 8; i++) h[i] = H0[i];
+  int full = nw / 16;
+  for (int bI = 0; bI < full; bI++) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) blk[i] = uni32(words[16 * bI + i]);
+    compress_u(h, blk);
+  }
+  // remaining words, the tail bytes, 0x80, zeros and the bit length (one or two blocks)
+  uint8_t rest[128];
+  int r = 0;
+  for (int i = 16 * full; i < nw; i++) {
+    uint32_t v = uni32(words[i]);
+    rest[r++] = (uint8_t)(v >> 24); rest[r++] = (uint8_t)(v >> 16); rest[r++] = (uint8_t)(v >> 8); rest[r++] = (uint8_t)v;
+  }
+  for (int i = 0; i < tlen; i++) rest[r++] = tail[i];
+  uint64_t bits = ((uint64_t)nw * 4 + (uint64_t)tlen) * 8;
+  rest[r++] = 0x80;
+  int nblk = r + 8 <= 64 ? 1 : 2;
+  while (r < 64 * nblk - 8) rest[r++] = 0;
+  for (int i = 7; i >= 0; i--) rest[r++] = (uint8_t)(bits >> (8 * i));
+  for (int bI = 0; bI < nblk; bI++) {
+#pragma unroll
+    for (int i = 0; i < 16; i++)
+      blk[i] = (uint32_t)rest[64 * bI + 4 * i] << 24 | (uint32_t)rest[64 * bI + 4 * i + 1] << 16 |
+               (uint32_t)rest[64 * bI + 4 * i + 2] << 8 | rest[64 * bI + 4 * i + 3];
+    compress_u(h, blk);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++) out[i] = h[i];
+}
+
+// hash_to_field to F_r (Montgomery form) of msg = words[16 .. nw), where words[0 .. 16) must
+// hold the 64 zero bytes Z_pad of expand_message_xmd (L = 48); same result as Hasher with
+// xmd_begin / xmd_finish_fr (the DST has at most 30 bytes)
+HD inline fe xmd_fr_words_u(const uint32_t *words, int nw, const char *dst) {
+  int dlen = cstrlen(dst);
+  uint8_t tail[64];
+  int r = 0;
+  tail[r++] = 0; tail[r++] = 48; tail[r++] = 0;
+  for (int i = 0; i < dlen; i++) tail[r++] = (uint8_t)dst[i];
+  tail[r++] = (uint8_t)dlen;
+  uint32_t b0[8], b1[8], b2[8];
+  sha_words_u(words, nw, tail, r, b0);
+  // b1 = H(b0 || 1 || DST'), b2 = H((b0 xor b1) || 2 || DST')
+  uint32_t wb[8];
+  for (int i = 0; i < 8; i++) wb[i] = b0[i];
+  uint8_t t2[64];
+  int r2 = 0;
+  for (int i = 0; i < 8; i++) { t2[r2++] = (uint8_t)(wb[i] >> 24); t2[r2++] = (uint8_t)(wb[i] >> 16); t2[r2++] = (uint8_t)(wb[i] >> 8); t2[r2++] = (uint8_t)wb[i]; }
+  t2[r2++] = 1;
+  for (int i = 0; i < dlen; i++) t2[r2++] = (uint8_t)dst[i];
+  t2[r2++] = (uint8_t)dlen;
+  sha_words_u(nullptr, 0, t2, r2, b1);
+  r2 = 0;
+  for (int i = 0; i < 8; i++) {
+    uint32_t v = b0[i] ^ b1[i];
+    t2[r2++] = (uint8_t)(v >> 24); t2[r2++] = (uint8_t)(v >> 16); t2[r2++] = (uint8_t)(v >> 8); t2[r2++] = (uint8_t)v;
+  }
+  t2[r2++] = 2;
+  for (int i = 0; i < dlen; i++) t2[r2++] = (uint8_t)dst[i];
+  t2[r2++] = (uint8_t)dlen;
+  sha_words_u(nullptr, 0, t2, r2, b2);
+  uint32_t hw[8], lw[8];
+  for (int i = 0; i < 4; i++) { hw[i] = b1[3 - i]; hw[4 + i] = 0; }
+  for (int i = 0; i < 4; i++) lw[i] = b2[3 - i];
+  for (int i = 0; i < 4; i++) lw[4 + i] = b1[7 - i];
+  fe hi = fe_from_words(hw), lo = fe_from_words(lw);
+  return fr_add(fr_mul(hi, fe_const(bn::R_R3)), fr_mul(lo, fe_const(bn::R_R2)));
+}
+
+// canonical big-endian words of a Montgomery-form element, written by one lane
+template <class F> HD inline void put_words(uint32_t *dst, const fe &a) {
+  fe c = f_from_mont<F>(a);
+#pragma unroll
+  for (int i = 0; i < 8; i++) dst[i] = fe_word(c, 7 - i);
+}
+
 // Merkle leaf SHA-256(0x00 || m_i || C_j): m given as 8 BE words, C as 16 BE words
 DEV void merkle_leaf(uint32_t out[8], const uint32_t mw[8], const uint32_t cw[16]) {
   uint32_t x[24];

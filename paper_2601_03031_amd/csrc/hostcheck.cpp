@@ -180,6 +180,19 @@ API void hc_h2f(const char *dst, const uint8_t *msg, uint64_t len, uint8_t *out)
   wr<FpR>(out, sha::xmd_finish_fr(h, dst));
 }
 
+// the word-message form (Z_pad and msg as big-endian words, len a multiple of 4, at most
+// 1024 bytes) used by the challenge kernels
+API void hc_h2f_words(const char *dst, const uint8_t *msg, uint64_t len, uint8_t *out) {
+  uint32_t w[16 + 256];
+  int nw = 16 + (int)(len / 4);
+  for (int i = 0; i < 16; i++) w[i] = 0;
+  for (int i = 16; i < nw; i++) {
+    const uint8_t *q = msg + 4 * (i - 16);
+    w[i] = (uint32_t)q[0] << 24 | (uint32_t)q[1] << 16 | (uint32_t)q[2] << 8 | q[3];
+  }
+  wr<FpR>(out, sha::xmd_fr_words_u(w, nw, dst));
+}
+
 API void hc_sha256(const uint8_t *msg, uint64_t len, uint8_t *out) {
   sha::Hasher h;
   h.init();
@@ -365,6 +378,68 @@ API int hc_g1_mul_engine(const uint8_t *Pb, const uint8_t *kb, const uint8_t *Ab
   c.run(slp::PROG_G1_AFF, 0, 0, 0);
   g1_aff r{slp::from29(slp::canon29(S[slp::G1_ax])), slp::from29(slp::canon29(S[slp::G1_ay]))};
   wrg1(out, r);
+  return 0;
+}
+
+// k P as the sum over t < 4 of chunk_t(k) (2^{32 t} P) on the engine (host model): the split
+// used to run the four parts in parallel
+API int hc_g1_mul_split(const uint8_t *Pb, const uint8_t *kb, uint8_t *out) {
+  static slp::f29 S[slp::G1_NSLOT + 2];
+  g1_aff P = rdg1(Pb);
+  fe k = rd_raw(kb);
+  glv::Dec dec = glv::decompose(k.l);
+  g1_jac acc = jac_inf<OpsG1>();
+  g1_jac Pt = jac_from_aff(P);
+  for (int t = 0; t < 4; t++) {
+    if (t)
+      for (int i = 0; i < 32; i++) Pt = jac_dbl(Pt);
+    g1_aff Pa = jac_to_aff(Pt);
+    S[slp::G1_xP] = slp::to29(Pa.x);
+    S[slp::G1_yP] = slp::to29(Pa.y);
+    ld_consts(S, slp::G1_CBASE, slp::G1_CONSTS, slp::G1_NCONST);
+    slp::HostCtx c{S};
+    bool inf = g1m::mul_add(c, glv::chunk(dec, t), aff_is_inf(Pa), false, slp::G1_NSLOT, S[slp::G1_CBASE + 1]);
+    if (!inf) {
+      g1_jac part{slp::from29(slp::canon29(S[slp::G1_T_0])), slp::from29(slp::canon29(S[slp::G1_T_1])),
+                  slp::from29(slp::canon29(S[slp::G1_T_2]))};
+      acc = jac_add(acc, part);
+    }
+  }
+  wrg1(out, jac_to_aff(acc));
+  return 0;
+}
+
+// g^k as the product over t < 4 of pow(g^{2^{16 t}}, chunk of bits [16 t, 16 t + w_t)) with
+// w_t = 16 (t < 3) or 17, on the engine (host model)
+API int hc_gt_pow_split(const uint8_t *gb, const uint8_t *kb, uint8_t *out) {
+  static slp::f29 S[slp::FE_NSLOT + 12 * gtp::NBUF];
+  fp12 g = rd12(gb), acc = f12_one();
+  fe k = rd_raw(kb);
+  gls::Dec dec = gls::decompose(k.l);
+  const fe *gw = reinterpret_cast<const fe *>(&g);
+  ld_consts(S, slp::FE_CBASE, slp::FE_CONSTS, slp::FE_NCONST);
+  for (int i = 0; i < 12; i++) S[slp::FE_NSLOT + i] = slp::to29(gw[i]);
+  slp::HostCtx c{S};
+  const int b0 = slp::FE_NSLOT, b17 = slp::FE_NSLOT + 12 * 17;
+  for (int t = 0; t < 4; t++) {
+    if (t) {
+      for (int i = 0; i < 16; i++) {
+        slp::run_host(S, slp::PROG_F12_CSQR, b0, b0, b17);
+        for (int q = 0; q < 12; q++) S[b0 + q] = S[b17 + q];
+      }
+    }
+    slp::f29 base[12];
+    for (int q = 0; q < 12; q++) base[q] = S[b0 + q];
+    int r = gtp::pow_cyc(c, gls::chunk(dec, 16 * t, t < 3 ? 16 : 17), slp::FE_NSLOT);
+    if (r >= 0) {
+      fp12 part;
+      fe *pw = reinterpret_cast<fe *>(&part);
+      for (int q = 0; q < 12; q++) pw[q] = slp::from29(slp::canon29(S[slp::FE_NSLOT + 12 * r + q]));
+      acc = f12_mul(acc, part);
+    }
+    for (int q = 0; q < 12; q++) S[b0 + q] = base[q];
+  }
+  wr12(out, acc);
   return 0;
 }
 

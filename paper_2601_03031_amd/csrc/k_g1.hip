@@ -202,11 +202,8 @@ void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t 
   uint64_t nslice = (M + S - 1) / S;
   LAUNCH(k_msm_slices, dim3((unsigned)(K * nslice)), dim3(256), 0, scal, M, nwin, S, table, partial);
 }
-void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
-  for (uint64_t s = 1; s < len; s <<= 1) {
-    uint64_t per = (len + 2 * s - 1) / (2 * s);
-    L1(k_jac_step<OpsG1>, nseg * per, data, nseg, stride, len, s);
-  }
+void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st) {
+  if (len > 1) L1(k_jac_tree<OpsG1>, nseg * ((len + 1) / 2), data, nseg, stride, len, cnt);
 }
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st) {
   L1(k_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);

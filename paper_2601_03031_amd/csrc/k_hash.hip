@@ -82,35 +82,54 @@ __global__ void __launch_bounds__(TPB) k_oa_lr_aff(const g1_jac *S, uint64_t K, 
   (side ? Rg1 : Lg1)[k * lK + (j - 1)] = a;
 }
 
-// (side ? R : L)[k lK] = U[2k + side] + P[4k + 2 side] + P[4k + 2 side + 1] (affine): the next
-// round's G1 parts from the groups of oa_terms.hpp (P holding x X and x^{-1} Y, Jacobian)
-__global__ void __launch_bounds__(TPB) k_oa_g1_combine(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R,
-                                                      uint64_t lK) {
-  uint64_t id = gtid();
+// (side ? R : L)[k lK] = U[2k + side] + sum_{g in {2 side, 2 side + 1}, p < 4} P[4 (4k + g) + p]
+// (affine): a block of 8 threads per (k, side) adds the 8 Jacobian parts in a tree
+__global__ void __launch_bounds__(8) k_oa_g1_combine8(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R,
+                                                     uint64_t lK) {
+  __shared__ g1_jac part[8];
+  uint64_t id = blockIdx.x;
   if (id >= 2 * nb) return;
   uint64_t k = id / 2, side = id % 2;
-  g1_jac t = jac_madd(jac_add(P[4 * k + 2 * side], P[4 * k + 2 * side + 1]), U[id]);
-  (side ? R : L)[k * lK] = jac_to_aff(t);
+  int t = threadIdx.x;
+  part[t] = P[4 * (4 * k + 2 * side) + t];
+  __syncthreads();
+  for (int w = 4; w >= 1; w >>= 1) {
+    if (t < w) part[t] = jac_add(part[t], part[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) (side ? R : L)[k * lK] = jac_to_aff(jac_madd(part[0], U[id]));
 }
 
-// per batch: hash L_j, R_j into x_j, keep x_j and 1/x_j
-__global__ void __launch_bounds__(TPB) k_oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j,
-                                                       uint32_t lK, const g1_aff *Lg1, const g1_aff *Rg1, fe *X, fe *Xinv,
-                                                       int *err) {
-  uint64_t k = gtid();
+// per batch: hash L_j, R_j into x_j, keep x_j and 1/x_j.  A workgroup of 64 per batch: lanes
+// encode the 28 coordinates (and x_{j-1}) in parallel into LDS, then all lanes hash the
+// uniform message on the scalar unit and invert x_j there.
+__global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j,
+                                                     uint32_t lK, const g1_aff *Lg1, const g1_aff *Rg1, fe *X, fe *Xinv,
+                                                     int *err) {
+  __shared__ uint32_t msg[16 + 8 + 2 * (96 + 16)];
+  uint64_t k = blockIdx.x;
   if (k >= nb) return;
   uint64_t slot = k * lK + (j - 1);
-  sha::Hasher hs;
-  sha::xmd_begin(hs);
-  if (j > 1) hs.field<FpR>(X[slot - 1]);
-  hs.gt(Lgt[slot]);
-  hs.g1(Lg1[slot]);
-  hs.gt(Rgt[slot]);
-  hs.g1(Rg1[slot]);
-  fe x = sha::xmd_finish_fr(hs, DSTR_FC_X);
-  if (fe_is_zero(x)) atomicOr(err, VC_ERRBIT_CHALLENGE);
-  X[slot] = x;
-  Xinv[slot] = fr_inv_fast(x);
+  const int t = threadIdx.x;
+  const int pre = j > 1 ? 8 : 0;
+  if (t < 16) msg[t] = 0;  // Z_pad
+  // element e: x_{j-1} (F_r) if j > 1, then L_gt (12), L_g1 (2), R_gt (12), R_g1 (2)
+  const int e = j > 1 ? t - 1 : t;
+  if (j > 1 && t == 0) sha::put_words<FpR>(msg + 16, X[slot - 1]);
+  if (e >= 0 && e < 28) {
+    int side = e / 14, q = e % 14;
+    const fe *src = q < 12 ? reinterpret_cast<const fe *>((side ? Rgt : Lgt) + slot) + q
+                           : reinterpret_cast<const fe *>((side ? Rg1 : Lg1) + slot) + (q - 12);
+    sha::put_words<FpP>(msg + 16 + pre + 112 * side + 8 * q, *src);
+  }
+  __syncthreads();
+  fe x = sha::xmd_fr_words_u(msg, 16 + pre + 224, DSTR_FC_X);
+  fe xi = f_inv_uniform<FpR>(x, bn::R_R3);
+  if (t == 0) {
+    if (fe_is_zero(x)) atomicOr(err, VC_ERRBIT_CHALLENGE);
+    X[slot] = x;
+    Xinv[slot] = xi;
+  }
 }
 
 // ---------------------------------------------------------------- KZG proof of v_l
@@ -242,12 +261,12 @@ void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hip
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st) {
   L1(k_oa_lr_aff, 2 * nb, S, K, nb, j, lK, Lg1, Rg1);
 }
-void oa_g1_combine(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st) {
-  L1(k_oa_g1_combine, 2 * nb, U, P, nb, L, R, lK);
+void oa_g1_combine8(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st) {
+  LAUNCH(k_oa_g1_combine8, dim3((unsigned)(2 * nb)), dim3(8), 0, U, P, nb, L, R, lK);
 }
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st) {
-  L1(k_oa_transcript, nb, Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err);
+  LAUNCH(k_oa_transcript, dim3((unsigned)nb), dim3(64), 0, Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err);
 }
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   hipStream_t st) {

@@ -74,23 +74,53 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_
 #define FE_SLOTS (slp::FE_NSLOT + 12 * slp::FE_NBUF)
 #define FE_BUF(b) (slp::FE_NSLOT + 12 * (b))
 
-// one tree step, a workgroup per product: data[g stride + 2 s q] *= data[g stride + 2 s q + s]
-__global__ void __launch_bounds__(SLP_T) ks_f12_step(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint64_t s) {
+// Product of each segment data[g stride + 0 .. len) into data[g stride] in one launch: a
+// workgroup per pair of the first level; of two sibling nodes, the workgroup that finishes
+// second climbs to the parent (arrival counters as in k_jac_tree).
+__global__ void __launch_bounds__(SLP_T) ks_f12_tree(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt) {
   __shared__ f29 S[slp::FE_NSLOT + 36];
-  uint64_t per = (len + 2 * s - 1) / (2 * s);
+  __shared__ uint32_t arrived;
+  uint64_t per = (len + 1) / 2;
   uint64_t id = blockIdx.x;
   if (id >= nseg * per) return;
   uint64_t g = id / per, q = id % per;
-  uint64_t a = 2 * s * q, b = a + s;
-  if (b >= len) return;
-  fe *da = reinterpret_cast<fe *>(data + g * stride + a);
-  const fe *db = reinterpret_cast<const fe *>(data + g * stride + b);
-  int t = threadIdx.x;
-  if (t < 12) { S[slp::FE_NSLOT + t] = slp::to29(da[t]); S[slp::FE_NSLOT + 12 + t] = slp::to29(db[t]); }
+  fp12 *seg = data + g * stride;
+  uint32_t *c = cnt + g * tree_counters(len);
+  const int t = threadIdx.x;
   load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
-  __syncthreads();
-  slp::run_seq<4>(S, slp::F12_MUL_CALL, 1, slp::FE_NSLOT, 0, 0);
-  if (t < 12) da[t] = slp::from29(slp::canon29(S[slp::FE_NSLOT + 24 + t]));
+  uint64_t s = 1, n = per, cb = 0;
+  for (;;) {
+    uint64_t a = 2 * s * q, b = a + s;
+    if (b < len) {
+      fe *da = reinterpret_cast<fe *>(seg + a);
+      const fe *db = reinterpret_cast<const fe *>(seg + b);
+      if (t < 12) {
+        S[slp::FE_NSLOT + t] = slp::to29(da[t]);
+        S[slp::FE_NSLOT + 12 + t] = slp::to29(db[t]);
+      }
+      __syncthreads();
+      slp::run_seq<4>(S, slp::F12_MUL_CALL, 1, slp::FE_NSLOT, 0, 0);
+      if (t < 12) da[t] = slp::from29(slp::canon29(S[slp::FE_NSLOT + 24 + t]));
+    }
+    if (n == 1) return;
+    uint64_t nn = (n + 1) / 2, qp = q >> 1;
+    if ((q ^ 1) < n) {
+      __threadfence();
+      __syncthreads();
+      if (t == 0) {
+        uint32_t old = atomicAdd(&c[cb + qp], 1u);
+        if (old) c[cb + qp] = 0;
+        arrived = old;
+      }
+      __syncthreads();
+      if (!arrived) return;
+      __threadfence();
+    }
+    cb += nn;
+    q = qp;
+    n = nn;
+    s *= 2;
+  }
 }
 
 // f^((p^12 - 1)/r), a workgroup per input; input s at in[s in_stride], output to
@@ -218,13 +248,15 @@ __global__ void __launch_bounds__(SLP_T) ks_gt_pow(const fp12 *in, const fe *k_m
 #define G1_SLOTS (slp::G1_NSLOT + 2)
 #define G1_ABASE slp::G1_NSLOT
 
-// out = k P + A on the engine (A optional); results written as affine (oaff) or Jacobian (ojac)
+// out = k P + A on the engine (A optional); results written as affine (oaff) or Jacobian (ojac).
+// With chunk >= 0 only that 32-bit part of the GLV split of k is applied (glv::chunk).
 __device__ void g1_job(f29 *S, glv::Dec *dec, const g1_aff *P, const fe *k_mont, const g1_aff *A, g1_aff *oaff,
-                       g1_jac *ojac) {
+                       g1_jac *ojac, int chunk = -1) {
   const int t = threadIdx.x;
   if (t == 0) {
     fe kc = f_from_mont<FpR>(*k_mont);
-    *dec = glv::decompose(kc.l);
+    glv::Dec d = glv::decompose(kc.l);
+    *dec = chunk < 0 ? d : glv::chunk(d, chunk);
   }
   if (t < 2) S[slp::G1_xP + t] = slp::to29(t ? P->y : P->x);
   if (A && t >= 2 && t < 4) S[G1_ABASE + t - 2] = slp::to29(t == 3 ? A->y : A->x);
@@ -297,36 +329,112 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_pterms(const g1_aff *A, const g2_
 // ---------------------------------------------------------------- cyclotomic G_T powers
 #define GTP_SLOTS (slp::FE_NSLOT + 12 * gtp::NBUF)
 
-// The x-dependent part of a round taken ahead: blocks [0, 4 nb) raise PX[s] (cyclotomic)
-// to k_s, blocks [4 nb, 8 nb) multiply PX1[s] (G1) by k_s, with k_s = (s odd ? k_odd :
-// k_even)[(s >> 2) kstride]; outputs PE[s] and PM[s] (Jacobian).
-__global__ void __launch_bounds__(SLP_T) ks_oa_combine_pow(const fp12 *PX, const g1_aff *PX1, const fe *k_even,
-                                                          const fe *k_odd, uint64_t kstride, uint64_t nb, fp12 *PE,
-                                                          g1_jac *PM) {
+// ---------------------------------------------------------------- split multiplications
+// Multiples for the time-split multiplications: M[3 s + m - 1] = G[s]^{2^{16 m}} (cyclotomic
+// squarings), a workgroup per (s, m), m = 1, 2, 3
+__global__ void __launch_bounds__(SLP_T) ks_gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M) {
+  __shared__ f29 S[slp::FE_NSLOT + 24];
+  uint64_t id = blockIdx.x;
+  if (id >= 3 * n) return;
+  uint64_t s = id / 3, m = id % 3 + 1;
+  const int t = threadIdx.x;
+  const fe *src = reinterpret_cast<const fe *>(G + s);
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  int b = 0;
+  for (int i = 0; i < 16 * (int)m; i++) {
+    slp::run1(S, slp::PROG_F12_CSQR, FE_BUF(b), FE_BUF(b), FE_BUF(1 - b));
+    b = 1 - b;
+  }
+  fe *dst = reinterpret_cast<fe *>(M + 3 * s + m - 1);
+  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(b) + t]));
+}
+
+// M[3 s + m - 1] = 2^{32 m} P[s] (affine), a workgroup per (s, m), m = 1, 2, 3
+__global__ void __launch_bounds__(SLP_T) ks_g1_dbl_mults(const g1_aff *P, uint64_t n, g1_aff *M) {
+  __shared__ f29 S[G1_SLOTS];
+  uint64_t id = blockIdx.x;
+  if (id >= 3 * n) return;
+  uint64_t s = id / 3, m = id % 3 + 1;
+  const int t = threadIdx.x;
+  fe *o = reinterpret_cast<fe *>(M + 3 * s + m - 1);
+  if (g1_inf(P[s])) {
+    if (t < 2) o[t] = fe_zero();
+    return;
+  }
+  load_consts<slp::G1_NCONST>(S, slp::G1_CBASE, slp::G1_CONSTS);
+  if (t < 3) S[slp::G1_T_0 + t] = slp::to29(t == 2 ? f_one<FpP>() : t ? P[s].y : P[s].x);
+  __syncthreads();
+  for (int i = 0; i < 16 * (int)m; i++) slp::run1(S, slp::PROG_G1_DBL2, 0, 0, 0);
+  {
+    fe zi = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G1_T_2])), bn::P_R3);
+    if (t == 0) S[slp::G1_tinv] = slp::to29(zi);
+  }
+  __syncthreads();
+  slp::run1(S, slp::PROG_G1_AFF, 0, 0, 0);
+  if (t < 2) o[t] = slp::from29(slp::canon29(S[t ? slp::G1_ay : slp::G1_ax]));
+}
+
+// The x-dependent part of a round taken ahead, each multiplication split in four parts run
+// in parallel: for s < 4 nb and part p < 4, k_s = (s odd ? k_odd : k_even)[(s >> 2) kstride];
+// blocks [0, 16 nb): PE[4 s + p] = (PX[s]^{2^{16 p}})^{chunk_p}, the Frobenius split of k_s
+// restricted to bits [16 p, 16 p + 16) (17 bits for p = 3); blocks [16 nb, 32 nb):
+// PM[4 s + p] = chunk_p(k_s) (2^{32 p} PX1[s]) (Jacobian).  Multiples come from
+// ks_gt_sqr_mults and ks_g1_dbl_mults (PXm, PX1m).
+__global__ void __launch_bounds__(SLP_T) ks_oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1,
+                                                            const g1_aff *PX1m, const fe *k_even, const fe *k_odd,
+                                                            uint64_t kstride, uint64_t nb, fp12 *PE, g1_jac *PM) {
   __shared__ f29 S[imax<GTP_SLOTS, G1_SLOTS>::v];
   __shared__ gls::Dec dec;
   __shared__ glv::Dec d1;
   uint64_t id = blockIdx.x;
-  if (id >= 8 * nb) return;
+  if (id >= 32 * nb) return;
   const int t = threadIdx.x;
-  if (id >= 4 * nb) {
-    uint64_t s = id - 4 * nb;
-    g1_job(S, &d1, PX1 + s, (s & 1 ? k_odd : k_even) + (s >> 2) * kstride, nullptr, nullptr, PM + s);
+  bool g1 = id >= 16 * nb;
+  if (g1) id -= 16 * nb;
+  uint64_t s = id >> 2;
+  int part = (int)(id & 3);
+  const fe *k = (s & 1 ? k_odd : k_even) + (s >> 2) * kstride;
+  if (g1) {
+    g1_job(S, &d1, part ? PX1m + 3 * s + part - 1 : PX1 + s, k, nullptr, nullptr, PM + 4 * s + part, part);
     return;
   }
-  uint64_t s = id;
   if (t == 0) {
-    fe kc = f_from_mont<FpR>((s & 1 ? k_odd : k_even)[(s >> 2) * kstride]);
-    dec = gls::decompose(kc.l);
+    fe kc = f_from_mont<FpR>(*k);
+    dec = gls::chunk(gls::decompose(kc.l), 16 * part, part < 3 ? 16 : 17);
   }
-  const fe *src = reinterpret_cast<const fe *>(PX + s);
+  const fe *src = reinterpret_cast<const fe *>(part ? PXm + 3 * s + part - 1 : PX + s);
   if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
   load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
   __syncthreads();
   slp::DevCtx c{S};
   int r = gtp::pow_cyc(c, dec, slp::FE_NSLOT);
-  fe *dst = reinterpret_cast<fe *>(PE + s);
+  fe *dst = reinterpret_cast<fe *>(PE + 4 * s + part);
   if (t < 12) dst[t] = r < 0 ? (t == 0 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[FE_BUF(r) + t]));
+}
+
+// (side ? R : L)[k lK] = U[2k + side] prod_{g in {2 side, 2 side + 1}, p < 4} P[4 (4k + g) + p]
+__global__ void __launch_bounds__(SLP_T) ks_oa_gt_combine8(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R,
+                                                          uint64_t lK) {
+  __shared__ f29 S[slp::FE_NSLOT + 36];
+  uint64_t id = blockIdx.x;
+  if (id >= 2 * nb) return;
+  uint64_t k = id / 2, side = id % 2;
+  const int t = threadIdx.x;
+  const fe *u = reinterpret_cast<const fe *>(U + id);
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(u[t]);
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  int acc = 0;
+  for (int i = 0; i < 8; i++) {
+    const fe *pi = reinterpret_cast<const fe *>(P + 4 * (4 * k + 2 * side) + i);
+    if (t < 12) S[FE_BUF(1) + t] = slp::to29(pi[t]);
+    __syncthreads();
+    slp::run1(S, slp::PROG_F12_MUL, FE_BUF(acc), FE_BUF(1), FE_BUF(2 - acc));
+    acc = 2 - acc;
+  }
+  fe *dst = reinterpret_cast<fe *>((side ? R : L) + k * lK);
+  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(acc) + t]));
 }
 
 // final exponentiations of two strided lists: job s < n0 takes in0[s st0] to out0[s], the
@@ -346,30 +454,6 @@ __global__ void __launch_bounds__(SLP_T) ks_final_exp2(const fp12 *in0, uint64_t
   if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(slp::FE_RESULT) + t]));
 }
 
-// (side ? R : L)[k lK] = U[2k + side] P[4k + 2 side] P[4k + 2 side + 1]: the next round's
-// G_T parts from the groups of oa_terms.hpp (P holding X^x and Y^{1/x})
-__global__ void __launch_bounds__(SLP_T) ks_oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R,
-                                                         uint64_t lK) {
-  __shared__ f29 S[slp::FE_NSLOT + 48];
-  uint64_t id = blockIdx.x;
-  if (id >= 2 * nb) return;
-  uint64_t k = id / 2, side = id % 2;
-  const int t = threadIdx.x;
-  const fe *u = reinterpret_cast<const fe *>(U + id), *p0 = reinterpret_cast<const fe *>(P + 4 * k + 2 * side),
-           *p1 = reinterpret_cast<const fe *>(P + 4 * k + 2 * side + 1);
-  if (t < 12) {
-    S[FE_BUF(0) + t] = slp::to29(u[t]);
-    S[FE_BUF(1) + t] = slp::to29(p0[t]);
-    S[FE_BUF(2) + t] = slp::to29(p1[t]);
-  }
-  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
-  __syncthreads();
-  slp::run1(S, slp::PROG_F12_MUL, FE_BUF(0), FE_BUF(1), FE_BUF(3));
-  slp::run1(S, slp::PROG_F12_MUL, FE_BUF(3), FE_BUF(2), FE_BUF(0));
-  fe *dst = reinterpret_cast<fe *>((side ? R : L) + k * lK);
-  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(0) + t]));
-}
-
 namespace ks {
 void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st) {
   if (n) LAUNCH(ks_miller, dim3((unsigned)n), dim3(SLP_T), 0, P, sp, Q, sq, n, out);
@@ -377,11 +461,8 @@ void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t
 void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st) {
   LAUNCH(ks_oa_miller, dim3((unsigned)(nb * 2 * h)), dim3(SLP_T), 0, A, V, K, nb, h, F);
 }
-void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
-  for (uint64_t s = 1; s < len; s <<= 1) {
-    uint64_t per = (len + 2 * s - 1) / (2 * s);
-    LAUNCH(ks_f12_step, dim3((unsigned)(nseg * per)), dim3(SLP_T), 0, data, nseg, stride, len, s);
-  }
+void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st) {
+  if (len > 1) LAUNCH(ks_f12_tree, dim3((unsigned)(nseg * ((len + 1) / 2))), dim3(SLP_T), 0, data, nseg, stride, len, cnt);
 }
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st) {
   if (n) LAUNCH(ks_final_exp, dim3((unsigned)n), dim3(SLP_T), 0, in, stride, n, out0, out1, ostride);
@@ -389,9 +470,6 @@ void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *ou
 void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st) {
   LAUNCH(ks_oa_fold_g2, dim3((unsigned)(nb * h)), dim3(SLP_T), 0, Vin, Vout, Xinv, K, nb, h, j, lK);
-}
-void oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st) {
-  LAUNCH(ks_oa_gt_combine, dim3((unsigned)(2 * nb)), dim3(SLP_T), 0, U, P, nb, L, R, lK);
 }
 void oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
              const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
@@ -401,9 +479,19 @@ void oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64
                hipStream_t st) {
   LAUNCH(ks_oa_pterms, dim3((unsigned)(2 * nb * 8 * q)), dim3(SLP_T), 0, A, V, B, K, nb, q, F, S1);
 }
-void oa_combine_pow(const fp12 *PX, const g1_aff *PX1, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t nb,
-                    fp12 *PE, g1_jac *PM, hipStream_t st) {
-  LAUNCH(ks_oa_combine_pow, dim3((unsigned)(8 * nb)), dim3(SLP_T), 0, PX, PX1, k_even, k_odd, kstride, nb, PE, PM);
+void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st) {
+  if (n) LAUNCH(ks_gt_sqr_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, G, n, M);
+}
+void g1_dbl_mults(const g1_aff *P, uint64_t n, g1_aff *M, hipStream_t st) {
+  if (n) LAUNCH(ks_g1_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, P, n, M);
+}
+void oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1, const g1_aff *PX1m, const fe *k_even,
+                      const fe *k_odd, uint64_t kstride, uint64_t nb, fp12 *PE, g1_jac *PM, hipStream_t st) {
+  LAUNCH(ks_oa_combine_split, dim3((unsigned)(32 * nb)), dim3(SLP_T), 0, PX, PXm, PX1, PX1m, k_even, k_odd, kstride, nb, PE,
+         PM);
+}
+void oa_gt_combine8(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st) {
+  LAUNCH(ks_oa_gt_combine8, dim3((unsigned)(2 * nb)), dim3(SLP_T), 0, U, P, nb, L, R, lK);
 }
 void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1, uint64_t st1, uint64_t n1, fp12 *out1,
                 hipStream_t st) {

@@ -34,16 +34,36 @@ __device__ __forceinline__ void canon_scalar(uint32_t k[8], const fe &mont) {
   for (int i = 0; i < 8; i++) k[i] = c.l[i];
 }
 
+// Sum of each segment data[g stride + 0 .. len) into data[g stride] in one launch: a thread per
+// pair of the first level; of two sibling nodes, the one that finishes second climbs to the
+// parent (arrival counters cnt[g tree_counters(len) + ...], zero before the launch and reset
+// by their second arrival).
 template <class O>
-__global__ void __launch_bounds__(TPB) k_jac_step(jac<O> *data, uint64_t nseg, uint64_t stride, uint64_t len, uint64_t s) {
-  uint64_t per = (len + 2 * s - 1) / (2 * s);
+__global__ void __launch_bounds__(TPB) k_jac_tree(jac<O> *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt) {
+  uint64_t per = (len + 1) / 2;
   uint64_t id = gtid();
   if (id >= nseg * per) return;
   uint64_t g = id / per, q = id % per;
-  uint64_t a = 2 * s * q, b = a + s;
-  if (b >= len) return;
   jac<O> *d = data + g * stride;
-  d[a] = jac_add(d[a], d[b]);
+  uint32_t *c = cnt + g * tree_counters(len);
+  uint64_t s = 1, n = per, cb = 0;
+  for (;;) {
+    uint64_t a = 2 * s * q, b = a + s;
+    if (b < len) d[a] = jac_add(d[a], d[b]);
+    if (n == 1) return;
+    uint64_t nn = (n + 1) / 2, qp = q >> 1;
+    if ((q ^ 1) < n) {
+      __threadfence();
+      uint32_t old = atomicAdd(&c[cb + qp], 1u);
+      if (!old) return;
+      c[cb + qp] = 0;
+      __threadfence();
+    }
+    cb += nn;
+    q = qp;
+    n = nn;
+    s *= 2;
+  }
 }
 template <class O>
 __global__ void __launch_bounds__(TPB) k_jac_to_aff(const jac<O> *in, uint64_t stride, uint64_t n, aff<O> *out, uint64_t ostride) {

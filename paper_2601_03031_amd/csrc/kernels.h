@@ -7,6 +7,10 @@
 #include "tower.hpp"
 #include "curve.hpp"
 
+// Counters per segment for the one-launch reduction trees (at least the nodes of all levels
+// above the first).
+__host__ __device__ inline uint64_t tree_counters(uint64_t len) { return len + 64; }
+
 #define VC_ERRBIT_RANGE 1
 #define VC_ERRBIT_CHALLENGE 2
 
@@ -20,7 +24,8 @@ void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st);
 // input s at in[s*stride]; output to (s odd ? out1 : out0)[(s >> 1) * ostride]
-void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+// one launch; cnt: nseg tree_counters(len) zeroed counters, zero again on return
+void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st);
 void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st);
 void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st);
@@ -29,8 +34,9 @@ void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hip
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st);
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
-// L[k lK], R[k lK] = U[2k + side] + P[4k + 2 side] + P[4k + 2 side + 1] (affine)
-void oa_g1_combine(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st);
+// L[k lK], R[k lK] = U[2k + side] + sum_{g, p} P[4 (4k + g) + p] over the 8 split parts of
+// each side (affine)
+void oa_g1_combine8(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st);
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   hipStream_t st);
 void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st);
@@ -65,22 +71,27 @@ void diag_field(int which, int op, const void *a, const void *b, uint64_t n, voi
 namespace ks {
 void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t n, fp12 *out, hipStream_t st);
 void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st);
-void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
+// one launch; cnt: nseg tree_counters(len) zeroed counters, zero again on return
+void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
 void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st);
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
 void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st);
-// L[k lK], R[k lK] = U[2k + side] P[4k + 2 side] P[4k + 2 side + 1] (next-round terms, oa_terms.hpp)
-void oa_gt_combine(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st);
-// fused round kernels: G1 + G2 fold; Miller loops + G1 terms of the next round; G_T powers
-// + G1 multiples by x, x^{-1}; final exponentiations of two strided lists
+// fused round kernels: G1 + G2 fold; Miller loops + G1 terms of the next round (oa_terms.hpp);
+// final exponentiations of two strided lists
 void oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
              const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, g1_jac *S1,
                hipStream_t st);
-void oa_combine_pow(const fp12 *PX, const g1_aff *PX1, const fe *k_even, const fe *k_odd, uint64_t kstride, uint64_t nb,
-                    fp12 *PE, g1_jac *PM, hipStream_t st);
 void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1, uint64_t st1, uint64_t n1, fp12 *out1,
                 hipStream_t st);
+// time-split multiplications: M[3 s + m - 1] = G[s]^{2^{16 m}}, = 2^{32 m} P[s] (m = 1..3);
+// the split combine (4 parts per power and per G1 multiple, PE/PM[4 s + p]) and the
+// product of U with the 8 G_T parts of each side
+void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st);
+void g1_dbl_mults(const g1_aff *P, uint64_t n, g1_aff *M, hipStream_t st);
+void oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1, const g1_aff *PX1m, const fe *k_even,
+                      const fe *k_odd, uint64_t kstride, uint64_t nb, fp12 *PE, g1_jac *PM, hipStream_t st);
+void oa_gt_combine8(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st);
 }  // namespace ks

@@ -126,6 +126,10 @@ struct vc_params {
   // side streams (default priority) and fork/join events for independent phases
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev[16] = {};
+  // arrival counters of the one-launch reduction trees: zeroed once, each tree leaves its
+  // counters zero again (grow-only)
+  uint32_t *cnt = nullptr;
+  uint64_t cnt_n = 0;
 };
 
 // Step 1 takes the next round's terms ahead (oa_terms.hpp) when the batches leave the
@@ -164,6 +168,17 @@ struct vc_proofs {
   void *mem = nullptr;  // the proof bundle
   size_t o_Cj, o_C, o_Lgt, o_Rgt, o_Lg1, o_Rg1, o_X, o_Al, o_vl, o_piv, o_tree, o_rho, o_Y, o_D, o_W;
 };
+
+static int ensure_cnt(vc_params *pp, uint64_t n) {
+  if (pp->cnt_n >= n) return VC_OK;
+  if (pp->cnt) CK(hipFree(pp->cnt));
+  pp->cnt = nullptr;
+  pp->cnt_n = 0;
+  CK(hipMalloc(&pp->cnt, n * sizeof(uint32_t)));
+  CK(hipMemset(pp->cnt, 0, n * sizeof(uint32_t)));
+  pp->cnt_n = n;
+  return VC_OK;
+}
 
 static int ensure_ws(vc_params *pp, size_t need) {
   if (pp->ws_size >= need) return VC_OK;
@@ -264,6 +279,7 @@ VC_API void vc_params_free(vc_params *pp) {
   hipSetDevice(pp->device);
   if (pp->mem) hipFree(pp->mem);
   if (pp->ws) hipFree(pp->ws);
+  if (pp->cnt) hipFree(pp->cnt);
   for (auto sd : pp->side)
     if (sd) hipStreamDestroy(sd);
   for (auto ev : pp->ev)
@@ -314,7 +330,8 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   // FC.Commit: C = prod_j e(C_j, v[j]), v[j] = h[2j]
   fp12 *F = at<fp12>(ws, o_F);
   ks::miller(cm->Cj, 1, pp->h, 2, K, F, st);
-  ks::f12_reduce(F, 1, K, K, st);
+  if (int rc = ensure_cnt(pp, tree_counters(K))) { vc_commitment_free(cm); return rc; }
+  ks::f12_reduce(F, 1, K, K, pp->cnt, st);
   ks::final_exp(F, 1, 1, cm->C, nullptr, 1, st);
   uint8_t *enc = at<uint8_t>(ws, o_enc);
   kl::encode(reinterpret_cast<const fe *>(cm->C), 12, 0, enc, st);
@@ -393,10 +410,11 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   const bool ahead = lK >= 2 && nb * K <= AHEAD_MAX_PAIRS;
   const uint64_t nterm = ahead ? 2 * nb * K : 0;
   size_t o_A2 = t.take<g1_aff>(nb * K), o_V2 = t.take<g2_aff>(nb * K), o_B2 = t.take<fe>(nb * K);
-  size_t o_F2 = t.take<fp12>(nterm), o_PS = t.take<g1_jac>(nterm);
-  size_t o_PU = t.take<fp12>(ahead ? 4 * nb : 0), o_PX = t.take<fp12>(ahead ? 8 * nb : 0), o_PE = t.take<fp12>(ahead ? 4 * nb : 0);
+  size_t o_F2 = t.take<fp12>(nterm), o_PS = t.take<g1_jac>(2 * nterm);
+  size_t o_PU = t.take<fp12>(ahead ? 4 * nb : 0), o_PX = t.take<fp12>(ahead ? 8 * nb : 0);
+  size_t o_PXm = t.take<fp12>(ahead ? 24 * nb : 0), o_PE = t.take<fp12>(ahead ? 16 * nb : 0);
   size_t o_PU1 = t.take<g1_aff>(ahead ? 4 * nb : 0), o_PX1 = t.take<g1_aff>(ahead ? 8 * nb : 0);
-  size_t o_PM = t.take<g1_jac>(ahead ? 4 * nb : 0);
+  size_t o_PX1m = t.take<g1_aff>(ahead ? 24 * nb : 0), o_PM = t.take<g1_jac>(ahead ? 16 * nb : 0);
   int rc = ensure_ws(pp, t.off);
   if (rc) { vc_proofs_free(pr); return rc; }
   void *ws = pp->ws;
@@ -415,13 +433,22 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   g2_aff *Vb[2] = {V, at<g2_aff>(ws, o_V2)};
   fe *Bb[2] = {B, at<fe>(ws, o_B2)};
   fp12 *F2 = at<fp12>(ws, o_F2);
-  g1_jac *PS = at<g1_jac>(ws, o_PS);
+  g1_jac *PS[2] = {at<g1_jac>(ws, o_PS), at<g1_jac>(ws, o_PS) + nterm};
   fp12 *PU[2] = {at<fp12>(ws, o_PU), at<fp12>(ws, o_PU) + 2 * nb};
   fp12 *PX[2] = {at<fp12>(ws, o_PX), at<fp12>(ws, o_PX) + 4 * nb};
+  fp12 *PXm[2] = {at<fp12>(ws, o_PXm), at<fp12>(ws, o_PXm) + 12 * nb};
+  g1_aff *PX1m[2] = {at<g1_aff>(ws, o_PX1m), at<g1_aff>(ws, o_PX1m) + 12 * nb};
   fp12 *PE = at<fp12>(ws, o_PE);
   g1_aff *PU1[2] = {at<g1_aff>(ws, o_PU1), at<g1_aff>(ws, o_PU1) + 2 * nb};
   g1_aff *PX1[2] = {at<g1_aff>(ws, o_PX1), at<g1_aff>(ws, o_PX1) + 4 * nb};
   g1_jac *PM = at<g1_jac>(ws, o_PM);
+  // reduction-tree counters: round-1 (or every direct round) products, and per stream the
+  // U and XY groups of the terms taken ahead (F_p12 on side stream 3, G1 on the caller's)
+  const uint64_t c_dir = 2 * nb * tree_counters(K / 2), c_u = 2 * nb * tree_counters(K / 2),
+                 c_xy = 4 * nb * tree_counters(K / 4);
+  if (int rc2 = ensure_cnt(pp, c_dir + 2 * (c_u + c_xy))) { vc_proofs_free(pr); return rc2; }
+  uint32_t *cnt_dir = pp->cnt, *cnt_fu = cnt_dir + c_dir, *cnt_fxy = cnt_fu + c_u, *cnt_gu = cnt_fxy + c_xy,
+           *cnt_gxy = cnt_gu + c_u;
 
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
@@ -470,19 +497,30 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   kl::fc_r(K, b, nb, sigma, B, st);
   if (int rc2 = stream_wait(pp, 1, st, sg)) return rc2;
   if (int rc2 = stream_wait(pp, 2, st, sf)) return rc2;
-  // terms of round jn >= 2 from the arrays of round jn - 1, on side stream 3
+  // terms of round jn >= 2 from the arrays of round jn - 1, on side stream 3; their G1 sums
+  // are reduced on the caller's stream (launch_g1_sums), beside the final exponentiations.
+  // Both then take the multiples for the four-part split multiplications of the combine.
   auto launch_terms = [&](uint32_t jn) -> int {
     uint64_t q = K >> jn;
     int par = jn & 1, src = (jn - 2) & 1;
-    ks::oa_pterms(Ab[src], Vb[src], Bb[src], K, nb, q, F2, PS, sf);
-    kl::g1_reduce(PS, 2 * nb, 2 * q, 2 * q, sf);
-    kl::g1_reduce(PS + nb * 4 * q, 4 * nb, q, q, sf);
-    kl::g1_to_aff(PS, 2 * q, 2 * nb, PU1[par], 1, sf);
-    kl::g1_to_aff(PS + nb * 4 * q, q, 4 * nb, PX1[par], 1, sf);
-    ks::f12_reduce(F2, 2 * nb, 2 * q, 2 * q, sf);
-    ks::f12_reduce(F2 + nb * 4 * q, 4 * nb, q, q, sf);
+    ks::oa_pterms(Ab[src], Vb[src], Bb[src], K, nb, q, F2, PS[par], sf);
+    if (int rc2 = ev_mark(pp, 8 + par, sf)) return rc2;
+    ks::f12_reduce(F2, 2 * nb, 2 * q, 2 * q, cnt_fu, sf);
+    ks::f12_reduce(F2 + nb * 4 * q, 4 * nb, q, q, cnt_fxy, sf);
     ks::final_exp2(F2, 2 * q, 2 * nb, PU[par], F2 + nb * 4 * q, q, 4 * nb, PX[par], sf);
+    ks::gt_sqr_mults(PX[par], 4 * nb, PXm[par], sf);
     return ev_mark(pp, 6 + par, sf);
+  };
+  auto launch_g1_sums = [&](uint32_t jn) -> int {
+    uint64_t q = K >> jn;
+    int par = jn & 1;
+    if (int rc2 = ev_wait(pp, 8 + par, st)) return rc2;
+    kl::g1_reduce(PS[par], 2 * nb, 2 * q, 2 * q, cnt_gu, st);
+    kl::g1_reduce(PS[par] + nb * 4 * q, 4 * nb, q, q, cnt_gxy, st);
+    kl::g1_to_aff(PS[par], 2 * q, 2 * nb, PU1[par], 1, st);
+    kl::g1_to_aff(PS[par] + nb * 4 * q, q, 4 * nb, PX1[par], 1, st);
+    ks::g1_dbl_mults(PX1[par], 4 * nb, PX1m[par], st);
+    return VC_OK;
   };
   for (uint32_t j = 1; j <= lK; j++) {
     const uint64_t h = K >> j;
@@ -495,20 +533,18 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       if (ahead)
         if (int rc2 = launch_terms(2)) return rc2;
       ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
-      ks::f12_reduce(F, 2 * nb, K / 2, h, st);
+      ks::f12_reduce(F, 2 * nb, K / 2, h, cnt_dir, st);
       ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
       if (int rc2 = ev_wait(pp, 3, st)) return rc2;
     } else {
       // L_j, R_j from the terms taken from the arrays of round j - 1 and x_{j-1}
       const int par = j & 1;
       if (int rc2 = ev_wait(pp, 6 + par, st)) return rc2;
-      ks::oa_combine_pow(PX[par], PX1[par], X + (j - 2), Xinv + (j - 2), lK, nb, PE, PM, st);
-      ks::oa_gt_combine(PU[par], PE, nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
-      kl::oa_g1_combine(PU1[par], PM, nb, Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
+      ks::oa_combine_split(PX[par], PXm[par], PX1[par], PX1m[par], X + (j - 2), Xinv + (j - 2), lK, nb, PE, PM, st);
+      ks::oa_gt_combine8(PU[par], PE, nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
+      kl::oa_g1_combine8(PU1[par], PM, nb, Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
     }
     kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
-    if (j == 1)
-      if (int rc2 = launch_step2()) return rc2;
     // fold with x_j into the other buffer
     if (ahead) {
       if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
@@ -518,6 +554,9 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
         if (int rc2 = stream_wait(pp, 10, sg, sf)) return rc2;
         if (int rc2 = launch_terms(j + 2)) return rc2;
       }
+      // the caller's stream idles until the terms of round j + 1 are exponentiated
+      if (j + 1 <= lK)
+        if (int rc2 = launch_g1_sums(j + 1)) return rc2;
     } else {
       if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
       kl::glv_dec(X, nb, j, lK, gdec, sg);
@@ -527,6 +566,8 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
       if (int rc2 = stream_wait(pp, 12, sf, st)) return rc2;
     }
+    if (j == 1)
+      if (int rc2 = launch_step2()) return rc2;
   }
   if (ahead)
     if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
@@ -781,6 +822,8 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
   size_t o_fzg2 = c.take<g2_aff>(1), o_gtb = c.take<fp12>(2 * lK), o_gto = c.take<fp12>(2 * lK + 1);
   size_t o_Cg1 = c.take<g1_aff>(1), o_bA = c.take<g1_aff>(1), o_pp = c.take<g1_aff>(npair), o_pq = c.take<g2_aff>(npair);
   size_t o_F = c.take<fp12>(npair), o_E = c.take<fp12>(3), o_fl = c.take<int>(1);
+  // the three product trees below run one after another and share one counter area
+  if (int rc = ensure_cnt(const_cast<vc_params *>(pp), tree_counters(npair > 2 * lK + 1 ? npair : 2 * lK + 1))) return rc;
   void *d = nullptr;
   CK(hipMalloc(&d, c.off));
   VCtx x;
@@ -808,10 +851,10 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
     klw::g2_mul(pp->g2gen, 1, x.fz, 1, x.fzg2, st);
     ks::gt_pow(x.gtb, x.gts, 2 * lK, x.gto, st);
     kv::assemble(x, st);
-    ks::f12_reduce(x.gto, 1, 2 * lK + 1, 2 * lK + 1, st);
+    ks::f12_reduce(x.gto, 1, 2 * lK + 1, 2 * lK + 1, pp->cnt, st);
     ks::miller(x.pp, 1, x.pq, 1, npair, x.F, st);
-    ks::f12_reduce(x.F + 1, 1, 2, 2, st);
-    ks::f12_reduce(x.F + 3, 1, npair - 3, npair - 3, st);
+    ks::f12_reduce(x.F + 1, 1, 2, 2, pp->cnt, st);
+    ks::f12_reduce(x.F + 3, 1, npair - 3, npair - 3, pp->cnt, st);
     ks::final_exp(x.F, 1, 1, x.E, nullptr, 1, st);
     ks::final_exp(x.F + 1, 1, 1, x.E + 1, nullptr, 1, st);
     ks::final_exp(x.F + 3, 1, 1, x.E + 2, nullptr, 1, st);

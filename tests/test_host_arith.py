@@ -154,6 +154,14 @@ def test_hashes(hc):
             o = buf(32)
             hc.hc_h2f(dst.encode(), msg, len(msg), o)
             assert int.from_bytes(o.raw, "big") == O.hash_to_fr(dst, msg)
+    # the word-message form of the challenge kernels, over lengths that put the tail in
+    # one or two final blocks
+    hc.hc_h2f_words.argtypes = [C.c_char_p, C.c_char_p, C.c_uint64, C.c_void_p]
+    for nw in list(range(0, 40)) + [224, 232, 240, 248, 255, 256]:
+        msg = bytes(rng.randrange(256) for _ in range(4 * nw))
+        o = buf(32)
+        hc.hc_h2f_words(b"FLEXPROOFS-V1-FC-X", msg, len(msg), o)
+        assert int.from_bytes(o.raw, "big") == O.hash_to_fr("FLEXPROOFS-V1-FC-X", msg), nw
     m, c = bytes(range(32)), bytes(range(64, 128))
     o = buf(32)
     hc.hc_merkle_leaf(m, c, o)
@@ -341,3 +349,22 @@ def test_g1_scalar_mul_engine(hc):
         if Ab is not None:
             want = O.g1_op("add", want, Ab)
         assert o.raw == want, (k,)
+
+
+def test_split_multiplications(hc):
+    """The time-split forms used to run a multiplication in parallel parts: k P as
+    sum_t chunk_t(k) (2^{32 t} P) over the GLV split, and g^k as prod_t of the Frobenius-split
+    chunks of g^{2^{16 t}}; both equal the oracle's k P and g^k."""
+    g1, g2 = O.generators()
+    rng = random.Random(27)
+    for k in [0, 1, R - 1, 2**32, 2**64 + 5] + [rng.randrange(R) for _ in range(12)]:
+        Pt = O.g1_op("mul", g1, O.be32(rng.randrange(1, R)))
+        o = buf(64)
+        assert hc.hc_g1_mul_split(Pt, k.to_bytes(32, "big"), o) == 0
+        assert o.raw == O.g1_op("mul", Pt, O.be32(k)), k
+    for trial in range(2):
+        g = O.pairing([O.g1_op("mul", g1, O.be32(rng.randrange(1, R)))], [g2])
+        for k in ([0, 1, R - 1, 2**16] if trial == 0 else [rng.randrange(R) for _ in range(4)]):
+            o = buf(384)
+            assert hc.hc_gt_pow_split(g, k.to_bytes(32, "big"), o) == 0
+            assert o.raw == O.fp12_op("pow", g, O.be32(k)), k
