@@ -31,6 +31,47 @@ template <class Ctx> __host__ __device__ inline bool add_degenerate(Ctx &c, bool
   return h;
 }
 
+// T += A (affine, at abase); inf says whether T is the identity, and is updated
+template <class Ctx> __host__ __device__ inline void add_affine(Ctx &c, bool &inf, int abase, const f29 &one) {
+  if (inf) {
+    load_affine(c, abase, one);
+    inf = false;
+    return;
+  }
+  c.run(slp::PROG_G1_MADD, 0, abase, 0);
+  bool dbl;
+  if (add_degenerate(c, dbl)) {
+    c.sync();
+    if (dbl) {
+      load_affine(c, abase, one);
+      c.run(slp::PROG_G1_DBL, 0, 0, 0);
+    } else {
+      inf = true;
+    }
+  }
+}
+
+// T += A (Jacobian, at abase; ainf when it is the identity); inf as in add_affine
+template <class Ctx> __host__ __device__ inline void add_jac(Ctx &c, bool &inf, int abase, bool ainf) {
+  if (ainf) return;
+  if (inf) {
+    copy3(c, slp::G1_T_0, abase);
+    inf = false;
+    return;
+  }
+  c.run(slp::PROG_G1_ADD, 0, abase, 0);
+  bool dbl;
+  if (add_degenerate(c, dbl)) {
+    c.sync();
+    if (dbl) {
+      copy3(c, slp::G1_T_0, abase);
+      c.run(slp::PROG_G1_DBL, 0, 0, 0);
+    } else {
+      inf = true;
+    }
+  }
+}
+
 // P (affine) must be in slots xP, yP and the constants loaded; A (affine) at abase when
 // has_a.  Leaves k P + A in T (Jacobian) and returns true when the result is the identity.
 template <class Ctx>
@@ -73,24 +114,7 @@ __host__ __device__ inline bool mul_add(Ctx &c, const glv::Dec &dec, bool pinf, 
       }
     }
   }
-  if (has_a) {
-    if (inf) {
-      load_affine(c, abase, one);
-      inf = false;
-    } else {
-      c.run(slp::PROG_G1_MADD, 0, abase, 0);
-      bool dbl;
-      if (add_degenerate(c, dbl)) {
-        c.sync();
-        if (dbl) {
-          load_affine(c, abase, one);
-          c.run(slp::PROG_G1_DBL, 0, 0, 0);
-        } else {
-          inf = true;
-        }
-      }
-    }
-  }
+  if (has_a) add_affine(c, inf, abase, one);
   return inf;
 }
 

@@ -49,6 +49,48 @@ template <class Ctx> __host__ __device__ inline bool add_degenerate(Ctx &c, bool
   return h;
 }
 
+// T += A (affine, at abase); inf says whether T is the identity, and is updated
+template <class Ctx>
+__host__ __device__ inline void add_affine(Ctx &c, bool &inf, int abase, const f29 &one, const f29 &zero) {
+  if (inf) {
+    load_affine(c, abase, one, zero);
+    inf = false;
+    return;
+  }
+  c.run(slp::PROG_G2_MADD, 0, abase, 0);
+  bool dbl;
+  if (add_degenerate(c, dbl)) {
+    c.sync();
+    if (dbl) {
+      load_affine(c, abase, one, zero);
+      c.run(slp::PROG_G2_DBL, 0, 0, 0);
+    } else {
+      inf = true;
+    }
+  }
+}
+
+// T += A (Jacobian, at abase; ainf when it is the identity); inf as in add_affine
+template <class Ctx> __host__ __device__ inline void add_jac(Ctx &c, bool &inf, int abase, bool ainf) {
+  if (ainf) return;
+  if (inf) {
+    copy_slots(c, slp::G2_T_0, abase, 6);
+    inf = false;
+    return;
+  }
+  c.run(slp::PROG_G2_ADD, 0, abase, 0);
+  bool dbl;
+  if (add_degenerate(c, dbl)) {
+    c.sync();
+    if (dbl) {
+      copy_slots(c, slp::G2_T_0, abase, 6);
+      c.run(slp::PROG_G2_DBL, 0, 0, 0);
+    } else {
+      inf = true;
+    }
+  }
+}
+
 // Q (affine) must be in slots xQ, yQ and the constants loaded; A (affine) at abase when
 // has_a.  Leaves k Q + A in T (Jacobian) and returns true when the result is the identity.
 template <class Ctx>
@@ -90,24 +132,7 @@ __host__ __device__ inline bool mul_add(Ctx &c, const gls::Dec &dec, bool qinf, 
       }
     }
   }
-  if (has_a) {
-    if (inf) {
-      load_affine(c, abase, one, zero);
-      inf = false;
-    } else {
-      c.run(slp::PROG_G2_MADD, 0, abase, 0);
-      bool dbl;
-      if (add_degenerate(c, dbl)) {
-        c.sync();
-        if (dbl) {
-          load_affine(c, abase, one, zero);
-          c.run(slp::PROG_G2_DBL, 0, 0, 0);
-        } else {
-          inf = true;
-        }
-      }
-    }
-  }
+  if (has_a) add_affine(c, inf, abase, one, zero);
   return inf;
 }
 

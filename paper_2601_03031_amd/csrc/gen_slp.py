@@ -996,6 +996,12 @@ def g1_programs():
     p.out("H", H)
     p.out("RR", r)
     progs[p.name] = p
+    p = Prog("g1_add")
+    T, H, r = j_add(g1_jin(p, "T"), g1_jin(p, "A"))
+    g1_jout(p, "T", T)
+    p.out("H", H)
+    p.out("RR", r)
+    progs[p.name] = p
     p = Prog("g1_madd")
     T, H, r = j_madd(g1_jin(p, "T"), (p.inp("A.0"), p.inp("A.1")))
     g1_jout(p, "T", T)
@@ -1766,6 +1772,11 @@ def check_g1(g1k, rng):
         run_levels(g1k.progs["g1_dbl2_add"], S, (0, 0, st["TB7.0"], 0, 0, 0, 0, 0))
         T32 = g1_aff_add(g1_aff_mul(Pt, 32), getj(S, "TB7"))
         assert getj(S, "T") == T32, "dbl2_add"
+        # Jacobian addition with a Jacobian operand (Z != 1)
+        Sj = list(S)
+        setj(Sj, "T", g1_aff_mul(Pt, 5))
+        run_levels(g1k.progs["g1_add"], Sj, (0, 0, st["TB6.0"], 0, 0, 0, 0, 0))
+        assert getj(Sj, "T") == g1_aff_add(g1_aff_mul(Pt, 5), getj(S, "TB6")), "add"
         A = g1_aff_mul((1, 2), rng.randrange(1, R))
         Sa = list(S) + [A[0], A[1]]
         run_levels(g1k.progs["g1_madd"], Sa, (0, 0, len(S), 0, 0, 0, 0, 0))

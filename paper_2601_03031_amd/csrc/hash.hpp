@@ -178,16 +178,38 @@ inline NOINL fe xmd_finish_fr(Hasher &hs, const char *dst) {
   return fr_add(fr_mul(hi, fe_const(bn::R_R3)), fr_mul(lo, fe_const(bn::R_R2)));
 }
 
-// ---- the same hashes for a message that every lane of the wavefront holds (word-aligned
-// prefix in LDS plus a short byte tail): on the device the values are made explicitly
-// uniform so that the compression runs on the scalar unit
+// ---- the same hashes for a message that a workgroup builds together in shared memory:
+// the message is kept as big-endian 32-bit words, lanes write its pieces and the padding
+// in parallel, and every lane then runs the compression on the same words (plain vector
+// code, no per-lane message state).  Coop gives the lane index, the lane count and the
+// barrier; the host model runs it as one lane.
+struct Coop {
+  int lane, n;
 #ifdef __HIP_DEVICE_COMPILE__
-__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+  __device__ void sync() const { __syncthreads(); }
 #else
-HD inline uint32_t uni32(uint32_t x) { return x; }
+  HD void sync() const {}
 #endif
+};
 
-HD inline void compress_u(uint32_t h[8], const uint32_t blk[16]) {
+// byte pos of a message held as big-endian words
+HD inline void put_byte(uint32_t *w, uint32_t pos, uint32_t v) {
+  reinterpret_cast<uint8_t *>(w)[(pos & ~3u) | (3u - (pos & 3u))] = (uint8_t)v;
+}
+
+// canonical big-endian words of a Montgomery-form element
+template <class F> HD inline void put_words(uint32_t *dst, const fe &a) {
+  fe c = f_from_mont<F>(a);
+  for (int i = 0; i < 8; i++) dst[i] = fe_word(c, 7 - i);
+}
+
+// the same at byte offset pos (any alignment)
+template <class F> HD inline void put_field_bytes(uint32_t *w, uint32_t pos, const fe &a) {
+  fe c = f_from_mont<F>(a);
+  for (int i = 0; i < 32; i++) put_byte(w, pos + i, fe_word(c, 7 - i / 4) >> (24 - 8 * (i & 3)));
+}
+
+HD inline void compress_inl(uint32_t h[8], const uint32_t *blk) {
   uint32_t w[16];
 #pragma unroll
   for (int i = 0; i < 16; i++) w[i] = blk[i];
@@ -221,86 +243,81 @@ HD inline void compress_u(uint32_t h[8], const uint32_t blk[16]) {
   h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
 }
 
-// SHA-256 of (words[0 .. nw) as big-endian words, in LDS) || tail[0 .. tlen) (tlen < 64);
-// every lane calls it with the same arguments; tlen <= 64 + 4 (nw mod 16) - 9
-HD inline void sha_words_u(const uint32_t *words, int nw, const uint8_t *tail, int tlen, uint32_t out[8]) {
-  uint32_t h[8], blk[16];
-#pragma unroll
-  for (int i = 0; i < 8; i++) h[i] = H0[i];
-  int full = nw / 16;
-  for (int bI = 0; bI < full; bI++) {
-#pragma unroll
-    for (int i = 0; i < 16; i++) blk[i] = uni32(words[16 * bI + i]);
-    compress_u(h, blk);
+// SHA-256 padding of a len-byte message in w (bytes from len on are overwritten); returns
+// the number of blocks.  The caller synchronizes before the blocks are read.
+HD inline int pad_coop(const Coop &cp, uint32_t *w, uint32_t len) {
+  uint32_t nblk = (len + 8) / 64 + 1, end = 64 * nblk;
+  uint64_t bits = (uint64_t)len * 8;
+  for (uint32_t p = len + cp.lane; p < end; p += cp.n) {
+    uint32_t v = p == len ? 0x80u : p >= end - 8 ? (uint32_t)(bits >> (8 * (end - 1 - p))) & 0xffu : 0u;
+    put_byte(w, p, v);
   }
-  // remaining words, the tail bytes, 0x80, zeros and the bit length (one or two blocks)
-  uint8_t rest[128];
-  int r = 0;
-  for (int i = 16 * full; i < nw; i++) {
-    uint32_t v = uni32(words[i]);
-    rest[r++] = (uint8_t)(v >> 24); rest[r++] = (uint8_t)(v >> 16); rest[r++] = (uint8_t)(v >> 8); rest[r++] = (uint8_t)v;
-  }
-  for (int i = 0; i < tlen; i++) rest[r++] = tail[i];
-  uint64_t bits = ((uint64_t)nw * 4 + (uint64_t)tlen) * 8;
-  rest[r++] = 0x80;
-  int nblk = r + 8 <= 64 ? 1 : 2;
-  while (r < 64 * nblk - 8) rest[r++] = 0;
-  for (int i = 7; i >= 0; i--) rest[r++] = (uint8_t)(bits >> (8 * i));
-  for (int bI = 0; bI < nblk; bI++) {
+  return (int)nblk;
+}
+
+// keeps a value in a vector register: the compression then runs as plain vector code (with
+// its rotate, three-input add and xor, and bit-select instructions) instead of alternating
+// between the vector and scalar units
+#ifdef __HIP_DEVICE_COMPILE__
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+#else
+HD inline uint32_t in_vgpr(uint32_t x) { return x; }
+#endif
+
+// digest of the nblk padded blocks in w
+HD inline void digest_blocks(const uint32_t *w, int nblk, uint32_t out[8]) {
+  uint32_t h[8];
+  for (int i = 0; i < 8; i++) h[i] = in_vgpr(H0[i]);
+  for (int b = 0; b < nblk; b++) {
+    uint32_t blk[16];
 #pragma unroll
-    for (int i = 0; i < 16; i++)
-      blk[i] = (uint32_t)rest[64 * bI + 4 * i] << 24 | (uint32_t)rest[64 * bI + 4 * i + 1] << 16 |
-               (uint32_t)rest[64 * bI + 4 * i + 2] << 8 | rest[64 * bI + 4 * i + 3];
-    compress_u(h, blk);
+    for (int i = 0; i < 16; i++) blk[i] = in_vgpr(w[16 * b + i]);
+    compress_inl(h, blk);
   }
-#pragma unroll
   for (int i = 0; i < 8; i++) out[i] = h[i];
 }
 
-// hash_to_field to F_r (Montgomery form) of msg = words[16 .. nw), where words[0 .. 16) must
-// hold the 64 zero bytes Z_pad of expand_message_xmd (L = 48); same result as Hasher with
-// xmd_begin / xmd_finish_fr (the DST has at most 30 bytes)
-HD inline fe xmd_fr_words_u(const uint32_t *words, int nw, const char *dst) {
-  int dlen = cstrlen(dst);
-  uint8_t tail[64];
-  int r = 0;
-  tail[r++] = 0; tail[r++] = 48; tail[r++] = 0;
-  for (int i = 0; i < dlen; i++) tail[r++] = (uint8_t)dst[i];
-  tail[r++] = (uint8_t)dlen;
+// SHA-256 of the len-byte message in w (room for the padding behind it required); the
+// message must be complete (and synchronized) when called; every lane gets the digest
+HD inline void sha_coop(const Coop &cp, uint32_t *w, uint32_t len, uint32_t out[8]) {
+  int nblk = pad_coop(cp, w, len);
+  cp.sync();
+  digest_blocks(w, nblk, out);
+}
+
+// hash_to_field to F_r (Montgomery form) of the mlen-byte message at byte 64 of w, whose
+// first 16 words must be zero (Z_pad of expand_message_xmd, L = 48); w needs room for
+// 64 + mlen + the DST suffix + padding (mlen + 64 + 4 + |DST| + 72 bytes), t2 for one
+// block; |DST| <= 21.  Same result as Hasher with xmd_begin / xmd_finish_fr.  The message
+// must be complete (and synchronized) when called.
+HD inline fe xmd_fr_coop(const Coop &cp, uint32_t *w, uint32_t mlen, const char *dst, uint32_t *t2) {
+  const uint32_t dlen = (uint32_t)cstrlen(dst), p = 64 + mlen;
+  // suffix I2OSP(48, 2) || I2OSP(0, 1) || DST || I2OSP(dlen, 1), then padding
+  for (uint32_t i = cp.lane; i < 4 + dlen; i += cp.n)
+    put_byte(w, p + i, i == 1 ? 48u : (i == 0 || i == 2) ? 0u : i < 3 + dlen ? (uint32_t)(uint8_t)dst[i - 3] : dlen);
   uint32_t b0[8], b1[8], b2[8];
-  sha_words_u(words, nw, tail, r, b0);
-  // b1 = H(b0 || 1 || DST'), b2 = H((b0 xor b1) || 2 || DST')
-  uint32_t wb[8];
-  for (int i = 0; i < 8; i++) wb[i] = b0[i];
-  uint8_t t2[64];
-  int r2 = 0;
-  for (int i = 0; i < 8; i++) { t2[r2++] = (uint8_t)(wb[i] >> 24); t2[r2++] = (uint8_t)(wb[i] >> 16); t2[r2++] = (uint8_t)(wb[i] >> 8); t2[r2++] = (uint8_t)wb[i]; }
-  t2[r2++] = 1;
-  for (int i = 0; i < dlen; i++) t2[r2++] = (uint8_t)dst[i];
-  t2[r2++] = (uint8_t)dlen;
-  sha_words_u(nullptr, 0, t2, r2, b1);
-  r2 = 0;
-  for (int i = 0; i < 8; i++) {
-    uint32_t v = b0[i] ^ b1[i];
-    t2[r2++] = (uint8_t)(v >> 24); t2[r2++] = (uint8_t)(v >> 16); t2[r2++] = (uint8_t)(v >> 8); t2[r2++] = (uint8_t)v;
-  }
-  t2[r2++] = 2;
-  for (int i = 0; i < dlen; i++) t2[r2++] = (uint8_t)dst[i];
-  t2[r2++] = (uint8_t)dlen;
-  sha_words_u(nullptr, 0, t2, r2, b2);
+  sha_coop(cp, w, p + 4 + dlen, b0);
+  // b1 = H(b0 || 1 || DST || dlen), b2 = H((b0 xor b1) || 2 || DST || dlen): one block each
+  for (int i = 0; i < 8; i++)
+    if (i % cp.n == cp.lane) t2[i] = b0[i];
+  for (uint32_t i = cp.lane; i < 2 + dlen; i += cp.n)
+    put_byte(t2, 32 + i, i == 0 ? 1u : i <= dlen ? (uint32_t)(uint8_t)dst[i - 1] : dlen);
+  sha_coop(cp, t2, 34 + dlen, b1);
+  cp.sync();
+  for (int i = 0; i < 8; i++)
+    if (i % cp.n == cp.lane) t2[i] = b0[i] ^ b1[i];
+  if (cp.lane == 0) put_byte(t2, 32, 2);
+  cp.sync();
+  digest_blocks(t2, 1, b2);
   uint32_t hw[8], lw[8];
   for (int i = 0; i < 4; i++) { hw[i] = b1[3 - i]; hw[4 + i] = 0; }
   for (int i = 0; i < 4; i++) lw[i] = b2[3 - i];
   for (int i = 0; i < 4; i++) lw[4 + i] = b1[7 - i];
   fe hi = fe_from_words(hw), lo = fe_from_words(lw);
   return fr_add(fr_mul(hi, fe_const(bn::R_R3)), fr_mul(lo, fe_const(bn::R_R2)));
-}
-
-// canonical big-endian words of a Montgomery-form element, written by one lane
-template <class F> HD inline void put_words(uint32_t *dst, const fe &a) {
-  fe c = f_from_mont<F>(a);
-#pragma unroll
-  for (int i = 0; i < 8; i++) dst[i] = fe_word(c, 7 - i);
 }
 
 // Merkle leaf SHA-256(0x00 || m_i || C_j): m given as 8 BE words, C as 16 BE words

@@ -180,17 +180,24 @@ API void hc_h2f(const char *dst, const uint8_t *msg, uint64_t len, uint8_t *out)
   wr<FpR>(out, sha::xmd_finish_fr(h, dst));
 }
 
-// the word-message form (Z_pad and msg as big-endian words, len a multiple of 4, at most
-// 1024 bytes) used by the challenge kernels
-API void hc_h2f_words(const char *dst, const uint8_t *msg, uint64_t len, uint8_t *out) {
-  uint32_t w[16 + 256];
-  int nw = 16 + (int)(len / 4);
+// the cooperative form used by the challenge kernels (one lane here): msg (len bytes, at
+// most 1024) after Z_pad
+API void hc_h2f_coop(const char *dst, const uint8_t *msg, uint64_t len, uint8_t *out) {
+  static uint32_t w[16 + 256 + 32], t2[16];
   for (int i = 0; i < 16; i++) w[i] = 0;
-  for (int i = 16; i < nw; i++) {
-    const uint8_t *q = msg + 4 * (i - 16);
-    w[i] = (uint32_t)q[0] << 24 | (uint32_t)q[1] << 16 | (uint32_t)q[2] << 8 | q[3];
+  for (uint64_t i = 0; i < len; i++) sha::put_byte(w, 64 + (uint32_t)i, msg[i]);
+  wr<FpR>(out, sha::xmd_fr_coop(sha::Coop{0, 1}, w, (uint32_t)len, dst, t2));
+}
+
+// SHA-256 through the cooperative form (len at most 1024)
+API void hc_sha256_coop(const uint8_t *msg, uint64_t len, uint8_t *out) {
+  static uint32_t w[256 + 32];
+  for (uint64_t i = 0; i < len; i++) sha::put_byte(w, (uint32_t)i, msg[i]);
+  uint32_t o[8];
+  sha::sha_coop(sha::Coop{0, 1}, w, (uint32_t)len, o);
+  for (int i = 0; i < 8; i++) {
+    out[4 * i] = o[i] >> 24; out[4 * i + 1] = o[i] >> 16; out[4 * i + 2] = o[i] >> 8; out[4 * i + 3] = o[i];
   }
-  wr<FpR>(out, sha::xmd_fr_words_u(w, nw, dst));
 }
 
 API void hc_sha256(const uint8_t *msg, uint64_t len, uint8_t *out) {
@@ -406,6 +413,102 @@ API int hc_g1_mul_split(const uint8_t *Pb, const uint8_t *kb, uint8_t *out) {
     }
   }
   wrg1(out, jac_to_aff(acc));
+  return 0;
+}
+
+// The split fold on the engine (host model), as the GPU runs it: multiples 2^{32 t} P by
+// repeated double doublings, the four chunked multiplications into Jacobian partials, then
+// their sum in the table slots plus A (affine; may be null or the identity).  Out affine.
+API int hc_fold_split_g1(const uint8_t *Pb, const uint8_t *kb, const uint8_t *Ab, uint8_t *out) {
+  static slp::f29 S[slp::G1_NSLOT + 2];
+  g1_aff P = rdg1(Pb);
+  fe k = rd_raw(kb);
+  glv::Dec dec = glv::decompose(k.l);
+  slp::HostCtx c{S};
+  fe part[4][3];
+  bool pinf[4];
+  for (int t = 0; t < 4; t++) {
+    ld_consts(S, slp::G1_CBASE, slp::G1_CONSTS, slp::G1_NCONST);
+    g1_aff base = P;
+    if (t && !aff_is_inf(P)) {
+      S[slp::G1_T_0] = slp::to29(P.x);
+      S[slp::G1_T_1] = slp::to29(P.y);
+      S[slp::G1_T_2] = slp::to29(f_one<FpP>());
+      for (int i = 0; i < 16 * t; i++) c.run(slp::PROG_G1_DBL2, 0, 0, 0);
+      S[slp::G1_tinv] = slp::to29(fp_inv_fast(slp::from29(slp::canon29(S[slp::G1_T_2]))));
+      c.run(slp::PROG_G1_AFF, 0, 0, 0);
+      base = {slp::from29(slp::canon29(S[slp::G1_ax])), slp::from29(slp::canon29(S[slp::G1_ay]))};
+    }
+    S[slp::G1_xP] = slp::to29(base.x);
+    S[slp::G1_yP] = slp::to29(base.y);
+    pinf[t] = g1m::mul_add(c, glv::chunk(dec, t), aff_is_inf(base), false, slp::G1_NSLOT, S[slp::G1_CBASE + 1]);
+    for (int q = 0; q < 3; q++)
+      part[t][q] = pinf[t] ? (q < 2 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::G1_T_0 + q]));
+  }
+  for (int t = 0; t < 4; t++)
+    for (int q = 0; q < 3; q++) S[slp::G1_TB1_0 + 3 * t + q] = slp::to29(part[t][q]);
+  bool inf = true;
+  for (int t = 0; t < 4; t++) g1m::add_jac(c, inf, slp::G1_TB1_0 + 3 * t, fe_is_zero(part[t][2]));
+  if (Ab) {
+    g1_aff A = rdg1(Ab);
+    S[slp::G1_NSLOT] = slp::to29(A.x);
+    S[slp::G1_NSLOT + 1] = slp::to29(A.y);
+    if (!aff_is_inf(A)) g1m::add_affine(c, inf, slp::G1_NSLOT, S[slp::G1_CBASE + 1]);
+  }
+  if (inf) { memset(out, 0, 64); return 0; }
+  S[slp::G1_tinv] = slp::to29(fp_inv_fast(slp::from29(slp::canon29(S[slp::G1_T_2]))));
+  c.run(slp::PROG_G1_AFF, 0, 0, 0);
+  g1_aff r{slp::from29(slp::canon29(S[slp::G1_ax])), slp::from29(slp::canon29(S[slp::G1_ay]))};
+  wrg1(out, r);
+  return 0;
+}
+
+// the same for G2: multiples 2^{16 t} Q, bits [16 t, 16 t + w_t) of the GLS split
+API int hc_fold_split_g2(const uint8_t *Qb, const uint8_t *kb, const uint8_t *Ab, uint8_t *out) {
+  static slp::f29 S[slp::G2_NSLOT + 4];
+  g2_aff Q = rdg2(Qb);
+  fe k = rd_raw(kb);
+  gls::Dec dec = gls::decompose(k.l);
+  slp::HostCtx c{S};
+  fe part[4][6];
+  for (int t = 0; t < 4; t++) {
+    ld_consts(S, slp::G2_CBASE, slp::G2_CONSTS, slp::G2_NCONST);
+    g2_aff base = Q;
+    const fe *q = reinterpret_cast<const fe *>(&Q);
+    if (t && !aff_is_inf(Q)) {
+      for (int i = 0; i < 6; i++) S[slp::G2_T_0 + i] = slp::to29(i < 4 ? q[i] : i == 4 ? f_one<FpP>() : fe_zero());
+      for (int i = 0; i < 16 * t; i++) c.run(slp::PROG_G2_DBL, 0, 0, 0);
+      c.run(slp::PROG_G2_NORM, 0, 0, 0);
+      S[slp::G2_tinv] = slp::to29(fp_inv_fast(slp::from29(slp::canon29(S[slp::G2_t]))));
+      c.run(slp::PROG_G2_AFF, 0, 0, 0);
+      fe *bw = reinterpret_cast<fe *>(&base);
+      for (int i = 0; i < 4; i++) bw[i] = slp::from29(slp::canon29(S[slp::G2_ax_0 + i]));
+    }
+    const fe *bq = reinterpret_cast<const fe *>(&base);
+    for (int i = 0; i < 4; i++) S[slp::G2_xQ_0 + i] = slp::to29(bq[i]);
+    bool pinf = g2m::mul_add(c, gls::chunk(dec, 16 * t, t < 3 ? 16 : 17), aff_is_inf(base), false, slp::G2_NSLOT,
+                             S[slp::G2_CBASE + 1], S[slp::G2_CBASE]);
+    for (int i = 0; i < 6; i++)
+      part[t][i] = pinf ? ((i == 0 || i == 2) ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::G2_T_0 + i]));
+  }
+  for (int t = 0; t < 4; t++)
+    for (int i = 0; i < 6; i++) S[slp::G2_TB1_0 + 6 * t + i] = slp::to29(part[t][i]);
+  bool inf = true;
+  for (int t = 0; t < 4; t++) g2m::add_jac(c, inf, slp::G2_TB1_0 + 6 * t, fe_is_zero(part[t][4]) && fe_is_zero(part[t][5]));
+  if (Ab) {
+    g2_aff A = rdg2(Ab);
+    const fe *a = reinterpret_cast<const fe *>(&A);
+    for (int i = 0; i < 4; i++) S[slp::G2_NSLOT + i] = slp::to29(a[i]);
+    if (!aff_is_inf(A)) g2m::add_affine(c, inf, slp::G2_NSLOT, S[slp::G2_CBASE + 1], S[slp::G2_CBASE]);
+  }
+  if (inf) { memset(out, 0, 128); return 0; }
+  c.run(slp::PROG_G2_NORM, 0, 0, 0);
+  S[slp::G2_tinv] = slp::to29(fp_inv_fast(slp::from29(slp::canon29(S[slp::G2_t]))));
+  c.run(slp::PROG_G2_AFF, 0, 0, 0);
+  g2_aff r;
+  fe *rw = reinterpret_cast<fe *>(&r);
+  for (int i = 0; i < 4; i++) rw[i] = slp::from29(slp::canon29(S[slp::G2_ax_0 + i]));
+  wrg2(out, r);
   return 0;
 }
 

@@ -205,6 +205,9 @@ void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t 
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st) {
   if (len > 1) L1(k_jac_tree<OpsG1>, nseg * ((len + 1) / 2), data, nseg, stride, len, cnt);
 }
+void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint64_t ostride, hipStream_t st) {
+  L1(k_jac_to_aff<OpsG2>, n, in, stride, n, out, ostride);
+}
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st) {
   L1(k_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);
 }

@@ -23,53 +23,80 @@ __global__ void __launch_bounds__(TPB) k_trapdoor(const uint8_t *seed, uint32_t 
   }
 }
 
-// chunk digests of the batch statement: H_q over (a_i || enc(C_{a_i})) for 32 entries
-__global__ void __launch_bounds__(TPB) k_fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq) {
-  uint64_t id = gtid();
+// chunk digests of the batch statement: H_q over (a_i || enc(C_{a_i})) for 32 entries; a
+// workgroup of 64 per chunk, one lane per entry writes the message words (sha::Coop)
+__global__ void __launch_bounds__(64) k_fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq) {
+  __shared__ uint32_t msg[FC_CHUNK * 18 + 18];
+  uint64_t id = blockIdx.x;
   uint64_t qmax = (b + FC_CHUNK - 1) / FC_CHUNK;
   if (id >= nb * qmax) return;
   uint64_t k = id / qmax, q = id % qmax;
   uint64_t lo = k * b, hi = (lo + b < K) ? lo + b : K;
   uint64_t s = lo + q * FC_CHUNK;
   if (s >= hi) return;
-  uint64_t e = (s + FC_CHUNK < hi) ? s + FC_CHUNK : hi;
-  sha::Hasher hs;
-  hs.init();
-  for (uint64_t a = s; a < e; a++) {
-    hs.u64(a);
-    hs.g1(Cj[a]);
+  int n = (int)(((s + FC_CHUNK < hi) ? s + FC_CHUNK : hi) - s);
+  const int t = threadIdx.x;
+  if (t < n) {
+    uint64_t a = s + t;
+    msg[18 * t] = (uint32_t)(a >> 32);
+    msg[18 * t + 1] = (uint32_t)a;
+    sha::put_words<FpP>(msg + 18 * t + 2, Cj[a].x);
+    sha::put_words<FpP>(msg + 18 * t + 10, Cj[a].y);
   }
-  hs.final(Hq + id * 8);
+  __syncthreads();
+  uint32_t out[8];
+  sha::sha_coop(sha::Coop{t, 64}, msg, 72u * n, out);
+  if (t == 0)
+    for (int w = 0; w < 8; w++) Hq[id * 8 + w] = out[w];
 }
 
-// sigma_k and r_i = H2F(DST_FC_R, sigma_k || i); the sparse exponent vector b = sum r_i u_{a_i}
-__global__ void __launch_bounds__(TPB) k_fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma) {
-  uint64_t k = gtid();
+// sigma_k = SHA-256(DST_FC_R || enc(C) || t || H_0 || H_1 ...), a workgroup of 64 per batch
+// (message in dynamic shared memory, fc_sigma_shm bytes)
+__host__ __device__ inline size_t fc_sigma_shm(uint32_t b) {
+  return ((410 + 32 * (size_t)((b + FC_CHUNK - 1) / FC_CHUNK) + 72 + 3) / 4) * 4;
+}
+__global__ void __launch_bounds__(64) k_fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq,
+                                                uint32_t *sigma) {
+  extern __shared__ uint32_t mw[];
+  uint64_t k = blockIdx.x;
   if (k >= nb) return;
+  const int t = threadIdx.x;
   uint64_t qmax = (b + FC_CHUNK - 1) / FC_CHUNK;
   uint64_t lo = k * b, hi = (lo + b < K) ? lo + b : K;
-  uint64_t t = hi - lo;
-  sha::Hasher hs;
-  hs.init();
-  hs.str(DSTR_FC_R);
-  hs.gt(*C);
-  hs.u64(t);
-  for (uint64_t q = 0; q * FC_CHUNK < t; q++)
-    for (int w = 0; w < 8; w++) hs.word(Hq[(k * qmax + q) * 8 + w]);
-  hs.final(sigma + k * 8);
+  uint64_t cnt = hi - lo, nq = (cnt + FC_CHUNK - 1) / FC_CHUNK;
+  const char *dst = DSTR_FC_R;
+  const uint32_t dl = (uint32_t)sha::cstrlen(dst);
+  if ((uint32_t)t < dl) sha::put_byte(mw, t, (uint8_t)dst[t]);
+  if (t < 12) sha::put_field_bytes<FpP>(mw, dl + 32 * t, reinterpret_cast<const fe *>(C)[t]);
+  if (t >= 12 && t < 20) sha::put_byte(mw, dl + 384 + (t - 12), (uint32_t)(cnt >> (8 * (19 - t))) & 0xff);
+  const uint32_t off = dl + 392;
+  for (uint64_t w = t; w < 8 * nq; w += 64) {
+    uint32_t v = Hq[k * qmax * 8 + w];
+    for (int i = 0; i < 4; i++) sha::put_byte(mw, off + 4 * (uint32_t)w + i, v >> (24 - 8 * i));
+  }
+  __syncthreads();
+  uint32_t out[8];
+  sha::sha_coop(sha::Coop{t, 64}, mw, off + 32 * (uint32_t)nq, out);
+  if (t == 0)
+    for (int w = 0; w < 8; w++) sigma[k * 8 + w] = out[w];
 }
 
-__global__ void __launch_bounds__(TPB) k_fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B) {
-  uint64_t id = gtid();
+// r_i = H2F(DST_FC_R, sigma_k || i), a workgroup of 64 per entry: the sparse exponent
+// vector b = sum r_i u_{a_i}
+__global__ void __launch_bounds__(64) k_fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B) {
+  __shared__ uint32_t w[16 + 10 + 32], t2[16];
+  uint64_t id = blockIdx.x;
   if (id >= nb * (uint64_t)b) return;
   uint64_t k = id / b, i = id % b;
   uint64_t a = k * b + i;
   if (a >= K) return;
-  sha::Hasher hs;
-  sha::xmd_begin(hs);
-  for (int w = 0; w < 8; w++) hs.word(sigma[k * 8 + w]);
-  hs.u64(i);
-  B[k * K + a] = sha::xmd_finish_fr(hs, DSTR_FC_R);
+  const int t = threadIdx.x;
+  if (t < 16) w[t] = 0;
+  else if (t < 24) w[t] = sigma[k * 8 + t - 16];
+  else if (t < 26) w[t] = t == 24 ? (uint32_t)(i >> 32) : (uint32_t)i;
+  __syncthreads();
+  fe r = sha::xmd_fr_coop(sha::Coop{t, 64}, w, 40, DSTR_FC_R, t2);
+  if (t == 0) B[k * K + a] = r;
 }
 
 // affine G1 parts of L_j, R_j from the reduced term sums, one thread per (batch, side)
@@ -100,13 +127,13 @@ __global__ void __launch_bounds__(8) k_oa_g1_combine8(const g1_aff *U, const g1_
   if (t == 0) (side ? R : L)[k * lK] = jac_to_aff(jac_madd(part[0], U[id]));
 }
 
-// per batch: hash L_j, R_j into x_j, keep x_j and 1/x_j.  A workgroup of 64 per batch: lanes
-// encode the 28 coordinates (and x_{j-1}) in parallel into LDS, then all lanes hash the
-// uniform message on the scalar unit and invert x_j there.
+// per batch: hash L_j, R_j into x_j, keep x_j and 1/x_j.  A workgroup of 64 per batch:
+// lanes encode x_{j-1} and the 28 coordinates of L_j, R_j in parallel (sha::Coop), and the
+// inverse runs on the scalar unit.
 __global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j,
                                                      uint32_t lK, const g1_aff *Lg1, const g1_aff *Rg1, fe *X, fe *Xinv,
                                                      int *err) {
-  __shared__ uint32_t msg[16 + 8 + 2 * (96 + 16)];
+  __shared__ uint32_t msg[16 + 8 + 2 * (96 + 16) + 32], t2[16];
   uint64_t k = blockIdx.x;
   if (k >= nb) return;
   uint64_t slot = k * lK + (j - 1);
@@ -123,7 +150,7 @@ __global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp1
     sha::put_words<FpP>(msg + 16 + pre + 112 * side + 8 * q, *src);
   }
   __syncthreads();
-  fe x = sha::xmd_fr_words_u(msg, 16 + pre + 224, DSTR_FC_X);
+  fe x = sha::xmd_fr_coop(sha::Coop{t, 64}, msg, 4 * (pre + 224), DSTR_FC_X, t2);
   fe xi = f_inv_uniform<FpR>(x, bn::R_R3);
   if (t == 0) {
     if (fe_is_zero(x)) atomicOr(err, VC_ERRBIT_CHALLENGE);
@@ -143,18 +170,17 @@ __global__ void __launch_bounds__(KZG_T) k_kzg_quotient(const fe *Xinv, const fe
   uint64_t k = blockIdx.x;
   uint64_t D = 2 * K - 1;
   fe *pw = sh, *acc = sh + D;
-  __shared__ fe zz, zi;
+  __shared__ uint32_t zmsg[16 + 8 + 32 + 24], t2[16];
   uint32_t t = threadIdx.x;
-  if (t == 0) {
-    sha::Hasher hs;
-    sha::xmd_begin(hs);
-    hs.field<FpR>(X[k * lK + lK - 1]);
-    hs.g2(V[k * K]);
-    zz = sha::xmd_finish_fr(hs, DSTR_FC_Z);
-    zi = fr_inv_fast(zz);
-    zout[k] = zz;
-  }
+  // z = H2F(DST_FC_Z, x_l || v_l): lanes encode, every wave hashes (sha::Coop); the inverse
+  // runs on the scalar unit
+  if (t < 16) zmsg[t] = 0;
+  if (t == 16) sha::put_words<FpR>(zmsg + 16, X[k * lK + lK - 1]);
+  if (t > 16 && t <= 20) sha::put_words<FpP>(zmsg + 24 + 8 * (t - 17), reinterpret_cast<const fe *>(V + k * K)[t - 17]);
   __syncthreads();
+  const fe zz = sha::xmd_fr_coop(sha::Coop{(int)t, KZG_T}, zmsg, 160, DSTR_FC_Z, t2);
+  const fe zi = f_inv_uniform<FpR>(zz, bn::R_R3);
+  if (t == 0) zout[k] = zz;
   // pw[i] = z^i via inclusive product scan of (1, z, z, ...)
   for (uint64_t i = t; i < D; i += KZG_T) pw[i] = (i == 0) ? f_one<FpR>() : zz;
   __syncthreads();
@@ -252,12 +278,14 @@ __global__ void __launch_bounds__(TPB) k_rho(const fp12 *C, const uint32_t *tree
 namespace kl {
 void trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta, hipStream_t st) { L1(k_trapdoor, lM + 1, seed, lM, s, beta); }
 void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st) {
-  L1(k_fc_chunks, nb * ((b + FC_CHUNK - 1) / FC_CHUNK), Cj, K, b, nb, Hq);
+  LAUNCH(k_fc_chunks, dim3((unsigned)(nb * ((b + FC_CHUNK - 1) / FC_CHUNK))), dim3(64), 0, Cj, K, b, nb, Hq);
 }
 void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st) {
-  L1(k_fc_sigma, nb, C, K, b, nb, Hq, sigma);
+  LAUNCH(k_fc_sigma, dim3((unsigned)nb), dim3(64), fc_sigma_shm(b), C, K, b, nb, Hq, sigma);
 }
-void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st) { L1(k_fc_r, nb * b, K, b, nb, sigma, B); }
+void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st) {
+  LAUNCH(k_fc_r, dim3((unsigned)(nb * b)), dim3(64), 0, K, b, nb, sigma, B);
+}
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st) {
   L1(k_oa_lr_aff, 2 * nb, S, K, nb, j, lK, Lg1, Rg1);
 }

@@ -146,13 +146,33 @@ __global__ void __launch_bounds__(SLP_T) ks_final_exp(const fp12 *in, uint64_t i
 #define G2_SLOTS (slp::G2_NSLOT + 4)
 #define G2_ABASE slp::G2_NSLOT
 
-// out = k Q + A on the engine (A optional); results written as affine (oaff) or Jacobian (ojac)
+// T (Jacobian, the identity when inf) to oaff
+__device__ void g2_store_aff(f29 *S, bool inf, g2_aff *oaff) {
+  const int t = threadIdx.x;
+  fe *o = reinterpret_cast<fe *>(oaff);
+  if (inf) {
+    if (t < 4) o[t] = fe_zero();
+    return;
+  }
+  slp::run1(S, slp::PROG_G2_NORM, 0, 0, 0);
+  {
+    fe ti = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G2_t])), bn::P_R3);
+    if (t == 0) S[slp::G2_tinv] = slp::to29(ti);
+  }
+  __syncthreads();
+  slp::run1(S, slp::PROG_G2_AFF, 0, 0, 0);
+  if (t < 4) o[t] = slp::from29(slp::canon29(S[slp::G2_ax_0 + t]));
+}
+
+// out = k Q + A on the engine (A optional); results written as affine (oaff) or Jacobian (ojac).
+// With lo >= 0 only bits [lo, lo + width) of the GLS split of k are applied (gls::chunk).
 __device__ void g2_job(f29 *S, gls::Dec *dec, const g2_aff *Q, const fe *k_mont, const g2_aff *A, g2_aff *oaff,
-                       g2_jac *ojac) {
+                       g2_jac *ojac, int lo = -1, int width = 0) {
   const int t = threadIdx.x;
   if (t == 0) {
     fe kc = f_from_mont<FpR>(*k_mont);
-    *dec = gls::decompose(kc.l);
+    gls::Dec d = gls::decompose(kc.l);
+    *dec = lo < 0 ? d : gls::chunk(d, lo, width);
   }
   const fe *q = reinterpret_cast<const fe *>(Q);
   if (t < 4) S[slp::G2_xQ_0 + t] = slp::to29(q[t]);
@@ -168,19 +188,7 @@ __device__ void g2_job(f29 *S, gls::Dec *dec, const g2_aff *Q, const fe *k_mont,
     if (t < 6) o[t] = inf ? ((t == 0 || t == 2) ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::G2_T_0 + t]));
     return;
   }
-  fe *o = reinterpret_cast<fe *>(oaff);
-  if (inf) {
-    if (t < 4) o[t] = fe_zero();
-    return;
-  }
-  c.run(slp::PROG_G2_NORM, 0, 0, 0);
-  {
-    fe ti = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G2_t])), bn::P_R3);
-    if (t == 0) S[slp::G2_tinv] = slp::to29(ti);
-  }
-  __syncthreads();
-  c.run(slp::PROG_G2_AFF, 0, 0, 0);
-  if (t < 4) o[t] = slp::from29(slp::canon29(S[slp::G2_ax_0 + t]));
+  g2_store_aff(S, inf, oaff);
 }
 
 // Vout[i] = Vin[i] + x^{-1} Vin[h + i] for every batch k (Eq. folding); Vout may be Vin
@@ -202,6 +210,22 @@ __global__ void __launch_bounds__(SLP_T) ks_kzg_terms(const g2_aff *h, const fe 
   uint64_t id = blockIdx.x;
   if (id >= nb * n) return;
   g2_job(S, &dec, h + id % n, Qc + id, nullptr, nullptr, S2 + id);
+}
+
+// the same with every multiplication split in four parts (bits [16 p, 16 p + 16) of the GLS
+// split, 17 for p = 3) on the multiples hm[3 m + p - 1] = 2^{16 p} h_m made at setup:
+// S2[4 id + p] (Jacobian) for term id = k (2K - 2) + m
+__global__ void __launch_bounds__(SLP_T) ks_kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K,
+                                                           uint64_t nb, g2_jac *S2) {
+  __shared__ f29 S[G2_SLOTS];
+  __shared__ gls::Dec dec;
+  uint64_t n = 2 * K - 2;
+  uint64_t id = blockIdx.x;
+  if (id >= 4 * nb * n) return;
+  uint64_t term = id >> 2, m = term % n;
+  int part = (int)(id & 3);
+  g2_job(S, &dec, part ? hm + 3 * m + part - 1 : h + m, Qc + term, nullptr, nullptr, S2 + id, 16 * part,
+         part < 3 ? 16 : 17);
 }
 
 // ---------------------------------------------------------------- G_T exponentiation
@@ -248,6 +272,23 @@ __global__ void __launch_bounds__(SLP_T) ks_gt_pow(const fp12 *in, const fe *k_m
 #define G1_SLOTS (slp::G1_NSLOT + 2)
 #define G1_ABASE slp::G1_NSLOT
 
+// T (Jacobian, the identity when inf) to oaff
+__device__ void g1_store_aff(f29 *S, bool inf, g1_aff *oaff) {
+  const int t = threadIdx.x;
+  fe *o = reinterpret_cast<fe *>(oaff);
+  if (inf) {
+    if (t < 2) o[t] = fe_zero();
+    return;
+  }
+  {
+    fe zi = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G1_T_2])), bn::P_R3);
+    if (t == 0) S[slp::G1_tinv] = slp::to29(zi);
+  }
+  __syncthreads();
+  slp::run1(S, slp::PROG_G1_AFF, 0, 0, 0);
+  if (t < 2) o[t] = slp::from29(slp::canon29(S[t ? slp::G1_ay : slp::G1_ax]));
+}
+
 // out = k P + A on the engine (A optional); results written as affine (oaff) or Jacobian (ojac).
 // With chunk >= 0 only that 32-bit part of the GLV split of k is applied (glv::chunk).
 __device__ void g1_job(f29 *S, glv::Dec *dec, const g1_aff *P, const fe *k_mont, const g1_aff *A, g1_aff *oaff,
@@ -270,21 +311,85 @@ __device__ void g1_job(f29 *S, glv::Dec *dec, const g1_aff *P, const fe *k_mont,
     if (t < 3) o[t] = inf ? (t < 2 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::G1_T_0 + t]));
     return;
   }
-  fe *o = reinterpret_cast<fe *>(oaff);
-  if (inf) {
-    if (t < 2) o[t] = fe_zero();
-    return;
+  g1_store_aff(S, inf, oaff);
+}
+
+// ---------------------------------------------------------------- group sums on the engine
+// Sum of each segment data[g stride + 0 .. len) of Jacobian points into data[g stride] in
+// one launch: a workgroup per pair of the first level; of two sibling nodes, the workgroup
+// that finishes second climbs to the parent (arrival counters as in ks_f12_tree).  The
+// identity is any point with Z = 0; additions meeting equal x are resolved exactly.
+template <bool G2>
+__global__ void __launch_bounds__(SLP_T) ks_jac_tree(void *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt) {
+  constexpr int NC = G2 ? 6 : 3;  // coordinates (F_p elements) per point
+  __shared__ f29 S[G2 ? G2_SLOTS : G1_SLOTS];
+  __shared__ uint32_t arrived;
+  uint64_t per = (len + 1) / 2;
+  uint64_t id = blockIdx.x;
+  if (id >= nseg * per) return;
+  uint64_t g = id / per, q = id % per;
+  fe *seg = reinterpret_cast<fe *>(data) + g * stride * NC;
+  uint32_t *c = cnt + g * tree_counters(len);
+  const int t = threadIdx.x;
+  const int T0 = G2 ? slp::G2_T_0 : slp::G1_T_0, A0 = G2 ? slp::G2_TB1_0 : slp::G1_TB1_0;
+  if (G2) load_consts<slp::G2_NCONST>(S, slp::G2_CBASE, slp::G2_CONSTS);
+  else load_consts<slp::G1_NCONST>(S, slp::G1_CBASE, slp::G1_CONSTS);
+  slp::DevCtx cx{S};
+  uint64_t s = 1, n = per, cb = 0;
+  for (;;) {
+    uint64_t a = 2 * s * q, b = a + s;
+    if (b < len) {
+      fe *da = seg + a * NC;
+      const fe *db = seg + b * NC;
+      bool binf = G2 ? fe_is_zero(db[4]) && fe_is_zero(db[5]) : fe_is_zero(db[2]);
+      if (!binf) {
+        bool inf = G2 ? fe_is_zero(da[4]) && fe_is_zero(da[5]) : fe_is_zero(da[2]);
+        if (t < NC) {
+          S[T0 + t] = slp::to29(da[t]);
+          S[A0 + t] = slp::to29(db[t]);
+        }
+        __syncthreads();
+        if (G2) g2m::add_jac(cx, inf, A0, false);
+        else g1m::add_jac(cx, inf, A0, false);
+        fe one_or_zero = (G2 ? (t == 0 || t == 2) : t < 2) ? f_one<FpP>() : fe_zero();
+        if (t < NC) da[t] = inf ? one_or_zero : slp::from29(slp::canon29(S[T0 + t]));
+      }
+    }
+    if (n == 1) return;
+    uint64_t nn = (n + 1) / 2, qp = q >> 1;
+    if ((q ^ 1) < n) {
+      __threadfence();
+      __syncthreads();
+      if (t == 0) {
+        uint32_t old = atomicAdd(&c[cb + qp], 1u);
+        if (old) c[cb + qp] = 0;
+        arrived = old;
+      }
+      __syncthreads();
+      if (!arrived) return;
+      __threadfence();
+    }
+    cb += nn;
+    q = qp;
+    n = nn;
+    s *= 2;
   }
-  {
-    fe zi = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G1_T_2])), bn::P_R3);
-    if (t == 0) S[slp::G1_tinv] = slp::to29(zi);
-  }
-  __syncthreads();
-  c.run(slp::PROG_G1_AFF, 0, 0, 0);
-  if (t < 2) o[t] = slp::from29(slp::canon29(S[t ? slp::G1_ay : slp::G1_ax]));
 }
 
 // ---------------------------------------------------------------- Step 1 rounds, fused
+// Round-1 (direct) G1 terms on the engine: b_L[i] A_R[i] (side 0) and b_R[i] A_L[i] (side 1)
+// into S[(2k + side) (K / 2) + i] (Jacobian)
+__global__ void __launch_bounds__(SLP_T) ks_oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h,
+                                                      g1_jac *Sout) {
+  __shared__ f29 S[G1_SLOTS];
+  __shared__ glv::Dec d1;
+  uint64_t id = blockIdx.x;
+  if (id >= nb * 2 * h) return;
+  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
+  g1_job(S, &d1, A + (side ? k * K + i : k * K + h + i), B + (side ? k * K + h + i : k * K + i), nullptr, nullptr,
+         Sout + (k * 2 + side) * (K / 2) + i);
+}
+
 template <int A_, int B_> struct imax { static constexpr int v = A_ > B_ ? A_ : B_; };
 
 // The fold of round j (Eq. folding) for every batch: blocks [0, nb h) fold G1 and b,
@@ -351,29 +456,123 @@ __global__ void __launch_bounds__(SLP_T) ks_gt_sqr_mults(const fp12 *G, uint64_t
   if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(b) + t]));
 }
 
-// M[3 s + m - 1] = 2^{32 m} P[s] (affine), a workgroup per (s, m), m = 1, 2, 3
-__global__ void __launch_bounds__(SLP_T) ks_g1_dbl_mults(const g1_aff *P, uint64_t n, g1_aff *M) {
+// point s of a segmented list: P[(s / seg) segstride + s % seg]
+__device__ __forceinline__ uint64_t seg_index(uint64_t s, uint64_t seg, uint64_t segstride) {
+  return (s / seg) * segstride + s % seg;
+}
+
+// M[3 s + m - 1] = 2^{32 m} P_s (affine), P_s as in seg_index, a workgroup per (s, m), m = 1, 2, 3
+__global__ void __launch_bounds__(SLP_T) ks_g1_dbl_mults(const g1_aff *P, uint64_t seg, uint64_t segstride, uint64_t n,
+                                                        g1_aff *M) {
   __shared__ f29 S[G1_SLOTS];
   uint64_t id = blockIdx.x;
   if (id >= 3 * n) return;
   uint64_t s = id / 3, m = id % 3 + 1;
+  const g1_aff *Ps = P + seg_index(s, seg, segstride);
   const int t = threadIdx.x;
-  fe *o = reinterpret_cast<fe *>(M + 3 * s + m - 1);
-  if (g1_inf(P[s])) {
-    if (t < 2) o[t] = fe_zero();
+  g1_aff *o = M + 3 * s + m - 1;
+  bool inf = g1_inf(*Ps);
+  if (!inf) {
+    load_consts<slp::G1_NCONST>(S, slp::G1_CBASE, slp::G1_CONSTS);
+    if (t < 3) S[slp::G1_T_0 + t] = slp::to29(t == 2 ? f_one<FpP>() : t ? Ps->y : Ps->x);
+    __syncthreads();
+    for (int i = 0; i < 16 * (int)m; i++) slp::run1(S, slp::PROG_G1_DBL2, 0, 0, 0);
+  }
+  g1_store_aff(S, inf, o);
+}
+
+// M[3 s + m - 1] = 2^{16 m} Q_s (affine), Q_s as in seg_index, a workgroup per (s, m), m = 1, 2, 3
+__global__ void __launch_bounds__(SLP_T) ks_g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n,
+                                                        g2_aff *M) {
+  __shared__ f29 S[G2_SLOTS];
+  uint64_t id = blockIdx.x;
+  if (id >= 3 * n) return;
+  uint64_t s = id / 3, m = id % 3 + 1;
+  const g2_aff *Qs = Q + seg_index(s, seg, segstride);
+  const int t = threadIdx.x;
+  bool inf = g2_inf(*Qs);
+  if (!inf) {
+    load_consts<slp::G2_NCONST>(S, slp::G2_CBASE, slp::G2_CONSTS);
+    const fe *q = reinterpret_cast<const fe *>(Qs);
+    if (t < 6) S[slp::G2_T_0 + t] = t < 4 ? slp::to29(q[t]) : slp::to29(t == 4 ? f_one<FpP>() : fe_zero());
+    __syncthreads();
+    for (int i = 0; i < 16 * (int)m; i++) slp::run1(S, slp::PROG_G2_DBL, 0, 0, 0);
+  }
+  g2_store_aff(S, inf, M + 3 * s + m - 1);
+}
+
+// of the four parts of one multiplication, the workgroup that finishes last returns true
+// (and resets the counter); partial results written before are visible to it
+__device__ bool last_of_four(uint32_t *cnt, uint32_t *flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t old = atomicAdd(cnt, 1u);
+    if (old == 3) *cnt = 0;
+    *flag = old == 3;
+  }
+  __syncthreads();
+  bool last = *flag;
+  if (last) __threadfence();
+  return last;
+}
+
+// The fold of round j with every multiplication split in four parts run in parallel:
+// blocks [0, 4 nb h): part p of x A[h + i] on the base 2^{32 p} A[h + i] (M1, p > 0) with
+// the p-th 32-bit chunk of the GLV split of x into J1[4 s + p]; blocks [4 nb h, 8 nb h):
+// part p of x^{-1} V[h + i] on 2^{16 p} V[h + i] (M2) with bits [16 p, 16 p + 16) (17 for
+// p = 3) of the GLS split into J2[4 s + p] (s = k h + i).  The last part to finish adds the
+// four partial results and A[i] (V[i]) and writes the affine result; part 0 of G1 also
+// folds b.  Same results as ks_oa_fold.
+__global__ void __launch_bounds__(SLP_T) ks_oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout,
+                                                         const g2_aff *Vin, g2_aff *Vout, const fe *X, const fe *Xinv,
+                                                         const g1_aff *M1, const g2_aff *M2, g1_jac *J1, g2_jac *J2,
+                                                         uint32_t *cnt, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+                                                         uint32_t lK) {
+  __shared__ f29 S[imax<G1_SLOTS, G2_SLOTS>::v];
+  __shared__ glv::Dec d1;
+  __shared__ gls::Dec d2;
+  __shared__ uint32_t flag;
+  uint64_t id = blockIdx.x, n = nb * h;
+  if (id >= 8 * n) return;
+  const int t = threadIdx.x;
+  bool g2 = id >= 4 * n;
+  if (g2) id -= 4 * n;
+  uint64_t s = id >> 2, k = s / h, i = s % h, slot = k * lK + (j - 1);
+  int part = (int)(id & 3);
+  slp::DevCtx c{S};
+  if (!g2) {
+    if (part == 0 && t == 32) Bout[k * K + i] = fr_add(Bin[k * K + i], fr_mul(Bin[k * K + h + i], Xinv[slot]));
+    g1_job(S, &d1, part ? M1 + 3 * s + part - 1 : Ain + k * K + h + i, X + slot, nullptr, nullptr, J1 + 4 * s + part,
+           part);
+    if (!last_of_four(cnt + s, &flag)) return;
+    // sum of the parts (in the table slots) and A[i]
+    const fe *pj = reinterpret_cast<const fe *>(J1 + 4 * s);
+    if (t < 12) S[slp::G1_TB1_0 + t] = slp::to29(pj[t]);
+    const g1_aff *A = Ain + k * K + i;
+    if (t >= 12 && t < 14) S[G1_ABASE + t - 12] = slp::to29(t == 13 ? A->y : A->x);
+    __syncthreads();
+    bool inf = true;
+    for (int p = 0; p < 4; p++) g1m::add_jac(c, inf, slp::G1_TB1_0 + 3 * p, fe_is_zero(J1[4 * s + p].Z));
+    if (!g1_inf(*A)) g1m::add_affine(c, inf, G1_ABASE, S[slp::G1_CBASE + 1]);
+    g1_store_aff(S, inf, Aout + k * K + i);
     return;
   }
-  load_consts<slp::G1_NCONST>(S, slp::G1_CBASE, slp::G1_CONSTS);
-  if (t < 3) S[slp::G1_T_0 + t] = slp::to29(t == 2 ? f_one<FpP>() : t ? P[s].y : P[s].x);
+  g2_job(S, &d2, part ? M2 + 3 * s + part - 1 : Vin + k * K + h + i, Xinv + slot, nullptr, nullptr, J2 + 4 * s + part,
+         16 * part, part < 3 ? 16 : 17);
+  if (!last_of_four(cnt + n + s, &flag)) return;
+  const fe *pj = reinterpret_cast<const fe *>(J2 + 4 * s);
+  if (t < 24) S[slp::G2_TB1_0 + t] = slp::to29(pj[t]);
+  const fe *a = reinterpret_cast<const fe *>(Vin + k * K + i);
+  if (t >= 24 && t < 28) S[G2_ABASE + t - 24] = slp::to29(a[t - 24]);
   __syncthreads();
-  for (int i = 0; i < 16 * (int)m; i++) slp::run1(S, slp::PROG_G1_DBL2, 0, 0, 0);
-  {
-    fe zi = f_inv_uniform<FpP>(slp::from29(slp::canon29(S[slp::G1_T_2])), bn::P_R3);
-    if (t == 0) S[slp::G1_tinv] = slp::to29(zi);
+  bool inf = true;
+  for (int p = 0; p < 4; p++) {
+    const g2_jac &Jp = J2[4 * s + p];
+    g2m::add_jac(c, inf, slp::G2_TB1_0 + 6 * p, fe_is_zero(Jp.Z.c0) && fe_is_zero(Jp.Z.c1));
   }
-  __syncthreads();
-  slp::run1(S, slp::PROG_G1_AFF, 0, 0, 0);
-  if (t < 2) o[t] = slp::from29(slp::canon29(S[t ? slp::G1_ay : slp::G1_ax]));
+  if (!g2_inf(Vin[k * K + i])) g2m::add_affine(c, inf, G2_ABASE, S[slp::G2_CBASE + 1], S[slp::G2_CBASE]);
+  g2_store_aff(S, inf, Vout + k * K + i);
 }
 
 // The x-dependent part of a round taken ahead, each multiplication split in four parts run
@@ -482,8 +681,17 @@ void oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64
 void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st) {
   if (n) LAUNCH(ks_gt_sqr_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, G, n, M);
 }
-void g1_dbl_mults(const g1_aff *P, uint64_t n, g1_aff *M, hipStream_t st) {
-  if (n) LAUNCH(ks_g1_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, P, n, M);
+void g1_dbl_mults(const g1_aff *P, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M, hipStream_t st) {
+  if (n) LAUNCH(ks_g1_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, P, seg, segstride, n, M);
+}
+void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st) {
+  if (n) LAUNCH(ks_g2_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, Q, seg, segstride, n, M);
+}
+void oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
+                   const fe *Xinv, const g1_aff *M1, const g2_aff *M2, g1_jac *J1, g2_jac *J2, uint32_t *cnt, uint64_t K,
+                   uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
+  LAUNCH(ks_oa_fold_split, dim3((unsigned)(8 * nb * h)), dim3(SLP_T), 0, Ain, Bin, Aout, Bout, Vin, Vout, X, Xinv, M1, M2, J1,
+         J2, cnt, K, nb, h, j, lK);
 }
 void oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1, const g1_aff *PX1m, const fe *k_even,
                       const fe *k_odd, uint64_t kstride, uint64_t nb, fp12 *PE, g1_jac *PM, hipStream_t st) {
@@ -499,6 +707,18 @@ void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp
 }
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st) {
   LAUNCH(ks_kzg_terms, dim3((unsigned)(nb * (2 * K - 2))), dim3(SLP_T), 0, h, Qc, K, nb, S2);
+}
+void g1_tree(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st) {
+  if (len > 1) LAUNCH(ks_jac_tree<false>, dim3((unsigned)(nseg * ((len + 1) / 2))), dim3(SLP_T), 0, data, nseg, stride, len, cnt);
+}
+void g2_tree(g2_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st) {
+  if (len > 1) LAUNCH(ks_jac_tree<true>, dim3((unsigned)(nseg * ((len + 1) / 2))), dim3(SLP_T), 0, data, nseg, stride, len, cnt);
+}
+void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st) {
+  LAUNCH(ks_oa_g1terms, dim3((unsigned)(nb * 2 * h)), dim3(SLP_T), 0, A, B, K, nb, h, S);
+}
+void kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st) {
+  LAUNCH(ks_kzg_terms_split, dim3((unsigned)(4 * nb * (2 * K - 2))), dim3(SLP_T), 0, h, hm, Qc, K, nb, S2);
 }
 void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st) {
   if (n) LAUNCH(ks_gt_pow, dim3((unsigned)n), dim3(SLP_T), 0, in, k, n, out);

@@ -27,6 +27,7 @@ void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t 
 // one launch; cnt: nseg tree_counters(len) zeroed counters, zero again on return
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st);
+void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint64_t ostride, hipStream_t st);
 void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st);
 void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st);
 void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
@@ -77,6 +78,13 @@ void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *ou
 void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st);
 void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
+// sums of Jacobian segments on the engine, one launch (tree_counters(len) counters per segment)
+void g1_tree(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
+void g2_tree(g2_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
+// round-1 G1 terms on the engine (same layout as klw::oa_g1terms)
+void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st);
+// four-part split terms on the setup multiples hm[3 m + p - 1] = 2^{16 p} h_m: S2[4 id + p]
+void kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
 void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st);
 // fused round kernels: G1 + G2 fold; Miller loops + G1 terms of the next round (oa_terms.hpp);
 // final exponentiations of two strided lists
@@ -90,7 +98,14 @@ void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp
 // the split combine (4 parts per power and per G1 multiple, PE/PM[4 s + p]) and the
 // product of U with the 8 G_T parts of each side
 void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st);
-void g1_dbl_mults(const g1_aff *P, uint64_t n, g1_aff *M, hipStream_t st);
+// (the points of the multiples are P[(s / seg) segstride + s % seg], s < n)
+void g1_dbl_mults(const g1_aff *P, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M, hipStream_t st);
+void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st);
+// the fold with four-part split multiplications on the multiples M1 = 2^{32 m} A[h + i],
+// M2 = 2^{16 m} V[h + i]; partial results in J1, J2; 2 nb h arrival counters
+void oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
+                   const fe *Xinv, const g1_aff *M1, const g2_aff *M2, g1_jac *J1, g2_jac *J2, uint32_t *cnt, uint64_t K,
+                   uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1, const g1_aff *PX1m, const fe *k_even,
                       const fe *k_odd, uint64_t kstride, uint64_t nb, fp12 *PE, g1_jac *PM, hipStream_t st);
 void oa_gt_combine8(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st);

@@ -121,6 +121,7 @@ struct vc_params {
   void *mem = nullptr;      // all keys in one allocation
   g1_aff *ek, *g1gen, *g1beta, *table;
   g2_aff *vk, *h, *g2gen;
+  g2_aff *hm;  // 2^{16 p} h_m (p = 1..3, m < 2K - 2) for the split KZG terms
   void *ws = nullptr;       // grow-only scratch shared by calls on these params
   size_t ws_size = 0;
   // side streams (default priority) and fork/join events for independent phases
@@ -136,6 +137,10 @@ struct vc_params {
 // device mostly idle: at most this many (batch, index) pairs per round.  Beyond it the
 // doubled Miller-loop count of that scheme costs more than the shorter chain saves.
 static constexpr uint64_t AHEAD_MAX_PAIRS = 4096;
+// folds of at most this many pairs (batches x h) run as four-part split multiplications
+static constexpr uint64_t FOLD_SPLIT_MAX = 256;
+// KZG proofs of at most this many split jobs (4 per term) run split
+static constexpr uint64_t KZG_SPLIT_MAX = 8192;
 
 // fork: `to` waits for the work issued so far on `from`
 static int stream_wait(vc_params *pp, int slot, hipStream_t from, hipStream_t to) {
@@ -235,7 +240,7 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   Carve c;
   size_t o_ek = c.take<g1_aff>(2 * M - 1), o_g1 = c.take<g1_aff>(1), o_g1b = c.take<g1_aff>(1);
   size_t o_tab = c.take<g1_aff>(NWIN * M), o_vk = c.take<g2_aff>(lM), o_h = c.take<g2_aff>(2 * K - 1);
-  size_t o_g2 = c.take<g2_aff>(1);
+  size_t o_g2 = c.take<g2_aff>(1), o_hm = c.take<g2_aff>(3 * (2 * K - 2));
   hipError_t e = hipMalloc(&pp->mem, c.off);
   if (e != hipSuccess) { delete pp; return hip_fail(e, "vc_setup alloc"); }
   pp->ek = at<g1_aff>(pp->mem, o_ek);
@@ -245,6 +250,7 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   pp->vk = at<g2_aff>(pp->mem, o_vk);
   pp->h = at<g2_aff>(pp->mem, o_h);
   pp->g2gen = at<g2_aff>(pp->mem, o_g2);
+  pp->hm = at<g2_aff>(pp->mem, o_hm);
   g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
   g2_aff g2 = {{fe_const(bn::G2X0), fe_const(bn::G2X1)}, {fe_const(bn::G2Y0), fe_const(bn::G2Y1)}};
   // temporaries: seed, trapdoor, weights
@@ -265,6 +271,7 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   klw::g2_mul(pp->g2gen, 1, s, lM, pp->vk, st);
   kl::pow_table(beta, pw, 2 * K - 1, st);
   klw::g2_mul(pp->g2gen, 1, pw, 2 * K - 1, pp->h, st);
+  ks::g2_dbl_mults(pp->h, 2 * K - 2, 0, 2 * K - 2, pp->hm, st);
   klw::g1_mul(pp->g1gen, 1, beta, 1, pp->g1beta, st);
   kl::msm_tables(pp->ek + (M - 1), M, NWIN, pp->table, st);
   CKL("vc_setup launch");
@@ -405,7 +412,9 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   size_t o_err = t.take<int>(1), o_A = t.take<g1_aff>(nb * K), o_V = t.take<g2_aff>(nb * K), o_B = t.take<fe>(nb * K);
   size_t o_F = t.take<fp12>(nb * K), o_S = t.take<g1_jac>(nb * K), o_Hq = t.take<uint32_t>(nb * qmax * 8);
   size_t o_sig = t.take<uint32_t>(nb * 8), o_Xi = t.take<fe>(nb * lK), o_Q = t.take<fe>(nb * nq), o_z = t.take<fe>(nb);
-  size_t o_S2 = t.take<g2_jac>(nb * nq), o_HS = t.take<g1_jac>(lM * (M / 2)), o_dec = t.take<glv::Dec>(nb);
+  // KZG terms split in four parts when the jobs are few (the device is otherwise idle)
+  const bool kzg_split = 4 * nb * nq <= KZG_SPLIT_MAX;
+  size_t o_S2 = t.take<g2_jac>((kzg_split ? 4 : 1) * nb * nq), o_HS = t.take<g1_jac>(lM * (M / 2)), o_dec = t.take<glv::Dec>(nb);
   // Step 1 arrays of alternate rounds, and the terms taken one round ahead (oa_terms.hpp)
   const bool ahead = lK >= 2 && nb * K <= AHEAD_MAX_PAIRS;
   const uint64_t nterm = ahead ? 2 * nb * K : 0;
@@ -415,6 +424,11 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   size_t o_PXm = t.take<fp12>(ahead ? 24 * nb : 0), o_PE = t.take<fp12>(ahead ? 16 * nb : 0);
   size_t o_PU1 = t.take<g1_aff>(ahead ? 4 * nb : 0), o_PX1 = t.take<g1_aff>(ahead ? 8 * nb : 0);
   size_t o_PX1m = t.take<g1_aff>(ahead ? 24 * nb : 0), o_PM = t.take<g1_jac>(ahead ? 16 * nb : 0);
+  // split folds: multiples of the halves A[h + i], V[h + i] and the four partial results
+  auto split_round = [&](uint32_t j) { return ahead && j <= lK && nb * (K >> j) <= FOLD_SPLIT_MAX; };
+  const uint64_t nsplit = ahead ? std::min<uint64_t>(nb * K / 2, FOLD_SPLIT_MAX) : 0;
+  size_t o_FM1 = t.take<g1_aff>(3 * nsplit), o_FM2 = t.take<g2_aff>(3 * nsplit);
+  size_t o_FJ1 = t.take<g1_jac>(4 * nsplit), o_FJ2 = t.take<g2_jac>(4 * nsplit);
   int rc = ensure_ws(pp, t.off);
   if (rc) { vc_proofs_free(pr); return rc; }
   void *ws = pp->ws;
@@ -442,13 +456,19 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   g1_aff *PU1[2] = {at<g1_aff>(ws, o_PU1), at<g1_aff>(ws, o_PU1) + 2 * nb};
   g1_aff *PX1[2] = {at<g1_aff>(ws, o_PX1), at<g1_aff>(ws, o_PX1) + 4 * nb};
   g1_jac *PM = at<g1_jac>(ws, o_PM);
+  g1_aff *FM1 = at<g1_aff>(ws, o_FM1);
+  g2_aff *FM2 = at<g2_aff>(ws, o_FM2);
+  g1_jac *FJ1 = at<g1_jac>(ws, o_FJ1);
+  g2_jac *FJ2 = at<g2_jac>(ws, o_FJ2);
   // reduction-tree counters: round-1 (or every direct round) products, and per stream the
   // U and XY groups of the terms taken ahead (F_p12 on side stream 3, G1 on the caller's)
   const uint64_t c_dir = 2 * nb * tree_counters(K / 2), c_u = 2 * nb * tree_counters(K / 2),
                  c_xy = 4 * nb * tree_counters(K / 4);
-  if (int rc2 = ensure_cnt(pp, c_dir + 2 * (c_u + c_xy))) { vc_proofs_free(pr); return rc2; }
+  const uint64_t c_kzg = kzg_split ? nb * tree_counters(4 * nq) : 0;
+  if (int rc2 = ensure_cnt(pp, 2 * c_dir + 2 * (c_u + c_xy) + 2 * nsplit + c_kzg)) { vc_proofs_free(pr); return rc2; }
   uint32_t *cnt_dir = pp->cnt, *cnt_fu = cnt_dir + c_dir, *cnt_fxy = cnt_fu + c_u, *cnt_gu = cnt_fxy + c_xy,
-           *cnt_gxy = cnt_gu + c_u;
+           *cnt_gxy = cnt_gu + c_u, *cnt_fold = cnt_gxy + c_xy, *cnt_kzg = cnt_fold + 2 * nsplit,
+           *cnt_g1dir = cnt_kzg + c_kzg;
 
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
@@ -492,6 +512,18 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // the terms; each launch pairs the G1 and the pairing-side work of its step.
   hipStream_t sg = s2, sf = pp->side[2];
   kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
+  // multiples 2^{32 m} A[h + i], 2^{16 m} V[h + i] (m = 1..3) of the arrays of round j for
+  // its split fold, on the fold stream
+  auto launch_fold_mults = [&](uint32_t j) {
+    const uint64_t h = K >> j;
+    const int cur = (j - 1) & 1;
+    ks::g1_dbl_mults(Ab[cur] + h, h, K, nb * h, FM1, sg);
+    ks::g2_dbl_mults(Vb[cur] + h, h, K, nb * h, FM2, sg);
+  };
+  if (split_round(1)) {
+    if (int rc2 = stream_wait(pp, 14, st, sg)) return rc2;
+    launch_fold_mults(1);
+  }
   kl::fc_chunks(Cj, K, b, nb, Hq, st);
   kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
   kl::fc_r(K, b, nb, sigma, B, st);
@@ -515,19 +547,24 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     uint64_t q = K >> jn;
     int par = jn & 1;
     if (int rc2 = ev_wait(pp, 8 + par, st)) return rc2;
-    kl::g1_reduce(PS[par], 2 * nb, 2 * q, 2 * q, cnt_gu, st);
-    kl::g1_reduce(PS[par] + nb * 4 * q, 4 * nb, q, q, cnt_gxy, st);
+    ks::g1_tree(PS[par], 2 * nb, 2 * q, 2 * q, cnt_gu, st);
+    ks::g1_tree(PS[par] + nb * 4 * q, 4 * nb, q, q, cnt_gxy, st);
     kl::g1_to_aff(PS[par], 2 * q, 2 * nb, PU1[par], 1, st);
     kl::g1_to_aff(PS[par] + nb * 4 * q, q, 4 * nb, PX1[par], 1, st);
-    ks::g1_dbl_mults(PX1[par], 4 * nb, PX1m[par], st);
+    ks::g1_dbl_mults(PX1[par], 4 * nb, 0, 4 * nb, PX1m[par], st);
     return VC_OK;
   };
   for (uint32_t j = 1; j <= lK; j++) {
     const uint64_t h = K >> j;
     const int cur = (j - 1) & 1, nxt = j & 1;
     if (j == 1 || !ahead) {
-      klw::oa_g1terms(Ab[cur], Bb[cur], K, nb, h, S, sg);
-      klw::g1_reduce(S, 2 * nb, K / 2, h, sg);
+      if (ahead) {
+        ks::oa_g1terms(Ab[cur], Bb[cur], K, nb, h, S, sg);
+        ks::g1_tree(S, 2 * nb, K / 2, h, cnt_g1dir, sg);
+      } else {
+        klw::oa_g1terms(Ab[cur], Bb[cur], K, nb, h, S, sg);
+        klw::g1_reduce(S, 2 * nb, K / 2, h, sg);
+      }
       kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
       if (int rc2 = ev_mark(pp, 3, sg)) return rc2;
       if (ahead)
@@ -548,12 +585,17 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     // fold with x_j into the other buffer
     if (ahead) {
       if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
-      ks::oa_fold(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, K, nb, h, j, lK, sg);
+      if (split_round(j))
+        ks::oa_fold_split(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, FM1, FM2, FJ1, FJ2, cnt_fold, K, nb,
+                          h, j, lK, sg);
+      else
+        ks::oa_fold(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, K, nb, h, j, lK, sg);
       // terms of round j + 2 from the arrays of round j + 1 (just folded)
       if (j + 2 <= lK) {
         if (int rc2 = stream_wait(pp, 10, sg, sf)) return rc2;
         if (int rc2 = launch_terms(j + 2)) return rc2;
       }
+      if (split_round(j + 1)) launch_fold_mults(j + 1);
       // the caller's stream idles until the terms of round j + 1 are exponentiated
       if (j + 1 <= lK)
         if (int rc2 = launch_g1_sums(j + 1)) return rc2;
@@ -577,9 +619,15 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
   // faster verifier: KZG-style proof in G2 that v_l = f_v(beta) g2
   kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, st);
-  ks::kzg_terms(pp->h, Q, K, nb, S2, st);
-  klw::g2_reduce(S2, nb, nq, nq, st);
-  klw::g2_to_aff(S2, nq, nb, piv, 1, st);
+  if (kzg_split) {
+    ks::kzg_terms_split(pp->h, pp->hm, Q, K, nb, S2, st);
+    ks::g2_tree(S2, nb, 4 * nq, 4 * nq, cnt_kzg, st);
+    kl::g2_to_aff(S2, 4 * nq, nb, piv, 1, st);
+  } else {
+    ks::kzg_terms(pp->h, Q, K, nb, S2, st);
+    klw::g2_reduce(S2, nb, nq, nq, st);
+    klw::g2_to_aff(S2, nq, nb, piv, 1, st);
+  }
   // join Step 2
   if (int rc2 = stream_wait(pp, 13, s1, st)) return rc2;
   CKL("vc_open_all launch");

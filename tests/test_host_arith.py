@@ -24,6 +24,8 @@ def hc():
     L = C.CDLL(HC_PATH)
     L.hc_h2f.argtypes = [C.c_char_p, C.c_char_p, C.c_uint64, C.c_void_p]
     L.hc_sha256.argtypes = [C.c_char_p, C.c_uint64, C.c_void_p]
+    L.hc_sha256_coop.argtypes = [C.c_char_p, C.c_uint64, C.c_void_p]
+    L.hc_h2f_coop.argtypes = [C.c_char_p, C.c_char_p, C.c_uint64, C.c_void_p]
     L.hc_count.restype = C.c_uint64
     return L
 
@@ -150,18 +152,21 @@ def test_hashes(hc):
         o = buf(32)
         hc.hc_sha256(msg, len(msg), o)
         assert o.raw == hashlib.sha256(msg).digest()
+        o = buf(32)
+        hc.hc_sha256_coop(msg, len(msg), o)
+        assert o.raw == hashlib.sha256(msg).digest()
         for dst in ("FLEXPROOFS-V1-FC-X", "FLEXPROOFS-V1-RHO"):
             o = buf(32)
             hc.hc_h2f(dst.encode(), msg, len(msg), o)
             assert int.from_bytes(o.raw, "big") == O.hash_to_fr(dst, msg)
-    # the word-message form of the challenge kernels, over lengths that put the tail in
-    # one or two final blocks
-    hc.hc_h2f_words.argtypes = [C.c_char_p, C.c_char_p, C.c_uint64, C.c_void_p]
-    for nw in list(range(0, 40)) + [224, 232, 240, 248, 255, 256]:
-        msg = bytes(rng.randrange(256) for _ in range(4 * nw))
-        o = buf(32)
-        hc.hc_h2f_words(b"FLEXPROOFS-V1-FC-X", msg, len(msg), o)
-        assert int.from_bytes(o.raw, "big") == O.hash_to_fr("FLEXPROOFS-V1-FC-X", msg), nw
+    # the cooperative form of the challenge kernels, over lengths that put the suffix and
+    # padding in one or two final blocks
+    for n in list(range(0, 80)) + [896, 928, 960, 992, 1000, 1024]:
+        msg = bytes(rng.randrange(256) for _ in range(n))
+        for dst in ("FLEXPROOFS-V1-FC-X", "FLEXPROOFS-V1-FC-Z"):
+            o = buf(32)
+            hc.hc_h2f_coop(dst.encode(), msg, len(msg), o)
+            assert int.from_bytes(o.raw, "big") == O.hash_to_fr(dst, msg), (n, dst)
     m, c = bytes(range(32)), bytes(range(64, 128))
     o = buf(32)
     hc.hc_merkle_leaf(m, c, o)
@@ -368,3 +373,29 @@ def test_split_multiplications(hc):
             o = buf(384)
             assert hc.hc_gt_pow_split(g, k.to_bytes(32, "big"), o) == 0
             assert o.raw == O.fp12_op("pow", g, O.be32(k)), k
+
+
+@pytest.mark.parametrize("grp", ["g1", "g2"])
+def test_split_fold(hc, grp):
+    """The split fold exactly as the kernels run it (multiples by the engine's doublings,
+    four chunked multiplications, their sum and A through the engine's Jacobian and
+    mixed additions): A + k P against the oracle, including the cases where partial
+    sums meet (A = k P doubles, A = -k P gives the identity) and identity inputs."""
+    g1, g2 = O.generators()
+    op, gen, size = (O.g1_op, g1, 64) if grp == "g1" else (O.g2_op, g2, 128)
+    fn = hc.hc_fold_split_g1 if grp == "g1" else hc.hc_fold_split_g2
+    rng = random.Random(41 if grp == "g1" else 42)
+    inf = bytes(size)
+    cases = []
+    for _ in range(5):
+        Pt = op("mul", gen, O.be32(rng.randrange(1, R)))
+        cases.append((Pt, rng.randrange(R), op("mul", gen, O.be32(rng.randrange(1, R)))))
+    Pt = op("mul", gen, O.be32(rng.randrange(1, R)))
+    k = rng.randrange(R)
+    kP = op("mul", Pt, O.be32(k))
+    cases += [(Pt, k, kP), (Pt, k, op("neg", kP)), (Pt, 0, kP), (Pt, k, inf), (inf, k, kP), (Pt, 1, inf),
+              (Pt, R - 1, Pt), (Pt, 2**16 + 1, inf), (Pt, 2**64, inf)]
+    for Pt, k, A in cases:
+        o = buf(size)
+        assert fn(Pt, k.to_bytes(32, "big"), A, o) == 0
+        assert o.raw == op("add", op("mul", Pt, O.be32(k)), A), (k,)
