@@ -24,6 +24,10 @@ import statistics
 import sys
 import time
 
+# hardware queues for the library's streams (as the package sets it), before any device use
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -32,6 +36,8 @@ PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12   # v_mad_u64_u32 issues at half rat
 PEAK_HBM_GBS = 8000.0
 MADS_PER_FMUL = 136                        # 8x32-bit CIOS: 64 + 64 products + 8 reduction words
 AHEAD_MAX_PAIRS = 4096                     # the library's switch to next-round terms (batches x K)
+FOLD_SPLIT_MAX = 256                       # folds of at most this many pairs run split in four parts
+KZG_SPLIT_MAX = 8192                       # KZG proofs of at most this many split jobs run split
 
 
 def op_costs():
@@ -43,7 +49,7 @@ def op_costs():
     names = ["miller", "final_exp", "g1_mul", "g2_mul", "g1_add", "g1_madd", "g2_add", "g2_madd",
              "g1_dbl", "g2_dbl", "f12_mul", "g1_to_aff", "g2_to_aff"]
     c = {n: int(L.hc_count(i)) for i, n in enumerate(names)}
-    e = [int(L.hc_engine_muls(i)) for i in range(16)]
+    e = [int(L.hc_engine_muls(i)) for i in range(17)]
     c["e_miller"], c["e_final_exp"], c["e_f12_mul"] = e[0], e[1], e[8]
     # GLS scalar multiplication on G2: psi images, table, then per bit of the 65-bit
     # split scalars one doubling and (with probability 15/16) one table addition
@@ -57,6 +63,11 @@ def op_costs():
     # products, then per bit one cyclotomic squaring and (15/16) one product
     c["e_gt_pow"] = e[15] + 11 * e[8] + 64 * e[14] + 60 * e[8]
     c["e_g1_tab"], c["e_g1_dbl2"], c["e_csqr"], c["e_gt_tab"] = e[9], e[11], e[14], e[15] + 11 * e[8]
+    c["e_g1_add"], c["e_g2_add"], c["e_g2_dbl"] = e[16], e[5], e[4]
+    # one of the four parts of a split multiplication: G1 on a 32-bit chunk (16 windows),
+    # G2 on a 16-bit chunk (16 bits); then the last part adds the four partial results and A
+    c["e_g1_part"] = e[9] + 15 * e[10] + e[11]
+    c["e_g2_part"] = e[2] + e[3] + 16 * e[4] + 15 * e[5]
     return c
 
 
@@ -71,37 +82,59 @@ def work_model(L, b, limbs, costs):
     S = min(M, 8192 // (4 if int(limbs[:, 1:].max()) == 0 else 32))
     blocks = K * ((M + S - 1) // S)
     g2_fold = costs["e_g2_mul"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]
+    nq = 2 * K - 2
     w = {
         "k_msm_slices": nz_digits * costs["g1_madd"] + blocks * 2048 * costs["g1_add"],
         "ks_miller": K * costs["e_miller"],
-        "ks_kzg_terms": nb * (2 * K - 2) * costs["e_g2_mul"],
         "kw_hyper_terms": lM * (M // 2) * costs["g1_mul"],
     }
+    if 4 * nb * nq <= KZG_SPLIT_MAX:
+        w["ks_kzg_terms_split"] = 4 * nb * nq * costs["e_g2_part"]
+        w["ks_jac_tree<true>"] = nb * (4 * nq - 1) * costs["e_g2_add"]
+    else:
+        w["ks_kzg_terms"] = nb * nq * costs["e_g2_mul"]
     if lK >= 2 and nb * K <= AHEAD_MAX_PAIRS:
         # round 1 direct; rounds j >= 2 from terms of the arrays of round j - 1 (q = K >> j)
         qs = [K >> j for j in range(2, lK + 1)]
         g1_fold = costs["e_g1_mul"] + costs["e_g1_madd"] + costs["e_g1_to_aff"]
+        split = [nb * h for h in rounds if nb * h <= FOLD_SPLIT_MAX]
+        whole = [nb * h for h in rounds if nb * h > FOLD_SPLIT_MAX]
+        g1_sum = 3 * costs["e_g1_add"] + costs["e_g1_madd"] + costs["e_g1_to_aff"]
+        g2_sum = 3 * costs["e_g2_add"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]
         w.update({
             "ks_oa_miller": nb * 2 * rounds[0] * costs["e_miller"],
-            "kw_oa_g1terms": nb * 2 * rounds[0] * costs["g1_mul"],
+            "ks_oa_g1terms": nb * 2 * rounds[0] * costs["e_g1_mul"],
             "ks_final_exp": (2 * nb + 1) * costs["e_final_exp"],
-            "ks_f12_step": (K - 1 + 2 * nb * (rounds[0] - 1)
+            "ks_f12_tree": (K - 1 + 2 * nb * (rounds[0] - 1)
                             + sum(2 * nb * (2 * q - 1) + 4 * nb * (q - 1) for q in qs)) * costs["e_f12_mul"],
-            "ks_oa_fold": sum(nb * h for h in rounds) * (g1_fold + g2_fold),
-            "ks_oa_pterms": sum(nb * 8 * q for q in qs) * (costs["e_miller"] + costs["e_g1_mul"]),
+            "ks_jac_tree<false>": (2 * nb * (rounds[0] - 1)
+                                   + sum(2 * nb * (2 * q - 1) + 4 * nb * (q - 1) for q in qs)) * costs["e_g1_add"],
+            "ks_oa_fold": sum(whole) * (g1_fold + g2_fold),
+            "ks_oa_fold_split": sum(split) * (4 * costs["e_g1_part"] + g1_sum + 4 * costs["e_g2_part"] + g2_sum),
+            # multiples 2^{32m} (G1, 16m double doublings) and 2^{16m} (G2, 16m doublings), m = 1..3,
+            # of the whole arrays of the split rounds
+            "ks_fold_mults": 2 * sum(split) * (96 * costs["e_g1_dbl2"] + 3 * costs["e_g1_to_aff"]
+                                               + 96 * costs["e_g2_dbl"] + 3 * costs["e_g2_to_aff"]),
+            "ks_oa_pterms": sum(nb * 8 * q for q in qs) * costs["e_miller"],
+            "ks_oa_g1terms_split": sum(nb * 8 * (K >> (j + 1)) * (4 * costs["e_g1_part"] + 3 * costs["e_g1_add"])
+                                       for j in range(1, lK) if nb * (K >> j) <= FOLD_SPLIT_MAX),
+            "ks_oa_g1terms_next": sum(nb * 8 * (K >> (j + 1)) * costs["e_g1_mul"]
+                                      for j in range(1, lK) if nb * (K >> j) > FOLD_SPLIT_MAX),
             "ks_final_exp2": len(qs) * 6 * nb * costs["e_final_exp"],
+            # the G1 groups to affine form, with their multiples 2^{32m} (16m double doublings)
+            "ks_g1_finish": len(qs) * (2 * nb * costs["e_g1_to_aff"]
+                                       + 4 * nb * (96 * costs["e_g1_dbl2"] + 4 * costs["e_g1_to_aff"])),
             # four-part split multiplications: the whole work plus three more tables each
             "ks_oa_combine_split": len(qs) * 4 * nb * (costs["e_gt_pow"] + 3 * costs["e_gt_tab"]
                                                        + costs["e_g1_mul"] + 3 * costs["e_g1_tab"]),
             "ks_oa_gt_combine8": len(qs) * 2 * nb * 8 * costs["e_f12_mul"],
             "ks_gt_sqr_mults": len(qs) * 4 * nb * 96 * costs["e_csqr"],
-            "ks_g1_dbl_mults": len(qs) * 4 * nb * (48 * costs["e_g1_dbl2"] + 3 * costs["e_g1_to_aff"]),
         })
     else:
         w.update({
             "ks_oa_miller": sum(nb * 2 * h for h in rounds) * costs["e_miller"],
             "ks_final_exp": (2 * lK * nb + 1) * costs["e_final_exp"],
-            "ks_f12_step": (K - 1 + sum(2 * nb * (h - 1) for h in rounds)) * costs["e_f12_mul"],
+            "ks_f12_tree": (K - 1 + sum(2 * nb * (h - 1) for h in rounds)) * costs["e_f12_mul"],
             "ks_oa_fold_g2": sum(nb * h for h in rounds) * g2_fold,
             "kw_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
             "kw_oa_g1terms": sum(nb * 2 * h for h in rounds) * costs["g1_mul"],

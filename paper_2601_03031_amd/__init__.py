@@ -13,6 +13,24 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libvc.so")
 
+# open-all runs on the caller's stream and five side streams; HIP maps streams onto
+# GPU_MAX_HW_QUEUES hardware queues per process (default 4), and streams that share a queue
+# run one after the other.  Raised to 8 here; takes effect only before the process first
+# uses the device.
+HW_QUEUES = 8
+
+
+def _raise_hw_queues() -> None:
+    try:
+        cur = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+    except ValueError:
+        cur = 4
+    if cur < HW_QUEUES:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
+
+
+_raise_hw_queues()
+
 VC_OK, VC_EINVAL, VC_ENOMEM, VC_EDEVICE, VC_ENOTIMPL, VC_ECHALLENGE = 0, -1, -2, -3, -4, -5
 
 _lib = None

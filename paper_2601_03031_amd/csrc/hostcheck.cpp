@@ -600,6 +600,7 @@ API uint64_t hc_engine_muls(int which) {
     case 13: return prog_muls(slp::PROG_G1_AFF);
     case 14: return prog_muls(slp::PROG_F12_CSQR);
     case 15: return prog_muls(slp::PROG_F12_FROB1) + prog_muls(slp::PROG_F12_FROB2) + prog_muls(slp::PROG_F12_FROB3);
+    case 16: return prog_muls(slp::PROG_G1_ADD);
   }
   return 0;
 }

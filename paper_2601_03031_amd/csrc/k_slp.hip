@@ -414,20 +414,24 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold(const g1_aff *Ain, const fe 
   g1_job(S, &d1, Ain + k * K + h + i, X + slot, Ain + k * K + i, Aout + k * K + i, nullptr);
 }
 
-// The next round's terms (oa_terms.hpp): blocks [0, nb 8q) run the Miller loops into
-// F[out], blocks [nb 8q, 2 nb 8q) the G1 terms b[v] A[a] into S1[out] (Jacobian).
-__global__ void __launch_bounds__(SLP_T) ks_oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64_t nb,
-                                                     uint64_t q, fp12 *F, g1_jac *S1) {
-  __shared__ f29 S[imax<slp::ML_NSLOT, G1_SLOTS>::v];
+// The next round's terms (oa_terms.hpp): the Miller loops into F[out], a workgroup per term
+__global__ void __launch_bounds__(SLP_T) ks_oa_pterms(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q,
+                                                     fp12 *F) {
+  __shared__ f29 S[slp::ML_NSLOT];
+  uint64_t id = blockIdx.x;
+  if (id >= nb * 8 * q) return;
+  oat::Term tm = oat::term(id, K, nb, q);
+  miller_one(S, A + tm.a, V + tm.v, F + tm.out);
+}
+
+// The G1 terms b[v] A[a] of the next round into S1[out] (Jacobian), a workgroup per term
+__global__ void __launch_bounds__(SLP_T) ks_oa_g1terms_next(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t q,
+                                                           g1_jac *S1) {
+  __shared__ f29 S[G1_SLOTS];
   __shared__ glv::Dec d1;
-  uint64_t id = blockIdx.x, n = nb * 8 * q;
-  if (id >= 2 * n) return;
-  if (id < n) {
-    oat::Term tm = oat::term(id, K, nb, q);
-    miller_one(S, A + tm.a, V + tm.v, F + tm.out);
-    return;
-  }
-  oat::Term tm = oat::term(id - n, K, nb, q);
+  uint64_t id = blockIdx.x;
+  if (id >= nb * 8 * q) return;
+  oat::Term tm = oat::term(id, K, nb, q);
   g1_job(S, &d1, A + tm.a, B + tm.v, nullptr, nullptr, S1 + tm.out);
 }
 
@@ -461,24 +465,31 @@ __device__ __forceinline__ uint64_t seg_index(uint64_t s, uint64_t seg, uint64_t
   return (s / seg) * segstride + s % seg;
 }
 
-// M[3 s + m - 1] = 2^{32 m} P_s (affine), P_s as in seg_index, a workgroup per (s, m), m = 1, 2, 3
-__global__ void __launch_bounds__(SLP_T) ks_g1_dbl_mults(const g1_aff *P, uint64_t seg, uint64_t segstride, uint64_t n,
-                                                        g1_aff *M) {
-  __shared__ f29 S[G1_SLOTS];
-  uint64_t id = blockIdx.x;
-  if (id >= 3 * n) return;
-  uint64_t s = id / 3, m = id % 3 + 1;
-  const g1_aff *Ps = P + seg_index(s, seg, segstride);
+// 2^{32 m} P (affine) by 16 m double doublings on the engine
+__device__ void g1_dbl_mult(f29 *S, const g1_aff *P, int m, g1_aff *o) {
   const int t = threadIdx.x;
-  g1_aff *o = M + 3 * s + m - 1;
-  bool inf = g1_inf(*Ps);
+  bool inf = g1_inf(*P);
   if (!inf) {
     load_consts<slp::G1_NCONST>(S, slp::G1_CBASE, slp::G1_CONSTS);
-    if (t < 3) S[slp::G1_T_0 + t] = slp::to29(t == 2 ? f_one<FpP>() : t ? Ps->y : Ps->x);
+    if (t < 3) S[slp::G1_T_0 + t] = slp::to29(t == 2 ? f_one<FpP>() : t ? P->y : P->x);
     __syncthreads();
-    for (int i = 0; i < 16 * (int)m; i++) slp::run1(S, slp::PROG_G1_DBL2, 0, 0, 0);
+    for (int i = 0; i < 16 * m; i++) slp::run1(S, slp::PROG_G1_DBL2, 0, 0, 0);
   }
   g1_store_aff(S, inf, o);
+}
+
+// 2^{16 m} Q (affine) by 16 m doublings on the engine
+__device__ void g2_dbl_mult(f29 *S, const g2_aff *Q, int m, g2_aff *o) {
+  const int t = threadIdx.x;
+  bool inf = g2_inf(*Q);
+  if (!inf) {
+    load_consts<slp::G2_NCONST>(S, slp::G2_CBASE, slp::G2_CONSTS);
+    const fe *q = reinterpret_cast<const fe *>(Q);
+    if (t < 6) S[slp::G2_T_0 + t] = t < 4 ? slp::to29(q[t]) : slp::to29(t == 4 ? f_one<FpP>() : fe_zero());
+    __syncthreads();
+    for (int i = 0; i < 16 * m; i++) slp::run1(S, slp::PROG_G2_DBL, 0, 0, 0);
+  }
+  g2_store_aff(S, inf, o);
 }
 
 // M[3 s + m - 1] = 2^{16 m} Q_s (affine), Q_s as in seg_index, a workgroup per (s, m), m = 1, 2, 3
@@ -488,17 +499,35 @@ __global__ void __launch_bounds__(SLP_T) ks_g2_dbl_mults(const g2_aff *Q, uint64
   uint64_t id = blockIdx.x;
   if (id >= 3 * n) return;
   uint64_t s = id / 3, m = id % 3 + 1;
-  const g2_aff *Qs = Q + seg_index(s, seg, segstride);
+  g2_dbl_mult(S, Q + seg_index(s, seg, segstride), (int)m, M + 3 * s + m - 1);
+}
+
+// 2^{32 m} P (affine) for a Jacobian P (m = 0: P itself), on the engine
+__device__ void g1_jac_mult_aff(f29 *S, const g1_jac *P, int m, g1_aff *o) {
   const int t = threadIdx.x;
-  bool inf = g2_inf(*Qs);
+  const fe *pj = reinterpret_cast<const fe *>(P);
+  bool inf = fe_is_zero(pj[2]);
   if (!inf) {
-    load_consts<slp::G2_NCONST>(S, slp::G2_CBASE, slp::G2_CONSTS);
-    const fe *q = reinterpret_cast<const fe *>(Qs);
-    if (t < 6) S[slp::G2_T_0 + t] = t < 4 ? slp::to29(q[t]) : slp::to29(t == 4 ? f_one<FpP>() : fe_zero());
+    load_consts<slp::G1_NCONST>(S, slp::G1_CBASE, slp::G1_CONSTS);
+    if (t < 3) S[slp::G1_T_0 + t] = slp::to29(pj[t]);
     __syncthreads();
-    for (int i = 0; i < 16 * (int)m; i++) slp::run1(S, slp::PROG_G2_DBL, 0, 0, 0);
+    for (int i = 0; i < 16 * m; i++) slp::run1(S, slp::PROG_G1_DBL2, 0, 0, 0);
   }
-  g2_store_aff(S, inf, M + 3 * s + m - 1);
+  g1_store_aff(S, inf, o);
+}
+
+// both multiples of a split fold in one launch: blocks [0, 3n) M1 from the G1 points, blocks
+// [3n, 6n) M2 from the G2 points (as in ks_g1_dbl_mults, ks_g2_dbl_mults)
+__global__ void __launch_bounds__(SLP_T) ks_fold_mults(const g1_aff *P, const g2_aff *Q, uint64_t seg, uint64_t segstride,
+                                                      uint64_t n, g1_aff *M1, g2_aff *M2) {
+  __shared__ f29 S[imax<G1_SLOTS, G2_SLOTS>::v];
+  uint64_t id = blockIdx.x;
+  if (id >= 6 * n) return;
+  bool g2 = id >= 3 * n;
+  if (g2) id -= 3 * n;
+  uint64_t s = id / 3, m = id % 3 + 1;
+  if (g2) g2_dbl_mult(S, Q + seg_index(s, seg, segstride), (int)m, M2 + 3 * s + m - 1);
+  else g1_dbl_mult(S, P + seg_index(s, seg, segstride), (int)m, M1 + 3 * s + m - 1);
 }
 
 // of the four parts of one multiplication, the workgroup that finishes last returns true
@@ -517,7 +546,8 @@ __device__ bool last_of_four(uint32_t *cnt, uint32_t *flag) {
   return last;
 }
 
-// The fold of round j with every multiplication split in four parts run in parallel:
+// The fold of round j with every multiplication split in four parts run in parallel (the
+// multiples M1, M2 cover the whole arrays, M[3 (k 2h + i') + p - 1] for index i' of batch k):
 // blocks [0, 4 nb h): part p of x A[h + i] on the base 2^{32 p} A[h + i] (M1, p > 0) with
 // the p-th 32-bit chunk of the GLV split of x into J1[4 s + p]; blocks [4 nb h, 8 nb h):
 // part p of x^{-1} V[h + i] on 2^{16 p} V[h + i] (M2) with bits [16 p, 16 p + 16) (17 for
@@ -543,8 +573,8 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_split(const g1_aff *Ain, con
   slp::DevCtx c{S};
   if (!g2) {
     if (part == 0 && t == 32) Bout[k * K + i] = fr_add(Bin[k * K + i], fr_mul(Bin[k * K + h + i], Xinv[slot]));
-    g1_job(S, &d1, part ? M1 + 3 * s + part - 1 : Ain + k * K + h + i, X + slot, nullptr, nullptr, J1 + 4 * s + part,
-           part);
+    g1_job(S, &d1, part ? M1 + 3 * (k * 2 * h + h + i) + part - 1 : Ain + k * K + h + i, X + slot, nullptr, nullptr,
+           J1 + 4 * s + part, part);
     if (!last_of_four(cnt + s, &flag)) return;
     // sum of the parts (in the table slots) and A[i]
     const fe *pj = reinterpret_cast<const fe *>(J1 + 4 * s);
@@ -558,8 +588,8 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_split(const g1_aff *Ain, con
     g1_store_aff(S, inf, Aout + k * K + i);
     return;
   }
-  g2_job(S, &d2, part ? M2 + 3 * s + part - 1 : Vin + k * K + h + i, Xinv + slot, nullptr, nullptr, J2 + 4 * s + part,
-         16 * part, part < 3 ? 16 : 17);
+  g2_job(S, &d2, part ? M2 + 3 * (k * 2 * h + h + i) + part - 1 : Vin + k * K + h + i, Xinv + slot, nullptr, nullptr,
+         J2 + 4 * s + part, 16 * part, part < 3 ? 16 : 17);
   if (!last_of_four(cnt + n + s, &flag)) return;
   const fe *pj = reinterpret_cast<const fe *>(J2 + 4 * s);
   if (t < 24) S[slp::G2_TB1_0 + t] = slp::to29(pj[t]);
@@ -574,6 +604,35 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_split(const g1_aff *Ain, con
   if (!g2_inf(Vin[k * K + i])) g2m::add_affine(c, inf, G2_ABASE, S[slp::G2_CBASE + 1], S[slp::G2_CBASE]);
   g2_store_aff(S, inf, Vout + k * K + i);
 }
+
+// The G1 terms b[v] A[a] of the next round (oa_terms.hpp, arrays of length 4q) with each
+// multiplication split in four parts: part p on the multiple M[3 (k 4q + a') + p - 1] =
+// 2^{32 p} A[k K + a'] (p > 0) with the p-th 32-bit chunk of the GLV split of b[v], into
+// J[4 term + p]; the last part to finish writes the sum to S1[out] (Jacobian)
+__global__ void __launch_bounds__(SLP_T) ks_oa_g1terms_split(const g1_aff *A, const fe *B, const g1_aff *M, uint64_t K,
+                                                            uint64_t nb, uint64_t q, g1_jac *J, uint32_t *cnt, g1_jac *S1) {
+  __shared__ f29 S[G1_SLOTS];
+  __shared__ glv::Dec d1;
+  __shared__ uint32_t flag;
+  uint64_t id = blockIdx.x;
+  if (id >= 4 * nb * 8 * q) return;
+  const int t = threadIdx.x;
+  uint64_t term = id >> 2, k = term / (8 * q);
+  int part = (int)(id & 3);
+  oat::Term tm = oat::term(term, K, nb, q);
+  g1_job(S, &d1, part ? M + 3 * (k * 4 * q + (tm.a - k * K)) + part - 1 : A + tm.a, B + tm.v, nullptr, nullptr,
+         J + 4 * term + part, part);
+  if (!last_of_four(cnt + term, &flag)) return;
+  const fe *pj = reinterpret_cast<const fe *>(J + 4 * term);
+  if (t < 12) S[slp::G1_TB1_0 + t] = slp::to29(pj[t]);
+  __syncthreads();
+  slp::DevCtx c{S};
+  bool inf = true;
+  for (int p = 0; p < 4; p++) g1m::add_jac(c, inf, slp::G1_TB1_0 + 3 * p, fe_is_zero(J[4 * term + p].Z));
+  fe *o = reinterpret_cast<fe *>(S1 + tm.out);
+  if (t < 3) o[t] = inf ? (t < 2 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[slp::G1_T_0 + t]));
+}
+
 
 // The x-dependent part of a round taken ahead, each multiplication split in four parts run
 // in parallel: for s < 4 nb and part p < 4, k_s = (s odd ? k_odd : k_even)[(s >> 2) kstride];
@@ -638,19 +697,43 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_gt_combine8(const fp12 *U, const 
 
 // final exponentiations of two strided lists: job s < n0 takes in0[s st0] to out0[s], the
 // others in1[(s - n0) st1] to out1[s - n0]
+// final exponentiation of one F_p12 element on the engine
+__device__ void fe_job(f29 *S, const fp12 *in, fp12 *out) {
+  int t = threadIdx.x;
+  const fe *src = reinterpret_cast<const fe *>(in);
+  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
+  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
+  __syncthreads();
+  slp::run_seq<4>(S, slp::FE_SEQ, slp::FE_SEQ_LEN, slp::FE_NSLOT, slp::FE_t, slp::FE_tinv);
+  fe *dst = reinterpret_cast<fe *>(out);
+  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(slp::FE_RESULT) + t]));
+}
+
 __global__ void __launch_bounds__(SLP_T) ks_final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1,
                                                       uint64_t st1, uint64_t n1, fp12 *out1) {
   __shared__ f29 S[FE_SLOTS];
   uint64_t s = blockIdx.x;
   if (s >= n0 + n1) return;
-  int t = threadIdx.x;
-  const fe *src = reinterpret_cast<const fe *>(s < n0 ? in0 + s * st0 : in1 + (s - n0) * st1);
-  if (t < 12) S[FE_BUF(0) + t] = slp::to29(src[t]);
-  load_consts<slp::FE_NCONST>(S, slp::FE_CBASE, slp::FE_CONSTS);
-  __syncthreads();
-  slp::run_seq<4>(S, slp::FE_SEQ, slp::FE_SEQ_LEN, slp::FE_NSLOT, slp::FE_t, slp::FE_tinv);
-  fe *dst = reinterpret_cast<fe *>(s < n0 ? out0 + s : out1 + (s - n0));
-  if (t < 12) dst[t] = slp::from29(slp::canon29(S[FE_BUF(slp::FE_RESULT) + t]));
+  fe_job(S, s < n0 ? in0 + s * st0 : in1 + (s - n0) * st1, s < n0 ? out0 + s : out1 + (s - n0));
+}
+
+// The reduced G1 groups of the terms taken ahead (oa_terms.hpp, segment sums in PS) made
+// ready for the combine: blocks [0, 2 nb): U group (2k + side) to PU1 (affine); blocks
+// [2 nb, 18 nb): XY group s = 4k + g as PX1[s] (affine, m = 0) and PX1m[3 s + m - 1] =
+// 2^{32 m} PX1[s] (m = 1..3)
+__global__ void __launch_bounds__(SLP_T) ks_g1_finish(const g1_jac *PS, uint64_t nb, uint64_t q, g1_aff *PU1, g1_aff *PX1,
+                                                     g1_aff *PX1m) {
+  __shared__ f29 S[G1_SLOTS];
+  uint64_t id = blockIdx.x;
+  if (id >= 18 * nb) return;
+  if (id < 2 * nb) {
+    g1_jac_mult_aff(S, PS + id * 2 * q, 0, PU1 + id);
+    return;
+  }
+  id -= 2 * nb;
+  uint64_t s = id >> 2;
+  int m = (int)(id & 3);
+  g1_jac_mult_aff(S, PS + nb * 4 * q + s * q, m, m ? PX1m + 3 * s + m - 1 : PX1 + s);
 }
 
 namespace ks {
@@ -674,18 +757,28 @@ void oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_
              const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
   LAUNCH(ks_oa_fold, dim3((unsigned)(2 * nb * h)), dim3(SLP_T), 0, Ain, Bin, Aout, Bout, Vin, Vout, X, Xinv, K, nb, h, j, lK);
 }
-void oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, g1_jac *S1,
-               hipStream_t st) {
-  LAUNCH(ks_oa_pterms, dim3((unsigned)(2 * nb * 8 * q)), dim3(SLP_T), 0, A, V, B, K, nb, q, F, S1);
+void oa_pterms(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, hipStream_t st) {
+  LAUNCH(ks_oa_pterms, dim3((unsigned)(nb * 8 * q)), dim3(SLP_T), 0, A, V, K, nb, q, F);
 }
 void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st) {
   if (n) LAUNCH(ks_gt_sqr_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, G, n, M);
 }
-void g1_dbl_mults(const g1_aff *P, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M, hipStream_t st) {
-  if (n) LAUNCH(ks_g1_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, P, seg, segstride, n, M);
-}
 void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st) {
   if (n) LAUNCH(ks_g2_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, Q, seg, segstride, n, M);
+}
+void g1_finish(const g1_jac *PS, uint64_t nb, uint64_t q, g1_aff *PU1, g1_aff *PX1, g1_aff *PX1m, hipStream_t st) {
+  LAUNCH(ks_g1_finish, dim3((unsigned)(18 * nb)), dim3(SLP_T), 0, PS, nb, q, PU1, PX1, PX1m);
+}
+void oa_g1terms_next(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t q, g1_jac *S1, hipStream_t st) {
+  LAUNCH(ks_oa_g1terms_next, dim3((unsigned)(nb * 8 * q)), dim3(SLP_T), 0, A, B, K, nb, q, S1);
+}
+void oa_g1terms_split(const g1_aff *A, const fe *B, const g1_aff *M, uint64_t K, uint64_t nb, uint64_t q, g1_jac *J,
+                      uint32_t *cnt, g1_jac *S1, hipStream_t st) {
+  LAUNCH(ks_oa_g1terms_split, dim3((unsigned)(4 * nb * 8 * q)), dim3(SLP_T), 0, A, B, M, K, nb, q, J, cnt, S1);
+}
+void fold_mults(const g1_aff *P, const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M1, g2_aff *M2,
+                hipStream_t st) {
+  if (n) LAUNCH(ks_fold_mults, dim3((unsigned)(6 * n)), dim3(SLP_T), 0, P, Q, seg, segstride, n, M1, M2);
 }
 void oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
                    const fe *Xinv, const g1_aff *M1, const g2_aff *M2, g1_jac *J1, g2_jac *J2, uint32_t *cnt, uint64_t K,

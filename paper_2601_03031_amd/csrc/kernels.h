@@ -90,8 +90,13 @@ void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st);
 // final exponentiations of two strided lists
 void oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
              const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
-void oa_pterms(const g1_aff *A, const g2_aff *V, const fe *B, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, g1_jac *S1,
-               hipStream_t st);
+void oa_pterms(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, hipStream_t st);
+// the G1 terms of the next round: whole multiplications, or split in four parts on the
+// multiples M (whole arrays of length 4q, as made by fold_mults) with partials J and nb 8q
+// arrival counters
+void oa_g1terms_next(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t q, g1_jac *S1, hipStream_t st);
+void oa_g1terms_split(const g1_aff *A, const fe *B, const g1_aff *M, uint64_t K, uint64_t nb, uint64_t q, g1_jac *J,
+                      uint32_t *cnt, g1_jac *S1, hipStream_t st);
 void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1, uint64_t st1, uint64_t n1, fp12 *out1,
                 hipStream_t st);
 // time-split multiplications: M[3 s + m - 1] = G[s]^{2^{16 m}}, = 2^{32 m} P[s] (m = 1..3);
@@ -99,8 +104,13 @@ void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp
 // product of U with the 8 G_T parts of each side
 void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st);
 // (the points of the multiples are P[(s / seg) segstride + s % seg], s < n)
-void g1_dbl_mults(const g1_aff *P, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M, hipStream_t st);
 void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st);
+// the reduced G1 groups of the terms taken ahead made ready for the combine: affine (PU1,
+// PX1) and PX1m[3 s + m - 1] = 2^{32 m} PX1[s]
+void g1_finish(const g1_jac *PS, uint64_t nb, uint64_t q, g1_aff *PU1, g1_aff *PX1, g1_aff *PX1m, hipStream_t st);
+// both in one launch (points P, Q at the same segmented indices)
+void fold_mults(const g1_aff *P, const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M1, g2_aff *M2,
+                hipStream_t st);
 // the fold with four-part split multiplications on the multiples M1 = 2^{32 m} A[h + i],
 // M2 = 2^{16 m} V[h + i]; partial results in J1, J2; 2 nb h arrival counters
 void oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,

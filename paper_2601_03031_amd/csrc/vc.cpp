@@ -125,8 +125,8 @@ struct vc_params {
   void *ws = nullptr;       // grow-only scratch shared by calls on these params
   size_t ws_size = 0;
   // side streams (default priority) and fork/join events for independent phases
-  hipStream_t side[3] = {nullptr, nullptr, nullptr};
-  hipEvent_t ev[16] = {};
+  hipStream_t side[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[20] = {};
   // arrival counters of the one-launch reduction trees: zeroed once, each tree leaves its
   // counters zero again (grow-only)
   uint32_t *cnt = nullptr;
@@ -419,7 +419,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   const bool ahead = lK >= 2 && nb * K <= AHEAD_MAX_PAIRS;
   const uint64_t nterm = ahead ? 2 * nb * K : 0;
   size_t o_A2 = t.take<g1_aff>(nb * K), o_V2 = t.take<g2_aff>(nb * K), o_B2 = t.take<fe>(nb * K);
-  size_t o_F2 = t.take<fp12>(nterm), o_PS = t.take<g1_jac>(2 * nterm);
+  size_t o_F2 = t.take<fp12>(2 * nterm), o_PS = t.take<g1_jac>(2 * nterm);
   size_t o_PU = t.take<fp12>(ahead ? 4 * nb : 0), o_PX = t.take<fp12>(ahead ? 8 * nb : 0);
   size_t o_PXm = t.take<fp12>(ahead ? 24 * nb : 0), o_PE = t.take<fp12>(ahead ? 16 * nb : 0);
   size_t o_PU1 = t.take<g1_aff>(ahead ? 4 * nb : 0), o_PX1 = t.take<g1_aff>(ahead ? 8 * nb : 0);
@@ -427,8 +427,9 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // split folds: multiples of the halves A[h + i], V[h + i] and the four partial results
   auto split_round = [&](uint32_t j) { return ahead && j <= lK && nb * (K >> j) <= FOLD_SPLIT_MAX; };
   const uint64_t nsplit = ahead ? std::min<uint64_t>(nb * K / 2, FOLD_SPLIT_MAX) : 0;
-  size_t o_FM1 = t.take<g1_aff>(3 * nsplit), o_FM2 = t.take<g2_aff>(3 * nsplit);
-  size_t o_FJ1 = t.take<g1_jac>(4 * nsplit), o_FJ2 = t.take<g2_jac>(4 * nsplit);
+  // (multiples of whole arrays, one set per round parity; the G1 terms split likewise use them)
+  size_t o_FM1 = t.take<g1_aff>(2 * 6 * nsplit), o_FM2 = t.take<g2_aff>(2 * 6 * nsplit);
+  size_t o_FJ1 = t.take<g1_jac>(4 * nsplit), o_FJ2 = t.take<g2_jac>(4 * nsplit), o_GJ = t.take<g1_jac>(16 * nsplit);
   int rc = ensure_ws(pp, t.off);
   if (rc) { vc_proofs_free(pr); return rc; }
   void *ws = pp->ws;
@@ -446,7 +447,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   g1_aff *Ab[2] = {A, at<g1_aff>(ws, o_A2)};
   g2_aff *Vb[2] = {V, at<g2_aff>(ws, o_V2)};
   fe *Bb[2] = {B, at<fe>(ws, o_B2)};
-  fp12 *F2 = at<fp12>(ws, o_F2);
+  fp12 *F2[2] = {at<fp12>(ws, o_F2), at<fp12>(ws, o_F2) + nterm};
   g1_jac *PS[2] = {at<g1_jac>(ws, o_PS), at<g1_jac>(ws, o_PS) + nterm};
   fp12 *PU[2] = {at<fp12>(ws, o_PU), at<fp12>(ws, o_PU) + 2 * nb};
   fp12 *PX[2] = {at<fp12>(ws, o_PX), at<fp12>(ws, o_PX) + 4 * nb};
@@ -456,19 +457,22 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   g1_aff *PU1[2] = {at<g1_aff>(ws, o_PU1), at<g1_aff>(ws, o_PU1) + 2 * nb};
   g1_aff *PX1[2] = {at<g1_aff>(ws, o_PX1), at<g1_aff>(ws, o_PX1) + 4 * nb};
   g1_jac *PM = at<g1_jac>(ws, o_PM);
-  g1_aff *FM1 = at<g1_aff>(ws, o_FM1);
-  g2_aff *FM2 = at<g2_aff>(ws, o_FM2);
-  g1_jac *FJ1 = at<g1_jac>(ws, o_FJ1);
+  g1_aff *FM1[2] = {at<g1_aff>(ws, o_FM1), at<g1_aff>(ws, o_FM1) + 6 * nsplit};
+  g2_aff *FM2[2] = {at<g2_aff>(ws, o_FM2), at<g2_aff>(ws, o_FM2) + 6 * nsplit};
+  g1_jac *FJ1 = at<g1_jac>(ws, o_FJ1), *GJ = at<g1_jac>(ws, o_GJ);
   g2_jac *FJ2 = at<g2_jac>(ws, o_FJ2);
   // reduction-tree counters: round-1 (or every direct round) products, and per stream the
   // U and XY groups of the terms taken ahead (F_p12 on side stream 3, G1 on the caller's)
   const uint64_t c_dir = 2 * nb * tree_counters(K / 2), c_u = 2 * nb * tree_counters(K / 2),
                  c_xy = 4 * nb * tree_counters(K / 4);
   const uint64_t c_kzg = kzg_split ? nb * tree_counters(4 * nq) : 0;
-  if (int rc2 = ensure_cnt(pp, 2 * c_dir + 2 * (c_u + c_xy) + 2 * nsplit + c_kzg)) { vc_proofs_free(pr); return rc2; }
-  uint32_t *cnt_dir = pp->cnt, *cnt_fu = cnt_dir + c_dir, *cnt_fxy = cnt_fu + c_u, *cnt_gu = cnt_fxy + c_xy,
-           *cnt_gxy = cnt_gu + c_u, *cnt_fold = cnt_gxy + c_xy, *cnt_kzg = cnt_fold + 2 * nsplit,
-           *cnt_g1dir = cnt_kzg + c_kzg;
+  if (int rc2 = ensure_cnt(pp, 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg)) { vc_proofs_free(pr); return rc2; }
+  // (the counters of the terms' trees per round parity, whose streams run concurrently)
+  uint32_t *cnt_dir = pp->cnt, *cnt_t = cnt_dir + c_dir;
+  uint32_t *cnt_fu[2] = {cnt_t, cnt_t + 2 * (c_u + c_xy)}, *cnt_fxy[2] = {cnt_fu[0] + c_u, cnt_fu[1] + c_u};
+  uint32_t *cnt_gu[2] = {cnt_fxy[0] + c_xy, cnt_fxy[1] + c_xy}, *cnt_gxy[2] = {cnt_gu[0] + c_u, cnt_gu[1] + c_u};
+  uint32_t *cnt_fold = cnt_t + 4 * (c_u + c_xy), *cnt_kzg = cnt_fold + 2 * nsplit, *cnt_g1dir = cnt_kzg + c_kzg,
+           *cnt_g1s = cnt_g1dir + c_dir;
 
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
@@ -510,49 +514,61 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // x_j, x_j^{-1} and multiplies: the Miller loops and final exponentiations leave the
   // chain of dependent rounds.  Then side stream 2 runs the fused folds and side stream 3
   // the terms; each launch pairs the G1 and the pairing-side work of its step.
-  hipStream_t sg = s2, sf = pp->side[2];
+  // Streams of the ahead mode: side 2 the folds and the multiples, sides 3 and 4 the
+  // pairing side of the terms of even and odd rounds (Miller loops, products, final
+  // exponentiations), side 5 their G1 side; the caller's stream combines and hashes.
+  hipStream_t sg = s2, sf = pp->side[2], sfp[2] = {pp->side[2], pp->side[3]}, sq = pp->side[4];
   kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
-  // multiples 2^{32 m} A[h + i], 2^{16 m} V[h + i] (m = 1..3) of the arrays of round j for
-  // its split fold, on the fold stream
-  auto launch_fold_mults = [&](uint32_t j) {
-    const uint64_t h = K >> j;
+  // multiples 2^{32 m} A[i], 2^{16 m} V[i] (m = 1..3) of the whole arrays of round j (for its
+  // split fold and the split G1 terms of round j + 1), into set j & 1 (round 1: on side
+  // stream 1 before Step 2, later rounds on the fold stream)
+  auto launch_fold_mults = [&](uint32_t j, hipStream_t s) {
+    const uint64_t n = K >> (j - 1);
     const int cur = (j - 1) & 1;
-    ks::g1_dbl_mults(Ab[cur] + h, h, K, nb * h, FM1, sg);
-    ks::g2_dbl_mults(Vb[cur] + h, h, K, nb * h, FM2, sg);
+    ks::fold_mults(Ab[cur], Vb[cur], n, K, nb * n, FM1[j & 1], FM2[j & 1], s);
   };
   if (split_round(1)) {
-    if (int rc2 = stream_wait(pp, 14, st, sg)) return rc2;
-    launch_fold_mults(1);
+    if (int rc2 = stream_wait(pp, 14, st, s1)) return rc2;
+    launch_fold_mults(1, s1);
+    if (int rc2 = ev_mark(pp, 15, s1)) return rc2;
   }
   kl::fc_chunks(Cj, K, b, nb, Hq, st);
   kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
   kl::fc_r(K, b, nb, sigma, B, st);
   if (int rc2 = stream_wait(pp, 1, st, sg)) return rc2;
   if (int rc2 = stream_wait(pp, 2, st, sf)) return rc2;
-  // terms of round jn >= 2 from the arrays of round jn - 1, on side stream 3; their G1 sums
-  // are reduced on the caller's stream (launch_g1_sums), beside the final exponentiations.
-  // Both then take the multiples for the four-part split multiplications of the combine.
+  if (ahead) {
+    if (int rc2 = stream_wait(pp, 17, st, sfp[1])) return rc2;
+    if (int rc2 = stream_wait(pp, 18, st, sq)) return rc2;
+  }
+  // terms of round jn >= 2 from the arrays of round jn - 1 (one buffer set per round parity):
+  // the pairing side (Miller loops, group products, final exponentiations, squaring
+  // multiples) on side stream 3 + (jn & 1), ready at event 6 + (jn & 1) ...
   auto launch_terms = [&](uint32_t jn) -> int {
     uint64_t q = K >> jn;
     int par = jn & 1, src = (jn - 2) & 1;
-    ks::oa_pterms(Ab[src], Vb[src], Bb[src], K, nb, q, F2, PS[par], sf);
-    if (int rc2 = ev_mark(pp, 8 + par, sf)) return rc2;
-    ks::f12_reduce(F2, 2 * nb, 2 * q, 2 * q, cnt_fu, sf);
-    ks::f12_reduce(F2 + nb * 4 * q, 4 * nb, q, q, cnt_fxy, sf);
-    ks::final_exp2(F2, 2 * q, 2 * nb, PU[par], F2 + nb * 4 * q, q, 4 * nb, PX[par], sf);
-    ks::gt_sqr_mults(PX[par], 4 * nb, PXm[par], sf);
-    return ev_mark(pp, 6 + par, sf);
+    hipStream_t s = sfp[par];
+    ks::oa_pterms(Ab[src], Vb[src], K, nb, q, F2[par], s);
+    ks::f12_reduce(F2[par], 2 * nb, 2 * q, 2 * q, cnt_fu[par], s);
+    ks::f12_reduce(F2[par] + nb * 4 * q, 4 * nb, q, q, cnt_fxy[par], s);
+    ks::final_exp2(F2[par], 2 * q, 2 * nb, PU[par], F2[par] + nb * 4 * q, q, 4 * nb, PX[par], s);
+    ks::gt_sqr_mults(PX[par], 4 * nb, PXm[par], s);
+    return ev_mark(pp, 6 + par, s);
   };
-  auto launch_g1_sums = [&](uint32_t jn) -> int {
+  // ... and the G1 side (terms, split in four parts when the arrays of round jn - 1 have
+  // multiples, group sums, affine forms and multiples) on side stream 5, ready at event
+  // 8 + (jn & 1)
+  auto launch_g1terms = [&](uint32_t jn) -> int {
     uint64_t q = K >> jn;
-    int par = jn & 1;
-    if (int rc2 = ev_wait(pp, 8 + par, st)) return rc2;
-    ks::g1_tree(PS[par], 2 * nb, 2 * q, 2 * q, cnt_gu, st);
-    ks::g1_tree(PS[par] + nb * 4 * q, 4 * nb, q, q, cnt_gxy, st);
-    kl::g1_to_aff(PS[par], 2 * q, 2 * nb, PU1[par], 1, st);
-    kl::g1_to_aff(PS[par] + nb * 4 * q, q, 4 * nb, PX1[par], 1, st);
-    ks::g1_dbl_mults(PX1[par], 4 * nb, 0, 4 * nb, PX1m[par], st);
-    return VC_OK;
+    int par = jn & 1, src = (jn - 2) & 1;
+    if (split_round(jn - 1))
+      ks::oa_g1terms_split(Ab[src], Bb[src], FM1[(jn - 1) & 1], K, nb, q, GJ, cnt_g1s, PS[par], sq);
+    else
+      ks::oa_g1terms_next(Ab[src], Bb[src], K, nb, q, PS[par], sq);
+    ks::g1_tree(PS[par], 2 * nb, 2 * q, 2 * q, cnt_gu[par], sq);
+    ks::g1_tree(PS[par] + nb * 4 * q, 4 * nb, q, q, cnt_gxy[par], sq);
+    ks::g1_finish(PS[par], nb, q, PU1[par], PX1[par], PX1m[par], sq);
+    return ev_mark(pp, 8 + par, sq);
   };
   for (uint32_t j = 1; j <= lK; j++) {
     const uint64_t h = K >> j;
@@ -567,8 +583,12 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       }
       kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
       if (int rc2 = ev_mark(pp, 3, sg)) return rc2;
-      if (ahead)
+      if (ahead) {
         if (int rc2 = launch_terms(2)) return rc2;
+        if (split_round(1))
+          if (int rc2 = ev_wait(pp, 15, sq)) return rc2;
+        if (int rc2 = launch_g1terms(2)) return rc2;
+      }
       ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
       ks::f12_reduce(F, 2 * nb, K / 2, h, cnt_dir, st);
       ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
@@ -577,6 +597,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       // L_j, R_j from the terms taken from the arrays of round j - 1 and x_{j-1}
       const int par = j & 1;
       if (int rc2 = ev_wait(pp, 6 + par, st)) return rc2;
+      if (int rc2 = ev_wait(pp, 8 + par, st)) return rc2;
       ks::oa_combine_split(PX[par], PXm[par], PX1[par], PX1m[par], X + (j - 2), Xinv + (j - 2), lK, nb, PE, PM, st);
       ks::oa_gt_combine8(PU[par], PE, nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
       kl::oa_g1_combine8(PU1[par], PM, nb, Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
@@ -585,20 +606,23 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     // fold with x_j into the other buffer
     if (ahead) {
       if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
+      if (j == 1 && split_round(1))
+        if (int rc2 = ev_wait(pp, 15, sg)) return rc2;
       if (split_round(j))
-        ks::oa_fold_split(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, FM1, FM2, FJ1, FJ2, cnt_fold, K, nb,
-                          h, j, lK, sg);
+        ks::oa_fold_split(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, FM1[j & 1], FM2[j & 1], FJ1, FJ2,
+                          cnt_fold, K, nb, h, j, lK, sg);
       else
         ks::oa_fold(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, K, nb, h, j, lK, sg);
       // terms of round j + 2 from the arrays of round j + 1 (just folded)
       if (j + 2 <= lK) {
-        if (int rc2 = stream_wait(pp, 10, sg, sf)) return rc2;
+        if (int rc2 = stream_wait(pp, 10, sg, sfp[j & 1])) return rc2;
         if (int rc2 = launch_terms(j + 2)) return rc2;
       }
-      if (split_round(j + 1)) launch_fold_mults(j + 1);
-      // the caller's stream idles until the terms of round j + 1 are exponentiated
-      if (j + 1 <= lK)
-        if (int rc2 = launch_g1_sums(j + 1)) return rc2;
+      if (split_round(j + 1)) launch_fold_mults(j + 1, sg);
+      if (j + 2 <= lK) {
+        if (int rc2 = stream_wait(pp, 16, sg, sq)) return rc2;
+        if (int rc2 = launch_g1terms(j + 2)) return rc2;
+      }
     } else {
       if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
       kl::glv_dec(X, nb, j, lK, gdec, sg);
@@ -608,7 +632,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
       if (int rc2 = stream_wait(pp, 12, sf, st)) return rc2;
     }
-    if (j == 1)
+    if (j == std::min<uint32_t>(2, lK))
       if (int rc2 = launch_step2()) return rc2;
   }
   if (ahead)
