@@ -113,8 +113,8 @@ def work_model(L, b, limbs, costs):
             "ks_oa_fold_split": sum(split) * (4 * costs["e_g1_part"] + g1_sum + 4 * costs["e_g2_part"] + g2_sum),
             # multiples 2^{32m} (G1, 16m double doublings) and 2^{16m} (G2, 16m doublings), m = 1..3,
             # of the whole arrays of the split rounds
-            "ks_fold_mults": 2 * sum(split) * (96 * costs["e_g1_dbl2"] + 3 * costs["e_g1_to_aff"]
-                                               + 96 * costs["e_g2_dbl"] + 3 * costs["e_g2_to_aff"]),
+            "ks_fold_mults": sum(split) * (2 * (96 * costs["e_g1_dbl2"] + 3 * costs["e_g1_to_aff"])
+                                           + 96 * costs["e_g2_dbl"] + 3 * costs["e_g2_to_aff"]),
             "ks_oa_pterms": sum(nb * 8 * q for q in qs) * costs["e_miller"],
             "ks_oa_g1terms_split": sum(nb * 8 * (K >> (j + 1)) * (4 * costs["e_g1_part"] + 3 * costs["e_g1_add"])
                                        for j in range(1, lK) if nb * (K >> j) <= FOLD_SPLIT_MAX),
@@ -127,7 +127,8 @@ def work_model(L, b, limbs, costs):
             # four-part split multiplications: the whole work plus three more tables each
             "ks_oa_combine_split": len(qs) * 4 * nb * (costs["e_gt_pow"] + 3 * costs["e_gt_tab"]
                                                        + costs["e_g1_mul"] + 3 * costs["e_g1_tab"]),
-            "ks_oa_gt_combine8": len(qs) * 2 * nb * 8 * costs["e_f12_mul"],
+            "ks_oa_combine8": len(qs) * 2 * nb * (8 * costs["e_f12_mul"] + 7 * costs["g1_add"] + costs["g1_madd"]
+                                                  + costs["g1_to_aff"]),
             "ks_gt_sqr_mults": len(qs) * 4 * nb * 96 * costs["e_csqr"],
         })
     else:

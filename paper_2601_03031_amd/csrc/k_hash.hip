@@ -26,6 +26,7 @@ __global__ void __launch_bounds__(TPB) k_trapdoor(const uint8_t *seed, uint32_t 
 // chunk digests of the batch statement: H_q over (a_i || enc(C_{a_i})) for 32 entries; a
 // workgroup of 64 per chunk, one lane per entry writes the message words (sha::Coop)
 __global__ void __launch_bounds__(64) k_fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq) {
+  CHAIN_PRIORITY();
   __shared__ uint32_t msg[FC_CHUNK * 18 + 18];
   uint64_t id = blockIdx.x;
   uint64_t qmax = (b + FC_CHUNK - 1) / FC_CHUNK;
@@ -57,6 +58,7 @@ __host__ __device__ inline size_t fc_sigma_shm(uint32_t b) {
 }
 __global__ void __launch_bounds__(64) k_fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq,
                                                 uint32_t *sigma) {
+  CHAIN_PRIORITY();
   extern __shared__ uint32_t mw[];
   uint64_t k = blockIdx.x;
   if (k >= nb) return;
@@ -84,6 +86,7 @@ __global__ void __launch_bounds__(64) k_fc_sigma(const fp12 *C, uint64_t K, uint
 // r_i = H2F(DST_FC_R, sigma_k || i), a workgroup of 64 per entry: the sparse exponent
 // vector b = sum r_i u_{a_i}
 __global__ void __launch_bounds__(64) k_fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B) {
+  CHAIN_PRIORITY();
   __shared__ uint32_t w[16 + 10 + 32], t2[16];
   uint64_t id = blockIdx.x;
   if (id >= nb * (uint64_t)b) return;
@@ -109,30 +112,13 @@ __global__ void __launch_bounds__(TPB) k_oa_lr_aff(const g1_jac *S, uint64_t K, 
   (side ? Rg1 : Lg1)[k * lK + (j - 1)] = a;
 }
 
-// (side ? R : L)[k lK] = U[2k + side] + sum_{g in {2 side, 2 side + 1}, p < 4} P[4 (4k + g) + p]
-// (affine): a block of 8 threads per (k, side) adds the 8 Jacobian parts in a tree
-__global__ void __launch_bounds__(8) k_oa_g1_combine8(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R,
-                                                     uint64_t lK) {
-  __shared__ g1_jac part[8];
-  uint64_t id = blockIdx.x;
-  if (id >= 2 * nb) return;
-  uint64_t k = id / 2, side = id % 2;
-  int t = threadIdx.x;
-  part[t] = P[4 * (4 * k + 2 * side) + t];
-  __syncthreads();
-  for (int w = 4; w >= 1; w >>= 1) {
-    if (t < w) part[t] = jac_add(part[t], part[t + w]);
-    __syncthreads();
-  }
-  if (t == 0) (side ? R : L)[k * lK] = jac_to_aff(jac_madd(part[0], U[id]));
-}
-
 // per batch: hash L_j, R_j into x_j, keep x_j and 1/x_j.  A workgroup of 64 per batch:
 // lanes encode x_{j-1} and the 28 coordinates of L_j, R_j in parallel (sha::Coop), and the
 // inverse runs on the scalar unit.
 __global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j,
                                                      uint32_t lK, const g1_aff *Lg1, const g1_aff *Rg1, fe *X, fe *Xinv,
                                                      int *err) {
+  CHAIN_PRIORITY();
   __shared__ uint32_t msg[16 + 8 + 2 * (96 + 16) + 32], t2[16];
   uint64_t k = blockIdx.x;
   if (k >= nb) return;
@@ -166,6 +152,7 @@ __global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp1
 // block-wide scans.  One block of KZG_T threads per batch, D = 2K - 1 coefficients.
 __global__ void __launch_bounds__(KZG_T) k_kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K,
                                                       uint32_t lK, fe *Q, fe *zout) {
+  CHAIN_PRIORITY();
   extern __shared__ fe sh[];  // 2 * D elements
   uint64_t k = blockIdx.x;
   uint64_t D = 2 * K - 1;
@@ -288,9 +275,6 @@ void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hip
 }
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st) {
   L1(k_oa_lr_aff, 2 * nb, S, K, nb, j, lK, Lg1, Rg1);
-}
-void oa_g1_combine8(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st) {
-  LAUNCH(k_oa_g1_combine8, dim3((unsigned)(2 * nb)), dim3(8), 0, U, P, nb, L, R, lK);
 }
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st) {

@@ -62,6 +62,7 @@ __global__ void __launch_bounds__(SLP_T) ks_miller(const g1_aff *P, uint64_t sp,
 // side 0 (L) pairs A[h+i] with V[i], side 1 (R) A[i] with V[h+i]; F[(2k+side) K/2 + i]
 __global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h,
                                                      fp12 *F) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[slp::ML_NSLOT];
   uint64_t id = blockIdx.x;
   if (id >= nb * 2 * h) return;
@@ -78,6 +79,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_miller(const g1_aff *A, const g2_
 // workgroup per pair of the first level; of two sibling nodes, the workgroup that finishes
 // second climbs to the parent (arrival counters as in k_jac_tree).
 __global__ void __launch_bounds__(SLP_T) ks_f12_tree(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[slp::FE_NSLOT + 36];
   __shared__ uint32_t arrived;
   uint64_t per = (len + 1) / 2;
@@ -127,6 +129,7 @@ __global__ void __launch_bounds__(SLP_T) ks_f12_tree(fp12 *data, uint64_t nseg, 
 // (s odd ? out1 : out0)[(s >> 1) ostride]
 __global__ void __launch_bounds__(SLP_T) ks_final_exp(const fp12 *in, uint64_t in_stride, uint64_t n, fp12 *out0, fp12 *out1,
                                                      uint64_t ostride) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[FE_SLOTS];
   uint64_t s = blockIdx.x;
   if (s >= n) return;
@@ -204,6 +207,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_g2(const g2_aff *Vin, g2_aff
 
 // terms q_m h_m of the KZG proof of v_l (Jacobian)
 __global__ void __launch_bounds__(SLP_T) ks_kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[G2_SLOTS];
   __shared__ gls::Dec dec;
   uint64_t n = 2 * K - 2;
@@ -217,6 +221,7 @@ __global__ void __launch_bounds__(SLP_T) ks_kzg_terms(const g2_aff *h, const fe 
 // S2[4 id + p] (Jacobian) for term id = k (2K - 2) + m
 __global__ void __launch_bounds__(SLP_T) ks_kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K,
                                                            uint64_t nb, g2_jac *S2) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[G2_SLOTS];
   __shared__ gls::Dec dec;
   uint64_t n = 2 * K - 2;
@@ -321,6 +326,8 @@ __device__ void g1_job(f29 *S, glv::Dec *dec, const g1_aff *P, const fe *k_mont,
 // identity is any point with Z = 0; additions meeting equal x are resolved exactly.
 template <bool G2>
 __global__ void __launch_bounds__(SLP_T) ks_jac_tree(void *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt) {
+  if (G2) CHAIN_PRIORITY();
+  else AHEAD_PRIORITY();
   constexpr int NC = G2 ? 6 : 3;  // coordinates (F_p elements) per point
   __shared__ f29 S[G2 ? G2_SLOTS : G1_SLOTS];
   __shared__ uint32_t arrived;
@@ -381,6 +388,7 @@ __global__ void __launch_bounds__(SLP_T) ks_jac_tree(void *data, uint64_t nseg, 
 // into S[(2k + side) (K / 2) + i] (Jacobian)
 __global__ void __launch_bounds__(SLP_T) ks_oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h,
                                                       g1_jac *Sout) {
+  AHEAD_PRIORITY();
   __shared__ f29 S[G1_SLOTS];
   __shared__ glv::Dec d1;
   uint64_t id = blockIdx.x;
@@ -398,6 +406,7 @@ template <int A_, int B_> struct imax { static constexpr int v = A_ > B_ ? A_ : 
 __global__ void __launch_bounds__(SLP_T) ks_oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin,
                                                    g2_aff *Vout, const fe *X, const fe *Xinv, uint64_t K, uint64_t nb,
                                                    uint64_t h, uint32_t j, uint32_t lK) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[imax<G1_SLOTS, G2_SLOTS>::v];
   __shared__ glv::Dec d1;
   __shared__ gls::Dec d2;
@@ -417,6 +426,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold(const g1_aff *Ain, const fe 
 // The next round's terms (oa_terms.hpp): the Miller loops into F[out], a workgroup per term
 __global__ void __launch_bounds__(SLP_T) ks_oa_pterms(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q,
                                                      fp12 *F) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[slp::ML_NSLOT];
   uint64_t id = blockIdx.x;
   if (id >= nb * 8 * q) return;
@@ -427,6 +437,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_pterms(const g1_aff *A, const g2_
 // The G1 terms b[v] A[a] of the next round into S1[out] (Jacobian), a workgroup per term
 __global__ void __launch_bounds__(SLP_T) ks_oa_g1terms_next(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t q,
                                                            g1_jac *S1) {
+  AHEAD_PRIORITY();
   __shared__ f29 S[G1_SLOTS];
   __shared__ glv::Dec d1;
   uint64_t id = blockIdx.x;
@@ -442,6 +453,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_g1terms_next(const g1_aff *A, con
 // Multiples for the time-split multiplications: M[3 s + m - 1] = G[s]^{2^{16 m}} (cyclotomic
 // squarings), a workgroup per (s, m), m = 1, 2, 3
 __global__ void __launch_bounds__(SLP_T) ks_gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[slp::FE_NSLOT + 24];
   uint64_t id = blockIdx.x;
   if (id >= 3 * n) return;
@@ -516,18 +528,21 @@ __device__ void g1_jac_mult_aff(f29 *S, const g1_jac *P, int m, g1_aff *o) {
   g1_store_aff(S, inf, o);
 }
 
-// both multiples of a split fold in one launch: blocks [0, 3n) M1 from the G1 points, blocks
-// [3n, 6n) M2 from the G2 points (as in ks_g1_dbl_mults, ks_g2_dbl_mults)
-__global__ void __launch_bounds__(SLP_T) ks_fold_mults(const g1_aff *P, const g2_aff *Q, uint64_t seg, uint64_t segstride,
-                                                      uint64_t n, g1_aff *M1, g2_aff *M2) {
+// the multiples of a round's arrays in one launch: blocks [0, 3 n1) M1[3 s + m - 1] =
+// 2^{32 m} P_s (G1, P_s at seg_index(s, seg1, segstride)), blocks [3 n1, 3 (n1 + n2))
+// M2[3 s + m - 1] = 2^{16 m} Q_s (G2, seg2)
+__global__ void __launch_bounds__(SLP_T) ks_fold_mults(const g1_aff *P, uint64_t seg1, uint64_t n1, const g2_aff *Q,
+                                                      uint64_t seg2, uint64_t n2, uint64_t segstride, g1_aff *M1,
+                                                      g2_aff *M2) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[imax<G1_SLOTS, G2_SLOTS>::v];
   uint64_t id = blockIdx.x;
-  if (id >= 6 * n) return;
-  bool g2 = id >= 3 * n;
-  if (g2) id -= 3 * n;
+  if (id >= 3 * (n1 + n2)) return;
+  bool g2 = id >= 3 * n1;
+  if (g2) id -= 3 * n1;
   uint64_t s = id / 3, m = id % 3 + 1;
-  if (g2) g2_dbl_mult(S, Q + seg_index(s, seg, segstride), (int)m, M2 + 3 * s + m - 1);
-  else g1_dbl_mult(S, P + seg_index(s, seg, segstride), (int)m, M1 + 3 * s + m - 1);
+  if (g2) g2_dbl_mult(S, Q + seg_index(s, seg2, segstride), (int)m, M2 + 3 * s + m - 1);
+  else g1_dbl_mult(S, P + seg_index(s, seg1, segstride), (int)m, M1 + 3 * s + m - 1);
 }
 
 // of the four parts of one multiplication, the workgroup that finishes last returns true
@@ -546,8 +561,9 @@ __device__ bool last_of_four(uint32_t *cnt, uint32_t *flag) {
   return last;
 }
 
-// The fold of round j with every multiplication split in four parts run in parallel (the
-// multiples M1, M2 cover the whole arrays, M[3 (k 2h + i') + p - 1] for index i' of batch k):
+// The fold of round j with every multiplication split in four parts run in parallel (M1
+// covers the whole arrays, M1[3 (k 2h + i') + p - 1] for index i' of batch k; M2 the halves,
+// M2[3 (k h + i) + p - 1] for V[h + i]):
 // blocks [0, 4 nb h): part p of x A[h + i] on the base 2^{32 p} A[h + i] (M1, p > 0) with
 // the p-th 32-bit chunk of the GLV split of x into J1[4 s + p]; blocks [4 nb h, 8 nb h):
 // part p of x^{-1} V[h + i] on 2^{16 p} V[h + i] (M2) with bits [16 p, 16 p + 16) (17 for
@@ -559,6 +575,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_split(const g1_aff *Ain, con
                                                          const g1_aff *M1, const g2_aff *M2, g1_jac *J1, g2_jac *J2,
                                                          uint32_t *cnt, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
                                                          uint32_t lK) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[imax<G1_SLOTS, G2_SLOTS>::v];
   __shared__ glv::Dec d1;
   __shared__ gls::Dec d2;
@@ -588,8 +605,8 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_split(const g1_aff *Ain, con
     g1_store_aff(S, inf, Aout + k * K + i);
     return;
   }
-  g2_job(S, &d2, part ? M2 + 3 * (k * 2 * h + h + i) + part - 1 : Vin + k * K + h + i, Xinv + slot, nullptr, nullptr,
-         J2 + 4 * s + part, 16 * part, part < 3 ? 16 : 17);
+  g2_job(S, &d2, part ? M2 + 3 * s + part - 1 : Vin + k * K + h + i, Xinv + slot, nullptr, nullptr, J2 + 4 * s + part,
+         16 * part, part < 3 ? 16 : 17);
   if (!last_of_four(cnt + n + s, &flag)) return;
   const fe *pj = reinterpret_cast<const fe *>(J2 + 4 * s);
   if (t < 24) S[slp::G2_TB1_0 + t] = slp::to29(pj[t]);
@@ -611,6 +628,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_split(const g1_aff *Ain, con
 // J[4 term + p]; the last part to finish writes the sum to S1[out] (Jacobian)
 __global__ void __launch_bounds__(SLP_T) ks_oa_g1terms_split(const g1_aff *A, const fe *B, const g1_aff *M, uint64_t K,
                                                             uint64_t nb, uint64_t q, g1_jac *J, uint32_t *cnt, g1_jac *S1) {
+  AHEAD_PRIORITY();
   __shared__ f29 S[G1_SLOTS];
   __shared__ glv::Dec d1;
   __shared__ uint32_t flag;
@@ -643,6 +661,7 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_g1terms_split(const g1_aff *A, co
 __global__ void __launch_bounds__(SLP_T) ks_oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1,
                                                             const g1_aff *PX1m, const fe *k_even, const fe *k_odd,
                                                             uint64_t kstride, uint64_t nb, fp12 *PE, g1_jac *PM) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[imax<GTP_SLOTS, G1_SLOTS>::v];
   __shared__ gls::Dec dec;
   __shared__ glv::Dec d1;
@@ -672,12 +691,30 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_combine_split(const fp12 *PX, con
   if (t < 12) dst[t] = r < 0 ? (t == 0 ? f_one<FpP>() : fe_zero()) : slp::from29(slp::canon29(S[FE_BUF(r) + t]));
 }
 
+// Both parts of L_j, R_j from the combine, in one launch.  Blocks [0, 2 nb):
 // (side ? R : L)[k lK] = U[2k + side] prod_{g in {2 side, 2 side + 1}, p < 4} P[4 (4k + g) + p]
-__global__ void __launch_bounds__(SLP_T) ks_oa_gt_combine8(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R,
-                                                          uint64_t lK) {
+// (G_T, engine); blocks [2 nb, 4 nb): the G1 parts U1[2k + side] + sum of the 8 Jacobian
+// parts P1[4 (4k + 2 side) + i] (a tree over 8 lanes), affine, into L1 / R1.
+__global__ void __launch_bounds__(SLP_T) ks_oa_combine8(const fp12 *U, const fp12 *P, const g1_aff *U1, const g1_jac *P1,
+                                                       uint64_t nb, fp12 *L, fp12 *R, g1_aff *L1, g1_aff *R1, uint64_t lK) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[slp::FE_NSLOT + 36];
   uint64_t id = blockIdx.x;
-  if (id >= 2 * nb) return;
+  if (id >= 4 * nb) return;
+  if (id >= 2 * nb) {
+    id -= 2 * nb;
+    g1_jac *part = reinterpret_cast<g1_jac *>(S);  // 8 Jacobian points in the slot memory
+    uint64_t k = id / 2, side = id % 2;
+    const int t = threadIdx.x;
+    if (t < 8) part[t] = P1[4 * (4 * k + 2 * side) + t];
+    __syncthreads();
+    for (int w = 4; w >= 1; w >>= 1) {
+      if (t < w) part[t] = jac_add(part[t], part[t + w]);
+      __syncthreads();
+    }
+    if (t == 0) (side ? R1 : L1)[k * lK] = jac_to_aff(jac_madd(part[0], U1[id]));
+    return;
+  }
   uint64_t k = id / 2, side = id % 2;
   const int t = threadIdx.x;
   const fe *u = reinterpret_cast<const fe *>(U + id);
@@ -711,6 +748,7 @@ __device__ void fe_job(f29 *S, const fp12 *in, fp12 *out) {
 
 __global__ void __launch_bounds__(SLP_T) ks_final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1,
                                                       uint64_t st1, uint64_t n1, fp12 *out1) {
+  CHAIN_PRIORITY();
   __shared__ f29 S[FE_SLOTS];
   uint64_t s = blockIdx.x;
   if (s >= n0 + n1) return;
@@ -723,6 +761,7 @@ __global__ void __launch_bounds__(SLP_T) ks_final_exp2(const fp12 *in0, uint64_t
 // 2^{32 m} PX1[s] (m = 1..3)
 __global__ void __launch_bounds__(SLP_T) ks_g1_finish(const g1_jac *PS, uint64_t nb, uint64_t q, g1_aff *PU1, g1_aff *PX1,
                                                      g1_aff *PX1m) {
+  AHEAD_PRIORITY();
   __shared__ f29 S[G1_SLOTS];
   uint64_t id = blockIdx.x;
   if (id >= 18 * nb) return;
@@ -776,9 +815,10 @@ void oa_g1terms_split(const g1_aff *A, const fe *B, const g1_aff *M, uint64_t K,
                       uint32_t *cnt, g1_jac *S1, hipStream_t st) {
   LAUNCH(ks_oa_g1terms_split, dim3((unsigned)(4 * nb * 8 * q)), dim3(SLP_T), 0, A, B, M, K, nb, q, J, cnt, S1);
 }
-void fold_mults(const g1_aff *P, const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M1, g2_aff *M2,
-                hipStream_t st) {
-  if (n) LAUNCH(ks_fold_mults, dim3((unsigned)(6 * n)), dim3(SLP_T), 0, P, Q, seg, segstride, n, M1, M2);
+void fold_mults(const g1_aff *P, uint64_t seg1, uint64_t n1, const g2_aff *Q, uint64_t seg2, uint64_t n2, uint64_t segstride,
+                g1_aff *M1, g2_aff *M2, hipStream_t st) {
+  if (n1 + n2)
+    LAUNCH(ks_fold_mults, dim3((unsigned)(3 * (n1 + n2))), dim3(SLP_T), 0, P, seg1, n1, Q, seg2, n2, segstride, M1, M2);
 }
 void oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
                    const fe *Xinv, const g1_aff *M1, const g2_aff *M2, g1_jac *J1, g2_jac *J2, uint32_t *cnt, uint64_t K,
@@ -791,8 +831,9 @@ void oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1, const 
   LAUNCH(ks_oa_combine_split, dim3((unsigned)(32 * nb)), dim3(SLP_T), 0, PX, PXm, PX1, PX1m, k_even, k_odd, kstride, nb, PE,
          PM);
 }
-void oa_gt_combine8(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st) {
-  LAUNCH(ks_oa_gt_combine8, dim3((unsigned)(2 * nb)), dim3(SLP_T), 0, U, P, nb, L, R, lK);
+void oa_combine8(const fp12 *U, const fp12 *P, const g1_aff *U1, const g1_jac *P1, uint64_t nb, fp12 *L, fp12 *R, g1_aff *L1,
+                 g1_aff *R1, uint64_t lK, hipStream_t st) {
+  LAUNCH(ks_oa_combine8, dim3((unsigned)(4 * nb)), dim3(SLP_T), 0, U, P, U1, P1, nb, L, R, L1, R1, lK);
 }
 void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp12 *in1, uint64_t st1, uint64_t n1, fp12 *out1,
                 hipStream_t st) {

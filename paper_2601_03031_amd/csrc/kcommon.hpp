@@ -22,6 +22,13 @@
 static inline unsigned nblk(uint64_t n, unsigned tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
 __device__ __forceinline__ uint64_t gtid() { return (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Kernels on the dependent chain of rounds raise their waves' issue priority, so that
+// waves of work taken ahead that share a SIMD with them yield to them: 3 for the pairing
+// side, folds, combine and transcript, 2 for the multiples and the G1 side of the terms;
+// Step 2 keeps the default.
+#define CHAIN_PRIORITY() __builtin_amdgcn_s_setprio(3)
+#define AHEAD_PRIORITY() __builtin_amdgcn_s_setprio(2)
+
 #define DSTR_SETUP "FLEXPROOFS-V1-SETUP"
 #define DSTR_FC_R "FLEXPROOFS-V1-FC-R"
 #define DSTR_FC_X "FLEXPROOFS-V1-FC-X"

@@ -37,7 +37,6 @@ void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, ui
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
 // L[k lK], R[k lK] = U[2k + side] + sum_{g, p} P[4 (4k + g) + p] over the 8 split parts of
 // each side (affine)
-void oa_g1_combine8(const g1_aff *U, const g1_jac *P, uint64_t nb, g1_aff *L, g1_aff *R, uint64_t lK, hipStream_t st);
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   hipStream_t st);
 void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st);
@@ -108,9 +107,9 @@ void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n,
 // the reduced G1 groups of the terms taken ahead made ready for the combine: affine (PU1,
 // PX1) and PX1m[3 s + m - 1] = 2^{32 m} PX1[s]
 void g1_finish(const g1_jac *PS, uint64_t nb, uint64_t q, g1_aff *PU1, g1_aff *PX1, g1_aff *PX1m, hipStream_t st);
-// both in one launch (points P, Q at the same segmented indices)
-void fold_mults(const g1_aff *P, const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g1_aff *M1, g2_aff *M2,
-                hipStream_t st);
+// both in one launch: n1 G1 points in segments of seg1, n2 G2 points in segments of seg2
+void fold_mults(const g1_aff *P, uint64_t seg1, uint64_t n1, const g2_aff *Q, uint64_t seg2, uint64_t n2, uint64_t segstride,
+                g1_aff *M1, g2_aff *M2, hipStream_t st);
 // the fold with four-part split multiplications on the multiples M1 = 2^{32 m} A[h + i],
 // M2 = 2^{16 m} V[h + i]; partial results in J1, J2; 2 nb h arrival counters
 void oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
@@ -118,5 +117,7 @@ void oa_fold_split(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, con
                    uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void oa_combine_split(const fp12 *PX, const fp12 *PXm, const g1_aff *PX1, const g1_aff *PX1m, const fe *k_even,
                       const fe *k_odd, uint64_t kstride, uint64_t nb, fp12 *PE, g1_jac *PM, hipStream_t st);
-void oa_gt_combine8(const fp12 *U, const fp12 *P, uint64_t nb, fp12 *L, fp12 *R, uint64_t lK, hipStream_t st);
+// L_j, R_j (G_T and G1 parts) from the U groups and the 8 parts per side of the combine
+void oa_combine8(const fp12 *U, const fp12 *P, const g1_aff *U1, const g1_jac *P1, uint64_t nb, fp12 *L, fp12 *R, g1_aff *L1,
+                 g1_aff *R1, uint64_t lK, hipStream_t st);
 }  // namespace ks

@@ -519,19 +519,15 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // exponentiations), side 5 their G1 side; the caller's stream combines and hashes.
   hipStream_t sg = s2, sf = pp->side[2], sfp[2] = {pp->side[2], pp->side[3]}, sq = pp->side[4];
   kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
-  // multiples 2^{32 m} A[i], 2^{16 m} V[i] (m = 1..3) of the whole arrays of round j (for its
-  // split fold and the split G1 terms of round j + 1), into set j & 1 (round 1: on side
-  // stream 1 before Step 2, later rounds on the fold stream)
+  // multiples 2^{32 m} A[i] (m = 1..3) of the whole arrays A of round j (for its split fold
+  // and the split G1 terms of round j + 1) and 2^{16 m} V[h + i] of the halves V[h..) (for
+  // its split fold), into set j & 1 (round 1 on side stream 1, later rounds on the fold
+  // stream)
   auto launch_fold_mults = [&](uint32_t j, hipStream_t s) {
-    const uint64_t n = K >> (j - 1);
+    const uint64_t n = K >> (j - 1), hh = n / 2;
     const int cur = (j - 1) & 1;
-    ks::fold_mults(Ab[cur], Vb[cur], n, K, nb * n, FM1[j & 1], FM2[j & 1], s);
+    ks::fold_mults(Ab[cur], n, nb * n, Vb[cur] + hh, hh, nb * hh, K, FM1[j & 1], FM2[j & 1], s);
   };
-  if (split_round(1)) {
-    if (int rc2 = stream_wait(pp, 14, st, s1)) return rc2;
-    launch_fold_mults(1, s1);
-    if (int rc2 = ev_mark(pp, 15, s1)) return rc2;
-  }
   kl::fc_chunks(Cj, K, b, nb, Hq, st);
   kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
   kl::fc_r(K, b, nb, sigma, B, st);
@@ -583,13 +579,23 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       }
       kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
       if (int rc2 = ev_mark(pp, 3, sg)) return rc2;
-      if (ahead) {
+      ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
+      // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
+      // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
+      if (j == 1 && split_round(1)) {
+        if (int rc2 = stream_wait(pp, 14, st, s1)) return rc2;
+        launch_fold_mults(1, s1);
+        if (int rc2 = ev_mark(pp, 15, s1)) return rc2;
+      }
+      // round 2's terms from the round-1 arrays, after the round-1 Miller loops (the G1 side
+      // after the multiples)
+      if (j == 1 && ahead) {
+        if (int rc2 = stream_wait(pp, 19, st, sfp[0])) return rc2;
         if (int rc2 = launch_terms(2)) return rc2;
         if (split_round(1))
           if (int rc2 = ev_wait(pp, 15, sq)) return rc2;
         if (int rc2 = launch_g1terms(2)) return rc2;
       }
-      ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
       ks::f12_reduce(F, 2 * nb, K / 2, h, cnt_dir, st);
       ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
       if (int rc2 = ev_wait(pp, 3, st)) return rc2;
@@ -599,8 +605,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
       if (int rc2 = ev_wait(pp, 6 + par, st)) return rc2;
       if (int rc2 = ev_wait(pp, 8 + par, st)) return rc2;
       ks::oa_combine_split(PX[par], PXm[par], PX1[par], PX1m[par], X + (j - 2), Xinv + (j - 2), lK, nb, PE, PM, st);
-      ks::oa_gt_combine8(PU[par], PE, nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
-      kl::oa_g1_combine8(PU1[par], PM, nb, Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
+      ks::oa_combine8(PU[par], PE, PU1[par], PM, nb, Lgt + (j - 1), Rgt + (j - 1), Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
     }
     kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
     // fold with x_j into the other buffer
