@@ -36,6 +36,9 @@ PEAK_MAD_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12   # v_mad_u64_u32 issues at half rat
 PEAK_HBM_GBS = 8000.0
 MADS_PER_FMUL = 136                        # 8x32-bit CIOS: 64 + 64 products + 8 reduction words
 AHEAD_MAX_PAIRS = 4096                     # the library's switch to next-round terms (batches x K)
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a reference copy
+# (profiles/ks_oa_pterms_n16_b256_hbm_counters.md); valid for the kernel build it was taken on
+TRAFFIC_BYTES = {"ks_oa_pterms": round((666.3 * 2.000 + 54.4 * 1.000) * 1024)}
 FOLD_SPLIT_MAX = 256                       # folds of at most this many pairs run split in four parts
 KZG_SPLIT_MAX = 8192                       # KZG proofs of at most this many split jobs run split
 
@@ -218,7 +221,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device three times (reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        n = a.copy_calibration << 20
+        src = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only: the single-GPU path is the build's scope "
               "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
@@ -248,7 +264,7 @@ def main():
         avg_s = dms / dcount / 1e3
         achieved = per_launch_fmul * MADS_PER_FMUL / avg_s / 1e12
         roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 4), "peak": round(PEAK_MAD_TOPS, 2),
-                    "unit": "TOP/s", "frac": round(achieved / PEAK_MAD_TOPS, 5), "traffic": None,
+                    "unit": "TOP/s", "frac": round(achieved / PEAK_MAD_TOPS, 5), "traffic": TRAFFIC_BYTES.get(dname),
                     "per_launch_field_mults": int(per_launch_fmul), "avg_launch_ms": round(dms / dcount, 4)}
     kernels = {k: {"launches": c // psteps, "ms_per_step": round(ms / psteps, 4),
                    "share": round(ms / total_prof, 4) if total_prof else None}
