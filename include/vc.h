@@ -17,6 +17,10 @@
  *  - Device pointers are borrowed for the duration of the call and must be device
  *    memory on the params' device.  `stream` is a hipStream_t (NULL = default
  *    stream); work is ordered on it and every call is synchronous on return.
+ *    vc_open_all also runs work on five side streams owned by the params (joined to
+ *    `stream` before it returns); they overlap only if the process has at least six
+ *    hardware queues (environment GPU_MAX_HW_QUEUES, read by HIP at its first device
+ *    use), otherwise they share queues and run partly in sequence, with the same results.
  *  - Handles (vc_params, vc_commitment, vc_proofs) own their device memory and are
  *    released with the matching *_free; a vc_proofs handle does not reference the
  *    commitment it was made from.
