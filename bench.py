@@ -40,6 +40,7 @@ AHEAD_MAX_PAIRS = 4096                     # the library's switch to next-round 
 # (profiles/ks_oa_pterms_n16_b256_hbm_counters.md); valid for the kernel build it was taken on
 TRAFFIC_BYTES = {"ks_oa_pterms": round((666.3 * 2.000 + 54.4 * 1.000) * 1024)}
 FOLD_SPLIT_MAX = 256                       # folds of at most this many pairs run split in four parts
+DIRECT_MIN = 512                           # rounds of more pairs than this run direct in the ahead mode
 KZG_SPLIT_MAX = 8192                       # KZG proofs of at most this many split jobs run split
 
 
@@ -87,30 +88,40 @@ def work_model(L, b, limbs, costs):
     g2_fold = costs["e_g2_mul"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]
     nq = 2 * K - 2
     w = {
-        "k_msm_slices": nz_digits * costs["g1_madd"] + blocks * 2048 * costs["g1_add"],
+        "k_msm_slices<OpsG1>": nz_digits * costs["g1_madd"] + blocks * 2048 * costs["g1_add"],
         "ks_miller": K * costs["e_miller"],
         "kw_hyper_terms": lM * (M // 2) * costs["g1_mul"],
     }
+    # KZG proof: with few terms, split multiplications; otherwise a G2 MSM over 8-bit windows
+    # of the fixed SRS points (about 255/256 of the (term, window) pairs have a nonzero digit;
+    # 2 x 255 additions per block of 32 bases); then the engine tree over the partial sums
     if 4 * nb * nq <= KZG_SPLIT_MAX:
         w["ks_kzg_terms_split"] = 4 * nb * nq * costs["e_g2_part"]
         w["ks_jac_tree<true>"] = nb * (4 * nq - 1) * costs["e_g2_add"]
     else:
-        w["ks_kzg_terms"] = nb * nq * costs["e_g2_mul"]
+        kzg_blocks = nb * (-(-nq // 32))
+        w["k_msm_slices<OpsG2>"] = (nb * nq * 32 * 255 // 256) * costs["g2_madd"] + kzg_blocks * 510 * costs["g2_add"]
+        w["ks_jac_tree<true>"] = (kzg_blocks - nb) * costs["e_g2_add"]
     if lK >= 2 and nb * K <= AHEAD_MAX_PAIRS:
-        # round 1 direct; rounds j >= 2 from terms of the arrays of round j - 1 (q = K >> j)
-        qs = [K >> j for j in range(2, lK + 1)]
+        # rounds j < j0 direct (the device is full), rounds j >= j0 from terms of the arrays of
+        # round j - 1 (q = K >> j)
+        j0 = 2
+        while j0 < lK and nb * (K >> j0) > DIRECT_MIN:
+            j0 += 1
+        direct = [K >> j for j in range(1, j0)]
+        qs = [K >> j for j in range(j0, lK + 1)]
         g1_fold = costs["e_g1_mul"] + costs["e_g1_madd"] + costs["e_g1_to_aff"]
         split = [nb * h for h in rounds if nb * h <= FOLD_SPLIT_MAX]
         whole = [nb * h for h in rounds if nb * h > FOLD_SPLIT_MAX]
         g1_sum = 3 * costs["e_g1_add"] + costs["e_g1_madd"] + costs["e_g1_to_aff"]
         g2_sum = 3 * costs["e_g2_add"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]
         w.update({
-            "ks_oa_miller": nb * 2 * rounds[0] * costs["e_miller"],
-            "ks_oa_g1terms": nb * 2 * rounds[0] * costs["e_g1_mul"],
-            "ks_final_exp": (2 * nb + 1) * costs["e_final_exp"],
-            "ks_f12_tree": (K - 1 + 2 * nb * (rounds[0] - 1)
+            "ks_oa_miller": sum(nb * 2 * h for h in direct) * costs["e_miller"],
+            "ks_oa_g1terms": sum(nb * 2 * h for h in direct) * costs["e_g1_mul"],
+            "ks_final_exp": (2 * nb * len(direct) + 1) * costs["e_final_exp"],
+            "ks_f12_tree": (K - 1 + sum(2 * nb * (h - 1) for h in direct)
                             + sum(2 * nb * (2 * q - 1) + 4 * nb * (q - 1) for q in qs)) * costs["e_f12_mul"],
-            "ks_jac_tree<false>": (2 * nb * (rounds[0] - 1)
+            "ks_jac_tree<false>": (sum(2 * nb * (h - 1) for h in direct)
                                    + sum(2 * nb * (2 * q - 1) + 4 * nb * (q - 1) for q in qs)) * costs["e_g1_add"],
             "ks_oa_fold": sum(whole) * (g1_fold + g2_fold),
             "ks_oa_fold_split": sum(split) * (4 * costs["e_g1_part"] + g1_sum + 4 * costs["e_g2_part"] + g2_sum),
@@ -120,9 +131,9 @@ def work_model(L, b, limbs, costs):
                                            + 96 * costs["e_g2_dbl"] + 3 * costs["e_g2_to_aff"]),
             "ks_oa_pterms": sum(nb * 8 * q for q in qs) * costs["e_miller"],
             "ks_oa_g1terms_split": sum(nb * 8 * (K >> (j + 1)) * (4 * costs["e_g1_part"] + 3 * costs["e_g1_add"])
-                                       for j in range(1, lK) if nb * (K >> j) <= FOLD_SPLIT_MAX),
+                                       for j in range(j0 - 1, lK) if nb * (K >> j) <= FOLD_SPLIT_MAX),
             "ks_oa_g1terms_next": sum(nb * 8 * (K >> (j + 1)) * costs["e_g1_mul"]
-                                      for j in range(1, lK) if nb * (K >> j) > FOLD_SPLIT_MAX),
+                                      for j in range(j0 - 1, lK) if nb * (K >> j) > FOLD_SPLIT_MAX),
             "ks_final_exp2": len(qs) * 6 * nb * costs["e_final_exp"],
             # the G1 groups to affine form, with their multiples 2^{32m} (16m double doublings)
             "ks_g1_finish": len(qs) * (2 * nb * costs["e_g1_to_aff"]
@@ -269,7 +280,7 @@ def main():
     kernels = {k: {"launches": c // psteps, "ms_per_step": round(ms / psteps, 4),
                    "share": round(ms / total_prof, 4) if total_prof else None}
                for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
-    msm_ms = (prof.get("k_msm_slices", (0, 0))[1] + prof.get("kw_sum_g1", (0, 0))[1]) / psteps
+    msm_ms = (prof.get("k_msm_slices<OpsG1>", (0, 0))[1] + prof.get("kw_sum_g1", (0, 0))[1]) / psteps
     extra = {"commit_ms": round(statistics.median(commit_ms), 3),
              "open_ms_all": [round(x, 3) for x in open_ms],
              "open_ms_mean": round(statistics.mean(open_ms), 3),
@@ -280,7 +291,7 @@ def main():
         n2 = max(1, min(a.steps, 2))
         _, _, _, p2, _ = run_workload(V, torch, L2, b2, 256, 3, 1, 1)
         _, c2, o2, _, _ = run_workload(V, torch, L2, b2, 256, 3, n2, 1, profile=None)
-        msm2 = p2.get("k_msm_slices", (0, 0))[1] + p2.get("kw_sum_g1", (0, 0))[1]
+        msm2 = p2.get("k_msm_slices<OpsG1>", (0, 0))[1] + p2.get("kw_sum_g1", (0, 0))[1]
         extra["n2^20_b400"] = {"all_proofs_ms": round(statistics.median(o2), 3), "commit_ms": round(statistics.median(c2), 3),
                                "msm_points_per_s": round((1 << L2) / (msm2 / 1e3)) if msm2 else None}
         # batch-size sweep (one timed step each): all-N-proofs ms

@@ -2,6 +2,7 @@
 #include "kcommon.hpp"
 
 #define MSM_MAXE 8192
+#define MSM_G2_MAXE 1024  // S nwin for the G2 MSM (its 256 Jacobian G2 points take 48 KB of LDS)
 
 // weights of the Lagrange keys at every level: node n = 2^k - 1 + c holds eq_k(c; s)
 __global__ void __launch_bounds__(TPB) k_ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n_total) {
@@ -30,15 +31,23 @@ __global__ void __launch_bounds__(TPB) k_pow_table(const fe *beta, fe *out, uint
 }
 
 // table[w M + a] = 2^{8w} base[a] for w < nwin
-__global__ void __launch_bounds__(TPB) k_msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table) {
+template <class O>
+__global__ void __launch_bounds__(TPB) k_msm_tables(const aff<O> *base, uint64_t M, uint32_t nwin, aff<O> *table) {
   uint64_t a = gtid();
   if (a >= M) return;
-  g1_jac acc = jac_from_aff(base[a]);
+  jac<O> acc = jac_from_aff(base[a]);
   table[a] = base[a];
   for (uint32_t w = 1; w < nwin; w++) {
     for (int d = 0; d < 8; d++) acc = jac_dbl(acc);
     table[(uint64_t)w * M + a] = jac_to_aff(acc);
   }
+}
+
+// out[i] = in[i] out of Montgomery form (F_r)
+__global__ void __launch_bounds__(TPB) k_fr_canon(const fe *in, uint64_t n, fe *out) {
+  uint64_t i = gtid();
+  if (i >= n) return;
+  out[i] = f_from_mont<FpR>(in[i]);
 }
 
 // ================================================================ commit
@@ -56,16 +65,19 @@ __global__ void __launch_bounds__(TPB) k_check_fr(const fe *m, uint64_t n, int *
   if (!fe_lt_mod(m[i], bn::R_MOD)) atomicOr(err, VC_ERRBIT_RANGE);
 }
 
-// Batched MSM with shared bases: C_j = sum_a m[jM+a] ek[a].  Block (j, slice) handles
-// bases [slice*S, (slice+1)*S); every (base, window) pair with a nonzero 8-bit digit
-// is counting-sorted by digit in LDS, thread d sums bucket d over the precomputed
-// table points 2^{8w} ek[a], and the block reduces sum_d d B_d with a suffix scan.
+// Batched MSM with shared bases: C_j = sum_a m[jM+a] ek[a] (canonical scalars).  Block
+// (j, slice) handles bases [slice*S, (slice+1)*S); every (base, window) pair with a nonzero
+// 8-bit digit is counting-sorted by digit in LDS, thread d sums bucket d over the
+// precomputed table points 2^{8w} ek[a], and the block reduces sum_d d B_d with a suffix
+// scan.  S nwin <= MSM_MAXE (G1), MSM_G2_MAXE (G2).
+template <class O>
 __global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, uint32_t nwin, uint32_t S,
-                                                    const g1_aff *table, g1_jac *partial) {
+                                                    const aff<O> *table, jac<O> *partial) {
   __shared__ uint32_t cnt[256];
   __shared__ uint32_t off[256];
-  __shared__ uint32_t ent[MSM_MAXE];
-  __shared__ g1_jac red[256];
+  constexpr uint32_t MAXE = sizeof(typename O::T) > sizeof(fe) ? MSM_G2_MAXE : MSM_MAXE;
+  __shared__ uint32_t ent[MAXE];
+  __shared__ jac<O> red[256];
   uint32_t nslice = (uint32_t)((M + S - 1) / S);
   uint64_t j = blockIdx.x / nslice;
   uint32_t sl = blockIdx.x % nslice;
@@ -98,20 +110,20 @@ __global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, 
     }
   }
   __syncthreads();
-  g1_jac acc = jac_inf<OpsG1>();
+  jac<O> acc = jac_inf<O>();
   for (uint32_t q = 0; q < len; q++) acc = jac_madd(acc, table[ent[start + q]]);
-  if (t == 0) acc = jac_inf<OpsG1>();
+  if (t == 0) acc = jac_inf<O>();
   red[t] = acc;
   __syncthreads();
   // suffix sums T_d = sum_{d' >= d} B_{d'}
   for (uint32_t s = 1; s < 256; s <<= 1) {
-    g1_jac v = red[t];
+    jac<O> v = red[t];
     if (t + s < 256) v = jac_add(v, red[t + s]);
     __syncthreads();
     red[t] = v;
     __syncthreads();
   }
-  if (t == 0) red[0] = jac_inf<OpsG1>();
+  if (t == 0) red[0] = jac_inf<O>();
   __syncthreads();
   // sum_{d >= 1} T_d
   for (uint32_t s = 128; s >= 1; s >>= 1) {
@@ -194,14 +206,25 @@ __global__ void __launch_bounds__(TPB) k_glv_dec(const fe *X, uint64_t nb, uint3
 namespace kl {
 void ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n, hipStream_t st) { L1(k_ek_weights, n, lM, s, w, n); }
 void pow_table(const fe *beta, fe *out, uint64_t n, hipStream_t st) { L1(k_pow_table, n, beta, out, n); }
-void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hipStream_t st) { L1(k_msm_tables, M, base, M, nwin, table); }
+void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hipStream_t st) {
+  L1(k_msm_tables<OpsG1>, M, base, M, nwin, table);
+}
+void msm_tables_g2(const g2_aff *base, uint64_t M, uint32_t nwin, g2_aff *table, hipStream_t st) {
+  L1(k_msm_tables<OpsG2>, M, base, M, nwin, table);
+}
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st) { L1(k_lift_u32, n, in, n, out); }
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st) { L1(k_check_fr, n, m, n, err); }
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st) {
   uint64_t nslice = (M + S - 1) / S;
-  LAUNCH(k_msm_slices, dim3((unsigned)(K * nslice)), dim3(256), 0, scal, M, nwin, S, table, partial);
+  LAUNCH(k_msm_slices<OpsG1>, dim3((unsigned)(K * nslice)), dim3(256), 0, scal, M, nwin, S, table, partial);
 }
+void msm_slices_g2(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g2_aff *table, g2_jac *partial,
+                   hipStream_t st) {
+  uint64_t nslice = (M + S - 1) / S;
+  LAUNCH(k_msm_slices<OpsG2>, dim3((unsigned)(K * nslice)), dim3(256), 0, scal, M, nwin, S, table, partial);
+}
+void fr_canon(const fe *in, uint64_t n, fe *out, hipStream_t st) { L1(k_fr_canon, n, in, n, out); }
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st) {
   if (len > 1) L1(k_jac_tree<OpsG1>, nseg * ((len + 1) / 2), data, nseg, stride, len, cnt);
 }

@@ -205,20 +205,9 @@ __global__ void __launch_bounds__(SLP_T) ks_oa_fold_g2(const g2_aff *Vin, g2_aff
   g2_job(S, &dec, Vin + k * K + h + i, Xinv + k * lK + (j - 1), Vin + k * K + i, Vout + k * K + i, nullptr);
 }
 
-// terms q_m h_m of the KZG proof of v_l (Jacobian)
-__global__ void __launch_bounds__(SLP_T) ks_kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2) {
-  CHAIN_PRIORITY();
-  __shared__ f29 S[G2_SLOTS];
-  __shared__ gls::Dec dec;
-  uint64_t n = 2 * K - 2;
-  uint64_t id = blockIdx.x;
-  if (id >= nb * n) return;
-  g2_job(S, &dec, h + id % n, Qc + id, nullptr, nullptr, S2 + id);
-}
-
-// the same with every multiplication split in four parts (bits [16 p, 16 p + 16) of the GLS
-// split, 17 for p = 3) on the multiples hm[3 m + p - 1] = 2^{16 p} h_m made at setup:
-// S2[4 id + p] (Jacobian) for term id = k (2K - 2) + m
+// terms q_m h_m of the KZG proof of v_l with every multiplication split in four parts (bits
+// [16 p, 16 p + 16) of the GLS split, 17 for p = 3) on the multiples hm[3 m + p - 1] =
+// 2^{16 p} h_m made at setup: S2[4 id + p] (Jacobian) for term id = k (2K - 2) + m
 __global__ void __launch_bounds__(SLP_T) ks_kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K,
                                                            uint64_t nb, g2_jac *S2) {
   CHAIN_PRIORITY();
@@ -504,16 +493,6 @@ __device__ void g2_dbl_mult(f29 *S, const g2_aff *Q, int m, g2_aff *o) {
   g2_store_aff(S, inf, o);
 }
 
-// M[3 s + m - 1] = 2^{16 m} Q_s (affine), Q_s as in seg_index, a workgroup per (s, m), m = 1, 2, 3
-__global__ void __launch_bounds__(SLP_T) ks_g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n,
-                                                        g2_aff *M) {
-  __shared__ f29 S[G2_SLOTS];
-  uint64_t id = blockIdx.x;
-  if (id >= 3 * n) return;
-  uint64_t s = id / 3, m = id % 3 + 1;
-  g2_dbl_mult(S, Q + seg_index(s, seg, segstride), (int)m, M + 3 * s + m - 1);
-}
-
 // 2^{32 m} P (affine) for a Jacobian P (m = 0: P itself), on the engine
 __device__ void g1_jac_mult_aff(f29 *S, const g1_jac *P, int m, g1_aff *o) {
   const int t = threadIdx.x;
@@ -526,6 +505,16 @@ __device__ void g1_jac_mult_aff(f29 *S, const g1_jac *P, int m, g1_aff *o) {
     for (int i = 0; i < 16 * m; i++) slp::run1(S, slp::PROG_G1_DBL2, 0, 0, 0);
   }
   g1_store_aff(S, inf, o);
+}
+
+// M[3 s + m - 1] = 2^{16 m} Q_s (affine), Q_s as in seg_index, a workgroup per (s, m), m = 1, 2, 3
+__global__ void __launch_bounds__(SLP_T) ks_g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n,
+                                                        g2_aff *M) {
+  __shared__ f29 S[G2_SLOTS];
+  uint64_t id = blockIdx.x;
+  if (id >= 3 * n) return;
+  uint64_t s = id / 3, m = id % 3 + 1;
+  g2_dbl_mult(S, Q + seg_index(s, seg, segstride), (int)m, M + 3 * s + m - 1);
 }
 
 // the multiples of a round's arrays in one launch: blocks [0, 3 n1) M1[3 s + m - 1] =
@@ -802,9 +791,6 @@ void oa_pterms(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64
 void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st) {
   if (n) LAUNCH(ks_gt_sqr_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, G, n, M);
 }
-void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st) {
-  if (n) LAUNCH(ks_g2_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, Q, seg, segstride, n, M);
-}
 void g1_finish(const g1_jac *PS, uint64_t nb, uint64_t q, g1_aff *PU1, g1_aff *PX1, g1_aff *PX1m, hipStream_t st) {
   LAUNCH(ks_g1_finish, dim3((unsigned)(18 * nb)), dim3(SLP_T), 0, PS, nb, q, PU1, PX1, PX1m);
 }
@@ -839,9 +825,6 @@ void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp
                 hipStream_t st) {
   if (n0 + n1) LAUNCH(ks_final_exp2, dim3((unsigned)(n0 + n1)), dim3(SLP_T), 0, in0, st0, n0, out0, in1, st1, n1, out1);
 }
-void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st) {
-  LAUNCH(ks_kzg_terms, dim3((unsigned)(nb * (2 * K - 2))), dim3(SLP_T), 0, h, Qc, K, nb, S2);
-}
 void g1_tree(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st) {
   if (len > 1) LAUNCH(ks_jac_tree<false>, dim3((unsigned)(nseg * ((len + 1) / 2))), dim3(SLP_T), 0, data, nseg, stride, len, cnt);
 }
@@ -853,6 +836,9 @@ void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t 
 }
 void kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st) {
   LAUNCH(ks_kzg_terms_split, dim3((unsigned)(4 * nb * (2 * K - 2))), dim3(SLP_T), 0, h, hm, Qc, K, nb, S2);
+}
+void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st) {
+  if (n) LAUNCH(ks_g2_dbl_mults, dim3((unsigned)(3 * n)), dim3(SLP_T), 0, Q, seg, segstride, n, M);
 }
 void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st) {
   if (n) LAUNCH(ks_gt_pow, dim3((unsigned)n), dim3(SLP_T), 0, in, k, n, out);

@@ -236,17 +236,8 @@ void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStre
     LW(kw_jac_step<OpsG1>, nseg * per, data, nseg, stride, len, s);
   }
 }
-void g2_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
-  for (uint64_t s = 1; s < len; s <<= 1) {
-    uint64_t per = (len + 2 * s - 1) / (2 * s);
-    LW(kw_jac_step<OpsG2>, nseg * per, data, nseg, stride, len, s);
-  }
-}
 void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st) {
   LW(kw_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);
-}
-void g2_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st) {
-  LW(kw_jac_to_aff<OpsG2>, n, in, stride, n, out, ostride);
 }
 void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st) { LW(kw_sum_g1, nseg, data, nseg, len, out); }
 void dlevel(void *D, uint64_t K, uint32_t h, hipStream_t st) { LW(kw_dlevel, K >> h, D, K, h); }

@@ -23,6 +23,12 @@ void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st);
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st);
+// the same over G2 (S nwin <= 1024), for the KZG proof over the fixed SRS points h_m
+void msm_slices_g2(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g2_aff *table, g2_jac *partial,
+                   hipStream_t st);
+void msm_tables_g2(const g2_aff *base, uint64_t M, uint32_t nwin, g2_aff *table, hipStream_t st);
+// out[i] = canonical value of the Montgomery-form F_r element in[i]
+void fr_canon(const fe *in, uint64_t n, fe *out, hipStream_t st);
 // input s at in[s*stride]; output to (s odd ? out1 : out0)[(s >> 1) * ostride]
 // one launch; cnt: nseg tree_counters(len) zeroed counters, zero again on return
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
@@ -59,9 +65,7 @@ void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const 
                 uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
 void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st);
 void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
-void g2_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st);
-void g2_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st);
 void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st);
 void dlevel(void *D, uint64_t K, uint32_t h, hipStream_t st);
 void diag_field(int which, int op, const void *a, const void *b, uint64_t n, void *out, hipStream_t st);
@@ -76,19 +80,20 @@ void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
 void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st);
-void kzg_terms(const g2_aff *h, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
 // sums of Jacobian segments on the engine, one launch (tree_counters(len) counters per segment)
 void g1_tree(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
 void g2_tree(g2_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
 // round-1 G1 terms on the engine (same layout as klw::oa_g1terms)
 void oa_g1terms(const g1_aff *A, const fe *B, uint64_t K, uint64_t nb, uint64_t h, g1_jac *S, hipStream_t st);
-// four-part split terms on the setup multiples hm[3 m + p - 1] = 2^{16 p} h_m: S2[4 id + p]
-void kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
 void gt_pow(const fp12 *in, const fe *k, uint64_t n, fp12 *out, hipStream_t st);
 // fused round kernels: G1 + G2 fold; Miller loops + G1 terms of the next round (oa_terms.hpp);
 // final exponentiations of two strided lists
 void oa_fold(const g1_aff *Ain, const fe *Bin, g1_aff *Aout, fe *Bout, const g2_aff *Vin, g2_aff *Vout, const fe *X,
              const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
+// KZG terms split in four parts on the setup multiples hm[3 m + p - 1] = 2^{16 p} h_m: S2[4 id + p]
+void kzg_terms_split(const g2_aff *h, const g2_aff *hm, const fe *Qc, uint64_t K, uint64_t nb, g2_jac *S2, hipStream_t st);
+// M[3 s + m - 1] = 2^{16 m} Q_s (affine), Q_s = Q[(s / seg) segstride + s % seg]
+void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st);
 void oa_pterms(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t q, fp12 *F, hipStream_t st);
 // the G1 terms of the next round: whole multiplications, or split in four parts on the
 // multiples M (whole arrays of length 4q, as made by fold_mults) with partials J and nb 8q
@@ -103,7 +108,6 @@ void final_exp2(const fp12 *in0, uint64_t st0, uint64_t n0, fp12 *out0, const fp
 // product of U with the 8 G_T parts of each side
 void gt_sqr_mults(const fp12 *G, uint64_t n, fp12 *M, hipStream_t st);
 // (the points of the multiples are P[(s / seg) segstride + s % seg], s < n)
-void g2_dbl_mults(const g2_aff *Q, uint64_t seg, uint64_t segstride, uint64_t n, g2_aff *M, hipStream_t st);
 // the reduced G1 groups of the terms taken ahead made ready for the combine: affine (PU1,
 // PX1) and PX1m[3 s + m - 1] = 2^{32 m} PX1[s]
 void g1_finish(const g1_jac *PS, uint64_t nb, uint64_t q, g1_aff *PU1, g1_aff *PX1, g1_aff *PX1m, hipStream_t st);

@@ -121,7 +121,8 @@ struct vc_params {
   void *mem = nullptr;      // all keys in one allocation
   g1_aff *ek, *g1gen, *g1beta, *table;
   g2_aff *vk, *h, *g2gen;
-  g2_aff *hm;  // 2^{16 p} h_m (p = 1..3, m < 2K - 2) for the split KZG terms
+  g2_aff *htab;  // 2^{8 w} h_m (w < 32, m < 2K - 2): fixed-base table of the KZG proof's MSM
+  g2_aff *hm;    // 2^{16 p} h_m (p = 1..3, m < 2K - 2) for the split KZG terms
   void *ws = nullptr;       // grow-only scratch shared by calls on these params
   size_t ws_size = 0;
   // side streams (default priority) and fork/join events for independent phases
@@ -137,9 +138,16 @@ struct vc_params {
 // device mostly idle: at most this many (batch, index) pairs per round.  Beyond it the
 // doubled Miller-loop count of that scheme costs more than the shorter chain saves.
 static constexpr uint64_t AHEAD_MAX_PAIRS = 4096;
+// in the ahead mode, rounds of more than this many pairs (batches x h) still run direct: the
+// device is full there and the terms taken ahead (twice the Miller loops) cost more than the
+// shorter chain saves; the first round at or below it is the first taken ahead
+static constexpr uint64_t DIRECT_MIN = 512;
 // folds of at most this many pairs (batches x h) run as four-part split multiplications
 static constexpr uint64_t FOLD_SPLIT_MAX = 256;
-// KZG proofs of at most this many split jobs (4 per term) run split
+// bases per block of the KZG proof's G2 MSM (times 32 windows: at most 1024 entries)
+static constexpr uint32_t KZG_S = 32;
+// KZG proofs of at most this many split jobs (4 per term) run as split multiplications
+// instead of the MSM: when the device is nearly idle the shorter chain wins
 static constexpr uint64_t KZG_SPLIT_MAX = 8192;
 
 // fork: `to` waits for the work issued so far on `from`
@@ -240,7 +248,7 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   Carve c;
   size_t o_ek = c.take<g1_aff>(2 * M - 1), o_g1 = c.take<g1_aff>(1), o_g1b = c.take<g1_aff>(1);
   size_t o_tab = c.take<g1_aff>(NWIN * M), o_vk = c.take<g2_aff>(lM), o_h = c.take<g2_aff>(2 * K - 1);
-  size_t o_g2 = c.take<g2_aff>(1), o_hm = c.take<g2_aff>(3 * (2 * K - 2));
+  size_t o_g2 = c.take<g2_aff>(1), o_htab = c.take<g2_aff>(NWIN * (2 * K - 2)), o_hm = c.take<g2_aff>(3 * (2 * K - 2));
   hipError_t e = hipMalloc(&pp->mem, c.off);
   if (e != hipSuccess) { delete pp; return hip_fail(e, "vc_setup alloc"); }
   pp->ek = at<g1_aff>(pp->mem, o_ek);
@@ -250,6 +258,7 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   pp->vk = at<g2_aff>(pp->mem, o_vk);
   pp->h = at<g2_aff>(pp->mem, o_h);
   pp->g2gen = at<g2_aff>(pp->mem, o_g2);
+  pp->htab = at<g2_aff>(pp->mem, o_htab);
   pp->hm = at<g2_aff>(pp->mem, o_hm);
   g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
   g2_aff g2 = {{fe_const(bn::G2X0), fe_const(bn::G2X1)}, {fe_const(bn::G2Y0), fe_const(bn::G2Y1)}};
@@ -271,6 +280,7 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   klw::g2_mul(pp->g2gen, 1, s, lM, pp->vk, st);
   kl::pow_table(beta, pw, 2 * K - 1, st);
   klw::g2_mul(pp->g2gen, 1, pw, 2 * K - 1, pp->h, st);
+  kl::msm_tables_g2(pp->h, 2 * K - 2, NWIN, pp->htab, st);
   ks::g2_dbl_mults(pp->h, 2 * K - 2, 0, 2 * K - 2, pp->hm, st);
   klw::g1_mul(pp->g1gen, 1, beta, 1, pp->g1beta, st);
   kl::msm_tables(pp->ek + (M - 1), M, NWIN, pp->table, st);
@@ -412,9 +422,12 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   size_t o_err = t.take<int>(1), o_A = t.take<g1_aff>(nb * K), o_V = t.take<g2_aff>(nb * K), o_B = t.take<fe>(nb * K);
   size_t o_F = t.take<fp12>(nb * K), o_S = t.take<g1_jac>(nb * K), o_Hq = t.take<uint32_t>(nb * qmax * 8);
   size_t o_sig = t.take<uint32_t>(nb * 8), o_Xi = t.take<fe>(nb * lK), o_Q = t.take<fe>(nb * nq), o_z = t.take<fe>(nb);
-  // KZG terms split in four parts when the jobs are few (the device is otherwise idle)
+  // KZG proof: split terms (4 partial results per term) or, with many terms, canonical
+  // quotient coefficients and the per-block partial sums of its MSM
   const bool kzg_split = 4 * nb * nq <= KZG_SPLIT_MAX;
-  size_t o_S2 = t.take<g2_jac>((kzg_split ? 4 : 1) * nb * nq), o_HS = t.take<g1_jac>(lM * (M / 2)), o_dec = t.take<glv::Dec>(nb);
+  const uint64_t kzg_nslice = (nq + KZG_S - 1) / KZG_S, kzg_len = kzg_split ? 4 * nq : kzg_nslice;
+  size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(lM * (M / 2));
+  size_t o_dec = t.take<glv::Dec>(nb);
   // Step 1 arrays of alternate rounds, and the terms taken one round ahead (oa_terms.hpp)
   const bool ahead = lK >= 2 && nb * K <= AHEAD_MAX_PAIRS;
   const uint64_t nterm = ahead ? 2 * nb * K : 0;
@@ -426,6 +439,9 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   size_t o_PX1m = t.take<g1_aff>(ahead ? 24 * nb : 0), o_PM = t.take<g1_jac>(ahead ? 16 * nb : 0);
   // split folds: multiples of the halves A[h + i], V[h + i] and the four partial results
   auto split_round = [&](uint32_t j) { return ahead && j <= lK && nb * (K >> j) <= FOLD_SPLIT_MAX; };
+  // first round whose L, R come from terms taken ahead (rounds before it run direct)
+  uint32_t j0 = 2;
+  while (j0 < lK && nb * (K >> j0) > DIRECT_MIN) j0++;
   const uint64_t nsplit = ahead ? std::min<uint64_t>(nb * K / 2, FOLD_SPLIT_MAX) : 0;
   // (multiples of whole arrays, one set per round parity; the G1 terms split likewise use them)
   size_t o_FM1 = t.take<g1_aff>(2 * 6 * nsplit), o_FM2 = t.take<g2_aff>(2 * 6 * nsplit);
@@ -442,6 +458,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   uint32_t *Hq = at<uint32_t>(ws, o_Hq), *sigma = at<uint32_t>(ws, o_sig);
   fe *Xinv = at<fe>(ws, o_Xi), *Q = at<fe>(ws, o_Q), *z = at<fe>(ws, o_z);
   g2_jac *S2 = at<g2_jac>(ws, o_S2);
+  fe *Qc = at<fe>(ws, o_Qc);
   g1_jac *HS = at<g1_jac>(ws, o_HS);
   glv::Dec *gdec = at<glv::Dec>(ws, o_dec);
   g1_aff *Ab[2] = {A, at<g1_aff>(ws, o_A2)};
@@ -465,7 +482,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // U and XY groups of the terms taken ahead (F_p12 on side stream 3, G1 on the caller's)
   const uint64_t c_dir = 2 * nb * tree_counters(K / 2), c_u = 2 * nb * tree_counters(K / 2),
                  c_xy = 4 * nb * tree_counters(K / 4);
-  const uint64_t c_kzg = kzg_split ? nb * tree_counters(4 * nq) : 0;
+  const uint64_t c_kzg = nb * tree_counters(kzg_len);
   if (int rc2 = ensure_cnt(pp, 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg)) { vc_proofs_free(pr); return rc2; }
   // (the counters of the terms' trees per round parity, whose streams run concurrently)
   uint32_t *cnt_dir = pp->cnt, *cnt_t = cnt_dir + c_dir;
@@ -569,7 +586,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   for (uint32_t j = 1; j <= lK; j++) {
     const uint64_t h = K >> j;
     const int cur = (j - 1) & 1, nxt = j & 1;
-    if (j == 1 || !ahead) {
+    if (!ahead || j < j0) {
       if (ahead) {
         ks::oa_g1terms(Ab[cur], Bb[cur], K, nb, h, S, sg);
         ks::g1_tree(S, 2 * nb, K / 2, h, cnt_g1dir, sg);
@@ -587,14 +604,18 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
         launch_fold_mults(1, s1);
         if (int rc2 = ev_mark(pp, 15, s1)) return rc2;
       }
-      // round 2's terms from the round-1 arrays, after the round-1 Miller loops (the G1 side
-      // after the multiples)
-      if (j == 1 && ahead) {
-        if (int rc2 = stream_wait(pp, 19, st, sfp[0])) return rc2;
-        if (int rc2 = launch_terms(2)) return rc2;
-        if (split_round(1))
-          if (int rc2 = ev_wait(pp, 15, sq)) return rc2;
-        if (int rc2 = launch_g1terms(2)) return rc2;
+      // the terms of round j0 from the arrays of the last direct round, after its Miller
+      // loops (the G1 side after the multiples of the arrays)
+      if (ahead && j + 1 == j0) {
+        if (int rc2 = stream_wait(pp, 19, st, sfp[j0 & 1])) return rc2;
+        if (int rc2 = launch_terms(j0)) return rc2;
+        if (j == 1) {
+          if (split_round(1))
+            if (int rc2 = ev_wait(pp, 15, sq)) return rc2;
+        } else if (int rc2 = stream_wait(pp, 16, sg, sq)) {  // the fold into these arrays, their multiples
+          return rc2;
+        }
+        if (int rc2 = launch_g1terms(j0)) return rc2;
       }
       ks::f12_reduce(F, 2 * nb, K / 2, h, cnt_dir, st);
       ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
@@ -618,13 +639,16 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
                           cnt_fold, K, nb, h, j, lK, sg);
       else
         ks::oa_fold(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, K, nb, h, j, lK, sg);
+      // a direct next round reads the folded arrays on the caller's stream
+      if (j + 1 < j0)
+        if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
       // terms of round j + 2 from the arrays of round j + 1 (just folded)
-      if (j + 2 <= lK) {
+      if (j + 2 <= lK && j + 2 > j0) {
         if (int rc2 = stream_wait(pp, 10, sg, sfp[j & 1])) return rc2;
         if (int rc2 = launch_terms(j + 2)) return rc2;
       }
       if (split_round(j + 1)) launch_fold_mults(j + 1, sg);
-      if (j + 2 <= lK) {
+      if (j + 2 <= lK && j + 2 > j0) {
         if (int rc2 = stream_wait(pp, 16, sg, sq)) return rc2;
         if (int rc2 = launch_g1terms(j + 2)) return rc2;
       }
@@ -650,13 +674,12 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, st);
   if (kzg_split) {
     ks::kzg_terms_split(pp->h, pp->hm, Q, K, nb, S2, st);
-    ks::g2_tree(S2, nb, 4 * nq, 4 * nq, cnt_kzg, st);
-    kl::g2_to_aff(S2, 4 * nq, nb, piv, 1, st);
   } else {
-    ks::kzg_terms(pp->h, Q, K, nb, S2, st);
-    klw::g2_reduce(S2, nb, nq, nq, st);
-    klw::g2_to_aff(S2, nq, nb, piv, 1, st);
+    kl::fr_canon(Q, nb * nq, Qc, st);
+    kl::msm_slices_g2(Qc, nb, nq, NWIN, KZG_S, pp->htab, S2, st);
   }
+  ks::g2_tree(S2, nb, kzg_len, kzg_len, cnt_kzg, st);
+  kl::g2_to_aff(S2, kzg_len, nb, piv, 1, st);
   // join Step 2
   if (int rc2 = stream_wait(pp, 13, s1, st)) return rc2;
   CKL("vc_open_all launch");
