@@ -25,8 +25,8 @@ import sys
 import time
 
 # hardware queues for the library's streams (as the package sets it), before any device use
-if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -207,6 +207,63 @@ def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile="all"):
     return limbs, commit_ms, open_ms, prof, wall
 
 
+BATCH_SETUPS = ((4, 6), (8, 2), (16, 1))   # (executors, streams per executor) of the batched-jobs runs
+
+
+def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2):
+    """Batched jobs: n_jobs independent vectors, N = 2^L with L uniform in [8, 18] (seeded),
+    b = min(L^2, K), uniform full-width entries, each committed once.  Open-all of every job
+    one after another on one stream, against the batch call on ne executors of ns streams
+    each (each job on its own executor, ne at a time); the best of `reps` passes each.  The
+    batch's serialized proofs at the ends of every vector are compared with the one-job
+    call's."""
+    import numpy as np
+    from paper_2601_03031_amd import inputs as I
+    rng = np.random.default_rng(seed)
+    Ls = [int(x) for x in rng.integers(8, 19, n_jobs)]
+    log("batched jobs: %d vectors, L in [8, 18]: setup and commit" % n_jobs)
+    params, jobs = {}, []
+    for i, L in enumerate(Ls):
+        if L not in params:
+            params[L] = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
+        pp = params[L]
+        limbs = I.entries(1 << L, 1000 * seed + i, 256)
+        m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+        jobs.append((pp, V.vc_commit(pp, m, 256), min(L * L, pp.K)))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def sequential():
+        t0 = time.perf_counter()
+        out = [V.vc_open_all(pp, cm, b, stream) for pp, cm, b in jobs]
+        return 1e3 * (time.perf_counter() - t0), out
+
+    seq_ms, seq_out = min((sequential() for _ in range(reps)), key=lambda r: r[0])
+    log("batched jobs: sequential %.1f ms" % seq_ms)
+    res = {"jobs": n_jobs, "L_counts": {str(L): Ls.count(L) for L in sorted(set(Ls))},
+           "proofs": sum(pp.N for pp, _, _ in jobs), "sequential_ms": round(seq_ms, 2), "batch_ms": {}}
+    for ne, ns in setups:
+        execs = [V.vc_exec_create(0, ns) for _ in range(ne)]
+        best, out = None, None
+        for _ in range(reps + 1):  # the first pass sizes every executor's workspace
+            t0 = time.perf_counter()
+            out = V.vc_open_all_batch(jobs, execs)
+            ms = 1e3 * (time.perf_counter() - t0)
+            best = ms if best is None or ms < best else best
+        for (pp, _, _), a, r in zip(jobs, out, seq_out):
+            for i in (0, pp.N - 1):
+                if V.vc_proof_get(a, i) != V.vc_proof_get(r, i):
+                    raise RuntimeError("batched proof %d of a 2^%d job differs from the one-job call" % (i, pp.log_n))
+        del out, execs
+        res["batch_ms"]["%dx%d" % (ne, ns)] = round(best, 2)
+        log("batched jobs: %d executors x %d streams %.1f ms" % (ne, ns, best))
+    k_best = min(res["batch_ms"], key=lambda k: res["batch_ms"][k])
+    res["speedup"] = round(seq_ms / res["batch_ms"][k_best], 2)
+    res["best_setup"] = k_best
+    res["hw_queues"] = int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)
+    return res
+
+
 def cpu_baseline(L, b, bits, seed):
     import oracle as O
     log("cpu baseline (oracle) L=%d b=%d" % (L, b))
@@ -232,6 +289,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--batch-only", type=str, default="", metavar="SETUPS",
+                    help="only run the batched-jobs comparison with these executors x streams setups "
+                         "(e.g. 4x6,16x1) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -256,6 +316,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.batch_only:
+        setups = [tuple(int(v) for v in x.split("x")) for x in a.batch_only.split(",")]
+        print(json.dumps(batched_jobs(V, torch, setups=setups)), flush=True)
+        return
 
     L, b, bits, seed = 16, 256, 32, 2
     # per-kernel table from a separate pass with every launch bracketed by events (the
@@ -300,6 +364,7 @@ def main():
             _, cs_, os_, _, _ = run_workload(V, torch, Ls, bs, bits_s, seed_s, 1, 1, profile=False)
             sweep["n2^%d_b%d" % (Ls, bs)] = round(os_[0], 3)
         extra["b_sweep_all_proofs_ms"] = sweep
+        extra["batched_64_jobs"] = batched_jobs(V, torch)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(L, b, bits, seed)

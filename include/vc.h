@@ -17,10 +17,11 @@
  *  - Device pointers are borrowed for the duration of the call and must be device
  *    memory on the params' device.  `stream` is a hipStream_t (NULL = default
  *    stream); work is ordered on it and every call is synchronous on return.
- *    vc_open_all also runs work on five side streams owned by the params (joined to
- *    `stream` before it returns); they overlap only if the process has at least six
- *    hardware queues (environment GPU_MAX_HW_QUEUES, read by HIP at its first device
- *    use), otherwise they share queues and run partly in sequence, with the same results.
+ *    vc_open_all also runs work on five side streams of the params' default executor
+ *    (joined to `stream` before it returns); they overlap only if the process has at
+ *    least six hardware queues (environment GPU_MAX_HW_QUEUES, read by HIP at its first
+ *    device use; the Python package raises it to 16), otherwise they share queues and run
+ *    partly in sequence, with the same results.
  *  - Handles (vc_params, vc_commitment, vc_proofs) own their device memory and are
  *    released with the matching *_free; a vc_proofs handle does not reference the
  *    commitment it was made from.
@@ -49,6 +50,7 @@ extern "C" {
 typedef struct vc_params vc_params;
 typedef struct vc_commitment vc_commitment;
 typedef struct vc_proofs vc_proofs;
+typedef struct vc_exec vc_exec;
 
 /* VC.Setup(1^lambda, 1^N) (Eq. vcpp): PST keys for log M variables and FC keys for
  * K entries, derived from a seeded TEST trapdoor (insecure: the paper requires a
@@ -68,6 +70,34 @@ int vc_commit(const vc_params *pp, const void *m_dev, uint64_t n, uint32_t entry
  * kept on the device in shared form (one FC batch proof per block of b
  * subvectors, the folding tree, the HyperEval commitments and the Merkle tree). */
 int vc_open_all(const vc_params *pp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out);
+
+/* Executor: the streams, events, workspace and reduction counters that vc_commit,
+ * vc_open_all and vc_verify use.  Every vc_params holds a default one (six streams), so calls
+ * on the same params must not overlap; calls that run at the same time need executors of
+ * their own.  nstreams in [1, 6]: the executor's own stream plus the five side streams of an
+ * open-all mapped onto nstreams streams in turn.  Six give one job the most overlap; with
+ * many jobs at once fewer streams per job (1 or 2) keep the jobs from sharing hardware
+ * queues (GPU_MAX_HW_QUEUES, read once when HIP starts).  Results do not depend on it.
+ * Created on `device`, owned by the caller, released with vc_exec_free (after the calls
+ * that use it have returned).  VC_EINVAL for nstreams outside [1, 6]. */
+int vc_exec_create(int device, uint32_t nstreams, vc_exec **out);
+void vc_exec_free(vc_exec *ex);
+
+/* vc_open_all (Protocol 1, §4.2) on executor ex (of the params' device) instead of the
+ * params' default one; `stream` as for vc_open_all. */
+int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t b, vc_exec *ex, void *stream,
+                   vc_proofs **out);
+
+/* Batched jobs: OpenAll (Protocol 1, §4.2) for n independent vectors, job i on params
+ * pps[i] (jobs may share params) with commitment cms[i] and batch size bs[i]; its proofs in
+ * outs[i] (n entries), each as from vc_open_all.  At most nexec jobs run at a time, one per
+ * executor exs[0..nexec) (each with its own host thread and stream); the jobs are
+ * independent latency-bound chains, so several of them share the device; the largest
+ * vectors are started first.  All params and
+ * executors must be on one device.  Returns VC_OK, or the first error; on error every
+ * outs[i] is NULL.  While profiling is enabled the jobs run one at a time. */
+int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms, const uint32_t *bs,
+                      uint32_t nexec, vc_exec *const *exs, vc_proofs **outs);
 
 /* Serialized length of a proof whose block holds t subvector commitments. */
 uint64_t vc_proof_len(uint32_t log_n, uint32_t t);

@@ -13,11 +13,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libvc.so")
 
-# open-all runs on the caller's stream and five side streams; HIP maps streams onto
-# GPU_MAX_HW_QUEUES hardware queues per process (default 4), and streams that share a queue
-# run one after the other.  Raised to 8 here; takes effect only before the process first
-# uses the device.
-HW_QUEUES = 8
+# open-all runs on the caller's stream and five side streams, and batches run several jobs
+# at once on executors of their own; HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues
+# per process (default 4), and streams that share a queue run one after the other.  Raised
+# to 16 here (one job's six streams, or sixteen one-stream jobs, on queues of their own;
+# more queues than that slowed single jobs down in measurements); takes effect only before
+# the process first uses the device.
+HW_QUEUES = 16
 
 
 def _raise_hw_queues() -> None:
@@ -55,6 +57,11 @@ def lib():
         L.vc_setup.argtypes = [u32, u8p, C.c_int, C.POINTER(vp)]
         L.vc_commit.argtypes = [vp, vp, u64, u32, vp, C.POINTER(vp), vp]
         L.vc_open_all.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
+        L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
+        L.vc_exec_free.argtypes = [vp]
+        L.vc_open_all_ex.argtypes = [vp, vp, u32, vp, vp, C.POINTER(vp)]
+        L.vc_open_all_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), u32, C.POINTER(vp),
+                                        C.POINTER(vp)]
         L.vc_proof_len.restype = u64
         L.vc_proof_len.argtypes = [u32, u32]
         L.vc_proof_get.argtypes = [vp, u64, vp, sz, C.POINTER(sz)]
@@ -169,6 +176,37 @@ def vc_open_all(pp: Params, cm: Commitment, b: int, stream=None) -> Proofs:
     out = C.c_void_p()
     _check(lib().vc_open_all(pp.ptr, cm.ptr, b, _stream_ptr(stream), C.byref(out)), "vc_open_all")
     return Proofs(out, pp, b)
+
+
+class Exec(_Handle):
+    """Streams, events and workspace of one open-all job at a time."""
+    _free = "vc_exec_free"
+
+
+def vc_exec_create(device: int = 0, nstreams: int = 6) -> Exec:
+    out = C.c_void_p()
+    _check(lib().vc_exec_create(device, nstreams, C.byref(out)), "vc_exec_create")
+    return Exec(out)
+
+
+def vc_open_all_ex(pp: Params, cm: Commitment, b: int, ex: Exec, stream=None) -> Proofs:
+    out = C.c_void_p()
+    _check(lib().vc_open_all_ex(pp.ptr, cm.ptr, b, ex.ptr, _stream_ptr(stream), C.byref(out)), "vc_open_all_ex")
+    return Proofs(out, pp, b)
+
+
+def vc_open_all_batch(jobs, execs) -> list:
+    """jobs: a list of (Params, Commitment, b); execs: the executors that run them, one job
+    at a time each.  Returns the Proofs of every job, in order."""
+    n = len(jobs)
+    VP = C.c_void_p
+    pps = (VP * max(n, 1))(*[pp.ptr for pp, _, _ in jobs])
+    cms = (VP * max(n, 1))(*[cm.ptr for _, cm, _ in jobs])
+    bs = (C.c_uint32 * max(n, 1))(*[b for _, _, b in jobs])
+    exs = (VP * max(len(execs), 1))(*[ex.ptr for ex in execs])
+    outs = (VP * max(n, 1))()
+    _check(lib().vc_open_all_batch(n, pps, cms, bs, len(execs), exs, outs), "vc_open_all_batch")
+    return [Proofs(outs[i], jobs[i][0], jobs[i][2]) for i in range(n)]
 
 
 def vc_proof_len(log_n: int, t: int) -> int:

@@ -283,11 +283,12 @@ void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, ui
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   hipStream_t st) {
   size_t shm = 2 * (2 * K - 1) * sizeof(fe);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void *)k_kzg_quotient, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (2 * KZG_T) * (int)sizeof(fe));
-    attr_set = true;
-  }
+  static const bool attr_set = [] {  // once per process (thread-safe initialisation)
+    (void)hipFuncSetAttribute((const void *)k_kzg_quotient, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * (2 * KZG_T) * (int)sizeof(fe));
+    return true;
+  }();
+  (void)attr_set;
   LAUNCH(k_kzg_quotient, dim3((unsigned)nb), dim3(KZG_T), shm, Xinv, X, V, K, lK, Q, z);
 }
 void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st) {

@@ -10,6 +10,9 @@
 #include <cstdlib>
 #include <string>
 #include <vector>
+#include <thread>
+#include <atomic>
+#include <algorithm>
 #include "kernels.h"
 #include "verify.h"
 #include "vc.h"
@@ -63,7 +66,7 @@ std::string g_prof_only;          // empty: every kernel
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;  // timing events, reused across profiling runs
 size_t g_prof_next = 0;
-hipEvent_t g_prof_open = nullptr;
+thread_local hipEvent_t g_prof_open = nullptr;
 
 hipEvent_t prof_event() {
   if (g_prof_next == g_prof_pool.size()) {
@@ -114,6 +117,27 @@ void name_last(const char *name) {
 }
 }  // namespace prof
 
+// Per-call resources of open-all (and commit / verify): side streams (default priority),
+// fork/join events, the grow-only workspace and the arrival counters of the one-launch
+// reduction trees (zeroed once; each tree leaves its counters zero again).  Calls that run at
+// the same time need executors of their own; each params holds a default one.  An executor
+// owns 1..6 streams: main (the job's stream in batch calls) and the five side streams map
+// onto them in turn, so with fewer than six the side work shares streams (same results,
+// less overlap inside one job, fewer hardware queues per job when many jobs run at once).
+struct vc_exec {
+  int device;
+  void *ws = nullptr;
+  size_t ws_size = 0;
+  hipStream_t own[6] = {};
+  uint32_t nown = 0;
+  hipStream_t main = nullptr;
+  hipStream_t side[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[20] = {};
+  uint32_t *cnt = nullptr;
+  uint64_t cnt_n = 0;
+  bool cnt_dirty = false;  // counters to be zeroed before the next use (new, or left by a failed call)
+};
+
 struct vc_params {
   int device;
   uint32_t L, lK, lM;
@@ -123,15 +147,7 @@ struct vc_params {
   g2_aff *vk, *h, *g2gen;
   g2_aff *htab;  // 2^{8 w} h_m (w < 32, m < 2K - 2): fixed-base table of the KZG proof's MSM
   g2_aff *hm;    // 2^{16 p} h_m (p = 1..3, m < 2K - 2) for the split KZG terms
-  void *ws = nullptr;       // grow-only scratch shared by calls on these params
-  size_t ws_size = 0;
-  // side streams (default priority) and fork/join events for independent phases
-  hipStream_t side[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t ev[20] = {};
-  // arrival counters of the one-launch reduction trees: zeroed once, each tree leaves its
-  // counters zero again (grow-only)
-  uint32_t *cnt = nullptr;
-  uint64_t cnt_n = 0;
+  vc_exec *ex = nullptr;  // default executor of calls on these params
 };
 
 // Step 1 takes the next round's terms ahead (oa_terms.hpp) when the batches leave the
@@ -151,18 +167,18 @@ static constexpr uint32_t KZG_S = 32;
 static constexpr uint64_t KZG_SPLIT_MAX = 8192;
 
 // fork: `to` waits for the work issued so far on `from`
-static int stream_wait(vc_params *pp, int slot, hipStream_t from, hipStream_t to) {
-  CK(hipEventRecord(pp->ev[slot], from));
-  CK(hipStreamWaitEvent(to, pp->ev[slot], 0));
+static int stream_wait(vc_exec *ex, int slot, hipStream_t from, hipStream_t to) {
+  CK(hipEventRecord(ex->ev[slot], from));
+  CK(hipStreamWaitEvent(to, ex->ev[slot], 0));
   return VC_OK;
 }
 // the same split in two: mark the work issued so far on a stream, wait for the mark later
-static int ev_mark(vc_params *pp, int slot, hipStream_t from) {
-  CK(hipEventRecord(pp->ev[slot], from));
+static int ev_mark(vc_exec *ex, int slot, hipStream_t from) {
+  CK(hipEventRecord(ex->ev[slot], from));
   return VC_OK;
 }
-static int ev_wait(vc_params *pp, int slot, hipStream_t to) {
-  CK(hipStreamWaitEvent(to, pp->ev[slot], 0));
+static int ev_wait(vc_exec *ex, int slot, hipStream_t to) {
+  CK(hipStreamWaitEvent(to, ex->ev[slot], 0));
   return VC_OK;
 }
 
@@ -182,24 +198,72 @@ struct vc_proofs {
   size_t o_Cj, o_C, o_Lgt, o_Rgt, o_Lg1, o_Rg1, o_X, o_Al, o_vl, o_piv, o_tree, o_rho, o_Y, o_D, o_W;
 };
 
-static int ensure_cnt(vc_params *pp, uint64_t n) {
-  if (pp->cnt_n >= n) return VC_OK;
-  if (pp->cnt) CK(hipFree(pp->cnt));
-  pp->cnt = nullptr;
-  pp->cnt_n = 0;
-  CK(hipMalloc(&pp->cnt, n * sizeof(uint32_t)));
-  CK(hipMemset(pp->cnt, 0, n * sizeof(uint32_t)));
-  pp->cnt_n = n;
+// At least n zeroed arrival counters.  New ones are cleared on the call's stream `st`, ahead of
+// every launch of the call (its side streams fork from st later): a plain hipMemset runs on the
+// null stream, which the non-blocking streams of the executor do not wait for.
+static int ensure_cnt(vc_exec *ex, uint64_t n, hipStream_t st) {
+  if (ex->cnt_n < n) {
+    if (ex->cnt) CK(hipFree(ex->cnt));
+    ex->cnt = nullptr;
+    ex->cnt_n = 0;
+    CK(hipMalloc(&ex->cnt, n * sizeof(uint32_t)));
+    ex->cnt_n = n;
+    ex->cnt_dirty = true;
+  }
+  if (ex->cnt_dirty) {
+    CK(hipMemsetAsync(ex->cnt, 0, ex->cnt_n * sizeof(uint32_t), st));
+    ex->cnt_dirty = false;
+  }
   return VC_OK;
 }
 
-static int ensure_ws(vc_params *pp, size_t need) {
-  if (pp->ws_size >= need) return VC_OK;
-  if (pp->ws) CK(hipFree(pp->ws));
-  pp->ws = nullptr;
-  pp->ws_size = 0;
-  CK(hipMalloc(&pp->ws, need));
-  pp->ws_size = need;
+static int ensure_ws(vc_exec *ex, size_t need) {
+  if (ex->ws_size >= need) return VC_OK;
+  if (ex->ws) CK(hipFree(ex->ws));
+  ex->ws = nullptr;
+  ex->ws_size = 0;
+  CK(hipMalloc(&ex->ws, need));
+  ex->ws_size = need;
+  return VC_OK;
+}
+
+VC_API void vc_exec_free(vc_exec *ex) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!ex) return;
+  hipSetDevice(ex->device);
+  if (ex->ws) hipFree(ex->ws);
+  if (ex->cnt) hipFree(ex->cnt);
+  for (auto sd : ex->own)
+    if (sd) hipStreamDestroy(sd);
+  for (auto ev : ex->ev)
+    if (ev) hipEventDestroy(ev);
+  delete ex;
+}
+
+VC_API int vc_exec_create(int device, uint32_t nstreams, vc_exec **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!out) return VC_EINVAL;
+  *out = nullptr;
+  if (nstreams < 1 || nstreams > 6) return VC_EINVAL;
+  CK(hipSetDevice(device));
+  vc_exec *ex = new vc_exec();
+  ex->device = device;
+  hipError_t e = hipSuccess;
+  for (uint32_t i = 0; i < nstreams && e == hipSuccess; i++) {
+    e = hipStreamCreateWithFlags(&ex->own[i], hipStreamNonBlocking);
+    if (e == hipSuccess) ex->nown = i + 1;
+  }
+  if (e == hipSuccess) {
+    ex->main = ex->own[0];
+    for (uint32_t i = 0; i < 5; i++) ex->side[i] = ex->own[(i + 1) % nstreams];
+  }
+  for (auto &ev : ex->ev)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    vc_exec_free(ex);
+    return hip_fail(e, "vc_exec_create");
+  }
+  *out = ex;
   return VC_OK;
 }
 
@@ -230,14 +294,11 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   CK(hipSetDevice(device));
   vc_params *pp = new vc_params();
   pp->device = device;
-  for (auto &sd : pp->side) {
-    hipError_t e = hipStreamCreateWithFlags(&sd, hipStreamNonBlocking);
-    if (e != hipSuccess) { vc_params_free(pp); return hip_fail(e, "vc_setup stream"); }
+  if (int rc = vc_exec_create(device, 6, &pp->ex)) {
+    vc_params_free(pp);
+    return rc;
   }
-  for (auto &ev : pp->ev) {
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) { vc_params_free(pp); return hip_fail(e, "vc_setup event"); }
-  }
+  vc_exec *ex = pp->ex;
   pp->L = log_n;
   pp->lK = log_n / 2;
   pp->lM = log_n - pp->lK;
@@ -266,10 +327,10 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   Carve t;
   size_t o_seed = t.take<uint8_t>(32), o_s = t.take<fe>(lM + 1), o_beta = t.take<fe>(1);
   size_t o_w = t.take<fe>(2 * M - 1), o_pw = t.take<fe>(2 * K - 1);
-  int rc = ensure_ws(pp, t.off);
+  int rc = ensure_ws(ex, t.off);
   if (rc) { vc_params_free(pp); return rc; }
   hipStream_t st = nullptr;
-  void *ws = pp->ws;
+  void *ws = ex->ws;
   CK(hipMemcpy(pp->g1gen, &g1, sizeof g1, hipMemcpyHostToDevice));
   CK(hipMemcpy(pp->g2gen, &g2, sizeof g2, hipMemcpyHostToDevice));
   CK(hipMemcpy(at<uint8_t>(ws, o_seed), seed, 32, hipMemcpyHostToDevice));
@@ -295,12 +356,7 @@ VC_API void vc_params_free(vc_params *pp) {
   if (!pp) return;
   hipSetDevice(pp->device);
   if (pp->mem) hipFree(pp->mem);
-  if (pp->ws) hipFree(pp->ws);
-  if (pp->cnt) hipFree(pp->cnt);
-  for (auto sd : pp->side)
-    if (sd) hipStreamDestroy(sd);
-  for (auto ev : pp->ev)
-    if (ev) hipEventDestroy(ev);
+  vc_exec_free(pp->ex);
   delete pp;
 }
 
@@ -309,7 +365,8 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
                      vc_commitment **out, uint8_t C_out[384]) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!cpp || !m_dev || !out || n != cpp->N || (entry_bits != 32 && entry_bits != 256)) return VC_EINVAL;
-  vc_params *pp = const_cast<vc_params *>(cpp);
+  const vc_params *pp = cpp;
+  vc_exec *ex = pp->ex;
   *out = nullptr;
   CK(hipSetDevice(pp->device));
   hipStream_t st = (hipStream_t)stream;
@@ -329,9 +386,9 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   uint64_t nslice = (M + S - 1) / S;
   Carve t;
   size_t o_err = t.take<int>(1), o_part = t.take<g1_jac>(K * nslice), o_F = t.take<fp12>(K), o_enc = t.take<uint8_t>(384);
-  int rc = ensure_ws(pp, t.off);
+  int rc = ensure_ws(ex, t.off);
   if (rc) { vc_commitment_free(cm); return rc; }
-  void *ws = pp->ws;
+  void *ws = ex->ws;
   int *err = at<int>(ws, o_err);
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   if (entry_bits == 32) {
@@ -347,16 +404,21 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   // FC.Commit: C = prod_j e(C_j, v[j]), v[j] = h[2j]
   fp12 *F = at<fp12>(ws, o_F);
   ks::miller(cm->Cj, 1, pp->h, 2, K, F, st);
-  if (int rc = ensure_cnt(pp, tree_counters(K))) { vc_commitment_free(cm); return rc; }
-  ks::f12_reduce(F, 1, K, K, pp->cnt, st);
+  if (int rc = ensure_cnt(ex, tree_counters(K), st)) { vc_commitment_free(cm); return rc; }
+  ks::f12_reduce(F, 1, K, K, ex->cnt, st);
   ks::final_exp(F, 1, 1, cm->C, nullptr, 1, st);
   uint8_t *enc = at<uint8_t>(ws, o_enc);
   kl::encode(reinterpret_cast<const fe *>(cm->C), 12, 0, enc, st);
-  CKL("vc_commit launch");
   int herr = 0;
-  CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
-  if (C_out) CK(hipMemcpyAsync(C_out, enc, 384, hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && C_out) e = hipMemcpyAsync(C_out, enc, 384, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    ex->cnt_dirty = true;  // the product tree may have stopped half way
+    vc_commitment_free(cm);
+    return hip_fail(e, "vc_commit");
+  }
   if (herr & VC_ERRBIT_RANGE) { vc_commitment_free(cm); return VC_EINVAL; }
   *out = cm;
   return VC_OK;
@@ -371,13 +433,12 @@ VC_API void vc_commitment_free(vc_commitment *cm) {
 }
 
 // ------------------------------------------------------------------ open-all
-VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out) {
-  (void)hipGetLastError();  // errors left by other HIP clients are not ours
-  if (!cpp || !cm || !out || cm->pp != cpp || b < 1 || b > cpp->K) return VC_EINVAL;
-  vc_params *pp = const_cast<vc_params *>(cpp);
+static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t b, vc_exec *ex, hipStream_t st,
+                         vc_proofs **out) {
+  if (!cpp || !cm || !out || !ex || cm->pp != cpp || b < 1 || b > cpp->K || ex->device != cpp->device) return VC_EINVAL;
+  const vc_params *pp = cpp;
   *out = nullptr;
   CK(hipSetDevice(pp->device));
-  hipStream_t st = (hipStream_t)stream;
   const uint64_t N = pp->N, K = pp->K, M = pp->M;
   const uint32_t lK = pp->lK, lM = pp->lM;
   const uint64_t nb = (K + b - 1) / b;
@@ -406,6 +467,18 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   pr->o_W = c.take<g1_aff>(M - 1);
   hipError_t e = hipMalloc(&pr->mem, c.off);
   if (e != hipSuccess) { delete pr; return hip_fail(e, "vc_open_all alloc"); }
+  // on every error return below the bundle is released (hipFree waits for the work in flight)
+  // and the executor's counters are cleared before their next use (trees may have stopped
+  // half way)
+  struct Release {
+    vc_proofs *p;
+    vc_exec *ex;
+    ~Release() {
+      if (!p) return;
+      vc_proofs_free(p);
+      ex->cnt_dirty = true;
+    }
+  } release{pr, ex};
   void *bm = pr->mem;
   g1_aff *Cj = at<g1_aff>(bm, pr->o_Cj);
   fp12 *C = at<fp12>(bm, pr->o_C);
@@ -446,9 +519,9 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // (multiples of whole arrays, one set per round parity; the G1 terms split likewise use them)
   size_t o_FM1 = t.take<g1_aff>(2 * 6 * nsplit), o_FM2 = t.take<g2_aff>(2 * 6 * nsplit);
   size_t o_FJ1 = t.take<g1_jac>(4 * nsplit), o_FJ2 = t.take<g2_jac>(4 * nsplit), o_GJ = t.take<g1_jac>(16 * nsplit);
-  int rc = ensure_ws(pp, t.off);
-  if (rc) { vc_proofs_free(pr); return rc; }
-  void *ws = pp->ws;
+  int rc = ensure_ws(ex, t.off);
+  if (rc) return rc;
+  void *ws = ex->ws;
   int *err = at<int>(ws, o_err);
   g1_aff *A = at<g1_aff>(ws, o_A);
   g2_aff *V = at<g2_aff>(ws, o_V);
@@ -483,9 +556,9 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   const uint64_t c_dir = 2 * nb * tree_counters(K / 2), c_u = 2 * nb * tree_counters(K / 2),
                  c_xy = 4 * nb * tree_counters(K / 4);
   const uint64_t c_kzg = nb * tree_counters(kzg_len);
-  if (int rc2 = ensure_cnt(pp, 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg)) { vc_proofs_free(pr); return rc2; }
+  if (int rc2 = ensure_cnt(ex, 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg, st)) return rc2;
   // (the counters of the terms' trees per round parity, whose streams run concurrently)
-  uint32_t *cnt_dir = pp->cnt, *cnt_t = cnt_dir + c_dir;
+  uint32_t *cnt_dir = ex->cnt, *cnt_t = cnt_dir + c_dir;
   uint32_t *cnt_fu[2] = {cnt_t, cnt_t + 2 * (c_u + c_xy)}, *cnt_fxy[2] = {cnt_fu[0] + c_u, cnt_fu[1] + c_u};
   uint32_t *cnt_gu[2] = {cnt_fxy[0] + c_xy, cnt_fxy[1] + c_xy}, *cnt_gxy[2] = {cnt_gu[0] + c_u, cnt_gu[1] + c_u};
   uint32_t *cnt_fold = cnt_t + 4 * (c_u + c_xy), *cnt_kzg = cnt_fold + 2 * nsplit, *cnt_g1dir = cnt_kzg + c_kzg,
@@ -499,10 +572,10 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // ---- Step 2 runs on side stream 1, concurrently with Step 1: Merkle tree (Fiat-Shamir),
   // randomized folding tree, HyperEval on g* (Protocol 1 Step 2 and its Sub-protocol).  Its
   // launches are issued after those of the first Step 1 round, which is on the critical path.
-  hipStream_t s1 = pp->side[0], s2 = pp->side[1];
-  if (int rc2 = ev_mark(pp, 0, st)) return rc2;
+  hipStream_t s1 = ex->side[0], s2 = ex->side[1];
+  if (int rc2 = ev_mark(ex, 0, st)) return rc2;
   auto launch_step2 = [&]() -> int {
-    if (int rc2 = ev_wait(pp, 0, s1)) return rc2;
+    if (int rc2 = ev_wait(ex, 0, s1)) return rc2;
     hipStream_t st = s1;  // launches below go to side stream 1
     kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
     for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(tree, s, st);
@@ -534,7 +607,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   // Streams of the ahead mode: side 2 the folds and the multiples, sides 3 and 4 the
   // pairing side of the terms of even and odd rounds (Miller loops, products, final
   // exponentiations), side 5 their G1 side; the caller's stream combines and hashes.
-  hipStream_t sg = s2, sf = pp->side[2], sfp[2] = {pp->side[2], pp->side[3]}, sq = pp->side[4];
+  hipStream_t sg = s2, sf = ex->side[2], sfp[2] = {ex->side[2], ex->side[3]}, sq = ex->side[4];
   kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
   // multiples 2^{32 m} A[i] (m = 1..3) of the whole arrays A of round j (for its split fold
   // and the split G1 terms of round j + 1) and 2^{16 m} V[h + i] of the halves V[h..) (for
@@ -548,11 +621,11 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   kl::fc_chunks(Cj, K, b, nb, Hq, st);
   kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
   kl::fc_r(K, b, nb, sigma, B, st);
-  if (int rc2 = stream_wait(pp, 1, st, sg)) return rc2;
-  if (int rc2 = stream_wait(pp, 2, st, sf)) return rc2;
+  if (int rc2 = stream_wait(ex, 1, st, sg)) return rc2;
+  if (int rc2 = stream_wait(ex, 2, st, sf)) return rc2;
   if (ahead) {
-    if (int rc2 = stream_wait(pp, 17, st, sfp[1])) return rc2;
-    if (int rc2 = stream_wait(pp, 18, st, sq)) return rc2;
+    if (int rc2 = stream_wait(ex, 17, st, sfp[1])) return rc2;
+    if (int rc2 = stream_wait(ex, 18, st, sq)) return rc2;
   }
   // terms of round jn >= 2 from the arrays of round jn - 1 (one buffer set per round parity):
   // the pairing side (Miller loops, group products, final exponentiations, squaring
@@ -566,7 +639,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     ks::f12_reduce(F2[par] + nb * 4 * q, 4 * nb, q, q, cnt_fxy[par], s);
     ks::final_exp2(F2[par], 2 * q, 2 * nb, PU[par], F2[par] + nb * 4 * q, q, 4 * nb, PX[par], s);
     ks::gt_sqr_mults(PX[par], 4 * nb, PXm[par], s);
-    return ev_mark(pp, 6 + par, s);
+    return ev_mark(ex, 6 + par, s);
   };
   // ... and the G1 side (terms, split in four parts when the arrays of round jn - 1 have
   // multiples, group sums, affine forms and multiples) on side stream 5, ready at event
@@ -581,7 +654,7 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
     ks::g1_tree(PS[par], 2 * nb, 2 * q, 2 * q, cnt_gu[par], sq);
     ks::g1_tree(PS[par] + nb * 4 * q, 4 * nb, q, q, cnt_gxy[par], sq);
     ks::g1_finish(PS[par], nb, q, PU1[par], PX1[par], PX1m[par], sq);
-    return ev_mark(pp, 8 + par, sq);
+    return ev_mark(ex, 8 + par, sq);
   };
   for (uint32_t j = 1; j <= lK; j++) {
     const uint64_t h = K >> j;
@@ -595,45 +668,45 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
         klw::g1_reduce(S, 2 * nb, K / 2, h, sg);
       }
       kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
-      if (int rc2 = ev_mark(pp, 3, sg)) return rc2;
+      if (int rc2 = ev_mark(ex, 3, sg)) return rc2;
       ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
       // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
       // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
       if (j == 1 && split_round(1)) {
-        if (int rc2 = stream_wait(pp, 14, st, s1)) return rc2;
+        if (int rc2 = stream_wait(ex, 14, st, s1)) return rc2;
         launch_fold_mults(1, s1);
-        if (int rc2 = ev_mark(pp, 15, s1)) return rc2;
+        if (int rc2 = ev_mark(ex, 15, s1)) return rc2;
       }
       // the terms of round j0 from the arrays of the last direct round, after its Miller
       // loops (the G1 side after the multiples of the arrays)
       if (ahead && j + 1 == j0) {
-        if (int rc2 = stream_wait(pp, 19, st, sfp[j0 & 1])) return rc2;
+        if (int rc2 = stream_wait(ex, 19, st, sfp[j0 & 1])) return rc2;
         if (int rc2 = launch_terms(j0)) return rc2;
         if (j == 1) {
           if (split_round(1))
-            if (int rc2 = ev_wait(pp, 15, sq)) return rc2;
-        } else if (int rc2 = stream_wait(pp, 16, sg, sq)) {  // the fold into these arrays, their multiples
+            if (int rc2 = ev_wait(ex, 15, sq)) return rc2;
+        } else if (int rc2 = stream_wait(ex, 16, sg, sq)) {  // the fold into these arrays, their multiples
           return rc2;
         }
         if (int rc2 = launch_g1terms(j0)) return rc2;
       }
       ks::f12_reduce(F, 2 * nb, K / 2, h, cnt_dir, st);
       ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
-      if (int rc2 = ev_wait(pp, 3, st)) return rc2;
+      if (int rc2 = ev_wait(ex, 3, st)) return rc2;
     } else {
       // L_j, R_j from the terms taken from the arrays of round j - 1 and x_{j-1}
       const int par = j & 1;
-      if (int rc2 = ev_wait(pp, 6 + par, st)) return rc2;
-      if (int rc2 = ev_wait(pp, 8 + par, st)) return rc2;
+      if (int rc2 = ev_wait(ex, 6 + par, st)) return rc2;
+      if (int rc2 = ev_wait(ex, 8 + par, st)) return rc2;
       ks::oa_combine_split(PX[par], PXm[par], PX1[par], PX1m[par], X + (j - 2), Xinv + (j - 2), lK, nb, PE, PM, st);
       ks::oa_combine8(PU[par], PE, PU1[par], PM, nb, Lgt + (j - 1), Rgt + (j - 1), Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
     }
     kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
     // fold with x_j into the other buffer
     if (ahead) {
-      if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
+      if (int rc2 = stream_wait(ex, 4, st, sg)) return rc2;
       if (j == 1 && split_round(1))
-        if (int rc2 = ev_wait(pp, 15, sg)) return rc2;
+        if (int rc2 = ev_wait(ex, 15, sg)) return rc2;
       if (split_round(j))
         ks::oa_fold_split(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, FM1[j & 1], FM2[j & 1], FJ1, FJ2,
                           cnt_fold, K, nb, h, j, lK, sg);
@@ -641,31 +714,31 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
         ks::oa_fold(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Vb[cur], Vb[nxt], X, Xinv, K, nb, h, j, lK, sg);
       // a direct next round reads the folded arrays on the caller's stream
       if (j + 1 < j0)
-        if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
+        if (int rc2 = stream_wait(ex, 11, sg, st)) return rc2;
       // terms of round j + 2 from the arrays of round j + 1 (just folded)
       if (j + 2 <= lK && j + 2 > j0) {
-        if (int rc2 = stream_wait(pp, 10, sg, sfp[j & 1])) return rc2;
+        if (int rc2 = stream_wait(ex, 10, sg, sfp[j & 1])) return rc2;
         if (int rc2 = launch_terms(j + 2)) return rc2;
       }
       if (split_round(j + 1)) launch_fold_mults(j + 1, sg);
       if (j + 2 <= lK && j + 2 > j0) {
-        if (int rc2 = stream_wait(pp, 16, sg, sq)) return rc2;
+        if (int rc2 = stream_wait(ex, 16, sg, sq)) return rc2;
         if (int rc2 = launch_g1terms(j + 2)) return rc2;
       }
     } else {
-      if (int rc2 = stream_wait(pp, 4, st, sg)) return rc2;
+      if (int rc2 = stream_wait(ex, 4, st, sg)) return rc2;
       kl::glv_dec(X, nb, j, lK, gdec, sg);
       klw::oa_fold_g1(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Xinv, gdec, K, nb, h, j, lK, sg);
-      if (int rc2 = stream_wait(pp, 5, st, sf)) return rc2;
+      if (int rc2 = stream_wait(ex, 5, st, sf)) return rc2;
       ks::oa_fold_g2(Vb[cur], Vb[nxt], Xinv, K, nb, h, j, lK, sf);
-      if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
-      if (int rc2 = stream_wait(pp, 12, sf, st)) return rc2;
+      if (int rc2 = stream_wait(ex, 11, sg, st)) return rc2;
+      if (int rc2 = stream_wait(ex, 12, sf, st)) return rc2;
     }
     if (j == std::min<uint32_t>(2, lK))
       if (int rc2 = launch_step2()) return rc2;
   }
   if (ahead)
-    if (int rc2 = stream_wait(pp, 11, sg, st)) return rc2;
+    if (int rc2 = stream_wait(ex, 11, sg, st)) return rc2;
   A = Ab[lK & 1];
   V = Vb[lK & 1];
   CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
@@ -681,14 +754,81 @@ VC_API int vc_open_all(const vc_params *cpp, const vc_commitment *cm, uint32_t b
   ks::g2_tree(S2, nb, kzg_len, kzg_len, cnt_kzg, st);
   kl::g2_to_aff(S2, kzg_len, nb, piv, 1, st);
   // join Step 2
-  if (int rc2 = stream_wait(pp, 13, s1, st)) return rc2;
+  if (int rc2 = stream_wait(ex, 13, s1, st)) return rc2;
   CKL("vc_open_all launch");
   int herr = 0;
   CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  if (herr & VC_ERRBIT_CHALLENGE) { vc_proofs_free(pr); return VC_ECHALLENGE; }
+  if (herr & VC_ERRBIT_CHALLENGE) return VC_ECHALLENGE;
+  release.p = nullptr;
   *out = pr;
   return VC_OK;
+}
+
+VC_API int vc_open_all(const vc_params *pp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pp) return VC_EINVAL;
+  return open_all_impl(pp, cm, b, pp->ex, (hipStream_t)stream, out);
+}
+
+VC_API int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t b, vc_exec *ex, void *stream,
+                          vc_proofs **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  return open_all_impl(pp, cm, b, ex, (hipStream_t)stream, out);
+}
+
+// Several open-all jobs, at most nexec at a time: host thread t takes the next job and runs it
+// on executor t (its own streams and workspace) and that executor's stream.
+VC_API int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms, const uint32_t *bs,
+                             uint32_t nexec, vc_exec *const *exs, vc_proofs **outs) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pps || !cms || !bs || !exs || !outs || nexec < 1) return VC_EINVAL;
+  for (uint32_t i = 0; i < n; i++) outs[i] = nullptr;
+  for (uint32_t t = 0; t < nexec; t++)
+    if (!exs[t]) return VC_EINVAL;
+  for (uint32_t i = 0; i < n; i++)
+    if (!pps[i] || !cms[i] || cms[i]->pp != pps[i] || pps[i]->device != exs[0]->device) return VC_EINVAL;
+  if (n == 0) return VC_OK;
+  if (g_prof) nexec = 1;  // the profiling hooks keep one record list
+  if (nexec > n) nexec = n;
+  // largest jobs first, so that the last ones to start are short
+  std::vector<uint32_t> order(n);
+  for (uint32_t i = 0; i < n; i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return pps[a]->N > pps[b]->N; });
+  std::atomic<uint32_t> next{0};
+  std::vector<int> rcs(n, VC_OK);
+  std::vector<std::string> msgs(n);  // error text of each job (kept per thread by hip_fail)
+  auto worker = [&](vc_exec *ex) {
+    hipError_t e = hipSetDevice(ex->device);
+    for (;;) {
+      uint32_t o = next.fetch_add(1);
+      if (o >= n) break;
+      uint32_t i = order[o];
+      if (e != hipSuccess) {
+        rcs[i] = hip_fail(e, "vc_open_all_batch worker");
+      } else {
+        g_last_error[0] = 0;
+        rcs[i] = open_all_impl(pps[i], cms[i], bs[i], ex, ex->main, &outs[i]);
+      }
+      if (rcs[i] != VC_OK) msgs[i] = g_last_error;
+    }
+  };
+  std::vector<std::thread> th;
+  for (uint32_t t = 1; t < nexec; t++) th.emplace_back(worker, exs[t]);
+  worker(exs[0]);
+  for (auto &x : th) x.join();
+  int rc = VC_OK;
+  for (uint32_t i = 0; i < n && rc == VC_OK; i++)
+    if (rcs[i] != VC_OK) {
+      rc = rcs[i];
+      snprintf(g_last_error, sizeof g_last_error, "%s", msgs[i].c_str());
+    }
+  if (rc != VC_OK)
+    for (uint32_t i = 0; i < n; i++) {
+      vc_proofs_free(outs[i]);
+      outs[i] = nullptr;
+    }
+  return rc;
 }
 
 VC_API void vc_proofs_free(vc_proofs *pr) {
@@ -910,7 +1050,8 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
   const uint32_t t = (uint32_t)(hi - lo);
   if (len != vc_proof_len(pp->L, t)) return VC_EINVAL;
   CK(hipSetDevice(pp->device));
-  hipStream_t st = pp->side[0];
+  vc_exec *ex = pp->ex;
+  hipStream_t st = ex->side[0];
   const uint32_t nmul = t + 2 * lK + 4, npair = 4 + lM;
   Carve c;
   size_t o_pf = c.take<uint8_t>(len), o_C = c.take<uint8_t>(384), o_m = c.take<uint8_t>(32);
@@ -923,7 +1064,7 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
   size_t o_Cg1 = c.take<g1_aff>(1), o_bA = c.take<g1_aff>(1), o_pp = c.take<g1_aff>(npair), o_pq = c.take<g2_aff>(npair);
   size_t o_F = c.take<fp12>(npair), o_E = c.take<fp12>(3), o_fl = c.take<int>(1);
   // the three product trees below run one after another and share one counter area
-  if (int rc = ensure_cnt(const_cast<vc_params *>(pp), tree_counters(npair > 2 * lK + 1 ? npair : 2 * lK + 1))) return rc;
+  if (int rc = ensure_cnt(ex, tree_counters(npair > 2 * lK + 1 ? npair : 2 * lK + 1), st)) return rc;
   void *d = nullptr;
   CK(hipMalloc(&d, c.off));
   VCtx x;
@@ -951,10 +1092,10 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
     klw::g2_mul(pp->g2gen, 1, x.fz, 1, x.fzg2, st);
     ks::gt_pow(x.gtb, x.gts, 2 * lK, x.gto, st);
     kv::assemble(x, st);
-    ks::f12_reduce(x.gto, 1, 2 * lK + 1, 2 * lK + 1, pp->cnt, st);
+    ks::f12_reduce(x.gto, 1, 2 * lK + 1, 2 * lK + 1, ex->cnt, st);
     ks::miller(x.pp, 1, x.pq, 1, npair, x.F, st);
-    ks::f12_reduce(x.F + 1, 1, 2, 2, pp->cnt, st);
-    ks::f12_reduce(x.F + 3, 1, npair - 3, npair - 3, pp->cnt, st);
+    ks::f12_reduce(x.F + 1, 1, 2, 2, ex->cnt, st);
+    ks::f12_reduce(x.F + 3, 1, npair - 3, npair - 3, ex->cnt, st);
     ks::final_exp(x.F, 1, 1, x.E, nullptr, 1, st);
     ks::final_exp(x.F + 1, 1, 1, x.E + 1, nullptr, 1, st);
     ks::final_exp(x.F + 3, 1, 1, x.E + 2, nullptr, 1, st);
@@ -964,7 +1105,10 @@ VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint
   if (e == hipSuccess) e = hipMemcpyAsync(&flags, x.flags, sizeof(int), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   hipFree(d);
-  if (e != hipSuccess) return hip_fail(e, "vc_verify");
+  if (e != hipSuccess) {
+    ex->cnt_dirty = true;  // the product trees may have stopped half way
+    return hip_fail(e, "vc_verify");
+  }
   if (flags & VFLAG_BAD_INPUT) return VC_EINVAL;
   if (flags & VFLAG_BAD_PROOF) return 0;
   return (flags & VFLAG_ACCEPT) ? 1 : 0;
