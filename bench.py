@@ -264,6 +264,75 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2):
     return res
 
 
+SERVE_SETUPS = ((1, 6), (8, 2))           # (executors, streams): the one-job path, then the pool
+
+
+def serving(V, torch, n_req=40, rate=8.0, seed=7, setups=SERVE_SETUPS, budget=64 << 30):
+    """Serving loop: a seeded Poisson stream of n_req open-all requests (rate per second),
+    N = 2^L with L uniform in [10, 20], b uniform in {1, L, L^2} within [1, K], 32-bit or
+    full-width entries half and half, each vector committed beforehand.  The same stream is
+    served by one executor of six streams (one request at a time, as vc_open_all) and by the
+    pool; latency is submission to completion.  Proof 0 of every request must agree."""
+    import numpy as np
+    from paper_2601_03031_amd import inputs as I
+    rng = np.random.default_rng(seed)
+    reqs, t = [], 0.0
+    for _ in range(n_req):
+        t += float(rng.exponential(1.0 / rate))
+        L = int(rng.integers(10, 21))
+        K = 1 << (L // 2)
+        b = int(rng.choice([x for x in (1, L, L * L) if x <= K]))
+        bits = 32 if rng.random() < 0.5 else 256
+        reqs.append((L, b, bits, t))
+    log("serving: %d requests over %.1f s: setup and commit" % (n_req, t))
+    params, cms = {}, []
+    for i, (L, b, bits, _) in enumerate(reqs):
+        if L not in params:
+            params[L] = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
+        limbs = I.entries(1 << L, 7000 + i, bits)
+        if bits == 32:
+            m = torch.from_numpy(limbs[:, 0].astype(np.uint32).view(np.int32).copy()).cuda()
+        else:
+            m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+        cms.append(V.vc_commit(params[L], m, bits))
+    torch.cuda.synchronize()
+    proofs = sum(1 << L for L, _, _, _ in reqs)
+    res = {"requests": n_req, "rate_per_s": rate, "span_s": round(t, 2), "proofs": proofs, "budget_bytes": budget,
+           "b_counts": {k: sum(1 for L, b, _, _ in reqs if ("1" if b == 1 else "L" if b == L else "L^2") == k)
+                        for k in ("1", "L", "L^2")},
+           "setups": {}}
+    first = None
+    for ne, ns in setups:
+        sv = V.vc_server_create(0, ne, ns, budget)
+        t0 = time.perf_counter()
+        tickets = []
+        for (L, b, bits, arr), cm in zip(reqs, cms):
+            dt = t0 + arr - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(sv.submit(params[L], cm, b))
+        lat, p0 = [], []
+        for tk in tickets:
+            pr, (_, total) = sv.wait(tk)
+            lat.append(total)
+            p0.append(V.vc_proof_get(pr, 0))
+            del pr
+        wall = time.perf_counter() - t0
+        del sv
+        if first is None:
+            first = p0
+        elif p0 != first:
+            raise RuntimeError("served proofs differ between executor setups")
+        key = "%dx%d" % (ne, ns)
+        res["setups"][key] = {"p50_ms": round(float(np.percentile(lat, 50)), 1),
+                              "p99_ms": round(float(np.percentile(lat, 99)), 1),
+                              "mean_ms": round(float(np.mean(lat)), 1), "wall_s": round(wall, 2),
+                              "proofs_per_s": round(proofs / wall)}
+        log("serving %s: p50 %.0f ms, p99 %.0f ms, wall %.1f s" % (key, res["setups"][key]["p50_ms"],
+                                                                   res["setups"][key]["p99_ms"], wall))
+    return res
+
+
 def cpu_baseline(L, b, bits, seed):
     import oracle as O
     log("cpu baseline (oracle) L=%d b=%d" % (L, b))
@@ -292,6 +361,10 @@ def main():
     ap.add_argument("--batch-only", type=str, default="", metavar="SETUPS",
                     help="only run the batched-jobs comparison with these executors x streams setups "
                          "(e.g. 4x6,16x1) and print its JSON")
+    ap.add_argument("--serve-only", action="store_true", help="only run the serving-loop comparison")
+    ap.add_argument("--serve-rate", type=float, default=0, help="request rate per second of the serving stream")
+    ap.add_argument("--serve-setups", type=str, default="", metavar="SETUPS",
+                    help="executors x streams of the served runs (e.g. 1x6,4x6)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -316,6 +389,14 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.serve_only:
+        kw = {}
+        if a.serve_rate:
+            kw["rate"] = a.serve_rate
+        if a.serve_setups:
+            kw["setups"] = [tuple(int(v) for v in x.split("x")) for x in a.serve_setups.split(",")]
+        print(json.dumps(serving(V, torch, **kw)), flush=True)
+        return
     if a.batch_only:
         setups = [tuple(int(v) for v in x.split("x")) for x in a.batch_only.split(",")]
         print(json.dumps(batched_jobs(V, torch, setups=setups)), flush=True)
@@ -365,6 +446,7 @@ def main():
             sweep["n2^%d_b%d" % (Ls, bs)] = round(os_[0], 3)
         extra["b_sweep_all_proofs_ms"] = sweep
         extra["batched_64_jobs"] = batched_jobs(V, torch)
+        extra["serving"] = serving(V, torch)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(L, b, bits, seed)

@@ -99,6 +99,31 @@ int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t b, vc_
 int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms, const uint32_t *bs,
                       uint32_t nexec, vc_exec *const *exs, vc_proofs **outs);
 
+/* Device bytes one vc_open_all of (pp, b) holds while it runs: proof bundle, workspace and
+ * reduction counters (the bundle stays with the returned proofs).  Host-only: nothing is
+ * allocated or launched.  VC_EINVAL for b outside [1, K]. */
+int vc_open_all_footprint(const vc_params *pp, uint32_t b, uint64_t *bytes);
+
+/* Serving loop (OpenAll requests of Protocol 1, §4.2, arriving over time): nexec executors of
+ * nstreams streams each, one host thread each.  Requests start in arrival order, each when an
+ * executor is free and the footprints of the running requests plus its own fit in hbm_budget
+ * bytes (the oldest waiting request is never overtaken).  Idle executors keep the workspace
+ * of their largest request so far; proofs returned by vc_server_wait belong to the caller.
+ * VC_EINVAL for nexec outside [1, 64], nstreams outside [1, 6] or a zero budget. */
+typedef struct vc_server vc_server;
+int vc_server_create(int device, uint32_t nexec, uint32_t nstreams, uint64_t hbm_budget, vc_server **out);
+/* Queue a request (params and commitment must stay alive until it is waited for); returns its
+ * ticket.  VC_ENOMEM if its footprint alone exceeds the budget, VC_EINVAL for bad arguments. */
+int vc_server_submit(vc_server *sv, const vc_params *pp, const vc_commitment *cm, uint32_t b, uint64_t *ticket);
+/* Block until request `ticket` has finished; then its proofs (as from vc_open_all) in *out and
+ * its return code.  times_ms (optional): [0] time waiting before it started, [1] time from
+ * submission to completion (the request's latency).  Each ticket is waited for once, by one
+ * thread; VC_EINVAL for an unknown ticket. */
+int vc_server_wait(vc_server *sv, uint64_t ticket, vc_proofs **out, double times_ms[2]);
+/* Finish the running requests, drop the waiting ones and release everything (proofs not
+ * collected included).  Not concurrent with other calls on sv. */
+void vc_server_free(vc_server *sv);
+
 /* Serialized length of a proof whose block holds t subvector commitments. */
 uint64_t vc_proof_len(uint32_t log_n, uint32_t t);
 

@@ -60,6 +60,11 @@ def lib():
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
         L.vc_open_all_ex.argtypes = [vp, vp, u32, vp, vp, C.POINTER(vp)]
+        L.vc_open_all_footprint.argtypes = [vp, u32, C.POINTER(u64)]
+        L.vc_server_create.argtypes = [C.c_int, u32, u32, u64, C.POINTER(vp)]
+        L.vc_server_submit.argtypes = [vp, vp, vp, u32, C.POINTER(u64)]
+        L.vc_server_wait.argtypes = [vp, u64, C.POINTER(vp), C.POINTER(C.c_double)]
+        L.vc_server_free.argtypes = [vp]
         L.vc_open_all_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), u32, C.POINTER(vp),
                                         C.POINTER(vp)]
         L.vc_proof_len.restype = u64
@@ -207,6 +212,43 @@ def vc_open_all_batch(jobs, execs) -> list:
     outs = (VP * max(n, 1))()
     _check(lib().vc_open_all_batch(n, pps, cms, bs, len(execs), exs, outs), "vc_open_all_batch")
     return [Proofs(outs[i], jobs[i][0], jobs[i][2]) for i in range(n)]
+
+
+def vc_open_all_footprint(pp: Params, b: int) -> int:
+    n = C.c_uint64(0)
+    _check(lib().vc_open_all_footprint(pp.ptr, b, C.byref(n)), "vc_open_all_footprint")
+    return n.value
+
+
+class Server(_Handle):
+    """Serving loop: open-all requests queued in arrival order, run on a pool of executors
+    under a device-memory budget."""
+    _free = "vc_server_free"
+
+    def __init__(self, ptr, device):
+        super().__init__(ptr)
+        self.device = device
+        self._jobs = {}  # ticket -> (params, commitment, b), kept alive until collected
+
+    def submit(self, pp: Params, cm: Commitment, b: int) -> int:
+        t = C.c_uint64(0)
+        _check(lib().vc_server_submit(self.ptr, pp.ptr, cm.ptr, b, C.byref(t)), "vc_server_submit")
+        self._jobs[t.value] = (pp, cm, b)
+        return t.value
+
+    def wait(self, ticket: int):
+        """(Proofs, [ms waiting before start, ms from submission to completion])"""
+        out = C.c_void_p()
+        times = (C.c_double * 2)()
+        pp, cm, b = self._jobs.pop(ticket)
+        _check(lib().vc_server_wait(self.ptr, ticket, C.byref(out), times), "vc_server_wait")
+        return Proofs(out, pp, b), [times[0], times[1]]
+
+
+def vc_server_create(device: int = 0, nexec: int = 16, nstreams: int = 1, hbm_budget: int = 64 << 30) -> Server:
+    out = C.c_void_p()
+    _check(lib().vc_server_create(device, nexec, nstreams, hbm_budget, C.byref(out)), "vc_server_create")
+    return Server(out, device)
 
 
 def vc_proof_len(log_n: int, t: int) -> int:

@@ -13,6 +13,11 @@
 #include <thread>
 #include <atomic>
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <unordered_map>
 #include "kernels.h"
 #include "verify.h"
 #include "vc.h"
@@ -433,12 +438,15 @@ VC_API void vc_commitment_free(vc_commitment *cm) {
 }
 
 // ------------------------------------------------------------------ open-all
+// With `footprint` set: only the device bytes the call would hold (proof bundle, workspace,
+// counters) are stored there; nothing is allocated or launched, and cm, ex, out may be NULL.
 static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t b, vc_exec *ex, hipStream_t st,
-                         vc_proofs **out) {
-  if (!cpp || !cm || !out || !ex || cm->pp != cpp || b < 1 || b > cpp->K || ex->device != cpp->device) return VC_EINVAL;
+                         vc_proofs **out, uint64_t *footprint = nullptr) {
+  if (!cpp || b < 1 || b > cpp->K) return VC_EINVAL;
+  if (!footprint && (!cm || !out || !ex || cm->pp != cpp || ex->device != cpp->device)) return VC_EINVAL;
   const vc_params *pp = cpp;
-  *out = nullptr;
-  CK(hipSetDevice(pp->device));
+  if (out) *out = nullptr;
+  if (!footprint) CK(hipSetDevice(pp->device));
   const uint64_t N = pp->N, K = pp->K, M = pp->M;
   const uint32_t lK = pp->lK, lM = pp->lM;
   const uint64_t nb = (K + b - 1) / b;
@@ -465,31 +473,6 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   pr->o_Y = c.take<fe>((2 * K - 1) * M);
   pr->o_D = c.take<g1_aff>(2 * K - 1);
   pr->o_W = c.take<g1_aff>(M - 1);
-  hipError_t e = hipMalloc(&pr->mem, c.off);
-  if (e != hipSuccess) { delete pr; return hip_fail(e, "vc_open_all alloc"); }
-  // on every error return below the bundle is released (hipFree waits for the work in flight)
-  // and the executor's counters are cleared before their next use (trees may have stopped
-  // half way)
-  struct Release {
-    vc_proofs *p;
-    vc_exec *ex;
-    ~Release() {
-      if (!p) return;
-      vc_proofs_free(p);
-      ex->cnt_dirty = true;
-    }
-  } release{pr, ex};
-  void *bm = pr->mem;
-  g1_aff *Cj = at<g1_aff>(bm, pr->o_Cj);
-  fp12 *C = at<fp12>(bm, pr->o_C);
-  fp12 *Lgt = at<fp12>(bm, pr->o_Lgt), *Rgt = at<fp12>(bm, pr->o_Rgt);
-  g1_aff *Lg1 = at<g1_aff>(bm, pr->o_Lg1), *Rg1 = at<g1_aff>(bm, pr->o_Rg1);
-  fe *X = at<fe>(bm, pr->o_X);
-  g1_aff *Al = at<g1_aff>(bm, pr->o_Al);
-  g2_aff *vl = at<g2_aff>(bm, pr->o_vl), *piv = at<g2_aff>(bm, pr->o_piv);
-  uint32_t *tree = at<uint32_t>(bm, pr->o_tree);
-  fe *rho = at<fe>(bm, pr->o_rho), *Y = at<fe>(bm, pr->o_Y);
-  g1_aff *D = at<g1_aff>(bm, pr->o_D), *W = at<g1_aff>(bm, pr->o_W);
   // ---- scratch
   Carve t;
   size_t o_err = t.take<int>(1), o_A = t.take<g1_aff>(nb * K), o_V = t.take<g2_aff>(nb * K), o_B = t.take<fe>(nb * K);
@@ -519,6 +502,40 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   // (multiples of whole arrays, one set per round parity; the G1 terms split likewise use them)
   size_t o_FM1 = t.take<g1_aff>(2 * 6 * nsplit), o_FM2 = t.take<g2_aff>(2 * 6 * nsplit);
   size_t o_FJ1 = t.take<g1_jac>(4 * nsplit), o_FJ2 = t.take<g2_jac>(4 * nsplit), o_GJ = t.take<g1_jac>(16 * nsplit);
+  const uint64_t c_dir = 2 * nb * tree_counters(K / 2), c_u = 2 * nb * tree_counters(K / 2),
+                 c_xy = 4 * nb * tree_counters(K / 4);
+  const uint64_t c_kzg = nb * tree_counters(kzg_len);
+  const uint64_t n_cnt = 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg;
+  if (footprint) {
+    *footprint = c.off + t.off + n_cnt * sizeof(uint32_t);
+    delete pr;
+    return VC_OK;
+  }
+  hipError_t e = hipMalloc(&pr->mem, c.off);
+  if (e != hipSuccess) { delete pr; return hip_fail(e, "vc_open_all alloc"); }
+  // on every error return below the bundle is released (hipFree waits for the work in flight)
+  // and the executor's counters are cleared before their next use (trees may have stopped
+  // half way)
+  struct Release {
+    vc_proofs *p;
+    vc_exec *ex;
+    ~Release() {
+      if (!p) return;
+      vc_proofs_free(p);
+      ex->cnt_dirty = true;
+    }
+  } release{pr, ex};
+  void *bm = pr->mem;
+  g1_aff *Cj = at<g1_aff>(bm, pr->o_Cj);
+  fp12 *C = at<fp12>(bm, pr->o_C);
+  fp12 *Lgt = at<fp12>(bm, pr->o_Lgt), *Rgt = at<fp12>(bm, pr->o_Rgt);
+  g1_aff *Lg1 = at<g1_aff>(bm, pr->o_Lg1), *Rg1 = at<g1_aff>(bm, pr->o_Rg1);
+  fe *X = at<fe>(bm, pr->o_X);
+  g1_aff *Al = at<g1_aff>(bm, pr->o_Al);
+  g2_aff *vl = at<g2_aff>(bm, pr->o_vl), *piv = at<g2_aff>(bm, pr->o_piv);
+  uint32_t *tree = at<uint32_t>(bm, pr->o_tree);
+  fe *rho = at<fe>(bm, pr->o_rho), *Y = at<fe>(bm, pr->o_Y);
+  g1_aff *D = at<g1_aff>(bm, pr->o_D), *W = at<g1_aff>(bm, pr->o_W);
   int rc = ensure_ws(ex, t.off);
   if (rc) return rc;
   void *ws = ex->ws;
@@ -553,10 +570,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   g2_jac *FJ2 = at<g2_jac>(ws, o_FJ2);
   // reduction-tree counters: round-1 (or every direct round) products, and per stream the
   // U and XY groups of the terms taken ahead (F_p12 on side stream 3, G1 on the caller's)
-  const uint64_t c_dir = 2 * nb * tree_counters(K / 2), c_u = 2 * nb * tree_counters(K / 2),
-                 c_xy = 4 * nb * tree_counters(K / 4);
-  const uint64_t c_kzg = nb * tree_counters(kzg_len);
-  if (int rc2 = ensure_cnt(ex, 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg, st)) return rc2;
+  if (int rc2 = ensure_cnt(ex, n_cnt, st)) return rc2;
   // (the counters of the terms' trees per round parity, whose streams run concurrently)
   uint32_t *cnt_dir = ex->cnt, *cnt_t = cnt_dir + c_dir;
   uint32_t *cnt_fu[2] = {cnt_t, cnt_t + 2 * (c_u + c_xy)}, *cnt_fxy[2] = {cnt_fu[0] + c_u, cnt_fu[1] + c_u};
@@ -828,6 +842,153 @@ VC_API int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_c
       vc_proofs_free(outs[i]);
       outs[i] = nullptr;
     }
+  return rc;
+}
+
+VC_API int vc_open_all_footprint(const vc_params *pp, uint32_t b, uint64_t *bytes) {
+  if (!bytes) return VC_EINVAL;
+  *bytes = 0;
+  return open_all_impl(pp, nullptr, b, nullptr, nullptr, nullptr, bytes);
+}
+
+// ------------------------------------------------------------------ serving loop
+// Requests wait in arrival order; a worker thread per executor takes the oldest one once it is
+// free and the footprints of the running requests plus the oldest one's fit the budget (the
+// oldest waits, and the ones behind it with it, until they do: no request is overtaken).
+struct vc_server {
+  using clock = std::chrono::steady_clock;
+  struct Req {
+    const vc_params *pp;
+    const vc_commitment *cm;
+    uint32_t b;
+    uint64_t foot;
+    int state = 0;  // 0 waiting, 1 running, 2 done
+    int rc = VC_OK;
+    vc_proofs *out = nullptr;
+    std::string err;
+    clock::time_point t_sub, t_start, t_done;
+  };
+  int device = 0;
+  uint64_t budget = 0;
+  std::vector<vc_exec *> exs;
+  std::vector<std::thread> th;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::unordered_map<uint64_t, Req> reqs;  // element addresses stay valid while others come and go
+  std::deque<uint64_t> queue;
+  uint64_t next_ticket = 1, in_use = 0;
+  bool stop = false;
+
+  void worker(vc_exec *ex) {
+    (void)hipSetDevice(ex->device);
+    for (;;) {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || (!queue.empty() && in_use + reqs[queue.front()].foot <= budget); });
+      if (stop) return;
+      uint64_t id = queue.front();
+      queue.pop_front();
+      Req *r = &reqs[id];
+      r->state = 1;
+      r->t_start = clock::now();
+      in_use += r->foot;
+      lk.unlock();
+      cv_work.notify_all();  // the next one may fit as well
+      vc_proofs *out = nullptr;
+      g_last_error[0] = 0;
+      int rc = open_all_impl(r->pp, r->cm, r->b, ex, ex->main, &out);
+      std::string err = rc != VC_OK ? std::string(g_last_error) : std::string();
+      lk.lock();
+      r->rc = rc;
+      r->out = out;
+      r->err = err;
+      r->t_done = clock::now();
+      r->state = 2;
+      in_use -= r->foot;
+      lk.unlock();
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
+  }
+};
+
+VC_API void vc_server_free(vc_server *sv) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  sv->cv_done.notify_all();
+  for (auto &t : sv->th) t.join();
+  for (auto &kv : sv->reqs) vc_proofs_free(kv.second.out);  // finished, never collected
+  for (auto ex : sv->exs) vc_exec_free(ex);
+  delete sv;
+}
+
+VC_API int vc_server_create(int device, uint32_t nexec, uint32_t nstreams, uint64_t hbm_budget, vc_server **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!out) return VC_EINVAL;
+  *out = nullptr;
+  if (nexec < 1 || nexec > 64 || nstreams < 1 || nstreams > 6 || hbm_budget == 0) return VC_EINVAL;
+  vc_server *sv = new vc_server();
+  sv->device = device;
+  sv->budget = hbm_budget;
+  for (uint32_t i = 0; i < nexec; i++) {
+    vc_exec *ex = nullptr;
+    if (int rc = vc_exec_create(device, nstreams, &ex)) {
+      vc_server_free(sv);
+      return rc;
+    }
+    sv->exs.push_back(ex);
+  }
+  for (auto ex : sv->exs) sv->th.emplace_back(&vc_server::worker, sv, ex);
+  *out = sv;
+  return VC_OK;
+}
+
+VC_API int vc_server_submit(vc_server *sv, const vc_params *pp, const vc_commitment *cm, uint32_t b, uint64_t *ticket) {
+  if (!sv || !pp || !cm || !ticket || cm->pp != pp || pp->device != sv->device) return VC_EINVAL;
+  *ticket = 0;
+  uint64_t foot = 0;
+  if (int rc = vc_open_all_footprint(pp, b, &foot)) return rc;
+  if (foot > sv->budget) {
+    snprintf(g_last_error, sizeof g_last_error, "request needs %llu bytes, budget %llu", (unsigned long long)foot,
+             (unsigned long long)sv->budget);
+    return VC_ENOMEM;
+  }
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    uint64_t id = sv->next_ticket++;
+    vc_server::Req &r = sv->reqs[id];
+    r.pp = pp;
+    r.cm = cm;
+    r.b = b;
+    r.foot = foot;
+    r.t_sub = vc_server::clock::now();
+    sv->queue.push_back(id);
+    *ticket = id;
+  }
+  sv->cv_work.notify_all();
+  return VC_OK;
+}
+
+VC_API int vc_server_wait(vc_server *sv, uint64_t ticket, vc_proofs **out, double times_ms[2]) {
+  if (!sv || !out) return VC_EINVAL;
+  *out = nullptr;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return VC_EINVAL;
+  vc_server::Req *r = &it->second;
+  sv->cv_done.wait(lk, [&] { return r->state == 2; });
+  if (times_ms) {
+    times_ms[0] = std::chrono::duration<double, std::milli>(r->t_start - r->t_sub).count();
+    times_ms[1] = std::chrono::duration<double, std::milli>(r->t_done - r->t_sub).count();
+  }
+  int rc = r->rc;
+  *out = r->out;
+  if (rc != VC_OK) snprintf(g_last_error, sizeof g_last_error, "%s", r->err.c_str());
+  sv->reqs.erase(ticket);
   return rc;
 }
 
