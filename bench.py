@@ -333,6 +333,44 @@ def serving(V, torch, n_req=40, rate=8.0, seed=7, setups=SERVE_SETUPS, budget=64
     return res
 
 
+def verify_all_timing(V, torch, L=16, b=256, seed=2, reps=3):
+    """Verification of all N proofs of the N = 2^16, b = 256 workload: device serialization of
+    the N proofs, then vc_verify_all (best of reps each), and the one-proof verifier on a few
+    proofs for comparison."""
+    import numpy as np
+    from paper_2601_03031_amd import inputs as I
+    limbs = I.entries(1 << L, seed, 32)
+    pp = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
+    cm = V.vc_commit(pp, torch.from_numpy(limbs[:, 0].astype(np.uint32).view(np.int32).copy()).cuda(), 32)
+    pr = V.vc_open_all(pp, cm, b)
+    m = torch.frombuffer(bytearray(I.limbs_to_bytes(limbs)), dtype=torch.uint8).cuda()
+    ser_ms, ver_ms, ser = [], [], None
+    for r in range(reps):
+        del ser
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ser = V.vc_proofs_serialize(pr)
+        t1 = time.perf_counter()
+        v, ns = V.vc_verify_all(pp, cm.C, b, m, ser, bytes([r]) * 32)
+        t2 = time.perf_counter()
+        if v != 1:
+            raise RuntimeError("verify_all rejected the honest proofs")
+        ser_ms.append(1e3 * (t1 - t0))
+        ver_ms.append(1e3 * (t2 - t1))
+    ints = I.limbs_to_ints(limbs)
+    one = []
+    for i in (0, 12345, 65535):
+        proof = V.vc_proof_get(pr, i)
+        t0 = time.perf_counter()
+        if V.vc_verify(pp, cm.C, b, i, ints[i], proof) != 1:
+            raise RuntimeError("vc_verify rejected an honest proof")
+        one.append(1e3 * (time.perf_counter() - t0))
+    n = 1 << L
+    return {"N": n, "b": b, "serialized_bytes": int(ser.numel()), "serialize_ms": round(min(ser_ms), 3),
+            "verify_all_ms": round(min(ver_ms), 3), "proofs_verified_per_s": round(n / (min(ver_ms) / 1e3)),
+            "checked_alone": ns, "one_proof_verify_ms": round(statistics.median(one), 3)}
+
+
 def cpu_baseline(L, b, bits, seed):
     import oracle as O
     log("cpu baseline (oracle) L=%d b=%d" % (L, b))
@@ -447,6 +485,7 @@ def main():
         extra["b_sweep_all_proofs_ms"] = sweep
         extra["batched_64_jobs"] = batched_jobs(V, torch)
         extra["serving"] = serving(V, torch)
+        extra["verify_all_n2^16_b256"] = verify_all_timing(V, torch)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(L, b, bits, seed)

@@ -124,6 +124,28 @@ int vc_server_wait(vc_server *sv, uint64_t ticket, vc_proofs **out, double times
  * collected included).  Not concurrent with other calls on sv. */
 void vc_server_free(vc_server *sv);
 
+/* All N proofs of a bundle serialized on the device, in index order, each exactly as
+ * vc_proof_get writes it: proofs of batch k (entries i with i / (b M) = k) are
+ * vc_proof_len(log N, t_k) bytes long, t_k = min(b, K - k b), and proof i starts where proof
+ * i - 1 ends.  dst: device memory of cap bytes, or NULL to get the total length only; *len:
+ * the total.  VC_EINVAL if cap is too small. */
+int vc_proofs_serialize(const vc_proofs *pr, void *dst, uint64_t cap, uint64_t *len);
+
+/* Verification of all N proofs at once (VC.Verify, appendix C, for every i; section 3
+ * FC.BVerify and section 4.2 Step 2).  proofs: the N serialized proofs on the device as
+ * vc_proofs_serialize lays them out (16-byte aligned, len bytes in all); m: the N entries on
+ * the device, 32 little-endian bytes each; C: the 384-byte commitment (host); seed: 32 bytes
+ * (host) from which the random weights of the combined check derive, to be chosen at random
+ * after the proofs are fixed.  Items that honest proofs share are compared byte for byte
+ * with the proof that represents them; the PST checks of all proofs are combined with random
+ * 128-bit weights into one product of log M + 1 pairings (a false accept has probability
+ * about 2^-128); the FC part is checked once per batch, and every proof that differs from a
+ * representative is checked alone with vc_verify.  Returns 1 if every proof is accepted, 0 if
+ * one is rejected, VC_EINVAL for malformed inputs (lengths, alignment, C, entries >= r).
+ * n_single (optional): the number of proofs checked alone. */
+int vc_verify_all(const vc_params *pp, const uint8_t C[384], uint32_t b, const void *m, const void *proofs,
+                  uint64_t len, const uint8_t seed[32], uint64_t *n_single);
+
 /* Serialized length of a proof whose block holds t subvector commitments. */
 uint64_t vc_proof_len(uint32_t log_n, uint32_t t);
 

@@ -65,6 +65,8 @@ def lib():
         L.vc_server_submit.argtypes = [vp, vp, vp, u32, C.POINTER(u64)]
         L.vc_server_wait.argtypes = [vp, u64, C.POINTER(vp), C.POINTER(C.c_double)]
         L.vc_server_free.argtypes = [vp]
+        L.vc_proofs_serialize.argtypes = [vp, vp, u64, C.POINTER(u64)]
+        L.vc_verify_all.argtypes = [vp, u8p, u32, vp, vp, u64, u8p, C.POINTER(u64)]
         L.vc_open_all_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), u32, C.POINTER(vp),
                                         C.POINTER(vp)]
         L.vc_proof_len.restype = u64
@@ -112,9 +114,9 @@ class _Handle:
 class Params(_Handle):
     _free = "vc_params_free"
 
-    def __init__(self, ptr, log_n):
+    def __init__(self, ptr, log_n, device=0):
         super().__init__(ptr)
-        self.log_n = log_n
+        self.log_n, self.device = log_n, device
         self.lK = log_n // 2
         self.lM = log_n - self.lK
         self.N, self.K, self.M = 1 << log_n, 1 << self.lK, 1 << self.lM
@@ -164,7 +166,7 @@ class Proofs(_Handle):
 def vc_setup(log_n: int, seed: bytes, device: int = 0) -> Params:
     out = C.c_void_p()
     _check(lib().vc_setup(log_n, seed, device, C.byref(out)), "vc_setup")
-    return Params(out, log_n)
+    return Params(out, log_n, device)
 
 
 def vc_commit(pp: Params, m, entry_bits: int = 256, stream=None) -> Commitment:
@@ -249,6 +251,38 @@ def vc_server_create(device: int = 0, nexec: int = 16, nstreams: int = 1, hbm_bu
     out = C.c_void_p()
     _check(lib().vc_server_create(device, nexec, nstreams, hbm_budget, C.byref(out)), "vc_server_create")
     return Server(out, device)
+
+
+def vc_proofs_serialize(pr: Proofs):
+    """All N serialized proofs in index order, as one uint8 device tensor."""
+    import torch
+    n = C.c_uint64(0)
+    _check(lib().vc_proofs_serialize(pr.ptr, None, 0, C.byref(n)), "vc_proofs_serialize")
+    out = torch.empty(n.value, dtype=torch.uint8, device="cuda:%d" % pr.pp.device)
+    _check(lib().vc_proofs_serialize(pr.ptr, C.c_void_p(out.data_ptr()), n.value, C.byref(n)), "vc_proofs_serialize")
+    return out
+
+
+def proof_offsets(pp: Params, b: int) -> list:
+    """Byte offset of every proof in the serialized layout (N + 1 entries)."""
+    K, M = pp.K, pp.M
+    nb = (K + b - 1) // b
+    offs, o = [0], 0
+    for k in range(nb):
+        ln = vc_proof_len(pp.log_n, min(b, K - k * b))
+        for _ in range(min(b, K - k * b) * M):
+            o += ln
+            offs.append(o)
+    return offs
+
+
+def vc_verify_all(pp: Params, C_bytes: bytes, b: int, m, proofs, seed: bytes):
+    """m: device tensor of N x 32 little-endian bytes; proofs: device tensor from
+    vc_proofs_serialize (or the same layout).  Returns (1 all accepted / 0, proofs checked alone)."""
+    ns = C.c_uint64(0)
+    v = _check(lib().vc_verify_all(pp.ptr, C_bytes, b, C.c_void_p(m.data_ptr()), C.c_void_p(proofs.data_ptr()),
+                                   proofs.numel(), seed, C.byref(ns)), "vc_verify_all")
+    return v, ns.value
 
 
 def vc_proof_len(log_n: int, t: int) -> int:

@@ -330,3 +330,402 @@ void transcript(const VCtx &c, hipStream_t st) { LAUNCH(kv_transcript, dim3(1), 
 void assemble(const VCtx &c, hipStream_t st) { LAUNCH(kv_assemble, dim3(1), dim3(64), 0, c); }
 void compare(const VCtx &c, hipStream_t st) { LAUNCH(kv_compare, dim3(1), dim3(64), 0, c); }
 }  // namespace kv
+
+// ------------------------------------------------------------------ every proof at once
+// Serialization of all N proofs (the wire format of vc_proof_get) and their verification in
+// one pass: items that honest proofs share (the block and FC proof of a batch, the D-tree
+// siblings, the W commitments) are compared byte for byte with the proof that represents
+// them and decoded once; the PST checks (section 4.2 Step 2, appendix C) of all proofs are
+// combined with random 128-bit weights delta_i into one product of l_M + 1 pairings:
+//   e(sum_i delta_i (D*_i - y*_i g1 + sum_d a_{i,var d} W_{i,d}), -g2) prod_d e(sum_i delta_i W_{i,d}, vk_{var d}) = 1
+// with var d = l_M - 1 - d.  The FC part (FC.BVerify with the faster verifier) is the same
+// for every proof of a batch and is checked once per batch by the one-proof verifier.
+namespace {
+
+__device__ uint64_t pl_bm(const PLayout &y) { return (uint64_t)y.b * y.M; }
+__device__ uint64_t pl_batch(const PLayout &y, uint64_t i) { return i / pl_bm(y); }
+__device__ uint32_t pl_t(const PLayout &y, uint64_t k) { return k == y.nb - 1 ? y.t_last : y.b; }
+// byte offset of proof i
+__device__ uint64_t pl_off(const PLayout &y, uint64_t i) {
+  uint64_t k = pl_batch(y, i), bm = pl_bm(y);
+  return k * bm * y.len_full + (i - k * bm) * (k == y.nb - 1 ? y.len_last : y.len_full);
+}
+// start of the Step 2 part (after block, rounds and tail) in a proof of batch k
+__device__ uint64_t pl_step2(const PLayout &y, uint64_t k) { return 32ull * pl_t(y, k) + 832ull * y.lK + 160; }
+
+__device__ void put_be(uint8_t *o, const fe &c) {
+  for (int q = 0; q < 8; q++) {
+    uint32_t w = c.l[7 - q];
+    o[4 * q] = (uint8_t)(w >> 24);
+    o[4 * q + 1] = (uint8_t)(w >> 16);
+    o[4 * q + 2] = (uint8_t)(w >> 8);
+    o[4 * q + 3] = (uint8_t)w;
+  }
+}
+__device__ void put_g1c(uint8_t *o, const g1_aff &p) {
+  if (aff_is_inf(p)) {
+    for (int q = 0; q < 32; q++) o[q] = q == 0 ? 0x80 : 0;
+    return;
+  }
+  put_be(o, f_from_mont<FpP>(p.x));
+  if (larger(p.y)) o[0] |= 0x40;
+}
+__device__ void put_g2c(uint8_t *o, const g2_aff &p) {
+  if (aff_is_inf(p)) {
+    for (int q = 0; q < 64; q++) o[q] = q == 0 ? 0x80 : 0;
+    return;
+  }
+  put_be(o, f_from_mont<FpP>(p.x.c0));
+  put_be(o + 32, f_from_mont<FpP>(p.x.c1));
+  if (fe_is_zero(p.y.c1) ? larger(p.y.c0) : larger(p.y.c1)) o[0] |= 0x40;
+}
+
+__device__ int ilog2(uint64_t v) {
+  int r = 0;
+  while (v >>= 1) r++;
+  return r;
+}
+// heap index n of a D-tree sibling (levels h < lK of K >> h nodes) to (h, s)
+__device__ void d_node(uint64_t n, uint64_t K, uint32_t &h, uint64_t &s) {
+  h = 0;
+  while (n >= (K >> h)) { n -= K >> h; h++; }
+  s = n;
+}
+// heap index w of a W commitment to depth d and prefix p
+__device__ void w_node(uint64_t w, uint32_t &d, uint64_t &p) {
+  d = (uint32_t)ilog2(w + 1);
+  p = w + 1 - (1ull << d);
+}
+
+}  // namespace
+
+// one thread per (proof, item)
+__global__ void __launch_bounds__(TPB) kps_serialize(PSCtx c) {
+  const PLayout &y = c.y;
+  const uint64_t per = y.b + 6ull * y.lK + 3 + y.lM + y.L;
+  uint64_t id = gtid();
+  if (id >= y.N * per) return;
+  uint64_t i = id / per, q = id % per;
+  uint64_t k = pl_batch(y, i), j = i / y.M, a = i % y.M, lo = k * y.b;
+  uint32_t t = pl_t(y, k), l = y.lK;
+  uint8_t *o = c.out + pl_off(y, i);
+  if (q < t) { put_g1c(o + 32 * q, c.Cj[lo + q]); return; }
+  q -= t;
+  if (q < 4ull * l) {
+    uint64_t r = q / 4, s = k * l + r;
+    uint8_t *b = o + 32ull * t + 832 * r;
+    switch (q % 4) {
+      case 0: { const fe *g = reinterpret_cast<const fe *>(c.Lgt + s); for (int e = 0; e < 12; e++) put_be(b + 32 * e, f_from_mont<FpP>(g[e])); break; }
+      case 1: put_g1c(b + 384, c.Lg1[s]); break;
+      case 2: { const fe *g = reinterpret_cast<const fe *>(c.Rgt + s); for (int e = 0; e < 12; e++) put_be(b + 416 + 32 * e, f_from_mont<FpP>(g[e])); break; }
+      default: put_g1c(b + 800, c.Rg1[s]);
+    }
+    return;
+  }
+  q -= 4ull * l;
+  uint8_t *b1 = o + 32ull * t + 832ull * l;
+  if (q < 3) {
+    if (q == 0) put_g1c(b1, c.Al[k]);
+    else if (q == 1) put_g2c(b1 + 32, c.vl[k]);
+    else put_g2c(b1 + 96, c.piv[k]);
+    return;
+  }
+  q -= 3;
+  uint8_t *b2 = b1 + 160;
+  if (q < 2ull * l) {
+    uint32_t h = (uint32_t)(q / 2);
+    uint64_t node = 2 * y.K - ((2 * y.K) >> h) + ((j >> h) ^ 1);
+    if (q % 2 == 0) put_g1c(b2 + 64 * h, c.D[node]);
+    else put_be(b2 + 64 * h + 32, c.Y[node * y.M + a]);  // stored canonical
+    return;
+  }
+  q -= 2ull * l;
+  if (q < y.lM) {
+    put_g1c(b2 + 64ull * l + 32 * q, c.W[(1ull << q) - 1 + (a >> (y.lM - q))]);
+    return;
+  }
+  q -= y.lM;
+  if (q < y.L) {
+    const uint32_t *nd = c.tree + 8 * (((y.N + i) >> q) ^ 1);
+    uint8_t *m = b2 + 64ull * l + 32ull * y.lM + 32 * q;
+    for (int w = 0; w < 8; w++) {
+      m[4 * w] = (uint8_t)(nd[w] >> 24);
+      m[4 * w + 1] = (uint8_t)(nd[w] >> 16);
+      m[4 * w + 2] = (uint8_t)(nd[w] >> 8);
+      m[4 * w + 3] = (uint8_t)nd[w];
+    }
+  }
+}
+
+// shared items, one thread each: K block commitments, 2K - 2 D-tree siblings, M - 1 W, C
+__global__ void __launch_bounds__(TPB) kva_decode(VACtx c) {
+  const PLayout &y = c.y;
+  uint64_t id = gtid(), K = y.K;
+  const uint64_t nD = 2 * K - 2, nW = y.M - 1;
+  if (id >= K + nD + nW + 1) return;
+  bool ok = true;
+  if (id < K) {
+    uint64_t j = id, k = j / y.b;
+    ok = g1_decompress(c.proofs + pl_off(y, k * pl_bm(y)) + 32 * (j - k * y.b), c.Cj[j]);
+  } else if ((id -= K) < nD) {
+    uint32_t h;
+    uint64_t s;
+    d_node(id, K, h, s);
+    uint64_t j = (s ^ 1) << h, i = j * y.M;
+    ok = g1_decompress(c.proofs + pl_off(y, i) + pl_step2(y, pl_batch(y, i)) + 64 * h, c.Dn[id]);
+  } else if ((id -= nD) < nW) {
+    uint32_t d;
+    uint64_t p;
+    w_node(id, d, p);
+    uint64_t i = p << (y.lM - d);
+    ok = g1_decompress(c.proofs + pl_off(y, i) + pl_step2(y, 0) + 64ull * y.lK + 32 * d, c.Wn[id]);
+  } else {
+    if (!gt_decode(c.Cb, *c.C)) atomicOr(c.flags, VFLAG_BAD_INPUT);
+  }
+  if (!ok) atomicOr(c.flags, VFLAG_BAD_PROOF);
+}
+
+// the root of every proof's Merkle path from its leaf (m_i, C_j), one thread per proof
+__global__ void __launch_bounds__(TPB) kva_roots(VACtx c) {
+  const PLayout &y = c.y;
+  uint64_t i = gtid();
+  if (i >= y.N) return;
+  uint64_t j = i / y.M;
+  fe m;
+  for (int q = 0; q < 8; q++) {
+    const uint8_t *b = c.m + 32 * i + 4 * q;
+    m.l[q] = (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+  }
+  if (!lt_words(m, bn::R_MOD)) atomicOr(c.flags, VFLAG_BAD_INPUT);
+  fe cx = f_from_mont<FpP>(c.Cj[j].x), cy = f_from_mont<FpP>(c.Cj[j].y);
+  uint32_t mw[8], cw[16], node[8];
+  for (int q = 0; q < 8; q++) { mw[q] = m.l[7 - q]; cw[q] = cx.l[7 - q]; cw[8 + q] = cy.l[7 - q]; }
+  sha::merkle_leaf(node, mw, cw);
+  const uint8_t *path = c.proofs + pl_off(y, i) + pl_step2(y, pl_batch(y, i)) + 64ull * y.lK + 32ull * y.lM;
+  uint64_t pos = y.N + i;
+  for (uint32_t h = 0; h < y.L; h++, pos >>= 1) {
+    uint32_t sib[8], o[8];
+    for (int q = 0; q < 8; q++) {
+      const uint8_t *sb = path + 32 * h + 4 * q;
+      sib[q] = ((uint32_t)sb[0] << 24) | ((uint32_t)sb[1] << 16) | ((uint32_t)sb[2] << 8) | sb[3];
+    }
+    if (pos & 1) sha::merkle_node(o, sib, node);
+    else sha::merkle_node(o, node, sib);
+    for (int q = 0; q < 8; q++) node[q] = o[q];
+  }
+  for (int q = 0; q < 8; q++) c.root[8 * i + q] = node[q];
+}
+
+// rho_j from C and the root of proof 0, one thread per j
+__global__ void __launch_bounds__(64) kva_rho(VACtx c) {
+  uint64_t j = gtid();
+  if (j >= c.y.K) return;
+  sha::Hasher hr;
+  sha::xmd_begin(hr);
+  hr.gt(*c.C);
+  for (int q = 0; q < 8; q++) hr.word(c.root[q]);
+  hr.u64(j);
+  c.rho[j] = sha::xmd_finish_fr(hr, DSTR_RHO);
+}
+
+// a workgroup per proof: its block, FC proof, D-tree siblings and W against the proofs that
+// represent them (16-byte words; every proof starts on a 32-byte boundary)
+__global__ void __launch_bounds__(256) kva_same(VACtx c) {
+  const PLayout &y = c.y;
+  __shared__ int diff;
+  uint64_t i = blockIdx.x;
+  if (i >= y.N) return;
+  const int t = threadIdx.x;
+  if (t == 0) diff = 0;
+  __syncthreads();
+  uint64_t k = pl_batch(y, i), j = i / y.M, a = i % y.M, i0 = k * pl_bm(y);
+  const uint4 *P = reinterpret_cast<const uint4 *>(c.proofs + pl_off(y, i));
+  bool d = false;
+  if (i != i0) {
+    const uint4 *R = reinterpret_cast<const uint4 *>(c.proofs + pl_off(y, i0));
+    uint64_t n16 = pl_step2(y, k) / 16;
+    for (uint64_t q = t; q < n16; q += 256) {
+      uint4 u = P[q], v = R[q];
+      d |= u.x != v.x || u.y != v.y || u.z != v.z || u.w != v.w;
+    }
+  }
+  // item x < lK: D-tree sibling of level x; lK <= x < lK + lM: W of depth x - lK (two words each)
+  uint32_t nit = y.lK + y.lM;
+  if ((uint32_t)t < 2 * nit) {
+    uint32_t x = t / 2, half = t % 2;
+    uint64_t ir, ofs_i, ofs_r;
+    if (x < y.lK) {
+      ir = ((j >> x) << x) * y.M;
+      ofs_i = pl_step2(y, k) + 64ull * x;
+      ofs_r = pl_step2(y, pl_batch(y, ir)) + 64ull * x;
+    } else {
+      uint32_t dd = x - y.lK;
+      ir = (a >> (y.lM - dd)) << (y.lM - dd);
+      ofs_i = pl_step2(y, k) + 64ull * y.lK + 32ull * dd;
+      ofs_r = pl_step2(y, 0) + 64ull * y.lK + 32ull * dd;
+    }
+    if (ir != i) {
+      uint4 u = reinterpret_cast<const uint4 *>(c.proofs + pl_off(y, i) + ofs_i)[half];
+      uint4 v = reinterpret_cast<const uint4 *>(c.proofs + pl_off(y, ir) + ofs_r)[half];
+      d |= u.x != v.x || u.y != v.y || u.z != v.z || u.w != v.w;
+    }
+  }
+  if (d) atomicOr(&diff, 1);
+  __syncthreads();
+  if (t == 0) c.odd[i] = diff ? 1 : 0;
+}
+
+// one thread per proof: y*_i = rho_j m_i + sum of the y siblings, the weight delta_i =
+// H(seed, i) (128 bits), and delta_i, delta_i y*_i (zero for a proof left to the one-proof
+// verifier, which joins the list)
+__global__ void __launch_bounds__(TPB) kva_proof(VACtx c) {
+  const PLayout &y = c.y;
+  uint64_t i = gtid();
+  if (i >= y.N) return;
+  bool odd = c.odd[i] != 0;
+  for (int q = 0; q < 8; q++) odd = odd || c.root[8 * i + q] != c.root[q];
+  uint64_t j = i / y.M;
+  fe m;
+  for (int q = 0; q < 8; q++) {
+    const uint8_t *b = c.m + 32 * i + 4 * q;
+    m.l[q] = (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+  }
+  fe ys = fr_mul(c.rho[j], f_to_mont<FpR>(m));
+  const uint8_t *s2 = c.proofs + pl_off(y, i) + pl_step2(y, pl_batch(y, i));
+  for (uint32_t h = 0; h < y.lK; h++) {
+    fe v = rd_be(s2 + 64 * h + 32);
+    if (!lt_words(v, bn::R_MOD)) atomicOr(c.flags, VFLAG_BAD_PROOF);
+    ys = fr_add(ys, f_to_mont<FpR>(v));
+  }
+  sha::Hasher hs;
+  hs.init();
+  hs.str(DSTR_VALL);
+  hs.bytes(c.seed, 32);
+  hs.u64(i);
+  uint32_t dg[8];
+  hs.final(dg);
+  fe w = fe_zero();
+  for (int q = 0; q < 4; q++) w.l[3 - q] = dg[q];
+  w = f_to_mont<FpR>(w);
+  if (odd) {
+    uint32_t at = atomicAdd(c.oddcnt, 1u);
+    c.oddlist[at] = i;  // at < N: one entry per proof at most
+    w = fe_zero();
+  }
+  c.delta[i] = w;
+  c.dy[i] = fr_mul(w, ys);
+}
+
+// sums of the weights: per row j (over a), per column a (over j), and of delta_i y*_i;
+// workgroups [0, K) rows, [K, K + M) columns, K + M the total
+__global__ void __launch_bounds__(256) kva_sums(VACtx c) {
+  const PLayout &y = c.y;
+  __shared__ fe sh[256];
+  uint64_t g = blockIdx.x;
+  const int t = threadIdx.x;
+  fe acc = fe_zero();
+  if (g < y.K) {
+    for (uint64_t a = t; a < y.M; a += 256) acc = fr_add(acc, c.delta[g * y.M + a]);
+  } else if (g < y.K + y.M) {
+    uint64_t a = g - y.K;
+    for (uint64_t j = t; j < y.K; j += 256) acc = fr_add(acc, c.delta[j * y.M + a]);
+  } else {
+    for (uint64_t i = t; i < y.N; i += 256) acc = fr_add(acc, c.dy[i]);
+  }
+  sh[t] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fr_add(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (g < y.K) c.rowsum[g] = sh[0];
+    else if (g < y.K + y.M) c.colsum[g - y.K] = sh[0];
+    else *c.sy = sh[0];
+  }
+}
+
+// the multiplication terms, one thread each.  Segment 0 (3K + M - 2 terms), paired with -g2:
+// rho_j Delta_j C_j; (sum of Delta over the subvectors whose sibling is D node (h, s)) D;
+// (sum of the column weights over the upper half of W's range) W; -(sum delta y*) g1.
+// Segment 1 + d (2^d terms), paired with vk_{l_M - 1 - d}: (sum over W's range) W.
+__global__ void __launch_bounds__(TPB) kva_terms(VACtx c) {
+  const PLayout &y = c.y;
+  const uint64_t K = y.K, M = y.M, T0 = 3 * K + M - 2;
+  uint64_t id = gtid();
+  if (id >= T0 + M - 1) return;
+  g1_aff base;
+  fe k = fe_zero();
+  if (id < K) {
+    base = c.Cj[id];
+    k = fr_mul(c.rho[id], c.rowsum[id]);
+  } else if (id < 3 * K - 2) {
+    uint64_t n = id - K, s;
+    uint32_t h;
+    d_node(n, K, h, s);
+    base = c.Dn[n];
+    uint64_t j0 = (s ^ 1) << h;
+    for (uint64_t j = j0; j < j0 + (1ull << h); j++) k = fr_add(k, c.rowsum[j]);
+  } else if (id < T0 - 1 || id >= T0) {
+    bool upper = id < T0;
+    uint64_t w = upper ? id - (3 * K - 2) : id - T0, p;
+    uint32_t d;
+    w_node(w, d, p);
+    base = c.Wn[w];
+    uint64_t len = 1ull << (y.lM - d), lo = p * len + (upper ? len / 2 : 0), hi = (p + 1) * len;
+    for (uint64_t a = lo; a < hi; a++) k = fr_add(k, c.colsum[a]);
+  } else {
+    base = {fe_const(bn::G1X), fe_const(bn::G1Y)};
+    k = fr_sub(fe_zero(), *c.sy);
+  }
+  c.bases[id] = base;
+  c.scal[id] = k;
+}
+
+// a workgroup per segment: the sum of its products, and the pairing inputs
+__global__ void __launch_bounds__(256) kva_segsum(VACtx c) {
+  const PLayout &y = c.y;
+  __shared__ g1_jac sh[256];
+  const uint64_t T0 = 3 * y.K + y.M - 2;
+  uint32_t g = blockIdx.x;
+  if (g > y.lM) return;
+  const int t = threadIdx.x;
+  uint64_t lo = g == 0 ? 0 : T0 + (1ull << (g - 1)) - 1, len = g == 0 ? T0 : 1ull << (g - 1);
+  g1_jac acc = jac_inf<OpsG1>();
+  for (uint64_t q = t; q < len; q += 256) acc = jac_madd(acc, c.prod[lo + q]);
+  sh[t] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] = jac_add(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    c.pp[g] = jac_to_aff(sh[0]);
+    g2_aff g2 = {f2_const(bn::G2X0, bn::G2X1), f2_const(bn::G2Y0, bn::G2Y1)};
+    c.pq[g] = g == 0 ? aff_neg(g2) : c.vk[y.lM - g];  // segment 1 + d: vk_{l_M - 1 - d}
+  }
+}
+
+__global__ void __launch_bounds__(64) kva_check(VACtx c) {
+  if (gtid() != 0) return;
+  const fe *e = reinterpret_cast<const fe *>(c.E);
+  bool one = fe_eq(e[0], f_one<FpP>());
+  for (int q = 1; q < 12; q++) one = one && fe_is_zero(e[q]);
+  if (one) atomicOr(c.flags, VFLAG_ACCEPT);
+}
+
+namespace kva {
+uint64_t nterms(const VACtx &c) { return 3 * c.y.K + 2 * c.y.M - 3; }
+void serialize(const PSCtx &c, hipStream_t st) {
+  L1(kps_serialize, c.y.N * (c.y.b + 6ull * c.y.lK + 3 + c.y.lM + c.y.L), c);
+}
+void decode(const VACtx &c, hipStream_t st) { L1(kva_decode, 3 * c.y.K + c.y.M - 2, c); }
+void roots(const VACtx &c, hipStream_t st) { L1(kva_roots, c.y.N, c); }
+void rho(const VACtx &c, hipStream_t st) { LAUNCH(kva_rho, dim3((unsigned)((c.y.K + 63) / 64)), dim3(64), 0, c); }
+void same(const VACtx &c, hipStream_t st) { LAUNCH(kva_same, dim3((unsigned)c.y.N), dim3(256), 0, c); }
+void proof(const VACtx &c, hipStream_t st) { L1(kva_proof, c.y.N, c); }
+void sums(const VACtx &c, hipStream_t st) { LAUNCH(kva_sums, dim3((unsigned)(c.y.K + c.y.M + 1)), dim3(256), 0, c); }
+void terms(const VACtx &c, hipStream_t st) { L1(kva_terms, nterms(c), c); }
+void segsum(const VACtx &c, hipStream_t st) { LAUNCH(kva_segsum, dim3(c.y.lM + 1), dim3(256), 0, c); }
+void check(const VACtx &c, hipStream_t st) { LAUNCH(kva_check, dim3(1), dim3(64), 0, c); }
+}  // namespace kva

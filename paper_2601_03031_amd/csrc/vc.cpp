@@ -1314,6 +1314,146 @@ VC_API int vc_profile_read(char *buf, size_t cap) {
 
 // ------------------------------------------------------------------ diagnostics
 // Runs one base-field operation on n pairs of canonical 32-byte little-endian inputs
+// ------------------------------------------------------------------ every proof at once
+static PLayout proof_layout(const vc_params *pp, uint32_t b) {
+  PLayout y;
+  y.L = pp->L; y.lK = pp->lK; y.lM = pp->lM; y.b = b;
+  y.N = pp->N; y.K = pp->K; y.M = pp->M;
+  y.nb = (pp->K + b - 1) / b;
+  y.t_last = (uint32_t)(pp->K - (y.nb - 1) * b);
+  y.len_full = vc_proof_len(pp->L, b);
+  y.len_last = vc_proof_len(pp->L, y.t_last);
+  return y;
+}
+static uint64_t proofs_total(const PLayout &y) {
+  return (y.nb - 1) * y.b * y.M * y.len_full + (uint64_t)y.t_last * y.M * y.len_last;
+}
+static uint64_t proof_offset(const PLayout &y, uint64_t i) {
+  uint64_t bm = (uint64_t)y.b * y.M, k = i / bm;
+  return k * bm * y.len_full + (i - k * bm) * (k == y.nb - 1 ? y.len_last : y.len_full);
+}
+
+VC_API int vc_proofs_serialize(const vc_proofs *pr, void *dst, uint64_t cap, uint64_t *len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pr || !len) return VC_EINVAL;
+  const vc_params *pp = pr->pp;
+  PLayout y = proof_layout(pp, pr->b);
+  *len = proofs_total(y);
+  if (!dst) return VC_OK;
+  if (cap < *len) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  hipStream_t st = pp->ex->side[0];
+  PSCtx c;
+  c.y = y;
+  void *bm = pr->mem;
+  c.Cj = at<g1_aff>(bm, pr->o_Cj); c.Lg1 = at<g1_aff>(bm, pr->o_Lg1); c.Rg1 = at<g1_aff>(bm, pr->o_Rg1);
+  c.Al = at<g1_aff>(bm, pr->o_Al); c.D = at<g1_aff>(bm, pr->o_D); c.W = at<g1_aff>(bm, pr->o_W);
+  c.Lgt = at<fp12>(bm, pr->o_Lgt); c.Rgt = at<fp12>(bm, pr->o_Rgt);
+  c.vl = at<g2_aff>(bm, pr->o_vl); c.piv = at<g2_aff>(bm, pr->o_piv);
+  c.Y = at<fe>(bm, pr->o_Y); c.tree = at<uint32_t>(bm, pr->o_tree);
+  c.out = static_cast<uint8_t *>(dst);
+  kva::serialize(c, st);
+  CKL("vc_proofs_serialize launch");
+  CK(hipStreamSynchronize(st));
+  return VC_OK;
+}
+
+VC_API int vc_verify_all(const vc_params *pp, const uint8_t C[384], uint32_t b, const void *m, const void *proofs,
+                         uint64_t len, const uint8_t seed[32], uint64_t *n_single) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (n_single) *n_single = 0;
+  if (!pp || !C || !m || !proofs || !seed || b < 1 || b > pp->K) return VC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(proofs) & 15) != 0) return VC_EINVAL;
+  PLayout y = proof_layout(pp, b);
+  if (len != proofs_total(y)) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  vc_exec *ex = pp->ex;
+  hipStream_t st = ex->main;
+  const uint64_t N = y.N, K = y.K, M = y.M;
+  VACtx c;
+  c.y = y;
+  c.proofs = static_cast<const uint8_t *>(proofs);
+  c.m = static_cast<const uint8_t *>(m);
+  c.vk = pp->vk;
+  Carve w;
+  size_t o_Cb = w.take<uint8_t>(384), o_seed = w.take<uint8_t>(32), o_Cj = w.take<g1_aff>(K), o_Dn = w.take<g1_aff>(2 * K),
+         o_Wn = w.take<g1_aff>(M), o_C = w.take<fp12>(1), o_root = w.take<uint32_t>(8 * N), o_rho = w.take<fe>(K),
+         o_delta = w.take<fe>(N), o_dy = w.take<fe>(N), o_odd = w.take<uint8_t>(N), o_ol = w.take<uint64_t>(N),
+         o_oc = w.take<uint32_t>(1), o_row = w.take<fe>(K), o_col = w.take<fe>(M), o_sy = w.take<fe>(1);
+  const uint64_t T = 3 * K + 2 * M - 3;
+  size_t o_bases = w.take<g1_aff>(T), o_scal = w.take<fe>(T), o_prod = w.take<g1_aff>(T), o_pp = w.take<g1_aff>(y.lM + 1),
+         o_pq = w.take<g2_aff>(y.lM + 1), o_F = w.take<fp12>(y.lM + 1), o_E = w.take<fp12>(1), o_fl = w.take<int>(1);
+  if (int rc = ensure_cnt(ex, tree_counters(y.lM + 1), st)) return rc;
+  void *d = nullptr;
+  CK(hipMalloc(&d, w.off));
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } free_d{d};
+  c.Cb = at<uint8_t>(d, o_Cb); c.seed = at<uint8_t>(d, o_seed);
+  c.Cj = at<g1_aff>(d, o_Cj); c.Dn = at<g1_aff>(d, o_Dn); c.Wn = at<g1_aff>(d, o_Wn); c.C = at<fp12>(d, o_C);
+  c.root = at<uint32_t>(d, o_root); c.rho = at<fe>(d, o_rho); c.delta = at<fe>(d, o_delta); c.dy = at<fe>(d, o_dy);
+  c.odd = at<uint8_t>(d, o_odd); c.oddlist = at<uint64_t>(d, o_ol); c.oddcnt = at<uint32_t>(d, o_oc);
+  c.rowsum = at<fe>(d, o_row); c.colsum = at<fe>(d, o_col); c.sy = at<fe>(d, o_sy);
+  c.bases = at<g1_aff>(d, o_bases); c.scal = at<fe>(d, o_scal); c.prod = at<g1_aff>(d, o_prod);
+  c.pp = at<g1_aff>(d, o_pp); c.pq = at<g2_aff>(d, o_pq); c.E = at<fp12>(d, o_E); c.flags = at<int>(d, o_fl);
+  fp12 *F = at<fp12>(d, o_F);
+  CK(hipMemcpyAsync(at<void>(d, o_Cb), C, 384, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(at<void>(d, o_seed), seed, 32, hipMemcpyHostToDevice, st));
+  CK(hipMemsetAsync(c.flags, 0, sizeof(int), st));
+  CK(hipMemsetAsync(c.oddcnt, 0, sizeof(uint32_t), st));
+  kva::decode(c, st);
+  kva::roots(c, st);
+  kva::rho(c, st);
+  kva::same(c, st);
+  kva::proof(c, st);
+  kva::sums(c, st);
+  kva::terms(c, st);
+  klw::g1_mul(c.bases, 0, c.scal, T, c.prod, st);
+  kva::segsum(c, st);
+  ks::miller(c.pp, 1, c.pq, 1, y.lM + 1, F, st);
+  ks::f12_reduce(F, 1, y.lM + 1, y.lM + 1, ex->cnt, st);
+  ks::final_exp(F, 1, 1, c.E, nullptr, 1, st);
+  kva::check(c, st);
+  int flags = 0;
+  uint32_t nodd = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, c.flags, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nodd, c.oddcnt, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    ex->cnt_dirty = true;
+    return hip_fail(e, "vc_verify_all");
+  }
+  if (flags & VFLAG_BAD_INPUT) return VC_EINVAL;
+  if (flags & VFLAG_BAD_PROOF) return 0;
+  // the combined check covers every proof that is not left to the one-proof verifier
+  if (nodd < N && !(flags & VFLAG_ACCEPT)) return 0;
+  // one proof per batch (its FC part) and the proofs that differ from their representatives,
+  // in index order, one at a time; the first rejection ends the call
+  std::vector<uint64_t> single;
+  for (uint64_t k = 0; k < y.nb; k++) single.push_back(k * y.b * M);
+  if (nodd) {
+    std::vector<uint64_t> ol(nodd);
+    CK(hipMemcpy(ol.data(), c.oddlist, nodd * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    single.insert(single.end(), ol.begin(), ol.end());
+  }
+  std::sort(single.begin(), single.end());
+  single.erase(std::unique(single.begin(), single.end()), single.end());
+  std::vector<uint8_t> pf(y.len_full);
+  uint8_t mi[32];
+  for (uint64_t i : single) {
+    uint64_t li = (i / ((uint64_t)y.b * M) == y.nb - 1) ? y.len_last : y.len_full;
+    CK(hipMemcpy(pf.data(), c.proofs + proof_offset(y, i), li, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(mi, c.m + 32 * i, 32, hipMemcpyDeviceToHost));
+    if (n_single) (*n_single)++;
+    int v = vc_verify(pp, C, N, b, i, mi, pf.data(), li);
+    if (v < 0) return v;
+    if (v != 1) return 0;
+  }
+  return 1;
+}
+
 // (host buffers) in the 8-lanes-per-element layout: op 0 mul, 1 add, 2 sub, 3 half,
 // 4 inverse, 5 square; which 0 = F_p, 1 = F_r.
 VC_API int vc_diag_field(int which, int op, uint64_t n, const void *a, const void *b, void *out) {

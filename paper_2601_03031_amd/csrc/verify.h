@@ -33,6 +33,60 @@ struct VCtx {
   int *flags;
 };
 
+// Layout of the N serialized proofs in index order: proofs of batch k (entries i with
+// i / (b M) = k) hold t_k = min(b, K - k b) block commitments and are len(t_k) bytes long; the
+// last batch alone can be shorter.
+struct PLayout {
+  uint32_t L, lK, lM, b, t_last;
+  uint64_t N, K, M, nb, len_full, len_last;
+};
+
+// Serialization of every proof of an open-all bundle (kps_serialize)
+struct PSCtx {
+  PLayout y;
+  const g1_aff *Cj, *Lg1, *Rg1, *Al, *D, *W;
+  const fp12 *Lgt, *Rgt;
+  const g2_aff *vl, *piv;
+  const fe *Y;
+  const uint32_t *tree;
+  uint8_t *out;
+};
+
+// Verification of all N proofs at once (kva_*): shared items are decoded once, from the proof
+// that represents them, and the PST checks of all proofs combine with random weights
+struct VACtx {
+  PLayout y;
+  const uint8_t *proofs, *m, *Cb, *seed;
+  g1_aff *Cj, *Dn, *Wn;  // K block commitments, 2K - 2 D-tree siblings (heap order), M - 1 W (heap order)
+  fp12 *C;
+  uint32_t *root;        // N x 8 words: root of each proof's Merkle path
+  fe *rho, *delta, *dy;  // K; N weights; N weighted y*
+  uint8_t *odd;          // N: proof differs from the representatives it shares items with
+  uint64_t *oddlist;
+  uint32_t *oddcnt;
+  fe *rowsum, *colsum, *sy;
+  g1_aff *bases, *prod, *pp;
+  fe *scal;
+  g2_aff *pq;
+  fp12 *E;
+  const g2_aff *vk;
+  int *flags;
+};
+
+namespace kva {
+uint64_t nterms(const VACtx &c);
+void serialize(const PSCtx &c, hipStream_t st);
+void decode(const VACtx &c, hipStream_t st);
+void roots(const VACtx &c, hipStream_t st);
+void rho(const VACtx &c, hipStream_t st);
+void same(const VACtx &c, hipStream_t st);
+void proof(const VACtx &c, hipStream_t st);
+void sums(const VACtx &c, hipStream_t st);
+void terms(const VACtx &c, hipStream_t st);
+void segsum(const VACtx &c, hipStream_t st);
+void check(const VACtx &c, hipStream_t st);
+}  // namespace kva
+
 namespace kv {
 void decode(const VCtx &c, hipStream_t st);
 void transcript(const VCtx &c, hipStream_t st);
