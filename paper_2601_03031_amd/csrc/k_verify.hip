@@ -115,8 +115,9 @@ __device__ bool gt_decode(const uint8_t *b, fp12 &f) {
 
 }  // namespace
 
-// one thread per item; layout of the proof in VCtx::off_*
-__global__ void __launch_bounds__(TPB) kv_decode(VCtx c) {
+// one thread per item of proof blockIdx.y (layout of the serialized proof, vc_proof_get)
+__global__ void __launch_bounds__(TPB) kv_decode(const VCtx *cs) {
+  const VCtx &c = cs[blockIdx.y];
   uint32_t id = (uint32_t)gtid();
   const uint32_t t = c.t, l = c.lK, lM = c.lM;
   const uint32_t n_items = t + 4 * l + 3 + 2 * l + lM + 2;
@@ -160,126 +161,171 @@ __global__ void __launch_bounds__(TPB) kv_decode(VCtx c) {
   if (!ok) atomicOr(c.flags, VFLAG_BAD_PROOF);
 }
 
-// Fiat-Shamir replay and scalar set-up (one thread)
-__global__ void __launch_bounds__(64) kv_transcript(VCtx c) {
-  if (gtid() != 0) return;
+// Fiat-Shamir replay and scalar set-up, a workgroup per proof: chunk digests and the batching
+// coefficients r_u one thread each, the challenge chain (x_j, z, f_v(z)) on thread 0 beside the
+// Merkle path (rho_j, y*) on thread 64, then b_l as a tree of per-thread partial sums and the
+// multiplication jobs in parallel
+__global__ void __launch_bounds__(256) kv_transcript(const VCtx *cs) {
+  const VCtx &c = cs[blockIdx.x];
+  const int tid = threadIdx.x;
   const uint32_t t = c.t, l = c.lK;
-  // batching coefficients r_u = H2F(FC-R, sigma || u), sigma over 32-entry chunk digests
-  uint32_t sigma[8];
-  {
+  __shared__ uint32_t dig[32][8];  // chunk digests: t <= 1024
+  __shared__ uint32_t sigma[8];
+  __shared__ fe part[256];
+  __shared__ fe s_z, s_rho, s_ystar;
+  const uint32_t nch = (t + 31) / 32;
+  // r_u = H2F(FC-R, sigma || u), sigma over the digests of 32-entry chunks
+  for (uint32_t q = tid; q < nch; q += 256) {
+    sha::Hasher hc;
+    hc.init();
+    for (uint32_t u = q * 32; u < t && u < q * 32 + 32; u++) {
+      hc.u64(c.lo + u);
+      hc.g1(c.blk[u]);
+    }
+    hc.final(dig[q]);
+  }
+  __syncthreads();
+  if (tid == 0) {
     sha::Hasher hs;
     hs.init();
     hs.str(DSTR_FC_R);
     hs.gt(*c.C);
     hs.u64(t);
-    for (uint32_t q = 0; q * 32 < t; q++) {
-      sha::Hasher hc;
-      hc.init();
-      for (uint32_t u = q * 32; u < t && u < q * 32 + 32; u++) {
-        hc.u64(c.lo + u);
-        hc.g1(c.blk[u]);
-      }
-      uint32_t d[8];
-      hc.final(d);
-      for (int w = 0; w < 8; w++) hs.word(d[w]);
-    }
+    for (uint32_t q = 0; q < nch; q++)
+      for (int w = 0; w < 8; w++) hs.word(dig[q][w]);
     hs.final(sigma);
   }
-  for (uint32_t u = 0; u < t; u++) {
+  __syncthreads();
+  for (uint32_t u = tid; u < t; u += 256) {
     sha::Hasher hs;
     sha::xmd_begin(hs);
     for (int w = 0; w < 8; w++) hs.word(sigma[w]);
     hs.u64(u);
     c.r[u] = sha::xmd_finish_fr(hs, DSTR_FC_R);
   }
-  // round challenges
-  for (uint32_t j = 0; j < l; j++) {
-    sha::Hasher hs;
-    sha::xmd_begin(hs);
-    if (j > 0) hs.field<FpR>(c.x[j - 1]);
-    hs.gt(c.Lgt[j]);
-    hs.g1(c.Lg1[j]);
-    hs.gt(c.Rgt[j]);
-    hs.g1(c.Rg1[j]);
-    fe x = sha::xmd_finish_fr(hs, DSTR_FC_X);
-    if (fe_is_zero(x)) atomicOr(c.flags, VFLAG_BAD_PROOF);
-    c.x[j] = x;
-    c.xinv[j] = fr_inv_fast(x);
+  if (tid == 0) {
+    // round challenges
+    for (uint32_t j = 0; j < l; j++) {
+      sha::Hasher hs;
+      sha::xmd_begin(hs);
+      if (j > 0) hs.field<FpR>(c.x[j - 1]);
+      hs.gt(c.Lgt[j]);
+      hs.g1(c.Lg1[j]);
+      hs.gt(c.Rgt[j]);
+      hs.g1(c.Rg1[j]);
+      fe x = sha::xmd_finish_fr(hs, DSTR_FC_X);
+      if (fe_is_zero(x)) atomicOr(c.flags, VFLAG_BAD_PROOF);
+      c.x[j] = x;
+      c.xinv[j] = fr_inv_fast(x);
+    }
+    // z = H2F(FC-Z, x_l || v_l); f_v(z) = prod_j (1 + x_j^{-1} z^{2^{l-j+1}})
+    sha::Hasher hz;
+    sha::xmd_begin(hz);
+    hz.field<FpR>(c.x[l - 1]);
+    hz.g2(*c.vl);
+    fe z = sha::xmd_finish_fr(hz, DSTR_FC_Z);
+    fe fz = f_one<FpR>(), zp = fr_mul(z, z);  // z^{2^1}
+    for (int j = (int)l; j >= 1; j--) {      // exponent 2^{l-j+1}: j = l first
+      fz = fr_mul(fz, fr_add(f_one<FpR>(), fr_mul(c.xinv[j - 1], zp)));
+      zp = fr_mul(zp, zp);
+    }
+    s_z = z;
+    *c.fz = fz;
+  } else if (tid == 64) {
+    // Merkle path of leaf i = SHA-256(0x00 || m_i || C_j) up to the root
+    const g1_aff &Cj = c.blk[c.j - c.lo];
+    uint32_t mw[8], cw[16], node[8];
+    fe mc = f_from_mont<FpR>(*c.mi);
+    fe cx = f_from_mont<FpP>(Cj.x), cy = f_from_mont<FpP>(Cj.y);
+    for (int q = 0; q < 8; q++) { mw[q] = mc.l[7 - q]; cw[q] = cx.l[7 - q]; cw[8 + q] = cy.l[7 - q]; }
+    sha::merkle_leaf(node, mw, cw);
+    uint64_t pos = c.N + c.i;
+    for (uint32_t h = 0; h < c.L; h++, pos >>= 1) {
+      uint32_t sib[8];
+      const uint8_t *sb = c.mpath + 32 * h;
+      for (int q = 0; q < 8; q++)
+        sib[q] = ((uint32_t)sb[4 * q] << 24) | ((uint32_t)sb[4 * q + 1] << 16) | ((uint32_t)sb[4 * q + 2] << 8) | sb[4 * q + 3];
+      uint32_t o[8];
+      if (pos & 1) sha::merkle_node(o, sib, node);
+      else sha::merkle_node(o, node, sib);
+      for (int q = 0; q < 8; q++) node[q] = o[q];
+    }
+    sha::Hasher hr;
+    sha::xmd_begin(hr);
+    hr.gt(*c.C);
+    for (int q = 0; q < 8; q++) hr.word(node[q]);
+    hr.u64(c.j);
+    fe rho = sha::xmd_finish_fr(hr, DSTR_RHO);
+    fe ystar = fr_mul(rho, *c.mi);
+    for (uint32_t h = 0; h < l; h++) ystar = fr_add(ystar, c.ysib[h]);
+    s_rho = rho;
+    s_ystar = ystar;
   }
-  // z = H2F(FC-Z, x_l || v_l); f_v(z) = prod_j (1 + x_j^{-1} z^{2^{l-j+1}})
-  sha::Hasher hz;
-  sha::xmd_begin(hz);
-  hz.field<FpR>(c.x[l - 1]);
-  hz.g2(*c.vl);
-  fe z = sha::xmd_finish_fr(hz, DSTR_FC_Z);
-  fe fz = f_one<FpR>(), zp = fr_mul(z, z);  // z^{2^1}
-  for (int j = (int)l; j >= 1; j--) {      // exponent 2^{l-j+1}: j = l first
-    fz = fr_mul(fz, fr_add(f_one<FpR>(), fr_mul(c.xinv[j - 1], zp)));
-    zp = fr_mul(zp, zp);
-  }
+  __syncthreads();
   // b_l = sum_u r_u prod_k (x_k^{-1})^{bit_{l-k}(a_u)}
-  fe bl = fe_zero();
-  for (uint32_t u = 0; u < t; u++) {
+  fe acc = fe_zero();
+  for (uint32_t u = tid; u < t; u += 256) {
     fe term = c.r[u];
     for (uint32_t k = 1; k <= l; k++)
       if (((c.lo + u) >> (l - k)) & 1) term = fr_mul(term, c.xinv[k - 1]);
-    bl = fr_add(bl, term);
+    acc = fr_add(acc, term);
   }
-  // Merkle path of leaf i = SHA-256(0x00 || m_i || C_j) up to the root
-  const g1_aff &Cj = c.blk[c.j - c.lo];
-  uint32_t mw[8], cw[16], node[8];
-  fe mc = f_from_mont<FpR>(*c.mi);
-  fe cx = f_from_mont<FpP>(Cj.x), cy = f_from_mont<FpP>(Cj.y);
-  for (int q = 0; q < 8; q++) { mw[q] = mc.l[7 - q]; cw[q] = cx.l[7 - q]; cw[8 + q] = cy.l[7 - q]; }
-  sha::merkle_leaf(node, mw, cw);
-  uint64_t pos = c.N + c.i;
-  for (uint32_t h = 0; h < c.L; h++, pos >>= 1) {
-    uint32_t sib[8];
-    const uint8_t *sb = c.mpath + 32 * h;
-    for (int q = 0; q < 8; q++)
-      sib[q] = ((uint32_t)sb[4 * q] << 24) | ((uint32_t)sb[4 * q + 1] << 16) | ((uint32_t)sb[4 * q + 2] << 8) | sb[4 * q + 3];
-    uint32_t o[8];
-    if (pos & 1) sha::merkle_node(o, sib, node);
-    else sha::merkle_node(o, node, sib);
-    for (int q = 0; q < 8; q++) node[q] = o[q];
+  part[tid] = acc;
+  __syncthreads();
+  for (int sft = 128; sft > 0; sft >>= 1) {
+    if (tid < sft) part[tid] = fr_add(part[tid], part[tid + sft]);
+    __syncthreads();
   }
-  sha::Hasher hr;
-  sha::xmd_begin(hr);
-  hr.gt(*c.C);
-  for (int q = 0; q < 8; q++) hr.word(node[q]);
-  hr.u64(c.j);
-  fe rho = sha::xmd_finish_fr(hr, DSTR_RHO);
-  fe ystar = fr_mul(rho, *c.mi);
-  for (uint32_t h = 0; h < l; h++) ystar = fr_add(ystar, c.ysib[h]);
-  // G1 multiplication jobs: r_u blk_u; x_j Lg1_j; x_j^{-1} Rg1_j; b_l A_l; rho C_j; y* g1; z g1
-  uint32_t n = 0;
-  for (uint32_t u = 0; u < t; u++) { c.mb[n] = c.blk[u]; c.ms[n++] = c.r[u]; }
-  for (uint32_t j = 0; j < l; j++) {
-    c.mb[n] = c.Lg1[j]; c.ms[n++] = c.x[j];
-    c.mb[n] = c.Rg1[j]; c.ms[n++] = c.xinv[j];
+  // G1 multiplication jobs: r_u blk_u; x_j Lg1_j; x_j^{-1} Rg1_j; b_l A_l; rho C_j; y* g1; z g1;
+  // then (g1, 0) up to the stride of the job arrays
+  const g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
+  for (uint32_t q = tid; q < c.nmul; q += 256) {
+    g1_aff base = g1;
+    fe k = fe_zero();
+    if (q < t) {
+      base = c.blk[q]; k = c.r[q];
+    } else if (q < t + 2 * l) {
+      uint32_t j = (q - t) / 2;
+      if ((q - t) % 2 == 0) { base = c.Lg1[j]; k = c.x[j]; }
+      else { base = c.Rg1[j]; k = c.xinv[j]; }
+    } else if (q == t + 2 * l) {
+      base = *c.Al; k = part[0];
+    } else if (q == t + 2 * l + 1) {
+      base = c.blk[c.j - c.lo]; k = s_rho;
+    } else if (q == t + 2 * l + 2) {
+      k = s_ystar;
+    } else if (q == t + 2 * l + 3) {
+      k = s_z;
+    }
+    c.mb[q] = base;
+    c.ms[q] = k;
   }
-  g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
-  c.mb[n] = *c.Al; c.ms[n++] = bl;
-  c.mb[n] = Cj; c.ms[n++] = rho;
-  c.mb[n] = g1; c.ms[n++] = ystar;
-  c.mb[n] = g1; c.ms[n++] = z;
-  // G2 job: f_v(z) g2; G_T jobs: L_j^{x_j}, R_j^{1/x_j}
-  *c.fz = fz;
-  for (uint32_t j = 0; j < l; j++) {
-    c.gts[2 * j] = c.x[j];
-    c.gts[2 * j + 1] = c.xinv[j];
-    c.gtb[2 * j] = c.Lgt[j];
-    c.gtb[2 * j + 1] = c.Rgt[j];
+  // G_T jobs: L_j^{x_j}, R_j^{1/x_j}
+  for (uint32_t q = tid; q < 2 * l; q += 256) {
+    c.gts[q] = (q % 2 == 0) ? c.x[q / 2] : c.xinv[q / 2];
+    c.gtb[q] = (q % 2 == 0) ? c.Lgt[q / 2] : c.Rgt[q / 2];
   }
 }
 
-// point sums and pairing inputs (one thread)
-__global__ void __launch_bounds__(64) kv_assemble(VCtx c) {
-  if (gtid() != 0) return;
+// point sums and pairing inputs, a workgroup per proof (the sum of the t + 2l products as a
+// tree of per-thread partial sums)
+__global__ void __launch_bounds__(256) kv_assemble(const VCtx *cs) {
+  const VCtx &c = cs[blockIdx.x];
+  __shared__ g1_jac sh[256];
+  const int tid = threadIdx.x;
   const uint32_t t = c.t, l = c.lK, lM = c.lM;
   g1_jac acc = jac_inf<OpsG1>();
-  for (uint32_t u = 0; u < t + 2 * l; u++) acc = jac_madd(acc, c.mo[u]);
-  *c.Cg1 = jac_to_aff(acc);
+  for (uint32_t u = tid; u < t + 2 * l; u += 256) acc = jac_madd(acc, c.mo[u]);
+  sh[tid] = acc;
+  __syncthreads();
+  for (int sft = 128; sft > 0; sft >>= 1) {
+    if (tid < sft) sh[tid] = jac_add(sh[tid], sh[tid + sft]);
+    __syncthreads();
+  }
+  // G_T product C prod L^x R^{1/x} gathers in gto[0..2l] with C last
+  for (uint32_t q = tid; q < 2 * l; q += 256) c.gto[q] = c.gtp[q];
+  if (tid != 0) return;
+  *c.Cg1 = jac_to_aff(sh[0]);
   *c.bA = c.mo[t + 2 * l];
   g1_jac D = jac_from_aff(c.mo[t + 2 * l + 1]);
   for (uint32_t h = 0; h < l; h++) D = jac_madd(D, c.Dsib[h]);
@@ -301,12 +347,14 @@ __global__ void __launch_bounds__(64) kv_assemble(VCtx c) {
     if ((a >> var) & 1) q = jac_to_aff(jac_madd(jac_from_aff(q), aff_neg(g2)));
     c.pq[4 + d] = q;
   }
-  // G_T product C prod L^x R^{1/x} gathers in gto[0..2l] with C last
   c.gto[2 * l] = *c.C;
 }
 
-__global__ void __launch_bounds__(64) kv_compare(VCtx c) {
-  if (gtid() != 0) return;
+// the final equalities, a thread per proof
+__global__ void __launch_bounds__(64) kv_compare(const VCtx *cs, uint32_t n) {
+  uint64_t p = gtid();
+  if (p >= n) return;
+  const VCtx &c = cs[p];
   fp12 one;
   fe *o = reinterpret_cast<fe *>(&one);
   for (int k = 0; k < 12; k++) o[k] = k == 0 ? f_one<FpP>() : fe_zero();
@@ -322,13 +370,15 @@ __global__ void __launch_bounds__(64) kv_compare(VCtx c) {
 }
 
 namespace kv {
-void decode(const VCtx &c, hipStream_t st) {
-  uint32_t n = c.t + 4 * c.lK + 3 + 2 * c.lK + c.lM + 2;
-  L1(kv_decode, n, c);
+void decode(const VCtx *cs, uint32_t n, uint32_t tmax, uint32_t lK, uint32_t lM, hipStream_t st) {
+  uint32_t items = tmax + 4 * lK + 3 + 2 * lK + lM + 2;
+  LAUNCH(kv_decode, dim3(nblk(items), n), dim3(TPB), 0, cs);
 }
-void transcript(const VCtx &c, hipStream_t st) { LAUNCH(kv_transcript, dim3(1), dim3(64), 0, c); }
-void assemble(const VCtx &c, hipStream_t st) { LAUNCH(kv_assemble, dim3(1), dim3(64), 0, c); }
-void compare(const VCtx &c, hipStream_t st) { LAUNCH(kv_compare, dim3(1), dim3(64), 0, c); }
+void transcript(const VCtx *cs, uint32_t n, hipStream_t st) { LAUNCH(kv_transcript, dim3(n), dim3(256), 0, cs); }
+void assemble(const VCtx *cs, uint32_t n, hipStream_t st) { LAUNCH(kv_assemble, dim3(n), dim3(256), 0, cs); }
+void compare(const VCtx *cs, uint32_t n, hipStream_t st) {
+  LAUNCH(kv_compare, dim3((n + 63) / 64), dim3(64), 0, cs, n);
+}
 }  // namespace kv
 
 // ------------------------------------------------------------------ every proof at once

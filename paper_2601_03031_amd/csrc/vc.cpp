@@ -1199,80 +1199,118 @@ VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst
   return export_items(pr->mem, idx, mode, dst, cap, len);
 }
 
-// VC.Verify (appendix C): FC.BVerify on the proof's block with the faster verifier,
-// the Merkle path to rho_j, the fold-up of D* and y*, and the PST check at Bin(a).
+// VC.Verify (appendix C) of n proofs at once, each as its own check: FC.BVerify on the proof's
+// block with the faster verifier, the Merkle path to rho_j, the fold-up of D* and y*, and the
+// PST check at Bin(a).  Proof q is entry idx[q]; its bytes (vc_proof_len(L, t) of them) are at
+// the device address pf[q] and its entry (32 bytes, little-endian) at mi[q]; Cb: the commitment
+// bytes on the device.  verdict[q]: 1 accept, 0 reject, VC_EINVAL malformed C or entry.
+static int verify_many(const vc_params *pp, const uint8_t *Cb, uint32_t b, uint32_t n, const uint64_t *idx,
+                       const uint8_t *const *pf, const uint8_t *const *mi, hipStream_t st, int *verdict) {
+  if (n == 0) return VC_OK;
+  const uint64_t K = pp->K, M = pp->M;
+  const uint32_t lK = pp->lK, lM = pp->lM, L = pp->L;
+  const uint32_t tmax = b, nmul = tmax + 2 * lK + 4, npair = 4 + lM;
+  vc_exec *ex = pp->ex;
+  Carve c;
+  size_t o_ctx = c.take<VCtx>(n), o_blk = c.take<g1_aff>((uint64_t)n * tmax), o_Lg1 = c.take<g1_aff>(n * lK),
+         o_Rg1 = c.take<g1_aff>(n * lK), o_Al = c.take<g1_aff>(n), o_D = c.take<g1_aff>(n * lK), o_W = c.take<g1_aff>(n * lM),
+         o_Lgt = c.take<fp12>(n * lK), o_Rgt = c.take<fp12>(n * lK), o_Cgt = c.take<fp12>(n), o_vl = c.take<g2_aff>(n),
+         o_piv = c.take<g2_aff>(n), o_ys = c.take<fe>(n * lK), o_mi = c.take<fe>(n), o_r = c.take<fe>((uint64_t)n * tmax),
+         o_x = c.take<fe>(n * lK), o_xi = c.take<fe>(n * lK), o_ms = c.take<fe>((uint64_t)n * nmul), o_fz = c.take<fe>(n),
+         o_gts = c.take<fe>(2 * n * lK), o_mb = c.take<g1_aff>((uint64_t)n * nmul), o_mo = c.take<g1_aff>((uint64_t)n * nmul),
+         o_fzg2 = c.take<g2_aff>(n), o_gtb = c.take<fp12>(2 * n * lK), o_gtp = c.take<fp12>(2 * n * lK),
+         o_gto = c.take<fp12>(n * (2 * lK + 1)), o_Cg1 = c.take<g1_aff>(n), o_bA = c.take<g1_aff>(n),
+         o_pp = c.take<g1_aff>(n * npair), o_pq = c.take<g2_aff>(n * npair), o_F = c.take<fp12>(n * npair),
+         o_E = c.take<fp12>(3 * n), o_fl = c.take<int>(n);
+  // the three product trees below run one after another and share one counter area
+  const uint64_t tc = tree_counters(npair > 2 * lK + 1 ? npair : 2 * lK + 1);
+  if (int rc = ensure_cnt(ex, n * tc, st)) return rc;
+  void *d = nullptr;
+  CK(hipMalloc(&d, c.off));
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } free_d{d};
+  std::vector<VCtx> xs(n);
+  for (uint32_t q = 0; q < n; q++) {
+    VCtx &x = xs[q];
+    const uint64_t i = idx[q], j = i / M, a = i % M, k = j / b, lo = k * b, hi = lo + b < K ? lo + b : K;
+    const uint32_t t = (uint32_t)(hi - lo);
+    x.t = t; x.lK = lK; x.lM = lM; x.L = L; x.nmul = nmul;
+    x.N = pp->N; x.i = i; x.j = j; x.a = a; x.lo = lo;
+    x.proof = pf[q]; x.Cb = Cb; x.mib = mi[q];
+    x.mpath = x.proof + (vc_proof_len(L, t) - 32ull * L);
+    x.blk = at<g1_aff>(d, o_blk) + (uint64_t)q * tmax; x.Lg1 = at<g1_aff>(d, o_Lg1) + q * lK;
+    x.Rg1 = at<g1_aff>(d, o_Rg1) + q * lK; x.Al = at<g1_aff>(d, o_Al) + q; x.Dsib = at<g1_aff>(d, o_D) + q * lK;
+    x.Wp = at<g1_aff>(d, o_W) + q * lM; x.Lgt = at<fp12>(d, o_Lgt) + q * lK; x.Rgt = at<fp12>(d, o_Rgt) + q * lK;
+    x.C = at<fp12>(d, o_Cgt) + q; x.vl = at<g2_aff>(d, o_vl) + q; x.piv = at<g2_aff>(d, o_piv) + q;
+    x.ysib = at<fe>(d, o_ys) + q * lK; x.mi = at<fe>(d, o_mi) + q; x.r = at<fe>(d, o_r) + (uint64_t)q * tmax;
+    x.x = at<fe>(d, o_x) + q * lK; x.xinv = at<fe>(d, o_xi) + q * lK; x.ms = at<fe>(d, o_ms) + (uint64_t)q * nmul;
+    x.fz = at<fe>(d, o_fz) + q; x.gts = at<fe>(d, o_gts) + 2 * q * lK; x.mb = at<g1_aff>(d, o_mb) + (uint64_t)q * nmul;
+    x.mo = at<g1_aff>(d, o_mo) + (uint64_t)q * nmul; x.fzg2 = at<g2_aff>(d, o_fzg2) + q;
+    x.gtb = at<fp12>(d, o_gtb) + 2 * q * lK; x.gtp = at<fp12>(d, o_gtp) + 2 * q * lK;
+    x.gto = at<fp12>(d, o_gto) + q * (2 * lK + 1); x.Cg1 = at<g1_aff>(d, o_Cg1) + q; x.bA = at<g1_aff>(d, o_bA) + q;
+    x.pp = at<g1_aff>(d, o_pp) + q * npair; x.pq = at<g2_aff>(d, o_pq) + q * npair; x.F = at<fp12>(d, o_F) + q * npair;
+    x.E = at<fp12>(d, o_E) + 3 * q; x.g1beta = pp->g1beta; x.vk = pp->vk; x.flags = at<int>(d, o_fl) + q;
+  }
+  const VCtx *cs = at<VCtx>(d, o_ctx);
+  fp12 *F = at<fp12>(d, o_F), *E = at<fp12>(d, o_E);
+  std::vector<int> flags(n, 0);
+  hipError_t e = hipMemcpyAsync(at<void>(d, o_ctx), xs.data(), n * sizeof(VCtx), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(at<int>(d, o_fl), 0, n * sizeof(int), st);
+  if (e == hipSuccess) {
+    kv::decode(cs, n, tmax, lK, lM, st);
+    kv::transcript(cs, n, st);
+    klw::g1_mul(at<g1_aff>(d, o_mb), 0, at<fe>(d, o_ms), (uint64_t)n * nmul, at<g1_aff>(d, o_mo), st);
+    klw::g2_mul(pp->g2gen, 1, at<fe>(d, o_fz), n, at<g2_aff>(d, o_fzg2), st);
+    ks::gt_pow(at<fp12>(d, o_gtb), at<fe>(d, o_gts), 2 * n * lK, at<fp12>(d, o_gtp), st);
+    kv::assemble(cs, n, st);
+    ks::f12_reduce(at<fp12>(d, o_gto), n, 2 * lK + 1, 2 * lK + 1, ex->cnt, st);
+    ks::miller(at<g1_aff>(d, o_pp), 1, at<g2_aff>(d, o_pq), 1, (uint64_t)n * npair, F, st);
+    ks::f12_reduce(F + 1, n, npair, 2, ex->cnt, st);
+    ks::f12_reduce(F + 3, n, npair, npair - 3, ex->cnt, st);
+    // E[3q + r]: input q even to out0[(q / 2) 6], odd to out1 = out0 + 3
+    ks::final_exp(F, npair, n, E, E + 3, 6, st);
+    ks::final_exp(F + 1, npair, n, E + 1, E + 4, 6, st);
+    ks::final_exp(F + 3, npair, n, E + 2, E + 5, 6, st);
+    kv::compare(cs, n, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), at<int>(d, o_fl), n * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    ex->cnt_dirty = true;  // the product trees may have stopped half way
+    return hip_fail(e, "vc_verify");
+  }
+  for (uint32_t q = 0; q < n; q++)
+    verdict[q] = (flags[q] & VFLAG_BAD_INPUT) ? VC_EINVAL : (flags[q] & VFLAG_BAD_PROOF) ? 0 : (flags[q] & VFLAG_ACCEPT) ? 1 : 0;
+  return VC_OK;
+}
+
+// VC.Verify (appendix C) of one proof: verify_many on a device copy of the inputs.
 VC_API int vc_verify(const vc_params *pp, const uint8_t C[384], uint64_t n, uint32_t b, uint64_t i, const uint8_t m_i[32],
                      const uint8_t *proof, size_t len) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pp || !C || !m_i || !proof || n != pp->N || i >= n || b < 1 || b > pp->K) return VC_EINVAL;
   const uint64_t K = pp->K, M = pp->M;
-  const uint32_t lK = pp->lK, lM = pp->lM;
-  const uint64_t j = i / M, a = i % M, k = j / b, lo = k * b, hi = lo + b < K ? lo + b : K;
-  const uint32_t t = (uint32_t)(hi - lo);
-  if (len != vc_proof_len(pp->L, t)) return VC_EINVAL;
+  const uint64_t j = i / M, k = j / b, lo = k * b, hi = lo + b < K ? lo + b : K;
+  if (len != vc_proof_len(pp->L, (uint32_t)(hi - lo))) return VC_EINVAL;
   CK(hipSetDevice(pp->device));
-  vc_exec *ex = pp->ex;
-  hipStream_t st = ex->side[0];
-  const uint32_t nmul = t + 2 * lK + 4, npair = 4 + lM;
-  Carve c;
-  size_t o_pf = c.take<uint8_t>(len), o_C = c.take<uint8_t>(384), o_m = c.take<uint8_t>(32);
-  size_t o_blk = c.take<g1_aff>(t), o_Lg1 = c.take<g1_aff>(lK), o_Rg1 = c.take<g1_aff>(lK), o_Al = c.take<g1_aff>(1);
-  size_t o_D = c.take<g1_aff>(lK), o_W = c.take<g1_aff>(lM), o_Lgt = c.take<fp12>(lK), o_Rgt = c.take<fp12>(lK);
-  size_t o_Cgt = c.take<fp12>(1), o_vl = c.take<g2_aff>(1), o_piv = c.take<g2_aff>(1), o_ys = c.take<fe>(lK);
-  size_t o_mi = c.take<fe>(1), o_r = c.take<fe>(t), o_x = c.take<fe>(lK), o_xi = c.take<fe>(lK), o_ms = c.take<fe>(nmul);
-  size_t o_fz = c.take<fe>(1), o_gts = c.take<fe>(2 * lK), o_mb = c.take<g1_aff>(nmul), o_mo = c.take<g1_aff>(nmul);
-  size_t o_fzg2 = c.take<g2_aff>(1), o_gtb = c.take<fp12>(2 * lK), o_gto = c.take<fp12>(2 * lK + 1);
-  size_t o_Cg1 = c.take<g1_aff>(1), o_bA = c.take<g1_aff>(1), o_pp = c.take<g1_aff>(npair), o_pq = c.take<g2_aff>(npair);
-  size_t o_F = c.take<fp12>(npair), o_E = c.take<fp12>(3), o_fl = c.take<int>(1);
-  // the three product trees below run one after another and share one counter area
-  if (int rc = ensure_cnt(ex, tree_counters(npair > 2 * lK + 1 ? npair : 2 * lK + 1), st)) return rc;
+  hipStream_t st = pp->ex->side[0];
   void *d = nullptr;
-  CK(hipMalloc(&d, c.off));
-  VCtx x;
-  x.t = t; x.lK = lK; x.lM = lM; x.L = pp->L;
-  x.N = pp->N; x.i = i; x.j = j; x.a = a; x.lo = lo;
-  x.proof = at<uint8_t>(d, o_pf); x.Cb = at<uint8_t>(d, o_C); x.mib = at<uint8_t>(d, o_m);
-  x.mpath = x.proof + (len - 32ull * pp->L);
-  x.blk = at<g1_aff>(d, o_blk); x.Lg1 = at<g1_aff>(d, o_Lg1); x.Rg1 = at<g1_aff>(d, o_Rg1); x.Al = at<g1_aff>(d, o_Al);
-  x.Dsib = at<g1_aff>(d, o_D); x.Wp = at<g1_aff>(d, o_W); x.Lgt = at<fp12>(d, o_Lgt); x.Rgt = at<fp12>(d, o_Rgt);
-  x.C = at<fp12>(d, o_Cgt); x.vl = at<g2_aff>(d, o_vl); x.piv = at<g2_aff>(d, o_piv); x.ysib = at<fe>(d, o_ys);
-  x.mi = at<fe>(d, o_mi); x.r = at<fe>(d, o_r); x.x = at<fe>(d, o_x); x.xinv = at<fe>(d, o_xi); x.ms = at<fe>(d, o_ms);
-  x.fz = at<fe>(d, o_fz); x.gts = at<fe>(d, o_gts); x.mb = at<g1_aff>(d, o_mb); x.mo = at<g1_aff>(d, o_mo);
-  x.fzg2 = at<g2_aff>(d, o_fzg2); x.gtb = at<fp12>(d, o_gtb); x.gto = at<fp12>(d, o_gto);
-  x.Cg1 = at<g1_aff>(d, o_Cg1); x.bA = at<g1_aff>(d, o_bA); x.pp = at<g1_aff>(d, o_pp); x.pq = at<g2_aff>(d, o_pq);
-  x.F = at<fp12>(d, o_F); x.E = at<fp12>(d, o_E); x.g1beta = pp->g1beta; x.vk = pp->vk; x.flags = at<int>(d, o_fl);
-  int flags = 0;
-  hipError_t e = hipMemcpyAsync(at<void>(d, o_pf), proof, len, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(at<void>(d, o_C), C, 384, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(at<void>(d, o_m), m_i, 32, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemsetAsync(x.flags, 0, sizeof(int), st);
-  if (e == hipSuccess) {
-    kv::decode(x, st);
-    kv::transcript(x, st);
-    klw::g1_mul(x.mb, 0, x.ms, nmul, x.mo, st);
-    klw::g2_mul(pp->g2gen, 1, x.fz, 1, x.fzg2, st);
-    ks::gt_pow(x.gtb, x.gts, 2 * lK, x.gto, st);
-    kv::assemble(x, st);
-    ks::f12_reduce(x.gto, 1, 2 * lK + 1, 2 * lK + 1, ex->cnt, st);
-    ks::miller(x.pp, 1, x.pq, 1, npair, x.F, st);
-    ks::f12_reduce(x.F + 1, 1, 2, 2, ex->cnt, st);
-    ks::f12_reduce(x.F + 3, 1, npair - 3, npair - 3, ex->cnt, st);
-    ks::final_exp(x.F, 1, 1, x.E, nullptr, 1, st);
-    ks::final_exp(x.F + 1, 1, 1, x.E + 1, nullptr, 1, st);
-    ks::final_exp(x.F + 3, 1, 1, x.E + 2, nullptr, 1, st);
-    kv::compare(x, st);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipMemcpyAsync(&flags, x.flags, sizeof(int), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  hipFree(d);
-  if (e != hipSuccess) {
-    ex->cnt_dirty = true;  // the product trees may have stopped half way
-    return hip_fail(e, "vc_verify");
-  }
-  if (flags & VFLAG_BAD_INPUT) return VC_EINVAL;
-  if (flags & VFLAG_BAD_PROOF) return 0;
-  return (flags & VFLAG_ACCEPT) ? 1 : 0;
+  CK(hipMalloc(&d, len + 384 + 32));
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } free_d{d};
+  uint8_t *dp = static_cast<uint8_t *>(d), *dC = dp + len, *dm = dC + 384;
+  CK(hipMemcpyAsync(dp, proof, len, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(dC, C, 384, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(dm, m_i, 32, hipMemcpyHostToDevice, st));
+  const uint8_t *pf[1] = {dp}, *mi[1] = {dm};
+  int v = 0;
+  if (int rc = verify_many(pp, dC, b, 1, &i, pf, mi, st, &v)) return rc;
+  return v;
 }
 
 // ------------------------------------------------------------------ profiling C ABI
@@ -1440,16 +1478,23 @@ VC_API int vc_verify_all(const vc_params *pp, const uint8_t C[384], uint32_t b, 
   }
   std::sort(single.begin(), single.end());
   single.erase(std::unique(single.begin(), single.end()), single.end());
-  std::vector<uint8_t> pf(y.len_full);
-  uint8_t mi[32];
-  for (uint64_t i : single) {
-    uint64_t li = (i / ((uint64_t)y.b * M) == y.nb - 1) ? y.len_last : y.len_full;
-    CK(hipMemcpy(pf.data(), c.proofs + proof_offset(y, i), li, hipMemcpyDeviceToHost));
-    CK(hipMemcpy(mi, c.m + 32 * i, 32, hipMemcpyDeviceToHost));
-    if (n_single) (*n_single)++;
-    int v = vc_verify(pp, C, N, b, i, mi, pf.data(), li);
-    if (v < 0) return v;
-    if (v != 1) return 0;
+  // (device copy of C for the one-proof checks)
+  std::vector<const uint8_t *> pfs(single.size()), mis(single.size());
+  for (size_t q = 0; q < single.size(); q++) {
+    pfs[q] = c.proofs + proof_offset(y, single[q]);
+    mis[q] = c.m + 32 * single[q];
+  }
+  std::vector<int> v(single.size(), 0);
+  const uint32_t chunk = 4096;  // bounded working memory per pass
+  for (size_t q0 = 0; q0 < single.size(); q0 += chunk) {
+    uint32_t nq = (uint32_t)std::min<size_t>(chunk, single.size() - q0);
+    if (int rc = verify_many(pp, c.Cb, b, nq, single.data() + q0, pfs.data() + q0, mis.data() + q0, st, v.data() + q0))
+      return rc;
+    if (n_single) *n_single += nq;
+    for (uint32_t q = 0; q < nq; q++) {
+      if (v[q0 + q] < 0) return v[q0 + q];
+      if (v[q0 + q] != 1) return 0;
+    }
   }
   return 1;
 }

@@ -11,7 +11,7 @@
 #define VFLAG_ACCEPT 4
 
 struct VCtx {
-  uint32_t t, lK, lM, L;
+  uint32_t t, lK, lM, L, nmul;  // nmul: stride of the multiplication jobs (>= t + 2 lK + 4)
   uint64_t N, i, j, a, lo;
   const uint8_t *proof, *Cb, *mib, *mpath;
   // decoded proof and inputs
@@ -23,7 +23,7 @@ struct VCtx {
   fe *r, *x, *xinv, *ms, *fz, *gts;
   g1_aff *mb, *mo;     // G1 multiplication bases and results
   g2_aff *fzg2;        // f_v(z) g2
-  fp12 *gtb, *gto;     // G_T exponentiation bases and results (+ C last)
+  fp12 *gtb, *gtp, *gto;  // G_T exponentiation bases, powers, and the product's inputs (powers + C last)
   // assembled
   g1_aff *Cg1, *bA, *pp;
   g2_aff *pq;
@@ -87,9 +87,10 @@ void segsum(const VACtx &c, hipStream_t st);
 void check(const VACtx &c, hipStream_t st);
 }  // namespace kva
 
+// kernels over n proofs at once, cs: device array of n contexts (tmax: largest t)
 namespace kv {
-void decode(const VCtx &c, hipStream_t st);
-void transcript(const VCtx &c, hipStream_t st);
-void assemble(const VCtx &c, hipStream_t st);
-void compare(const VCtx &c, hipStream_t st);
+void decode(const VCtx *cs, uint32_t n, uint32_t tmax, uint32_t lK, uint32_t lM, hipStream_t st);
+void transcript(const VCtx *cs, uint32_t n, hipStream_t st);
+void assemble(const VCtx *cs, uint32_t n, hipStream_t st);
+void compare(const VCtx *cs, uint32_t n, hipStream_t st);
 }  // namespace kv
