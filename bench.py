@@ -334,9 +334,9 @@ def serving(V, torch, n_req=40, rate=8.0, seed=7, setups=SERVE_SETUPS, budget=64
 
 
 def verify_all_timing(V, torch, L=16, b=256, seed=2, reps=3):
-    """Verification of all N proofs of the N = 2^16, b = 256 workload: device serialization of
-    the N proofs, then vc_verify_all (best of reps each), and the one-proof verifier on a few
-    proofs for comparison."""
+    """Verification of all N proofs of the N = 2^L workload with batch size b (32-bit entries,
+    seed 2): device serialization of the N proofs, then vc_verify_all (best of reps each), and
+    the one-proof verifier on a few proofs for comparison."""
     import numpy as np
     from paper_2601_03031_amd import inputs as I
     limbs = I.entries(1 << L, seed, 32)
@@ -485,7 +485,7 @@ def main():
         extra["b_sweep_all_proofs_ms"] = sweep
         extra["batched_64_jobs"] = batched_jobs(V, torch)
         extra["serving"] = serving(V, torch)
-        extra["verify_all_n2^16_b256"] = verify_all_timing(V, torch)
+        extra["verify_all_n2^16"] = {"b256": verify_all_timing(V, torch, b=256), "b1": verify_all_timing(V, torch, b=1)}
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(L, b, bits, seed)
