@@ -371,6 +371,35 @@ def verify_all_timing(V, torch, L=16, b=256, seed=2, reps=3):
             "checked_alone": ns, "one_proof_verify_ms": round(statistics.median(one), 3)}
 
 
+def subarray_timing(V, torch, cases=((16, 256, 32, 2), (20, 400, 256, 3)), reps=3):
+    """OpenAll for sub-arrays (Step 1 alone) against the full open-all on the same commitment,
+    best of reps each."""
+    import numpy as np
+    from paper_2601_03031_amd import inputs as I
+    out = {}
+    for L, b, bits, seed in cases:
+        limbs = I.entries(1 << L, seed, bits)
+        if bits == 32:
+            m = torch.from_numpy(limbs[:, 0].astype(np.uint32).view(np.int32).copy()).cuda()
+        else:
+            m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+        pp = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
+        cm = V.vc_commit(pp, m, bits)
+        st = torch.cuda.current_stream()
+        times = {}
+        for name, fn in (("subarrays_ms", V.vc_open_subarrays), ("open_all_ms", V.vc_open_all)):
+            best = None
+            for _ in range(reps + 1):  # the first call sizes the workspace
+                t0 = time.perf_counter()
+                pr = fn(pp, cm, b, st)
+                ms = 1e3 * (time.perf_counter() - t0)
+                del pr
+                best = ms if best is None or ms < best else best
+            times[name] = round(best, 3)
+        out["n2^%d_b%d" % (L, b)] = times
+    return out
+
+
 def cpu_baseline(L, b, bits, seed):
     import oracle as O
     log("cpu baseline (oracle) L=%d b=%d" % (L, b))
@@ -485,6 +514,7 @@ def main():
         extra["b_sweep_all_proofs_ms"] = sweep
         extra["batched_64_jobs"] = batched_jobs(V, torch)
         extra["serving"] = serving(V, torch)
+        extra["subarrays"] = subarray_timing(V, torch)
         extra["verify_all_n2^16"] = {"b256": verify_all_timing(V, torch, b=256), "b1": verify_all_timing(V, torch, b=1)}
     cpu = None
     if not a.no_cpu_baseline:

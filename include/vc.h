@@ -146,6 +146,26 @@ int vc_proofs_serialize(const vc_proofs *pr, void *dst, uint64_t cap, uint64_t *
 int vc_verify_all(const vc_params *pp, const uint8_t C[384], uint32_t b, const void *m, const void *proofs,
                   uint64_t len, const uint8_t seed[32], uint64_t *n_single);
 
+/* OpenAll for consecutive sub-arrays (section 4.3): Step 1 alone, the FC batch proofs that
+ * open every subvector commitment C_j (j < K), each proving that sub-array m_j (entries
+ * [j M, (j + 1) M)) is the j-th segment of the committed vector.  The bundle holds no Merkle
+ * tree, y-tree, D-tree or W: vc_proof_get, vc_proofs_serialize and the Step 2 exports
+ * (merkle, rho, y, D, W) return VC_EINVAL on it; vc_subarray_proof_get and the FC exports
+ * work.  Otherwise as vc_open_all. */
+int vc_open_subarrays(const vc_params *pp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out);
+/* Length of a sub-array proof whose block holds t subvector commitments: the block, the FC
+ * proof (L_j, R_j, A_l, v_l, pi_v) in the wire format of vc_proof_get, which it prefixes. */
+uint64_t vc_subarray_proof_len(uint32_t log_n, uint32_t t);
+/* The sub-array proof of subvector j (< K) into buf (cap bytes), *len its length; from a
+ * vc_open_subarrays or a vc_open_all bundle (then it is the first part of proof j M). */
+int vc_subarray_proof_get(const vc_proofs *pr, uint64_t j, uint8_t *buf, size_t cap, size_t *len);
+/* Sub-array verification: recomputes PC.Commit of m_j (M entries of 32 little-endian bytes,
+ * host), requires it to be entry j of the proof's block, and checks the block with FC.BVerify
+ * and the faster verifier (section 3).  1 accept, 0 reject, VC_EINVAL for malformed inputs
+ * (lengths, C, an entry >= r). */
+int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_t b, uint64_t j, const uint8_t *m_j,
+                       const uint8_t *proof, size_t len);
+
 /* Serialized length of a proof whose block holds t subvector commitments. */
 uint64_t vc_proof_len(uint32_t log_n, uint32_t t);
 

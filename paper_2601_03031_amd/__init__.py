@@ -66,6 +66,11 @@ def lib():
         L.vc_server_wait.argtypes = [vp, u64, C.POINTER(vp), C.POINTER(C.c_double)]
         L.vc_server_free.argtypes = [vp]
         L.vc_proofs_serialize.argtypes = [vp, vp, u64, C.POINTER(u64)]
+        L.vc_open_subarrays.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
+        L.vc_subarray_proof_len.restype = u64
+        L.vc_subarray_proof_len.argtypes = [u32, u32]
+        L.vc_subarray_proof_get.argtypes = [vp, u64, vp, sz, C.POINTER(sz)]
+        L.vc_verify_subarray.argtypes = [vp, u8p, u32, u64, u8p, u8p, sz]
         L.vc_verify_all.argtypes = [vp, u8p, u32, vp, vp, u64, u8p, C.POINTER(u64)]
         L.vc_open_all_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), u32, C.POINTER(vp),
                                         C.POINTER(vp)]
@@ -251,6 +256,25 @@ def vc_server_create(device: int = 0, nexec: int = 16, nstreams: int = 1, hbm_bu
     out = C.c_void_p()
     _check(lib().vc_server_create(device, nexec, nstreams, hbm_budget, C.byref(out)), "vc_server_create")
     return Server(out, device)
+
+
+def vc_open_subarrays(pp: Params, cm: Commitment, b: int, stream=None) -> Proofs:
+    out = C.c_void_p()
+    _check(lib().vc_open_subarrays(pp.ptr, cm.ptr, b, _stream_ptr(stream), C.byref(out)), "vc_open_subarrays")
+    return Proofs(out, pp, b)
+
+
+def vc_subarray_proof_get(pr: Proofs, j: int) -> bytes:
+    cap = int(lib().vc_subarray_proof_len(pr.pp.log_n, pr.b))
+    buf = C.create_string_buffer(cap)
+    n = C.c_size_t(0)
+    _check(lib().vc_subarray_proof_get(pr.ptr, j, buf, cap, C.byref(n)), "vc_subarray_proof_get")
+    return buf.raw[:n.value]
+
+
+def vc_verify_subarray(pp: Params, C_bytes: bytes, b: int, j: int, m_j: bytes, proof: bytes) -> int:
+    """m_j: the M entries of sub-array j, 32 little-endian bytes each."""
+    return _check(lib().vc_verify_subarray(pp.ptr, C_bytes, b, j, m_j, proof, len(proof)), "vc_verify_subarray")
 
 
 def vc_proofs_serialize(pr: Proofs):

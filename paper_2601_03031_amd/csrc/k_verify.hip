@@ -138,6 +138,18 @@ __global__ void __launch_bounds__(TPB) kv_decode(const VCtx *cs) {
     if (id == 0) ok = g1_decompress(q, *c.Al);
     else if (id == 1) ok = g2_decompress(q + 32, *c.vl);
     else ok = g2_decompress(q + 96, *c.piv);
+  } else if (c.fc_only && (id -= 3) < 2 * l + lM + 2 && id != 2 * l + lM) {
+    // sub-array proof: no Step 2 items and no entry
+    if (id < 2 * l) {
+      if (id % 2 == 0) c.Dsib[id / 2] = g1_aff{fe_zero(), fe_zero()};
+      else c.ysib[id / 2] = fe_zero();
+    } else if (id < 2 * l + lM) {
+      c.Wp[id - 2 * l] = g1_aff{fe_zero(), fe_zero()};
+    } else {
+      *c.mi = fe_zero();
+    }
+  } else if (c.fc_only) {
+    if (!gt_decode(c.Cb, *c.C)) atomicOr(c.flags, VFLAG_BAD_INPUT);
   } else if ((id -= 3) < 2 * l) {
     const uint8_t *q = pf + 32 * t + (uint64_t)l * (2 * 384 + 2 * 32) + 160 + 64 * (id / 2);
     if (id % 2 == 0) {
@@ -231,6 +243,9 @@ __global__ void __launch_bounds__(256) kv_transcript(const VCtx *cs) {
     }
     s_z = z;
     *c.fz = fz;
+  } else if (tid == 64 && c.fc_only) {
+    s_rho = fe_zero();
+    s_ystar = fe_zero();
   } else if (tid == 64) {
     // Merkle path of leaf i = SHA-256(0x00 || m_i || C_j) up to the root
     const g1_aff &Cj = c.blk[c.j - c.lo];
@@ -366,6 +381,10 @@ __global__ void __launch_bounds__(64) kv_compare(const VCtx *cs, uint32_t n) {
   };
   bool ok = eq12(c.E[0], c.gto[0]) && eq12(c.E[1], one) && eq12(c.E[2], one) && fe_eq(c.bA->x, c.Cg1->x) &&
             fe_eq(c.bA->y, c.Cg1->y);
+  if (c.cj_expect) {
+    const g1_aff &cj = c.blk[c.j - c.lo];
+    ok = ok && fe_eq(cj.x, c.cj_expect->x) && fe_eq(cj.y, c.cj_expect->y);
+  }
   if (ok) atomicOr(c.flags, VFLAG_ACCEPT);
 }
 

@@ -201,6 +201,7 @@ struct vc_proofs {
   uint64_t nb;
   void *mem = nullptr;  // the proof bundle
   size_t o_Cj, o_C, o_Lgt, o_Rgt, o_Lg1, o_Rg1, o_X, o_Al, o_vl, o_piv, o_tree, o_rho, o_Y, o_D, o_W;
+  bool step2 = true;    // false: sub-array proofs only (Step 1), no Merkle tree, y-tree, D-tree or W
 };
 
 // At least n zeroed arrival counters.  New ones are cleared on the call's stream `st`, ahead of
@@ -440,8 +441,10 @@ VC_API void vc_commitment_free(vc_commitment *cm) {
 // ------------------------------------------------------------------ open-all
 // With `footprint` set: only the device bytes the call would hold (proof bundle, workspace,
 // counters) are stored there; nothing is allocated or launched, and cm, ex, out may be NULL.
+// With step2 false only Step 1 runs: the FC batch proofs that open every C_j (the sub-array
+// form of OpenAll, section 4.3).
 static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t b, vc_exec *ex, hipStream_t st,
-                         vc_proofs **out, uint64_t *footprint = nullptr) {
+                         vc_proofs **out, uint64_t *footprint = nullptr, bool step2 = true) {
   if (!cpp || b < 1 || b > cpp->K) return VC_EINVAL;
   if (!footprint && (!cm || !out || !ex || cm->pp != cpp || ex->device != cpp->device)) return VC_EINVAL;
   const vc_params *pp = cpp;
@@ -457,6 +460,8 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   pr->pp = pp;
   pr->b = b;
   pr->nb = nb;
+  pr->step2 = step2;
+  const uint64_t with2 = step2 ? 1 : 0;  // Step 2 arrays are left out of a sub-array bundle
   Carve c;
   pr->o_Cj = c.take<g1_aff>(K);
   pr->o_C = c.take<fp12>(1);
@@ -468,11 +473,11 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   pr->o_Al = c.take<g1_aff>(nb);
   pr->o_vl = c.take<g2_aff>(nb);
   pr->o_piv = c.take<g2_aff>(nb);
-  pr->o_tree = c.take<fe>(2 * N);
-  pr->o_rho = c.take<fe>(K);
-  pr->o_Y = c.take<fe>((2 * K - 1) * M);
-  pr->o_D = c.take<g1_aff>(2 * K - 1);
-  pr->o_W = c.take<g1_aff>(M - 1);
+  pr->o_tree = c.take<fe>(with2 * 2 * N);
+  pr->o_rho = c.take<fe>(with2 * K);
+  pr->o_Y = c.take<fe>(with2 * (2 * K - 1) * M);
+  pr->o_D = c.take<g1_aff>(with2 * (2 * K - 1));
+  pr->o_W = c.take<g1_aff>(with2 * (M - 1));
   // ---- scratch
   Carve t;
   size_t o_err = t.take<int>(1), o_A = t.take<g1_aff>(nb * K), o_V = t.take<g2_aff>(nb * K), o_B = t.take<fe>(nb * K);
@@ -482,7 +487,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   // quotient coefficients and the per-block partial sums of its MSM
   const bool kzg_split = 4 * nb * nq <= KZG_SPLIT_MAX;
   const uint64_t kzg_nslice = (nq + KZG_S - 1) / KZG_S, kzg_len = kzg_split ? 4 * nq : kzg_nslice;
-  size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(lM * (M / 2));
+  size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(with2 * lM * (M / 2));
   size_t o_dec = t.take<glv::Dec>(nb);
   // Step 1 arrays of alternate rounds, and the terms taken one round ahead (oa_terms.hpp)
   const bool ahead = lK >= 2 && nb * K <= AHEAD_MAX_PAIRS;
@@ -581,7 +586,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
   CK(hipMemcpyAsync(C, cm->C, sizeof(fp12), hipMemcpyDeviceToDevice, st));
-  CK(hipMemsetAsync(tree, 0, 32, st));  // heap node 0 is unused
+  if (step2) CK(hipMemsetAsync(tree, 0, 32, st));  // heap node 0 is unused
 
   // ---- Step 2 runs on side stream 1, concurrently with Step 1: Merkle tree (Fiat-Shamir),
   // randomized folding tree, HyperEval on g* (Protocol 1 Step 2 and its Sub-protocol).  Its
@@ -749,7 +754,8 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
       if (int rc2 = stream_wait(ex, 12, sf, st)) return rc2;
     }
     if (j == std::min<uint32_t>(2, lK))
-      if (int rc2 = launch_step2()) return rc2;
+      if (step2)
+        if (int rc2 = launch_step2()) return rc2;
   }
   if (ahead)
     if (int rc2 = stream_wait(ex, 11, sg, st)) return rc2;
@@ -783,6 +789,12 @@ VC_API int vc_open_all(const vc_params *pp, const vc_commitment *cm, uint32_t b,
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pp) return VC_EINVAL;
   return open_all_impl(pp, cm, b, pp->ex, (hipStream_t)stream, out);
+}
+
+VC_API int vc_open_subarrays(const vc_params *pp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pp) return VC_EINVAL;
+  return open_all_impl(pp, cm, b, pp->ex, (hipStream_t)stream, out, nullptr, false);
 }
 
 VC_API int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t b, vc_exec *ex, void *stream,
@@ -1058,13 +1070,61 @@ void compress_g2(uint8_t *o, const uint8_t *xy) {
 
 }  // namespace
 
+VC_API uint64_t vc_subarray_proof_len(uint32_t log_n, uint32_t t) {
+  uint32_t lK = log_n / 2;
+  return 32ull * t + lK * (2ull * 384 + 2 * 32) + 32 + 64 + 64;
+}
+
+VC_API int vc_subarray_proof_get(const vc_proofs *pr, uint64_t j, uint8_t *buf, size_t cap, size_t *len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pr || !buf || !len) return VC_EINVAL;
+  const vc_params *pp = pr->pp;
+  const uint64_t K = pp->K;
+  const uint32_t lK = pp->lK;
+  if (j >= K) return VC_EINVAL;
+  uint64_t k = j / pr->b, lo = k * pr->b, hi = lo + pr->b < K ? lo + pr->b : K;
+  uint64_t need = vc_subarray_proof_len(pp->L, (uint32_t)(hi - lo));
+  if (cap < need) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  std::vector<uint64_t> idx;
+  std::vector<int> mode;
+  for (uint64_t q = lo; q < hi; q++) push_run(idx, mode, pr->o_Cj + q * 64, 2, 0);
+  for (uint32_t r = 0; r < lK; r++) {
+    uint64_t s = k * lK + r;
+    push_run(idx, mode, pr->o_Lgt + s * 384, 12, 0);
+    push_run(idx, mode, pr->o_Lg1 + s * 64, 2, 0);
+    push_run(idx, mode, pr->o_Rgt + s * 384, 12, 0);
+    push_run(idx, mode, pr->o_Rg1 + s * 64, 2, 0);
+  }
+  push_run(idx, mode, pr->o_Al + k * 64, 2, 0);
+  push_run(idx, mode, pr->o_vl + k * 128, 4, 0);
+  push_run(idx, mode, pr->o_piv + k * 128, 4, 0);
+  std::vector<uint8_t> g;
+  int rc = gather(pr->mem, idx, mode, g);
+  if (rc) return rc;
+  const uint8_t *s = g.data();
+  uint8_t *q = buf;
+  for (uint64_t t = lo; t < hi; t++, s += 64, q += 32) compress_g1(q, s);
+  for (uint32_t r = 0; r < lK; r++) {
+    memcpy(q, s, 384); q += 384; s += 384;
+    compress_g1(q, s); q += 32; s += 64;
+    memcpy(q, s, 384); q += 384; s += 384;
+    compress_g1(q, s); q += 32; s += 64;
+  }
+  compress_g1(q, s); q += 32; s += 64;
+  compress_g2(q, s); q += 64; s += 128;
+  compress_g2(q, s); q += 64;
+  *len = (size_t)(q - buf);
+  return *len == need ? VC_OK : VC_EDEVICE;
+}
+
 VC_API int vc_proof_get(const vc_proofs *pr, uint64_t i, uint8_t *buf, size_t cap, size_t *len) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pr || !buf || !len) return VC_EINVAL;
   const vc_params *pp = pr->pp;
   const uint64_t N = pp->N, K = pp->K, M = pp->M;
   const uint32_t lK = pp->lK, lM = pp->lM, L = pp->L;
-  if (i >= N) return VC_EINVAL;
+  if (i >= N || !pr->step2) return VC_EINVAL;
   uint64_t j = i / M, a = i % M, k = j / pr->b;
   uint64_t lo = k * pr->b, hi = lo + pr->b < K ? lo + pr->b : K;
   uint64_t need = vc_proof_len(L, (uint32_t)(hi - lo));
@@ -1171,6 +1231,7 @@ VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst
   const uint32_t lK = pp->lK;
   CK(hipSetDevice(pp->device));
   if (what <= 2 && k >= pr->nb) return VC_EINVAL;
+  if (what >= 3 && !pr->step2) return VC_EINVAL;  // a sub-array bundle has no Step 2 arrays
   std::vector<uint64_t> idx;
   std::vector<int> mode;
   switch (what) {
@@ -1204,8 +1265,10 @@ VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst
 // PST check at Bin(a).  Proof q is entry idx[q]; its bytes (vc_proof_len(L, t) of them) are at
 // the device address pf[q] and its entry (32 bytes, little-endian) at mi[q]; Cb: the commitment
 // bytes on the device.  verdict[q]: 1 accept, 0 reject, VC_EINVAL malformed C or entry.
+// fc_only: sub-array proofs (block and FC proof), the block's entry j checked against cj_expect.
 static int verify_many(const vc_params *pp, const uint8_t *Cb, uint32_t b, uint32_t n, const uint64_t *idx,
-                       const uint8_t *const *pf, const uint8_t *const *mi, hipStream_t st, int *verdict) {
+                       const uint8_t *const *pf, const uint8_t *const *mi, hipStream_t st, int *verdict,
+                       bool fc_only = false, const g1_aff *cj_expect = nullptr) {
   if (n == 0) return VC_OK;
   const uint64_t K = pp->K, M = pp->M;
   const uint32_t lK = pp->lK, lM = pp->lM, L = pp->L;
@@ -1252,6 +1315,9 @@ static int verify_many(const vc_params *pp, const uint8_t *Cb, uint32_t b, uint3
     x.gto = at<fp12>(d, o_gto) + q * (2 * lK + 1); x.Cg1 = at<g1_aff>(d, o_Cg1) + q; x.bA = at<g1_aff>(d, o_bA) + q;
     x.pp = at<g1_aff>(d, o_pp) + q * npair; x.pq = at<g2_aff>(d, o_pq) + q * npair; x.F = at<fp12>(d, o_F) + q * npair;
     x.E = at<fp12>(d, o_E) + 3 * q; x.g1beta = pp->g1beta; x.vk = pp->vk; x.flags = at<int>(d, o_fl) + q;
+    x.fc_only = fc_only ? 1 : 0;
+    x.cj_expect = cj_expect;
+    if (fc_only) x.mpath = nullptr;
   }
   const VCtx *cs = at<VCtx>(d, o_ctx);
   fp12 *F = at<fp12>(d, o_F), *E = at<fp12>(d, o_E);
@@ -1352,6 +1418,48 @@ VC_API int vc_profile_read(char *buf, size_t cap) {
 
 // ------------------------------------------------------------------ diagnostics
 // Runs one base-field operation on n pairs of canonical 32-byte little-endian inputs
+// Sub-array verification (section 4.3): the commitment of m_j is recomputed (PC.Commit, the
+// MSM of the commit) and must be entry j of the proof's block, whose FC proof must hold.
+VC_API int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_t b, uint64_t j, const uint8_t *m_j,
+                              const uint8_t *proof, size_t len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pp || !C || !m_j || !proof || j >= pp->K || b < 1 || b > pp->K) return VC_EINVAL;
+  const uint64_t K = pp->K, M = pp->M;
+  const uint64_t k = j / b, lo = k * b, hi = lo + b < K ? lo + b : K;
+  if (len != vc_subarray_proof_len(pp->L, (uint32_t)(hi - lo))) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  hipStream_t st = pp->ex->side[0];
+  uint32_t S = (uint32_t)(8192 / NWIN);
+  if (S > M) S = (uint32_t)M;
+  const uint64_t nslice = (M + S - 1) / S;
+  Carve w;
+  size_t o_pf = w.take<uint8_t>(len), o_C = w.take<uint8_t>(384), o_m = w.take<fe>(M), o_err = w.take<int>(1),
+         o_part = w.take<g1_jac>(nslice), o_cj = w.take<g1_aff>(1);
+  void *d = nullptr;
+  CK(hipMalloc(&d, w.off));
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } free_d{d};
+  int *err = at<int>(d, o_err);
+  CK(hipMemcpyAsync(at<void>(d, o_pf), proof, len, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(at<void>(d, o_C), C, 384, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(at<void>(d, o_m), m_j, M * 32, hipMemcpyHostToDevice, st));
+  CK(hipMemsetAsync(err, 0, sizeof(int), st));
+  kl::check_fr(at<fe>(d, o_m), M, err, st);
+  kl::msm_slices(at<fe>(d, o_m), 1, M, NWIN, S, pp->table, at<g1_jac>(d, o_part), st);
+  klw::sum_g1(at<g1_jac>(d, o_part), 1, nslice, at<g1_aff>(d, o_cj), st);
+  int herr = 0;
+  CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (herr & VC_ERRBIT_RANGE) return VC_EINVAL;
+  const uint64_t i = j * M;
+  const uint8_t *pf[1] = {at<uint8_t>(d, o_pf)}, *mi[1] = {at<uint8_t>(d, o_C)};  // (no entry is read)
+  int v = 0;
+  if (int rc = verify_many(pp, at<uint8_t>(d, o_C), b, 1, &i, pf, mi, st, &v, true, at<g1_aff>(d, o_cj))) return rc;
+  return v;
+}
+
 // ------------------------------------------------------------------ every proof at once
 static PLayout proof_layout(const vc_params *pp, uint32_t b) {
   PLayout y;
@@ -1373,7 +1481,7 @@ static uint64_t proof_offset(const PLayout &y, uint64_t i) {
 
 VC_API int vc_proofs_serialize(const vc_proofs *pr, void *dst, uint64_t cap, uint64_t *len) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
-  if (!pr || !len) return VC_EINVAL;
+  if (!pr || !len || !pr->step2) return VC_EINVAL;
   const vc_params *pp = pr->pp;
   PLayout y = proof_layout(pp, pr->b);
   *len = proofs_total(y);

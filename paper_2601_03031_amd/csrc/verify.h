@@ -31,6 +31,11 @@ struct VCtx {
   const g1_aff *g1beta;
   const g2_aff *vk;
   int *flags;
+  // sub-array proofs (block and FC proof only): the Step 2 items are left out (points at
+  // infinity, zero scalars, so their pairing checks hold trivially) and the block's entry j
+  // must equal cj_expect, the commitment recomputed from the sub-array
+  int fc_only;
+  const g1_aff *cj_expect;
 };
 
 // Layout of the N serialized proofs in index order: proofs of batch k (entries i with
