@@ -64,6 +64,11 @@ def lib():
         L.or_verify.argtypes = [vp, u8p, u64, u32, u64, u8p, u8p, C.c_size_t]
         L.or_naive_proof.argtypes = [vp, u8p, u64, u32, u64, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
         L.or_two_step_pst.argtypes = [vp, u64, C.c_void_p, C.c_void_p]
+        L.or_eval_proof_len.restype = u64
+        L.or_eval_proof_len.argtypes = [u32]
+        L.or_eval_proof.argtypes = [vp, u8p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.or_eval_verify.argtypes = [vp, u8p, u8p, u8p, C.c_size_t]
+        L.or_pst_commit.argtypes = [vp, u8p, C.c_void_p]
         L.or_two_step_fc.argtypes = [vp, u64]
         L.or_fc_roundtrip.argtypes = [vp, C.POINTER(C.c_uint64), u32, C.c_int]
         L.or_set_invariant_check.argtypes = [C.c_int]
@@ -269,6 +274,14 @@ class Commitment:
             lib().or_commit_free(self.h)
             self.h = None
 
+    def eval_proof(self, r: list) -> bytes:
+        """evaluation proof of f_m at r = [r_0, ..., r_{L-1}] (section 4.3)"""
+        cap = eval_proof_len(self.pp.log_n)
+        out, ln = _buf(cap), C.c_size_t(0)
+        if lib().or_eval_proof(self.h, b"".join(le32(x) for x in r), out, cap, C.byref(ln)) < 0:
+            raise ValueError("eval proof")
+        return out.raw[:ln.value]
+
     def two_step_pst(self, i: int):
         w, y = _buf(64 * self.pp.lM), _buf(32)
         ok = lib().or_two_step_pst(self.h, i, w, y)
@@ -316,6 +329,22 @@ class Opening:
 
 def verify(pp: Params, C_gt: bytes, b: int, i: int, m_i: int, proof: bytes) -> int:
     return int(lib().or_verify(pp.h, C_gt, pp.N, b, i, le32(m_i), proof, len(proof)))
+
+
+def eval_proof_len(log_n: int) -> int:
+    return int(lib().or_eval_proof_len(log_n))
+
+
+def eval_verify(pp: Params, C_gt: bytes, r: list, proof: bytes) -> int:
+    return int(lib().or_eval_verify(pp.h, C_gt, b"".join(le32(x) for x in r), proof, len(proof)))
+
+
+def pst_commit(pp: Params, table: list) -> bytes:
+    """PST commitment (x || y, 64 bytes) of a table of M values with ek_{lM}"""
+    out = _buf(64)
+    if lib().or_pst_commit(pp.h, b"".join(le32(x) for x in table), out) < 0:
+        raise ValueError("pst commit")
+    return out.raw
 
 
 def naive_proof(pp: Params, m_le: bytes, b: int, i: int) -> bytes:

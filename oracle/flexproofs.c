@@ -22,6 +22,7 @@
 #define DST_FC_X "FLEXPROOFS-V1-FC-X"
 #define DST_FC_Z "FLEXPROOFS-V1-FC-Z"
 #define DST_RHO "FLEXPROOFS-V1-RHO"
+#define DST_EVAL "FLEXPROOFS-V1-EVAL"
 
 typedef struct {
     uint32_t L, lK, lM;
@@ -348,12 +349,35 @@ static fe poly_eval(const fe *c, uint64_t deg, const fe *z) {
  * v_l = f_v(beta) g2, opened at z = H'(x_l, v_l): pi_v = q(beta) g2 with
  * q = (f_v - f_v(z)) / (X - z).
  */
+static int fc_bopen_b(fcproof *pr, const params *pp, const fp12 *C, const g1a *Avec, const fe *bvec,
+                      const g1a *claim);
+
 static int fc_bopen(fcproof *pr, const params *pp, const fp12 *C, const g1a *Avec,
                     const uint64_t *idx, uint32_t t) {
     uint64_t K = pp->K;
-    uint32_t l = pp->lK;
     pr->t = t;
     pr->first = idx[0];
+    fe *b = (fe *)calloc(K, sizeof(fe));
+    fe *r = (fe *)calloc(t, sizeof(fe));
+    g1a *yv = (g1a *)calloc(t, sizeof(g1a));
+    for (uint32_t i = 0; i < t; i++) yv[i] = Avec[idx[i]];
+    fc_batch_coeffs(r, C, idx, yv, t);
+    for (uint32_t i = 0; i < t; i++) fr_add(&b[idx[i]], &b[idx[i]], &r[i]);
+    /* the claim y = prod y_i^{r_i} (Eq. comy), for the invariant bookkeeping */
+    g1a Cg1;
+    memset(&Cg1, 0, sizeof Cg1);
+    if (g_check_invariant) g1_msm(&Cg1, yv, r, t);
+    int rc = fc_bopen_b(pr, pp, C, Avec, b, &Cg1);
+    free(b); free(r); free(yv);
+    return rc;
+}
+
+/* The rounds of FC.BOpen for a given dense b (Eq. folding) and the faster verifier's pi_v;
+ * claim: <A, b>, used only by the invariant bookkeeping */
+static int fc_bopen_b(fcproof *pr, const params *pp, const fp12 *C, const g1a *Avec, const fe *bvec,
+                      const g1a *claim) {
+    uint64_t K = pp->K;
+    uint32_t l = pp->lK;
     pr->Lgt = (fp12 *)calloc(l, sizeof(fp12));
     pr->Rgt = (fp12 *)calloc(l, sizeof(fp12));
     pr->Lg1 = (g1a *)calloc(l, sizeof(g1a));
@@ -363,16 +387,11 @@ static int fc_bopen(fcproof *pr, const params *pp, const fp12 *C, const g1a *Ave
     g2a *v = (g2a *)malloc(K * sizeof(g2a));
     fe *b = (fe *)calloc(K, sizeof(fe));
     memcpy(A, Avec, K * sizeof(g1a));
+    memcpy(b, bvec, K * sizeof(fe));
     for (uint64_t i = 0; i < K; i++) v[i] = pp->h[2 * i];
-    fe *r = (fe *)calloc(t, sizeof(fe));
-    g1a *yv = (g1a *)calloc(t, sizeof(g1a));
-    for (uint32_t i = 0; i < t; i++) yv[i] = Avec[idx[i]];
-    fc_batch_coeffs(r, C, idx, yv, t);
-    for (uint32_t i = 0; i < t; i++) fr_add(&b[idx[i]], &b[idx[i]], &r[i]);
     /* invariant bookkeeping: the verifier's running pair C_j = (C_gt, C_g1) */
     fp12 Cgt = *C;
-    g1a Cg1;
-    if (g_check_invariant) g1_msm(&Cg1, yv, r, t);
+    g1a Cg1 = *claim;
     fe *xinv = (fe *)calloc(l, sizeof(fe));
     int rc = 0;
     for (uint32_t j = 1; j <= l; j++) {
@@ -446,8 +465,6 @@ static int fc_bopen(fcproof *pr, const params *pp, const fp12 *C, const g1a *Ave
     free(A);
     free(v);
     free(b);
-    free(r);
-    free(yv);
     return rc;
 }
 
@@ -693,14 +710,28 @@ OR_API int or_proof(void *o, uint64_t i, uint8_t *out, size_t cap, size_t *len) 
 /* ============================ VC.Verify ============================ */
 /* FC.BVerify (section 3, Eq. comy, with the faster verifier and the O(|I| log mu)
  * closed form b_l = sum_i r_i prod_k (1/x_k)^{bit_{l-k}(a_i)}, Eq. b_l) */
+static int fc_bverify_b(const params *pp, const fp12 *C, const g1a *claim, const fe *bv, const uint64_t *bidx,
+                        uint64_t nterm, const fp12 *Lgt, const g1a *Lg1, const fp12 *Rgt, const g1a *Rg1,
+                        const g1a *Al, const g2a *vl, const g2a *piv);
+
 static int fc_bverify(const params *pp, const fp12 *C, const uint64_t *idx, const g1a *yv, uint32_t t,
                       const fp12 *Lgt, const g1a *Lg1, const fp12 *Rgt, const g1a *Rg1,
                       const g1a *Al, const g2a *vl, const g2a *piv) {
-    uint32_t l = pp->lK;
     fe *r = (fe *)calloc(t, sizeof(fe));
     fc_batch_coeffs(r, C, idx, yv, t);
     g1a Cg1;
     g1_msm(&Cg1, yv, r, t);
+    int ok = fc_bverify_b(pp, C, &Cg1, r, idx, t, Lgt, Lg1, Rgt, Rg1, Al, vl, piv);
+    free(r);
+    return ok;
+}
+
+/* the checks of FC.BVerify for b = sum_i bv[i] u_{bidx[i]} and the claimed <A, b> */
+static int fc_bverify_b(const params *pp, const fp12 *C, const g1a *claim, const fe *bv, const uint64_t *bidx,
+                        uint64_t nterm, const fp12 *Lgt, const g1a *Lg1, const fp12 *Rgt, const g1a *Rg1,
+                        const g1a *Al, const g2a *vl, const g2a *piv) {
+    uint32_t l = pp->lK;
+    g1a Cg1 = *claim;
     fp12 Cgt = *C;
     fe *x = (fe *)calloc(l, sizeof(fe)), *xinv = (fe *)calloc(l, sizeof(fe));
     int ok = 1;
@@ -724,10 +755,10 @@ static int fc_bverify(const params *pp, const fp12 *C, const uint64_t *idx, cons
     if (ok) {
         /* b_l by the closed form */
         fe bl = {{0, 0, 0, 0}};
-        for (uint32_t i = 0; i < t; i++) {
-            fe term = r[i];
+        for (uint64_t i = 0; i < nterm; i++) {
+            fe term = bv[i];
             for (uint32_t k = 1; k <= l; k++)
-                if ((idx[i] >> (l - k)) & 1) fr_mul(&term, &term, &xinv[k - 1]);
+                if ((bidx[i] >> (l - k)) & 1) fr_mul(&term, &term, &xinv[k - 1]);
             fr_add(&bl, &bl, &term);
         }
         /* v_l is checked by e(beta g1 - z g1, pi_v) = e(g1, v_l - f_v(z) g2) */
@@ -757,7 +788,7 @@ static int fc_bverify(const params *pp, const fp12 *C, const uint64_t *idx, cons
         g1_mul(&bA, Al, &bl);
         if (!fp12_eq(&e1, &Cgt) || !g1_eq(&bA, &Cg1)) ok = 0;
     }
-    free(r); free(x); free(xinv);
+    free(x); free(xinv);
     return ok;
 }
 
@@ -868,6 +899,208 @@ OR_API int or_verify(void *p, const uint8_t Cbytes[384], uint64_t n, uint32_t b,
     }
     free(blk); free(Lgt); free(Rgt); free(Lg1); free(Rg1); free(Dsib); free(Wp); free(ysib); free(idx);
     return result;
+}
+
+/* ================= evaluation proof at a point (section 4.3) ================= */
+/*
+ * f_m(r) with r = (r_{L-1}, ..., r_0): entry i = jM + a pairs its bit k with x_k, so the bits of
+ * j go with r_L = (r_{L-1}, ..., r_{lM}) and those of a with r_R = (r_{lM-1}, ..., r_0).
+ *   T_j = prod_{c<lK} (j_c r_{lM+c} + (1 - j_c)(1 - r_{lM+c})),  C_F = sum_j T_j C_j,
+ *   F = sum_j T_j f_j, whose table is g[a] = sum_j T_j m[jM + a], evaluated at r_R by PST.
+ * Reading: the paper gives the three steps but no transcript.  The FC statement is the one
+ * query vector T with claimed value C_F, batched (Eq. b) with
+ *   sigma_E = SHA-256(DST_EVAL || enc(C) || enc(r_{L-1}) || ... || enc(r_0) || enc(C_F)),
+ *   r_0 = H2F(DST_EVAL, sigma_E || 0),  b = r_0 T,  claimed <C, b> = r_0 C_F;
+ * rounds, x_j, z and pi_v as in FC.BOpen.  Proof bytes: C_F (32) || lK rounds (L_gt 384,
+ * L_g1 32, R_gt 384, R_g1 32) || A_l 32 || v_l 64 || pi_v 64 || y = F(r_R) (32, big-endian)
+ * || W_0 .. W_{lM-1} (32 each).
+ */
+static fe pst_eval_generic(g1a *Wout, const params *pp, const fe *table, const fe *z);
+
+static void eq_top(fe *T, const params *pp, const fe *r) {
+    fe one;
+    mf_one(&MR, &one);
+    for (uint64_t j = 0; j < pp->K; j++) {
+        fe acc = one;
+        for (uint32_t c = 0; c < pp->lK; c++) {
+            fe f;
+            if ((j >> c) & 1) f = r[pp->lM + c];
+            else fr_sub(&f, &one, &r[pp->lM + c]);
+            fr_mul(&acc, &acc, &f);
+        }
+        T[j] = acc;
+    }
+}
+
+static void eval_r0(fe *r0, const fp12 *C, const fe *r, uint32_t L, const g1a *CF) {
+    bytes b = {0};
+    bytes_put(&b, DST_EVAL, strlen(DST_EVAL));
+    put_gt(&b, C);
+    for (int k = (int)L - 1; k >= 0; k--) put_fr(&b, &r[k]);
+    put_g1(&b, CF);
+    uint8_t sigma[32];
+    sha256(sigma, b.p, b.n);
+    bytes_free(&b);
+    bytes m = {0};
+    bytes_put(&m, sigma, 32);
+    bytes_put_u64(&m, 0);
+    hash_to_fr(r0, DST_EVAL, m.p, m.n);
+    bytes_free(&m);
+}
+
+OR_API uint64_t or_eval_proof_len(uint32_t log_n) {
+    uint32_t lK = log_n / 2, lM = log_n - lK;
+    return 32 + 832ULL * lK + 160 + 32 + 32ULL * lM;
+}
+
+static int parse_point(fe *r, const uint8_t *r_le, uint32_t L) {
+    for (uint32_t k = 0; k < L; k++)
+        if (mf_from_le(&MR, &r[k], r_le + 32 * k)) return -1;
+    return 0;
+}
+
+OR_API int or_eval_proof(void *c, const uint8_t *r_le, uint8_t *out, size_t cap, size_t *len) {
+    commitment *cm = (commitment *)c;
+    const params *pp = cm->pp;
+    uint64_t K = pp->K, M = pp->M;
+    uint32_t L = pp->L, lK = pp->lK, lM = pp->lM;
+    if (cap < or_eval_proof_len(L)) return -1;
+    fe *r = (fe *)calloc(L, sizeof(fe));
+    if (parse_point(r, r_le, L)) { free(r); return -1; }
+    fe *T = (fe *)calloc(K, sizeof(fe)), *b = (fe *)calloc(K, sizeof(fe)), *g = (fe *)calloc(M, sizeof(fe));
+    eq_top(T, pp, r);
+    g1a CF, claim;
+    g1_msm(&CF, cm->Cj, T, K);
+    fe r0;
+    eval_r0(&r0, &cm->C, r, L, &CF);
+    for (uint64_t j = 0; j < K; j++) fr_mul(&b[j], &r0, &T[j]);
+    g1_mul(&claim, &CF, &r0);
+    fcproof pr;
+    memset(&pr, 0, sizeof pr);
+    int rc = fc_bopen_b(&pr, pp, &cm->C, cm->Cj, b, &claim);
+    if (rc == 0) {
+        for (uint64_t a = 0; a < M; a++) {
+            fe acc = {{0, 0, 0, 0}};
+            for (uint64_t j = 0; j < K; j++) {
+                fe t;
+                fr_mul(&t, &T[j], &cm->m[j * M + a]);
+                fr_add(&acc, &acc, &t);
+            }
+            g[a] = acc;
+        }
+        g1a *W = (g1a *)calloc(lM, sizeof(g1a));
+        fe y = pst_eval_generic(W, pp, g, r);  /* z_k = r_k for the low lM variables */
+        uint8_t *q = out;
+        g1_compress(q, &CF); q += 32;
+        for (uint32_t j = 0; j < lK; j++) {
+            fp12_to_bytes(q, &pr.Lgt[j]); q += 384;
+            g1_compress(q, &pr.Lg1[j]); q += 32;
+            fp12_to_bytes(q, &pr.Rgt[j]); q += 384;
+            g1_compress(q, &pr.Rg1[j]); q += 32;
+        }
+        g1_compress(q, &pr.A); q += 32;
+        g2_compress(q, &pr.v); q += 64;
+        g2_compress(q, &pr.piv); q += 64;
+        enc_fr(q, &y); q += 32;
+        for (uint32_t d = 0; d < lM; d++) { g1_compress(q, &W[d]); q += 32; }
+        *len = (size_t)(q - out);
+        free(W);
+    }
+    fcproof_free(&pr);
+    free(r); free(T); free(b); free(g);
+    return rc ? -1 : 0;
+}
+
+/* 1 accept, 0 reject, -1 malformed C or point */
+OR_API int or_eval_verify(void *p, const uint8_t Cbytes[384], const uint8_t *r_le, const uint8_t *proof, size_t len) {
+    const params *pp = (const params *)p;
+    uint64_t K = pp->K;
+    uint32_t L = pp->L, l = pp->lK, lM = pp->lM;
+    if (len != or_eval_proof_len(L)) return -1;
+    fp12 C;
+    if (fp12_from_bytes(&C, Cbytes)) return -1;
+    fe *r = (fe *)calloc(L, sizeof(fe));
+    if (parse_point(r, r_le, L)) { free(r); return -1; }
+    fp12 *Lgt = (fp12 *)calloc(l, sizeof(fp12)), *Rgt = (fp12 *)calloc(l, sizeof(fp12));
+    g1a *Lg1 = (g1a *)calloc(l, sizeof(g1a)), *Rg1 = (g1a *)calloc(l, sizeof(g1a)), *W = (g1a *)calloc(lM, sizeof(g1a));
+    g1a CF, Al;
+    g2a vl, piv;
+    fe y;
+    const uint8_t *q = proof;
+    int ok = g1_decompress(&CF, q) == 0;
+    q += 32;
+    for (uint32_t j = 0; j < l && ok; j++) {
+        if (fp12_from_bytes(&Lgt[j], q)) ok = 0;
+        q += 384;
+        if (g1_decompress(&Lg1[j], q)) ok = 0;
+        q += 32;
+        if (fp12_from_bytes(&Rgt[j], q)) ok = 0;
+        q += 384;
+        if (g1_decompress(&Rg1[j], q)) ok = 0;
+        q += 32;
+    }
+    if (ok && g1_decompress(&Al, q)) ok = 0;
+    q += 32;
+    if (ok && g2_decompress(&vl, q)) ok = 0;
+    q += 64;
+    if (ok && g2_decompress(&piv, q)) ok = 0;
+    q += 64;
+    if (ok && mf_from_be(&MR, &y, q)) ok = 0;
+    q += 32;
+    for (uint32_t d = 0; d < lM && ok; d++) { if (g1_decompress(&W[d], q)) ok = 0;
+        q += 32; }
+    if (ok) {
+        /* Part 1: C_F = <C, T(r_L)> by FC.BVerify on the dense query r_0 T */
+        fe *T = (fe *)calloc(K, sizeof(fe)), *b = (fe *)calloc(K, sizeof(fe));
+        uint64_t *bidx = (uint64_t *)calloc(K, sizeof(uint64_t));
+        eq_top(T, pp, r);
+        fe r0;
+        eval_r0(&r0, &C, r, L, &CF);
+        for (uint64_t j = 0; j < K; j++) { fr_mul(&b[j], &r0, &T[j]); bidx[j] = j; }
+        g1a claim;
+        g1_mul(&claim, &CF, &r0);
+        if (!fc_bverify_b(pp, &C, &claim, b, bidx, K, Lgt, Lg1, Rgt, Rg1, &Al, &vl, &piv)) ok = 0;
+        free(T); free(b); free(bidx);
+    }
+    if (ok) {
+        /* Part 2: PC.Verify at r_R: e(C_F - y g1, g2) = prod_d e(W_d, (s_var - r_var) g2) */
+        g1a *P = (g1a *)calloc(lM + 1, sizeof(g1a));
+        g2a *Q = (g2a *)calloc(lM + 1, sizeof(g2a));
+        g1a yg;
+        g1_mul(&yg, &G1_GEN, &y);
+        g1_neg(&yg, &yg);
+        g1_add(&P[0], &CF, &yg);
+        g2_neg(&Q[0], &G2_GEN);
+        for (uint32_t d = 0; d < lM; d++) {
+            uint32_t var = lM - 1 - d;
+            g2a rg;
+            g2_mul(&rg, &G2_GEN, &r[var]);
+            g2_neg(&rg, &rg);
+            P[d + 1] = W[d];
+            g2_add(&Q[d + 1], &pp->vk[var], &rg);
+        }
+        fp12 chk;
+        multi_pairing(&chk, P, Q, lM + 1);
+        if (!fp12_is_one(&chk)) ok = 0;
+        free(P); free(Q);
+    }
+    free(r); free(Lgt); free(Rgt); free(Lg1); free(Rg1); free(W);
+    return ok;
+}
+
+/* PST commitment of a table of M values (Montgomery limbs little-endian 32-byte canonical
+ * input) with ek_{lM}: an independent route to C_F for the tests */
+OR_API int or_pst_commit(void *p, const uint8_t *tab_le, uint8_t out[64]) {
+    const params *pp = (const params *)p;
+    uint64_t M = pp->M;
+    fe *t = (fe *)calloc(M, sizeof(fe));
+    for (uint64_t a = 0; a < M; a++)
+        if (mf_from_le(&MR, &t[a], tab_le + 32 * a)) { free(t); return -1; }
+    g1a o;
+    g1_msm(&o, pp->ek[pp->lM], t, M);
+    g1_to_bytes(out, &o);
+    free(t);
+    return 0;
 }
 
 /* ============================ naive openers ============================ */
