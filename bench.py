@@ -400,6 +400,33 @@ def subarray_timing(V, torch, cases=((16, 256, 32, 2), (20, 400, 256, 3)), reps=
     return out
 
 
+def eval_timing(V, torch, cases=((16, 32, 2), (20, 256, 3)), reps=3):
+    """Evaluation proof of f_m at a seeded random point (section 4.3), best of reps, after one
+    call that sizes the workspace."""
+    import random
+    import numpy as np
+    from paper_2601_03031_amd import inputs as I
+    out = {}
+    for L, bits, seed in cases:
+        limbs = I.entries(1 << L, seed, bits)
+        if bits == 32:
+            m = torch.from_numpy(limbs[:, 0].astype(np.uint32).view(np.int32).copy()).cuda()
+        else:
+            m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+        pp = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
+        cm = V.vc_commit(pp, m, bits)
+        rng = random.Random(seed)
+        r = [rng.randrange(I.R) for _ in range(L)]
+        best = None
+        for _ in range(reps + 1):
+            t0 = time.perf_counter()
+            V.vc_eval_proof(pp, cm, r)
+            ms = 1e3 * (time.perf_counter() - t0)
+            best = ms if best is None or ms < best else best
+        out["n2^%d" % L] = round(best, 3)
+    return out
+
+
 def cpu_baseline(L, b, bits, seed):
     import oracle as O
     log("cpu baseline (oracle) L=%d b=%d" % (L, b))
@@ -515,6 +542,7 @@ def main():
         extra["batched_64_jobs"] = batched_jobs(V, torch)
         extra["serving"] = serving(V, torch)
         extra["subarrays"] = subarray_timing(V, torch)
+        extra["eval_proof_ms"] = eval_timing(V, torch)
         extra["verify_all_n2^16"] = {"b256": verify_all_timing(V, torch, b=256), "b1": verify_all_timing(V, torch, b=1)}
     cpu = None
     if not a.no_cpu_baseline:

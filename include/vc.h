@@ -166,6 +166,19 @@ int vc_subarray_proof_get(const vc_proofs *pr, uint64_t j, uint8_t *buf, size_t 
 int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_t b, uint64_t j, const uint8_t *m_j,
                        const uint8_t *proof, size_t len);
 
+/* Evaluation proof of the committed vector's multilinear extension at a point (section 4.3,
+ * compatibility with multilinear zkSNARKs): r holds log N little-endian 32-byte field
+ * elements r_0 .. r_{log N - 1} (host), x_k paired with bit k of the index (Eq. f_m).  The
+ * proof: C_F = sum_j T_j(r_L) C_j (32 bytes), an FC proof that C_F = <C, T(r_L)> (the
+ * rounds, A_l, v_l, pi_v, as in vc_proof_get; the query batched with r_0 = H2F(EVAL,
+ * SHA-256(EVAL || C || r_{log N - 1} || ... || r_0 || C_F) || 0)), y = f_m(r) (32 bytes,
+ * big-endian) and the PST proof of F = sum_j T_j(r_L) f_j at r_R (log M commitments, the
+ * quotient of x_{log M - 1} first), vc_eval_proof_len(log N) bytes into out (cap bytes,
+ * host); *len its length.  VC_EINVAL for r_k >= r or a short buffer. */
+uint64_t vc_eval_proof_len(uint32_t log_n);
+int vc_eval_proof(const vc_params *pp, const vc_commitment *cm, const uint8_t *r, void *stream, uint8_t *out,
+                  size_t cap, size_t *len);
+
 /* Serialized length of a proof whose block holds t subvector commitments. */
 uint64_t vc_proof_len(uint32_t log_n, uint32_t t);
 

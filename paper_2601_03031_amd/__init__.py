@@ -67,6 +67,9 @@ def lib():
         L.vc_server_free.argtypes = [vp]
         L.vc_proofs_serialize.argtypes = [vp, vp, u64, C.POINTER(u64)]
         L.vc_open_subarrays.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
+        L.vc_eval_proof_len.restype = u64
+        L.vc_eval_proof_len.argtypes = [u32]
+        L.vc_eval_proof.argtypes = [vp, vp, u8p, vp, vp, sz, C.POINTER(sz)]
         L.vc_subarray_proof_len.restype = u64
         L.vc_subarray_proof_len.argtypes = [u32, u32]
         L.vc_subarray_proof_get.argtypes = [vp, u64, vp, sz, C.POINTER(sz)]
@@ -256,6 +259,18 @@ def vc_server_create(device: int = 0, nexec: int = 16, nstreams: int = 1, hbm_bu
     out = C.c_void_p()
     _check(lib().vc_server_create(device, nexec, nstreams, hbm_budget, C.byref(out)), "vc_server_create")
     return Server(out, device)
+
+
+def vc_eval_proof(pp: Params, cm: Commitment, r: list, stream=None) -> bytes:
+    """evaluation proof of f_m at r = [r_0, ..., r_{L-1}] (integers below the group order)"""
+    cap = int(lib().vc_eval_proof_len(pp.log_n))
+    buf = C.create_string_buffer(cap)
+    n = C.c_size_t(0)
+    rb = b"".join(int(x).to_bytes(32, "little") for x in r)
+    if len(r) != pp.log_n:
+        raise ValueError("the point has log N coordinates")
+    _check(lib().vc_eval_proof(pp.ptr, cm.ptr, rb, _stream_ptr(stream), buf, cap, C.byref(n)), "vc_eval_proof")
+    return buf.raw[:n.value]
 
 
 def vc_open_subarrays(pp: Params, cm: Commitment, b: int, stream=None) -> Proofs:

@@ -297,3 +297,131 @@ void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32
 void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st) { L1(k_merkle_level, start, tree, start); }
 void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st) { L1(k_rho, K, C, tree, K, r); }
 }  // namespace kl
+
+// ------------------------------------------------------------------ evaluation proof at a point
+// f_m at r = (r_{L-1}, ..., r_0) (section 4.3): entry i = jM + a pairs its bit k with x_k.
+// T_j = prod_{c<lK} (j_c r_{lM+c} + (1 - j_c)(1 - r_{lM+c})); C_F = sum_j T_j C_j; the FC
+// statement is the query T with claimed value C_F, batched with r_0 = H2F(EVAL, sigma_E || 0),
+// sigma_E = SHA-256(EVAL || C || r_{L-1} || ... || r_0 || C_F); F's table g[a] = sum_j T_j
+// m[jM + a] is opened at r_R by PST, eliminating x_{lM-1} first.
+
+// r_k from 32 little-endian bytes (range-checked), Montgomery form; a thread per k
+__global__ void __launch_bounds__(64) k_ev_point(const uint8_t *rle, uint32_t L, fe *r, int *err) {
+  uint32_t k = (uint32_t)gtid();
+  if (k >= L) return;
+  fe v;
+  for (int q = 0; q < 8; q++) {
+    const uint8_t *b = rle + 32 * k + 4 * q;
+    v.l[q] = (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+  }
+  if (!fe_lt_mod(v, bn::R_MOD)) atomicOr(err, VC_ERRBIT_RANGE);
+  r[k] = f_to_mont<FpR>(v);
+}
+
+// T_j, a thread per j < K
+__global__ void __launch_bounds__(TPB) k_ev_eq(const fe *r, uint32_t lM, uint32_t lK, uint64_t K, fe *T) {
+  uint64_t j = gtid();
+  if (j >= K) return;
+  fe acc = f_one<FpR>();
+  for (uint32_t c = 0; c < lK; c++) {
+    fe rc = r[lM + c];
+    acc = fr_mul(acc, ((j >> c) & 1) ? rc : fr_sub(f_one<FpR>(), rc));
+  }
+  T[j] = acc;
+}
+
+// the sum of n affine points (one workgroup of 256)
+__global__ void __launch_bounds__(256) k_ev_sum(const g1_aff *P, uint64_t n, g1_aff *out) {
+  __shared__ g1_jac sh[256];
+  const int t = threadIdx.x;
+  g1_jac acc = jac_inf<OpsG1>();
+  for (uint64_t q = t; q < n; q += 256) acc = jac_madd(acc, P[q]);
+  sh[t] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] = jac_add(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) *out = jac_to_aff(sh[0]);
+}
+
+// r_0 on thread 0, then b = r_0 T (one workgroup)
+__global__ void __launch_bounds__(256) k_ev_r0(const fp12 *C, const fe *r, uint32_t L, const g1_aff *CF, const fe *T,
+                                               uint64_t K, fe *B) {
+  CHAIN_PRIORITY();
+  __shared__ fe r0;
+  if (threadIdx.x == 0) {
+    sha::Hasher hs;
+    hs.init();
+    hs.str(DSTR_EVAL);
+    hs.gt(*C);
+    for (int k = (int)L - 1; k >= 0; k--) hs.field<FpR>(r[k]);
+    hs.g1(*CF);
+    uint32_t sigma[8];
+    hs.final(sigma);
+    sha::Hasher hx;
+    sha::xmd_begin(hx);
+    for (int w = 0; w < 8; w++) hx.word(sigma[w]);
+    hx.u64(0);
+    r0 = sha::xmd_finish_fr(hx, DSTR_EVAL);
+  }
+  __syncthreads();
+  for (uint64_t j = threadIdx.x; j < K; j += 256) B[j] = fr_mul(r0, T[j]);
+}
+
+// g[a] = sum_j T_j m[jM + a] (m canonical, T and g Montgomery), a thread per a
+__global__ void __launch_bounds__(TPB) k_ev_table(const fe *m, const fe *T, uint64_t K, uint64_t M, fe *g) {
+  uint64_t a = gtid();
+  if (a >= M) return;
+  fe acc = fe_zero();
+  for (uint64_t j = 0; j < K; j++) acc = fr_add(acc, fr_mul(T[j], m[j * M + a]));  // T R * m / R: canonical
+  g[a] = f_to_mont<FpR>(acc);
+}
+
+// one PST step on a table of 2 half entries: q = hi - lo, lo += r q; a thread per c < half
+__global__ void __launch_bounds__(TPB) k_ev_pst_step(fe *g, uint64_t half, const fe *rvar, fe *q) {
+  uint64_t c = gtid();
+  if (c >= half) return;
+  fe d = fr_sub(g[half + c], g[c]);
+  q[c] = d;
+  g[c] = fr_add(g[c], fr_mul(*rvar, d));
+}
+
+// W_d = sum of segment d of the products (entries [2^{lM-1-d} - 1, 2^{lM-d} - 1)); y = g[0]
+__global__ void __launch_bounds__(256) k_ev_finish(const g1_aff *prod, uint32_t lM, const fe *g, g1_aff *W, fe *y) {
+  __shared__ g1_jac sh[256];
+  uint32_t d = blockIdx.x;
+  if (d >= lM) return;
+  const int t = threadIdx.x;
+  uint64_t len = 1ull << (lM - 1 - d), lo = len - 1;
+  g1_jac acc = jac_inf<OpsG1>();
+  for (uint64_t q = t; q < len; q += 256) acc = jac_madd(acc, prod[lo + q]);
+  sh[t] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] = jac_add(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    W[d] = jac_to_aff(sh[0]);
+    if (d == 0) *y = g[0];
+  }
+}
+
+namespace kl {
+void ev_point(const uint8_t *rle, uint32_t L, fe *r, int *err, hipStream_t st) {
+  LAUNCH(k_ev_point, dim3(1), dim3(64), 0, rle, L, r, err);
+}
+void ev_eq(const fe *r, uint32_t lM, uint32_t lK, uint64_t K, fe *T, hipStream_t st) { L1(k_ev_eq, K, r, lM, lK, K, T); }
+void ev_sum(const g1_aff *P, uint64_t n, g1_aff *out, hipStream_t st) {
+  LAUNCH(k_ev_sum, dim3(1), dim3(256), 0, P, n, out);
+}
+void ev_r0(const fp12 *C, const fe *r, uint32_t L, const g1_aff *CF, const fe *T, uint64_t K, fe *B, hipStream_t st) {
+  LAUNCH(k_ev_r0, dim3(1), dim3(256), 0, C, r, L, CF, T, K, B);
+}
+void ev_table(const fe *m, const fe *T, uint64_t K, uint64_t M, fe *g, hipStream_t st) { L1(k_ev_table, M, m, T, K, M, g); }
+void ev_pst_step(fe *g, uint64_t half, const fe *rvar, fe *q, hipStream_t st) { L1(k_ev_pst_step, half, g, half, rvar, q); }
+void ev_finish(const g1_aff *prod, uint32_t lM, const fe *g, g1_aff *W, fe *y, hipStream_t st) {
+  LAUNCH(k_ev_finish, dim3(lM), dim3(256), 0, prod, lM, g, W, y);
+}
+}  // namespace kl

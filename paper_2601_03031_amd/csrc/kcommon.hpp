@@ -35,6 +35,7 @@ __device__ __forceinline__ uint64_t gtid() { return (uint64_t)blockIdx.x * block
 #define DSTR_FC_Z "FLEXPROOFS-V1-FC-Z"
 #define DSTR_RHO "FLEXPROOFS-V1-RHO"
 #define DSTR_VALL "FLEXPROOFS-V1-VERIFY-ALL"
+#define DSTR_EVAL "FLEXPROOFS-V1-EVAL"
 
 __device__ __forceinline__ void canon_scalar(uint32_t k[8], const fe &mont) {
   fe c = f_from_mont<FpR>(mont);

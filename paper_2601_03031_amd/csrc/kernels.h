@@ -53,6 +53,14 @@ void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_
 void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st);
 void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st);
 void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st);
+// evaluation proof at a point (k_hash.hip)
+void ev_point(const uint8_t *rle, uint32_t L, fe *r, int *err, hipStream_t st);
+void ev_eq(const fe *r, uint32_t lM, uint32_t lK, uint64_t K, fe *T, hipStream_t st);
+void ev_sum(const g1_aff *P, uint64_t n, g1_aff *out, hipStream_t st);
+void ev_r0(const fp12 *C, const fe *r, uint32_t L, const g1_aff *CF, const fe *T, uint64_t K, fe *B, hipStream_t st);
+void ev_table(const fe *m, const fe *T, uint64_t K, uint64_t M, fe *g, hipStream_t st);
+void ev_pst_step(fe *g, uint64_t half, const fe *rvar, fe *q, hipStream_t st);
+void ev_finish(const g1_aff *prod, uint32_t lM, const fe *g, g1_aff *W, fe *y, hipStream_t st);
 }  // namespace kl
 
 // Wide-layout kernels (k_wide.hip, 8 lanes per field element); same memory layouts

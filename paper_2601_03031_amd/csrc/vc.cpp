@@ -137,7 +137,7 @@ struct vc_exec {
   uint32_t nown = 0;
   hipStream_t main = nullptr;
   hipStream_t side[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t ev[20] = {};
+  hipEvent_t ev[21] = {};
   uint32_t *cnt = nullptr;
   uint64_t cnt_n = 0;
   bool cnt_dirty = false;  // counters to be zeroed before the next use (new, or left by a failed call)
@@ -202,6 +202,7 @@ struct vc_proofs {
   void *mem = nullptr;  // the proof bundle
   size_t o_Cj, o_C, o_Lgt, o_Rgt, o_Lg1, o_Rg1, o_X, o_Al, o_vl, o_piv, o_tree, o_rho, o_Y, o_D, o_W;
   bool step2 = true;    // false: sub-array proofs only (Step 1), no Merkle tree, y-tree, D-tree or W
+  size_t o_CF = 0, o_yv = 0, o_We = 0;  // evaluation proof: C_F, F(r_R), the PST quotients W_d
 };
 
 // At least n zeroed arrival counters.  New ones are cleared on the call's stream `st`, ahead of
@@ -443,8 +444,12 @@ VC_API void vc_commitment_free(vc_commitment *cm) {
 // counters) are stored there; nothing is allocated or launched, and cm, ex, out may be NULL.
 // With step2 false only Step 1 runs: the FC batch proofs that open every C_j (the sub-array
 // form of OpenAll, section 4.3).
+// With eval_r (host, log N little-endian 32-byte values r_0 .. r_{L-1}) the one batch b = K
+// proves C_F = <C, T(r_L)> and the PST part opens F at r_R in place of Step 2 (section 4.3,
+// evaluation proof at a point).
 static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t b, vc_exec *ex, hipStream_t st,
-                         vc_proofs **out, uint64_t *footprint = nullptr, bool step2 = true) {
+                         vc_proofs **out, uint64_t *footprint = nullptr, bool step2 = true,
+                         const uint8_t *eval_r = nullptr) {
   if (!cpp || b < 1 || b > cpp->K) return VC_EINVAL;
   if (!footprint && (!cm || !out || !ex || cm->pp != cpp || ex->device != cpp->device)) return VC_EINVAL;
   const vc_params *pp = cpp;
@@ -462,6 +467,8 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   pr->nb = nb;
   pr->step2 = step2;
   const uint64_t with2 = step2 ? 1 : 0;  // Step 2 arrays are left out of a sub-array bundle
+  const uint64_t ev = eval_r ? 1 : 0;
+  if (eval_r && (b != K || step2)) return VC_EINVAL;
   Carve c;
   pr->o_Cj = c.take<g1_aff>(K);
   pr->o_C = c.take<fp12>(1);
@@ -478,6 +485,9 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   pr->o_Y = c.take<fe>(with2 * (2 * K - 1) * M);
   pr->o_D = c.take<g1_aff>(with2 * (2 * K - 1));
   pr->o_W = c.take<g1_aff>(with2 * (M - 1));
+  pr->o_CF = c.take<g1_aff>(ev);
+  pr->o_yv = c.take<fe>(ev);
+  pr->o_We = c.take<g1_aff>(ev * lM);
   // ---- scratch
   Carve t;
   size_t o_err = t.take<int>(1), o_A = t.take<g1_aff>(nb * K), o_V = t.take<g2_aff>(nb * K), o_B = t.take<fe>(nb * K);
@@ -489,6 +499,9 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   const uint64_t kzg_nslice = (nq + KZG_S - 1) / KZG_S, kzg_len = kzg_split ? 4 * nq : kzg_nslice;
   size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(with2 * lM * (M / 2));
   size_t o_dec = t.take<glv::Dec>(nb);
+  // evaluation proof: point, T, the terms of C_F, F's table, the PST quotients and their products
+  size_t o_rle = t.take<uint8_t>(ev * 32 * pp->L), o_er = t.take<fe>(ev * pp->L), o_T = t.take<fe>(ev * K),
+         o_pK = t.take<g1_aff>(ev * K), o_eg = t.take<fe>(ev * M), o_eq = t.take<fe>(ev * M), o_pW = t.take<g1_aff>(ev * M);
   // Step 1 arrays of alternate rounds, and the terms taken one round ahead (oa_terms.hpp)
   const bool ahead = lK >= 2 && nb * K <= AHEAD_MAX_PAIRS;
   const uint64_t nterm = ahead ? 2 * nb * K : 0;
@@ -637,9 +650,35 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
     const int cur = (j - 1) & 1;
     ks::fold_mults(Ab[cur], n, nb * n, Vb[cur] + hh, hh, nb * hh, K, FM1[j & 1], FM2[j & 1], s);
   };
-  kl::fc_chunks(Cj, K, b, nb, Hq, st);
-  kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
-  kl::fc_r(K, b, nb, sigma, B, st);
+  fe *er = at<fe>(ws, o_er), *eT = at<fe>(ws, o_T), *eg = at<fe>(ws, o_eg), *eq = at<fe>(ws, o_eq);
+  if (eval_r) {
+    // the point, T(r_L), C_F = sum_j T_j C_j, then b = r_0 T for the one batch
+    CK(hipMemcpyAsync(at<void>(ws, o_rle), eval_r, 32ull * pp->L, hipMemcpyHostToDevice, st));
+    kl::ev_point(at<uint8_t>(ws, o_rle), pp->L, er, err, st);
+    kl::ev_eq(er, lM, lK, K, eT, st);
+    klw::g1_mul(Cj, 0, eT, K, at<g1_aff>(ws, o_pK), st);
+    kl::ev_sum(at<g1_aff>(ws, o_pK), K, at<g1_aff>(bm, pr->o_CF), st);
+    kl::ev_r0(C, er, pp->L, at<g1_aff>(bm, pr->o_CF), eT, K, B, st);
+  } else {
+    kl::fc_chunks(Cj, K, b, nb, Hq, st);
+    kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
+    kl::fc_r(K, b, nb, sigma, B, st);
+  }
+  // the PST part of an evaluation proof on side stream 1, beside the FC rounds: F's table,
+  // then l_M steps eliminating x_{lM-1} first, the quotients' products with ek_0 .. ek_{lM-1}
+  // (contiguous at the start of ek, in the same order) and their sums
+  auto launch_pst = [&]() -> int {
+    if (int rc2 = stream_wait(ex, 20, st, s1)) return rc2;
+    kl::ev_table(cm->m, eT, K, M, eg, s1);
+    for (uint32_t d = 0; d < lM; d++) {
+      uint32_t k = lM - d;
+      uint64_t half = 1ull << (k - 1);
+      kl::ev_pst_step(eg, half, er + (k - 1), eq + (half - 1), s1);
+    }
+    klw::g1_mul(pp->ek, 0, eq, M - 1, at<g1_aff>(ws, o_pW), s1);
+    kl::ev_finish(at<g1_aff>(ws, o_pW), lM, eg, at<g1_aff>(bm, pr->o_We), at<fe>(bm, pr->o_yv), s1);
+    return VC_OK;
+  };
   if (int rc2 = stream_wait(ex, 1, st, sg)) return rc2;
   if (int rc2 = stream_wait(ex, 2, st, sf)) return rc2;
   if (ahead) {
@@ -754,8 +793,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
       if (int rc2 = stream_wait(ex, 12, sf, st)) return rc2;
     }
     if (j == std::min<uint32_t>(2, lK))
-      if (step2)
-        if (int rc2 = launch_step2()) return rc2;
+      if (int rc2 = step2 ? launch_step2() : eval_r ? launch_pst() : VC_OK) return rc2;
   }
   if (ahead)
     if (int rc2 = stream_wait(ex, 11, sg, st)) return rc2;
@@ -780,6 +818,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (herr & VC_ERRBIT_CHALLENGE) return VC_ECHALLENGE;
+  if (eval_r && (herr & VC_ERRBIT_RANGE)) return VC_EINVAL;
   release.p = nullptr;
   *out = pr;
   return VC_OK;
@@ -1069,6 +1108,60 @@ void compress_g2(uint8_t *o, const uint8_t *xy) {
 }
 
 }  // namespace
+
+VC_API uint64_t vc_eval_proof_len(uint32_t log_n) {
+  uint32_t lK = log_n / 2, lM = log_n - lK;
+  return 32 + lK * (2ull * 384 + 2 * 32) + 160 + 32 + 32ull * lM;
+}
+
+// Evaluation proof of f_m at r (section 4.3): one open-all batch over T(r_L) with the PST part
+// in place of Step 2; bytes C_F || rounds || A_l v_l pi_v || F(r_R) || W_0 .. W_{lM-1}.
+VC_API int vc_eval_proof(const vc_params *pp, const vc_commitment *cm, const uint8_t *r, void *stream, uint8_t *out,
+                         size_t cap, size_t *len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pp || !cm || !r || !out || !len) return VC_EINVAL;
+  const uint32_t lK = pp->lK, lM = pp->lM;
+  const uint64_t need = vc_eval_proof_len(pp->L);
+  if (cap < need) return VC_EINVAL;
+  vc_proofs *pr = nullptr;
+  if (int rc = open_all_impl(pp, cm, (uint32_t)pp->K, pp->ex, (hipStream_t)stream, &pr, nullptr, false, r)) return rc;
+  struct Release {
+    vc_proofs *p;
+    ~Release() { vc_proofs_free(p); }
+  } release{pr};
+  std::vector<uint64_t> idx;
+  std::vector<int> mode;
+  push_run(idx, mode, pr->o_CF, 2, 0);
+  for (uint32_t q = 0; q < lK; q++) {
+    push_run(idx, mode, pr->o_Lgt + q * 384, 12, 0);
+    push_run(idx, mode, pr->o_Lg1 + q * 64, 2, 0);
+    push_run(idx, mode, pr->o_Rgt + q * 384, 12, 0);
+    push_run(idx, mode, pr->o_Rg1 + q * 64, 2, 0);
+  }
+  push_run(idx, mode, pr->o_Al, 2, 0);
+  push_run(idx, mode, pr->o_vl, 4, 0);
+  push_run(idx, mode, pr->o_piv, 4, 0);
+  push_run(idx, mode, pr->o_yv, 1, 1);
+  for (uint32_t d = 0; d < lM; d++) push_run(idx, mode, pr->o_We + d * 64, 2, 0);
+  std::vector<uint8_t> g;
+  if (int rc = gather(pr->mem, idx, mode, g)) return rc;
+  const uint8_t *s = g.data();
+  uint8_t *q = out;
+  compress_g1(q, s); q += 32; s += 64;
+  for (uint32_t k = 0; k < lK; k++) {
+    memcpy(q, s, 384); q += 384; s += 384;
+    compress_g1(q, s); q += 32; s += 64;
+    memcpy(q, s, 384); q += 384; s += 384;
+    compress_g1(q, s); q += 32; s += 64;
+  }
+  compress_g1(q, s); q += 32; s += 64;
+  compress_g2(q, s); q += 64; s += 128;
+  compress_g2(q, s); q += 64; s += 128;
+  memcpy(q, s, 32); q += 32; s += 32;
+  for (uint32_t d = 0; d < lM; d++, q += 32, s += 64) compress_g1(q, s);
+  *len = (size_t)(q - out);
+  return *len == need ? VC_OK : VC_EDEVICE;
+}
 
 VC_API uint64_t vc_subarray_proof_len(uint32_t log_n, uint32_t t) {
   uint32_t lK = log_n / 2;
