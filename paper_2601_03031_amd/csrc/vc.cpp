@@ -189,6 +189,7 @@ static int ev_wait(vc_exec *ex, int slot, hipStream_t to) {
 
 struct vc_commitment {
   const vc_params *pp;
+  int device = 0;  // its own copy: a handle may be released after its params
   void *mem = nullptr;
   fe *m;          // N canonical entries
   g1_aff *Cj;     // K
@@ -197,6 +198,7 @@ struct vc_commitment {
 
 struct vc_proofs {
   const vc_params *pp;
+  int device = 0;  // its own copy: a handle may be released after its params
   uint32_t b;
   uint64_t nb;
   void *mem = nullptr;  // the proof bundle
@@ -245,6 +247,7 @@ VC_API void vc_exec_free(vc_exec *ex) {
   for (auto ev : ex->ev)
     if (ev) hipEventDestroy(ev);
   delete ex;
+  (void)hipGetLastError();  // a release reports nothing and leaves no error behind
 }
 
 VC_API int vc_exec_create(int device, uint32_t nstreams, vc_exec **out) {
@@ -365,6 +368,7 @@ VC_API void vc_params_free(vc_params *pp) {
   if (pp->mem) hipFree(pp->mem);
   vc_exec_free(pp->ex);
   delete pp;
+  (void)hipGetLastError();  // a release reports nothing and leaves no error behind
 }
 
 // ------------------------------------------------------------------ commit
@@ -380,6 +384,7 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   uint64_t N = pp->N, K = pp->K, M = pp->M;
   vc_commitment *cm = new vc_commitment();
   cm->pp = pp;
+  cm->device = pp->device;
   Carve c;
   size_t o_m = c.take<fe>(N), o_Cj = c.take<g1_aff>(K), o_C = c.take<fp12>(1);
   hipError_t e = hipMalloc(&cm->mem, c.off);
@@ -434,9 +439,10 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
 VC_API void vc_commitment_free(vc_commitment *cm) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!cm) return;
-  hipSetDevice(cm->pp->device);
-  if (cm->mem) hipFree(cm->mem);
+  (void)hipSetDevice(cm->device);
+  if (cm->mem) (void)hipFree(cm->mem);
   delete cm;
+  (void)hipGetLastError();  // a release reports nothing and leaves no error behind
 }
 
 // ------------------------------------------------------------------ open-all
@@ -463,6 +469,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   // ---- the proof bundle
   vc_proofs *pr = new vc_proofs();
   pr->pp = pp;
+  pr->device = pp->device;
   pr->b = b;
   pr->nb = nb;
   pr->step2 = step2;
@@ -1046,9 +1053,10 @@ VC_API int vc_server_wait(vc_server *sv, uint64_t ticket, vc_proofs **out, doubl
 VC_API void vc_proofs_free(vc_proofs *pr) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pr) return;
-  hipSetDevice(pr->pp->device);
-  if (pr->mem) hipFree(pr->mem);
+  (void)hipSetDevice(pr->device);
+  if (pr->mem) (void)hipFree(pr->mem);
   delete pr;
+  (void)hipGetLastError();  // a release reports nothing and leaves no error behind
 }
 
 // ------------------------------------------------------------------ gathering / export
