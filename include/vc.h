@@ -178,6 +178,11 @@ int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_t b, ui
 uint64_t vc_eval_proof_len(uint32_t log_n);
 int vc_eval_proof(const vc_params *pp, const vc_commitment *cm, const uint8_t *r, void *stream, uint8_t *out,
                   size_t cap, size_t *len);
+/* Verification of an evaluation proof (host buffers): FC.BVerify of C_F = <C, T(r_L)> with
+ * the faster verifier (section 3) and PC.Verify of F at r_R, e(C_F - y g1, g2) =
+ * prod_d e(W_d, (s_var - r_var) g2).  1 accept, 0 reject, VC_EINVAL for malformed inputs
+ * (length, C, r_k >= r). */
+int vc_verify_eval(const vc_params *pp, const uint8_t C[384], const uint8_t *r, const uint8_t *proof, size_t len);
 
 /* Serialized length of a proof whose block holds t subvector commitments. */
 uint64_t vc_proof_len(uint32_t log_n, uint32_t t);

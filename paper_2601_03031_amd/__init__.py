@@ -70,6 +70,7 @@ def lib():
         L.vc_eval_proof_len.restype = u64
         L.vc_eval_proof_len.argtypes = [u32]
         L.vc_eval_proof.argtypes = [vp, vp, u8p, vp, vp, sz, C.POINTER(sz)]
+        L.vc_verify_eval.argtypes = [vp, u8p, u8p, u8p, sz]
         L.vc_subarray_proof_len.restype = u64
         L.vc_subarray_proof_len.argtypes = [u32, u32]
         L.vc_subarray_proof_get.argtypes = [vp, u64, vp, sz, C.POINTER(sz)]
@@ -271,6 +272,13 @@ def vc_eval_proof(pp: Params, cm: Commitment, r: list, stream=None) -> bytes:
         raise ValueError("the point has log N coordinates")
     _check(lib().vc_eval_proof(pp.ptr, cm.ptr, rb, _stream_ptr(stream), buf, cap, C.byref(n)), "vc_eval_proof")
     return buf.raw[:n.value]
+
+
+def vc_verify_eval(pp: Params, C_bytes: bytes, r: list, proof: bytes) -> int:
+    rb = b"".join(int(x).to_bytes(32, "little") for x in r)
+    if len(r) != pp.log_n:
+        raise ValueError("the point has log N coordinates")
+    return _check(lib().vc_verify_eval(pp.ptr, C_bytes, rb, proof, len(proof)), "vc_verify_eval")
 
 
 def vc_open_subarrays(pp: Params, cm: Commitment, b: int, stream=None) -> Proofs:

@@ -798,3 +798,168 @@ void terms(const VACtx &c, hipStream_t st) { L1(kva_terms, nterms(c), c); }
 void segsum(const VACtx &c, hipStream_t st) { LAUNCH(kva_segsum, dim3(c.y.lM + 1), dim3(256), 0, c); }
 void check(const VACtx &c, hipStream_t st) { LAUNCH(kva_check, dim3(1), dim3(64), 0, c); }
 }  // namespace kva
+
+// ------------------------------------------------------------------ evaluation proof at a point
+// Verifier of the evaluation proof (section 4.3): FC.BVerify of C_F = <C, T(r_L)> on the dense
+// query b = r_0 T (faster verifier), then PC.Verify of F at r_R:
+//   e(C_F - y g1, g2) = prod_d e(W_d, (s_var - r_var) g2),  var = l_M - 1 - d.
+// The pairs and the final equalities are laid out as for one opening proof (kv_compare).
+
+// one thread per item: C_F, the rounds, A_l v_l pi_v, y, W, C and the point
+__global__ void __launch_bounds__(TPB) kve_decode(VECtx c) {
+  uint32_t id = (uint32_t)gtid();
+  const uint32_t l = c.lK, lM = c.lM;
+  if (id >= 1 + 4 * l + 3 + 1 + lM + 1 + c.L) return;
+  const uint8_t *pf = c.proof;
+  bool ok = true;
+  if (id == 0) {
+    ok = g1_decompress(pf, *c.CF);
+  } else if ((id -= 1) < 4 * l) {
+    uint32_t r = id / 4, w = id % 4;
+    const uint8_t *q = pf + 32 + (uint64_t)r * (2 * 384 + 2 * 32);
+    if (w == 0) ok = gt_decode(q, c.Lgt[r]);
+    else if (w == 1) ok = g1_decompress(q + 384, c.Lg1[r]);
+    else if (w == 2) ok = gt_decode(q + 416, c.Rgt[r]);
+    else ok = g1_decompress(q + 800, c.Rg1[r]);
+  } else if ((id -= 4 * l) < 3) {
+    const uint8_t *q = pf + 32 + (uint64_t)l * (2 * 384 + 2 * 32);
+    if (id == 0) ok = g1_decompress(q, *c.Al);
+    else if (id == 1) ok = g2_decompress(q + 32, *c.vl);
+    else ok = g2_decompress(q + 96, *c.piv);
+  } else if ((id -= 3) == 0) {
+    fe v = rd_be(pf + 32 + (uint64_t)l * (2 * 384 + 2 * 32) + 160);
+    ok = lt_words(v, bn::R_MOD);
+    *c.y = f_to_mont<FpR>(v);
+  } else if ((id -= 1) < lM) {
+    ok = g1_decompress(pf + 32 + (uint64_t)l * (2 * 384 + 2 * 32) + 192 + 32 * id, c.W[id]);
+  } else if ((id -= lM) == 0) {
+    if (!gt_decode(c.Cb, *c.C)) atomicOr(c.flags, VFLAG_BAD_INPUT);
+  } else {
+    uint32_t k = id - 1;
+    fe v;
+    for (int q = 0; q < 32; q++) reinterpret_cast<uint8_t *>(v.l)[q] = c.rle[32 * k + q];  // little-endian limbs
+    if (!lt_words(v, bn::R_MOD)) atomicOr(c.flags, VFLAG_BAD_INPUT);
+    c.r[k] = f_to_mont<FpR>(v);
+  }
+  if (!ok) atomicOr(c.flags, VFLAG_BAD_PROOF);
+}
+
+// r_0, the challenges x_j, z, f_v(z) (thread 0), b_l = r_0 sum_j T_j prod_k (x_k^{-1})^{bit_{l-k}(j)}
+// as a tree, and the jobs (one workgroup)
+__global__ void __launch_bounds__(256) kve_transcript(VECtx c) {
+  const int tid = threadIdx.x;
+  const uint32_t l = c.lK, lM = c.lM;
+  __shared__ fe part[256];
+  __shared__ fe s_r0, s_z;
+  if (tid == 0) {
+    sha::Hasher hs;
+    hs.init();
+    hs.str(DSTR_EVAL);
+    hs.gt(*c.C);
+    for (int k = (int)c.L - 1; k >= 0; k--) hs.field<FpR>(c.r[k]);
+    hs.g1(*c.CF);
+    uint32_t sigma[8];
+    hs.final(sigma);
+    sha::Hasher hx;
+    sha::xmd_begin(hx);
+    for (int w = 0; w < 8; w++) hx.word(sigma[w]);
+    hx.u64(0);
+    s_r0 = sha::xmd_finish_fr(hx, DSTR_EVAL);
+    for (uint32_t j = 0; j < l; j++) {
+      sha::Hasher h2;
+      sha::xmd_begin(h2);
+      if (j > 0) h2.field<FpR>(c.x[j - 1]);
+      h2.gt(c.Lgt[j]);
+      h2.g1(c.Lg1[j]);
+      h2.gt(c.Rgt[j]);
+      h2.g1(c.Rg1[j]);
+      fe x = sha::xmd_finish_fr(h2, DSTR_FC_X);
+      if (fe_is_zero(x)) atomicOr(c.flags, VFLAG_BAD_PROOF);
+      c.x[j] = x;
+      c.xinv[j] = fr_inv_fast(x);
+    }
+    sha::Hasher hz;
+    sha::xmd_begin(hz);
+    hz.field<FpR>(c.x[l - 1]);
+    hz.g2(*c.vl);
+    fe z = sha::xmd_finish_fr(hz, DSTR_FC_Z);
+    fe fz = f_one<FpR>(), zp = fr_mul(z, z);
+    for (int j = (int)l; j >= 1; j--) {
+      fz = fr_mul(fz, fr_add(f_one<FpR>(), fr_mul(c.xinv[j - 1], zp)));
+      zp = fr_mul(zp, zp);
+    }
+    s_z = z;
+    c.g2s[0] = fz;
+  }
+  __syncthreads();
+  fe acc = fe_zero();
+  for (uint64_t j = tid; j < c.K; j += 256) {
+    fe term = c.T[j];
+    for (uint32_t k = 1; k <= l; k++)
+      if ((j >> (l - k)) & 1) term = fr_mul(term, c.xinv[k - 1]);
+    acc = fr_add(acc, term);
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int sft = 128; sft > 0; sft >>= 1) {
+    if (tid < sft) part[tid] = fr_add(part[tid], part[tid + sft]);
+    __syncthreads();
+  }
+  const g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
+  for (uint32_t q = tid; q < 2 * l + 4; q += 256) {
+    g1_aff base = g1;
+    fe k;
+    if (q < 2 * l) {
+      uint32_t j = q / 2;
+      if (q % 2 == 0) { base = c.Lg1[j]; k = c.x[j]; }
+      else { base = c.Rg1[j]; k = c.xinv[j]; }
+    } else if (q == 2 * l) {
+      base = *c.Al; k = fr_mul(s_r0, part[0]);
+    } else if (q == 2 * l + 1) {
+      base = *c.CF; k = s_r0;
+    } else if (q == 2 * l + 2) {
+      k = *c.y;
+    } else {
+      k = s_z;
+    }
+    c.mb[q] = base;
+    c.ms[q] = k;
+  }
+  for (uint32_t d = tid; d < lM; d += 256) c.g2s[1 + d] = c.r[lM - 1 - d];
+  for (uint32_t q = tid; q < 2 * l; q += 256) {
+    c.gts[q] = (q % 2 == 0) ? c.x[q / 2] : c.xinv[q / 2];
+    c.gtb[q] = (q % 2 == 0) ? c.Lgt[q / 2] : c.Rgt[q / 2];
+  }
+}
+
+// point sums and the pairs (one thread)
+__global__ void __launch_bounds__(64) kve_assemble(VECtx c) {
+  if (gtid() != 0) return;
+  const uint32_t l = c.lK, lM = c.lM;
+  g1_jac acc = jac_from_aff(c.mo[2 * l + 1]);  // r_0 C_F
+  for (uint32_t u = 0; u < 2 * l; u++) acc = jac_madd(acc, c.mo[u]);
+  *c.Cg1 = jac_to_aff(acc);
+  *c.bA = c.mo[2 * l];
+  g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
+  g2_aff g2 = {f2_const(bn::G2X0, bn::G2X1), f2_const(bn::G2Y0, bn::G2Y1)};
+  g1_aff Pk = jac_to_aff(jac_madd(jac_from_aff(*c.g1beta), aff_neg(c.mo[2 * l + 3])));
+  g2_aff Qk = jac_to_aff(jac_madd(jac_from_aff(*c.vl), aff_neg(c.g2o[0])));
+  g1_aff P0 = jac_to_aff(jac_madd(jac_from_aff(*c.CF), aff_neg(c.mo[2 * l + 2])));
+  // pairs: (A_l, v_l) | (beta g1 - z g1, pi_v), (-g1, v_l - f_v(z) g2) | (C_F - y g1, -g2), (W_d, (s - r)_var g2)
+  c.pp[0] = *c.Al; c.pq[0] = *c.vl;
+  c.pp[1] = Pk; c.pq[1] = *c.piv;
+  c.pp[2] = aff_neg(g1); c.pq[2] = Qk;
+  c.pp[3] = P0; c.pq[3] = aff_neg(g2);
+  for (uint32_t d = 0; d < lM; d++) {
+    c.pp[4 + d] = c.W[d];
+    c.pq[4 + d] = jac_to_aff(jac_madd(jac_from_aff(c.vk[lM - 1 - d]), aff_neg(c.g2o[1 + d])));
+  }
+  for (uint32_t q = 0; q < 2 * l; q++) c.gto[q] = c.gtp[q];
+  c.gto[2 * l] = *c.C;
+}
+
+namespace kve {
+void decode(const VECtx &c, hipStream_t st) { L1(kve_decode, 1 + 4 * c.lK + 3 + 1 + c.lM + 1 + c.L, c); }
+void transcript(const VECtx &c, hipStream_t st) { LAUNCH(kve_transcript, dim3(1), dim3(256), 0, c); }
+void assemble(const VECtx &c, hipStream_t st) { LAUNCH(kve_assemble, dim3(1), dim3(64), 0, c); }
+}  // namespace kve

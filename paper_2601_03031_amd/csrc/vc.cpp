@@ -1519,6 +1519,86 @@ VC_API int vc_profile_read(char *buf, size_t cap) {
 
 // ------------------------------------------------------------------ diagnostics
 // Runs one base-field operation on n pairs of canonical 32-byte little-endian inputs
+// Verification of an evaluation proof at a point (section 4.3): FC.BVerify of C_F = <C, T(r_L)>
+// with the faster verifier, and PC.Verify of F at r_R; the final equalities as for one opening
+// proof.
+VC_API int vc_verify_eval(const vc_params *pp, const uint8_t C[384], const uint8_t *r, const uint8_t *proof,
+                          size_t len) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pp || !C || !r || !proof || len != vc_eval_proof_len(pp->L)) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  vc_exec *ex = pp->ex;
+  hipStream_t st = ex->side[0];
+  const uint32_t L = pp->L, l = pp->lK, lM = pp->lM, npair = 4 + lM, nmul = 2 * l + 4;
+  const uint64_t K = pp->K;
+  Carve w;
+  size_t o_pf = w.take<uint8_t>(len), o_Cb = w.take<uint8_t>(384), o_rle = w.take<uint8_t>(32 * L),
+         o_CF = w.take<g1_aff>(1), o_Lg1 = w.take<g1_aff>(l), o_Rg1 = w.take<g1_aff>(l), o_Al = w.take<g1_aff>(1),
+         o_W = w.take<g1_aff>(lM), o_Lgt = w.take<fp12>(l), o_Rgt = w.take<fp12>(l), o_C = w.take<fp12>(1),
+         o_vl = w.take<g2_aff>(1), o_piv = w.take<g2_aff>(1), o_r = w.take<fe>(L), o_y = w.take<fe>(1),
+         o_T = w.take<fe>(K), o_x = w.take<fe>(l), o_xi = w.take<fe>(l), o_ms = w.take<fe>(nmul),
+         o_mb = w.take<g1_aff>(nmul), o_mo = w.take<g1_aff>(nmul), o_g2s = w.take<fe>(1 + lM),
+         o_g2o = w.take<g2_aff>(1 + lM), o_gts = w.take<fe>(2 * l), o_gtb = w.take<fp12>(2 * l),
+         o_gtp = w.take<fp12>(2 * l), o_gto = w.take<fp12>(2 * l + 1), o_pp = w.take<g1_aff>(npair),
+         o_pq = w.take<g2_aff>(npair), o_F = w.take<fp12>(npair), o_E = w.take<fp12>(3), o_Cg1 = w.take<g1_aff>(1),
+         o_bA = w.take<g1_aff>(1), o_fl = w.take<int>(1), o_ctx = w.take<VCtx>(1);
+  if (int rc = ensure_cnt(ex, tree_counters(npair > 2 * l + 1 ? npair : 2 * l + 1), st)) return rc;
+  void *d = nullptr;
+  CK(hipMalloc(&d, w.off));
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } free_d{d};
+  VECtx c;
+  c.L = L; c.lK = l; c.lM = lM; c.K = K; c.M = pp->M;
+  c.proof = at<uint8_t>(d, o_pf); c.Cb = at<uint8_t>(d, o_Cb); c.rle = at<uint8_t>(d, o_rle);
+  c.CF = at<g1_aff>(d, o_CF); c.Lg1 = at<g1_aff>(d, o_Lg1); c.Rg1 = at<g1_aff>(d, o_Rg1); c.Al = at<g1_aff>(d, o_Al);
+  c.W = at<g1_aff>(d, o_W); c.Lgt = at<fp12>(d, o_Lgt); c.Rgt = at<fp12>(d, o_Rgt); c.C = at<fp12>(d, o_C);
+  c.vl = at<g2_aff>(d, o_vl); c.piv = at<g2_aff>(d, o_piv); c.r = at<fe>(d, o_r); c.y = at<fe>(d, o_y);
+  c.T = at<fe>(d, o_T); c.x = at<fe>(d, o_x); c.xinv = at<fe>(d, o_xi); c.ms = at<fe>(d, o_ms);
+  c.mb = at<g1_aff>(d, o_mb); c.mo = at<g1_aff>(d, o_mo); c.g2s = at<fe>(d, o_g2s); c.g2o = at<g2_aff>(d, o_g2o);
+  c.gts = at<fe>(d, o_gts); c.gtb = at<fp12>(d, o_gtb); c.gtp = at<fp12>(d, o_gtp); c.gto = at<fp12>(d, o_gto);
+  c.pp = at<g1_aff>(d, o_pp); c.pq = at<g2_aff>(d, o_pq); c.Cg1 = at<g1_aff>(d, o_Cg1); c.bA = at<g1_aff>(d, o_bA);
+  c.g1beta = pp->g1beta; c.vk = pp->vk; c.flags = at<int>(d, o_fl);
+  // the final equalities reuse the one-proof comparison
+  VCtx x = {};
+  x.E = at<fp12>(d, o_E); x.gto = c.gto; x.bA = c.bA; x.Cg1 = c.Cg1; x.flags = c.flags;
+  fp12 *F = at<fp12>(d, o_F), *E = x.E;
+  int flags = 0;
+  hipError_t e = hipMemcpyAsync(at<void>(d, o_pf), proof, len, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(at<void>(d, o_Cb), C, 384, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(at<void>(d, o_rle), r, 32ull * L, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(at<void>(d, o_ctx), &x, sizeof x, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c.flags, 0, sizeof(int), st);
+  if (e == hipSuccess) {
+    kve::decode(c, st);
+    kl::ev_eq(c.r, lM, l, K, c.T, st);
+    kve::transcript(c, st);
+    klw::g1_mul(c.mb, 0, c.ms, nmul, c.mo, st);
+    klw::g2_mul(pp->g2gen, 1, c.g2s, 1 + lM, c.g2o, st);
+    ks::gt_pow(c.gtb, c.gts, 2 * l, c.gtp, st);
+    kve::assemble(c, st);
+    ks::f12_reduce(c.gto, 1, 2 * l + 1, 2 * l + 1, ex->cnt, st);
+    ks::miller(c.pp, 1, c.pq, 1, npair, F, st);
+    ks::f12_reduce(F + 1, 1, npair, 2, ex->cnt, st);
+    ks::f12_reduce(F + 3, 1, npair, npair - 3, ex->cnt, st);
+    ks::final_exp(F, npair, 1, E, E + 3, 6, st);
+    ks::final_exp(F + 1, npair, 1, E + 1, E + 4, 6, st);
+    ks::final_exp(F + 3, npair, 1, E + 2, E + 5, 6, st);
+    kv::compare(at<VCtx>(d, o_ctx), 1, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, c.flags, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    ex->cnt_dirty = true;  // the product trees may have stopped half way
+    return hip_fail(e, "vc_verify_eval");
+  }
+  if (flags & VFLAG_BAD_INPUT) return VC_EINVAL;
+  if (flags & VFLAG_BAD_PROOF) return 0;
+  return (flags & VFLAG_ACCEPT) ? 1 : 0;
+}
+
 // Sub-array verification (section 4.3): the commitment of m_j is recomputed (PC.Commit, the
 // MSM of the commit) and must be entry j of the proof's block, whose FC proof must hold.
 VC_API int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_t b, uint64_t j, const uint8_t *m_j,

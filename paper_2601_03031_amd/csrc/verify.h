@@ -78,6 +78,35 @@ struct VACtx {
   int *flags;
 };
 
+// Verification of an evaluation proof at a point (kve_*): proof C_F || rounds || A_l v_l pi_v
+// || y || W; point r_0 .. r_{L-1} (32 bytes little-endian each)
+struct VECtx {
+  uint32_t L, lK, lM;
+  uint64_t K, M;
+  const uint8_t *proof, *Cb, *rle;
+  g1_aff *CF, *Lg1, *Rg1, *Al, *W;
+  fp12 *Lgt, *Rgt, *C;
+  g2_aff *vl, *piv;
+  fe *r, *y, *T, *x, *xinv;
+  fe *ms;            // G1 jobs: x_j Lg1_j, x_j^{-1} Rg1_j (2 lK), b_l A_l, r_0 C_F, y g1, z g1
+  g1_aff *mb, *mo;
+  fe *g2s;           // G2 jobs: f_v(z) g2, then r_{lM-1-d} g2 (d < lM)
+  g2_aff *g2o;
+  fe *gts;
+  fp12 *gtb, *gtp, *gto;
+  g1_aff *pp, *Cg1, *bA;
+  g2_aff *pq;
+  const g1_aff *g1beta;
+  const g2_aff *vk;
+  int *flags;
+};
+
+namespace kve {
+void decode(const VECtx &c, hipStream_t st);
+void transcript(const VECtx &c, hipStream_t st);
+void assemble(const VECtx &c, hipStream_t st);
+}  // namespace kve
+
 namespace kva {
 uint64_t nterms(const VACtx &c);
 void serialize(const PSCtx &c, hipStream_t st);

@@ -68,3 +68,42 @@ def test_eval_proof_rejects_bad_point(vc):
     r = [3] * L
     opp = O.Params(L, SEED)
     assert O.eval_verify(opp, cm.C, r, vc.vc_eval_proof(pp, cm, r)) == 1
+
+
+@pytest.mark.parametrize("L,seed", [(5, 111), (6, 112), (10, 113)])
+def test_verify_eval_matches_oracle(vc, L, seed):
+    say("verify eval L=%d" % L)
+    limbs = I.entries(1 << L, seed, 256)
+    pp = vc.vc_setup(L, SEED, 0)
+    cm = vc.vc_commit(pp, dev_entries(limbs, 256), 256)
+    opp = O.Params(L, SEED)
+    rng = random.Random(seed)
+    r = [rng.randrange(O.R) for _ in range(L)]
+    p = vc.vc_eval_proof(pp, cm, r)
+    assert vc.vc_verify_eval(pp, cm.C, r, p) == 1
+    rb = [rng.randrange(2) for _ in range(L)]
+    assert vc.vc_verify_eval(pp, cm.C, rb, vc.vc_eval_proof(pp, cm, rb)) == 1
+    lK, lM = L // 2, L - L // 2
+    y_off = 32 + 832 * lK + 160
+
+    def flip(pos, mask=1):
+        a = bytearray(p)
+        a[pos] ^= mask
+        return bytes(a)
+
+    r2 = list(r)
+    r2[0] = (r2[0] + 1) % O.R
+    cm2 = vc.vc_commit(pp, dev_entries(I.entries(1 << L, seed + 50, 256), 256), 256)
+    cases = [("value", cm.C, r, flip(y_off + 31)), ("W", cm.C, r, flip(y_off + 32 + 32 * (lM - 1) + 7, 0x04)),
+             ("FC byte", cm.C, r, flip(32 + 31)), ("C_F", cm.C, r, flip(5, 0x04)), ("point", cm.C, r2, p),
+             ("commitment", cm2.C, r, p)]
+    for label, Cb, rr, pf in cases:
+        v = vc.vc_verify_eval(pp, Cb, rr, pf)
+        assert v == 0, label
+        assert O.eval_verify(opp, Cb, rr, pf) == 0, label
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_verify_eval(pp, cm.C, [O.R] + r[1:], p)
+    assert e.value.code == vc.VC_EINVAL
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_verify_eval(pp, cm.C, r, p[:-1])
+    assert e.value.code == vc.VC_EINVAL
