@@ -456,6 +456,8 @@ def main():
                     help="only run the batched-jobs comparison with these executors x streams setups "
                          "(e.g. 4x6,16x1) and print its JSON")
     ap.add_argument("--serve-only", action="store_true", help="only run the serving-loop comparison")
+    ap.add_argument("--only", choices=("verify_all", "eval", "subarrays"), default=None,
+                    help="only run this extra measurement and print its JSON (for profiling)")
     ap.add_argument("--serve-rate", type=float, default=0, help="request rate per second of the serving stream")
     ap.add_argument("--serve-setups", type=str, default="", metavar="SETUPS",
                     help="executors x streams of the served runs (e.g. 1x6,4x6)")
@@ -483,6 +485,11 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.only:
+        fn = {"verify_all": lambda: verify_all_timing(V, torch), "eval": lambda: eval_timing(V, torch),
+              "subarrays": lambda: subarray_timing(V, torch)}[a.only]
+        print(json.dumps(fn()), flush=True)
+        return
     if a.serve_only:
         kw = {}
         if a.serve_rate:
