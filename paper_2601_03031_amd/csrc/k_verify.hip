@@ -215,21 +215,31 @@ __global__ void __launch_bounds__(256) kv_transcript(const VCtx *cs) {
     hs.u64(u);
     c.r[u] = sha::xmd_finish_fr(hs, DSTR_FC_R);
   }
-  if (tid == 0) {
-    // round challenges
-    for (uint32_t j = 0; j < l; j++) {
-      sha::Hasher hs;
-      sha::xmd_begin(hs);
-      if (j > 0) hs.field<FpR>(c.x[j - 1]);
-      hs.gt(c.Lgt[j]);
-      hs.g1(c.Lg1[j]);
-      hs.gt(c.Rgt[j]);
-      hs.g1(c.Rg1[j]);
-      fe x = sha::xmd_finish_fr(hs, DSTR_FC_X);
+  // round challenges x_j = H2F(FC-X, x_{j-1} || L_gt || L_g1 || R_gt || R_g1), the workgroup
+  // hashing together: lanes write the message words into shared memory, all compress
+  __shared__ uint32_t xmsg[16 + 8 + 2 * (96 + 16) + 32], xt2[16];
+  for (uint32_t j = 0; j < l; j++) {
+    const int pre = j > 0 ? 8 : 0;
+    if (tid < 16) xmsg[tid] = 0;  // Z_pad
+    const int e = j > 0 ? tid - 1 : tid;
+    if (j > 0 && tid == 0) sha::put_words<FpR>(xmsg + 16, c.x[j - 1]);
+    if (e >= 0 && e < 28) {
+      int side = e / 14, q = e % 14;
+      const fe *src = q < 12 ? reinterpret_cast<const fe *>(side ? c.Rgt + j : c.Lgt + j) + q
+                             : reinterpret_cast<const fe *>(side ? c.Rg1 + j : c.Lg1 + j) + (q - 12);
+      sha::put_words<FpP>(xmsg + 16 + pre + 112 * side + 8 * q, *src);
+    }
+    __syncthreads();
+    fe x = sha::xmd_fr_coop(sha::Coop{tid, 256}, xmsg, 4 * (pre + 224), DSTR_FC_X, xt2);
+    fe xi = f_inv_uniform<FpR>(x, bn::R_R3);
+    if (tid == 0) {
       if (fe_is_zero(x)) atomicOr(c.flags, VFLAG_BAD_PROOF);
       c.x[j] = x;
-      c.xinv[j] = fr_inv_fast(x);
+      c.xinv[j] = xi;
     }
+    __syncthreads();
+  }
+  if (tid == 0) {
     // z = H2F(FC-Z, x_l || v_l); f_v(z) = prod_j (1 + x_j^{-1} z^{2^{l-j+1}})
     sha::Hasher hz;
     sha::xmd_begin(hz);
@@ -388,7 +398,17 @@ __global__ void __launch_bounds__(64) kv_compare(const VCtx *cs, uint32_t n) {
   if (ok) atomicOr(c.flags, VFLAG_ACCEPT);
 }
 
+// the three final exponentiations' inputs of every proof side by side (products of the pairs
+// 0, 1..2 and 3..), so that one launch takes them all: G[3 p + r] = F[p npair + {0, 1, 3}[r]]
+__global__ void __launch_bounds__(TPB) kv_fe_gather(const fp12 *F, uint64_t npair, uint32_t n, fp12 *G) {
+  uint64_t id = gtid();
+  if (id >= 3ull * n) return;
+  uint64_t p = id / 3, r = id % 3;
+  G[id] = F[p * npair + (r == 2 ? 3 : r)];
+}
+
 namespace kv {
+void fe_gather(const fp12 *F, uint64_t npair, uint32_t n, fp12 *G, hipStream_t st) { L1(kv_fe_gather, 3ull * n, F, npair, n, G); }
 void decode(const VCtx *cs, uint32_t n, uint32_t tmax, uint32_t lK, uint32_t lM, hipStream_t st) {
   uint32_t items = tmax + 4 * lK + 3 + 2 * lK + lM + 2;
   LAUNCH(kv_decode, dim3(nblk(items), n), dim3(TPB), 0, cs);
@@ -865,19 +885,31 @@ __global__ void __launch_bounds__(256) kve_transcript(VECtx c) {
     for (int w = 0; w < 8; w++) hx.word(sigma[w]);
     hx.u64(0);
     s_r0 = sha::xmd_finish_fr(hx, DSTR_EVAL);
-    for (uint32_t j = 0; j < l; j++) {
-      sha::Hasher h2;
-      sha::xmd_begin(h2);
-      if (j > 0) h2.field<FpR>(c.x[j - 1]);
-      h2.gt(c.Lgt[j]);
-      h2.g1(c.Lg1[j]);
-      h2.gt(c.Rgt[j]);
-      h2.g1(c.Rg1[j]);
-      fe x = sha::xmd_finish_fr(h2, DSTR_FC_X);
+  }
+  // round challenges, the workgroup hashing together (as in kv_transcript)
+  __shared__ uint32_t xmsg[16 + 8 + 2 * (96 + 16) + 32], xt2[16];
+  for (uint32_t j = 0; j < l; j++) {
+    const int pre = j > 0 ? 8 : 0;
+    if (tid < 16) xmsg[tid] = 0;  // Z_pad
+    const int e = j > 0 ? tid - 1 : tid;
+    if (j > 0 && tid == 0) sha::put_words<FpR>(xmsg + 16, c.x[j - 1]);
+    if (e >= 0 && e < 28) {
+      int side = e / 14, q = e % 14;
+      const fe *src = q < 12 ? reinterpret_cast<const fe *>(side ? c.Rgt + j : c.Lgt + j) + q
+                             : reinterpret_cast<const fe *>(side ? c.Rg1 + j : c.Lg1 + j) + (q - 12);
+      sha::put_words<FpP>(xmsg + 16 + pre + 112 * side + 8 * q, *src);
+    }
+    __syncthreads();
+    fe x = sha::xmd_fr_coop(sha::Coop{tid, 256}, xmsg, 4 * (pre + 224), DSTR_FC_X, xt2);
+    fe xi = f_inv_uniform<FpR>(x, bn::R_R3);
+    if (tid == 0) {
       if (fe_is_zero(x)) atomicOr(c.flags, VFLAG_BAD_PROOF);
       c.x[j] = x;
-      c.xinv[j] = fr_inv_fast(x);
+      c.xinv[j] = xi;
     }
+    __syncthreads();
+  }
+  if (tid == 0) {
     sha::Hasher hz;
     sha::xmd_begin(hz);
     hz.field<FpR>(c.x[l - 1]);

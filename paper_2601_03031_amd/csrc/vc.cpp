@@ -1385,7 +1385,7 @@ static int verify_many(const vc_params *pp, const uint8_t *Cb, uint32_t b, uint3
          o_fzg2 = c.take<g2_aff>(n), o_gtb = c.take<fp12>(2 * n * lK), o_gtp = c.take<fp12>(2 * n * lK),
          o_gto = c.take<fp12>(n * (2 * lK + 1)), o_Cg1 = c.take<g1_aff>(n), o_bA = c.take<g1_aff>(n),
          o_pp = c.take<g1_aff>(n * npair), o_pq = c.take<g2_aff>(n * npair), o_F = c.take<fp12>(n * npair),
-         o_E = c.take<fp12>(3 * n), o_fl = c.take<int>(n);
+         o_E = c.take<fp12>(3 * n), o_G = c.take<fp12>(3 * n), o_fl = c.take<int>(n);
   // the three product trees below run one after another and share one counter area
   const uint64_t tc = tree_counters(npair > 2 * lK + 1 ? npair : 2 * lK + 1);
   if (int rc = ensure_cnt(ex, n * tc, st)) return rc;
@@ -1436,10 +1436,10 @@ static int verify_many(const vc_params *pp, const uint8_t *Cb, uint32_t b, uint3
     ks::miller(at<g1_aff>(d, o_pp), 1, at<g2_aff>(d, o_pq), 1, (uint64_t)n * npair, F, st);
     ks::f12_reduce(F + 1, n, npair, 2, ex->cnt, st);
     ks::f12_reduce(F + 3, n, npair, npair - 3, ex->cnt, st);
-    // E[3q + r]: input q even to out0[(q / 2) 6], odd to out1 = out0 + 3
-    ks::final_exp(F, npair, n, E, E + 3, 6, st);
-    ks::final_exp(F + 1, npair, n, E + 1, E + 4, 6, st);
-    ks::final_exp(F + 3, npair, n, E + 2, E + 5, 6, st);
+    // all 3n final exponentiations in one launch: E[s] (input s even to out0[(s / 2) 2], odd to
+    // out1 = out0 + 1)
+    kv::fe_gather(F, npair, n, at<fp12>(d, o_G), st);
+    ks::final_exp(at<fp12>(d, o_G), 1, 3ull * n, E, E + 1, 2, st);
     kv::compare(cs, n, st);
     e = hipGetLastError();
   }
@@ -1541,7 +1541,7 @@ VC_API int vc_verify_eval(const vc_params *pp, const uint8_t C[384], const uint8
          o_g2o = w.take<g2_aff>(1 + lM), o_gts = w.take<fe>(2 * l), o_gtb = w.take<fp12>(2 * l),
          o_gtp = w.take<fp12>(2 * l), o_gto = w.take<fp12>(2 * l + 1), o_pp = w.take<g1_aff>(npair),
          o_pq = w.take<g2_aff>(npair), o_F = w.take<fp12>(npair), o_E = w.take<fp12>(3), o_Cg1 = w.take<g1_aff>(1),
-         o_bA = w.take<g1_aff>(1), o_fl = w.take<int>(1), o_ctx = w.take<VCtx>(1);
+         o_bA = w.take<g1_aff>(1), o_fl = w.take<int>(1), o_ctx = w.take<VCtx>(1), o_G = w.take<fp12>(3);
   if (int rc = ensure_cnt(ex, tree_counters(npair > 2 * l + 1 ? npair : 2 * l + 1), st)) return rc;
   void *d = nullptr;
   CK(hipMalloc(&d, w.off));
@@ -1582,9 +1582,8 @@ VC_API int vc_verify_eval(const vc_params *pp, const uint8_t C[384], const uint8
     ks::miller(c.pp, 1, c.pq, 1, npair, F, st);
     ks::f12_reduce(F + 1, 1, npair, 2, ex->cnt, st);
     ks::f12_reduce(F + 3, 1, npair, npair - 3, ex->cnt, st);
-    ks::final_exp(F, npair, 1, E, E + 3, 6, st);
-    ks::final_exp(F + 1, npair, 1, E + 1, E + 4, 6, st);
-    ks::final_exp(F + 3, npair, 1, E + 2, E + 5, 6, st);
+    kv::fe_gather(F, npair, 1, at<fp12>(d, o_G), st);
+    ks::final_exp(at<fp12>(d, o_G), 1, 3, E, E + 1, 2, st);
     kv::compare(at<VCtx>(d, o_ctx), 1, st);
     e = hipGetLastError();
   }

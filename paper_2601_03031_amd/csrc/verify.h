@@ -127,4 +127,5 @@ void decode(const VCtx *cs, uint32_t n, uint32_t tmax, uint32_t lK, uint32_t lM,
 void transcript(const VCtx *cs, uint32_t n, hipStream_t st);
 void assemble(const VCtx *cs, uint32_t n, hipStream_t st);
 void compare(const VCtx *cs, uint32_t n, hipStream_t st);
+void fe_gather(const fp12 *F, uint64_t npair, uint32_t n, fp12 *G, hipStream_t st);
 }  // namespace kv
