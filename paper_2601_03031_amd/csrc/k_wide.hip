@@ -108,6 +108,19 @@ __global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(const void *Ain, const voi
   wst(Bout, k * K + i, b);
 }
 
+// v_j = v_L o v_R^{1/x_j} (Eq. folding) on the wide layout: the direct rounds, where the batches
+// fill the device and throughput decides; Vout may be Vin
+__global__ void __launch_bounds__(TPBW) kw_oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K,
+                                                     uint64_t nb, uint64_t h, uint32_t j, uint32_t lK) {
+  uint64_t id = wgid();
+  if (id >= nb * h) return;
+  uint64_t k = id / h, i = id % h, slot = k * lK + (j - 1);
+  uint32_t kk[8];
+  wscalar(kk, wld<fe>(Xinv, slot));
+  g2_jac t = mul_any(wld<g2_aff>(Vin, k * K + h + i), kk);
+  wst(Vout, k * K + i, jac_to_aff(jac_madd(t, wld<g2_aff>(Vin, k * K + i))));
+}
+
 // HyperEval terms (canonical differences of the folded table times PST keys)
 __global__ void __launch_bounds__(TPBW) kw_hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S) {
   uint64_t id = wgid();
@@ -226,6 +239,10 @@ void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t 
 void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv, const void *dec, uint64_t K,
                 uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
   LW(kw_oa_fold_g1, nb * h, Ain, Bin, Aout, Bout, Xinv, static_cast<const glv::Dec *>(dec), K, nb, h, j, lK);
+}
+void oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
+                uint32_t lK, hipStream_t st) {
+  LW(kw_oa_fold_g2, nb * h, Vin, Vout, Xinv, K, nb, h, j, lK);
 }
 void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st) {
   LW(kw_hyper_terms, lM * (M / 2), g, ek, M, lM, S);

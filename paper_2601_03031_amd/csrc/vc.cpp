@@ -165,6 +165,9 @@ static constexpr uint64_t AHEAD_MAX_PAIRS = 4096;
 static constexpr uint64_t DIRECT_MIN = 512;
 // folds of at most this many pairs (batches x h) run as four-part split multiplications
 static constexpr uint64_t FOLD_SPLIT_MAX = 256;
+// direct-round G2 folds of at least this many (batch, index) pairs run on the wide layout (8
+// lanes per element, throughput), smaller ones on the engine (GLS, latency)
+static constexpr uint64_t WIDE_FOLD_MIN = 4096;
 // bases per block of the KZG proof's G2 MSM (times 32 windows: at most 1024 entries)
 static constexpr uint32_t KZG_S = 32;
 // KZG proofs of at most this many split jobs (4 per term) run as split multiplications
@@ -795,7 +798,8 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
       kl::glv_dec(X, nb, j, lK, gdec, sg);
       klw::oa_fold_g1(Ab[cur], Bb[cur], Ab[nxt], Bb[nxt], Xinv, gdec, K, nb, h, j, lK, sg);
       if (int rc2 = stream_wait(ex, 5, st, sf)) return rc2;
-      ks::oa_fold_g2(Vb[cur], Vb[nxt], Xinv, K, nb, h, j, lK, sf);
+      if (nb * h >= WIDE_FOLD_MIN) klw::oa_fold_g2(Vb[cur], Vb[nxt], Xinv, K, nb, h, j, lK, sf);
+      else ks::oa_fold_g2(Vb[cur], Vb[nxt], Xinv, K, nb, h, j, lK, sf);
       if (int rc2 = stream_wait(ex, 11, sg, st)) return rc2;
       if (int rc2 = stream_wait(ex, 12, sf, st)) return rc2;
     }
