@@ -108,6 +108,19 @@ __global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(const void *Ain, const voi
   wst(Bout, k * K + i, b);
 }
 
+// Miller values of the direct rounds (the pairs of L_j and R_j, laid out as by ks_oa_miller) on
+// the wide layout, for rounds whose batches fill the device; each value differs from the
+// engine's only by factors the final exponentiation removes
+__global__ void __launch_bounds__(TPBW) kw_oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h,
+                                                    void *F) {
+  uint64_t id = wgid();
+  if (id >= nb * 2 * h) return;
+  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
+  g1_aff P = wld<g1_aff>(A, side ? k * K + i : k * K + h + i);
+  g2_aff Q = wld<g2_aff>(V, side ? k * K + h + i : k * K + i);
+  wst(F, (k * 2 + side) * (K / 2) + i, miller_loop(P, Q));
+}
+
 // v_j = v_L o v_R^{1/x_j} (Eq. folding) on the wide layout: the direct rounds, where the batches
 // fill the device and throughput decides; Vout may be Vin
 __global__ void __launch_bounds__(TPBW) kw_oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K,
@@ -239,6 +252,9 @@ void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t 
 void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv, const void *dec, uint64_t K,
                 uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
   LW(kw_oa_fold_g1, nb * h, Ain, Bin, Aout, Bout, Xinv, static_cast<const glv::Dec *>(dec), K, nb, h, j, lK);
+}
+void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st) {
+  LW(kw_oa_miller, nb * 2 * h, A, V, K, nb, h, F);
 }
 void oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
                 uint32_t lK, hipStream_t st) {

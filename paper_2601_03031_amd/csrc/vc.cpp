@@ -165,8 +165,8 @@ static constexpr uint64_t AHEAD_MAX_PAIRS = 4096;
 static constexpr uint64_t DIRECT_MIN = 512;
 // folds of at most this many pairs (batches x h) run as four-part split multiplications
 static constexpr uint64_t FOLD_SPLIT_MAX = 256;
-// direct-round G2 folds of at least this many (batch, index) pairs run on the wide layout (8
-// lanes per element, throughput), smaller ones on the engine (GLS, latency)
+// direct-round Miller loops and G2 folds of at least this many (batch, index) pairs run on the
+// wide layout (8 lanes per element, throughput), smaller ones on the engine (latency)
 static constexpr uint64_t WIDE_FOLD_MIN = 4096;
 // bases per block of the KZG proof's G2 MSM (times 32 windows: at most 1024 entries)
 static constexpr uint32_t KZG_S = 32;
@@ -737,7 +737,8 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
       }
       kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
       if (int rc2 = ev_mark(ex, 3, sg)) return rc2;
-      ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
+      if (nb * h >= WIDE_FOLD_MIN) klw::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
+      else ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
       // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
       // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
       if (j == 1 && split_round(1)) {

@@ -172,3 +172,23 @@ def test_n20_b1_sampled(vc):
         proof = vc.vc_proof_get(gpr, i)
         assert proof == O.naive_proof(opp, m_le, b, i), i
         assert O.verify(opp, gcm.C, b, i, ints[i], proof) == 1, i
+
+
+def test_n14_b1_direct_wide_sampled(vc):
+    """N = 2^14, b = 1: 128 batches fill the device, so the rounds run direct, the first ones
+    (at least 4096 pairs) with the Miller loops and G2 folds on the wide layout.  Sampled
+    proofs against the oracle's one-proof-at-a-time construction and its verifier."""
+    L, b = 14, 1
+    say("case L=14 b=1 (direct rounds, sampled)")
+    limbs = I.entries(1 << L, 7, 256)
+    ints = I.limbs_to_ints(limbs)
+    gpp = vc.vc_setup(L, SEED, 0)
+    gcm = vc.vc_commit(gpp, dev_entries(limbs), 256)
+    gpr = vc.vc_open_all(gpp, gcm, b)
+    torch.cuda.synchronize()
+    opp = O.Params(L, SEED)
+    m_le = I.limbs_to_bytes(limbs)
+    for i in (0, 129, 8191, 16383):
+        proof = vc.vc_proof_get(gpr, i)
+        assert proof == O.naive_proof(opp, m_le, b, i), i
+        assert O.verify(opp, gcm.C, b, i, ints[i], proof) == 1, i
