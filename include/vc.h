@@ -12,8 +12,10 @@
  * BN_SNARK1), optimal ate pairing.
  *
  * Conventions for every entry point:
- *  - Return value: VC_OK (0) or a negative VC_E* code; vc_verify returns 1 (accept),
- *    0 (reject) or a negative code.  vc_strerror() names a code.
+ *  - Return value: VC_OK (0) or a negative VC_E* code; the verifiers (vc_verify,
+ *    vc_verify_all, vc_verify_subarray, vc_verify_eval) return 1 (accept), 0 (reject) or a
+ *    negative code.  vc_strerror() names a code (with the HIP error text of the calling
+ *    thread's last failure for VC_EDEVICE).
  *  - Device pointers are borrowed for the duration of the call and must be device
  *    memory on the params' device.  `stream` is a hipStream_t (NULL = default
  *    stream); work is ordered on it and every call is synchronous on return.
@@ -22,9 +24,11 @@
  *    least six hardware queues (environment GPU_MAX_HW_QUEUES, read by HIP at its first
  *    device use; the Python package raises it to 16), otherwise they share queues and run
  *    partly in sequence, with the same results.
- *  - Handles (vc_params, vc_commitment, vc_proofs) own their device memory and are
- *    released with the matching *_free; a vc_proofs handle does not reference the
- *    commitment it was made from.
+ *  - Handles (vc_params, vc_commitment, vc_proofs, vc_exec, vc_server) own their device
+ *    memory and are released with the matching *_free, in any order (each keeps its own
+ *    device id; a release reports nothing and leaves no HIP error behind).  A commitment
+ *    or proof bundle is used only while its params live; a vc_proofs handle does not
+ *    reference the commitment it was made from.
  *  - Field entries and scalars are canonical (< r) 32-byte little-endian integers
  *    unless stated otherwise; serialized group elements are canonical big-endian:
  *    G1 64 B (x || y), G2 128 B (x.c0 || x.c1 || y.c0 || y.c1), G_T 384 B (12 F_p
