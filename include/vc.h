@@ -169,6 +169,15 @@ int vc_subarray_proof_get(const vc_proofs *pr, uint64_t j, uint8_t *buf, size_t 
  * (lengths, C, an entry >= r). */
 int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_t b, uint64_t j, const uint8_t *m_j,
                        const uint8_t *proof, size_t len);
+/* All K sub-array proofs at once: m (device) holds the N entries (32 little-endian bytes
+ * each), proofs (device, 16-byte aligned) the K sub-array proofs in order (proof j after
+ * proof j - 1, each vc_subarray_proof_len(log N, t_k) bytes), len bytes in all.  Every C_j
+ * is recomputed (PC.Commit) and must be entry j of its proof's block; proofs are compared
+ * with the first of their batch (honest ones are equal) and the FC part is checked once per
+ * batch and for every proof that differs.  1 if all are accepted, 0 if one is rejected,
+ * VC_EINVAL for malformed inputs; n_single (optional): the proofs checked by the verifier. */
+int vc_verify_subarrays_all(const vc_params *pp, const uint8_t C[384], uint32_t b, const void *m, const void *proofs,
+                            uint64_t len, uint64_t *n_single);
 
 /* Evaluation proof of the committed vector's multilinear extension at a point (section 4.3,
  * compatibility with multilinear zkSNARKs): r holds log N little-endian 32-byte field

@@ -75,6 +75,7 @@ def lib():
         L.vc_subarray_proof_len.argtypes = [u32, u32]
         L.vc_subarray_proof_get.argtypes = [vp, u64, vp, sz, C.POINTER(sz)]
         L.vc_verify_subarray.argtypes = [vp, u8p, u32, u64, u8p, u8p, sz]
+        L.vc_verify_subarrays_all.argtypes = [vp, u8p, u32, vp, vp, u64, C.POINTER(u64)]
         L.vc_verify_all.argtypes = [vp, u8p, u32, vp, vp, u64, u8p, C.POINTER(u64)]
         L.vc_open_all_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), u32, C.POINTER(vp),
                                         C.POINTER(vp)]
@@ -298,6 +299,15 @@ def vc_subarray_proof_get(pr: Proofs, j: int) -> bytes:
 def vc_verify_subarray(pp: Params, C_bytes: bytes, b: int, j: int, m_j: bytes, proof: bytes) -> int:
     """m_j: the M entries of sub-array j, 32 little-endian bytes each."""
     return _check(lib().vc_verify_subarray(pp.ptr, C_bytes, b, j, m_j, proof, len(proof)), "vc_verify_subarray")
+
+
+def vc_verify_subarrays_all(pp: Params, C_bytes: bytes, b: int, m, proofs):
+    """m: device tensor of N x 32 little-endian bytes; proofs: device uint8 tensor holding the K
+    sub-array proofs in order.  Returns (1 all accepted / 0, proofs checked by the verifier)."""
+    ns = C.c_uint64(0)
+    v = _check(lib().vc_verify_subarrays_all(pp.ptr, C_bytes, b, C.c_void_p(m.data_ptr()), C.c_void_p(proofs.data_ptr()),
+                                             proofs.numel(), C.byref(ns)), "vc_verify_subarrays_all")
+    return v, ns.value
 
 
 def vc_proofs_serialize(pr: Proofs):

@@ -995,3 +995,43 @@ void decode(const VECtx &c, hipStream_t st) { L1(kve_decode, 1 + 4 * c.lK + 3 + 
 void transcript(const VECtx &c, hipStream_t st) { LAUNCH(kve_transcript, dim3(1), dim3(256), 0, c); }
 void assemble(const VECtx &c, hipStream_t st) { LAUNCH(kve_assemble, dim3(1), dim3(64), 0, c); }
 }  // namespace kve
+
+// ------------------------------------------------------------------ all sub-array proofs at once
+// A workgroup per subvector j: its proof against the first proof of its batch (16-byte words;
+// honest proofs of a batch are equal), and entry j of its block against the commitment
+// recomputed from m_j.  Proofs that differ join the list checked alone.
+__global__ void __launch_bounds__(256) ksa_check(const uint8_t *proofs, uint64_t K, uint32_t b, uint64_t nb,
+                                                 uint64_t len_full, uint64_t len_last, const g1_aff *Cre,
+                                                 uint64_t *oddlist, uint32_t *oddcnt, int *flags) {
+  __shared__ int diff;
+  uint64_t j = blockIdx.x;
+  if (j >= K) return;
+  const int t = threadIdx.x;
+  uint64_t k = j / b, j0 = k * b, len = k == nb - 1 ? len_last : len_full;
+  const uint8_t *P = proofs + k * (uint64_t)b * len_full + (j - j0) * len;
+  const uint8_t *R = proofs + k * (uint64_t)b * len_full;
+  if (t == 0) diff = 0;
+  __syncthreads();
+  bool d = false;
+  if (j != j0) {
+    const uint4 *p4 = reinterpret_cast<const uint4 *>(P), *r4 = reinterpret_cast<const uint4 *>(R);
+    for (uint64_t q = t; q < len / 16; q += 256) {
+      uint4 u = p4[q], v = r4[q];
+      d |= u.x != v.x || u.y != v.y || u.z != v.z || u.w != v.w;
+    }
+  }
+  if (d) atomicOr(&diff, 1);
+  __syncthreads();
+  if (t != 0) return;
+  g1_aff e;
+  bool ok = g1_decompress(P + 32 * (j - j0), e);
+  if (!ok || !fe_eq(e.x, Cre[j].x) || !fe_eq(e.y, Cre[j].y)) atomicOr(flags, VFLAG_BAD_PROOF);
+  if (diff) oddlist[atomicAdd(oddcnt, 1u)] = j;
+}
+
+namespace ksa {
+void check(const uint8_t *proofs, uint64_t K, uint32_t b, uint64_t nb, uint64_t len_full, uint64_t len_last,
+           const g1_aff *Cre, uint64_t *oddlist, uint32_t *oddcnt, int *flags, hipStream_t st) {
+  LAUNCH(ksa_check, dim3((unsigned)K), dim3(256), 0, proofs, K, b, nb, len_full, len_last, Cre, oddlist, oddcnt, flags);
+}
+}  // namespace ksa

@@ -1371,7 +1371,8 @@ VC_API int vc_proofs_export(const vc_proofs *pr, int what, uint64_t k, void *dst
 // PST check at Bin(a).  Proof q is entry idx[q]; its bytes (vc_proof_len(L, t) of them) are at
 // the device address pf[q] and its entry (32 bytes, little-endian) at mi[q]; Cb: the commitment
 // bytes on the device.  verdict[q]: 1 accept, 0 reject, VC_EINVAL malformed C or entry.
-// fc_only: sub-array proofs (block and FC proof), the block's entry j checked against cj_expect.
+// fc_only: sub-array proofs (block and FC proof), the block's entry j checked against
+// cj_expect[j] (an array over the K subvectors).
 static int verify_many(const vc_params *pp, const uint8_t *Cb, uint32_t b, uint32_t n, const uint64_t *idx,
                        const uint8_t *const *pf, const uint8_t *const *mi, hipStream_t st, int *verdict,
                        bool fc_only = false, const g1_aff *cj_expect = nullptr) {
@@ -1422,7 +1423,7 @@ static int verify_many(const vc_params *pp, const uint8_t *Cb, uint32_t b, uint3
     x.pp = at<g1_aff>(d, o_pp) + q * npair; x.pq = at<g2_aff>(d, o_pq) + q * npair; x.F = at<fp12>(d, o_F) + q * npair;
     x.E = at<fp12>(d, o_E) + 3 * q; x.g1beta = pp->g1beta; x.vk = pp->vk; x.flags = at<int>(d, o_fl) + q;
     x.fc_only = fc_only ? 1 : 0;
-    x.cj_expect = cj_expect;
+    x.cj_expect = cj_expect ? cj_expect + j : nullptr;
     if (fc_only) x.mpath = nullptr;
   }
   const VCtx *cs = at<VCtx>(d, o_ctx);
@@ -1619,7 +1620,7 @@ VC_API int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_
   const uint64_t nslice = (M + S - 1) / S;
   Carve w;
   size_t o_pf = w.take<uint8_t>(len), o_C = w.take<uint8_t>(384), o_m = w.take<fe>(M), o_err = w.take<int>(1),
-         o_part = w.take<g1_jac>(nslice), o_cj = w.take<g1_aff>(1);
+         o_part = w.take<g1_jac>(nslice), o_cj = w.take<g1_aff>(K);
   void *d = nullptr;
   CK(hipMalloc(&d, w.off));
   struct Free {
@@ -1633,7 +1634,7 @@ VC_API int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_
   CK(hipMemsetAsync(err, 0, sizeof(int), st));
   kl::check_fr(at<fe>(d, o_m), M, err, st);
   kl::msm_slices(at<fe>(d, o_m), 1, M, NWIN, S, pp->table, at<g1_jac>(d, o_part), st);
-  klw::sum_g1(at<g1_jac>(d, o_part), 1, nslice, at<g1_aff>(d, o_cj), st);
+  klw::sum_g1(at<g1_jac>(d, o_part), 1, nslice, at<g1_aff>(d, o_cj) + j, st);  // entry j of the K
   int herr = 0;
   CK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -1643,6 +1644,86 @@ VC_API int vc_verify_subarray(const vc_params *pp, const uint8_t C[384], uint32_
   int v = 0;
   if (int rc = verify_many(pp, at<uint8_t>(d, o_C), b, 1, &i, pf, mi, st, &v, true, at<g1_aff>(d, o_cj))) return rc;
   return v;
+}
+
+// All K sub-array proofs at once (section 4.3): every C_j recomputed with the commit's MSM
+// and found at its place in its proof's block; proofs compared with the first of their batch;
+// one FC check per batch and per differing proof, in one pass of the verifier.
+VC_API int vc_verify_subarrays_all(const vc_params *pp, const uint8_t C[384], uint32_t b, const void *m,
+                                   const void *proofs, uint64_t len, uint64_t *n_single) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (n_single) *n_single = 0;
+  if (!pp || !C || !m || !proofs || b < 1 || b > pp->K) return VC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(proofs) & 15) != 0) return VC_EINVAL;
+  const uint64_t K = pp->K, M = pp->M, N = pp->N, nb = (K + b - 1) / b;
+  const uint32_t t_last = (uint32_t)(K - (nb - 1) * b);
+  const uint64_t len_full = vc_subarray_proof_len(pp->L, b), len_last = vc_subarray_proof_len(pp->L, t_last);
+  if (len != (nb - 1) * b * len_full + t_last * len_last) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  vc_exec *ex = pp->ex;
+  hipStream_t st = ex->main;
+  uint32_t S = (uint32_t)(8192 / NWIN);
+  if (S > M) S = (uint32_t)M;
+  const uint64_t nslice = (M + S - 1) / S;
+  Carve w;
+  size_t o_Cb = w.take<uint8_t>(384), o_err = w.take<int>(1), o_fl = w.take<int>(1), o_oc = w.take<uint32_t>(1),
+         o_part = w.take<g1_jac>(K * nslice), o_Cre = w.take<g1_aff>(K), o_ol = w.take<uint64_t>(K);
+  void *d = nullptr;
+  CK(hipMalloc(&d, w.off));
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } free_d{d};
+  const uint8_t *P = static_cast<const uint8_t *>(proofs);
+  g1_aff *Cre = at<g1_aff>(d, o_Cre);
+  CK(hipMemcpyAsync(at<void>(d, o_Cb), C, 384, hipMemcpyHostToDevice, st));
+  CK(hipMemsetAsync(at<void>(d, o_err), 0, sizeof(int), st));
+  CK(hipMemsetAsync(at<void>(d, o_fl), 0, sizeof(int), st));
+  CK(hipMemsetAsync(at<void>(d, o_oc), 0, sizeof(uint32_t), st));
+  kl::check_fr(static_cast<const fe *>(m), N, at<int>(d, o_err), st);
+  kl::msm_slices(static_cast<const fe *>(m), K, M, NWIN, S, pp->table, at<g1_jac>(d, o_part), st);
+  klw::sum_g1(at<g1_jac>(d, o_part), K, nslice, Cre, st);
+  ksa::check(P, K, b, nb, len_full, len_last, Cre, at<uint64_t>(d, o_ol), at<uint32_t>(d, o_oc), at<int>(d, o_fl), st);
+  int herr = 0, flags = 0;
+  uint32_t nodd = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, at<int>(d, o_err), sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, at<int>(d, o_fl), sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nodd, at<uint32_t>(d, o_oc), sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "vc_verify_subarrays_all");
+  if (herr & VC_ERRBIT_RANGE) return VC_EINVAL;
+  if (flags & VFLAG_BAD_PROOF) return 0;
+  std::vector<uint64_t> single;
+  for (uint64_t k = 0; k < nb; k++) single.push_back(k * b);
+  if (nodd) {
+    std::vector<uint64_t> ol(nodd);
+    CK(hipMemcpy(ol.data(), at<uint64_t>(d, o_ol), nodd * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    single.insert(single.end(), ol.begin(), ol.end());
+  }
+  std::sort(single.begin(), single.end());
+  single.erase(std::unique(single.begin(), single.end()), single.end());
+  std::vector<uint64_t> idx(single.size());
+  std::vector<const uint8_t *> pfs(single.size()), mis(single.size(), at<uint8_t>(d, o_Cb));  // (no entry is read)
+  for (size_t q = 0; q < single.size(); q++) {
+    uint64_t j = single[q], k = j / b;
+    idx[q] = j * M;
+    pfs[q] = P + k * b * len_full + (j - k * b) * (k == nb - 1 ? len_last : len_full);
+  }
+  std::vector<int> v(single.size(), 0);
+  const uint32_t chunk = 4096;
+  for (size_t q0 = 0; q0 < single.size(); q0 += chunk) {
+    uint32_t nq = (uint32_t)std::min<size_t>(chunk, single.size() - q0);
+    if (int rc = verify_many(pp, at<uint8_t>(d, o_Cb), b, nq, idx.data() + q0, pfs.data() + q0, mis.data() + q0, st,
+                             v.data() + q0, true, Cre))
+      return rc;
+    if (n_single) *n_single += nq;
+    for (uint32_t q = 0; q < nq; q++) {
+      if (v[q0 + q] < 0) return v[q0 + q];
+      if (v[q0 + q] != 1) return 0;
+    }
+  }
+  return 1;
 }
 
 // ------------------------------------------------------------------ every proof at once

@@ -107,6 +107,11 @@ void transcript(const VECtx &c, hipStream_t st);
 void assemble(const VECtx &c, hipStream_t st);
 }  // namespace kve
 
+namespace ksa {
+void check(const uint8_t *proofs, uint64_t K, uint32_t b, uint64_t nb, uint64_t len_full, uint64_t len_last,
+           const g1_aff *Cre, uint64_t *oddlist, uint32_t *oddcnt, int *flags, hipStream_t st);
+}  // namespace ksa
+
 namespace kva {
 uint64_t nterms(const VACtx &c);
 void serialize(const PSCtx &c, hipStream_t st);

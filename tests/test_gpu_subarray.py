@@ -113,3 +113,65 @@ def test_subarrays_n16_b256(vc):
         p = vc.vc_subarray_proof_get(sub, j)
         assert p == vc.vc_proof_get(full, j * M)[:len(p)], j
         assert vc.vc_verify_subarray(pp, cm.C, b, j, m_le[32 * M * j: 32 * M * (j + 1)], p) == 1, j
+
+
+def _subarray_set(vc, sub, K):
+    return b"".join(vc.vc_subarray_proof_get(sub, j) for j in range(K))
+
+
+def _dev(b: bytes):
+    return torch.frombuffer(bytearray(b), dtype=torch.uint8).cuda()
+
+
+def test_verify_subarrays_all(vc):
+    L, b = 7, 3  # K = 8: batches of 3, 3, 2
+    limbs = I.entries(1 << L, 84, 256)
+    m_le = I.limbs_to_bytes(limbs)
+    pp = vc.vc_setup(L, SEED, 0)
+    cm = vc.vc_commit(pp, dev_entries(limbs, 256), 256)
+    sub = vc.vc_open_subarrays(pp, cm, b)
+    K, M = pp.K, pp.M
+    blob = _subarray_set(vc, sub, K)
+    offs = [0]
+    for j in range(K):
+        offs.append(offs[-1] + len(vc.vc_subarray_proof_get(sub, j)))
+    m = _dev(m_le)
+    v, ns = vc.vc_verify_subarrays_all(pp, cm.C, b, m, _dev(blob))
+    say("  sub-arrays all: %d (%d checked by the verifier)" % (v, ns))
+    assert v == 1 and ns == 3
+
+    def flip(data, pos, mask=1):
+        a = bytearray(data)
+        a[pos] ^= mask
+        return bytes(a)
+
+    # an entry of sub-array 4: its recomputed C_4 is not in the block
+    assert vc.vc_verify_subarrays_all(pp, cm.C, b, _dev(flip(m_le, 32 * (4 * M + 2))), _dev(blob))[0] == 0
+    # the FC proof of sub-array 4 alone (not its batch's first): checked by the verifier, rejected
+    fc_byte = 32 * 3 + 31
+    v, ns = vc.vc_verify_subarrays_all(pp, cm.C, b, m, _dev(flip(blob, offs[4] + fc_byte)))
+    assert v == 0 and ns == 4
+    opp = O.Params(L, SEED)
+    oop = O.Opening(O.Commitment(opp, m_le), b)
+    i = 4 * M
+    assert O.verify(opp, cm.C, b, i, I.limbs_to_ints(limbs)[i], flip(oop.proof(i), fc_byte)) == 0
+    # the FC proof of batch 1 in all its proofs (3, 4, 5): its first proof is rejected
+    bad = blob
+    for j in (3, 4, 5):
+        bad = flip(bad, offs[j] + fc_byte)
+    assert vc.vc_verify_subarrays_all(pp, cm.C, b, m, _dev(bad))[0] == 0
+    # entry 5 of the block in proof 5 only
+    assert vc.vc_verify_subarrays_all(pp, cm.C, b, m, _dev(flip(blob, offs[5] + 32 * 2 + 5, 0x04)))[0] == 0
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_verify_subarrays_all(pp, cm.C, b, m, _dev(blob[:-32]))
+    assert e.value.code == vc.VC_EINVAL
+
+
+def test_verify_subarrays_all_n16_b256(vc):
+    L, b = 16, 256
+    limbs = I.entries(1 << L, 2, 32)
+    pp = vc.vc_setup(L, SEED, 0)
+    cm = vc.vc_commit(pp, dev_entries(limbs, 32), 32)
+    sub = vc.vc_open_subarrays(pp, cm, b)
+    v, ns = vc.vc_verify_subarrays_all(pp, cm.C, b, _dev(I.limbs_to_bytes(limbs)), _dev(_subarray_set(vc, sub, pp.K)))
+    assert v == 1 and ns == 1
