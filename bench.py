@@ -222,12 +222,16 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2):
     rng = np.random.default_rng(seed)
     Ls = [int(x) for x in rng.integers(8, 19, n_jobs)]
     log("batched jobs: %d vectors, L in [8, 18]: setup and commit" % n_jobs)
-    params, jobs = {}, []
+    params, jobs, fmul = {}, [], 0
+    costs = op_costs()
     for i, L in enumerate(Ls):
         if L not in params:
             params[L] = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
         pp = params[L]
         limbs = I.entries(1 << L, 1000 * seed + i, 256)
+        # algorithmic field multiplications of this job's open-all (the commit's kernels left out)
+        w = work_model(L, min(L * L, pp.K), limbs, costs)
+        fmul += sum(v for k, v in w.items() if k not in ("k_msm_slices<OpsG1>", "ks_miller"))
         m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
         jobs.append((pp, V.vc_commit(pp, m, 256), min(L * L, pp.K)))
     torch.cuda.synchronize()
@@ -260,6 +264,11 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2):
     k_best = min(res["batch_ms"], key=lambda k: res["batch_ms"][k])
     res["speedup"] = round(seq_ms / res["batch_ms"][k_best], 2)
     res["best_setup"] = k_best
+    # device utilization: the jobs' algorithmic multiply-adds over the time, against the ALU peak
+    tops = lambda ms: fmul * MADS_PER_FMUL / (ms / 1e3) / 1e12
+    res["field_mults"] = int(fmul)
+    res["alu_frac"] = {"sequential": round(tops(seq_ms) / PEAK_MAD_TOPS, 5),
+                       "batched": round(tops(res["batch_ms"][k_best]) / PEAK_MAD_TOPS, 5)}
     res["hw_queues"] = int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)
     return res
 
