@@ -461,6 +461,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
                          const uint8_t *eval_r = nullptr) {
   if (!cpp || b < 1 || b > cpp->K) return VC_EINVAL;
   if (!footprint && (!cm || !out || !ex || cm->pp != cpp || ex->device != cpp->device)) return VC_EINVAL;
+  if (eval_r && (b != cpp->K || step2)) return VC_EINVAL;  // an evaluation proof is one batch, no Step 2
   const vc_params *pp = cpp;
   if (out) *out = nullptr;
   if (!footprint) CK(hipSetDevice(pp->device));
@@ -478,7 +479,6 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   pr->step2 = step2;
   const uint64_t with2 = step2 ? 1 : 0;  // Step 2 arrays are left out of a sub-array bundle
   const uint64_t ev = eval_r ? 1 : 0;
-  if (eval_r && (b != K || step2)) return VC_EINVAL;
   Carve c;
   pr->o_Cj = c.take<g1_aff>(K);
   pr->o_C = c.take<fp12>(1);
