@@ -62,6 +62,7 @@ def lib():
         L.or_proof_len.argtypes = [u32, u32]
         L.or_proof.argtypes = [vp, u64, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
         L.or_verify.argtypes = [vp, u8p, u64, u32, u64, u8p, u8p, C.c_size_t]
+        L.or_open_blocks.argtypes = [vp, u32, C.POINTER(C.c_uint64), u64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_naive_proof.argtypes = [vp, u8p, u64, u32, u64, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
         L.or_two_step_pst.argtypes = [vp, u64, C.c_void_p, C.c_void_p]
         L.or_eval_proof_len.restype = u64
@@ -281,6 +282,23 @@ class Commitment:
         if lib().or_eval_proof(self.h, b"".join(le32(x) for x in r), out, cap, C.byref(ln)) < 0:
             raise ValueError("eval proof")
         return out.raw[:ln.value]
+
+    def open_blocks(self, b: int, ks) -> list:
+        """Step 1 of OpenAll(b) for blocks ks only: per block the byte strings of
+        Opening.export's "fc_rounds", "fc_tail" and "fc_x"."""
+        ks = [int(k) for k in ks]
+        lK, n = self.pp.lK, len(ks)
+        arr = (C.c_uint64 * n)(*ks)
+        rounds, tail, xs = _buf(896 * lK * n), _buf(320 * n), _buf(32 * lK * n)
+        rc = lib().or_open_blocks(self.h, b, arr, n, rounds, tail, xs)
+        if rc < 0:
+            raise ValueError("open_blocks rc=%d" % rc)
+        out = []
+        for q in range(n):
+            out.append({"fc_rounds": rounds.raw[896 * lK * q:896 * lK * (q + 1)],
+                        "fc_tail": tail.raw[320 * q:320 * (q + 1)],
+                        "fc_x": xs.raw[32 * lK * q:32 * lK * (q + 1)]})
+        return out
 
     def two_step_pst(self, i: int):
         w, y = _buf(64 * self.pp.lM), _buf(32)

@@ -582,6 +582,63 @@ OR_API void or_open_free(void *o) {
     free(op);
 }
 
+/* per round: L.gt(384) L.g1(64) R.gt(384) R.g1(64) */
+static void export_fc_rounds(uint8_t *out, const fcproof *pr, uint32_t l) {
+    for (uint32_t j = 0; j < l; j++) {
+        uint8_t *q = out + j * 896;
+        fp12_to_bytes(q, &pr->Lgt[j]);
+        g1_to_bytes(q + 384, &pr->Lg1[j]);
+        fp12_to_bytes(q + 448, &pr->Rgt[j]);
+        g1_to_bytes(q + 832, &pr->Rg1[j]);
+    }
+}
+
+/* A_l(64) v_l(128) pi_v(128) */
+static void export_fc_tail(uint8_t *out, const fcproof *pr) {
+    g1_to_bytes(out, &pr->A);
+    g2_to_bytes(out + 64, &pr->v);
+    g2_to_bytes(out + 192, &pr->piv);
+}
+
+/*
+ * Step 1 of OpenAll(b) for the listed blocks only (section 4.2, Protocol 1 Step 1: one
+ * FC.BOpen per block S_k, Eq. genFCBatchProof), for parity checks of sizes whose whole
+ * OpenAll is too slow here.  Block q of the list is written as or_open_export's formats
+ * 0, 1 and 2 at rounds + 896*lK*q, tail + 320*q and xs + 32*lK*q.  Returns 0, or -1 for a
+ * bad b or block index, -2 for a zero challenge.
+ */
+OR_API int or_open_blocks(void *c, uint32_t b, const uint64_t *ks, uint64_t n, uint8_t *rounds,
+                          uint8_t *tail, uint8_t *xs) {
+    commitment *cm = (commitment *)c;
+    const params *pp = cm->pp;
+    uint64_t K = pp->K;
+    uint32_t l = pp->lK;
+    if (b < 1 || b > K) return -1;
+    uint64_t nb = (K + b - 1) / b;
+    for (uint64_t q = 0; q < n; q++)
+        if (ks[q] >= nb) return -1;
+    int fail = 0;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (uint64_t q = 0; q < n; q++) {
+        uint64_t lo = ks[q] * b, hi = lo + b < K ? lo + b : K;
+        uint32_t t = (uint32_t)(hi - lo);
+        uint64_t *idx = (uint64_t *)malloc(t * sizeof(uint64_t));
+        for (uint32_t i = 0; i < t; i++) idx[i] = lo + i;
+        fcproof pr;
+        memset(&pr, 0, sizeof pr);
+        if (fc_bopen(&pr, pp, &cm->C, cm->Cj, idx, t)) {
+            fail = 1;
+        } else {
+            export_fc_rounds(rounds + 896ULL * l * q, &pr, l);
+            export_fc_tail(tail + 320 * q, &pr);
+            for (uint32_t j = 0; j < l; j++) enc_fr(xs + 32ULL * (l * q + j), &pr.x[j]);
+        }
+        fcproof_free(&pr);
+        free(idx);
+    }
+    return fail ? -2 : 0;
+}
+
 /*
  * Bulk canonical arrays, for parity checks:
  *  0: per batch k (idx), per round: L.gt(384) L.g1(64) R.gt(384) R.g1(64)
@@ -600,24 +657,12 @@ OR_API int or_open_export(void *o, int what, uint64_t idx, uint8_t *out) {
     uint32_t l = pp->lK;
     if ((what <= 2) && idx >= op->nb) return -1;
     switch (what) {
-    case 0: {
-        fcproof *pr = &op->bt[idx];
-        for (uint32_t j = 0; j < l; j++) {
-            uint8_t *q = out + j * 896;
-            fp12_to_bytes(q, &pr->Lgt[j]);
-            g1_to_bytes(q + 384, &pr->Lg1[j]);
-            fp12_to_bytes(q + 448, &pr->Rgt[j]);
-            g1_to_bytes(q + 832, &pr->Rg1[j]);
-        }
+    case 0:
+        export_fc_rounds(out, &op->bt[idx], l);
         return 0;
-    }
-    case 1: {
-        fcproof *pr = &op->bt[idx];
-        g1_to_bytes(out, &pr->A);
-        g2_to_bytes(out + 64, &pr->v);
-        g2_to_bytes(out + 192, &pr->piv);
+    case 1:
+        export_fc_tail(out, &op->bt[idx]);
         return 0;
-    }
     case 2:
         for (uint32_t j = 0; j < l; j++) enc_fr(out + 32 * j, &op->bt[idx].x[j]);
         return 0;

@@ -43,6 +43,26 @@ def dev_u32(v: np.ndarray):
     return torch.from_numpy(v.astype(np.uint32).view(np.int32).copy()).cuda()
 
 
+# oracle objects of the large workloads, shared by the tests that check the same vector
+# (an oracle commitment at N = 2^20 takes tens of seconds); keyed by (L, seed, bits[, b])
+_ORACLE = {}
+
+
+def oracle_commitment(L, seed, bits, limbs):
+    key = (L, seed, bits)
+    if key not in _ORACLE:
+        opp = O.Params(L, SEED)
+        _ORACLE[key] = (opp, O.Commitment(opp, I.limbs_to_bytes(limbs)))
+    return _ORACLE[key]
+
+
+def oracle_opening(L, seed, bits, limbs, b):
+    key = (L, seed, bits, b)
+    if key not in _ORACLE:
+        _ORACLE[key] = O.Opening(oracle_commitment(L, seed, bits, limbs)[1], b)
+    return _ORACLE[key]
+
+
 class Case:
     """one workload run through both paths"""
 
@@ -52,12 +72,14 @@ class Case:
         N = 1 << L
         if zero:
             limbs = np.zeros((N, 4), dtype=np.uint64)
+            self.opp = O.Params(L, SEED)
+            self.ocm = O.Commitment(self.opp, I.limbs_to_bytes(limbs))
+            self.oop = O.Opening(self.ocm, b)
         else:
             limbs = I.entries(N, seed, bits)
+            self.opp, self.ocm = oracle_commitment(L, seed, bits, limbs)
+            self.oop = oracle_opening(L, seed, bits, limbs, b) if L >= 20 else O.Opening(self.ocm, b)
         self.m = I.limbs_to_ints(limbs)
-        self.opp = O.Params(L, SEED)
-        self.ocm = O.Commitment(self.opp, I.limbs_to_bytes(limbs))
-        self.oop = O.Opening(self.ocm, b)
         say("  oracle done; GPU setup/commit/open_all")
         self.gpp = V.vc_setup(L, SEED, 0)
         if bits == 32:
@@ -153,27 +175,6 @@ def test_full_n20_b400(vc):
     compare_all(vc, cs, proofs=sample_indices(1 << 20, 1024, 400, 4))
 
 
-def test_n20_b1_sampled(vc):
-    """N = 2^20, b = 1 (1024 FC batches) is beyond the oracle's full OpenAll here; sampled
-    proofs are checked against the oracle's one-proof-at-a-time construction (no shared
-    work) and its verifier."""
-    L, b = 20, 1
-    say("case L=20 b=1 (sampled)")
-    limbs = I.entries(1 << L, 3, 256)
-    ints = I.limbs_to_ints(limbs)
-    gpp = vc.vc_setup(L, SEED, 0)
-    gcm = vc.vc_commit(gpp, dev_entries(limbs), 256)
-    gpr = vc.vc_open_all(gpp, gcm, b)
-    torch.cuda.synchronize()
-    say("  GPU done")
-    opp = O.Params(L, SEED)
-    m_le = I.limbs_to_bytes(limbs)
-    for i in (0, 777777):
-        proof = vc.vc_proof_get(gpr, i)
-        assert proof == O.naive_proof(opp, m_le, b, i), i
-        assert O.verify(opp, gcm.C, b, i, ints[i], proof) == 1, i
-
-
 def test_n14_b1_direct_wide_sampled(vc):
     """N = 2^14, b = 1: 128 batches fill the device, so the rounds run direct, the first ones
     (at least 4096 pairs) with the Miller loops and G2 folds on the wide layout.  Sampled
@@ -192,3 +193,80 @@ def test_n14_b1_direct_wide_sampled(vc):
         proof = vc.vc_proof_get(gpr, i)
         assert proof == O.naive_proof(opp, m_le, b, i), i
         assert O.verify(opp, gcm.C, b, i, ints[i], proof) == 1, i
+
+
+def dev_le32(limbs: np.ndarray):
+    """the entries as N x 32 little-endian bytes on the device (what the verifiers read)"""
+    return torch.frombuffer(bytearray(I.limbs_to_bytes(limbs)), dtype=torch.uint8).cuda()
+
+
+def verify_every_proof(V, gpp, gcm, gpr, b, limbs):
+    """all N proofs serialized on the device and checked by vc_verify_all (the random-weight
+    combination of every PST check plus the FC check of every batch)"""
+    ser = V.vc_proofs_serialize(gpr)
+    v, alone = V.vc_verify_all(gpp, gcm.C, b, dev_le32(limbs), ser, bytes(range(32)))
+    say("  verify_all over %d proofs: %d (%d checked alone)" % (gpp.N, v, alone))
+    assert v == 1
+    del ser
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_full_n16_b1_u32(vc):
+    """N = 2^16, b = 1 (256 FC batches, the device-full direct rounds with wide Miller loops
+    and G2 folds), 32-bit entries (seed 2): every batch's fc_x / fc_rounds / fc_tail and every
+    Step-2 array against the oracle's whole OpenAll, sampled serialized proofs, and every
+    proof through the GPU verifier."""
+    cs = Case(vc, 16, 1, seed=2, bits=32)
+    compare_all(vc, cs, proofs=sample_indices(1 << 16, 256, 1, 5, extra=(129 * 256, 200 * 256 + 77)))
+    verify_every_proof(vc, cs.gpp, cs.gcm, cs.gpr, 1, I.entries(1 << 16, 2, 32))
+
+
+@pytest.mark.timeout(900)
+def test_full_n20_b20(vc):
+    """N = 2^20, b = 20 (52 FC batches, the last with t = 4), full-width entries (seed 3):
+    every batch's FC arrays and every Step-2 array against the oracle's whole OpenAll;
+    sampled proofs including the first and last of the short batch and of middle batches;
+    every proof through the GPU verifier."""
+    cs = Case(vc, 20, 20, seed=3, bits=256)
+    M = 1024
+    extra = (1020 * M, 1020 * M + 1, 1023 * M + 1023, 500 * M, 519 * M + 1023, 260 * M + 5, 279 * M)
+    compare_all(vc, cs, proofs=sample_indices(1 << 20, M, 20, 6, extra=extra))
+    verify_every_proof(vc, cs.gpp, cs.gcm, cs.gpr, 20, I.entries(1 << 20, 3, 256))
+
+
+@pytest.mark.timeout(900)
+def test_n20_b1_blocks(vc):
+    """N = 2^20, b = 1 (1024 FC batches): the oracle's whole OpenAll is beyond a test here, so
+    34 batches spread over the range (first and last included) are computed by the oracle's
+    Step 1 for those blocks alone and compared whole; the Step-2 arrays (which do not depend
+    on b) against the oracle's OpenAll at b = 400; sampled proofs against the one-proof-at-a-
+    time construction; every proof through the GPU verifier."""
+    L, b = 20, 1
+    say("case L=20 b=1 (34 whole batches)")
+    limbs = I.entries(1 << L, 3, 256)
+    ints = I.limbs_to_ints(limbs)
+    gpp = vc.vc_setup(L, SEED, 0)
+    gcm = vc.vc_commit(gpp, dev_entries(limbs), 256)
+    gpr = vc.vc_open_all(gpp, gcm, b)
+    torch.cuda.synchronize()
+    say("  GPU done; oracle commit")
+    opp, ocm = oracle_commitment(L, 3, 256, limbs)
+    m_le = I.limbs_to_bytes(limbs)
+    assert gcm.export("Cj") == b"".join(ocm.Cj) and gcm.C == ocm.C
+    ks = sorted(set([0, 1, 2, 511, 512, 1022, 1023] + [int(x) for x in np.linspace(3, 1021, 27)]))
+    assert len(ks) >= 32
+    say("  oracle Step 1 for %d blocks" % len(ks))
+    blocks = ocm.open_blocks(b, ks)
+    for k, blk in zip(ks, blocks):
+        for w in ("fc_x", "fc_rounds", "fc_tail"):
+            assert gpr.export(w, k) == blk[w], (w, k)
+    say("  oracle Step 2 (OpenAll at b = 400)")
+    oop = oracle_opening(L, 3, 256, limbs, 400)
+    for w in ("merkle", "rho", "y", "D", "W"):
+        assert gpr.export(w) == oop.export(w), w
+    for i in (0, 1023, 777777, (1 << 20) - 1):
+        proof = vc.vc_proof_get(gpr, i)
+        assert proof == O.naive_proof(opp, m_le, b, i), i
+        assert O.verify(opp, gcm.C, b, i, ints[i], proof) == 1, i
+    verify_every_proof(vc, gpp, gcm, gpr, b, limbs)

@@ -241,3 +241,19 @@ def test_c1_workload_n1024_b1_sampled():
     cm = O.Commitment(pp, I.limbs_to_bytes(w))
     rng = random.Random(1)
     _check_all(pp, m, cm, 1, sample=rng.sample(range(pp.N), 24) + [0, pp.N - 1], naive=[777])
+
+
+@pytest.mark.parametrize("L,b,ks", [(6, 3, [2, 0]), (7, 1, [0, 7, 3]), (8, 5, [3])])
+def test_open_blocks_equals_open_all(L, b, ks):
+    """Step 1 for selected blocks alone gives the same FC proofs as the whole OpenAll
+    (blocks are independent; the partial last block included)."""
+    pp = O.Params(L, SEED)
+    w = I.field_entries(pp.N, 40 + L)
+    cm = O.Commitment(pp, I.limbs_to_bytes(w))
+    op = O.Opening(cm, b)
+    got = cm.open_blocks(b, ks)
+    for k, blk in zip(ks, got):
+        for what in ("fc_rounds", "fc_tail", "fc_x"):
+            assert blk[what] == op.export(what, k), (what, k)
+    with pytest.raises(ValueError):
+        cm.open_blocks(b, [op.nb])
