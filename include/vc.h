@@ -70,6 +70,20 @@ int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out
 int vc_commit(const vc_params *pp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
               vc_commitment **out, uint8_t C_out[384]);
 
+/* VC.Commit without device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same commitment
+ * as vc_commit, from the same kernels, but no handle: m_dev and n as for vc_commit, with
+ * n <= 2^20.  Writes C_0..C_{K-1} to Cj_out (device, K x 64 B canonical big-endian affine
+ * x || y, the identity as zeros: the bytes of vc_commitment_export(cm, 0)) and C to C_out
+ * (host, 384 B; may be NULL).  All scratch (about 33 MiB at n = 2^20) lives in one static
+ * device array of 34 MiB that each GPU the library runs on holds until the process ends;
+ * the call clears what must start at zero.  Every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (any streams, any params) race and must be serialized by the
+ * caller.  Synchronous on return.  VC_EINVAL: n != N of the params, n > 2^20, bad
+ * entry_bits, or an entry >= r.  The params (vc_setup) were allocated beforehand. */
+int vc_commit_noalloc(const vc_params *pp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
+                      void *Cj_out, uint8_t C_out[384]);
+
 /* VC.OpenAll(aux, m) with batch size b, 1 <= b <= K (Protocol 1): all N proofs,
  * kept on the device in shared form (one FC batch proof per block of b
  * subvectors, the folding tree, the HyperEval commitments and the Merkle tree). */

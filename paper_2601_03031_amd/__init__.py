@@ -57,6 +57,7 @@ def lib():
         L.vc_setup.argtypes = [u32, u8p, C.c_int, C.POINTER(vp)]
         L.vc_commit.argtypes = [vp, vp, u64, u32, vp, C.POINTER(vp), vp]
         L.vc_open_all.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
+        L.vc_commit_noalloc.argtypes = [vp, vp, u64, u32, vp, vp, vp]
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
         L.vc_open_all_ex.argtypes = [vp, vp, u32, vp, vp, C.POINTER(vp)]
@@ -179,14 +180,32 @@ def vc_setup(log_n: int, seed: bytes, device: int = 0) -> Params:
     return Params(out, log_n, device)
 
 
+def _check_entries(pp: Params, m, entry_bits: int) -> None:
+    if m.numel() * m.element_size() < pp.N * (4 if entry_bits == 32 else 32):
+        raise ValueError("the entry tensor holds fewer than N entries of %d bits" % entry_bits)
+
+
 def vc_commit(pp: Params, m, entry_bits: int = 256, stream=None) -> Commitment:
     """m: a device tensor holding N x 32 little-endian bytes (entry_bits=256) or
     N 32-bit integers (entry_bits=32)."""
+    _check_entries(pp, m, entry_bits)
     out = C.c_void_p()
     cbuf = C.create_string_buffer(384)
     _check(lib().vc_commit(pp.ptr, C.c_void_p(m.data_ptr()), pp.N, entry_bits, _stream_ptr(stream),
                            C.byref(out), cbuf), "vc_commit")
     return Commitment(out, pp, cbuf.raw)
+
+
+def vc_commit_noalloc(pp: Params, m, entry_bits: int, Cj_out, stream=None) -> bytes:
+    """m as for vc_commit; Cj_out: a device uint8 tensor of K x 64 bytes that receives the
+    encoded C_j.  Returns C (384 bytes)."""
+    _check_entries(pp, m, entry_bits)
+    if Cj_out.numel() * Cj_out.element_size() < 64 * pp.K:
+        raise ValueError("Cj_out holds fewer than K x 64 bytes")
+    cbuf = C.create_string_buffer(384)
+    _check(lib().vc_commit_noalloc(pp.ptr, C.c_void_p(m.data_ptr()), pp.N, entry_bits, _stream_ptr(stream),
+                                   C.c_void_p(Cj_out.data_ptr()), cbuf), "vc_commit_noalloc")
+    return cbuf.raw
 
 
 def vc_open_all(pp: Params, cm: Commitment, b: int, stream=None) -> Proofs:

@@ -59,6 +59,13 @@ __global__ void __launch_bounds__(TPB) k_lift_u32(const uint32_t *in, uint64_t n
   out[i] = v;
 }
 
+// plain zero fill: flags and arrival counters that must start at zero (a kernel, so that a
+// caller capturing the launches in a graph records no memset node)
+__global__ void __launch_bounds__(TPB) k_zero_u32(uint32_t *p, uint64_t n) {
+  uint64_t i = gtid();
+  if (i < n) p[i] = 0;
+}
+
 __global__ void __launch_bounds__(TPB) k_check_fr(const fe *m, uint64_t n, int *err) {
   uint64_t i = gtid();
   if (i >= n) return;
@@ -214,6 +221,7 @@ void msm_tables_g2(const g2_aff *base, uint64_t M, uint32_t nwin, g2_aff *table,
 }
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st) { L1(k_lift_u32, n, in, n, out); }
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st) { L1(k_check_fr, n, m, n, err); }
+void zero_u32(uint32_t *p, uint64_t n, hipStream_t st) { if (n) L1(k_zero_u32, n, p, n); }
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st) {
   uint64_t nslice = (M + S - 1) / S;

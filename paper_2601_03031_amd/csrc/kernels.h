@@ -21,6 +21,7 @@ void pow_table(const fe *beta, fe *out, uint64_t n, hipStream_t st);
 void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hipStream_t st);
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st);
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
+void zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st);
 // the same over G2 (S nwin <= 1024), for the KZG proof over the fixed SRS points h_m

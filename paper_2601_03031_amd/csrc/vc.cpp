@@ -448,6 +448,92 @@ VC_API void vc_commitment_free(vc_commitment *cm) {
   (void)hipGetLastError();  // a release reports nothing and leaves no error behind
 }
 
+// ------------------------------------------------------------------ commit without allocation
+// vc_commit_noalloc keeps all of its scratch (entries, MSM partial sums, Miller values, tree
+// counters, C_j before encoding, C) in one file-scope device array: every GPU the library runs
+// on holds its own copy until the process ends.  On the host the array's name only stands for
+// the symbol; kernels and copies get the device address that hipGetSymbolAddress returned for
+// the current device, looked up once per device.
+static constexpr uint64_t NOALLOC_MAX_N = 1ull << 20;
+static constexpr size_t NOALLOC_SCRATCH_BYTES = 34ull << 20;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<int, void *> g_scratch_addr;  // device -> address of its copy of `scratch`
+
+// `device` must be current
+int scratch_address(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return VC_OK;
+  }
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "scratch address");
+  if (!ptr) return hip_fail(hipErrorInvalidSymbol, "scratch address");
+  g_scratch_addr[device] = ptr;
+  *out = ptr;
+  return VC_OK;
+}
+}  // namespace
+
+VC_API int vc_commit_noalloc(const vc_params *pp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
+                             void *Cj_out, uint8_t C_out[384]) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pp || !m_dev || !Cj_out || n != pp->N || (entry_bits != 32 && entry_bits != 256)) return VC_EINVAL;
+  if (n > NOALLOC_MAX_N) return VC_EINVAL;
+  CK(hipSetDevice(pp->device));
+  void *base = nullptr;
+  if (int rc = scratch_address(pp->device, &base)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t N = pp->N, K = pp->K, M = pp->M;
+  // the same MSM shape as vc_commit
+  const uint32_t nwin = entry_bits == 32 ? 4 : NWIN;
+  uint32_t S = (uint32_t)(8192 / nwin);
+  if (S > M) S = (uint32_t)M;
+  const uint64_t nslice = (M + S - 1) / S;
+  Carve t;
+  size_t o_err = t.take<int>(1), o_m = t.take<fe>(N), o_part = t.take<g1_jac>(K * nslice), o_F = t.take<fp12>(K);
+  size_t o_cnt = t.take<uint32_t>(tree_counters(K)), o_Cj = t.take<g1_aff>(K), o_C = t.take<fp12>(1);
+  size_t o_enc = t.take<uint8_t>(384);
+  if (t.off > NOALLOC_SCRATCH_BYTES) return VC_EINVAL;
+  int *err = at<int>(base, o_err);
+  fe *m = at<fe>(base, o_m);
+  g1_jac *part = at<g1_jac>(base, o_part);
+  fp12 *F = at<fp12>(base, o_F), *C = at<fp12>(base, o_C);
+  uint32_t *cnt = at<uint32_t>(base, o_cnt);
+  g1_aff *Cj = at<g1_aff>(base, o_Cj);
+  uint8_t *enc = at<uint8_t>(base, o_enc);
+  // the array keeps the last call's contents: clear the flag and the counters (a call that
+  // failed part way may have left counters set)
+  kl::zero_u32(reinterpret_cast<uint32_t *>(err), 1, st);
+  kl::zero_u32(cnt, tree_counters(K), st);
+  if (entry_bits == 32) {
+    kl::lift_u32((const uint32_t *)m_dev, N, m, st);
+  } else {
+    CK(hipMemcpyAsync(m, m_dev, N * sizeof(fe), hipMemcpyDeviceToDevice, st));
+    kl::check_fr(m, N, err, st);
+  }
+  kl::msm_slices(m, K, M, nwin, S, pp->table, part, st);
+  klw::sum_g1(part, K, nslice, Cj, st);
+  ks::miller(Cj, 1, pp->h, 2, K, F, st);
+  ks::f12_reduce(F, 1, K, K, cnt, st);
+  ks::final_exp(F, 1, 1, C, nullptr, 1, st);
+  kl::encode(reinterpret_cast<const fe *>(Cj), 2 * K, 0, static_cast<uint8_t *>(Cj_out), st);
+  kl::encode(reinterpret_cast<const fe *>(C), 12, 0, enc, st);
+  int herr = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && C_out) e = hipMemcpyAsync(C_out, enc, 384, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "vc_commit_noalloc");
+  if (herr & VC_ERRBIT_RANGE) return VC_EINVAL;
+  return VC_OK;
+}
+
 // ------------------------------------------------------------------ open-all
 // With `footprint` set: only the device bytes the call would hold (proof bundle, workspace,
 // counters) are stored there; nothing is allocated or launched, and cm, ex, out may be NULL.
