@@ -42,6 +42,7 @@ TRAFFIC_BYTES = {"ks_oa_pterms": round((666.3 * 2.000 + 54.4 * 1.000) * 1024)}
 FOLD_SPLIT_MAX = 256                       # folds of at most this many pairs run split in four parts
 DIRECT_MIN = 512                           # rounds of more pairs than this run direct in the ahead mode
 KZG_SPLIT_MAX = 8192                       # KZG proofs of at most this many split jobs run split
+WIDE_FOLD_MIN = 4096                       # direct-round Miller loops / G2 folds of this many pairs run wide
 
 
 def op_costs():
@@ -72,7 +73,74 @@ def op_costs():
     # G2 on a 16-bit chunk (16 bits); then the last part adds the four partial results and A
     c["e_g1_part"] = e[9] + 15 * e[10] + e[11]
     c["e_g2_part"] = e[2] + e[3] + 16 * e[4] + 15 * e[5]
+    c["f12_sqr"] = int(L.hc_count(13))
     return c
+
+
+MILLER_SQUARINGS = 63   # F_p12 squarings of the Miller loop over 6u+2 (its 65-bit NAF-free binary form)
+
+
+def fc_support_terms(K, lo, t):
+    """non-zero terms of the sparse G1 parts <A_R, b_L> and <A_L, b_R> over the rounds of one
+    FC batch opening whose exponent vector b is supported on [lo, lo + t) (section 3, Eq. (b)
+    and (folding)): the support folds to {s mod h} each round"""
+    sup, n, h = set(range(lo, lo + t)), 0, K
+    while h > 1:
+        h //= 2
+        n += sum(1 for s in sup if s < 2 * h)   # every support index meets one side of the round
+        sup = {s % h for s in sup}
+    return n
+
+
+def method_work(L, b, limbs, c):
+    """Algorithmic field multiplications of the method (the operation counts of the paper's
+    algorithms at this size: commit MSM, FC.Commit, Protocol 1 Step 1 with round 1's pairings
+    shared by all batches, Step 2), priced with the one-lane formulas of the library (host
+    build count): a multi-pairing of h pairs costs h Miller loops without their F_p12
+    squarings plus one set of squarings; an MSM of n terms over fixed bases with 8-bit windows
+    costs one mixed addition per non-zero digit and a running-sum bucket reduction
+    (2 x 255 additions per bucket set); every other MSM is priced as its scalar
+    multiplications.  Returns per-phase and per-kernel totals."""
+    import numpy as np
+    lK, lM = L // 2, L - L // 2
+    K, M, N = 1 << lK, 1 << lM, 1 << L
+    nb = (K + b - 1) // b
+    sq = MILLER_SQUARINGS * c["f12_sqr"]
+    pair = c["miller"] - sq
+    mpair = lambda h: h * pair + sq               # one multi-pairing of h pairs
+    nz_digits = int(np.count_nonzero(np.ascontiguousarray(limbs).view(np.uint8)))
+    S = min(M, 8192 // (4 if int(limbs[:, 1:].max()) == 0 else 32))
+    msm = nz_digits * c["g1_madd"] + K * ((M + S - 1) // S) * 510 * c["g1_add"]
+    fc_commit = mpair(K) + c["final_exp"]
+    rounds = [(j, K >> j) for j in range(1, lK + 1)]
+    # Miller work and final exponentiations per round (round 1 shared by every batch)
+    miller = {j: (2 * mpair(h) if j == 1 else nb * 2 * mpair(h)) for j, h in rounds}
+    fexp = {j: (2 if j == 1 else 2 * nb) * c["final_exp"] for j, h in rounds}
+    sparse = sum(fc_support_terms(K, k * b, min(b, K - k * b)) for k in range(nb)) * c["g1_mul"]
+    fold_g1 = sum(nb * h for _, h in rounds) * (c["g1_mul"] + c["g1_madd"])
+    fold_g2 = sum(nb * h for _, h in rounds) * (c["g2_mul"] + c["g2_madd"])
+    nq = 2 * K - 2   # the KZG quotient's terms: a G2 MSM over the fixed SRS points h_m
+    kzg = nb * (nq * 32 * 255 // 256 * c["g2_madd"] + -(-nq // 32) * 510 * c["g2_add"])
+    step2 = K * c["g1_mul"] + (K - 1) * c["g1_add"] + lM * (M // 2) * c["g1_mul"] + N
+    phases = {"commit_msm": msm, "fc_commit": fc_commit, "step1_miller": sum(miller.values()),
+              "step1_final_exp": sum(fexp.values()), "step1_sparse_g1": sparse, "step1_fold_g1": fold_g1,
+              "step1_fold_g2": fold_g2, "step1_kzg": kzg, "step2": step2}
+    # attribution to the kernels that carry each part of the work in the library's schedule
+    ahead = lK >= 2 and nb * K <= AHEAD_MAX_PAIRS
+    j0 = 2
+    while j0 < lK and nb * (K >> j0) > DIRECT_MIN:
+        j0 += 1
+    direct = [j for j, _ in rounds if not ahead or j < j0]
+    taken = [j for j, _ in rounds if ahead and j >= j0]
+    by_kernel = {"k_msm_slices<OpsG1>": msm, "ks_miller": mpair(K),
+                 "ks_oa_pterms": sum(miller[j] for j in taken),
+                 "ks_final_exp2": sum(fexp[j] for j in taken),
+                 "ks_final_exp": sum(fexp[j] for j in direct) + c["final_exp"]}
+    wide = [j for j in direct if (1 if j == 1 else nb) * (K >> j) >= WIDE_FOLD_MIN]
+    by_kernel["kw_oa_miller"] = sum(miller[j] for j in wide)
+    by_kernel["ks_oa_miller"] = sum(miller[j] for j in direct if j not in wide)
+    return {"phases": phases, "open_all": sum(v for k, v in phases.items() if k not in ("commit_msm", "fc_commit")),
+            "commit": msm + fc_commit, "by_kernel": {k: v for k, v in by_kernel.items() if v}}
 
 
 def work_model(L, b, limbs, costs):
@@ -109,6 +177,7 @@ def work_model(L, b, limbs, costs):
         while j0 < lK and nb * (K >> j0) > DIRECT_MIN:
             j0 += 1
         direct = [K >> j for j in range(1, j0)]
+        nbr = lambda h: 1 if h == K // 2 else nb   # round 1's pairings are computed once for all batches
         qs = [K >> j for j in range(j0, lK + 1)]
         g1_fold = costs["e_g1_mul"] + costs["e_g1_madd"] + costs["e_g1_to_aff"]
         split = [nb * h for h in rounds if nb * h <= FOLD_SPLIT_MAX]
@@ -116,10 +185,10 @@ def work_model(L, b, limbs, costs):
         g1_sum = 3 * costs["e_g1_add"] + costs["e_g1_madd"] + costs["e_g1_to_aff"]
         g2_sum = 3 * costs["e_g2_add"] + costs["e_g2_madd"] + costs["e_g2_to_aff"]
         w.update({
-            "ks_oa_miller": sum(nb * 2 * h for h in direct) * costs["e_miller"],
+            "ks_oa_miller": sum(nbr(h) * 2 * h for h in direct) * costs["e_miller"],
             "ks_oa_g1terms": sum(nb * 2 * h for h in direct) * costs["e_g1_mul"],
-            "ks_final_exp": (2 * nb * len(direct) + 1) * costs["e_final_exp"],
-            "ks_f12_tree": (K - 1 + sum(2 * nb * (h - 1) for h in direct)
+            "ks_final_exp": (sum(2 * nbr(h) for h in direct) + 1) * costs["e_final_exp"],
+            "ks_f12_tree": (K - 1 + sum(2 * nbr(h) * (h - 1) for h in direct)
                             + sum(2 * nb * (2 * q - 1) + 4 * nb * (q - 1) for q in qs)) * costs["e_f12_mul"],
             "ks_jac_tree<false>": (sum(2 * nb * (h - 1) for h in direct)
                                    + sum(2 * nb * (2 * q - 1) + 4 * nb * (q - 1) for q in qs)) * costs["e_g1_add"],
@@ -146,15 +215,31 @@ def work_model(L, b, limbs, costs):
             "ks_gt_sqr_mults": len(qs) * 4 * nb * 96 * costs["e_csqr"],
         })
     else:
+        nbr = lambda h: 1 if h == K // 2 else nb   # round 1's pairings are computed once for all batches
+        wide = [h for h in rounds if nbr(h) * h >= WIDE_FOLD_MIN]
         w.update({
-            "ks_oa_miller": sum(nb * 2 * h for h in rounds) * costs["e_miller"],
-            "ks_final_exp": (2 * lK * nb + 1) * costs["e_final_exp"],
-            "ks_f12_tree": (K - 1 + sum(2 * nb * (h - 1) for h in rounds)) * costs["e_f12_mul"],
+            "ks_oa_miller": sum(nbr(h) * 2 * h for h in rounds if h not in wide) * costs["e_miller"],
+            "kw_oa_miller": sum(nbr(h) * 2 * h for h in wide) * costs["miller"],
+            "ks_final_exp": (sum(2 * nbr(h) for h in rounds) + 1) * costs["e_final_exp"],
+            "ks_f12_tree": (K - 1 + sum(2 * nbr(h) * (h - 1) for h in rounds)) * costs["e_f12_mul"],
             "ks_oa_fold_g2": sum(nb * h for h in rounds) * g2_fold,
             "kw_oa_fold_g1": sum(nb * h for h in rounds) * (costs["g1_mul"] + costs["g1_madd"] + costs["g1_to_aff"]),
             "kw_oa_g1terms": sum(nb * 2 * h for h in rounds) * costs["g1_mul"],
         })
     return w
+
+
+def mad_peak(V):
+    """ALU peak for the roofline: the measured multiply-add rate (probe kernel in the library)
+    when it exceeds the rate derived from the unit counts and clock"""
+    try:
+        measured = V.vc_diag_mad_rate(0)
+    except Exception as e:  # noqa: BLE001 - the derived peak stands in
+        log("mad probe failed: %s" % e)
+        measured = 0.0
+    if measured > PEAK_MAD_TOPS:
+        return measured, "measured (vc_diag_mad_rate: v_mad_u64_u32 probe, 8 chains per lane)"
+    return PEAK_MAD_TOPS, "derived: 256 CU x 64 lanes x 2.4 GHz / 2 (half-rate v_mad_u64_u32); probe %.2f" % measured
 
 
 def hbm_model(L):
@@ -210,7 +295,7 @@ def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile="all"):
 BATCH_SETUPS = ((4, 6), (8, 2), (16, 1))   # (executors, streams per executor) of the batched-jobs runs
 
 
-def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2):
+def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=PEAK_MAD_TOPS):
     """Batched jobs: n_jobs independent vectors, N = 2^L with L uniform in [8, 18] (seeded),
     b = min(L^2, K), uniform full-width entries, each committed once.  Open-all of every job
     one after another on one stream, against the batch call on ne executors of ns streams
@@ -222,16 +307,18 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2):
     rng = np.random.default_rng(seed)
     Ls = [int(x) for x in rng.integers(8, 19, n_jobs)]
     log("batched jobs: %d vectors, L in [8, 18]: setup and commit" % n_jobs)
-    params, jobs, fmul = {}, [], 0
+    params, jobs, fmul, fexec = {}, [], 0, 0
     costs = op_costs()
     for i, L in enumerate(Ls):
         if L not in params:
             params[L] = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
         pp = params[L]
         limbs = I.entries(1 << L, 1000 * seed + i, 256)
-        # algorithmic field multiplications of this job's open-all (the commit's kernels left out)
+        # algorithmic field multiplications of this job's open-all (the method's counts), and
+        # what the library executes for it
+        fmul += method_work(L, min(L * L, pp.K), limbs, costs)["open_all"]
         w = work_model(L, min(L * L, pp.K), limbs, costs)
-        fmul += sum(v for k, v in w.items() if k not in ("k_msm_slices<OpsG1>", "ks_miller"))
+        fexec += sum(v for k, v in w.items() if k not in ("k_msm_slices<OpsG1>", "ks_miller"))
         m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
         jobs.append((pp, V.vc_commit(pp, m, 256), min(L * L, pp.K)))
     torch.cuda.synchronize()
@@ -265,10 +352,12 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2):
     res["speedup"] = round(seq_ms / res["batch_ms"][k_best], 2)
     res["best_setup"] = k_best
     # device utilization: the jobs' algorithmic multiply-adds over the time, against the ALU peak
-    tops = lambda ms: fmul * MADS_PER_FMUL / (ms / 1e3) / 1e12
+    tops = lambda f, ms: f * MADS_PER_FMUL / (ms / 1e3) / 1e12
     res["field_mults"] = int(fmul)
-    res["alu_frac"] = {"sequential": round(tops(seq_ms) / PEAK_MAD_TOPS, 5),
-                       "batched": round(tops(res["batch_ms"][k_best]) / PEAK_MAD_TOPS, 5)}
+    res["executed_field_mults"] = int(fexec)
+    res["alu_frac"] = {"sequential": round(tops(fmul, seq_ms) / peak, 5),
+                       "batched": round(tops(fmul, res["batch_ms"][k_best]) / peak, 5),
+                       "batched_executed": round(tops(fexec, res["batch_ms"][k_best]) / peak, 5)}
     res["hw_queues"] = int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0)
     return res
 
@@ -436,7 +525,20 @@ def eval_timing(V, torch, cases=((16, 32, 2), (20, 256, 3)), reps=3):
     return out
 
 
-def cpu_baseline(L, b, bits, seed):
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(L, b, bits, seed, reps=5, reps1=2):
+    """The oracle (plain C, OpenMP over independent units) on the host cores: one warm-up,
+    then the median of `reps` OpenAll runs on all threads, and the median of `reps1` runs on
+    one thread (the paper's setting), on the full workload's commitment."""
     import oracle as O
     log("cpu baseline (oracle) L=%d b=%d" % (L, b))
     from paper_2601_03031_amd import inputs as I
@@ -445,13 +547,29 @@ def cpu_baseline(L, b, bits, seed):
     pp = O.Params(L, I.TRAPDOOR_SEED)
     t0 = time.perf_counter()
     cm = O.Commitment(pp, I.limbs_to_bytes(limbs))
-    t1 = time.perf_counter()
-    op = O.Opening(cm, b)
-    t2 = time.perf_counter()
-    del op, cm, pp
-    return {"value": round(1e3 * (t2 - t1), 1), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": "the full N=2^%d, b=%d, %d-bit-entry workload: oracle OpenAll (all-N-proofs) time; "
-                      "oracle commit took %.1f ms" % (L, b, bits, 1e3 * (t1 - t0))}
+    commit_ms = 1e3 * (time.perf_counter() - t0)
+
+    def runs(n):
+        out = []
+        for _ in range(n):
+            t = time.perf_counter()
+            op = O.Opening(cm, b)
+            out.append(1e3 * (time.perf_counter() - t))
+            del op
+        return out
+
+    runs(1)  # warm-up
+    many = runs(reps)
+    O.set_threads(1)
+    one = runs(reps1)
+    O.set_threads(threads)
+    del cm, pp
+    return {"value": round(statistics.median(many), 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": "the full N=2^%d, b=%d, %d-bit-entry workload: oracle OpenAll (all-N-proofs) time, "
+                      "median of %d after a warm-up; one commitment (%.1f ms)" % (L, b, bits, reps, commit_ms),
+            "runs_ms": [round(x, 1) for x in many], "mean_ms": round(statistics.mean(many), 1),
+            "one_thread_ms": round(statistics.median(one), 1), "one_thread_runs": len(one),
+            "cpu_model": cpu_model()}
 
 
 def main():
@@ -473,7 +591,14 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--mad-peak", action="store_true",
+                    help="only measure the multiply-add peak with the library's probe kernel and exit")
     a = ap.parse_args()
+    if a.mad_peak:
+        import paper_2601_03031_amd as V
+        r = V.vc_diag_mad_rate(0)
+        print(json.dumps({"mad_per_s_T": round(r, 3), "derived_T": round(PEAK_MAD_TOPS, 3)}), flush=True)
+        return
     if a.copy_calibration:
         import torch
         n = a.copy_calibration << 20
@@ -524,38 +649,75 @@ def main():
     dcount, dms = pdom.get(dname, (0, 0.0))
     costs = op_costs()
     work = work_model(L, b, limbs, costs)
+    method = method_work(L, b, limbs, costs)
+    peak, peak_src = mad_peak(V)
     roofline = None
-    if dname in work and dcount:
-        per_launch_fmul = work[dname] / (dcount / a.steps)
+    if dcount and (dname in method["by_kernel"] or dname in work):
+        # algorithmic work: the method's operation counts (method_work) where the kernel carries a
+        # part of them, else what the kernel executes; the executed work is reported beside it
+        basis = "method" if dname in method["by_kernel"] else "executed"
+        fm = method["by_kernel"].get(dname, work.get(dname, 0))
+        per_launch_fmul = fm / (dcount / a.steps)
         avg_s = dms / dcount / 1e3
         achieved = per_launch_fmul * MADS_PER_FMUL / avg_s / 1e12
-        roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 4), "peak": round(PEAK_MAD_TOPS, 2),
-                    "unit": "TOP/s", "frac": round(achieved / PEAK_MAD_TOPS, 5), "traffic": TRAFFIC_BYTES.get(dname),
-                    "per_launch_field_mults": int(per_launch_fmul), "avg_launch_ms": round(dms / dcount, 4)}
+        exec_per_launch = work.get(dname, 0) / (dcount / a.steps)
+        roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 5), "peak": round(peak, 3),
+                    "unit": "T mad/s", "frac": round(achieved / peak, 6), "traffic": TRAFFIC_BYTES.get(dname),
+                    "work_basis": basis, "per_launch_field_mults": int(per_launch_fmul),
+                    "mads_per_field_mult": MADS_PER_FMUL, "avg_launch_ms": round(dms / dcount, 4),
+                    "launches_per_step": dcount / a.steps, "peak_source": peak_src,
+                    "peak_derived": round(PEAK_MAD_TOPS, 3),
+                    "executed_field_mults_per_launch": int(exec_per_launch),
+                    "executed_frac": round(exec_per_launch * MADS_PER_FMUL / avg_s / 1e12 / peak, 6)}
     kernels = {k: {"launches": c // psteps, "ms_per_step": round(ms / psteps, 4),
                    "share": round(ms / total_prof, 4) if total_prof else None}
                for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
     msm_ms = (prof.get("k_msm_slices<OpsG1>", (0, 0))[1] + prof.get("kw_sum_g1", (0, 0))[1]) / psteps
+    tops = lambda fm, ms: fm * MADS_PER_FMUL / (ms / 1e3) / 1e12   # 10^12 multiply-adds per second
+    open_med = statistics.median(open_ms)
     extra = {"commit_ms": round(statistics.median(commit_ms), 3),
              "open_ms_all": [round(x, 3) for x in open_ms],
              "open_ms_mean": round(statistics.mean(open_ms), 3),
              "msm_points_per_s": round((1 << L) / (msm_ms / 1e3)) if msm_ms else None,
+             "msm_points_per_s_commit_wall": round((1 << L) / (statistics.median(commit_ms) / 1e3)),
+             "method_field_mults": {k: int(v) for k, v in method["phases"].items()},
+             "fractions": {"open_all_n2^16_b256": round(tops(method["open_all"], open_med) / peak, 6)},
              "kernels": kernels}
     if not a.no_extra:
         L2, b2 = 20, 400
         n2 = max(1, min(a.steps, 2))
-        _, _, _, p2, _ = run_workload(V, torch, L2, b2, 256, 3, 1, 1)
+        limbs2, _, _, p2, _ = run_workload(V, torch, L2, b2, 256, 3, 1, 1)
         _, c2, o2, _, _ = run_workload(V, torch, L2, b2, 256, 3, n2, 1, profile=None)
+        method2 = method_work(L2, b2, limbs2, costs)
         msm2 = p2.get("k_msm_slices<OpsG1>", (0, 0))[1] + p2.get("kw_sum_g1", (0, 0))[1]
+        fold_bytes = sum(hbm_model(L2).values())
+        fold_ms = p2.get("k_ylevel0", (0, 0))[1] + p2.get("k_ylevel", (0, 0))[1]
+        fold_gbs = fold_bytes / (fold_ms / 1e3) / 1e9 if fold_ms else None
         extra["n2^20_b400"] = {"all_proofs_ms": round(statistics.median(o2), 3), "commit_ms": round(statistics.median(c2), 3),
-                               "msm_points_per_s": round((1 << L2) / (msm2 / 1e3)) if msm2 else None}
-        # batch-size sweep (one timed step each): all-N-proofs ms
-        sweep = {}
+                               "msm_points_per_s": round((1 << L2) / (msm2 / 1e3)) if msm2 else None,
+                               "msm_points_per_s_commit_wall": round((1 << L2) / (statistics.median(c2) / 1e3)),
+                               "method_field_mults": {k: int(v) for k, v in method2["phases"].items()}}
+        fr = extra["fractions"]
+        fr["open_all_n2^20_b400"] = round(tops(method2["open_all"], statistics.median(o2)) / peak, 6)
+        if msm2:
+            # the commit MSM kernels alone (sorted-digit bucket accumulation, then the slice sums)
+            fr["msm_n2^20"] = {"frac": round(tops(method2["phases"]["commit_msm"], msm2) / peak, 5),
+                               "kernel_ms": round(msm2, 4), "field_mults": int(method2["phases"]["commit_msm"])}
+        if fold_gbs:
+            # the y-tree passes (Step 2 folding of the randomized rows) against HBM bandwidth
+            fr["fold_n2^20"] = {"GB_per_s": round(fold_gbs, 1), "frac_of_hbm": round(fold_gbs / PEAK_HBM_GBS, 5),
+                                "bytes": fold_bytes, "kernel_ms": round(fold_ms, 4),
+                                "kernels": ["k_ylevel0", "k_ylevel"]}
+        # batch-size sweep (one timed step each): all-N-proofs ms and the whole-open-all fraction
+        sweep, sweep_fr = {}, {}
         for (Ls, bs, bits_s, seed_s) in ((16, 1, 32, 2), (16, 16, 32, 2), (20, 20, 256, 3), (20, 1, 256, 3)):
-            _, cs_, os_, _, _ = run_workload(V, torch, Ls, bs, bits_s, seed_s, 1, 1, profile=False)
+            lim_s, cs_, os_, _, _ = run_workload(V, torch, Ls, bs, bits_s, seed_s, 1, 1, profile=False)
             sweep["n2^%d_b%d" % (Ls, bs)] = round(os_[0], 3)
+            sweep_fr["open_all_n2^%d_b%d" % (Ls, bs)] = round(
+                tops(method_work(Ls, bs, lim_s, costs)["open_all"], os_[0]) / peak, 6)
         extra["b_sweep_all_proofs_ms"] = sweep
-        extra["batched_64_jobs"] = batched_jobs(V, torch)
+        fr.update(sweep_fr)
+        extra["batched_64_jobs"] = batched_jobs(V, torch, peak=peak)
         extra["serving"] = serving(V, torch)
         extra["subarrays"] = subarray_timing(V, torch)
         extra["eval_proof_ms"] = eval_timing(V, torch)
@@ -566,7 +728,8 @@ def main():
     line = {"metric": METRIC, "value": round(statistics.median(open_ms), 3), "unit": "ms", "n_gpus": 1,
             "steps": a.steps, "warmup": a.warmup,
             "ms_per_step": round(statistics.median([c + o for c, o in zip(commit_ms, open_ms)]), 3),
-            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32 limbs: exact 254-bit F_p/F_r (BN254)",
             "data": "synthetic", "config": {"workload": "N=2^16 commit + open-all, b=log^2 N=256, uniform 32-bit entries "
                                             "(seed 2), BN254", "N": 1 << L, "b": b, "entry_bits": bits},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}

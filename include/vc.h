@@ -253,6 +253,11 @@ int vc_profile_read(char *buf, size_t cap);
  * which: 0 = F_p, 1 = F_r.  Inputs must be < the modulus. */
 int vc_diag_field(int which, int op, uint64_t n, const void *a, const void *b, void *out);
 
+/* Diagnostic: measured throughput of the 32 x 32 -> 64-bit multiply-add on `device`, in
+ * 10^12 multiply-adds per second (best of five timed launches of a probe kernel that keeps
+ * every SIMD busy with independent chains).  The roofline's ALU peak. */
+int vc_diag_mad_rate(int device, double *tera_per_s);
+
 void vc_params_free(vc_params *pp);
 void vc_commitment_free(vc_commitment *cm);
 void vc_proofs_free(vc_proofs *pr);

@@ -58,6 +58,7 @@ def lib():
         L.vc_commit.argtypes = [vp, vp, u64, u32, vp, C.POINTER(vp), vp]
         L.vc_open_all.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
         L.vc_commit_noalloc.argtypes = [vp, vp, u64, u32, vp, vp, vp]
+        L.vc_diag_mad_rate.argtypes = [C.c_int, C.POINTER(C.c_double)]
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
         L.vc_open_all_ex.argtypes = [vp, vp, u32, vp, vp, C.POINTER(vp)]
@@ -376,6 +377,13 @@ def vc_proof_get(pr: Proofs, i: int) -> bytes:
 def vc_verify(pp: Params, C_bytes: bytes, b: int, i: int, m_i: int, proof: bytes) -> int:
     return _check(lib().vc_verify(pp.ptr, C_bytes, pp.N, b, i, int(m_i).to_bytes(32, "little"), proof, len(proof)),
                   "vc_verify")
+
+
+def vc_diag_mad_rate(device: int = 0) -> float:
+    """measured 32 x 32 -> 64-bit multiply-add throughput of the device (10^12 per second)"""
+    r = C.c_double(0)
+    _check(lib().vc_diag_mad_rate(device, C.byref(r)), "vc_diag_mad_rate")
+    return r.value
 
 
 def vc_profile_enable(on: bool = True) -> None:

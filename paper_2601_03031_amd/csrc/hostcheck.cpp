@@ -620,7 +620,7 @@ API int hc_g1_mul_glv(const uint8_t *Pb, const uint8_t *kb, uint8_t *out, uint8_
 // GPU path's formulas: 0 Miller loop, 1 final exponentiation, 2 G1 scalar mul
 // (254-bit scalar), 3 G2 scalar mul, 4 G1 add, 5 G1 mixed add, 6 G2 add, 7 G2 mixed
 // add, 8 G1 doubling, 9 G2 doubling, 10 F_p12 mul, 11 Jacobian->affine G1 (excluding
-// the binary-GCD inversion), 12 Jacobian->affine G2.
+// the binary-GCD inversion), 12 Jacobian->affine G2, 13 F_p12 squaring (general).
 API uint64_t hc_count(int op) {
   uint8_t gb1[64], gb2[128];
   g1_aff G1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
@@ -648,6 +648,7 @@ API uint64_t hc_count(int op) {
     case 10: (void)f12_mul(f, f); break;
     case 11: (void)jac_to_aff(P1); break;
     case 12: (void)jac_to_aff(P2); break;
+    case 13: (void)f12_sqr(f); break;
     default: return 0;
   }
   uint64_t n = c;

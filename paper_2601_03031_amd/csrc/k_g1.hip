@@ -59,6 +59,26 @@ __global__ void __launch_bounds__(TPB) k_lift_u32(const uint32_t *in, uint64_t n
   out[i] = v;
 }
 
+// Throughput probe of the 32 x 32 -> 64-bit multiply-add that the Montgomery products are
+// built from (v_mad_u64_u32): every lane runs 8 independent chains of `iters` steps
+// x <- lo(x) * b + x (one instruction, no moves); the results are stored so that no chain
+// is dropped.
+__global__ void __launch_bounds__(256) k_diag_mad(uint32_t seed, uint32_t iters, uint64_t *out) {
+  uint32_t a = seed ^ (uint32_t)gtid();
+  uint32_t b = a * 2654435761u + 12345u;
+  uint64_t x[8];
+#pragma unroll
+  for (int k = 0; k < 8; k++) x[k] = a + 977u * k;
+  for (uint32_t i = 0; i < iters; i++) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) x[k] = (uint64_t)(uint32_t)x[k] * b + x[k];
+  }
+  uint64_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) r ^= x[k];
+  out[gtid()] = r;
+}
+
 // plain zero fill: flags and arrival counters that must start at zero (a kernel, so that a
 // caller capturing the launches in a graph records no memset node)
 __global__ void __launch_bounds__(TPB) k_zero_u32(uint32_t *p, uint64_t n) {
@@ -141,6 +161,17 @@ __global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, 
 }
 
 // ================================================================ open-all, step 1
+// Round 1's G_T parts are the same for every batch (A = aux and V = v in all of them): copy
+// batch 0's L_1, R_1 (slot 0 of every batch's row of lK) to the other batches
+__global__ void __launch_bounds__(TPB) k_bcast_round1(fp12 *L, fp12 *R, uint64_t nb, uint32_t lK) {
+  const uint64_t words = sizeof(fp12) / 4;
+  uint64_t id = gtid();
+  if (id >= 2 * (nb - 1) * words) return;
+  uint64_t w = id % words, r = id / words, side = r & 1, k = 1 + (r >> 1);
+  uint32_t *base = reinterpret_cast<uint32_t *>(side ? R : L);
+  base[k * lK * words + w] = base[w];
+}
+
 __global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B) {
   uint64_t id = gtid();
   if (id >= nb * K) return;
@@ -222,6 +253,9 @@ void msm_tables_g2(const g2_aff *base, uint64_t M, uint32_t nwin, g2_aff *table,
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st) { L1(k_lift_u32, n, in, n, out); }
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st) { L1(k_check_fr, n, m, n, err); }
 void zero_u32(uint32_t *p, uint64_t n, hipStream_t st) { if (n) L1(k_zero_u32, n, p, n); }
+void diag_mad(uint32_t seed, uint32_t iters, unsigned blocks, uint64_t *out, hipStream_t st) {
+  LAUNCH(k_diag_mad, dim3(blocks), dim3(256), 0, seed, iters, out);
+}
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st) {
   uint64_t nslice = (M + S - 1) / S;
@@ -241,6 +275,9 @@ void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint6
 }
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st) {
   L1(k_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);
+}
+void bcast_round1(fp12 *L, fp12 *R, uint64_t nb, uint32_t lK, hipStream_t st) {
+  if (nb > 1) L1(k_bcast_round1, 2 * (nb - 1) * (sizeof(fp12) / 4), L, R, nb, lK);
 }
 void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st) {
   L1(k_oa_init, nb * K, Cj, h, K, nb, A, V, B);

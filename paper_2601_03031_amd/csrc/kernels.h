@@ -22,6 +22,8 @@ void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hi
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st);
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
 void zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
+// multiply-add throughput probe: blocks x 256 lanes, 8 iters multiply-adds each
+void diag_mad(uint32_t seed, uint32_t iters, unsigned blocks, uint64_t *out, hipStream_t st);
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
                 hipStream_t st);
 // the same over G2 (S nwin <= 1024), for the KZG proof over the fixed SRS points h_m
@@ -36,6 +38,8 @@ void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint3
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st);
 void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint64_t ostride, hipStream_t st);
 void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st);
+// L[k lK] = L[0], R[k lK] = R[0] for batches k = 1 .. nb - 1 (round 1's G_T parts)
+void bcast_round1(fp12 *L, fp12 *R, uint64_t nb, uint32_t lK, hipStream_t st);
 void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st);
 void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
 void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st);

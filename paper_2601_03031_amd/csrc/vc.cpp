@@ -823,8 +823,11 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
       }
       kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
       if (int rc2 = ev_mark(ex, 3, sg)) return rc2;
-      if (nb * h >= WIDE_FOLD_MIN) klw::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
-      else ks::oa_miller(Ab[cur], Vb[cur], K, nb, h, F, st);
+      // round 1 pairs the same A = aux with the same v in every batch: its G_T parts are
+      // computed once (batch 0) and copied to the other batches
+      const uint64_t nbm = j == 1 ? 1 : nb;
+      if (nbm * h >= WIDE_FOLD_MIN) klw::oa_miller(Ab[cur], Vb[cur], K, nbm, h, F, st);
+      else ks::oa_miller(Ab[cur], Vb[cur], K, nbm, h, F, st);
       // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
       // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
       if (j == 1 && split_round(1)) {
@@ -845,8 +848,9 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
         }
         if (int rc2 = launch_g1terms(j0)) return rc2;
       }
-      ks::f12_reduce(F, 2 * nb, K / 2, h, cnt_dir, st);
-      ks::final_exp(F, K / 2, 2 * nb, Lgt + (j - 1), Rgt + (j - 1), lK, st);
+      ks::f12_reduce(F, 2 * nbm, K / 2, h, cnt_dir, st);
+      ks::final_exp(F, K / 2, 2 * nbm, Lgt + (j - 1), Rgt + (j - 1), lK, st);
+      if (j == 1) kl::bcast_round1(Lgt, Rgt, nb, lK, st);
       if (int rc2 = ev_wait(ex, 3, st)) return rc2;
     } else {
       // L_j, R_j from the terms taken from the arrays of round j - 1 and x_{j-1}
@@ -1975,5 +1979,41 @@ VC_API int vc_diag_field(int which, int op, uint64_t n, const void *a, const voi
   if (e == hipSuccess) e = hipMemcpy(out, static_cast<char *>(d) + 2 * n * 32, n * 32, hipMemcpyDeviceToHost);
   hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "vc_diag_field");
+  return VC_OK;
+}
+
+VC_API int vc_diag_mad_rate(int device, double *tera_per_s) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!tera_per_s) return VC_EINVAL;
+  CK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  CK(hipGetDeviceProperties(&prop, device));
+  // 8 workgroups of 4 waves per compute unit: 8 waves per SIMD
+  const unsigned blocks = 8u * (unsigned)prop.multiProcessorCount;
+  const uint32_t iters = 8192;
+  uint64_t *d = nullptr;
+  CK(hipMalloc(&d, (size_t)blocks * 256 * sizeof(uint64_t)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  double best = 0;
+  for (int rep = 0; rep < 6 && e == hipSuccess; rep++) {
+    e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess) {
+      kl::diag_mad(0x9e3779b9u + rep, iters, blocks, d, nullptr);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    double mads = (double)blocks * 256.0 * 8.0 * iters;
+    if (e == hipSuccess && rep > 0 && ms > 0) best = std::max(best, mads / (ms * 1e-3) / 1e12);
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "vc_diag_mad_rate");
+  *tera_per_s = best;
   return VC_OK;
 }
