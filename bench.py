@@ -242,10 +242,12 @@ def mad_peak(V):
     return PEAK_MAD_TOPS, "derived: 256 CU x 64 lanes x 2.4 GHz / 2 (half-rate v_mad_u64_u32); probe %.2f" % measured
 
 
-def hbm_model(L):
+def fold_bytes(L):
+    """HBM bytes the y-tree must move at least (section 4.2, Sub-protocol): read the N entries
+    and the K randomizers rho_j, write every node of the (2K - 1) x M tree, 32 bytes each"""
     lK, lM = L // 2, L - L // 2
     K, M, N = 1 << lK, 1 << lM, 1 << L
-    return {"k_ylevel0": 64 * N + 32 * K, "k_ylevel": sum(3 * (K >> h) * M * 32 for h in range(1, lK + 1))}
+    return 32 * (N + K + (2 * K - 1) * M)
 
 
 def log(msg):
@@ -525,6 +527,49 @@ def eval_timing(V, torch, cases=((16, 32, 2), (20, 256, 3)), reps=3):
     return out
 
 
+def c3_timing(V, torch, Ls=(22, 24), seed=3, warm=True):
+    """Single-job open-all beyond 2^20 (Table 3's larger columns and the largest size that fits
+    the device): b = log^2 N, full-width entries drawn on the device (uniform in [0, 2^253),
+    seeded); setup, commit and open-all times, the open-all's own device bytes
+    (vc_open_all_footprint) and the device memory in use after it returns."""
+    from paper_2601_03031_amd import inputs as I
+    out = {}
+    for L in Ls:
+        N = 1 << L
+        K = 1 << (L // 2)
+        b = min(L * L, K)
+        log("c3: N=2^%d b=%d: setup" % (L, b))
+        t0 = time.perf_counter()
+        pp = V.vc_setup(L, I.TRAPDOOR_SEED, 0)
+        setup_s = time.perf_counter() - t0
+        m = I.device_entries(N, seed)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        runs = []
+        for r in range(2 if warm else 1):
+            log("c3: N=2^%d commit + open-all, pass %d" % (L, r))
+            t0 = time.perf_counter()
+            cm = V.vc_commit(pp, m, 256, st)
+            t1 = time.perf_counter()
+            pr = V.vc_open_all(pp, cm, b, st)
+            t2 = time.perf_counter()
+            runs.append((1e3 * (t1 - t0), 1e3 * (t2 - t1)))
+            free, total = torch.cuda.mem_get_info()
+            if r + 1 < (2 if warm else 1):
+                del pr, cm
+        c_ms, o_ms = runs[-1]
+        out["n2^%d_b%d" % (L, b)] = {
+            "all_proofs_ms": round(o_ms, 2), "commit_ms": round(c_ms, 2), "setup_s": round(setup_s, 2),
+            "first_call_ms": [round(x, 2) for x in runs[0]], "open_all_footprint_bytes": V.vc_open_all_footprint(pp, b),
+            "device_bytes_in_use": int(total - free), "proofs": N,
+            "proofs_per_s": round(N / (o_ms / 1e3))}
+        log("c3: N=2^%d open-all %.1f ms, commit %.1f ms, %.1f GB in use" % (L, o_ms, c_ms, (total - free) / 1e9))
+        del pr, cm, m, pp
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_model():
     try:
         for ln in open("/proc/cpuinfo"):
@@ -591,6 +636,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--c3", type=str, default="", metavar="LOGNS",
+                    help="only time single-job open-all at these log2 N (e.g. 22,24,26) and print its JSON")
     ap.add_argument("--mad-peak", action="store_true",
                     help="only measure the multiply-add peak with the library's probe kernel and exit")
     a = ap.parse_args()
@@ -619,6 +666,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.c3:
+        print(json.dumps(c3_timing(V, torch, [int(x) for x in a.c3.split(",")])), flush=True)
+        return
     if a.only:
         fn = {"verify_all": lambda: verify_all_timing(V, torch), "eval": lambda: eval_timing(V, torch),
               "subarrays": lambda: subarray_timing(V, torch)}[a.only]
@@ -690,9 +740,10 @@ def main():
         _, c2, o2, _, _ = run_workload(V, torch, L2, b2, 256, 3, n2, 1, profile=None)
         method2 = method_work(L2, b2, limbs2, costs)
         msm2 = p2.get("k_msm_slices<OpsG1>", (0, 0))[1] + p2.get("kw_sum_g1", (0, 0))[1]
-        fold_bytes = sum(hbm_model(L2).values())
-        fold_ms = p2.get("k_ylevel0", (0, 0))[1] + p2.get("k_ylevel", (0, 0))[1]
-        fold_gbs = fold_bytes / (fold_ms / 1e3) / 1e9 if fold_ms else None
+        fbytes = fold_bytes(L2)
+        fold_k = sorted(k for k in p2 if k.startswith("k_ytree"))
+        fold_ms = sum(p2[k][1] for k in fold_k)
+        fold_gbs = fbytes / (fold_ms / 1e3) / 1e9 if fold_ms else None
         extra["n2^20_b400"] = {"all_proofs_ms": round(statistics.median(o2), 3), "commit_ms": round(statistics.median(c2), 3),
                                "msm_points_per_s": round((1 << L2) / (msm2 / 1e3)) if msm2 else None,
                                "msm_points_per_s_commit_wall": round((1 << L2) / (statistics.median(c2) / 1e3)),
@@ -706,8 +757,7 @@ def main():
         if fold_gbs:
             # the y-tree passes (Step 2 folding of the randomized rows) against HBM bandwidth
             fr["fold_n2^20"] = {"GB_per_s": round(fold_gbs, 1), "frac_of_hbm": round(fold_gbs / PEAK_HBM_GBS, 5),
-                                "bytes": fold_bytes, "kernel_ms": round(fold_ms, 4),
-                                "kernels": ["k_ylevel0", "k_ylevel"]}
+                                "bytes": fbytes, "kernel_ms": round(fold_ms, 4), "kernels": fold_k}
         # batch-size sweep (one timed step each): all-N-proofs ms and the whole-open-all fraction
         sweep, sweep_fr = {}, {}
         for (Ls, bs, bits_s, seed_s) in ((16, 1, 32, 2), (16, 16, 32, 2), (20, 20, 256, 3), (20, 1, 256, 3)):

@@ -51,6 +51,12 @@ extern "C" {
 #define VC_ENOTIMPL (-4)
 #define VC_ECHALLENGE (-5) /* a Fiat-Shamir challenge was zero (probability ~2^-254) */
 
+/* Largest log2 N: at N = 2^30 an open-all with b = log^2 N holds about 194 GB of device
+ * memory with its input (entries, commitment copy, Merkle tree and y-tree dominate, about
+ * 192 N bytes), which fits the 288 GB of one MI355X; 2^31 does not.  Per-element thread
+ * indices stay below 2^32 up to this size. */
+#define VC_MAX_LOG_N 30
+
 typedef struct vc_params vc_params;
 typedef struct vc_commitment vc_commitment;
 typedef struct vc_proofs vc_proofs;
@@ -58,7 +64,7 @@ typedef struct vc_exec vc_exec;
 
 /* VC.Setup(1^lambda, 1^N) (Eq. vcpp): PST keys for log M variables and FC keys for
  * K entries, derived from a seeded TEST trapdoor (insecure: the paper requires a
- * trusted setup).  2 <= log_n <= 20.  The keys stay resident on `device`. */
+ * trusted setup).  2 <= log_n <= VC_MAX_LOG_N.  The keys stay resident on `device`. */
 int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out);
 
 /* VC.Commit(m) (Eq. genCi, genC).  m_dev: n entries on the device, either n x 32 B

@@ -96,7 +96,10 @@ __global__ void __launch_bounds__(TPB) k_check_fr(const fe *m, uint64_t n, int *
 // (j, slice) handles bases [slice*S, (slice+1)*S); every (base, window) pair with a nonzero
 // 8-bit digit is counting-sorted by digit in LDS, thread d sums bucket d over the
 // precomputed table points 2^{8w} ek[a], and the block reduces sum_d d B_d with a suffix
-// scan.  S nwin <= MSM_MAXE (G1), MSM_G2_MAXE (G2).
+// scan.  S nwin <= MSM_MAXE (G1), MSM_G2_MAXE (G2).  (A tree over bucket ranges that merges
+// (S, W) pairs with doublings does a quarter of the scan's additions but measured slower:
+// with one block per CU at N = 2^16 the block's latency sets the time, and its doubling
+// chains are longer than the scan's eight steps.)
 template <class O>
 __global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, uint32_t nwin, uint32_t S,
                                                     const aff<O> *table, jac<O> *partial) {
@@ -181,22 +184,40 @@ __global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff 
   B[id] = fe_zero();
 }
 
-// fold rows, canonical F_r: y[0][j][a] = rho_j m[jM+a]; the Montgomery product of a
-// Montgomery-form rho with a canonical m is the canonical product
-__global__ void __launch_bounds__(TPB) k_ylevel0(const fe *m, const fe *rho, uint64_t M, uint64_t N, fe *Y) {
-  uint64_t i = gtid();
-  if (i >= N) return;
-  Y[i] = fr_mul(rho[i / M], m[i]);
-}
-
-// level h: node w < K >> h, Y[(off(h)+w)M + a] = Y[(off(h-1)+2w)M + a] + Y[(off(h-1)+2w+1)M + a]
-__global__ void __launch_bounds__(TPB) k_ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h) {
-  uint64_t nw = K >> h;
+// Several levels of the y-tree (fold rows, canonical F_r) in one pass: thread (g, a) takes
+// the 2^s nodes g 2^s .. (g + 1) 2^s - 1 of level h0 in column a (at level 0 their values
+// y[0][j][a] = rho_j m[jM + a], written out first: the Montgomery product of a
+// Montgomery-form rho with a canonical m is the canonical product) and writes their sums at
+// levels h0 + 1 .. h0 + s.  Consecutive threads take
+// consecutive columns, so every row access is coalesced; the entries are read once and
+// every node is written once.
+template <int S>
+__global__ void __launch_bounds__(TPB) k_ytree(const fe *m, const fe *rho, fe *Y, uint64_t M, uint64_t K, uint32_t h0) {
+  const uint64_t groups = (K >> h0) >> S;
   uint64_t id = gtid();
-  if (id >= nw * M) return;
-  uint64_t w = id / M, a = id % M;
-  uint64_t off = 2 * K - ((2 * K) >> h), offc = 2 * K - ((2 * K) >> (h - 1));
-  Y[(off + w) * M + a] = fr_add(Y[(offc + 2 * w) * M + a], Y[(offc + 2 * w + 1) * M + a]);
+  if (id >= groups * M) return;
+  const uint64_t g = id / M, a = id % M;
+  fe v[1 << S];
+  const uint64_t in = 2 * K - ((2 * K) >> h0);  // first row of level h0
+#pragma unroll
+  for (int q = 0; q < (1 << S); q++) {
+    const uint64_t node = (g << S) + q;
+    if (h0 == 0) {
+      v[q] = fr_mul(rho[node], m[node * M + a]);
+      Y[node * M + a] = v[q];
+    } else {
+      v[q] = Y[(in + node) * M + a];
+    }
+  }
+#pragma unroll
+  for (int l = 1; l <= S; l++) {
+    const uint64_t out = 2 * K - ((2 * K) >> (h0 + l));
+#pragma unroll
+    for (int q = 0; q < (1 << (S - l)); q++) {
+      v[q] = fr_add(v[2 * q], v[2 * q + 1]);
+      Y[(out + (g << (S - l)) + q) * M + a] = v[q];
+    }
+  }
 }
 
 // ================================================================ export
@@ -285,8 +306,25 @@ void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff 
 void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st) {
   L1(k_glv_dec, nb, X, nb, j, lK, out);
 }
-void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_t st) { L1(k_ylevel0, N, m, r, M, N, Y); }
-void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st) { L1(k_ylevel, (K >> h) * M, Y, M, K, h); }
+void ytree(const fe *m, const fe *r, fe *Y, uint64_t M, uint64_t K, uint32_t lK, hipStream_t st) {
+  // passes of four levels (the last pass takes what remains); level 0 is made in the first
+  uint32_t h0 = 0;
+  if (lK == 0) {
+    L1(k_ytree<0>, M, m, r, Y, M, K, 0u);
+    return;
+  }
+  while (h0 < lK) {
+    const uint32_t s = lK - h0 >= 4 ? 4 : lK - h0;
+    const uint64_t n = ((K >> h0) >> s) * M;
+    switch (s) {
+      case 4: L1(k_ytree<4>, n, m, r, Y, M, K, h0); break;
+      case 3: L1(k_ytree<3>, n, m, r, Y, M, K, h0); break;
+      case 2: L1(k_ytree<2>, n, m, r, Y, M, K, h0); break;
+      default: L1(k_ytree<1>, n, m, r, Y, M, K, h0); break;
+    }
+    h0 += s;
+  }
+}
 void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st) { if (n) L1(k_encode, n, in, n, mode, out); }
 void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st) {
   if (n) L1(k_gather_encode, n, base, idx, mode, n, out);

@@ -218,6 +218,61 @@ __global__ void __launch_bounds__(KZG_T) k_kzg_quotient(const fe *Xinv, const fe
   for (uint64_t m = t; m + 1 < D; m += KZG_T) Q[k * (D - 1) + m] = fr_mul(pw[m + 1], acc[m + 1]);
 }
 
+// The same quotient for K > 1024, whose 2(2K - 1) working values do not fit in shared
+// memory: the scans run over global arrays (two per scan, read and written alternately),
+// with the same operations in the same order.  gws: 4 (2K - 1) elements per batch.
+__global__ void __launch_bounds__(KZG_T) k_kzg_quotient_g(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K,
+                                                        uint32_t lK, fe *Q, fe *zout, fe *gws) {
+  CHAIN_PRIORITY();
+  uint64_t k = blockIdx.x;
+  uint64_t D = 2 * K - 1;
+  fe *pa = gws + k * 4 * D, *pb = pa + D, *aa = pa + 2 * D, *ab = pa + 3 * D;
+  __shared__ uint32_t zmsg[16 + 8 + 32 + 24], t2[16];
+  uint32_t t = threadIdx.x;
+  if (t < 16) zmsg[t] = 0;
+  if (t == 16) sha::put_words<FpR>(zmsg + 16, X[k * lK + lK - 1]);
+  if (t > 16 && t <= 20) sha::put_words<FpP>(zmsg + 24 + 8 * (t - 17), reinterpret_cast<const fe *>(V + k * K)[t - 17]);
+  __syncthreads();
+  const fe zz = sha::xmd_fr_coop(sha::Coop{(int)t, KZG_T}, zmsg, 160, DSTR_FC_Z, t2);
+  const fe zi = f_inv_uniform<FpR>(zz, bn::R_R3);
+  if (t == 0) zout[k] = zz;
+  // z^i: inclusive product scan of (1, z, z, ...)
+  for (uint64_t i = t; i < D; i += KZG_T) pa[i] = (i == 0) ? f_one<FpR>() : zz;
+  __syncthreads();
+  for (uint64_t s = 1; s < D; s <<= 1) {
+    for (uint64_t i = t; i < D; i += KZG_T) pb[i] = (i >= s) ? fr_mul(pa[i], pa[i - s]) : pa[i];
+    __syncthreads();
+    fe *tmp = pa; pa = pb; pb = tmp;
+  }
+  // c_i z^i
+  for (uint64_t i = t; i < D; i += KZG_T) {
+    fe c = fe_zero();
+    if ((i & 1) == 0) {
+      uint64_t s2 = i >> 1;
+      c = f_one<FpR>();
+      for (uint32_t bt = 0; bt < lK; bt++)
+        if ((s2 >> bt) & 1) c = fr_mul(c, Xinv[k * lK + (lK - bt) - 1]);
+    }
+    aa[i] = fr_mul(c, pa[i]);
+  }
+  __syncthreads();
+  // suffix sums
+  for (uint64_t s = 1; s < D; s <<= 1) {
+    for (uint64_t i = t; i < D; i += KZG_T) ab[i] = (i + s < D) ? fr_add(aa[i], aa[i + s]) : aa[i];
+    __syncthreads();
+    fe *tmp = aa; aa = ab; ab = tmp;
+  }
+  // z^{-i}
+  for (uint64_t i = t; i < D; i += KZG_T) pa[i] = (i == 0) ? f_one<FpR>() : zi;
+  __syncthreads();
+  for (uint64_t s = 1; s < D; s <<= 1) {
+    for (uint64_t i = t; i < D; i += KZG_T) pb[i] = (i >= s) ? fr_mul(pa[i], pa[i - s]) : pa[i];
+    __syncthreads();
+    fe *tmp = pa; pa = pb; pb = tmp;
+  }
+  for (uint64_t m = t; m + 1 < D; m += KZG_T) Q[k * (D - 1) + m] = fr_mul(pa[m + 1], aa[m + 1]);
+}
+
 // ================================================================ open-all, step 2
 // Merkle leaves SHA-256(0x00 || m_i || C_j), stored as 8 big-endian words per node;
 // node n of the heap (root = 1, leaf i = N + i) at tree[8n]
@@ -281,7 +336,11 @@ void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, ui
   LAUNCH(k_oa_transcript, dim3((unsigned)nb), dim3(64), 0, Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err);
 }
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
-                  hipStream_t st) {
+                  fe *gws, hipStream_t st) {
+  if (K > KZG_T) {
+    LAUNCH(k_kzg_quotient_g, dim3((unsigned)nb), dim3(KZG_T), 0, Xinv, X, V, K, lK, Q, z, gws);
+    return;
+  }
   size_t shm = 2 * (2 * K - 1) * sizeof(fe);
   static const bool attr_set = [] {  // once per process (thread-safe initialisation)
     (void)hipFuncSetAttribute((const void *)k_kzg_quotient, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) kv_transcript(const VCtx *cs) {
   const VCtx &c = cs[blockIdx.x];
   const int tid = threadIdx.x;
   const uint32_t t = c.t, l = c.lK;
-  __shared__ uint32_t dig[32][8];  // chunk digests: t <= 1024
+  __shared__ uint32_t dig[1024][8];  // chunk digests: t <= 32768 (K of log N <= 30)
   __shared__ uint32_t sigma[8];
   __shared__ fe part[256];
   __shared__ fe s_z, s_rho, s_ystar;

@@ -48,14 +48,15 @@ void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, ui
                    const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
 // L[k lK], R[k lK] = U[2k + side] + sum_{g, p} P[4 (4k + g) + p] over the 8 split parts of
 // each side (affine)
+// gws: 4 (2K - 1) elements per batch of global working space, used when K > 1024
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
-                  hipStream_t st);
+                  fe *gws, hipStream_t st);
 void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st);
 void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st);
 void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st);
 void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st);
-void ylevel0(const fe *m, const fe *r, uint64_t M, uint64_t N, fe *Y, hipStream_t st);
-void ylevel(fe *Y, uint64_t M, uint64_t K, uint32_t h, hipStream_t st);
+// the whole y-tree (level 0 from the entries, levels 1 .. lK) in passes of up to four levels
+void ytree(const fe *m, const fe *r, fe *Y, uint64_t M, uint64_t K, uint32_t lK, hipStream_t st);
 void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st);
 void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st);
 // evaluation proof at a point (k_hash.hip)

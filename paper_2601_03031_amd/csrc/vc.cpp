@@ -302,7 +302,7 @@ VC_API const char *vc_strerror(int code) {
 // ------------------------------------------------------------------ setup
 VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
-  if (!out || !seed || log_n < 2 || log_n > 20) return VC_EINVAL;
+  if (!out || !seed || log_n < 2 || log_n > VC_MAX_LOG_N) return VC_EINVAL;
   *out = nullptr;
   CK(hipSetDevice(device));
   vc_params *pp = new vc_params();
@@ -595,6 +595,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   const uint64_t kzg_nslice = (nq + KZG_S - 1) / KZG_S, kzg_len = kzg_split ? 4 * nq : kzg_nslice;
   size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(with2 * lM * (M / 2));
   size_t o_dec = t.take<glv::Dec>(nb);
+  size_t o_KQ = t.take<fe>(K > 1024 ? nb * 4 * (2 * K - 1) : 0);  // the KZG quotient's scans beyond shared memory
   // evaluation proof: point, T, the terms of C_F, F's table, the PST quotients and their products
   size_t o_rle = t.take<uint8_t>(ev * 32 * pp->L), o_er = t.take<fe>(ev * pp->L), o_T = t.take<fe>(ev * K),
          o_pK = t.take<g1_aff>(ev * K), o_eg = t.take<fe>(ev * M), o_eq = t.take<fe>(ev * M), o_pW = t.take<g1_aff>(ev * M);
@@ -708,8 +709,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
     kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
     for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(tree, s, st);
     kl::rho(C, tree, K, rho, st);
-    kl::ylevel0(cm->m, rho, M, N, Y, st);
-    for (uint32_t h = 1; h <= lK; h++) kl::ylevel(Y, M, K, h, st);
+    kl::ytree(cm->m, rho, Y, M, K, lK, st);
     klw::g1_mul(Cj, 0, rho, K, D, st);
     for (uint32_t h = 1; h <= lK; h++) klw::dlevel(D, K, h, st);
     klw::hyper_terms(Y + (2 * K - 2) * M, pp->ek, M, lM, HS, st);
@@ -904,7 +904,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
   CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
   // faster verifier: KZG-style proof in G2 that v_l = f_v(beta) g2
-  kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, st);
+  kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, at<fe>(ws, o_KQ), st);
   if (kzg_split) {
     ks::kzg_terms_split(pp->h, pp->hm, Q, K, nb, S2, st);
   } else {

@@ -68,3 +68,21 @@ def entries(n: int, seed: int, bits: int = 256) -> np.ndarray:
     if bits == 32:
         return u32_to_limbs(u32_entries(n, seed))
     return field_entries(n, seed)
+
+
+def device_entries(n: int, seed: int, device: str = "cuda", chunk: int = 1 << 22):
+    """n full-width entries drawn on the device (for sizes where drawing on the host is slow):
+    a seeded torch generator, eight 32-bit words per entry with the top word below 2^29, so
+    the entries are uniform in [0, 2^253), all below r.  Drawn in chunks of `chunk` entries.
+    Returns an (n * 32)-byte uint8 tensor of little-endian encodings."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty((n, 8), dtype=torch.int32, device=device)
+    for lo in range(0, n, chunk):
+        c = min(chunk, n - lo)
+        w = torch.randint(0, 2**32, (c, 8), generator=g, device=device, dtype=torch.int64)
+        w[:, 7] &= (1 << 29) - 1
+        out[lo:lo + c] = w.to(torch.int32)  # the low 32 bits of each word
+        del w
+    return out.view(torch.uint8).reshape(-1)

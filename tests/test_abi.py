@@ -70,7 +70,7 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     """Argument checks run before any device call."""
     lib.vc_setup.argtypes = [C.c_uint32, C.c_char_p, C.c_int, C.POINTER(C.c_void_p)]
     out = C.c_void_p()
-    for bad in (0, 1, 21, 64):
+    for bad in (0, 1, 31, 64):
         assert lib.vc_setup(bad, bytes(32), 0, C.byref(out)) == -1  # VC_EINVAL
     assert lib.vc_setup(4, None, 0, C.byref(out)) == -1
     assert lib.vc_setup(4, bytes(32), 0, None) == -1

@@ -78,7 +78,7 @@ class Case:
         else:
             limbs = I.entries(N, seed, bits)
             self.opp, self.ocm = oracle_commitment(L, seed, bits, limbs)
-            self.oop = oracle_opening(L, seed, bits, limbs, b) if L >= 20 else O.Opening(self.ocm, b)
+            self.oop = oracle_opening(L, seed, bits, limbs, b) if L == 20 else O.Opening(self.ocm, b)
         self.m = I.limbs_to_ints(limbs)
         say("  oracle done; GPU setup/commit/open_all")
         self.gpp = V.vc_setup(L, SEED, 0)
@@ -270,3 +270,31 @@ def test_n20_b1_blocks(vc):
         assert proof == O.naive_proof(opp, m_le, b, i), i
         assert O.verify(opp, gcm.C, b, i, ints[i], proof) == 1, i
     verify_every_proof(vc, gpp, gcm, gpr, b, limbs)
+
+
+@pytest.mark.timeout(1200)
+def test_n22_b484_beyond_2_20(vc):
+    """N = 2^22 (K = M = 2048, past the shared-memory KZG quotient and the 1024-entry
+    batches), b = log^2 N = 484 (5 batches, the last with 112 entries), full-width entries
+    (seed 3): every exported array against the oracle's OpenAll, sampled proofs byte for
+    byte and through the oracle's verifier, one proof against the oracle's one-proof-at-a-time
+    construction."""
+    L, b = 22, 484
+    cs = Case(vc, L, b, seed=3, bits=256)
+    N, M = 1 << L, 2048
+    idx = sample_indices(N, M, b, 7, extra=(4 * b * M, 4 * b * M + 111 * M + M - 1))
+    compare_all(vc, cs, proofs=idx)
+    limbs = I.entries(N, 3, 256)
+    for i in idx[:6]:
+        assert O.verify(cs.opp, cs.gcm.C, b, i, cs.m[i], vc.vc_proof_get(cs.gpr, i)) == 1, i
+    i = N - 1
+    assert vc.vc_proof_get(cs.gpr, i) == O.naive_proof(cs.opp, I.limbs_to_bytes(limbs), b, i)
+
+
+def test_setup_size_limits(vc):
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_setup(31, SEED, 0)
+    assert e.value.code == vc.VC_EINVAL
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_setup(1, SEED, 0)
+    assert e.value.code == vc.VC_EINVAL

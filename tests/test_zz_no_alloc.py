@@ -71,3 +71,13 @@ def test_errors(vc):
     c = vc.vc_commit_noalloc(pp, dev_entries(good, 256), 256, cj)
     ref = vc.vc_commit(pp, dev_entries(good, 256), 256)
     assert c == ref.C and bytes(cj.cpu().numpy()) == ref.export("Cj")
+
+
+def test_rejects_beyond_its_scratch(vc):
+    # N = 2^21 is past the array's stated maximum (N <= 2^20): refused before any launch
+    pp = vc.vc_setup(21, SEED, 0)
+    m = torch.zeros(32 << 21, dtype=torch.uint8, device="cuda")
+    cj = torch.zeros(64 * pp.K, dtype=torch.uint8, device="cuda")
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_commit_noalloc(pp, m, 256, cj)
+    assert e.value.code == vc.VC_EINVAL
