@@ -418,6 +418,7 @@ def serving(V, torch, n_req=40, rate=8.0, seed=7, setups=SERVE_SETUPS, budget=64
             p0.append(V.vc_proof_get(pr, 0))
             del pr
         wall = time.perf_counter() - t0
+        held, peak, _ = sv.stats()
         del sv
         if first is None:
             first = p0
@@ -427,7 +428,7 @@ def serving(V, torch, n_req=40, rate=8.0, seed=7, setups=SERVE_SETUPS, budget=64
         res["setups"][key] = {"p50_ms": round(float(np.percentile(lat, 50)), 1),
                               "p99_ms": round(float(np.percentile(lat, 99)), 1),
                               "mean_ms": round(float(np.mean(lat)), 1), "wall_s": round(wall, 2),
-                              "proofs_per_s": round(proofs / wall)}
+                              "proofs_per_s": round(proofs / wall), "peak_held_bytes": int(peak)}
         log("serving %s: p50 %.0f ms, p99 %.0f ms, wall %.1f s" % (key, res["setups"][key]["p50_ms"],
                                                                    res["setups"][key]["p99_ms"], wall))
     return res
@@ -769,6 +770,7 @@ def main():
         fr.update(sweep_fr)
         extra["batched_64_jobs"] = batched_jobs(V, torch, peak=peak)
         extra["serving"] = serving(V, torch)
+        extra["serving_16_per_s"] = serving(V, torch, rate=16.0)
         extra["subarrays"] = subarray_timing(V, torch)
         extra["eval_proof_ms"] = eval_timing(V, torch)
         extra["verify_all_n2^16"] = {"b256": verify_all_timing(V, torch, b=256), "b1": verify_all_timing(V, torch, b=1)}

@@ -129,10 +129,15 @@ int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitme
 int vc_open_all_footprint(const vc_params *pp, uint32_t b, uint64_t *bytes);
 
 /* Serving loop (OpenAll requests of Protocol 1, §4.2, arriving over time): nexec executors of
- * nstreams streams each, one host thread each.  Requests start in arrival order, each when an
- * executor is free and the footprints of the running requests plus its own fit in hbm_budget
- * bytes (the oldest waiting request is never overtaken).  Idle executors keep the workspace
- * of their largest request so far; proofs returned by vc_server_wait belong to the caller.
+ * nstreams streams each, one host thread each.  Requests start in arrival order (the oldest
+ * waiting request is never overtaken), each when an executor is free and the device bytes the
+ * server holds stay within hbm_budget.  Those bytes are: the proof bundles of running requests
+ * and of finished ones not yet collected, and the workspace and counters every executor keeps
+ * between requests (exact sizes from the open-all's own layout).  A request adds its bundle and
+ * what its executor's workspace must grow by; when the oldest does not fit, idle executors
+ * release what they keep.  Proofs returned by vc_server_wait belong to the caller and leave
+ * the budget.  Collect tickets in submission order: a finished request's bundle counts until
+ * it is collected, so waiting first for a later ticket that cannot start would block.
  * VC_EINVAL for nexec outside [1, 64], nstreams outside [1, 6] or a zero budget. */
 typedef struct vc_server vc_server;
 int vc_server_create(int device, uint32_t nexec, uint32_t nstreams, uint64_t hbm_budget, vc_server **out);
@@ -144,6 +149,9 @@ int vc_server_submit(vc_server *sv, const vc_params *pp, const vc_commitment *cm
  * submission to completion (the request's latency).  Each ticket is waited for once, by one
  * thread; VC_EINVAL for an unknown ticket. */
 int vc_server_wait(vc_server *sv, uint64_t ticket, vc_proofs **out, double times_ms[2]);
+/* Accounting of the budget: stats[0] bytes held now, stats[1] the most held at any time (at
+ * most the budget), stats[2] the budget. */
+int vc_server_stats(vc_server *sv, uint64_t stats[3]);
 /* Finish the running requests, drop the waiting ones and release everything (proofs not
  * collected included).  Not concurrent with other calls on sv. */
 void vc_server_free(vc_server *sv);

@@ -67,6 +67,7 @@ def lib():
         L.vc_server_submit.argtypes = [vp, vp, vp, u32, C.POINTER(u64)]
         L.vc_server_wait.argtypes = [vp, u64, C.POINTER(vp), C.POINTER(C.c_double)]
         L.vc_server_free.argtypes = [vp]
+        L.vc_server_stats.argtypes = [vp, C.POINTER(u64)]
         L.vc_proofs_serialize.argtypes = [vp, vp, u64, C.POINTER(u64)]
         L.vc_open_subarrays.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
         L.vc_eval_proof_len.restype = u64
@@ -267,6 +268,12 @@ class Server(_Handle):
         _check(lib().vc_server_submit(self.ptr, pp.ptr, cm.ptr, b, C.byref(t)), "vc_server_submit")
         self._jobs[t.value] = (pp, cm, b)
         return t.value
+
+    def stats(self):
+        """(bytes held now, most bytes held at any time, budget)"""
+        v = (C.c_uint64 * 3)()
+        _check(lib().vc_server_stats(self.ptr, v), "vc_server_stats")
+        return v[0], v[1], v[2]
 
     def wait(self, ticket: int):
         """(Proofs, [ms waiting before start, ms from submission to completion])"""

@@ -307,14 +307,16 @@ void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, h
   L1(k_glv_dec, nb, X, nb, j, lK, out);
 }
 void ytree(const fe *m, const fe *r, fe *Y, uint64_t M, uint64_t K, uint32_t lK, hipStream_t st) {
-  // passes of four levels (the last pass takes what remains); level 0 is made in the first
+  // passes of four levels (the last pass takes what remains); level 0 is made in the first,
+  // which takes two levels below N = 2^24 so that its N / 4 threads still fill the device
   uint32_t h0 = 0;
   if (lK == 0) {
     L1(k_ytree<0>, M, m, r, Y, M, K, 0u);
     return;
   }
   while (h0 < lK) {
-    const uint32_t s = lK - h0 >= 4 ? 4 : lK - h0;
+    const uint32_t want = (h0 == 0 && K * M < (1ull << 24)) ? 2 : 4;
+    const uint32_t s = lK - h0 >= want ? want : lK - h0;
     const uint64_t n = ((K >> h0) >> s) * M;
     switch (s) {
       case 4: L1(k_ytree<4>, n, m, r, Y, M, K, h0); break;

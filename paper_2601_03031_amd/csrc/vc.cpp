@@ -239,6 +239,19 @@ static int ensure_ws(vc_exec *ex, size_t need) {
   return VC_OK;
 }
 
+// release the workspace and counters an executor keeps between calls (its next call
+// allocates them again)
+static void exec_release(vc_exec *ex) {
+  (void)hipSetDevice(ex->device);
+  if (ex->ws) (void)hipFree(ex->ws);
+  if (ex->cnt) (void)hipFree(ex->cnt);
+  ex->ws = nullptr;
+  ex->ws_size = 0;
+  ex->cnt = nullptr;
+  ex->cnt_n = 0;
+  ex->cnt_dirty = false;
+}
+
 VC_API void vc_exec_free(vc_exec *ex) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!ex) return;
@@ -544,7 +557,7 @@ VC_API int vc_commit_noalloc(const vc_params *pp, const void *m_dev, uint64_t n,
 // evaluation proof at a point).
 static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t b, vc_exec *ex, hipStream_t st,
                          vc_proofs **out, uint64_t *footprint = nullptr, bool step2 = true,
-                         const uint8_t *eval_r = nullptr) {
+                         const uint8_t *eval_r = nullptr, uint64_t *parts = nullptr) {
   if (!cpp || b < 1 || b > cpp->K) return VC_EINVAL;
   if (!footprint && (!cm || !out || !ex || cm->pp != cpp || ex->device != cpp->device)) return VC_EINVAL;
   if (eval_r && (b != cpp->K || step2)) return VC_EINVAL;  // an evaluation proof is one batch, no Step 2
@@ -623,6 +636,11 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   const uint64_t n_cnt = 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg;
   if (footprint) {
     *footprint = c.off + t.off + n_cnt * sizeof(uint32_t);
+    if (parts) {
+      parts[0] = c.off;  // the proof bundle
+      parts[1] = t.off;  // the executor's workspace
+      parts[2] = n_cnt;  // arrival counters
+    }
     delete pr;
     return VC_OK;
   }
@@ -1006,16 +1024,21 @@ VC_API int vc_open_all_footprint(const vc_params *pp, uint32_t b, uint64_t *byte
 
 // ------------------------------------------------------------------ serving loop
 // Requests wait in arrival order; a worker thread per executor takes the oldest one once it is
-// free and the footprints of the running requests plus the oldest one's fit the budget (the
-// oldest waits, and the ones behind it with it, until they do: no request is overtaken).
+// free and its bytes fit the budget (the oldest waits, and the ones behind it with it, until
+// they do: no request is overtaken).  The budget counts every byte the server holds: the proof
+// bundles of running requests and of finished ones not yet collected by vc_server_wait, and
+// the workspace and counters each executor keeps between requests.  A request needs its bundle
+// plus whatever its executor's workspace and counters must grow by; when it does not fit, idle
+// executors release what they keep.
 struct vc_server {
   using clock = std::chrono::steady_clock;
   struct Req {
     const vc_params *pp;
     const vc_commitment *cm;
     uint32_t b;
-    uint64_t foot;
-    int state = 0;  // 0 waiting, 1 running, 2 done
+    uint64_t bundle, ws, cnt;  // bytes of its proof bundle; workspace bytes and counters it needs
+    uint64_t held = 0;         // bytes charged for it (its bundle while the server holds it)
+    int state = 0;             // 0 waiting, 1 running, 2 done
     int rc = VC_OK;
     vc_proofs *out = nullptr;
     std::string err;
@@ -1029,34 +1052,73 @@ struct vc_server {
   std::condition_variable cv_work, cv_done;
   std::unordered_map<uint64_t, Req> reqs;  // element addresses stay valid while others come and go
   std::deque<uint64_t> queue;
-  uint64_t next_ticket = 1, in_use = 0;
+  uint64_t next_ticket = 1, in_use = 0, peak = 0;
   bool stop = false;
+
+  static uint64_t kept(const vc_exec *ex) { return ex->ws_size + ex->cnt_n * sizeof(uint32_t); }
+  // bytes request r adds when it runs on ex
+  static uint64_t need(const Req &r, const vc_exec *ex) {
+    uint64_t grow_ws = r.ws > ex->ws_size ? r.ws - ex->ws_size : 0;
+    uint64_t grow_cnt = r.cnt > ex->cnt_n ? (r.cnt - ex->cnt_n) * sizeof(uint32_t) : 0;
+    return r.bundle + grow_ws + grow_cnt;
+  }
 
   void worker(vc_exec *ex) {
     (void)hipSetDevice(ex->device);
     for (;;) {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || (!queue.empty() && in_use + reqs[queue.front()].foot <= budget); });
-      if (stop) return;
+      Req *r = nullptr;
+      uint64_t add = 0;
+      for (;;) {
+        if (stop) return;
+        if (!queue.empty()) {
+          Req &f = reqs[queue.front()];
+          add = need(f, ex);
+          if (in_use + add <= budget) {
+            r = &f;
+            break;
+          }
+          if (kept(ex)) {
+            // idle and keeping memory while the oldest request does not fit: release it (the
+            // executor's own thread frees it, outside the lock)
+            uint64_t k = kept(ex);
+            lk.unlock();
+            exec_release(ex);
+            lk.lock();
+            in_use -= k;
+            continue;
+          }
+        }
+        cv_work.wait(lk);
+      }
       uint64_t id = queue.front();
       queue.pop_front();
-      Req *r = &reqs[id];
       r->state = 1;
       r->t_start = clock::now();
-      in_use += r->foot;
+      r->held = r->bundle;
+      in_use += add;
+      peak = std::max(peak, in_use);
       lk.unlock();
       cv_work.notify_all();  // the next one may fit as well
       vc_proofs *out = nullptr;
       g_last_error[0] = 0;
+      uint64_t before = kept(ex);
       int rc = open_all_impl(r->pp, r->cm, r->b, ex, ex->main, &out);
       std::string err = rc != VC_OK ? std::string(g_last_error) : std::string();
       lk.lock();
+      // what the executor keeps now is charged in full (a failed call may have grown less)
+      in_use += kept(ex);
+      in_use -= before + (add - r->bundle);
+      if (rc != VC_OK) {
+        in_use -= r->held;
+        r->held = 0;
+      }
       r->rc = rc;
       r->out = out;
       r->err = err;
       r->t_done = clock::now();
       r->state = 2;
-      in_use -= r->foot;
+      (void)id;
       lk.unlock();
       cv_done.notify_all();
       cv_work.notify_all();
@@ -1103,8 +1165,8 @@ VC_API int vc_server_create(int device, uint32_t nexec, uint32_t nstreams, uint6
 VC_API int vc_server_submit(vc_server *sv, const vc_params *pp, const vc_commitment *cm, uint32_t b, uint64_t *ticket) {
   if (!sv || !pp || !cm || !ticket || cm->pp != pp || pp->device != sv->device) return VC_EINVAL;
   *ticket = 0;
-  uint64_t foot = 0;
-  if (int rc = vc_open_all_footprint(pp, b, &foot)) return rc;
+  uint64_t foot = 0, parts[3] = {0, 0, 0};
+  if (int rc = open_all_impl(pp, nullptr, b, nullptr, nullptr, nullptr, &foot, true, nullptr, parts)) return rc;
   if (foot > sv->budget) {
     snprintf(g_last_error, sizeof g_last_error, "request needs %llu bytes, budget %llu", (unsigned long long)foot,
              (unsigned long long)sv->budget);
@@ -1117,7 +1179,9 @@ VC_API int vc_server_submit(vc_server *sv, const vc_params *pp, const vc_commitm
     r.pp = pp;
     r.cm = cm;
     r.b = b;
-    r.foot = foot;
+    r.bundle = parts[0];
+    r.ws = parts[1];
+    r.cnt = parts[2];
     r.t_sub = vc_server::clock::now();
     sv->queue.push_back(id);
     *ticket = id;
@@ -1141,8 +1205,20 @@ VC_API int vc_server_wait(vc_server *sv, uint64_t ticket, vc_proofs **out, doubl
   int rc = r->rc;
   *out = r->out;
   if (rc != VC_OK) snprintf(g_last_error, sizeof g_last_error, "%s", r->err.c_str());
+  sv->in_use -= r->held;  // the bundle now belongs to the caller
   sv->reqs.erase(ticket);
+  lk.unlock();
+  sv->cv_work.notify_all();
   return rc;
+}
+
+VC_API int vc_server_stats(vc_server *sv, uint64_t stats[3]) {
+  if (!sv || !stats) return VC_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  stats[0] = sv->in_use;
+  stats[1] = sv->peak;
+  stats[2] = sv->budget;
+  return VC_OK;
 }
 
 VC_API void vc_proofs_free(vc_proofs *pr) {

@@ -66,7 +66,9 @@ def test_server_matches_single_jobs_and_oracle(vc):
     sv = vc.vc_server_create(0, 3, 2, budget)
     tickets = [sv.submit(pp, cm, b) for pp, cm, b, _ in jobs]
     got = [sv.wait(t) for t in tickets]
-    say("  served; single jobs")
+    held, peak, bud = sv.stats()
+    say("  served; the server held at most %d bytes (budget %d); single jobs" % (peak, bud))
+    assert bud == budget and 0 < peak <= budget
     for (pp, cm, b, limbs), (pr, (waited, total)), (L, _, bits, seed) in zip(jobs, got, spec):
         assert 0 <= waited <= total
         one = vc.vc_open_all(pp, cm, b)
@@ -110,3 +112,58 @@ def test_server_errors(vc):
         sv.submit(pp, cm, 1 + s)
     del sv
     torch.cuda.synchronize()
+
+
+def test_server_budget_counts_kept_workspace(vc):
+    """A budget that fits one large request but not a large request beside another executor's
+    kept workspace: the server stays within it (its accounting is exact), by releasing idle
+    executors' workspaces, and every request still equals the one-job call.  Device memory in
+    use, sampled while it serves, rises by at most the budget plus the one bundle the caller
+    holds, plus the runtime's queue allocations for an executor's first launches."""
+    import threading
+    spec = [(18, 1, 256, 51), (14, 1, 32, 52), (18, 2, 256, 53), (16, 1, 256, 54), (18, 1, 32, 55), (12, 2, 32, 56)]
+    params, jobs = {}, []
+    for L, b, bits, seed in spec:
+        if L not in params:
+            params[L] = vc.vc_setup(L, SEED, 0)
+        limbs = I.entries(1 << L, seed, bits)
+        jobs.append((params[L], vc.vc_commit(params[L], dev_entries(limbs, bits), bits), b))
+    foot = [vc.vc_open_all_footprint(pp, b) for pp, _, b in jobs]
+    budget = max(foot) + max(foot) // 8
+    sv = vc.vc_server_create(0, 3, 1, budget)
+    # warm-up: three small requests at once, so that every executor has launched (its queues
+    # exist) before the baseline is taken
+    pw = vc.vc_setup(10, SEED, 0)
+    cw = vc.vc_commit(pw, dev_entries(I.entries(1 << 10, 57, 32), 32), 32)
+    for t in [sv.submit(pw, cw, 1) for _ in range(3)]:
+        sv.wait(t)
+    torch.cuda.synchronize()
+    f0, tot = torch.cuda.mem_get_info()
+    used0 = tot - f0 - sv.stats()[0]  # without what the server holds now
+    seen = [0]
+    done = threading.Event()
+
+    def sample():
+        while not done.is_set():
+            f, t = torch.cuda.mem_get_info()
+            seen[0] = max(seen[0], t - f - used0)
+            done.wait(0.002)
+
+    th = threading.Thread(target=sample)
+    th.start()
+    tickets = [sv.submit(pp, cm, b) for pp, cm, b in jobs]
+    results = []
+    for t in tickets:
+        pr, _ = sv.wait(t)
+        results.append(pr.export("fc_x", 0) + pr.export("W"))
+        del pr  # the caller holds one bundle at a time
+    held, peak, bud = sv.stats()
+    done.set()
+    th.join()
+    say("  budget %d: the server held at most %d; device use rose by at most %d" % (budget, peak, seen[0]))
+    assert peak <= budget
+    assert seen[0] <= budget + max(foot) + (64 << 20)
+    del sv
+    for (pp, cm, b), got in zip(jobs, results):
+        one = vc.vc_open_all(pp, cm, b)
+        assert got == one.export("fc_x", 0) + one.export("W")
