@@ -8,6 +8,8 @@
 #include "oa_terms.hpp"
 
 #define SLP_T 64
+// slp::run_seq stages a call sequence of at most 256 calls in LDS
+static_assert(slp::ML_SEQ_LEN <= 256 && slp::FE_SEQ_LEN <= 256, "call sequence longer than its LDS copy");
 
 namespace {
 
