@@ -264,7 +264,9 @@ int vc_profile_read(char *buf, size_t cap);
 /* Self-test of the device field layer used by the proof rounds (8 lanes per
  * element): one operation on n pairs of canonical 32-byte little-endian host inputs,
  * results to out (n x 32 B).  op: 0 mul, 1 add, 2 sub, 3 halve, 4 inverse, 5 square;
- * which: 0 = F_p, 1 = F_r.  Inputs must be < the modulus. */
+ * which: 0 = F_p, 1 = F_r.  Inputs must be < the modulus.  which 2 (F_p) or 3 (F_r): raw
+ * Montgomery limbs in and out with no conversion (ops 0 mul, 1 add, 2 sub), any 256-bit
+ * inputs, for checking the layout's output range. */
 int vc_diag_field(int which, int op, uint64_t n, const void *a, const void *b, void *out);
 
 /* Diagnostic: measured throughput of the 32 x 32 -> 64-bit multiply-add on `device`, in

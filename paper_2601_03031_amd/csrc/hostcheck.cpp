@@ -313,6 +313,115 @@ API int hc_slp_lane(int op, int n, const int *k, const uint8_t *xs, uint8_t *out
 }
 
 
+// ---- host model of the 8-lane field layout (field_wide.hpp), lane for lane: element limbs
+// g = 0..7 as an array, the cross-lane steps written out (ds_swizzle broadcasts of limb k,
+// DPP shifts by one limb, the ballot carry-lookahead).  Raw Montgomery limbs in and out, no
+// conversions, so that the range of every output can be checked at the inputs' extremes and
+// compared bit for bit with the device (vc_diag_field's raw modes).
+namespace w8 {
+struct V { uint32_t v[8]; };
+static void shdn(const uint32_t *x, uint32_t *o) { for (int g = 0; g < 8; g++) o[g] = g < 7 ? x[g + 1] : 0u; }
+static void shup(const uint32_t *x, uint32_t *o) { for (int g = 0; g < 8; g++) o[g] = g ? x[g - 1] : 0u; }
+// carry into each lane from per-lane generate/propagate flags, and the carry out of lane 7,
+// exactly as wchain(): C = ((g|p) + g) ^ (g|p) ^ g over the lanes 0..6, lane 7's own flags
+// decide the carry out
+static uint32_t g_active = 0xFF;  // lanes taking part in the ballots (all 8 in the library)
+static void chain(const bool *gen, const bool *prop, uint32_t *cin, bool &out) {
+  uint32_t G = 0, P = 0;
+  for (int g = 0; g < 8; g++) { G |= (uint32_t)gen[g] << g; P |= (uint32_t)prop[g] << g; }
+  G &= g_active;  // a ballot sees only active lanes
+  P &= g_active;
+  uint32_t gg = G & 0x7f, pp = P & 0x7f, a = gg | pp;
+  uint32_t C = (a + gg) ^ a ^ gg;
+  for (int g = 0; g < 8; g++) cin[g] = (C >> g) & 1u;
+  out = (((G >> 7) & 1u) | (((P >> 7) & 1u) & ((C >> 7) & 1u))) != 0;
+}
+static void reduce(const uint32_t *M, const uint32_t *s, uint32_t *o) {  // s - m if s >= m
+  bool gen[8], prop[8], bout;
+  uint32_t bin[8];
+  for (int g = 0; g < 8; g++) { gen[g] = s[g] < M[g]; prop[g] = s[g] == M[g]; }
+  chain(gen, prop, bin, bout);
+  for (int g = 0; g < 8; g++) o[g] = bout ? s[g] : s[g] - M[g] - bin[g];
+}
+static void add(const uint32_t *M, const uint32_t *a, const uint32_t *b, uint32_t *o) {
+  uint32_t lo[8], cin[8], t[8];
+  bool gen[8], prop[8], out;
+  for (int g = 0; g < 8; g++) {
+    uint64_t s = (uint64_t)a[g] + b[g];
+    lo[g] = (uint32_t)s;
+    gen[g] = (s >> 32) != 0;
+    prop[g] = lo[g] == 0xFFFFFFFFu;
+  }
+  chain(gen, prop, cin, out);
+  for (int g = 0; g < 8; g++) t[g] = lo[g] + cin[g];
+  reduce(M, t, o);
+}
+static void sub(const uint32_t *M, const uint32_t *a, const uint32_t *b, uint32_t *o) {
+  bool gen[8], prop[8], bout, out;
+  uint32_t bin[8], d[8], lo[8], cin[8];
+  for (int g = 0; g < 8; g++) { gen[g] = a[g] < b[g]; prop[g] = a[g] == b[g]; }
+  chain(gen, prop, bin, bout);
+  for (int g = 0; g < 8; g++) {
+    d[g] = a[g] - b[g] - bin[g];
+    uint64_t s = (uint64_t)d[g] + (bout ? M[g] : 0u);
+    lo[g] = (uint32_t)s;
+    gen[g] = (s >> 32) != 0;
+    prop[g] = lo[g] == 0xFFFFFFFFu;
+  }
+  chain(gen, prop, cin, out);
+  for (int g = 0; g < 8; g++) o[g] = lo[g] + cin[g];
+}
+static void mul(const uint32_t *M, uint32_t INV, const uint32_t *a, const uint32_t *b, uint32_t *o) {
+  uint32_t t[8] = {0}, c[8] = {0};
+  for (int j = 0; j < 8; j++) {
+    uint64_t X[8], Y[8];
+    uint32_t ylo[8], yd[8];
+    for (int g = 0; g < 8; g++) X[g] = (uint64_t)a[g] * b[j] + t[g];
+    uint32_t m = (uint32_t)X[0] * INV;
+    for (int g = 0; g < 8; g++) { Y[g] = (uint64_t)m * M[g] + (uint32_t)X[g]; ylo[g] = (uint32_t)Y[g]; }
+    shdn(ylo, yd);
+    for (int g = 0; g < 8; g++) {
+      uint64_t s = (uint64_t)yd[g] + (X[g] >> 32) + (Y[g] >> 32) + c[g];
+      t[g] = (uint32_t)s;
+      c[g] = (uint32_t)(s >> 32);
+    }
+  }
+  uint32_t cu[8], lo[8], cin[8], r[8];
+  bool gen[8], prop[8], out;
+  shup(c, cu);
+  for (int g = 0; g < 8; g++) {
+    uint64_t f = (uint64_t)t[g] + cu[g];
+    lo[g] = (uint32_t)f;
+    gen[g] = (f >> 32) != 0;
+    prop[g] = lo[g] == 0xFFFFFFFFu;
+  }
+  chain(gen, prop, cin, out);
+  for (int g = 0; g < 8; g++) r[g] = lo[g] + cin[g];
+  reduce(M, r, o);
+}
+}  // namespace w8
+
+// the lanes of a group that take part in the ballots (0xFF: all; the library's kernels keep
+// every group whole)
+API void hc_wide_active(uint32_t mask) { w8::g_active = mask & 0xFF; }
+
+// op 0 mul, 1 add, 2 sub on raw little-endian limbs (32 bytes each); which 0: p, 1: r
+API int hc_wide_raw(int which, int op, const uint8_t *a, const uint8_t *b, uint8_t *out) {
+  const uint32_t *M = which ? bn::R_MOD : bn::P_MOD;
+  const uint32_t INV = which ? bn::R_INV : bn::P_INV;
+  uint32_t x[8], y[8], z[8];
+  memcpy(x, a, 32);
+  memcpy(y, b, 32);
+  switch (op) {
+    case 0: w8::mul(M, INV, x, y, z); break;
+    case 1: w8::add(M, x, y, z); break;
+    case 2: w8::sub(M, x, y, z); break;
+    default: return -1;
+  }
+  memcpy(out, z, 32);
+  return 0;
+}
+
 // GLS decomposition of a canonical scalar (big-endian 32 bytes): out = 4 signed 128-bit
 // two's-complement values (little-endian 16 bytes each) and the bit length
 API int hc_gls(const uint8_t *kb, uint8_t *out, uint32_t *nbits) {

@@ -195,13 +195,18 @@ __global__ void __launch_bounds__(TPBW) kw_dlevel(void *D, uint64_t K, uint32_t 
 
 // ---------------------------------------------------------------- diagnostics
 // field operation on canonical inputs (limbs), for the layout self-test:
-// op 0 mul, 1 add, 2 sub, 3 half, 4 inverse, 5 square; F_p if which == 0 else F_r
+// op 0 mul, 1 add, 2 sub, 3 half, 4 inverse, 5 square; F_p if which == 0, F_r if 1;
+// which 2 (F_p) / 3 (F_r): ops 0-2 on raw Montgomery limbs, no conversion either way
 __global__ void __launch_bounds__(TPBW) kw_diag_field(int which, int op, const void *a, const void *b, uint64_t n,
                                                      void *out) {
   uint64_t i = wgid();
   if (i >= n) return;
   fe x = wld<fe>(a, i), y = wld<fe>(b, i), r;
-  if (which == 0) {
+  if (which >= 2) {
+    // raw Montgomery limbs in and out (ops 0 mul, 1 add, 2 sub), to check the range of results
+    if (which == 2) r = op == 0 ? f_mul<FpP>(x, y) : op == 1 ? f_add<FpP>(x, y) : f_sub<FpP>(x, y);
+    else r = op == 0 ? f_mul<FpR>(x, y) : op == 1 ? f_add<FpR>(x, y) : f_sub<FpR>(x, y);
+  } else if (which == 0) {
     x = f_to_mont<FpP>(x);
     y = f_to_mont<FpP>(y);
     switch (op) {

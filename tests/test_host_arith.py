@@ -399,3 +399,36 @@ def test_split_fold(hc, grp):
         o = buf(size)
         assert fn(Pt, k.to_bytes(32, "big"), A, o) == 0
         assert o.raw == op("add", op("mul", Pt, O.be32(k)), A), (k,)
+
+
+def wide_raw(hc, which, op, a, b):
+    o = buf(32)
+    assert hc.hc_wide_raw(which, op, a.to_bytes(32, "little"), b.to_bytes(32, "little"), o) == 0
+    return int.from_bytes(o.raw, "little")
+
+
+@pytest.mark.parametrize("which,mod", [(0, P), (1, R)])
+def test_wide_layout_output_range(hc, which, mod):
+    """The 8-lane field layout's operations (lane model of field_wide.hpp: limb broadcasts, limb
+    shifts, ballot carry-lookahead) on raw Montgomery limbs at the extremes of their inputs.
+    With canonical inputs (below the modulus) every result is canonical and correct; products
+    stay canonical and correct for inputs up to twice the modulus.  So values built only from
+    these operations on canonical inputs (the wide Miller loop's F_p12 coefficients from
+    canonical affine points) are canonical."""
+    rng = random.Random(41 + which)
+    rinv = pow(1 << 256, -1, mod)
+    canon = [0, 1, 2, mod - 1, mod - 2, mod >> 1, (1 << 32) - 1, 1 << 32, (1 << 224) + 5] + \
+        [rng.randrange(mod) for _ in range(200)]
+    for i, a in enumerate(canon):
+        b = canon[(7 * i + 3) % len(canon)]
+        m = wide_raw(hc, which, 0, a, b)
+        assert m < mod and m == a * b * rinv % mod, (a, b)
+        s = wide_raw(hc, which, 1, a, b)
+        assert s < mod and s == (a + b) % mod, (a, b)
+        d = wide_raw(hc, which, 2, a, b)
+        assert d < mod and d == (a - b) % mod, (a, b)
+    below2 = [mod, mod + 1, 2 * mod - 1, 2 * mod - 2] + [rng.randrange(mod, 2 * mod) for _ in range(200)]
+    for i, a in enumerate(below2):
+        for b in (below2[(5 * i + 1) % len(below2)], canon[i % len(canon)]):
+            m = wide_raw(hc, which, 0, a, b)
+            assert m < mod and m == a * b * rinv % mod, (a, b)
