@@ -51,10 +51,10 @@ extern "C" {
 #define VC_ENOTIMPL (-4)
 #define VC_ECHALLENGE (-5) /* a Fiat-Shamir challenge was zero (probability ~2^-254) */
 
-/* Largest log2 N: at N = 2^30 an open-all with b = log^2 N holds about 194 GB of device
- * memory with its input (entries, commitment copy, Merkle tree and y-tree dominate, about
- * 192 N bytes), which fits the 288 GB of one MI355X; 2^31 does not.  Per-element thread
- * indices stay below 2^32 up to this size. */
+/* Largest log2 N: at N = 2^30 an open-all with b = log^2 N, its entries and commitment hold
+ * about 212 GB of device memory (measured; the entries, their copy in the commitment, the
+ * Merkle tree and the y-tree dominate, about 192 N bytes), which fits the 288 GB of one
+ * MI355X; 2^31 does not.  Per-element thread indices stay below 2^32 up to this size. */
 #define VC_MAX_LOG_N 30
 
 typedef struct vc_params vc_params;
@@ -66,6 +66,21 @@ typedef struct vc_exec vc_exec;
  * K entries, derived from a seeded TEST trapdoor (insecure: the paper requires a
  * trusted setup).  2 <= log_n <= VC_MAX_LOG_N.  The keys stay resident on `device`. */
 int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out);
+
+/* Parameters from an externally made SRS (PC.Setup, section 4.1; FC.Setup, section 3; the
+ * faster verifier's extra G2 powers, section 3): srs (host, borrowed for the call) is the
+ * concatenation, in this order, of ek_k for k = 0..log M (2^k G1 points each, the
+ * Lagrange-basis keys of k variables), vk (log M G2 points s_k g2), h (2K - 1 G2 points
+ * beta^k g2) and beta g1 (one G1 point) -- exactly what vc_params_export returns for what 0
+ * (idx 0..log M), 1, 2 and 3.  Each coordinate is 32 B canonical big-endian; G2
+ * coordinates are (c0, c1).  len fixes N: it must equal 64 (2M - 1) + 128 log M +
+ * 128 (2K - 1) + 64 for some 2 <= log N <= VC_MAX_LOG_N (K = 2^floor(log N / 2),
+ * M = N / K), else VC_EINVAL.  A coordinate >= p or a point off its curve (G1, or the
+ * twist for G2) gives VC_EINVAL; points are not checked for membership in the order-r
+ * subgroup of the twist, nor the keys for coming from one trapdoor (the caller trusts the
+ * setup that made them).  The keys and the tables derived from them stay resident on
+ * `device`; free with vc_params_free. */
+int vc_params_load(const uint8_t *srs, size_t len, int device, vc_params **out);
 
 /* VC.Commit(m) (Eq. genCi, genC).  m_dev: n entries on the device, either n x 32 B
  * canonical little-endian (entry_bits = 256) or n x uint32 (entry_bits = 32, the
@@ -260,6 +275,15 @@ int vc_proofs_export(const vc_proofs *pr, int what, uint64_t idx, void *dst, siz
 void vc_profile_enable(int on);
 void vc_profile_only(const char *kernel);
 int vc_profile_read(char *buf, size_t cap);
+
+/* Test hook for the zero-challenge error (section 3, FC.BOpen: the fold needs x_j^{-1}, so
+ * a challenge of zero ends the proof; a hashed challenge is zero with probability about
+ * 2^-254, so nothing else reaches that path).  round >= 1: every later open-all
+ * (vc_open_all, vc_open_all_ex, vc_open_all_batch, the serving loop, sub-arrays,
+ * evaluation proofs) replaces batch 0's challenge x_round by zero and returns
+ * VC_ECHALLENGE, releasing the bundle it made; 0 (the default) turns the hook off.
+ * Process-wide; for tests only. */
+void vc_test_zero_challenge(uint32_t round);
 
 /* Self-test of the device field layer used by the proof rounds (8 lanes per
  * element): one operation on n pairs of canonical 32-byte little-endian host inputs,

@@ -58,6 +58,7 @@ def lib():
         L.vc_commit.argtypes = [vp, vp, u64, u32, vp, C.POINTER(vp), vp]
         L.vc_open_all.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
         L.vc_commit_noalloc.argtypes = [vp, vp, u64, u32, vp, vp, vp]
+        L.vc_params_load.argtypes = [u8p, sz, C.c_int, C.POINTER(vp)]
         L.vc_diag_mad_rate.argtypes = [C.c_int, C.POINTER(C.c_double)]
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
@@ -94,6 +95,7 @@ def lib():
         L.vc_profile_enable.argtypes = [C.c_int]
         L.vc_profile_only.argtypes = [C.c_char_p]
         L.vc_profile_read.argtypes = [C.c_char_p, sz]
+        L.vc_test_zero_challenge.argtypes = [u32]
         L.vc_strerror.restype = C.c_char_p
         L.vc_strerror.argtypes = [C.c_int]
         _lib = L
@@ -142,6 +144,11 @@ class Params(_Handle):
         _check(lib().vc_params_export(self.ptr, codes[what], idx, buf, n.value, C.byref(n)), "vc_params_export")
         return buf.raw
 
+    def srs_bytes(self) -> bytes:
+        """The keys in vc_params_load's layout: ek_0..ek_{log M}, vk, h, beta g1."""
+        return b"".join([self.export("ek", k) for k in range(self.lM + 1)] +
+                        [self.export("vk"), self.export("h"), self.export("g1beta")])
+
 
 class Commitment(_Handle):
     _free = "vc_commitment_free"
@@ -180,6 +187,20 @@ def vc_setup(log_n: int, seed: bytes, device: int = 0) -> Params:
     out = C.c_void_p()
     _check(lib().vc_setup(log_n, seed, device, C.byref(out)), "vc_setup")
     return Params(out, log_n, device)
+
+
+def vc_params_load(srs: bytes, device: int = 0) -> Params:
+    """Parameters from an externally made SRS (the layout of Params.srs_bytes)."""
+    out = C.c_void_p()
+    _check(lib().vc_params_load(srs, len(srs), device, C.byref(out)), "vc_params_load")
+    log_n = next(L for L in range(2, 31) if _srs_len(L) == len(srs))
+    return Params(out, log_n, device)
+
+
+def _srs_len(L: int) -> int:
+    lK = L // 2
+    lM = L - lK
+    return 64 * (2 * (1 << lM) - 1) + 128 * lM + 128 * (2 * (1 << lK) - 1) + 64
 
 
 def _check_entries(pp: Params, m, entry_bits: int) -> None:
@@ -395,6 +416,12 @@ def vc_diag_mad_rate(device: int = 0) -> float:
 
 def vc_profile_enable(on: bool = True) -> None:
     lib().vc_profile_enable(1 if on else 0)
+
+
+def vc_test_zero_challenge(round_: int) -> None:
+    """Test hook: later open-alls force batch 0's challenge x_round to zero and fail with
+    VC_ECHALLENGE (0 turns it off)."""
+    lib().vc_test_zero_challenge(round_)
 
 
 def vc_profile_only(kernel=None) -> None:

@@ -92,6 +92,30 @@ __global__ void __launch_bounds__(TPB) k_check_fr(const fe *m, uint64_t n, int *
   if (!fe_lt_mod(m[i], bn::R_MOD)) atomicOr(err, VC_ERRBIT_RANGE);
 }
 
+// canonical 32-byte big-endian F_p encodings -> Montgomery form; a value >= p sets the range
+// bit (and is stored as zero)
+__global__ void __launch_bounds__(TPB) k_decode_fp(const uint8_t *in, uint64_t n, fe *out, int *err) {
+  uint64_t i = gtid();
+  if (i >= n) return;
+  fe c;
+  const uint8_t *b = in + 32 * i;
+  for (int q = 0; q < 8; q++)
+    c.l[7 - q] = ((uint32_t)b[4 * q] << 24) | ((uint32_t)b[4 * q + 1] << 16) | ((uint32_t)b[4 * q + 2] << 8) | b[4 * q + 3];
+  if (!fe_lt_mod(c, bn::P_MOD)) {
+    atomicOr(err, VC_ERRBIT_RANGE);
+    c = fe_zero();
+  }
+  out[i] = f_to_mont<FpP>(c);
+}
+
+// points off the curve (G1: y^2 = x^3 + 3; G2: the twist) set the range bit
+template <class O>
+__global__ void __launch_bounds__(TPB) k_check_curve(const aff<O> *p, uint64_t n, int *err) {
+  uint64_t i = gtid();
+  if (i >= n) return;
+  if (!aff_on_curve(p[i])) atomicOr(err, VC_ERRBIT_RANGE);
+}
+
 // Batched MSM with shared bases: C_j = sum_a m[jM+a] ek[a] (canonical scalars).  Block
 // (j, slice) handles bases [slice*S, (slice+1)*S); every (base, window) pair with a nonzero
 // 8-bit digit is counting-sorted by digit in LDS, thread d sums bucket d over the
@@ -274,6 +298,9 @@ void msm_tables_g2(const g2_aff *base, uint64_t M, uint32_t nwin, g2_aff *table,
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st) { L1(k_lift_u32, n, in, n, out); }
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st) { L1(k_check_fr, n, m, n, err); }
 void zero_u32(uint32_t *p, uint64_t n, hipStream_t st) { if (n) L1(k_zero_u32, n, p, n); }
+void decode_fp(const uint8_t *in, uint64_t n, fe *out, int *err, hipStream_t st) { if (n) L1(k_decode_fp, n, in, n, out, err); }
+void check_curve_g1(const g1_aff *p, uint64_t n, int *err, hipStream_t st) { if (n) L1(k_check_curve<OpsG1>, n, p, n, err); }
+void check_curve_g2(const g2_aff *p, uint64_t n, int *err, hipStream_t st) { if (n) L1(k_check_curve<OpsG2>, n, p, n, err); }
 void diag_mad(uint32_t seed, uint32_t iters, unsigned blocks, uint64_t *out, hipStream_t st) {
   LAUNCH(k_diag_mad, dim3(blocks), dim3(256), 0, seed, iters, out);
 }

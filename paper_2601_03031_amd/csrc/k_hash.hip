@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(TPB) k_oa_lr_aff(const g1_jac *S, uint64_t K, 
 // inverse runs on the scalar unit.
 __global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j,
                                                      uint32_t lK, const g1_aff *Lg1, const g1_aff *Rg1, fe *X, fe *Xinv,
-                                                     int *err) {
+                                                     int *err, uint32_t zero_round) {
   CHAIN_PRIORITY();
   __shared__ uint32_t msg[16 + 8 + 2 * (96 + 16) + 32], t2[16];
   uint64_t k = blockIdx.x;
@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp1
   }
   __syncthreads();
   fe x = sha::xmd_fr_coop(sha::Coop{t, 64}, msg, 4 * (pre + 224), DSTR_FC_X, t2);
+  if (zero_round == j && k == 0) x = fe_zero();  // test hook: the host forces a zero challenge
   fe xi = f_inv_uniform<FpR>(x, bn::R_R3);
   if (t == 0) {
     if (fe_is_zero(x)) atomicOr(err, VC_ERRBIT_CHALLENGE);
@@ -332,8 +333,8 @@ void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK
   L1(k_oa_lr_aff, 2 * nb, S, K, nb, j, lK, Lg1, Rg1);
 }
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
-                   const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st) {
-  LAUNCH(k_oa_transcript, dim3((unsigned)nb), dim3(64), 0, Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err);
+                   const g1_aff *Rg1, fe *X, fe *Xinv, int *err, uint32_t zero_round, hipStream_t st) {
+  LAUNCH(k_oa_transcript, dim3((unsigned)nb), dim3(64), 0, Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, zero_round);
 }
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   fe *gws, hipStream_t st) {

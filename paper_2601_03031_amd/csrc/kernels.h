@@ -22,6 +22,11 @@ void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hi
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st);
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
 void zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
+// canonical big-endian F_p encodings (32 B each) -> Montgomery form; >= p sets VC_ERRBIT_RANGE
+void decode_fp(const uint8_t *in, uint64_t n, fe *out, int *err, hipStream_t st);
+// points not on their curve set VC_ERRBIT_RANGE
+void check_curve_g1(const g1_aff *p, uint64_t n, int *err, hipStream_t st);
+void check_curve_g2(const g2_aff *p, uint64_t n, int *err, hipStream_t st);
 // multiply-add throughput probe: blocks x 256 lanes, 8 iters multiply-adds each
 void diag_mad(uint32_t seed, uint32_t iters, unsigned blocks, uint64_t *out, hipStream_t st);
 void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g1_aff *table, g1_jac *partial,
@@ -44,8 +49,10 @@ void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *
 void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
 void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st);
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st);
+// x_j = H'(x_{j-1} || L_j || R_j) per batch (zero_round == j: batch 0's challenge is forced to
+// zero, a test hook for the zero-challenge error; 0 leaves every challenge as hashed)
 void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, uint32_t lK, const g1_aff *Lg1,
-                   const g1_aff *Rg1, fe *X, fe *Xinv, int *err, hipStream_t st);
+                   const g1_aff *Rg1, fe *X, fe *Xinv, int *err, uint32_t zero_round, hipStream_t st);
 // L[k lK], R[k lK] = U[2k + side] + sum_{g, p} P[4 (4k + g) + p] over the 8 split parts of
 // each side (affine)
 // gws: 4 (2K - 1) elements per batch of global working space, used when K > 1024

@@ -68,6 +68,7 @@ struct ProfRec {
 };
 bool g_prof = false;
 std::string g_prof_only;          // empty: every kernel
+std::atomic<uint32_t> g_zero_round{0};  // test hook: round whose batch-0 challenge is forced to zero
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;  // timing events, reused across profiling runs
 size_t g_prof_next = 0;
@@ -313,18 +314,14 @@ VC_API const char *vc_strerror(int code) {
 }
 
 // ------------------------------------------------------------------ setup
-VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out) {
-  (void)hipGetLastError();  // errors left by other HIP clients are not ours
-  if (!out || !seed || log_n < 2 || log_n > VC_MAX_LOG_N) return VC_EINVAL;
-  *out = nullptr;
-  CK(hipSetDevice(device));
+// the parameters' executor and key memory for N = 2^log_n (keys not yet written)
+static int params_alloc(uint32_t log_n, int device, vc_params **out) {
   vc_params *pp = new vc_params();
   pp->device = device;
   if (int rc = vc_exec_create(device, 6, &pp->ex)) {
     vc_params_free(pp);
     return rc;
   }
-  vc_exec *ex = pp->ex;
   pp->L = log_n;
   pp->lK = log_n / 2;
   pp->lM = log_n - pp->lK;
@@ -337,7 +334,10 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   size_t o_tab = c.take<g1_aff>(NWIN * M), o_vk = c.take<g2_aff>(lM), o_h = c.take<g2_aff>(2 * K - 1);
   size_t o_g2 = c.take<g2_aff>(1), o_htab = c.take<g2_aff>(NWIN * (2 * K - 2)), o_hm = c.take<g2_aff>(3 * (2 * K - 2));
   hipError_t e = hipMalloc(&pp->mem, c.off);
-  if (e != hipSuccess) { delete pp; return hip_fail(e, "vc_setup alloc"); }
+  if (e != hipSuccess) {
+    vc_params_free(pp);
+    return hip_fail(e, "vc_setup alloc");
+  }
   pp->ek = at<g1_aff>(pp->mem, o_ek);
   pp->g1gen = at<g1_aff>(pp->mem, o_g1);
   pp->g1beta = at<g1_aff>(pp->mem, o_g1b);
@@ -349,6 +349,34 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   pp->hm = at<g2_aff>(pp->mem, o_hm);
   g1_aff g1 = {fe_const(bn::G1X), fe_const(bn::G1Y)};
   g2_aff g2 = {{fe_const(bn::G2X0), fe_const(bn::G2X1)}, {fe_const(bn::G2Y0), fe_const(bn::G2Y1)}};
+  e = hipMemcpy(pp->g1gen, &g1, sizeof g1, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pp->g2gen, &g2, sizeof g2, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    vc_params_free(pp);
+    return hip_fail(e, "vc_setup");
+  }
+  *out = pp;
+  return VC_OK;
+}
+
+// fixed-base tables of the keys: the commit MSM's 2^{8 w} ek_{l_M}[a], the KZG MSM's
+// 2^{8 w} h_m and the split KZG terms' 2^{16 p} h_m
+static void params_tables(vc_params *pp, hipStream_t st) {
+  const uint64_t K = pp->K, M = pp->M;
+  kl::msm_tables_g2(pp->h, 2 * K - 2, NWIN, pp->htab, st);
+  ks::g2_dbl_mults(pp->h, 2 * K - 2, 0, 2 * K - 2, pp->hm, st);
+  kl::msm_tables(pp->ek + (M - 1), M, NWIN, pp->table, st);
+}
+
+VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_params **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!out || !seed || log_n < 2 || log_n > VC_MAX_LOG_N) return VC_EINVAL;
+  *out = nullptr;
+  CK(hipSetDevice(device));
+  vc_params *pp = nullptr;
+  if (int rc = params_alloc(log_n, device, &pp)) return rc;
+  vc_exec *ex = pp->ex;
+  const uint64_t K = pp->K, M = pp->M, lM = pp->lM;
   // temporaries: seed, trapdoor, weights
   Carve t;
   size_t o_seed = t.take<uint8_t>(32), o_s = t.take<fe>(lM + 1), o_beta = t.take<fe>(1);
@@ -357,9 +385,8 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   if (rc) { vc_params_free(pp); return rc; }
   hipStream_t st = nullptr;
   void *ws = ex->ws;
-  CK(hipMemcpy(pp->g1gen, &g1, sizeof g1, hipMemcpyHostToDevice));
-  CK(hipMemcpy(pp->g2gen, &g2, sizeof g2, hipMemcpyHostToDevice));
-  CK(hipMemcpy(at<uint8_t>(ws, o_seed), seed, 32, hipMemcpyHostToDevice));
+  hipError_t e = hipMemcpy(at<uint8_t>(ws, o_seed), seed, 32, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { vc_params_free(pp); return hip_fail(e, "vc_setup"); }
   fe *s = at<fe>(ws, o_s), *beta = at<fe>(ws, o_beta), *w = at<fe>(ws, o_w), *pw = at<fe>(ws, o_pw);
   kl::trapdoor(at<uint8_t>(ws, o_seed), pp->lM, s, beta, st);
   kl::ek_weights(pp->lM, s, w, 2 * M - 1, st);
@@ -367,12 +394,66 @@ VC_API int vc_setup(uint32_t log_n, const uint8_t seed[32], int device, vc_param
   klw::g2_mul(pp->g2gen, 1, s, lM, pp->vk, st);
   kl::pow_table(beta, pw, 2 * K - 1, st);
   klw::g2_mul(pp->g2gen, 1, pw, 2 * K - 1, pp->h, st);
-  kl::msm_tables_g2(pp->h, 2 * K - 2, NWIN, pp->htab, st);
-  ks::g2_dbl_mults(pp->h, 2 * K - 2, 0, 2 * K - 2, pp->hm, st);
   klw::g1_mul(pp->g1gen, 1, beta, 1, pp->g1beta, st);
-  kl::msm_tables(pp->ek + (M - 1), M, NWIN, pp->table, st);
-  CKL("vc_setup launch");
-  CK(hipDeviceSynchronize());
+  params_tables(pp, st);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) { vc_params_free(pp); return hip_fail(e, "vc_setup"); }
+  *out = pp;
+  return VC_OK;
+}
+
+// bytes of an SRS for N = 2^log_n in vc_params_load's layout
+static uint64_t srs_bytes(uint32_t log_n) {
+  const uint64_t lK = log_n / 2, lM = log_n - lK, K = 1ull << lK, M = 1ull << lM;
+  return 64 * (2 * M - 1) + 128 * lM + 128 * (2 * K - 1) + 64;
+}
+
+VC_API int vc_params_load(const uint8_t *srs, size_t len, int device, vc_params **out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!out || !srs) return VC_EINVAL;
+  *out = nullptr;
+  uint32_t log_n = 0;
+  for (uint32_t L = 2; L <= VC_MAX_LOG_N && !log_n; L++)
+    if (srs_bytes(L) == len) log_n = L;
+  if (!log_n) return VC_EINVAL;
+  CK(hipSetDevice(device));
+  vc_params *pp = nullptr;
+  if (int rc = params_alloc(log_n, device, &pp)) return rc;
+  const uint64_t K = pp->K, M = pp->M, lM = pp->lM;
+  const uint64_t n_ek = 2 * (2 * M - 1), n_vk = 4 * lM, n_h = 4 * (2 * K - 1), n_fe = len / 32;
+  Carve t;
+  size_t o_err = t.take<int>(1), o_in = t.take<uint8_t>(len), o_fe = t.take<fe>(n_fe);
+  int rc = ensure_ws(pp->ex, t.off);
+  if (rc) { vc_params_free(pp); return rc; }
+  hipStream_t st = nullptr;
+  void *ws = pp->ex->ws;
+  int *err = at<int>(ws, o_err);
+  fe *v = at<fe>(ws, o_fe);
+  int herr = 0;
+  hipError_t e = hipMemcpy(at<uint8_t>(ws, o_in), srs, len, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    kl::zero_u32(reinterpret_cast<uint32_t *>(err), 1, st);
+    kl::decode_fp(at<uint8_t>(ws, o_in), n_fe, v, err, st);
+    e = hipGetLastError();
+  }
+  // the decoded elements are the key arrays' memory images, in the order ek, vk, h, beta g1
+  if (e == hipSuccess) e = hipMemcpyAsync(pp->ek, v, n_ek * sizeof(fe), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(pp->vk, v + n_ek, n_vk * sizeof(fe), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(pp->h, v + n_ek + n_vk, n_h * sizeof(fe), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(pp->g1beta, v + n_ek + n_vk + n_h, 2 * sizeof(fe), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) {
+    kl::check_curve_g1(pp->ek, 2 * M - 1, err, st);
+    kl::check_curve_g1(pp->g1beta, 1, err, st);
+    kl::check_curve_g2(pp->vk, lM, err, st);
+    kl::check_curve_g2(pp->h, 2 * K - 1, err, st);
+    params_tables(pp, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(&herr, err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) { vc_params_free(pp); return hip_fail(e, "vc_params_load"); }
+  if (herr) { vc_params_free(pp); return VC_EINVAL; }
   *out = pp;
   return VC_OK;
 }
@@ -878,7 +959,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
       ks::oa_combine_split(PX[par], PXm[par], PX1[par], PX1m[par], X + (j - 2), Xinv + (j - 2), lK, nb, PE, PM, st);
       ks::oa_combine8(PU[par], PE, PU1[par], PM, nb, Lgt + (j - 1), Rgt + (j - 1), Lg1 + (j - 1), Rg1 + (j - 1), lK, st);
     }
-    kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, st);
+    kl::oa_transcript(Lgt, Rgt, nb, j, lK, Lg1, Rg1, X, Xinv, err, g_zero_round.load(), st);
     // fold with x_j into the other buffer
     if (ahead) {
       if (int rc2 = stream_wait(ex, 4, st, sg)) return rc2;
@@ -1661,6 +1742,8 @@ VC_API void vc_profile_enable(int on) {
 }
 
 VC_API void vc_profile_only(const char *kernel) { g_prof_only = kernel ? kernel : ""; }
+
+VC_API void vc_test_zero_challenge(uint32_t round) { g_zero_round.store(round); }
 
 // one line per kernel: "<name> <launches> <total_ms>\n"; returns bytes needed
 VC_API int vc_profile_read(char *buf, size_t cap) {

@@ -147,6 +147,88 @@ def test_rejects_bad_input(vc):
         assert e.value.code == vc.VC_EINVAL
 
 
+@pytest.mark.parametrize("L,b", [(5, 2), (8, 16)])
+def test_params_load_oracle_srs(vc, L, b):
+    """An externally made SRS: the oracle's keys from a trapdoor seed no device setup uses,
+    loaded with vc_params_load; the keys read back unchanged, and commit + open-all on them
+    equal the oracle's on the same keys, every array and every proof."""
+    other = b"external-srs".ljust(32, b"\0")
+    say("params load: L=%d b=%d" % (L, b))
+    opp = O.Params(L, other)
+    srs = b"".join([opp.export("ek", k) for k in range(L - L // 2 + 1)] +
+                   [opp.export("vk"), opp.export("h"), opp.export("g1beta")])
+    gpp = vc.vc_params_load(srs, 0)
+    assert gpp.log_n == L and gpp.srs_bytes() == srs
+    limbs = I.entries(1 << L, 40 + L)
+    ocm = O.Commitment(opp, I.limbs_to_bytes(limbs))
+    oop = O.Opening(ocm, b)
+    gcm = vc.vc_commit(gpp, dev_entries(limbs), 256)
+    assert gcm.C == ocm.C and gcm.export("Cj") == b"".join(ocm.Cj)
+    gpr = vc.vc_open_all(gpp, gcm, b)
+    for k in range(oop.nb):
+        for w in ("fc_x", "fc_rounds", "fc_tail"):
+            assert gpr.export(w, k) == oop.export(w, k), (w, k)
+    for w in ("merkle", "rho", "y", "D", "W"):
+        assert gpr.export(w) == oop.export(w), w
+    for i in range(1 << L):
+        assert vc.vc_proof_get(gpr, i) == oop.proof(i), i
+
+
+def test_params_load_rejects(vc):
+    """Lengths that fit no size, a coordinate >= p and a point moved off its curve."""
+    srs = vc.vc_setup(4, SEED, 0).srs_bytes()
+    for bad_len in (srs[:-1], srs + b"\0" * 32, b""):
+        with pytest.raises(vc.VCError) as e:
+            vc.vc_params_load(bad_len, 0)
+        assert e.value.code == vc.VC_EINVAL
+    P = O.P
+    big = bytearray(srs)
+    big[0:32] = P.to_bytes(32, "big")  # x of ek_0[0] = p
+    off = bytearray(srs)
+    y = int.from_bytes(off[32:64], "big")
+    off[32:64] = ((y + 1) % P).to_bytes(32, "big")  # y of ek_0[0] + 1: off the curve
+    h0 = 64 * (2 * 4 - 1) + 128 * 2  # first h point (L = 4: M = 4, log M = 2)
+    off2 = bytearray(srs)
+    x = int.from_bytes(off2[h0:h0 + 32], "big")
+    off2[h0:h0 + 32] = ((x + 1) % P).to_bytes(32, "big")  # a G2 point off the twist
+    for bad in (big, off, off2):
+        with pytest.raises(vc.VCError) as e:
+            vc.vc_params_load(bytes(bad), 0)
+        assert e.value.code == vc.VC_EINVAL
+    assert vc.vc_params_load(srs, 0).srs_bytes() == srs
+
+
+@pytest.mark.parametrize("L,b", [(8, 1), (8, 16), (14, 1)])
+def test_zero_challenge_is_reported(vc, L, b):
+    """A zero Fiat-Shamir challenge (section 3, FC.BOpen: the fold needs x_j^{-1}) ends the
+    open-all with VC_ECHALLENGE.  Forced from the host in the first and the last round, in the
+    rounds taken one ahead (L = 8) and the direct ones (2^14, b = 1); the one-job and the
+    batch call both report it, and the same executor then opens the vector as before."""
+    say("zero challenge: L=%d b=%d" % (L, b))
+    pp = vc.vc_setup(L, SEED, 0)
+    N, lK = 1 << L, L // 2
+    cm = vc.vc_commit(pp, dev_entries(I.entries(N, 11)), 256)
+    ref = vc.vc_open_all(pp, cm, b)
+    want = [vc.vc_proof_get(ref, i) for i in (0, N - 1)]
+    del ref
+    ex = vc.vc_exec_create(0, 6)
+    try:
+        for rnd in (1, lK):
+            vc.vc_test_zero_challenge(rnd)
+            with pytest.raises(vc.VCError) as e:
+                vc.vc_open_all(pp, cm, b)
+            assert e.value.code == vc.VC_ECHALLENGE
+            with pytest.raises(vc.VCError) as e:
+                vc.vc_open_all_batch([(pp, cm, b), (pp, cm, b)], [ex])
+            assert e.value.code == vc.VC_ECHALLENGE
+    finally:
+        vc.vc_test_zero_challenge(0)
+    got = vc.vc_open_all_batch([(pp, cm, b)], [ex])[0]
+    assert [vc.vc_proof_get(got, i) for i in (0, N - 1)] == want
+    again = vc.vc_open_all(pp, cm, b)
+    assert [vc.vc_proof_get(again, i) for i in (0, N - 1)] == want
+
+
 def sample_indices(N, M, b, seed, extra=()):
     """edges of the first and last batch and block, plus seeded random positions"""
     rng = np.random.default_rng(seed)
