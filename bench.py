@@ -294,16 +294,19 @@ def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile="all"):
     return limbs, commit_ms, open_ms, prof, wall
 
 
-BATCH_SETUPS = ((4, 6), (8, 2), (16, 1))   # (executors, streams per executor) of the batched-jobs runs
+# (executors, streams per executor, jobs per fused group) of the batched-jobs runs: group 1 is
+# one job per executor (vc_open_all_batch), larger groups fuse the jobs of one size
+BATCH_SETUPS = ((8, 2, 1), (16, 1, 1), (16, 1, 64), (16, 2, 64), (16, 1, 4))
 
 
 def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=PEAK_MAD_TOPS):
     """Batched jobs: n_jobs independent vectors, N = 2^L with L uniform in [8, 18] (seeded),
     b = min(L^2, K), uniform full-width entries, each committed once.  Open-all of every job
     one after another on one stream, against the batch call on ne executors of ns streams
-    each (each job on its own executor, ne at a time); the best of `reps` passes each.  The
-    batch's serialized proofs at the ends of every vector are compared with the one-job
-    call's."""
+    each, either one job per executor (g = 1, vc_open_all_batch) or the jobs of one size fused
+    in groups of at most g (vc_open_all_grouped), ne groups at a time; the best of `reps`
+    passes each.  The serialized proofs at the ends of every vector are compared with the
+    one-job call's."""
     import numpy as np
     from paper_2601_03031_amd import inputs as I
     rng = np.random.default_rng(seed)
@@ -335,12 +338,12 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=
     log("batched jobs: sequential %.1f ms" % seq_ms)
     res = {"jobs": n_jobs, "L_counts": {str(L): Ls.count(L) for L in sorted(set(Ls))},
            "proofs": sum(pp.N for pp, _, _ in jobs), "sequential_ms": round(seq_ms, 2), "batch_ms": {}}
-    for ne, ns in setups:
+    for ne, ns, g in setups:
         execs = [V.vc_exec_create(0, ns) for _ in range(ne)]
         best, out = None, None
         for _ in range(reps + 1):  # the first pass sizes every executor's workspace
             t0 = time.perf_counter()
-            out = V.vc_open_all_batch(jobs, execs)
+            out = V.vc_open_all_batch(jobs, execs) if g == 1 else V.vc_open_all_grouped(jobs, execs, g)
             ms = 1e3 * (time.perf_counter() - t0)
             best = ms if best is None or ms < best else best
         for (pp, _, _), a, r in zip(jobs, out, seq_out):
@@ -348,8 +351,9 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=
                 if V.vc_proof_get(a, i) != V.vc_proof_get(r, i):
                     raise RuntimeError("batched proof %d of a 2^%d job differs from the one-job call" % (i, pp.log_n))
         del out, execs
-        res["batch_ms"]["%dx%d" % (ne, ns)] = round(best, 2)
-        log("batched jobs: %d executors x %d streams %.1f ms" % (ne, ns, best))
+        key = "%dx%d" % (ne, ns) + ("" if g == 1 else "_g%d" % g)
+        res["batch_ms"][key] = round(best, 2)
+        log("batched jobs: %d executors x %d streams, groups of %d: %.1f ms" % (ne, ns, g, best))
     k_best = min(res["batch_ms"], key=lambda k: res["batch_ms"][k])
     res["speedup"] = round(seq_ms / res["batch_ms"][k_best], 2)
     res["best_setup"] = k_best
@@ -626,8 +630,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--batch-only", type=str, default="", metavar="SETUPS",
-                    help="only run the batched-jobs comparison with these executors x streams setups "
-                         "(e.g. 4x6,16x1) and print its JSON")
+                    help="only run the batched-jobs comparison with these executors x streams[ x group] "
+                         "setups (e.g. 4x6,16x1,16x1x64) and print its JSON")
     ap.add_argument("--serve-only", action="store_true", help="only run the serving-loop comparison")
     ap.add_argument("--only", choices=("verify_all", "eval", "subarrays"), default=None,
                     help="only run this extra measurement and print its JSON (for profiling)")
@@ -684,7 +688,7 @@ def main():
         print(json.dumps(serving(V, torch, **kw)), flush=True)
         return
     if a.batch_only:
-        setups = [tuple(int(v) for v in x.split("x")) for x in a.batch_only.split(",")]
+        setups = [tuple(int(v) for v in x.split("x")) + ((1,) if x.count("x") == 1 else ()) for x in a.batch_only.split(",")]
         print(json.dumps(batched_jobs(V, torch, setups=setups)), flush=True)
         return
 

@@ -138,6 +138,20 @@ int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t b, vc_
 int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms, const uint32_t *bs,
                       uint32_t nexec, vc_exec *const *exs, vc_proofs **outs);
 
+/* Batched jobs with fused launches: as vc_open_all_batch, but jobs on the same params with
+ * the same b are opened together, in groups of at most max_group jobs (in input order).  A
+ * group is one open-all whose Step 1 (Protocol 1, Eq. genFCBatchProof) runs the batches of
+ * all its jobs in lockstep, job after job in one array, so each kernel launch takes the same
+ * step of every job's batches (round 1's G_T parts are computed once per job); Step 2 runs
+ * job after job on a side stream.  Each outs[i] holds the same bytes as vc_open_all of job
+ * i alone.  At most nexec groups run at a time (largest first), one per executor; a group
+ * takes workspace for all its batches.  A failure in any job (including a zero challenge,
+ * VC_ECHALLENGE) fails the call: every outs[i] is NULL.  max_group = 1 is
+ * vc_open_all_batch. */
+int vc_open_all_grouped(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms,
+                        const uint32_t *bs, uint32_t max_group, uint32_t nexec, vc_exec *const *exs,
+                        vc_proofs **outs);
+
 /* Device bytes one vc_open_all of (pp, b) holds while it runs: proof bundle, workspace and
  * reduction counters (the bundle stays with the returned proofs).  Host-only: nothing is
  * allocated or launched.  VC_EINVAL for b outside [1, K]. */

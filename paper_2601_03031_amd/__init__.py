@@ -83,6 +83,8 @@ def lib():
         L.vc_verify_all.argtypes = [vp, u8p, u32, vp, vp, u64, u8p, C.POINTER(u64)]
         L.vc_open_all_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), u32, C.POINTER(vp),
                                         C.POINTER(vp)]
+        L.vc_open_all_grouped.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), u32, u32,
+                                          C.POINTER(vp), C.POINTER(vp)]
         L.vc_proof_len.restype = u64
         L.vc_proof_len.argtypes = [u32, u32]
         L.vc_proof_get.argtypes = [vp, u64, vp, sz, C.POINTER(sz)]
@@ -265,6 +267,20 @@ def vc_open_all_batch(jobs, execs) -> list:
     exs = (VP * max(len(execs), 1))(*[ex.ptr for ex in execs])
     outs = (VP * max(n, 1))()
     _check(lib().vc_open_all_batch(n, pps, cms, bs, len(execs), exs, outs), "vc_open_all_batch")
+    return [Proofs(outs[i], jobs[i][0], jobs[i][2]) for i in range(n)]
+
+
+def vc_open_all_grouped(jobs, execs, max_group: int) -> list:
+    """As vc_open_all_batch, with the jobs on the same Params and b opened together in fused
+    groups of at most max_group jobs."""
+    n = len(jobs)
+    VP = C.c_void_p
+    pps = (VP * max(n, 1))(*[pp.ptr for pp, _, _ in jobs])
+    cms = (VP * max(n, 1))(*[cm.ptr for _, cm, _ in jobs])
+    bs = (C.c_uint32 * max(n, 1))(*[b for _, _, b in jobs])
+    exs = (VP * max(len(execs), 1))(*[ex.ptr for ex in execs])
+    outs = (VP * max(n, 1))()
+    _check(lib().vc_open_all_grouped(n, pps, cms, bs, max_group, len(execs), exs, outs), "vc_open_all_grouped")
     return [Proofs(outs[i], jobs[i][0], jobs[i][2]) for i in range(n)]
 
 

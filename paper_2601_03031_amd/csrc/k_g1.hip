@@ -188,22 +188,27 @@ __global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, 
 }
 
 // ================================================================ open-all, step 1
-// Round 1's G_T parts are the same for every batch (A = aux and V = v in all of them): copy
-// batch 0's L_1, R_1 (slot 0 of every batch's row of lK) to the other batches
-__global__ void __launch_bounds__(TPB) k_bcast_round1(fp12 *L, fp12 *R, uint64_t nb, uint32_t lK) {
+// Round 1's G_T parts are the same for every batch of a job (A = aux and V = v in all of
+// them): copy job x's L_1, R_1 (LT[x], RT[x]) to slot 0 of the row of every batch of job x
+// (batches job-major, nbj per job)
+__global__ void __launch_bounds__(TPB) k_bcast_round1(const fp12 *LT, const fp12 *RT, uint64_t nb, uint64_t nbj,
+                                                      uint32_t lK, fp12 *L, fp12 *R) {
   const uint64_t words = sizeof(fp12) / 4;
   uint64_t id = gtid();
-  if (id >= 2 * (nb - 1) * words) return;
-  uint64_t w = id % words, r = id / words, side = r & 1, k = 1 + (r >> 1);
-  uint32_t *base = reinterpret_cast<uint32_t *>(side ? R : L);
-  base[k * lK * words + w] = base[w];
+  if (id >= 2 * nb * words) return;
+  uint64_t w = id % words, r = id / words, side = r & 1, k = r >> 1;
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(side ? RT : LT) + (k / nbj) * words;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(side ? R : L) + k * lK * words;
+  dst[w] = src[w];
 }
 
-__global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B) {
+// Batches are job-major: batch x nbj + k is batch k of job x, whose aux row is Cj + x K
+__global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, uint64_t nbj,
+                                                 g1_aff *A, g2_aff *V, fe *B) {
   uint64_t id = gtid();
   if (id >= nb * K) return;
   uint64_t i = id % K;
-  A[id] = Cj[i];
+  A[id] = Cj[(id / (nbj * K)) * K + i];
   V[id] = h[2 * i];
   B[id] = fe_zero();
 }
@@ -216,10 +221,14 @@ __global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff 
 // consecutive columns, so every row access is coalesced; the entries are read once and
 // every node is written once.
 template <int S>
-__global__ void __launch_bounds__(TPB) k_ytree(const fe *m, const fe *rho, fe *Y, uint64_t M, uint64_t K, uint32_t h0) {
+__global__ void __launch_bounds__(TPB) k_ytree(const S2Job *J, uint32_t G, uint64_t M, uint64_t K, uint32_t h0) {
   const uint64_t groups = (K >> h0) >> S;
   uint64_t id = gtid();
-  if (id >= groups * M) return;
+  if (id >= G * groups * M) return;
+  const S2Job &jb = J[id / (groups * M)];  // each job's threads in turn
+  const fe *m = jb.m, *rho = jb.rho;
+  fe *Y = jb.Y;
+  id %= groups * M;
   const uint64_t g = id / M, a = id % M;
   fe v[1 << S];
   const uint64_t in = 2 * K - ((2 * K) >> h0);  // first row of level h0
@@ -324,32 +333,34 @@ void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint6
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st) {
   L1(k_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);
 }
-void bcast_round1(fp12 *L, fp12 *R, uint64_t nb, uint32_t lK, hipStream_t st) {
-  if (nb > 1) L1(k_bcast_round1, 2 * (nb - 1) * (sizeof(fp12) / 4), L, R, nb, lK);
+void bcast_round1(const fp12 *LT, const fp12 *RT, uint64_t nb, uint64_t nbj, uint32_t lK, fp12 *L, fp12 *R,
+                  hipStream_t st) {
+  L1(k_bcast_round1, 2 * nb * (sizeof(fp12) / 4), LT, RT, nb, nbj, lK, L, R);
 }
-void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st) {
-  L1(k_oa_init, nb * K, Cj, h, K, nb, A, V, B);
+void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, uint64_t nbj, g1_aff *A, g2_aff *V, fe *B,
+             hipStream_t st) {
+  L1(k_oa_init, nb * K, Cj, h, K, nb, nbj, A, V, B);
 }
 void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st) {
   L1(k_glv_dec, nb, X, nb, j, lK, out);
 }
-void ytree(const fe *m, const fe *r, fe *Y, uint64_t M, uint64_t K, uint32_t lK, hipStream_t st) {
+void ytree(const S2Job *J, uint32_t G, uint64_t M, uint64_t K, uint32_t lK, hipStream_t st) {
   // passes of four levels (the last pass takes what remains); level 0 is made in the first,
-  // which takes two levels below N = 2^24 so that its N / 4 threads still fill the device
+  // which takes two levels below G N = 2^24 so that its G N / 4 threads still fill the device
   uint32_t h0 = 0;
   if (lK == 0) {
-    L1(k_ytree<0>, M, m, r, Y, M, K, 0u);
+    L1(k_ytree<0>, G * M, J, G, M, K, 0u);
     return;
   }
   while (h0 < lK) {
-    const uint32_t want = (h0 == 0 && K * M < (1ull << 24)) ? 2 : 4;
+    const uint32_t want = (h0 == 0 && G * K * M < (1ull << 24)) ? 2 : 4;
     const uint32_t s = lK - h0 >= want ? want : lK - h0;
-    const uint64_t n = ((K >> h0) >> s) * M;
+    const uint64_t n = G * ((K >> h0) >> s) * M;
     switch (s) {
-      case 4: L1(k_ytree<4>, n, m, r, Y, M, K, h0); break;
-      case 3: L1(k_ytree<3>, n, m, r, Y, M, K, h0); break;
-      case 2: L1(k_ytree<2>, n, m, r, Y, M, K, h0); break;
-      default: L1(k_ytree<1>, n, m, r, Y, M, K, h0); break;
+      case 4: L1(k_ytree<4>, n, J, G, M, K, h0); break;
+      case 3: L1(k_ytree<3>, n, J, G, M, K, h0); break;
+      case 2: L1(k_ytree<2>, n, J, G, M, K, h0); break;
+      default: L1(k_ytree<1>, n, J, G, M, K, h0); break;
     }
     h0 += s;
   }

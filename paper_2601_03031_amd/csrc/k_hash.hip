@@ -25,13 +25,16 @@ __global__ void __launch_bounds__(TPB) k_trapdoor(const uint8_t *seed, uint32_t 
 
 // chunk digests of the batch statement: H_q over (a_i || enc(C_{a_i})) for 32 entries; a
 // workgroup of 64 per chunk, one lane per entry writes the message words (sha::Coop)
-__global__ void __launch_bounds__(64) k_fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq) {
+__global__ void __launch_bounds__(64) k_fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj,
+                                                 uint32_t *Hq) {
   CHAIN_PRIORITY();
   __shared__ uint32_t msg[FC_CHUNK * 18 + 18];
   uint64_t id = blockIdx.x;
   uint64_t qmax = (b + FC_CHUNK - 1) / FC_CHUNK;
   if (id >= nb * qmax) return;
-  uint64_t k = id / qmax, q = id % qmax;
+  // batch k of job x (batches job-major, nbj per job), whose aux row is Cj + x K
+  uint64_t kk = id / qmax, q = id % qmax, k = kk % nbj;
+  Cj += (kk / nbj) * K;
   uint64_t lo = k * b, hi = (lo + b < K) ? lo + b : K;
   uint64_t s = lo + q * FC_CHUNK;
   if (s >= hi) return;
@@ -56,12 +59,14 @@ __global__ void __launch_bounds__(64) k_fc_chunks(const g1_aff *Cj, uint64_t K, 
 __host__ __device__ inline size_t fc_sigma_shm(uint32_t b) {
   return ((410 + 32 * (size_t)((b + FC_CHUNK - 1) / FC_CHUNK) + 72 + 3) / 4) * 4;
 }
-__global__ void __launch_bounds__(64) k_fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq,
-                                                uint32_t *sigma) {
+__global__ void __launch_bounds__(64) k_fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj,
+                                                const uint32_t *Hq, uint32_t *sigma) {
   CHAIN_PRIORITY();
   extern __shared__ uint32_t mw[];
-  uint64_t k = blockIdx.x;
-  if (k >= nb) return;
+  const uint64_t kk = blockIdx.x;
+  if (kk >= nb) return;
+  const uint64_t k = kk % nbj;  // batch k of job kk / nbj, whose commitment is C[kk / nbj]
+  C += kk / nbj;
   const int t = threadIdx.x;
   uint64_t qmax = (b + FC_CHUNK - 1) / FC_CHUNK;
   uint64_t lo = k * b, hi = (lo + b < K) ? lo + b : K;
@@ -73,33 +78,34 @@ __global__ void __launch_bounds__(64) k_fc_sigma(const fp12 *C, uint64_t K, uint
   if (t >= 12 && t < 20) sha::put_byte(mw, dl + 384 + (t - 12), (uint32_t)(cnt >> (8 * (19 - t))) & 0xff);
   const uint32_t off = dl + 392;
   for (uint64_t w = t; w < 8 * nq; w += 64) {
-    uint32_t v = Hq[k * qmax * 8 + w];
+    uint32_t v = Hq[kk * qmax * 8 + w];
     for (int i = 0; i < 4; i++) sha::put_byte(mw, off + 4 * (uint32_t)w + i, v >> (24 - 8 * i));
   }
   __syncthreads();
   uint32_t out[8];
   sha::sha_coop(sha::Coop{t, 64}, mw, off + 32 * (uint32_t)nq, out);
   if (t == 0)
-    for (int w = 0; w < 8; w++) sigma[k * 8 + w] = out[w];
+    for (int w = 0; w < 8; w++) sigma[kk * 8 + w] = out[w];
 }
 
 // r_i = H2F(DST_FC_R, sigma_k || i), a workgroup of 64 per entry: the sparse exponent
 // vector b = sum r_i u_{a_i}
-__global__ void __launch_bounds__(64) k_fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B) {
+__global__ void __launch_bounds__(64) k_fc_r(uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj, const uint32_t *sigma,
+                                            fe *B) {
   CHAIN_PRIORITY();
   __shared__ uint32_t w[16 + 10 + 32], t2[16];
   uint64_t id = blockIdx.x;
   if (id >= nb * (uint64_t)b) return;
-  uint64_t k = id / b, i = id % b;
-  uint64_t a = k * b + i;
+  uint64_t kk = id / b, i = id % b;
+  uint64_t a = (kk % nbj) * b + i;  // entry i of batch kk % nbj of its job
   if (a >= K) return;
   const int t = threadIdx.x;
   if (t < 16) w[t] = 0;
-  else if (t < 24) w[t] = sigma[k * 8 + t - 16];
+  else if (t < 24) w[t] = sigma[kk * 8 + t - 16];
   else if (t < 26) w[t] = t == 24 ? (uint32_t)(i >> 32) : (uint32_t)i;
   __syncthreads();
   fe r = sha::xmd_fr_coop(sha::Coop{t, 64}, w, 40, DSTR_FC_R, t2);
-  if (t == 0) B[k * K + a] = r;
+  if (t == 0) B[kk * K + a] = r;
 }
 
 // affine G1 parts of L_j, R_j from the reduced term sums, one thread per (batch, side)
@@ -277,9 +283,14 @@ __global__ void __launch_bounds__(KZG_T) k_kzg_quotient_g(const fe *Xinv, const 
 // ================================================================ open-all, step 2
 // Merkle leaves SHA-256(0x00 || m_i || C_j), stored as 8 big-endian words per node;
 // node n of the heap (root = 1, leaf i = N + i) at tree[8n]
-__global__ void __launch_bounds__(TPB) k_merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree) {
-  uint64_t i = gtid();
-  if (i >= N) return;
+__global__ void __launch_bounds__(TPB) k_merkle_leaves(const S2Job *J, uint32_t G, uint64_t M, uint64_t N) {
+  uint64_t id = gtid();
+  if (id >= G * N) return;
+  const S2Job &jb = J[id / N];
+  const uint64_t i = id % N;
+  const fe *m = jb.m;
+  const g1_aff *Cj = jb.Cj;
+  uint32_t *tree = jb.tree;
   uint32_t mw[8], cw[16];
   const fe &mi = m[i];
 #pragma unroll
@@ -295,9 +306,11 @@ __global__ void __launch_bounds__(TPB) k_merkle_leaves(const fe *m, const g1_aff
 }
 
 // nodes [start, 2 start): node n = SHA-256(0x01 || node 2n || node 2n+1)
-__global__ void __launch_bounds__(TPB) k_merkle_level(uint32_t *tree, uint64_t start) {
-  uint64_t n = start + gtid();
-  if (n >= 2 * start) return;
+__global__ void __launch_bounds__(TPB) k_merkle_level(const S2Job *J, uint32_t G, uint64_t start) {
+  uint64_t id = gtid();
+  if (id >= G * start) return;
+  uint32_t *tree = J[id / start].tree;
+  uint64_t n = start + id % start;
   uint32_t l[8], r[8], o[8];
 #pragma unroll
   for (int q = 0; q < 8; q++) { l[q] = tree[16 * n + q]; r[q] = tree[16 * n + 8 + q]; }
@@ -307,27 +320,30 @@ __global__ void __launch_bounds__(TPB) k_merkle_level(uint32_t *tree, uint64_t s
 }
 
 // rho_j = H2F(DST_RHO, C || root || j)
-__global__ void __launch_bounds__(TPB) k_rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *rho) {
-  uint64_t j = gtid();
-  if (j >= K) return;
+__global__ void __launch_bounds__(TPB) k_rho(const S2Job *J, uint32_t G, uint64_t K) {
+  uint64_t id = gtid();
+  if (id >= G * K) return;
+  const S2Job &jb = J[id / K];
+  const uint64_t j = id % K;
   sha::Hasher hs;
   sha::xmd_begin(hs);
-  hs.gt(*C);
-  for (int q = 0; q < 8; q++) hs.word(tree[8 + q]);
+  hs.gt(*jb.C);
+  for (int q = 0; q < 8; q++) hs.word(jb.tree[8 + q]);
   hs.u64(j);
-  rho[j] = sha::xmd_finish_fr(hs, DSTR_RHO);
+  jb.rho[j] = sha::xmd_finish_fr(hs, DSTR_RHO);
 }
 
 namespace kl {
 void trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta, hipStream_t st) { L1(k_trapdoor, lM + 1, seed, lM, s, beta); }
-void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st) {
-  LAUNCH(k_fc_chunks, dim3((unsigned)(nb * ((b + FC_CHUNK - 1) / FC_CHUNK))), dim3(64), 0, Cj, K, b, nb, Hq);
+void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj, uint32_t *Hq, hipStream_t st) {
+  LAUNCH(k_fc_chunks, dim3((unsigned)(nb * ((b + FC_CHUNK - 1) / FC_CHUNK))), dim3(64), 0, Cj, K, b, nb, nbj, Hq);
 }
-void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st) {
-  LAUNCH(k_fc_sigma, dim3((unsigned)nb), dim3(64), fc_sigma_shm(b), C, K, b, nb, Hq, sigma);
+void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj, const uint32_t *Hq, uint32_t *sigma,
+              hipStream_t st) {
+  LAUNCH(k_fc_sigma, dim3((unsigned)nb), dim3(64), fc_sigma_shm(b), C, K, b, nb, nbj, Hq, sigma);
 }
-void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st) {
-  LAUNCH(k_fc_r, dim3((unsigned)(nb * b)), dim3(64), 0, K, b, nb, sigma, B);
+void fc_r(uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj, const uint32_t *sigma, fe *B, hipStream_t st) {
+  LAUNCH(k_fc_r, dim3((unsigned)(nb * b)), dim3(64), 0, K, b, nb, nbj, sigma, B);
 }
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st) {
   L1(k_oa_lr_aff, 2 * nb, S, K, nb, j, lK, Lg1, Rg1);
@@ -351,11 +367,11 @@ void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint
   (void)attr_set;
   LAUNCH(k_kzg_quotient, dim3((unsigned)nb), dim3(KZG_T), shm, Xinv, X, V, K, lK, Q, z);
 }
-void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st) {
-  L1(k_merkle_leaves, N, m, Cj, M, N, tree);
+void merkle_leaves(const S2Job *J, uint32_t G, uint64_t M, uint64_t N, hipStream_t st) {
+  L1(k_merkle_leaves, G * N, J, G, M, N);
 }
-void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st) { L1(k_merkle_level, start, tree, start); }
-void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st) { L1(k_rho, K, C, tree, K, r); }
+void merkle_level(const S2Job *J, uint32_t G, uint64_t start, hipStream_t st) { L1(k_merkle_level, G * start, J, G, start); }
+void rho(const S2Job *J, uint32_t G, uint64_t K, hipStream_t st) { L1(k_rho, G * K, J, G, K); }
 }  // namespace kl
 
 // ------------------------------------------------------------------ evaluation proof at a point

@@ -134,24 +134,51 @@ __global__ void __launch_bounds__(TPBW) kw_oa_fold_g2(const void *Vin, void *Vou
   wst(Vout, k * K + i, jac_to_aff(jac_madd(t, wld<g2_aff>(Vin, k * K + i))));
 }
 
-// HyperEval terms (canonical differences of the folded table times PST keys)
-__global__ void __launch_bounds__(TPBW) kw_hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S) {
+// HyperEval terms (canonical differences of the folded table g* times PST keys) of every job:
+// term r of level d of job x goes to S[(d G + x) M / 2 + r]
+__global__ void __launch_bounds__(TPBW) kw_hyper_terms(const S2Job *J, uint32_t G, uint64_t K, const void *ek, uint64_t M,
+                                                      uint32_t lM, void *S) {
   uint64_t id = wgid();
   uint64_t per = M / 2;
-  if (id >= lM * per) return;
+  if (id >= G * lM * per) return;
+  const uint64_t x = id / (lM * per);
+  // g*, the root row of the y-tree, as an element offset (fe here is one limb per lane)
+  const void *g = J[x].Y;
+  const uint64_t g0 = (2 * K - 2) * M;
+  id %= lM * per;
   uint32_t d = (uint32_t)(id / per);
   uint64_t r = id % per;
   uint32_t k = lM - d;
   uint64_t half = 1ull << (k - 1);
   uint64_t p = r / half, c = r % half;
-  fe q = fr_sub(wld<fe>(g, p * (2 * half) + half + c), wld<fe>(g, p * (2 * half) + c));
+  fe q = fr_sub(wld<fe>(g, g0 + p * (2 * half) + half + c), wld<fe>(g, g0 + p * (2 * half) + c));
   g1_jac out = jac_inf<OpsG1>();
   if (!fe_is_zero(q)) {
     uint32_t kk[8];
     wunpack(kk, q);
     out = mul_any(wld<g1_aff>(ek, (1ull << (k - 1)) - 1 + c), kk);
   }
-  wst(S, id, out);
+  wst(S, (d * G + x) * per + r, out);
+}
+
+// W of every job at level d: segment s = x 2^d + p (reduced at in + s stride) is W_x[2^d - 1 + p]
+__global__ void __launch_bounds__(TPBW) kw_w_aff(const S2Job *J, uint32_t G, const void *in, uint64_t stride, uint32_t d) {
+  uint64_t s = wgid();
+  if (s >= ((uint64_t)G << d)) return;
+  const uint64_t x = s >> d, p = s & ((1ull << d) - 1);
+  g1_aff a = jac_to_aff(wld<g1_jac>(in, s * stride));
+  wst(J[x].W, (1ull << d) - 1 + p, a);
+}
+
+// the D-tree's leaves D_j = rho_j C_j of every job
+__global__ void __launch_bounds__(TPBW) kw_d_leaves(const S2Job *J, uint32_t G, uint64_t K) {
+  uint64_t id = wgid();
+  if (id >= G * K) return;
+  const S2Job &jb = J[id / K];
+  const uint64_t j = id % K;
+  uint32_t kk[8];
+  wscalar(kk, wld<fe>(jb.rho, j));
+  wst(jb.D, j, jac_to_aff(mul_any(wld<g1_aff>(jb.Cj, j), kk)));
 }
 
 // ---------------------------------------------------------------- sums
@@ -184,9 +211,11 @@ __global__ void __launch_bounds__(TPBW) kw_sum_g1(const void *data, uint64_t nse
   wst(out, s, jac_to_aff(acc));
 }
 
-__global__ void __launch_bounds__(TPBW) kw_dlevel(void *D, uint64_t K, uint32_t h) {
+__global__ void __launch_bounds__(TPBW) kw_dlevel(const S2Job *J, uint32_t G, uint64_t K, uint32_t h) {
   uint64_t w = wgid();
-  if (w >= (K >> h)) return;
+  if (w >= G * (K >> h)) return;
+  g1_aff *D = J[w / (K >> h)].D;
+  w %= K >> h;
   uint64_t off = 2 * K - ((2 * K) >> h), offc = 2 * K - ((2 * K) >> (h - 1));
   g1_aff l = wld<g1_aff>(D, offc + 2 * w), r = wld<g1_aff>(D, offc + 2 * w + 1);
   wst(D, off + w, jac_to_aff(jac_madd(jac_from_aff(l), r)));
@@ -265,8 +294,14 @@ void oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K, uint6
                 uint32_t lK, hipStream_t st) {
   LW(kw_oa_fold_g2, nb * h, Vin, Vout, Xinv, K, nb, h, j, lK);
 }
-void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st) {
-  LW(kw_hyper_terms, lM * (M / 2), g, ek, M, lM, S);
+void hyper_terms(const S2Job *J, uint32_t G, uint64_t K, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st) {
+  LW(kw_hyper_terms, G * lM * (M / 2), J, G, K, ek, M, lM, S);
+}
+void w_aff(const S2Job *J, uint32_t G, const void *in, uint64_t stride, uint32_t d, hipStream_t st) {
+  LW(kw_w_aff, (uint64_t)G << d, J, G, in, stride, d);
+}
+void d_leaves(const S2Job *J, uint32_t G, uint64_t K, hipStream_t st) {
+  LW(kw_d_leaves, G * K, J, G, K);
 }
 void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st) {
   for (uint64_t s = 1; s < len; s <<= 1) {
@@ -278,7 +313,9 @@ void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t 
   LW(kw_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);
 }
 void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st) { LW(kw_sum_g1, nseg, data, nseg, len, out); }
-void dlevel(void *D, uint64_t K, uint32_t h, hipStream_t st) { LW(kw_dlevel, K >> h, D, K, h); }
+void dlevel(const S2Job *J, uint32_t G, uint64_t K, uint32_t h, hipStream_t st) {
+  LW(kw_dlevel, G * (K >> h), J, G, K, h);
+}
 void diag_field(int which, int op, const void *a, const void *b, uint64_t n, void *out, hipStream_t st) {
   LW(kw_diag_field, n, which, op, a, b, n, out);
 }

@@ -14,6 +14,20 @@ __host__ __device__ inline uint64_t tree_counters(uint64_t len) { return len + 6
 #define VC_ERRBIT_RANGE 1
 #define VC_ERRBIT_CHALLENGE 2
 
+// Step 2 (Protocol 1 Step 2) of one job of a group: its entries, aux row and commitment, and
+// the arrays of its proof bundle that Step 2 writes.  The Step 2 kernels take a table of G of
+// these and a thread range per job (job x's threads follow job x - 1's), so one launch does the
+// same step for every job of the group.  (In the wide-layout kernels fe is one limb per lane,
+// so they reach these arrays through element offsets of wld/wst, never pointer arithmetic.)
+struct S2Job {
+  const fe *m;       // N entries (as kept by the commitment)
+  const g1_aff *Cj;  // K subvector commitments
+  const fp12 *C;     // the commitment
+  uint32_t *tree;    // Merkle heap, 2N digests
+  fe *rho, *Y;       // K challenges; the y-tree, (2K - 1) M canonical F_r
+  g1_aff *D, *W;     // the D-tree, 2K - 1 points; HyperEval commitments, M - 1 points
+};
+
 namespace kl {
 void trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta, hipStream_t st);
 void ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n, hipStream_t st);
@@ -42,12 +56,18 @@ void fr_canon(const fe *in, uint64_t n, fe *out, hipStream_t st);
 void g1_reduce(g1_jac *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
 void g1_to_aff(const g1_jac *in, uint64_t stride, uint64_t n, g1_aff *out, uint64_t ostride, hipStream_t st);
 void g2_to_aff(const g2_jac *in, uint64_t stride, uint64_t n, g2_aff *out, uint64_t ostride, hipStream_t st);
-void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, g1_aff *A, g2_aff *V, fe *B, hipStream_t st);
+// Step 1's batches are job-major: batch x nbj + k is batch k of job x (nbj = ceil(K / b)
+// batches per job; one job: nbj = nb).  Job x's aux row is Cj + x K, its commitment C[x].
+void oa_init(const g1_aff *Cj, const g2_aff *h, uint64_t K, uint64_t nb, uint64_t nbj, g1_aff *A, g2_aff *V, fe *B,
+             hipStream_t st);
 // L[k lK] = L[0], R[k lK] = R[0] for batches k = 1 .. nb - 1 (round 1's G_T parts)
-void bcast_round1(fp12 *L, fp12 *R, uint64_t nb, uint32_t lK, hipStream_t st);
-void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint32_t *Hq, hipStream_t st);
-void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, const uint32_t *Hq, uint32_t *sigma, hipStream_t st);
-void fc_r(uint64_t K, uint32_t b, uint64_t nb, const uint32_t *sigma, fe *B, hipStream_t st);
+// L[k lK] = LT[k / nbj], R[k lK] = RT[k / nbj] for every batch k (round 1's G_T parts of each job)
+void bcast_round1(const fp12 *LT, const fp12 *RT, uint64_t nb, uint64_t nbj, uint32_t lK, fp12 *L, fp12 *R,
+                  hipStream_t st);
+void fc_chunks(const g1_aff *Cj, uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj, uint32_t *Hq, hipStream_t st);
+void fc_sigma(const fp12 *C, uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj, const uint32_t *Hq, uint32_t *sigma,
+              hipStream_t st);
+void fc_r(uint64_t K, uint32_t b, uint64_t nb, uint64_t nbj, const uint32_t *sigma, fe *B, hipStream_t st);
 void oa_lr_aff(const g1_jac *S, uint64_t K, uint64_t nb, uint32_t j, uint32_t lK, g1_aff *Lg1, g1_aff *Rg1, hipStream_t st);
 // x_j = H'(x_{j-1} || L_j || R_j) per batch (zero_round == j: batch 0's challenge is forced to
 // zero, a test hook for the zero-challenge error; 0 leaves every challenge as hashed)
@@ -58,12 +78,12 @@ void oa_transcript(const fp12 *Lgt, const fp12 *Rgt, uint64_t nb, uint32_t j, ui
 // gws: 4 (2K - 1) elements per batch of global working space, used when K > 1024
 void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint64_t nb, uint32_t lK, fe *Q, fe *z,
                   fe *gws, hipStream_t st);
-void merkle_leaves(const fe *m, const g1_aff *Cj, uint64_t M, uint64_t N, uint32_t *tree, hipStream_t st);
-void merkle_level(uint32_t *tree, uint64_t start, hipStream_t st);
-void rho(const fp12 *C, const uint32_t *tree, uint64_t K, fe *r, hipStream_t st);
+void merkle_leaves(const S2Job *J, uint32_t G, uint64_t M, uint64_t N, hipStream_t st);
+void merkle_level(const S2Job *J, uint32_t G, uint64_t start, hipStream_t st);
+void rho(const S2Job *J, uint32_t G, uint64_t K, hipStream_t st);
 void glv_dec(const fe *X, uint64_t nb, uint32_t j, uint32_t lK, glv::Dec *out, hipStream_t st);
 // the whole y-tree (level 0 from the entries, levels 1 .. lK) in passes of up to four levels
-void ytree(const fe *m, const fe *r, fe *Y, uint64_t M, uint64_t K, uint32_t lK, hipStream_t st);
+void ytree(const S2Job *J, uint32_t G, uint64_t M, uint64_t K, uint32_t lK, hipStream_t st);
 void encode(const fe *in, uint64_t n, int mode, uint8_t *out, hipStream_t st);
 void gather_encode(const fe *base, const uint64_t *idx, const int *mode, uint64_t n, uint8_t *out, hipStream_t st);
 // evaluation proof at a point (k_hash.hip)
@@ -87,11 +107,17 @@ void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const 
 void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st);
 void oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
                 uint32_t lK, hipStream_t st);
-void hyper_terms(const void *g, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st);
+// HyperEval terms of every job's g* (the root row of its y-tree): level d of job x at
+// S + (d G + x) M / 2, so the M / 2 terms of a level of all jobs are contiguous
+void hyper_terms(const S2Job *J, uint32_t G, uint64_t K, const void *ek, uint64_t M, uint32_t lM, void *S, hipStream_t st);
+// W of every job at level d from the reduced segment sums (segment x 2^d + p at in + (x 2^d + p) stride)
+void w_aff(const S2Job *J, uint32_t G, const void *in, uint64_t stride, uint32_t d, hipStream_t st);
+// D_j = rho_j C_j, the D-tree's leaves of every job
+void d_leaves(const S2Job *J, uint32_t G, uint64_t K, hipStream_t st);
 void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st);
 void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st);
-void dlevel(void *D, uint64_t K, uint32_t h, hipStream_t st);
+void dlevel(const S2Job *J, uint32_t G, uint64_t K, uint32_t h, hipStream_t st);
 void diag_field(int which, int op, const void *a, const void *b, uint64_t n, void *out, hipStream_t st);
 }  // namespace klw
 

@@ -636,18 +636,31 @@ VC_API int vc_commit_noalloc(const vc_params *pp, const void *m_dev, uint64_t n,
 // With eval_r (host, log N little-endian 32-byte values r_0 .. r_{L-1}) the one batch b = K
 // proves C_F = <C, T(r_L)> and the PST part opens F at r_R in place of Step 2 (section 4.3,
 // evaluation proof at a point).
-static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t b, vc_exec *ex, hipStream_t st,
-                         vc_proofs **out, uint64_t *footprint = nullptr, bool step2 = true,
-                         const uint8_t *eval_r = nullptr, uint64_t *parts = nullptr) {
-  if (!cpp || b < 1 || b > cpp->K) return VC_EINVAL;
-  if (!footprint && (!cm || !out || !ex || cm->pp != cpp || ex->device != cpp->device)) return VC_EINVAL;
+// Open-all of G jobs on the same params with the same b (G = 1: one job).  Their batches run
+// as one Step 1 of G nbj batches, job-major (batch x nbj + k is batch k of job x), so every
+// launch takes the same step of all the jobs' batches; Step 2 runs job after job on its side
+// stream.  With G > 1 the Step 1 outputs are made in the workspace and copied to each job's
+// bundle at the end; a zero challenge in any job fails the call for all of them.
+static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms, uint32_t G, uint32_t b, vc_exec *ex,
+                          hipStream_t st, vc_proofs **outs, uint64_t *footprint = nullptr, bool step2 = true,
+                          const uint8_t *eval_r = nullptr, uint64_t *parts = nullptr) {
+  if (!cpp || b < 1 || b > cpp->K || G < 1) return VC_EINVAL;
+  if (!footprint) {
+    if (!cms || !outs || !ex || ex->device != cpp->device) return VC_EINVAL;
+    for (uint32_t x = 0; x < G; x++)
+      if (!cms[x] || cms[x]->pp != cpp) return VC_EINVAL;
+  }
+  if ((eval_r || !step2) && G != 1) return VC_EINVAL;  // sub-arrays and evaluation proofs: one job
   if (eval_r && (b != cpp->K || step2)) return VC_EINVAL;  // an evaluation proof is one batch, no Step 2
   const vc_params *pp = cpp;
-  if (out) *out = nullptr;
+  if (outs)
+    for (uint32_t x = 0; x < G; x++) outs[x] = nullptr;
   if (!footprint) CK(hipSetDevice(pp->device));
   const uint64_t N = pp->N, K = pp->K, M = pp->M;
   const uint32_t lK = pp->lK, lM = pp->lM;
-  const uint64_t nb = (K + b - 1) / b;
+  const uint64_t nbj = (K + b - 1) / b;  // batches per job
+  const uint64_t nb = G * nbj;           // batches of the whole Step 1
+  const bool grp = G > 1;
   const uint64_t qmax = (b + 31) / 32;
   const uint64_t nq = 2 * K - 2;  // KZG quotient length
   // ---- the proof bundle
@@ -655,21 +668,21 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   pr->pp = pp;
   pr->device = pp->device;
   pr->b = b;
-  pr->nb = nb;
+  pr->nb = nbj;
   pr->step2 = step2;
   const uint64_t with2 = step2 ? 1 : 0;  // Step 2 arrays are left out of a sub-array bundle
   const uint64_t ev = eval_r ? 1 : 0;
   Carve c;
   pr->o_Cj = c.take<g1_aff>(K);
   pr->o_C = c.take<fp12>(1);
-  pr->o_Lgt = c.take<fp12>(nb * lK);
-  pr->o_Rgt = c.take<fp12>(nb * lK);
-  pr->o_Lg1 = c.take<g1_aff>(nb * lK);
-  pr->o_Rg1 = c.take<g1_aff>(nb * lK);
-  pr->o_X = c.take<fe>(nb * lK);
-  pr->o_Al = c.take<g1_aff>(nb);
-  pr->o_vl = c.take<g2_aff>(nb);
-  pr->o_piv = c.take<g2_aff>(nb);
+  pr->o_Lgt = c.take<fp12>(nbj * lK);
+  pr->o_Rgt = c.take<fp12>(nbj * lK);
+  pr->o_Lg1 = c.take<g1_aff>(nbj * lK);
+  pr->o_Rg1 = c.take<g1_aff>(nbj * lK);
+  pr->o_X = c.take<fe>(nbj * lK);
+  pr->o_Al = c.take<g1_aff>(nbj);
+  pr->o_vl = c.take<g2_aff>(nbj);
+  pr->o_piv = c.take<g2_aff>(nbj);
   pr->o_tree = c.take<fe>(with2 * 2 * N);
   pr->o_rho = c.take<fe>(with2 * K);
   pr->o_Y = c.take<fe>(with2 * (2 * K - 1) * M);
@@ -687,9 +700,17 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   // quotient coefficients and the per-block partial sums of its MSM
   const bool kzg_split = 4 * nb * nq <= KZG_SPLIT_MAX;
   const uint64_t kzg_nslice = (nq + KZG_S - 1) / KZG_S, kzg_len = kzg_split ? 4 * nq : kzg_nslice;
-  size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(with2 * lM * (M / 2));
+  size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(with2 * G * lM * (M / 2));
+  size_t o_J = t.take<S2Job>(with2 * G);  // Step 2's job table
   size_t o_dec = t.take<glv::Dec>(nb);
   size_t o_KQ = t.take<fe>(K > 1024 ? nb * 4 * (2 * K - 1) : 0);  // the KZG quotient's scans beyond shared memory
+  // round 1's G_T parts of each job; with several jobs, their aux rows and commitments side
+  // by side and the Step 1 outputs of all batches (copied to the bundles at the end)
+  size_t o_LT = t.take<fp12>(G), o_RT = t.take<fp12>(G);
+  size_t o_CjG = t.take<g1_aff>(grp ? G * K : 0), o_CG = t.take<fp12>(grp ? G : 0);
+  size_t o_gLgt = t.take<fp12>(grp ? nb * lK : 0), o_gRgt = t.take<fp12>(grp ? nb * lK : 0);
+  size_t o_gLg1 = t.take<g1_aff>(grp ? nb * lK : 0), o_gRg1 = t.take<g1_aff>(grp ? nb * lK : 0);
+  size_t o_gX = t.take<fe>(grp ? nb * lK : 0), o_gpiv = t.take<g2_aff>(grp ? nb : 0);
   // evaluation proof: point, T, the terms of C_F, F's table, the PST quotients and their products
   size_t o_rle = t.take<uint8_t>(ev * 32 * pp->L), o_er = t.take<fe>(ev * pp->L), o_T = t.take<fe>(ev * K),
          o_pK = t.take<g1_aff>(ev * K), o_eg = t.take<fe>(ev * M), o_eq = t.take<fe>(ev * M), o_pW = t.take<g1_aff>(ev * M);
@@ -716,43 +737,52 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   const uint64_t c_kzg = nb * tree_counters(kzg_len);
   const uint64_t n_cnt = 2 * c_dir + 4 * (c_u + c_xy) + 6 * nsplit + c_kzg;
   if (footprint) {
-    *footprint = c.off + t.off + n_cnt * sizeof(uint32_t);
+    *footprint = G * c.off + t.off + n_cnt * sizeof(uint32_t);
     if (parts) {
-      parts[0] = c.off;  // the proof bundle
+      parts[0] = G * c.off;  // the proof bundles
       parts[1] = t.off;  // the executor's workspace
       parts[2] = n_cnt;  // arrival counters
     }
     delete pr;
     return VC_OK;
   }
-  hipError_t e = hipMalloc(&pr->mem, c.off);
-  if (e != hipSuccess) { delete pr; return hip_fail(e, "vc_open_all alloc"); }
-  // on every error return below the bundle is released (hipFree waits for the work in flight)
-  // and the executor's counters are cleared before their next use (trees may have stopped
-  // half way)
+  // one bundle per job (same layout); on every error return below they are released
+  // (hipFree waits for the work in flight) and the executor's counters are cleared before
+  // their next use (trees may have stopped half way)
   struct Release {
-    vc_proofs *p;
+    std::vector<vc_proofs *> p;
     vc_exec *ex;
+    bool keep = false;
     ~Release() {
-      if (!p) return;
-      vc_proofs_free(p);
-      ex->cnt_dirty = true;
+      if (keep) return;
+      for (vc_proofs *q : p) vc_proofs_free(q);
+      if (!p.empty()) ex->cnt_dirty = true;
     }
-  } release{pr, ex};
-  void *bm = pr->mem;
+  } release{{}, ex};
+  for (uint32_t x = 0; x < G; x++) {
+    vc_proofs *q = x == 0 ? pr : new vc_proofs(*pr);
+    q->mem = nullptr;
+    release.p.push_back(q);
+    hipError_t e = hipMalloc(&q->mem, c.off);
+    if (e != hipSuccess) return hip_fail(e, "vc_open_all alloc");
+  }
+  auto bundle = [&](uint32_t x) { return release.p[x]->mem; };
+  void *bm = bundle(0);
   g1_aff *Cj = at<g1_aff>(bm, pr->o_Cj);
   fp12 *C = at<fp12>(bm, pr->o_C);
-  fp12 *Lgt = at<fp12>(bm, pr->o_Lgt), *Rgt = at<fp12>(bm, pr->o_Rgt);
-  g1_aff *Lg1 = at<g1_aff>(bm, pr->o_Lg1), *Rg1 = at<g1_aff>(bm, pr->o_Rg1);
-  fe *X = at<fe>(bm, pr->o_X);
-  g1_aff *Al = at<g1_aff>(bm, pr->o_Al);
-  g2_aff *vl = at<g2_aff>(bm, pr->o_vl), *piv = at<g2_aff>(bm, pr->o_piv);
-  uint32_t *tree = at<uint32_t>(bm, pr->o_tree);
-  fe *rho = at<fe>(bm, pr->o_rho), *Y = at<fe>(bm, pr->o_Y);
-  g1_aff *D = at<g1_aff>(bm, pr->o_D), *W = at<g1_aff>(bm, pr->o_W);
   int rc = ensure_ws(ex, t.off);
   if (rc) return rc;
   void *ws = ex->ws;
+  // Step 1 outputs: the bundle's arrays for one job, else the workspace's
+  fp12 *Lgt = grp ? at<fp12>(ws, o_gLgt) : at<fp12>(bm, pr->o_Lgt);
+  fp12 *Rgt = grp ? at<fp12>(ws, o_gRgt) : at<fp12>(bm, pr->o_Rgt);
+  g1_aff *Lg1 = grp ? at<g1_aff>(ws, o_gLg1) : at<g1_aff>(bm, pr->o_Lg1);
+  g1_aff *Rg1 = grp ? at<g1_aff>(ws, o_gRg1) : at<g1_aff>(bm, pr->o_Rg1);
+  fe *X = grp ? at<fe>(ws, o_gX) : at<fe>(bm, pr->o_X);
+  g2_aff *piv = grp ? at<g2_aff>(ws, o_gpiv) : at<g2_aff>(bm, pr->o_piv);
+  g1_aff *CjG = grp ? at<g1_aff>(ws, o_CjG) : Cj;  // every job's aux row
+  fp12 *CG = grp ? at<fp12>(ws, o_CG) : C;         // every job's commitment
+  fp12 *LT = at<fp12>(ws, o_LT), *RT = at<fp12>(ws, o_RT);
   int *err = at<int>(ws, o_err);
   g1_aff *A = at<g1_aff>(ws, o_A);
   g2_aff *V = at<g2_aff>(ws, o_V);
@@ -792,10 +822,26 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   uint32_t *cnt_fold = cnt_t + 4 * (c_u + c_xy), *cnt_kzg = cnt_fold + 2 * nsplit, *cnt_g1dir = cnt_kzg + c_kzg,
            *cnt_g1s = cnt_g1dir + c_dir;
 
-  CK(hipMemsetAsync(err, 0, sizeof(int), st));
-  CK(hipMemcpyAsync(Cj, cm->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
-  CK(hipMemcpyAsync(C, cm->C, sizeof(fp12), hipMemcpyDeviceToDevice, st));
-  if (step2) CK(hipMemsetAsync(tree, 0, 32, st));  // heap node 0 is unused
+  kl::zero_u32(reinterpret_cast<uint32_t *>(err), 1, st);
+  for (uint32_t x = 0; x < G; x++) {
+    void *bx = bundle(x);
+    CK(hipMemcpyAsync(at<g1_aff>(bx, pr->o_Cj), cms[x]->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(at<fp12>(bx, pr->o_C), cms[x]->C, sizeof(fp12), hipMemcpyDeviceToDevice, st));
+    if (grp) {
+      CK(hipMemcpyAsync(CjG + x * K, cms[x]->Cj, K * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
+      CK(hipMemcpyAsync(CG + x, cms[x]->C, sizeof(fp12), hipMemcpyDeviceToDevice, st));
+    }
+    if (step2) kl::zero_u32(at<uint32_t>(bx, pr->o_tree), 8, st);  // heap node 0 is unused
+  }
+  // Step 2's job table: each launch takes all G jobs, their inputs and bundle arrays through it
+  std::vector<S2Job> jobs(step2 ? G : 0);
+  for (uint32_t x = 0; x < jobs.size(); x++) {
+    void *bx = bundle(x);
+    jobs[x] = {cms[x]->m, at<g1_aff>(bx, pr->o_Cj), at<fp12>(bx, pr->o_C), at<uint32_t>(bx, pr->o_tree),
+               at<fe>(bx, pr->o_rho), at<fe>(bx, pr->o_Y), at<g1_aff>(bx, pr->o_D), at<g1_aff>(bx, pr->o_W)};
+  }
+  S2Job *J = at<S2Job>(ws, o_J);
+  if (step2) CK(hipMemcpyAsync(J, jobs.data(), G * sizeof(S2Job), hipMemcpyHostToDevice, st));
 
   // ---- Step 2 runs on side stream 1, concurrently with Step 1: Merkle tree (Fiat-Shamir),
   // randomized folding tree, HyperEval on g* (Protocol 1 Step 2 and its Sub-protocol).  Its
@@ -805,18 +851,19 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   auto launch_step2 = [&]() -> int {
     if (int rc2 = ev_wait(ex, 0, s1)) return rc2;
     hipStream_t st = s1;  // launches below go to side stream 1
-    kl::merkle_leaves(cm->m, Cj, M, N, tree, st);
-    for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(tree, s, st);
-    kl::rho(C, tree, K, rho, st);
-    kl::ytree(cm->m, rho, Y, M, K, lK, st);
-    klw::g1_mul(Cj, 0, rho, K, D, st);
-    for (uint32_t h = 1; h <= lK; h++) klw::dlevel(D, K, h, st);
-    klw::hyper_terms(Y + (2 * K - 2) * M, pp->ek, M, lM, HS, st);
+    kl::merkle_leaves(J, G, M, N, st);
+    for (uint64_t s = N / 2; s >= 1; s /= 2) kl::merkle_level(J, G, s, st);
+    kl::rho(J, G, K, st);
+    kl::ytree(J, G, M, K, lK, st);
+    klw::d_leaves(J, G, K, st);
+    for (uint32_t h = 1; h <= lK; h++) klw::dlevel(J, G, K, h, st);
+    klw::hyper_terms(J, G, K, pp->ek, M, lM, HS, st);
     for (uint32_t d = 0; d < lM; d++) {
+      // level d of every job: G 2^d segments of M / 2^{d+1} terms, contiguous
       uint64_t half = M >> (d + 1);
-      g1_jac *base = HS + (uint64_t)d * (M / 2);
-      klw::g1_reduce(base, 1ull << d, half, half, st);
-      klw::g1_to_aff(base, half, 1ull << d, W + (1ull << d) - 1, 1, st);
+      g1_jac *base = HS + (uint64_t)d * G * (M / 2);
+      klw::g1_reduce(base, (uint64_t)G << d, half, half, st);
+      klw::w_aff(J, G, base, half, d, st);
     }
     return VC_OK;
   };
@@ -835,7 +882,7 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   // pairing side of the terms of even and odd rounds (Miller loops, products, final
   // exponentiations), side 5 their G1 side; the caller's stream combines and hashes.
   hipStream_t sg = s2, sf = ex->side[2], sfp[2] = {ex->side[2], ex->side[3]}, sq = ex->side[4];
-  kl::oa_init(Cj, pp->h, K, nb, A, V, B, st);
+  kl::oa_init(CjG, pp->h, K, nb, nbj, A, V, B, st);
   // multiples 2^{32 m} A[i] (m = 1..3) of the whole arrays A of round j (for its split fold
   // and the split G1 terms of round j + 1) and 2^{16 m} V[h + i] of the halves V[h..) (for
   // its split fold), into set j & 1 (round 1 on side stream 1, later rounds on the fold
@@ -855,16 +902,16 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
     kl::ev_sum(at<g1_aff>(ws, o_pK), K, at<g1_aff>(bm, pr->o_CF), st);
     kl::ev_r0(C, er, pp->L, at<g1_aff>(bm, pr->o_CF), eT, K, B, st);
   } else {
-    kl::fc_chunks(Cj, K, b, nb, Hq, st);
-    kl::fc_sigma(C, K, b, nb, Hq, sigma, st);
-    kl::fc_r(K, b, nb, sigma, B, st);
+    kl::fc_chunks(CjG, K, b, nb, nbj, Hq, st);
+    kl::fc_sigma(CG, K, b, nb, nbj, Hq, sigma, st);
+    kl::fc_r(K, b, nb, nbj, sigma, B, st);
   }
   // the PST part of an evaluation proof on side stream 1, beside the FC rounds: F's table,
   // then l_M steps eliminating x_{lM-1} first, the quotients' products with ek_0 .. ek_{lM-1}
   // (contiguous at the start of ek, in the same order) and their sums
   auto launch_pst = [&]() -> int {
     if (int rc2 = stream_wait(ex, 20, st, s1)) return rc2;
-    kl::ev_table(cm->m, eT, K, M, eg, s1);
+    kl::ev_table(cms[0]->m, eT, K, M, eg, s1);
     for (uint32_t d = 0; d < lM; d++) {
       uint32_t k = lM - d;
       uint64_t half = 1ull << (k - 1);
@@ -922,11 +969,13 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
       }
       kl::oa_lr_aff(S, K, nb, j, lK, Lg1, Rg1, sg);
       if (int rc2 = ev_mark(ex, 3, sg)) return rc2;
-      // round 1 pairs the same A = aux with the same v in every batch: its G_T parts are
-      // computed once (batch 0) and copied to the other batches
-      const uint64_t nbm = j == 1 ? 1 : nb;
-      if (nbm * h >= WIDE_FOLD_MIN) klw::oa_miller(Ab[cur], Vb[cur], K, nbm, h, F, st);
-      else ks::oa_miller(Ab[cur], Vb[cur], K, nbm, h, F, st);
+      // round 1 pairs the same A = aux with the same v in every batch of a job: its G_T
+      // parts are computed once per job (from the aux rows; the first G rows of V all hold v)
+      // and copied to the job's batches
+      const uint64_t nbm = j == 1 ? G : nb;
+      const g1_aff *Am = j == 1 ? CjG : Ab[cur];
+      if (nbm * h >= WIDE_FOLD_MIN) klw::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
+      else ks::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
       // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
       if (j == 1 && split_round(1)) {
@@ -948,8 +997,12 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
         if (int rc2 = launch_g1terms(j0)) return rc2;
       }
       ks::f12_reduce(F, 2 * nbm, K / 2, h, cnt_dir, st);
-      ks::final_exp(F, K / 2, 2 * nbm, Lgt + (j - 1), Rgt + (j - 1), lK, st);
-      if (j == 1) kl::bcast_round1(Lgt, Rgt, nb, lK, st);
+      if (j == 1) {
+        ks::final_exp(F, K / 2, 2 * nbm, LT, RT, 1, st);
+        kl::bcast_round1(LT, RT, nb, nbj, lK, Lgt, Rgt, st);
+      } else {
+        ks::final_exp(F, K / 2, 2 * nbm, Lgt + (j - 1), Rgt + (j - 1), lK, st);
+      }
       if (int rc2 = ev_wait(ex, 3, st)) return rc2;
     } else {
       // L_j, R_j from the terms taken from the arrays of round j - 1 and x_{j-1}
@@ -1000,8 +1053,13 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
     if (int rc2 = stream_wait(ex, 11, sg, st)) return rc2;
   A = Ab[lK & 1];
   V = Vb[lK & 1];
-  CK(hipMemcpy2DAsync(Al, sizeof(g1_aff), A, K * sizeof(g1_aff), sizeof(g1_aff), nb, hipMemcpyDeviceToDevice, st));
-  CK(hipMemcpy2DAsync(vl, sizeof(g2_aff), V, K * sizeof(g2_aff), sizeof(g2_aff), nb, hipMemcpyDeviceToDevice, st));
+  for (uint32_t x = 0; x < G; x++) {
+    void *bx = bundle(x);
+    CK(hipMemcpy2DAsync(at<g1_aff>(bx, pr->o_Al), sizeof(g1_aff), A + x * nbj * K, K * sizeof(g1_aff), sizeof(g1_aff),
+                        nbj, hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpy2DAsync(at<g2_aff>(bx, pr->o_vl), sizeof(g2_aff), V + x * nbj * K, K * sizeof(g2_aff), sizeof(g2_aff),
+                        nbj, hipMemcpyDeviceToDevice, st));
+  }
   // faster verifier: KZG-style proof in G2 that v_l = f_v(beta) g2
   kl::kzg_quotient(Xinv, X, V, K, nb, lK, Q, z, at<fe>(ws, o_KQ), st);
   if (kzg_split) {
@@ -1012,6 +1070,17 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   }
   ks::g2_tree(S2, nb, kzg_len, kzg_len, cnt_kzg, st);
   kl::g2_to_aff(S2, kzg_len, nb, piv, 1, st);
+  // each job's rows of the Step 1 outputs into its bundle
+  for (uint32_t x = 0; grp && x < G; x++) {
+    void *bx = bundle(x);
+    const uint64_t r0 = x * nbj * lK, nr = nbj * lK;
+    CK(hipMemcpyAsync(at<fp12>(bx, pr->o_Lgt), Lgt + r0, nr * sizeof(fp12), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(at<fp12>(bx, pr->o_Rgt), Rgt + r0, nr * sizeof(fp12), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(at<g1_aff>(bx, pr->o_Lg1), Lg1 + r0, nr * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(at<g1_aff>(bx, pr->o_Rg1), Rg1 + r0, nr * sizeof(g1_aff), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(at<fe>(bx, pr->o_X), X + r0, nr * sizeof(fe), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(at<g2_aff>(bx, pr->o_piv), piv + x * nbj, nbj * sizeof(g2_aff), hipMemcpyDeviceToDevice, st));
+  }
   // join Step 2
   if (int rc2 = stream_wait(ex, 13, s1, st)) return rc2;
   CKL("vc_open_all launch");
@@ -1020,9 +1089,16 @@ static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t
   CK(hipStreamSynchronize(st));
   if (herr & VC_ERRBIT_CHALLENGE) return VC_ECHALLENGE;
   if (eval_r && (herr & VC_ERRBIT_RANGE)) return VC_EINVAL;
-  release.p = nullptr;
-  *out = pr;
+  release.keep = true;
+  for (uint32_t x = 0; x < G; x++) outs[x] = release.p[x];
   return VC_OK;
+}
+
+static int open_all_impl(const vc_params *cpp, const vc_commitment *cm, uint32_t b, vc_exec *ex, hipStream_t st,
+                         vc_proofs **out, uint64_t *footprint = nullptr, bool step2 = true,
+                         const uint8_t *eval_r = nullptr, uint64_t *parts = nullptr) {
+  if (!footprint && !cm) return VC_EINVAL;
+  return open_all_group(cpp, cm ? &cm : nullptr, 1, b, ex, st, out, footprint, step2, eval_r, parts);
 }
 
 VC_API int vc_open_all(const vc_params *pp, const vc_commitment *cm, uint32_t b, void *stream, vc_proofs **out) {
@@ -1043,40 +1119,65 @@ VC_API int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t
   return open_all_impl(pp, cm, b, ex, (hipStream_t)stream, out);
 }
 
-// Several open-all jobs, at most nexec at a time: host thread t takes the next job and runs it
-// on executor t (its own streams and workspace) and that executor's stream.
-VC_API int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms, const uint32_t *bs,
-                             uint32_t nexec, vc_exec *const *exs, vc_proofs **outs) {
+// Several open-all jobs.  Jobs on the same params with the same b form groups of at most
+// max_group jobs, each group one fused open-all (open_all_group); host thread t takes the next
+// group (largest first) and runs it on executor t (its own streams and workspace) and that
+// executor's stream, at most nexec groups at a time.
+VC_API int vc_open_all_grouped(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms,
+                               const uint32_t *bs, uint32_t max_group, uint32_t nexec, vc_exec *const *exs,
+                               vc_proofs **outs) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
-  if (!pps || !cms || !bs || !exs || !outs || nexec < 1) return VC_EINVAL;
+  if (!pps || !cms || !bs || !exs || !outs || nexec < 1 || max_group < 1) return VC_EINVAL;
   for (uint32_t i = 0; i < n; i++) outs[i] = nullptr;
   for (uint32_t t = 0; t < nexec; t++)
     if (!exs[t]) return VC_EINVAL;
   for (uint32_t i = 0; i < n; i++)
-    if (!pps[i] || !cms[i] || cms[i]->pp != pps[i] || pps[i]->device != exs[0]->device) return VC_EINVAL;
+    if (!pps[i] || !cms[i] || cms[i]->pp != pps[i] || pps[i]->device != exs[0]->device || bs[i] < 1 ||
+        bs[i] > pps[i]->K)
+      return VC_EINVAL;
   if (n == 0) return VC_OK;
   if (g_prof) nexec = 1;  // the profiling hooks keep one record list
-  if (nexec > n) nexec = n;
-  // largest jobs first, so that the last ones to start are short
-  std::vector<uint32_t> order(n);
-  for (uint32_t i = 0; i < n; i++) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return pps[a]->N > pps[b]->N; });
+  // groups: jobs in input order per (params, b), cut into pieces of at most max_group
+  std::vector<std::vector<uint32_t>> groups;
+  {
+    std::vector<std::pair<std::pair<const vc_params *, uint32_t>, uint32_t>> key(n);
+    for (uint32_t i = 0; i < n; i++) key[i] = {{pps[i], bs[i]}, i};
+    std::stable_sort(key.begin(), key.end(), [](const auto &a, const auto &b) {
+      return a.first.first != b.first.first ? a.first.first < b.first.first : a.first.second < b.first.second;
+    });
+    for (uint32_t i = 0; i < n; i++) {
+      if (i == 0 || key[i].first != key[i - 1].first || groups.back().size() >= max_group) groups.emplace_back();
+      groups.back().push_back(key[i].second);
+    }
+  }
+  // largest groups (entries) first, so that the last ones to start are short
+  std::stable_sort(groups.begin(), groups.end(), [&](const auto &a, const auto &b) {
+    return pps[a[0]]->N * a.size() > pps[b[0]]->N * b.size();
+  });
+  const uint32_t ng = (uint32_t)groups.size();
+  if (nexec > ng) nexec = ng;
   std::atomic<uint32_t> next{0};
-  std::vector<int> rcs(n, VC_OK);
-  std::vector<std::string> msgs(n);  // error text of each job (kept per thread by hip_fail)
+  std::vector<int> rcs(ng, VC_OK);
+  std::vector<std::string> msgs(ng);  // error text of each group (kept per thread by hip_fail)
   auto worker = [&](vc_exec *ex) {
     hipError_t e = hipSetDevice(ex->device);
+    std::vector<const vc_commitment *> gc;
+    std::vector<vc_proofs *> go;
     for (;;) {
       uint32_t o = next.fetch_add(1);
-      if (o >= n) break;
-      uint32_t i = order[o];
+      if (o >= ng) break;
+      const auto &g = groups[o];
       if (e != hipSuccess) {
-        rcs[i] = hip_fail(e, "vc_open_all_batch worker");
+        rcs[o] = hip_fail(e, "vc_open_all_batch worker");
       } else {
         g_last_error[0] = 0;
-        rcs[i] = open_all_impl(pps[i], cms[i], bs[i], ex, ex->main, &outs[i]);
+        gc.clear();
+        for (uint32_t i : g) gc.push_back(cms[i]);
+        go.assign(g.size(), nullptr);
+        rcs[o] = open_all_group(pps[g[0]], gc.data(), (uint32_t)g.size(), bs[g[0]], ex, ex->main, go.data());
+        for (size_t x = 0; x < g.size(); x++) outs[g[x]] = go[x];
       }
-      if (rcs[i] != VC_OK) msgs[i] = g_last_error;
+      if (rcs[o] != VC_OK) msgs[o] = g_last_error;
     }
   };
   std::vector<std::thread> th;
@@ -1084,10 +1185,10 @@ VC_API int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_c
   worker(exs[0]);
   for (auto &x : th) x.join();
   int rc = VC_OK;
-  for (uint32_t i = 0; i < n && rc == VC_OK; i++)
-    if (rcs[i] != VC_OK) {
-      rc = rcs[i];
-      snprintf(g_last_error, sizeof g_last_error, "%s", msgs[i].c_str());
+  for (uint32_t o = 0; o < ng && rc == VC_OK; o++)
+    if (rcs[o] != VC_OK) {
+      rc = rcs[o];
+      snprintf(g_last_error, sizeof g_last_error, "%s", msgs[o].c_str());
     }
   if (rc != VC_OK)
     for (uint32_t i = 0; i < n; i++) {
@@ -1095,6 +1196,11 @@ VC_API int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_c
       outs[i] = nullptr;
     }
   return rc;
+}
+
+VC_API int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms, const uint32_t *bs,
+                             uint32_t nexec, vc_exec *const *exs, vc_proofs **outs) {
+  return vc_open_all_grouped(n, pps, cms, bs, 1, nexec, exs, outs);
 }
 
 VC_API int vc_open_all_footprint(const vc_params *pp, uint32_t b, uint64_t *bytes) {

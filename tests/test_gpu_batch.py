@@ -101,3 +101,55 @@ def test_batch_on_one_executor_and_errors(vc):
         with pytest.raises(vc.VCError) as e:
             vc.vc_exec_create(0, ns)
         assert e.value.code == vc.VC_EINVAL
+
+
+def test_grouped_matches_single_jobs_and_oracle(vc):
+    """Fused groups (vc_open_all_grouped): jobs on the same params with the same b run as one
+    Step 1 over all their batches.  Every job's arrays and sampled proofs equal its one-job
+    call's, and the oracle's at L <= 6; groups cut at 2 and at 8 jobs; rounds taken ahead
+    (small groups), direct rounds where the group's batches fill the device but the single
+    job's do not (four 2^12, b = 1 jobs), ragged last batches, u32 and full-width entries in
+    one group, a job with no partner."""
+    spec = [(6, 2, 31, 32), (6, 2, 32, 256), (6, 2, 33, 32), (5, 3, 34, 256), (5, 3, 35, 256),
+            (9, 3, 36, 32), (9, 3, 37, 256), (9, 3, 38, 32), (12, 1, 39, 32), (12, 1, 40, 256),
+            (12, 1, 41, 32), (12, 1, 42, 32), (14, 2, 43, 256), (14, 2, 44, 32), (10, 32, 45, 256),
+            (10, 32, 46, 256), (8, 16, 47, 32), (8, 16, 48, 256), (7, 4, 49, 256)]
+    params, jobs, ints = {}, [], []
+    for L, b, seed, bits in spec:
+        if L not in params:
+            params[L] = vc.vc_setup(L, SEED, 0)
+        limbs = I.entries(1 << L, seed, bits)
+        m = dev_u32(limbs[:, 0]) if bits == 32 else \
+            torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+        jobs.append((params[L], vc.vc_commit(params[L], m, bits), b))
+        ints.append(limbs)
+    singles = [vc.vc_open_all(pp, cm, b) for pp, cm, b in jobs]
+    execs = [vc.vc_exec_create(0, ns) for ns in (6, 2)]
+    for gmax in (8, 2):
+        say("grouped: %d jobs, groups of at most %d" % (len(jobs), gmax))
+        out = vc.vc_open_all_grouped(jobs, execs, gmax)
+        torch.cuda.synchronize()
+        for (pp, cm, b), pr, one, limbs, (L, _, seed, bits) in zip(jobs, out, singles, ints, spec):
+            N, M = pp.N, pp.M
+            same_proofs(vc, pp, pr, one, sorted({0, 1, M - 1, M, N - 1, N // 2 + 3}))
+            if L <= 6:
+                opp = O.Params(L, SEED)
+                oop = O.Opening(O.Commitment(opp, I.limbs_to_bytes(limbs)), b)
+                for i in range(N):
+                    assert vc.vc_proof_get(pr, i) == oop.proof(i), (L, b, seed, i)
+        say("  every job equal")
+        del out
+    say("grouped: zero challenge in a group")
+    try:
+        vc.vc_test_zero_challenge(2)
+        with pytest.raises(vc.VCError) as e:
+            vc.vc_open_all_grouped(jobs[:3], execs, 8)
+        assert e.value.code == vc.VC_ECHALLENGE
+    finally:
+        vc.vc_test_zero_challenge(0)
+    again = vc.vc_open_all_grouped(jobs[:3], execs[:1], 8)
+    for pr, one, (pp, _, _) in zip(again, singles[:3], jobs[:3]):
+        same_proofs(vc, pp, pr, one, range(pp.N))
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_open_all_grouped(jobs[:2], execs, 0)
+    assert e.value.code == vc.VC_EINVAL
