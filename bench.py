@@ -306,13 +306,16 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=
     each, either one job per executor (g = 1, vc_open_all_batch) or the jobs of one size fused
     in groups of at most g (vc_open_all_grouped), ne groups at a time; the best of `reps`
     passes each.  The serialized proofs at the ends of every vector are compared with the
-    one-job call's."""
+    one-job call's.  The commits are timed too: vc_commit of every job in turn against
+    vc_commit_batch (all MSMs in one persistent launch, FC.Commit fused), with the MSM schedule
+    autotuned for these sizes first; commit + open-all is reported for the sequential path, the
+    executor pool and the fused form."""
     import numpy as np
     from paper_2601_03031_amd import inputs as I
     rng = np.random.default_rng(seed)
     Ls = [int(x) for x in rng.integers(8, 19, n_jobs)]
     log("batched jobs: %d vectors, L in [8, 18]: setup and commit" % n_jobs)
-    params, jobs, fmul, fexec = {}, [], 0, 0
+    params, jobs, fmul, fexec, ents = {}, [], 0, 0, []
     costs = op_costs()
     for i, L in enumerate(Ls):
         if L not in params:
@@ -325,9 +328,32 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=
         w = work_model(L, min(L * L, pp.K), limbs, costs)
         fexec += sum(v for k, v in w.items() if k not in ("k_msm_slices<OpsG1>", "ks_miller"))
         m = torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+        ents.append((pp, m, 256))
         jobs.append((pp, V.vc_commit(pp, m, 256), min(L * L, pp.K)))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    # commits: one after another, then batched (after the schedule is tuned for these sizes)
+    t0 = time.perf_counter()
+    V.vc_tune_msm(8, 18)
+    tune_s = time.perf_counter() - t0
+
+    def seq_commit():
+        t0 = time.perf_counter()
+        out = [V.vc_commit(pp, m, bits, stream) for pp, m, bits in ents]
+        return 1e3 * (time.perf_counter() - t0), out
+
+    def batch_commit():
+        t0 = time.perf_counter()
+        out = V.vc_commit_batch(ents, stream=stream)
+        return 1e3 * (time.perf_counter() - t0), out
+
+    seq_c_ms, seq_c = min((seq_commit() for _ in range(reps)), key=lambda r: r[0])
+    bat_c_ms, bat_c = min((batch_commit() for _ in range(reps + 1)), key=lambda r: r[0])
+    for a, r, (_, cm, _) in zip(bat_c, seq_c, jobs):
+        if a.C != r.C or a.C != cm.C:
+            raise RuntimeError("a batched commitment differs from the one-job call's")
+    del seq_c, bat_c
+    log("batched jobs: commits one by one %.1f ms, batched %.1f ms (tuning %.1f s)" % (seq_c_ms, bat_c_ms, tune_s))
 
     def sequential():
         t0 = time.perf_counter()
@@ -357,6 +383,16 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=
     k_best = min(res["batch_ms"], key=lambda k: res["batch_ms"][k])
     res["speedup"] = round(seq_ms / res["batch_ms"][k_best], 2)
     res["best_setup"] = k_best
+    pool = min((v for k, v in res["batch_ms"].items() if "_g" not in k), default=None)
+    fused = min((v for k, v in res["batch_ms"].items() if "_g" in k), default=None)
+    res["commit_ms"] = {"sequential": round(seq_c_ms, 2), "batched": round(bat_c_ms, 2),
+                        "speedup": round(seq_c_ms / bat_c_ms, 2), "msm_tuning_s": round(tune_s, 2)}
+    res["commit_plus_open_ms"] = {"sequential": round(seq_c_ms + seq_ms, 2),
+                                  "pool": round(seq_c_ms + pool, 2) if pool else None,
+                                  "fused": round(bat_c_ms + fused, 2) if fused else None}
+    if fused:
+        res["commit_plus_open_ms"]["speedup_fused"] = round((seq_c_ms + seq_ms) / (bat_c_ms + fused), 2)
+    V.vc_tune_load(None)  # the rest of the run keeps the default schedule
     # device utilization: the jobs' algorithmic multiply-adds over the time, against the ALU peak
     tops = lambda f, ms: f * MADS_PER_FMUL / (ms / 1e3) / 1e12
     res["field_mults"] = int(fmul)

@@ -105,6 +105,35 @@ int vc_commit(const vc_params *pp, const void *m_dev, uint64_t n, uint32_t entry
 int vc_commit_noalloc(const vc_params *pp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
                       void *Cj_out, uint8_t C_out[384]);
 
+/* VC.Commit (Eq. genCi, genC) of n independent vectors at once: job i commits m_devs[i] (as
+ * m_dev of vc_commit, N of pps[i] entries of entry_bits[i] = 32 or 256 bits) on params
+ * pps[i] (jobs may share params; all on one device).  All jobs' PC.Commit MSMs run in one
+ * persistent launch (workgroups take the (subvector, slice) blocks of every job in turn, jobs
+ * of uneven N and entry width side by side), their C_j in one launch, and FC.Commit of all
+ * jobs in one Miller-loop launch, one product tree and one final-exponentiation launch.
+ * outs[i] receives job i's commitment (the same as vc_commit's), C_out (host, n x 384 B, may
+ * be NULL) the C's.  Work runs on `stream` with the workspace and counters of executor ex
+ * (NULL: the default executor of pps[0], so the call must not overlap other calls on those
+ * params).  Synchronous on return.  VC_EINVAL on a bad argument or an entry >= r (then every
+ * outs[i] is NULL). */
+int vc_commit_batch(uint32_t n, const vc_params *const *pps, const void *const *m_devs, const uint32_t *entry_bits,
+                    vc_exec *ex, void *stream, vc_commitment **outs, uint8_t *C_out);
+
+/* Autotuner of the commit MSM's schedule: for each log2 N in [log_lo, log_hi] and entry width
+ * 32 and 256, times the commit MSM kernel (on seeded entries, on `device`) for every slice
+ * length from 1024 to 8192 digits per workgroup (capped at a whole subvector) and keeps the
+ * fastest.  The choices go into a process-wide table that vc_commit and vc_commit_batch use
+ * (results never depend on it: the MSM is exact); with path non-NULL they are also written
+ * there as text lines "log_n entry_bits entries_per_block".  Builds test parameters for each
+ * size (about as long as vc_setup).  VC_EINVAL for a bad range or an unwritable path. */
+int vc_tune_msm(int device, uint32_t log_lo, uint32_t log_hi, const char *path);
+
+/* Replaces the process-wide MSM schedule table with the one in file `path` (as written by
+ * vc_tune_msm); NULL restores the default schedule (the most entries a workgroup's shared
+ * memory sorts).  VC_EINVAL for an unreadable or malformed file (the table is then unchanged).
+ * vc_commit_noalloc always uses the default schedule (its scratch is sized for it). */
+int vc_tune_load(const char *path);
+
 /* VC.OpenAll(aux, m) with batch size b, 1 <= b <= K (Protocol 1): all N proofs,
  * kept on the device in shared form (one FC batch proof per block of b
  * subvectors, the folding tree, the HyperEval commitments and the Merkle tree). */

@@ -59,6 +59,9 @@ def lib():
         L.vc_open_all.argtypes = [vp, vp, u32, vp, C.POINTER(vp)]
         L.vc_commit_noalloc.argtypes = [vp, vp, u64, u32, vp, vp, vp]
         L.vc_params_load.argtypes = [u8p, sz, C.c_int, C.POINTER(vp)]
+        L.vc_commit_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), vp, vp, C.POINTER(vp), vp]
+        L.vc_tune_msm.argtypes = [C.c_int, u32, u32, C.c_char_p]
+        L.vc_tune_load.argtypes = [C.c_char_p]
         L.vc_diag_mad_rate.argtypes = [C.c_int, C.POINTER(C.c_double)]
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
@@ -219,6 +222,33 @@ def vc_commit(pp: Params, m, entry_bits: int = 256, stream=None) -> Commitment:
     _check(lib().vc_commit(pp.ptr, C.c_void_p(m.data_ptr()), pp.N, entry_bits, _stream_ptr(stream),
                            C.byref(out), cbuf), "vc_commit")
     return Commitment(out, pp, cbuf.raw)
+
+
+def vc_commit_batch(jobs, ex=None, stream=None) -> list:
+    """jobs: a list of (Params, device tensor of entries, entry_bits).  All commitments in fused
+    launches; returns the Commitment of every job, in order."""
+    n = len(jobs)
+    VP = C.c_void_p
+    for pp, m, bits in jobs:
+        _check_entries(pp, m, bits)
+    pps = (VP * max(n, 1))(*[pp.ptr for pp, _, _ in jobs])
+    ms = (VP * max(n, 1))(*[m.data_ptr() for _, m, _ in jobs])
+    bits = (C.c_uint32 * max(n, 1))(*[b for _, _, b in jobs])
+    outs = (VP * max(n, 1))()
+    Cb = C.create_string_buffer(384 * max(n, 1))
+    _check(lib().vc_commit_batch(n, pps, ms, bits, ex.ptr if ex else None, _stream_ptr(stream), outs, Cb),
+           "vc_commit_batch")
+    return [Commitment(VP(outs[i]), jobs[i][0], Cb.raw[384 * i:384 * i + 384]) for i in range(n)]
+
+
+def vc_tune_msm(lo: int, hi: int, path=None, device: int = 0) -> None:
+    """Autotune the commit MSM's slice length for log2 N in [lo, hi] (and write the table)."""
+    _check(lib().vc_tune_msm(device, lo, hi, path.encode() if path else None), "vc_tune_msm")
+
+
+def vc_tune_load(path=None) -> None:
+    """Load a tuned MSM schedule table (None: back to the default schedule)."""
+    _check(lib().vc_tune_load(path.encode() if path else None), "vc_tune_load")
 
 
 def vc_commit_noalloc(pp: Params, m, entry_bits: int, Cj_out, stream=None) -> bytes:

@@ -123,18 +123,18 @@ __global__ void __launch_bounds__(TPB) k_check_curve(const aff<O> *p, uint64_t n
 // scan.  S nwin <= MSM_MAXE (G1), MSM_G2_MAXE (G2).  (A tree over bucket ranges that merges
 // (S, W) pairs with doublings does a quarter of the scan's additions but measured slower:
 // with one block per CU at N = 2^16 the block's latency sets the time, and its doubling
-// chains are longer than the scan's eight steps.)
+// chains are longer than the scan's eight steps.)  One (j, slice) block: blk = j nslice + slice.
 template <class O>
-__global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, uint32_t nwin, uint32_t S,
-                                                    const aff<O> *table, jac<O> *partial) {
+__device__ __forceinline__ void msm_slice(const fe *scal, uint64_t M, uint32_t nwin, uint32_t S, const aff<O> *table,
+                                          jac<O> *partial, uint64_t blk) {
   __shared__ uint32_t cnt[256];
   __shared__ uint32_t off[256];
   constexpr uint32_t MAXE = sizeof(typename O::T) > sizeof(fe) ? MSM_G2_MAXE : MSM_MAXE;
   __shared__ uint32_t ent[MAXE];
   __shared__ jac<O> red[256];
   uint32_t nslice = (uint32_t)((M + S - 1) / S);
-  uint64_t j = blockIdx.x / nslice;
-  uint32_t sl = blockIdx.x % nslice;
+  uint64_t j = blk / nslice;
+  uint32_t sl = blk % nslice;
   uint64_t a0 = (uint64_t)sl * S;
   uint32_t na = (uint32_t)((a0 + S <= M) ? S : (M - a0));
   uint32_t t = threadIdx.x;
@@ -184,7 +184,70 @@ __global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, 
     if (t < s) red[t] = jac_add(red[t], red[t + s]);
     __syncthreads();
   }
-  if (t == 0) partial[blockIdx.x] = red[0];
+  if (t == 0) partial[blk] = red[0];
+}
+
+template <class O>
+__global__ void __launch_bounds__(256) k_msm_slices(const fe *scal, uint64_t M, uint32_t nwin, uint32_t S,
+                                                    const aff<O> *table, jac<O> *partial) {
+  msm_slice<O>(scal, M, nwin, S, table, partial, blockIdx.x);
+}
+
+// ================================================================ batched commit
+// job x of a batched commit owns blocks [J[x].blk0, J[x + 1].blk0) and packed entries
+// [J[x].k0, J[x + 1].k0): binary search over the table (job 0 starts at 0)
+__device__ __forceinline__ uint32_t job_of_blk(const CJob *J, uint32_t n, uint64_t b) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (J[mid].blk0 <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ uint32_t job_of_k(const CJob *J, uint32_t n, uint64_t i) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (J[mid].k0 <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// The PC.Commit MSMs of every job in one persistent launch: each workgroup takes blocks
+// blockIdx.x, blockIdx.x + gridDim.x, ... of all jobs' (j, slice) blocks (jobs of uneven N, entry
+// width and slice length side by side; every block sorts at most MSM_MAXE digits).
+__global__ void __launch_bounds__(256) k_msm_batch(const CJob *J, uint32_t n, uint64_t total) {
+  for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const CJob &c = J[job_of_blk(J, n, b)];
+    msm_slice<OpsG1>(c.m, c.M, c.nwin, c.S, c.table, c.part, b - c.blk0);
+    __syncthreads();  // the next block reuses the shared arrays
+  }
+}
+
+// v[k0 + j] = h[2 j] of each job (FC.Commit pairs C_j with v_j = h_{2j})
+__global__ void __launch_bounds__(TPB) k_commit_v(const CJob *J, uint32_t n, uint64_t total, g2_aff *v) {
+  uint64_t i = gtid();
+  if (i >= total) return;
+  const CJob &c = J[job_of_k(J, n, i)];
+  v[i] = c.h[2 * (i - c.k0)];
+}
+
+// Miller values of job x at F[x Kmax + j], padded with ones up to Kmax
+__global__ void __launch_bounds__(TPB) k_commit_pad(const CJob *J, uint32_t n, uint64_t Kmax, const fp12 *Fc, fp12 *F) {
+  uint64_t id = gtid();
+  if (id >= n * Kmax) return;
+  const CJob &c = J[id / Kmax];
+  const uint64_t j = id % Kmax;
+  F[id] = j < c.K ? Fc[c.k0 + j] : f12_one();
+}
+
+// C of job x into its commitment
+__global__ void __launch_bounds__(TPB) k_commit_store(const CJob *J, uint32_t n, const fp12 *Cs) {
+  uint64_t x = gtid();
+  if (x >= n) return;
+  *J[x].C = Cs[x];
 }
 
 // ================================================================ open-all, step 1
@@ -318,6 +381,21 @@ void msm_slices(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t 
   uint64_t nslice = (M + S - 1) / S;
   LAUNCH(k_msm_slices<OpsG1>, dim3((unsigned)(K * nslice)), dim3(256), 0, scal, M, nwin, S, table, partial);
 }
+void msm_batch(const CJob *J, uint32_t n, uint64_t total, unsigned grid, hipStream_t st) {
+  if (total) LAUNCH(k_msm_batch, dim3(grid), dim3(256), 0, J, n, total);
+}
+int msm_batch_grid(int device) {
+  // workgroups resident per compute unit (shared memory and registers allow), times the units
+  int per = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_msm_batch, 256, 0) != hipSuccess || per < 1) per = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
+  return per * cus;
+}
+void commit_v(const CJob *J, uint32_t n, uint64_t total, g2_aff *v, hipStream_t st) { L1(k_commit_v, total, J, n, total, v); }
+void commit_pad(const CJob *J, uint32_t n, uint64_t Kmax, const fp12 *Fc, fp12 *F, hipStream_t st) {
+  L1(k_commit_pad, n * Kmax, J, n, Kmax, Fc, F);
+}
+void commit_store(const CJob *J, uint32_t n, const fp12 *Cs, hipStream_t st) { L1(k_commit_store, n, J, n, Cs); }
 void msm_slices_g2(const fe *scal, uint64_t K, uint64_t M, uint32_t nwin, uint32_t S, const g2_aff *table, g2_jac *partial,
                    hipStream_t st) {
   uint64_t nslice = (M + S - 1) / S;

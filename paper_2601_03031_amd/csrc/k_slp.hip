@@ -777,6 +777,10 @@ void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32
   if (len > 1) LAUNCH(ks_f12_tree, dim3((unsigned)(nseg * ((len + 1) / 2))), dim3(SLP_T), 0, data, nseg, stride, len, cnt);
 }
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st) {
+  if (!out1) {  // every output to out0[s ostride]
+    out1 = out0 + ostride;
+    ostride *= 2;
+  }
   if (n) LAUNCH(ks_final_exp, dim3((unsigned)n), dim3(SLP_T), 0, in, stride, n, out0, out1, ostride);
 }
 void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,

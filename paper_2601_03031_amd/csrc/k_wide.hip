@@ -211,6 +211,26 @@ __global__ void __launch_bounds__(TPBW) kw_sum_g1(const void *data, uint64_t nse
   wst(out, s, jac_to_aff(acc));
 }
 
+// C_j of every job of a batched commit: the sum of its nslice MSM block results, affine, into
+// the job's commitment and into the packed array Cp (entry k0 + j)
+__global__ void __launch_bounds__(TPBW) kw_commit_sums(const CJob *J, uint32_t n, uint64_t total, void *Cp) {
+  uint64_t i = wgid();
+  if (i >= total) return;
+  uint32_t lo = 0, hi = n;  // the job holding packed entry i
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (J[mid].k0 <= i) lo = mid;
+    else hi = mid;
+  }
+  const CJob &c = J[lo];
+  const uint64_t j = i - c.k0;
+  g1_jac acc = wld<g1_jac>(c.part, j * c.nslice);
+  for (uint64_t q = 1; q < c.nslice; q++) acc = jac_add(acc, wld<g1_jac>(c.part, j * c.nslice + q));
+  g1_aff a = jac_to_aff(acc);
+  wst(c.Cj, j, a);
+  wst(Cp, i, a);
+}
+
 __global__ void __launch_bounds__(TPBW) kw_dlevel(const S2Job *J, uint32_t G, uint64_t K, uint32_t h) {
   uint64_t w = wgid();
   if (w >= G * (K >> h)) return;
@@ -313,6 +333,9 @@ void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t 
   LW(kw_jac_to_aff<OpsG1>, n, in, stride, n, out, ostride);
 }
 void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st) { LW(kw_sum_g1, nseg, data, nseg, len, out); }
+void commit_sums(const CJob *J, uint32_t n, uint64_t total, void *Cp, hipStream_t st) {
+  if (total) LW(kw_commit_sums, total, J, n, total, Cp);
+}
 void dlevel(const S2Job *J, uint32_t G, uint64_t K, uint32_t h, hipStream_t st) {
   LW(kw_dlevel, G * (K >> h), J, G, K, h);
 }

@@ -28,6 +28,20 @@ struct S2Job {
   g1_aff *D, *W;     // the D-tree, 2K - 1 points; HyperEval commitments, M - 1 points
 };
 
+// One job of a batched commit (VC.Commit of many vectors at once): its entries, keys, MSM
+// schedule and outputs.  Jobs follow one another in the MSM's block range (blk0: job x has
+// blocks blk0 .. + K nslice) and in the packed per-subvector arrays (k0: entries k0 .. + K).
+struct CJob {
+  const fe *m;          // N canonical entries
+  const g1_aff *table;  // fixed-base table 2^{8 w} ek_{lM}[a] of the job's params
+  const g2_aff *h;      // h of the job's params (v_j = h_{2j})
+  g1_jac *part;         // K nslice partial sums of the MSM blocks
+  g1_aff *Cj;           // the commitment's C_j
+  fp12 *C;              // the commitment's C
+  uint64_t M, K, nslice, blk0, k0;
+  uint32_t nwin, S;     // 8-bit windows per entry, entries per MSM block
+};
+
 namespace kl {
 void trapdoor(const uint8_t *seed, uint32_t lM, fe *s, fe *beta, hipStream_t st);
 void ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n, hipStream_t st);
@@ -36,6 +50,14 @@ void msm_tables(const g1_aff *base, uint64_t M, uint32_t nwin, g1_aff *table, hi
 void lift_u32(const uint32_t *in, uint64_t n, fe *out, hipStream_t st);
 void check_fr(const fe *m, uint64_t n, int *err, hipStream_t st);
 void zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
+// batched commit: every job's MSM blocks in one persistent launch of `grid` workgroups
+// (msm_batch_grid: as many as stay resident), v_j of every job packed, Miller values padded
+// with ones to Kmax per job, each C stored into its commitment
+void msm_batch(const CJob *J, uint32_t n, uint64_t total, unsigned grid, hipStream_t st);
+int msm_batch_grid(int device);
+void commit_v(const CJob *J, uint32_t n, uint64_t total, g2_aff *v, hipStream_t st);
+void commit_pad(const CJob *J, uint32_t n, uint64_t Kmax, const fp12 *Fc, fp12 *F, hipStream_t st);
+void commit_store(const CJob *J, uint32_t n, const fp12 *Cs, hipStream_t st);
 // canonical big-endian F_p encodings (32 B each) -> Montgomery form; >= p sets VC_ERRBIT_RANGE
 void decode_fp(const uint8_t *in, uint64_t n, fe *out, int *err, hipStream_t st);
 // points not on their curve set VC_ERRBIT_RANGE
@@ -117,6 +139,8 @@ void d_leaves(const S2Job *J, uint32_t G, uint64_t K, hipStream_t st);
 void g1_reduce(void *data, uint64_t nseg, uint64_t stride, uint64_t len, hipStream_t st);
 void g1_to_aff(const void *in, uint64_t stride, uint64_t n, void *out, uint64_t ostride, hipStream_t st);
 void sum_g1(const void *data, uint64_t nseg, uint64_t len, void *out, hipStream_t st);
+// batched commit: C_j of every job (into its commitment and packed at Cp + k0 + j)
+void commit_sums(const CJob *J, uint32_t n, uint64_t total, void *Cp, hipStream_t st);
 void dlevel(const S2Job *J, uint32_t G, uint64_t K, uint32_t h, hipStream_t st);
 void diag_field(int which, int op, const void *a, const void *b, uint64_t n, void *out, hipStream_t st);
 }  // namespace klw
@@ -127,6 +151,8 @@ void miller(const g1_aff *P, uint64_t sp, const g2_aff *Q, uint64_t sq, uint64_t
 void oa_miller(const g1_aff *A, const g2_aff *V, uint64_t K, uint64_t nb, uint64_t h, fp12 *F, hipStream_t st);
 // one launch; cnt: nseg tree_counters(len) zeroed counters, zero again on return
 void f12_reduce(fp12 *data, uint64_t nseg, uint64_t stride, uint64_t len, uint32_t *cnt, hipStream_t st);
+// input s at in[s stride]; output to (s odd ? out1 : out0)[(s >> 1) ostride], or to
+// out0[s ostride] when out1 is NULL
 void final_exp(const fp12 *in, uint64_t stride, uint64_t n, fp12 *out0, fp12 *out1, uint64_t ostride, hipStream_t st);
 void oa_fold_g2(const g2_aff *Vin, g2_aff *Vout, const fe *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j, uint32_t lK,
                 hipStream_t st);

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <unordered_map>
 #include "kernels.h"
@@ -469,6 +470,28 @@ VC_API void vc_params_free(vc_params *pp) {
 }
 
 // ------------------------------------------------------------------ commit
+// ------------------------------------------------------------------ MSM schedule
+// Entries per block of the commit MSM (its slice length S), per (log N, entry bits): the
+// autotuner's choice (vc_tune_msm, vc_tune_load), else as many as a block's shared-memory sort
+// holds (MSM_MAXE = 8192 digits).  Process-wide; results do not depend on it.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::pair<uint32_t, uint32_t>, uint32_t> g_tune;
+constexpr uint32_t MSM_DIGITS = 8192;  // digits one MSM block sorts in shared memory
+
+uint32_t msm_slice_len(uint32_t L, uint64_t M, uint32_t bits) {
+  const uint32_t nwin = bits == 32 ? 4 : NWIN;
+  uint32_t S = MSM_DIGITS / nwin;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({L, bits});
+    if (it != g_tune.end()) S = it->second;
+  }
+  if (S > M) S = (uint32_t)M;
+  return S;
+}
+}  // namespace
+
 VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32_t entry_bits, void *stream,
                      vc_commitment **out, uint8_t C_out[384]) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
@@ -490,8 +513,7 @@ VC_API int vc_commit(const vc_params *cpp, const void *m_dev, uint64_t n, uint32
   cm->Cj = at<g1_aff>(cm->mem, o_Cj);
   cm->C = at<fp12>(cm->mem, o_C);
   uint32_t nwin = entry_bits == 32 ? 4 : NWIN;
-  uint32_t S = (uint32_t)(8192 / nwin);
-  if (S > M) S = (uint32_t)M;
+  uint32_t S = msm_slice_len(pp->L, M, entry_bits);
   uint64_t nslice = (M + S - 1) / S;
   Carve t;
   size_t o_err = t.take<int>(1), o_part = t.take<g1_jac>(K * nslice), o_F = t.take<fp12>(K), o_enc = t.take<uint8_t>(384);
@@ -540,6 +562,239 @@ VC_API void vc_commitment_free(vc_commitment *cm) {
   if (cm->mem) (void)hipFree(cm->mem);
   delete cm;
   (void)hipGetLastError();  // a release reports nothing and leaves no error behind
+}
+
+// ------------------------------------------------------------------ batched commit
+// VC.Commit of n vectors at once: every job's PC.Commit MSM blocks in one persistent launch
+// (k_msm_batch), their C_j in one launch, all FC.Commit Miller loops in one launch over the
+// packed (C_j, v_j) pairs, one product tree over per-job segments padded with ones, and one
+// final exponentiation launch for all C.
+VC_API int vc_commit_batch(uint32_t n, const vc_params *const *pps, const void *const *m_devs, const uint32_t *entry_bits,
+                           vc_exec *exa, void *stream, vc_commitment **outs, uint8_t *C_out) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (!pps || !m_devs || !entry_bits || !outs) return VC_EINVAL;
+  for (uint32_t i = 0; i < n; i++) outs[i] = nullptr;
+  if (n == 0) return VC_OK;
+  for (uint32_t i = 0; i < n; i++)
+    if (!pps[i] || !m_devs[i] || (entry_bits[i] != 32 && entry_bits[i] != 256) || pps[i]->device != pps[0]->device)
+      return VC_EINVAL;
+  vc_exec *ex = exa ? exa : pps[0]->ex;
+  if (ex->device != pps[0]->device) return VC_EINVAL;
+  CK(hipSetDevice(pps[0]->device));
+  hipStream_t st = (hipStream_t)stream;
+  struct Release {
+    std::vector<vc_commitment *> c;
+    bool keep = false;
+    ~Release() {
+      if (!keep)
+        for (vc_commitment *q : c) vc_commitment_free(q);
+    }
+  } rel;
+  std::vector<CJob> J(n);
+  uint64_t blocks = 0, totalK = 0, parts = 0, Kmax = 0;
+  for (uint32_t x = 0; x < n; x++) {
+    const vc_params *pp = pps[x];
+    vc_commitment *cm = new vc_commitment();
+    rel.c.push_back(cm);
+    cm->pp = pp;
+    cm->device = pp->device;
+    Carve c;
+    size_t o_m = c.take<fe>(pp->N), o_Cj = c.take<g1_aff>(pp->K), o_C = c.take<fp12>(1);
+    hipError_t e = hipMalloc(&cm->mem, c.off);
+    if (e != hipSuccess) return hip_fail(e, "vc_commit_batch alloc");
+    cm->m = at<fe>(cm->mem, o_m);
+    cm->Cj = at<g1_aff>(cm->mem, o_Cj);
+    cm->C = at<fp12>(cm->mem, o_C);
+    const uint32_t S = msm_slice_len(pp->L, pp->M, entry_bits[x]);
+    const uint64_t nslice = (pp->M + S - 1) / S;
+    J[x] = {cm->m, pp->table, pp->h, nullptr, cm->Cj, cm->C, pp->M, pp->K, nslice, blocks, totalK,
+            entry_bits[x] == 32 ? 4u : NWIN, S};
+    blocks += pp->K * nslice;
+    parts += pp->K * nslice;
+    totalK += pp->K;
+    Kmax = std::max<uint64_t>(Kmax, pp->K);
+  }
+  Carve t;
+  size_t o_err = t.take<int>(1), o_J = t.take<CJob>(n), o_part = t.take<g1_jac>(parts), o_Cp = t.take<g1_aff>(totalK),
+         o_v = t.take<g2_aff>(totalK), o_Fc = t.take<fp12>(totalK), o_F = t.take<fp12>(n * Kmax),
+         o_Cs = t.take<fp12>(n), o_enc = t.take<uint8_t>(384ull * n);
+  if (int rc = ensure_ws(ex, t.off)) return rc;
+  if (int rc = ensure_cnt(ex, n * tree_counters(Kmax), st)) return rc;
+  void *ws = ex->ws;
+  for (uint64_t x = 0, o = 0; x < n; o += J[x].K * J[x].nslice, x++) J[x].part = at<g1_jac>(ws, o_part) + o;
+  int *err = at<int>(ws, o_err);
+  CJob *Jd = at<CJob>(ws, o_J);
+  kl::zero_u32(reinterpret_cast<uint32_t *>(err), 1, st);
+  CK(hipMemcpyAsync(Jd, J.data(), n * sizeof(CJob), hipMemcpyHostToDevice, st));
+  for (uint32_t x = 0; x < n; x++) {
+    vc_commitment *cm = rel.c[x];
+    if (entry_bits[x] == 32) {
+      kl::lift_u32(static_cast<const uint32_t *>(m_devs[x]), pps[x]->N, cm->m, st);
+    } else {
+      CK(hipMemcpyAsync(cm->m, m_devs[x], pps[x]->N * sizeof(fe), hipMemcpyDeviceToDevice, st));
+      kl::check_fr(cm->m, pps[x]->N, err, st);
+    }
+  }
+  kl::msm_batch(Jd, n, blocks, (unsigned)std::min<uint64_t>(blocks, kl::msm_batch_grid(pps[0]->device)), st);
+  g1_aff *Cp = at<g1_aff>(ws, o_Cp);
+  g2_aff *v = at<g2_aff>(ws, o_v);
+  fp12 *Fc = at<fp12>(ws, o_Fc), *F = at<fp12>(ws, o_F), *Cs = at<fp12>(ws, o_Cs);
+  klw::commit_sums(Jd, n, totalK, Cp, st);
+  kl::commit_v(Jd, n, totalK, v, st);
+  ks::miller(Cp, 1, v, 1, totalK, Fc, st);
+  kl::commit_pad(Jd, n, Kmax, Fc, F, st);
+  ks::f12_reduce(F, n, Kmax, Kmax, ex->cnt, st);
+  // (input s goes to (s odd ? out1 : out0)[(s >> 1) ostride]: Cs[s] for every job)
+  ks::final_exp(F, Kmax, n, Cs, Cs + 1, 2, st);
+  kl::commit_store(Jd, n, Cs, st);
+  uint8_t *enc = at<uint8_t>(ws, o_enc);
+  kl::encode(reinterpret_cast<const fe *>(Cs), 12ull * n, 0, enc, st);
+  int herr = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && C_out) e = hipMemcpyAsync(C_out, enc, 384ull * n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    ex->cnt_dirty = true;  // the product tree may have stopped half way
+    return hip_fail(e, "vc_commit_batch");
+  }
+  if (herr & VC_ERRBIT_RANGE) return VC_EINVAL;
+  rel.keep = true;
+  for (uint32_t x = 0; x < n; x++) outs[x] = rel.c[x];
+  return VC_OK;
+}
+
+// ------------------------------------------------------------------ MSM schedule autotuner
+namespace {
+// seeded entries below 2^253 (host, splitmix64), for timing only
+void tune_entries(std::vector<fe> &m, uint64_t seed) {
+  uint64_t z = seed;
+  auto next = [&]() {
+    z += 0x9e3779b97f4a7c15ull;
+    uint64_t r = z;
+    r = (r ^ (r >> 30)) * 0xbf58476d1ce4e5b9ull;
+    r = (r ^ (r >> 27)) * 0x94d049bb133111ebull;
+    return r ^ (r >> 31);
+  };
+  for (fe &v : m) {
+    for (int q = 0; q < 8; q += 2) {
+      uint64_t r = next();
+      v.l[q] = (uint32_t)r;
+      v.l[q + 1] = (uint32_t)(r >> 32);
+    }
+    v.l[7] &= (1u << 29) - 1;
+  }
+}
+}  // namespace
+
+VC_API int vc_tune_msm(int device, uint32_t log_lo, uint32_t log_hi, const char *path) {
+  (void)hipGetLastError();  // errors left by other HIP clients are not ours
+  if (log_lo < 2 || log_hi > VC_MAX_LOG_N || log_lo > log_hi) return VC_EINVAL;
+  CK(hipSetDevice(device));
+  const int grid = kl::msm_batch_grid(device);
+  std::map<std::pair<uint32_t, uint32_t>, uint32_t> best;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CK(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  static const uint8_t seed[32] = {'t', 'u', 'n', 'e'};
+  for (uint32_t L = log_lo; L <= log_hi && e == hipSuccess; L++) {
+    vc_params *pp = nullptr;
+    if (int rc = vc_setup(L, seed, device, &pp)) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+    std::vector<fe> hm(pp->N);
+    tune_entries(hm, 0x5eed0000ull + L);
+    const uint64_t maxparts = pp->K * pp->M;  // partial sums at the shortest slice (S = 1)
+    Carve t;
+    size_t o_m = t.take<fe>(pp->N), o_part = t.take<g1_jac>(std::min<uint64_t>(maxparts, pp->K * (pp->M + 31) / 32 + pp->K)),
+           o_J = t.take<CJob>(1);
+    void *d = nullptr;
+    e = hipMalloc(&d, t.off);
+    if (e == hipSuccess) e = hipMemcpy(at<fe>(d, o_m), hm.data(), pp->N * sizeof(fe), hipMemcpyHostToDevice);
+    for (uint32_t bits : {32u, 256u}) {
+      const uint32_t nwin = bits == 32 ? 4 : NWIN;
+      float best_ms = 0;
+      uint32_t best_S = 0;
+      // candidates: blocks of 1024 .. 8192 digits (a 32-bit entry has 4, a full one 32), at
+      // most a whole subvector (S >= 32 or S = M: within the partial-sum buffer)
+      std::vector<uint32_t> cand;
+      for (uint32_t digits = 1024; digits <= MSM_DIGITS; digits *= 2) {
+        const uint32_t S = (uint32_t)std::min<uint64_t>(digits / nwin, pp->M);
+        if (cand.empty() || cand.back() != S) cand.push_back(S);
+      }
+      for (uint32_t S : cand) {
+        if (e != hipSuccess) break;
+        const uint64_t nslice = (pp->M + S - 1) / S;
+        CJob j = {at<fe>(d, o_m), pp->table, pp->h, at<g1_jac>(d, o_part), nullptr, nullptr, pp->M, pp->K, nslice, 0, 0,
+                  nwin, S};
+        e = hipMemcpy(at<CJob>(d, o_J), &j, sizeof j, hipMemcpyHostToDevice);
+        const uint64_t blocks = pp->K * nslice;
+        const unsigned g = (unsigned)std::min<uint64_t>(blocks, grid);
+        float ms_best = 0;
+        for (int rep = 0; rep < 4 && e == hipSuccess; rep++) {
+          e = hipEventRecord(e0, nullptr);
+          if (e == hipSuccess) {
+            kl::msm_batch(at<CJob>(d, o_J), 1, blocks, g, nullptr);
+            e = hipGetLastError();
+          }
+          if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0 && (ms_best == 0 || ms < ms_best)) ms_best = ms;  // rep 0 warms up
+        }
+        if (e == hipSuccess && (best_S == 0 || ms_best < best_ms)) {
+          best_ms = ms_best;
+          best_S = S;
+        }
+      }
+      if (best_S) best[{L, bits}] = best_S;
+    }
+    if (d) (void)hipFree(d);
+    vc_params_free(pp);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "vc_tune_msm");
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &kv : best) g_tune[kv.first] = kv.second;
+  }
+  if (path) {
+    FILE *f = fopen(path, "w");
+    if (!f) return VC_EINVAL;
+    fprintf(f, "# commit MSM slice lengths: log_n entry_bits entries_per_block\n");
+    for (auto &kv : best) fprintf(f, "%u %u %u\n", kv.first.first, kv.first.second, kv.second);
+    if (fclose(f) != 0) return VC_EINVAL;
+  }
+  return VC_OK;
+}
+
+VC_API int vc_tune_load(const char *path) {
+  std::map<std::pair<uint32_t, uint32_t>, uint32_t> tab;
+  if (path) {
+    FILE *f = fopen(path, "r");
+    if (!f) return VC_EINVAL;
+    char line[256];
+    int bad = 0;
+    while (fgets(line, sizeof line, f)) {
+      if (line[0] == '#' || line[0] == '\n') continue;
+      unsigned L = 0, bits = 0, S = 0;
+      if (sscanf(line, "%u %u %u", &L, &bits, &S) != 3 || L < 2 || L > VC_MAX_LOG_N || (bits != 32 && bits != 256) ||
+          S < 1 || S * (bits == 32 ? 4u : NWIN) > MSM_DIGITS) {
+        bad = 1;
+        break;
+      }
+      tab[{L, bits}] = S;
+    }
+    fclose(f);
+    if (bad) return VC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune = tab;  // NULL: back to the default schedule
+  return VC_OK;
 }
 
 // ------------------------------------------------------------------ commit without allocation

@@ -153,3 +153,69 @@ def test_grouped_matches_single_jobs_and_oracle(vc):
     with pytest.raises(vc.VCError) as e:
         vc.vc_open_all_grouped(jobs[:2], execs, 0)
     assert e.value.code == vc.VC_EINVAL
+
+
+def _dev_entries(limbs, bits):
+    if bits == 32:
+        return dev_u32(limbs[:, 0])
+    return torch.from_numpy(np.ascontiguousarray(limbs).view(np.uint8).reshape(-1).copy()).cuda()
+
+
+def test_commit_batch_matches_single_and_oracle(vc, tmp_path):
+    """vc_commit_batch (all jobs' MSMs in one persistent launch, FC.Commit of all jobs in fused
+    launches): every job's C_j and C equal vc_commit's and the oracle's (L <= 8); jobs of uneven
+    N and entry width, some on shared params; open-all from a batch-made commitment equals the
+    one from vc_commit's; the autotuned schedule gives the same bytes; an entry >= r fails the
+    batch."""
+    spec = [(4, 256, 51), (8, 32, 52), (12, 256, 53), (6, 32, 54), (8, 256, 55), (14, 32, 56), (10, 256, 57),
+            (12, 32, 58), (5, 256, 59), (16, 256, 60)]
+    params = {}
+    jobs, limbs_all = [], []
+    for L, bits, seed in spec:
+        if L not in params:
+            params[L] = vc.vc_setup(L, SEED, 0)
+        limbs = I.entries(1 << L, seed, bits)
+        jobs.append((params[L], _dev_entries(limbs, bits), bits))
+        limbs_all.append(limbs)
+    say("commit batch of %d jobs" % len(jobs))
+    got = vc.vc_commit_batch(jobs)
+    singles = [vc.vc_commit(pp, m, bits) for pp, m, bits in jobs]
+    for (L, bits, seed), g, s, limbs in zip(spec, got, singles, limbs_all):
+        assert g.C == s.C and g.export("C") == s.C, (L, bits, seed)
+        assert g.export("Cj") == s.export("Cj"), (L, bits, seed)
+        if L <= 8:
+            ocm = O.Commitment(O.Params(L, SEED), I.limbs_to_bytes(limbs))
+            assert g.C == ocm.C and g.export("Cj") == b"".join(ocm.Cj), (L, bits, seed)
+    for i in (2, 5):
+        pp = jobs[i][0]
+        a = vc.vc_open_all(pp, got[i], 3)
+        b_ = vc.vc_open_all(pp, singles[i], 3)
+        same_proofs(vc, pp, a, b_, [0, pp.N - 1, pp.N // 3])
+    say("autotuned schedule")
+    path = str(tmp_path / "msm.txt")
+    vc.vc_tune_msm(4, 16, path)
+    rows = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    assert {(int(a), int(b)) for a, b, _ in rows} == {(L, w) for L in range(4, 17) for w in (32, 256)}
+    try:
+        vc.vc_tune_load(path)
+        tuned = vc.vc_commit_batch(jobs)
+        for g, s in zip(tuned, singles):
+            assert g.C == s.C and g.export("Cj") == s.export("Cj")
+        for (pp, m, bits), s in zip(jobs, singles):
+            t1 = vc.vc_commit(pp, m, bits)
+            assert t1.C == s.C and t1.export("Cj") == s.export("Cj")
+        bad = tmp_path / "bad.txt"
+        bad.write_text("16 256 1000\n")  # 1000 x 32 digits: more than a workgroup sorts
+        with pytest.raises(vc.VCError) as e:
+            vc.vc_tune_load(str(bad))
+        assert e.value.code == vc.VC_EINVAL
+    finally:
+        vc.vc_tune_load(None)
+    say("commit batch with an entry >= r")
+    limbs = I.entries(64, 61)
+    r_limbs = [(I.R >> (64 * k)) & (2**64 - 1) for k in range(4)]
+    limbs[7] = np.array(r_limbs, dtype=np.uint64)
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_commit_batch([jobs[3], (params[6], _dev_entries(limbs, 256), 256)])
+    assert e.value.code == vc.VC_EINVAL
+    assert vc.vc_commit_batch([]) == []
