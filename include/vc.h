@@ -151,6 +151,17 @@ int vc_open_all(const vc_params *pp, const vc_commitment *cm, uint32_t b, void *
 int vc_exec_create(int device, uint32_t nstreams, vc_exec **out);
 void vc_exec_free(vc_exec *ex);
 
+/* HIP graphs for batched commits on executor ex (on != 0; off by default): vc_commit_batch on
+ * this executor captures its fused launch chain (MSM, C_j sums, Miller loops, product tree,
+ * final exponentiations, encoding) into a graph on the executor's own stream, and replays the
+ * graph on later calls with the same batch shape (number of jobs and the sizes of every
+ * packed array) while the executor's workspace stays where it was; the jobs' entries and
+ * outputs are reached through the job table the call writes before the replay.  Results are
+ * the same as without graphs.  Turning graphs off releases the graph.  Not while profiling
+ * (then the chain runs eagerly).  vc_exec_graph_stats: stats[0] captures, stats[1] replays. */
+int vc_exec_set_graphs(vc_exec *ex, int on);
+int vc_exec_graph_stats(const vc_exec *ex, uint64_t stats[2]);
+
 /* vc_open_all (Protocol 1, §4.2) on executor ex (of the params' device) instead of the
  * params' default one; `stream` as for vc_open_all. */
 int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t b, vc_exec *ex, void *stream,

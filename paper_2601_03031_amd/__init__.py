@@ -65,6 +65,8 @@ def lib():
         L.vc_diag_mad_rate.argtypes = [C.c_int, C.POINTER(C.c_double)]
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
+        L.vc_exec_set_graphs.argtypes = [vp, C.c_int]
+        L.vc_exec_graph_stats.argtypes = [vp, vp]
         L.vc_open_all_ex.argtypes = [vp, vp, u32, vp, vp, C.POINTER(vp)]
         L.vc_open_all_footprint.argtypes = [vp, u32, C.POINTER(u64)]
         L.vc_server_create.argtypes = [C.c_int, u32, u32, u64, C.POINTER(vp)]
@@ -272,6 +274,16 @@ def vc_open_all(pp: Params, cm: Commitment, b: int, stream=None) -> Proofs:
 class Exec(_Handle):
     """Streams, events and workspace of one open-all job at a time."""
     _free = "vc_exec_free"
+
+    def set_graphs(self, on: bool = True) -> None:
+        """Capture and replay batched commits on this executor as HIP graphs."""
+        _check(lib().vc_exec_set_graphs(self.ptr, 1 if on else 0), "vc_exec_set_graphs")
+
+    def graph_stats(self) -> tuple:
+        """(captures, replays) of batched-commit graphs on this executor."""
+        st = (C.c_uint64 * 2)()
+        _check(lib().vc_exec_graph_stats(self.ptr, st), "vc_exec_graph_stats")
+        return int(st[0]), int(st[1])
 
 
 def vc_exec_create(device: int = 0, nstreams: int = 6) -> Exec:

@@ -143,7 +143,19 @@ struct vc_exec {
   uint32_t *cnt = nullptr;
   uint64_t cnt_n = 0;
   bool cnt_dirty = false;  // counters to be zeroed before the next use (new, or left by a failed call)
+  // batched commits: capture their fused launch chain into a HIP graph and replay it while the
+  // batch shape and the workspace stay the same (vc_exec_set_graphs)
+  bool graphs = false;
+  hipGraphExec_t cgraph = nullptr;
+  std::vector<uint64_t> ckey;  // the shape and buffers the graph was captured for
+  uint64_t captures = 0, replays = 0;
 };
+
+static void drop_graph(vc_exec *ex) {
+  if (ex->cgraph) (void)hipGraphExecDestroy(ex->cgraph);
+  ex->cgraph = nullptr;
+  ex->ckey.clear();
+}
 
 struct vc_params {
   int device;
@@ -245,6 +257,7 @@ static int ensure_ws(vc_exec *ex, size_t need) {
 // allocates them again)
 static void exec_release(vc_exec *ex) {
   (void)hipSetDevice(ex->device);
+  drop_graph(ex);  // it refers to the buffers released below
   if (ex->ws) (void)hipFree(ex->ws);
   if (ex->cnt) (void)hipFree(ex->cnt);
   ex->ws = nullptr;
@@ -258,6 +271,7 @@ VC_API void vc_exec_free(vc_exec *ex) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!ex) return;
   hipSetDevice(ex->device);
+  drop_graph(ex);
   if (ex->ws) hipFree(ex->ws);
   if (ex->cnt) hipFree(ex->cnt);
   for (auto sd : ex->own)
@@ -266,6 +280,23 @@ VC_API void vc_exec_free(vc_exec *ex) {
     if (ev) hipEventDestroy(ev);
   delete ex;
   (void)hipGetLastError();  // a release reports nothing and leaves no error behind
+}
+
+VC_API int vc_exec_set_graphs(vc_exec *ex, int on) {
+  if (!ex) return VC_EINVAL;
+  ex->graphs = on != 0;
+  if (!ex->graphs) {
+    (void)hipSetDevice(ex->device);
+    drop_graph(ex);
+  }
+  return VC_OK;
+}
+
+VC_API int vc_exec_graph_stats(const vc_exec *ex, uint64_t stats[2]) {
+  if (!ex || !stats) return VC_EINVAL;
+  stats[0] = ex->captures;
+  stats[1] = ex->replays;
+  return VC_OK;
 }
 
 VC_API int vc_exec_create(int device, uint32_t nstreams, vc_exec **out) {
@@ -635,20 +666,53 @@ VC_API int vc_commit_batch(uint32_t n, const vc_params *const *pps, const void *
       kl::check_fr(cm->m, pps[x]->N, err, st);
     }
   }
-  kl::msm_batch(Jd, n, blocks, (unsigned)std::min<uint64_t>(blocks, kl::msm_batch_grid(pps[0]->device)), st);
+  const unsigned grid = (unsigned)std::min<uint64_t>(blocks, kl::msm_batch_grid(pps[0]->device));
   g1_aff *Cp = at<g1_aff>(ws, o_Cp);
   g2_aff *v = at<g2_aff>(ws, o_v);
   fp12 *Fc = at<fp12>(ws, o_Fc), *F = at<fp12>(ws, o_F), *Cs = at<fp12>(ws, o_Cs);
-  klw::commit_sums(Jd, n, totalK, Cp, st);
-  kl::commit_v(Jd, n, totalK, v, st);
-  ks::miller(Cp, 1, v, 1, totalK, Fc, st);
-  kl::commit_pad(Jd, n, Kmax, Fc, F, st);
-  ks::f12_reduce(F, n, Kmax, Kmax, ex->cnt, st);
-  // (input s goes to (s odd ? out1 : out0)[(s >> 1) ostride]: Cs[s] for every job)
-  ks::final_exp(F, Kmax, n, Cs, Cs + 1, 2, st);
-  kl::commit_store(Jd, n, Cs, st);
   uint8_t *enc = at<uint8_t>(ws, o_enc);
-  kl::encode(reinterpret_cast<const fe *>(Cs), 12ull * n, 0, enc, st);
+  // the fused chain: its arguments are the workspace's buffers and the batch's shape; each
+  // job's entries and outputs are reached through the job table written above
+  auto chain = [&](hipStream_t s) {
+    kl::msm_batch(Jd, n, blocks, grid, s);
+    klw::commit_sums(Jd, n, totalK, Cp, s);
+    kl::commit_v(Jd, n, totalK, v, s);
+    ks::miller(Cp, 1, v, 1, totalK, Fc, s);
+    kl::commit_pad(Jd, n, Kmax, Fc, F, s);
+    ks::f12_reduce(F, n, Kmax, Kmax, ex->cnt, s);
+    // (input s goes to (s odd ? out1 : out0)[(s >> 1) ostride]: Cs[s] for every job)
+    ks::final_exp(F, Kmax, n, Cs, Cs + 1, 2, s);
+    kl::commit_store(Jd, n, Cs, s);
+    kl::encode(reinterpret_cast<const fe *>(Cs), 12ull * n, 0, enc, s);
+  };
+  if (!ex->graphs || g_prof || dbg::on()) {
+    chain(st);
+  } else {
+    // captured on the executor's own stream (the caller's may be the null stream, which cannot
+    // be captured) and replayed there between the caller's work before and after it
+    std::vector<uint64_t> key = {n, blocks, totalK, Kmax, grid, (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)ex->cnt,
+                                 o_J, o_part, o_Cp, o_v, o_Fc, o_F, o_Cs, o_enc};
+    hipStream_t gs = ex->main;
+    if (!ex->cgraph || key != ex->ckey) {
+      drop_graph(ex);
+      hipGraph_t g = nullptr;
+      CK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      chain(gs);
+      hipError_t ec = hipStreamEndCapture(gs, &g);
+      if (ec == hipSuccess) ec = hipGraphInstantiate(&ex->cgraph, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (ec != hipSuccess) {
+        ex->cgraph = nullptr;
+        return hip_fail(ec, "vc_commit_batch capture");
+      }
+      ex->ckey = key;
+      ex->captures++;
+    }
+    if (int rc = stream_wait(ex, 0, st, gs)) return rc;
+    CK(hipGraphLaunch(ex->cgraph, gs));
+    ex->replays++;
+    if (int rc = stream_wait(ex, 1, gs, st)) return rc;
+  }
   int herr = 0;
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);

@@ -219,3 +219,41 @@ def test_commit_batch_matches_single_and_oracle(vc, tmp_path):
         vc.vc_commit_batch([jobs[3], (params[6], _dev_entries(limbs, 256), 256)])
     assert e.value.code == vc.VC_EINVAL
     assert vc.vc_commit_batch([]) == []
+
+
+def test_commit_batch_graph_replays(vc):
+    """Batched commits through a captured HIP graph (vc_exec_set_graphs): the first call of a
+    shape captures the fused chain, later calls of that shape replay it with new entries (with
+    other device work between the replays); every replay equals the eager batch and vc_commit,
+    a new shape captures again, and the old shape after it too."""
+    shapes = {"A": [(8, 256), (12, 32), (10, 256), (6, 32)], "B": [(14, 256), (9, 32)]}
+    params = {}
+
+    def jobs_for(shape, seed):
+        out = []
+        for k, (L, bits) in enumerate(shapes[shape]):
+            if L not in params:
+                params[L] = vc.vc_setup(L, SEED, 0)
+            out.append((params[L], _dev_entries(I.entries(1 << L, 1000 * seed + k, bits), bits), bits))
+        return out
+
+    gex = vc.vc_exec_create(0, 2)
+    gex.set_graphs(True)
+    eex = vc.vc_exec_create(0, 2)
+    order = [("A", 71), ("A", 72), ("A", 73), ("B", 74), ("B", 75), ("A", 76)]
+    for shape, seed in order:
+        say("graph batch %s seed %d" % (shape, seed))
+        jobs = jobs_for(shape, seed)
+        got = vc.vc_commit_batch(jobs, ex=gex)
+        # other device work between replays: an eager batch, single commits, a torch op
+        ref = vc.vc_commit_batch(jobs, ex=eex)
+        x = torch.arange(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert int(x) == (1 << 20) * ((1 << 20) - 1) // 2
+        for g, r, (pp, m, bits) in zip(got, ref, jobs):
+            one = vc.vc_commit(pp, m, bits)
+            assert g.C == r.C == one.C and g.export("Cj") == r.export("Cj") == one.export("Cj")
+    caps, reps = gex.graph_stats()
+    assert reps == len(order) and caps == 3, (caps, reps)  # A, B, then A again
+    assert eex.graph_stats() == (0, 0)
+    gex.set_graphs(False)
