@@ -295,9 +295,12 @@ def run_workload(V, torch, L, b, bits, seed, steps, warmup, profile="all"):
     return limbs, commit_ms, open_ms, prof, wall
 
 
-# (executors, streams per executor, jobs per fused group) of the batched-jobs runs: group 1 is
-# one job per executor (vc_open_all_batch), larger groups fuse the jobs of one size
-BATCH_SETUPS = ((8, 2, 1), (16, 1, 1), (16, 1, 64), (8, 2, 64))
+# (executors, streams per executor, jobs per fused group[, ahead threshold]) of the batched-jobs
+# runs: group 1 is one job per executor (vc_open_all_batch), larger groups fuse the jobs of one
+# size; a threshold set on the executors overrides the library's choice (0: every Step 1 round
+# direct; 4096: terms taken one round ahead up to 4096 batch-index pairs, the one-job default;
+# fused groups sharing the device run direct unless one is set)
+BATCH_SETUPS = ((8, 2, 1), (16, 1, 1), (16, 1, 1, 0), (16, 1, 64), (16, 1, 64, 4096), (8, 2, 64))
 
 
 def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=PEAK_MAD_TOPS):
@@ -376,8 +379,13 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=
     log("batched jobs: sequential %.1f ms" % seq_ms)
     res = {"jobs": n_jobs, "L_counts": {str(L): Ls.count(L) for L in sorted(set(Ls))},
            "proofs": sum(pp.N for pp, _, _ in jobs), "sequential_ms": round(seq_ms, 2), "batch_ms": {}}
-    for ne, ns, g in setups:
+    for st_ in setups:
+        ne, ns, g = st_[:3]
         execs = [V.vc_exec_create(0, ns) for _ in range(ne)]
+        thr = st_[3] if len(st_) > 3 else None
+        for ex in execs:
+            if thr is not None:
+                ex.set_ahead(thr)
         best, out = None, None
         for _ in range(reps + 1):  # the first pass sizes every executor's workspace
             t0 = time.perf_counter()
@@ -389,14 +397,17 @@ def batched_jobs(V, torch, n_jobs=64, seed=5, setups=BATCH_SETUPS, reps=2, peak=
                 if V.vc_proof_get(a, i) != V.vc_proof_get(r, i):
                     raise RuntimeError("batched proof %d of a 2^%d job differs from the one-job call" % (i, pp.log_n))
         del out, execs
-        key = "%dx%d" % (ne, ns) + ("" if g == 1 else "_g%d" % g)
+        key = "%dx%d" % (ne, ns) + ("" if g == 1 else "_g%d" % g) + \
+            ("" if thr is None else "_direct" if thr == 0 else "_ahead%d" % thr)
         res["batch_ms"][key] = round(best, 2)
-        log("batched jobs: %d executors x %d streams, groups of %d: %.1f ms" % (ne, ns, g, best))
+        log("batched jobs: %d executors x %d streams, groups of %d%s: %.1f ms"
+            % (ne, ns, g, "" if thr is None else " (ahead threshold %d)" % thr, best))
     k_best = min(res["batch_ms"], key=lambda k: res["batch_ms"][k])
     res["speedup"] = round(seq_ms / res["batch_ms"][k_best], 2)
     res["best_setup"] = k_best
     pool = min((v for k, v in res["batch_ms"].items() if "_g" not in k), default=None)
     fused = min((v for k, v in res["batch_ms"].items() if "_g" in k), default=None)
+    res["ahead_vs_direct_ms"] = {k: v for k, v in res["batch_ms"].items() if k.startswith("16x1")}
     res["commit_ms"] = {"sequential": round(seq_c_ms, 2), "batched": round(bat_c_ms, 2),
                         "batched_graph": round(gra_c_ms, 2), "graph_captures_replays": list(graph_stats),
                         "speedup": round(seq_c_ms / min(bat_c_ms, gra_c_ms), 2), "msm_tuning_s": round(tune_s, 2)}
@@ -683,6 +694,7 @@ def main():
     ap.add_argument("--batch-only", type=str, default="", metavar="SETUPS",
                     help="only run the batched-jobs comparison with these executors x streams[ x group] "
                          "setups (e.g. 4x6,16x1,16x1x64) and print its JSON")
+    ap.add_argument("--batch-direct", action="store_true", help="with --batch-only: every Step 1 round direct")
     ap.add_argument("--serve-only", action="store_true", help="only run the serving-loop comparison")
     ap.add_argument("--only", choices=("verify_all", "eval", "subarrays"), default=None,
                     help="only run this extra measurement and print its JSON (for profiling)")
@@ -740,6 +752,8 @@ def main():
         return
     if a.batch_only:
         setups = [tuple(int(v) for v in x.split("x")) + ((1,) if x.count("x") == 1 else ()) for x in a.batch_only.split(",")]
+        if a.batch_direct:
+            setups = [s_ + (0,) for s_ in setups]
         print(json.dumps(batched_jobs(V, torch, setups=setups)), flush=True)
         return
 

@@ -160,6 +160,13 @@ void vc_exec_free(vc_exec *ex);
  * the same as without graphs.  Turning graphs off releases the graph.  Not while profiling
  * (then the chain runs eagerly).  vc_exec_graph_stats: stats[0] captures, stats[1] replays. */
 int vc_exec_set_graphs(vc_exec *ex, int on);
+
+/* Step 1 scheduling of open-alls on executor ex (§3 Eq. (folding), Protocol 1 Step 1): their
+ * rounds take the next round's terms one round ahead (shorter dependent chain, about four times
+ * the Miller loops) while batches x K <= max_pairs, and run direct (the paper's order) above
+ * it; the default is 4096.  0 makes every round direct.  Results are the same either way; the
+ * footprint reported by vc_open_all_footprint assumes the default. */
+int vc_exec_set_ahead(vc_exec *ex, uint64_t max_pairs);
 int vc_exec_graph_stats(const vc_exec *ex, uint64_t stats[2]);
 
 /* vc_open_all (Protocol 1, §4.2) on executor ex (of the params' device) instead of the
@@ -185,8 +192,10 @@ int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitme
  * step of every job's batches (round 1's G_T parts are computed once per job); Step 2 runs
  * job after job on a side stream.  Each outs[i] holds the same bytes as vc_open_all of job
  * i alone.  At most nexec groups run at a time (largest first), one per executor; a group
- * takes workspace for all its batches.  A failure in any job (including a zero challenge,
- * VC_ECHALLENGE) fails the call: every outs[i] is NULL.  max_group = 1 is
+ * takes workspace for all its batches.  When more than one group runs at a time, groups of
+ * several jobs run every Step 1 round direct (measured faster on a shared device), unless
+ * the executor's schedule was set with vc_exec_set_ahead.  A failure in any job (including a
+ * zero challenge, VC_ECHALLENGE) fails the call: every outs[i] is NULL.  max_group = 1 is
  * vc_open_all_batch. */
 int vc_open_all_grouped(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms,
                         const uint32_t *bs, uint32_t max_group, uint32_t nexec, vc_exec *const *exs,

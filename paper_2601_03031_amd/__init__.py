@@ -66,6 +66,7 @@ def lib():
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
         L.vc_exec_set_graphs.argtypes = [vp, C.c_int]
+        L.vc_exec_set_ahead.argtypes = [vp, u64]
         L.vc_exec_graph_stats.argtypes = [vp, vp]
         L.vc_open_all_ex.argtypes = [vp, vp, u32, vp, vp, C.POINTER(vp)]
         L.vc_open_all_footprint.argtypes = [vp, u32, C.POINTER(u64)]
@@ -278,6 +279,10 @@ class Exec(_Handle):
     def set_graphs(self, on: bool = True) -> None:
         """Capture and replay batched commits on this executor as HIP graphs."""
         _check(lib().vc_exec_set_graphs(self.ptr, 1 if on else 0), "vc_exec_set_graphs")
+
+    def set_ahead(self, max_pairs: int) -> None:
+        """Take Step 1's terms one round ahead while batches x K <= max_pairs (0: never)."""
+        _check(lib().vc_exec_set_ahead(self.ptr, max_pairs), "vc_exec_set_ahead")
 
     def graph_stats(self) -> tuple:
         """(captures, replays) of batched-commit graphs on this executor."""

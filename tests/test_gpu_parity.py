@@ -229,6 +229,28 @@ def test_zero_challenge_is_reported(vc, L, b):
     assert [vc.vc_proof_get(again, i) for i in (0, N - 1)] == want
 
 
+@pytest.mark.parametrize("L,b", [(8, 16), (10, 3), (12, 1), (16, 256)])
+def test_direct_rounds_equal_rounds_ahead(vc, L, b):
+    """Step 1 with every round direct (an executor with vc_exec_set_ahead(0): the paper's
+    order) gives the same bytes as the default schedule, which takes terms one round ahead
+    at these sizes (Eq. (folding): the lookahead only regroups the same pairings)."""
+    say("direct rounds: L=%d b=%d" % (L, b))
+    pp = vc.vc_setup(L, SEED, 0)
+    N = 1 << L
+    cm = vc.vc_commit(pp, dev_entries(I.entries(N, 90 + L)), 256)
+    ref = vc.vc_open_all(pp, cm, b)
+    ex = vc.vc_exec_create(0, 6)
+    ex.set_ahead(0)
+    got = vc.vc_open_all_ex(pp, cm, b, ex)
+    for k in range((pp.K + b - 1) // b):
+        for w in ("fc_x", "fc_rounds", "fc_tail"):
+            assert got.export(w, k) == ref.export(w, k), (w, k)
+    for w in ("merkle", "rho", "y", "D", "W"):
+        assert got.export(w) == ref.export(w), w
+    for i in (0, N // 2 + 1, N - 1):
+        assert vc.vc_proof_get(got, i) == vc.vc_proof_get(ref, i), i
+
+
 def sample_indices(N, M, b, seed, extra=()):
     """edges of the first and last batch and block, plus seeded random positions"""
     rng = np.random.default_rng(seed)
