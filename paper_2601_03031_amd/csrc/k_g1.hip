@@ -2,7 +2,7 @@
 #include "kcommon.hpp"
 
 #define MSM_MAXE 8192
-#define MSM_G2_MAXE 1024  // S nwin for the G2 MSM (its 256 Jacobian G2 points take 48 KB of LDS)
+#define MSM_G2_MAXE 8192  // S nwin for the G2 MSM (with its 256 Jacobian G2 points, 48 KB, 82 KB of LDS)
 
 // weights of the Lagrange keys at every level: node n = 2^k - 1 + c holds eq_k(c; s)
 __global__ void __launch_bounds__(TPB) k_ek_weights(uint32_t lM, const fe *s, fe *w, uint64_t n_total) {

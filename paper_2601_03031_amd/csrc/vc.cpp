@@ -184,8 +184,12 @@ static constexpr uint64_t FOLD_SPLIT_MAX = 256;
 // direct-round Miller loops and G2 folds of at least this many (batch, index) pairs run on the
 // wide layout (8 lanes per element, throughput), smaller ones on the engine (latency)
 static constexpr uint64_t WIDE_FOLD_MIN = 4096;
-// bases per block of the KZG proof's G2 MSM (times 32 windows: at most 1024 entries)
-static constexpr uint32_t KZG_S = 32;
+// bases per block of the KZG proof's G2 MSM (times 32 windows: at most 8192 digits): long
+// slices when the MSMs of all batches give at least KZG_LONG_MIN_BLOCKS blocks (the bucket
+// reduction, about 2300 G2 additions per block, is then spread over eight times the digits),
+// short ones otherwise (more blocks, shorter chains, for few batches)
+static constexpr uint32_t KZG_S = 32, KZG_S_LONG = 256;
+static constexpr uint64_t KZG_LONG_MIN_BLOCKS = 512;
 // KZG proofs of at most this many split jobs (4 per term) run as split multiplications
 // instead of the MSM: when the device is nearly idle the shorter chain wins
 static constexpr uint64_t KZG_SPLIT_MAX = 8192;
@@ -1028,7 +1032,8 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
   // KZG proof: split terms (4 partial results per term) or, with many terms, canonical
   // quotient coefficients and the per-block partial sums of its MSM
   const bool kzg_split = 4 * nb * nq <= KZG_SPLIT_MAX;
-  const uint64_t kzg_nslice = (nq + KZG_S - 1) / KZG_S, kzg_len = kzg_split ? 4 * nq : kzg_nslice;
+  const uint32_t kzg_s = nb * ((nq + KZG_S_LONG - 1) / KZG_S_LONG) >= KZG_LONG_MIN_BLOCKS ? KZG_S_LONG : KZG_S;
+  const uint64_t kzg_nslice = (nq + kzg_s - 1) / kzg_s, kzg_len = kzg_split ? 4 * nq : kzg_nslice;
   size_t o_Qc = t.take<fe>(nb * nq), o_S2 = t.take<g2_jac>(nb * kzg_len), o_HS = t.take<g1_jac>(with2 * G * lM * (M / 2));
   size_t o_J = t.take<S2Job>(with2 * G);  // Step 2's job table
   size_t o_dec = t.take<glv::Dec>(nb);
@@ -1395,7 +1400,7 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
     ks::kzg_terms_split(pp->h, pp->hm, Q, K, nb, S2, st);
   } else {
     kl::fr_canon(Q, nb * nq, Qc, st);
-    kl::msm_slices_g2(Qc, nb, nq, NWIN, KZG_S, pp->htab, S2, st);
+    kl::msm_slices_g2(Qc, nb, nq, NWIN, kzg_s, pp->htab, S2, st);
   }
   ks::g2_tree(S2, nb, kzg_len, kzg_len, cnt_kzg, st);
   kl::g2_to_aff(S2, kzg_len, nb, piv, 1, st);
