@@ -19,7 +19,13 @@
 #define HD __host__ __device__
 #define DEV __host__ __device__ __forceinline__
 // large routines are kept out of line so every kernel does not carry its own copy
+#ifdef VC_WIDE
+// (the 8-lane kernels hold a few registers per element: their helpers are inlined, so that
+// operands passed by reference stay in registers instead of going through scratch memory)
+#define NOINL __host__ __device__ __forceinline__
+#else
 #define NOINL __host__ __device__ __attribute__((noinline))
+#endif
 
 struct FpP {
   static constexpr const uint32_t *M = bn::P_MOD;

@@ -13,6 +13,7 @@
 #include "pairing.hpp"
 #include "kernels.h"
 #include "oa_terms.hpp"
+#include "gls.hpp"
 
 #define TPBW 64
 #define GPB (TPBW / 8)  // groups (elements) per block
@@ -61,9 +62,35 @@ __device__ __forceinline__ bool scalar_is_zero(const uint32_t k[8]) {
   return t == 0;
 }
 
-// scalar multiplication by a canonical scalar: GLV split on G1, fixed windows on G2
+// k P on G2 with the 4-dimensional split k = sum_j k_j lam^j (psi = the twisted Frobenius
+// acts as lam = p mod r): bases B_j = sign(k_j) psi^j(P), a table of the 15 nonzero subset
+// sums (Jacobian), then one doubling and at most one addition per bit of max |k_j| (65 bits)
+__device__ __forceinline__ g2_jac g2_mul_gls(const g2_aff &P, const gls::Dec &d) {
+  if (aff_is_inf(P) || d.nbits == 0) return jac_inf<OpsG2>();
+  g2_aff B[4];
+  B[0] = P;
+  for (int j = 1; j < 4; j++) B[j] = g2_frobenius(B[j - 1]);
+  for (int j = 0; j < 4; j++)
+    if (d.neg >> j & 1) B[j] = aff_neg(B[j]);
+  g2_jac T[16];
+  T[0] = jac_inf<OpsG2>();
+  for (int e = 1; e < 16; e++) {
+    const int j = __builtin_ctz(e);  // the lowest set bit: T[e] = T[e without it] + B_j
+    T[e] = (e & (e - 1)) ? jac_madd(T[e & (e - 1)], B[j]) : jac_from_aff(B[j]);
+  }
+  int t = (int)d.nbits - 1;
+  g2_jac acc = T[gls::digit(d, (uint32_t)t)];
+  for (t = t - 1; t >= 0; t--) {
+    acc = jac_dbl(acc);
+    uint32_t dg = gls::digit(d, (uint32_t)t);
+    if (dg) acc = jac_add(acc, T[dg]);
+  }
+  return acc;
+}
+
+// scalar multiplication by a canonical scalar: GLV split on G1, GLS split on G2
 __device__ __forceinline__ g1_jac mul_any(const g1_aff &P, const uint32_t kk[8]) { return g1_mul_glv(P, glv::decompose(kk)); }
-__device__ __forceinline__ g2_jac mul_any(const g2_aff &P, const uint32_t kk[8]) { return scalar_mul(P, kk); }
+__device__ __forceinline__ g2_jac mul_any(const g2_aff &P, const uint32_t kk[8]) { return g2_mul_gls(P, gls::decompose(kk)); }
 
 // ---------------------------------------------------------------- scalar multiplications
 template <class O>
