@@ -19,9 +19,10 @@
 #define HD __host__ __device__
 #define DEV __host__ __device__ __forceinline__
 // large routines are kept out of line so every kernel does not carry its own copy
-#ifdef VC_WIDE
+#if defined(VC_WIDE) || defined(VC_INLINE_HELPERS)
 // (the 8-lane kernels hold a few registers per element: their helpers are inlined, so that
-// operands passed by reference stay in registers instead of going through scratch memory)
+// operands passed by reference stay in registers instead of going through scratch memory;
+// a one-lane file may ask for the same)
 #define NOINL __host__ __device__ __forceinline__
 #else
 #define NOINL __host__ __device__ __attribute__((noinline))

@@ -1,4 +1,7 @@
 // Kernels: G1: setup keys, commitment MSM, fold of A, fold tree, HyperEval, encoding.
+// (the curve helpers are inlined here: passed by reference to out-of-line calls, the MSM's
+// points went through scratch memory)
+#define VC_INLINE_HELPERS 1
 #include "kcommon.hpp"
 
 #define MSM_MAXE 8192
@@ -130,8 +133,11 @@ __device__ __forceinline__ void msm_slice(const fe *scal, uint64_t M, uint32_t n
   __shared__ uint32_t cnt[256];
   __shared__ uint32_t off[256];
   constexpr uint32_t MAXE = sizeof(typename O::T) > sizeof(fe) ? MSM_G2_MAXE : MSM_MAXE;
-  __shared__ uint32_t ent[MAXE];
-  __shared__ jac<O> red[256];
+  // the sorted digits and, once the buckets are summed, the bucket sums share one array
+  constexpr size_t ENT_B = MAXE * sizeof(uint32_t), RED_B = 256 * sizeof(jac<O>);
+  __shared__ __align__(16) uint8_t pool[ENT_B > RED_B ? ENT_B : RED_B];
+  uint32_t *ent = reinterpret_cast<uint32_t *>(pool);
+  jac<O> *red = reinterpret_cast<jac<O> *>(pool);
   uint32_t nslice = (uint32_t)((M + S - 1) / S);
   uint64_t j = blk / nslice;
   uint32_t sl = blk % nslice;
@@ -167,6 +173,7 @@ __device__ __forceinline__ void msm_slice(const fe *scal, uint64_t M, uint32_t n
   jac<O> acc = jac_inf<O>();
   for (uint32_t q = 0; q < len; q++) acc = jac_madd(acc, table[ent[start + q]]);
   if (t == 0) acc = jac_inf<O>();
+  __syncthreads();  // every bucket is summed before the sums overwrite the digits
   red[t] = acc;
   __syncthreads();
   // suffix sums T_d = sum_{d' >= d} B_{d'}
