@@ -356,6 +356,13 @@ void vc_test_zero_challenge(uint32_t round);
  * inputs, for checking the layout's output range. */
 int vc_diag_field(int which, int op, uint64_t n, const void *a, const void *b, void *out);
 
+/* Diagnostic: the y-tree passes of Step 2 (the randomized folding tree, Protocol 1 Step 2
+ * Eq. ProverRand; all weights rho_j = 1) over commitment cm's entries, alone on the device:
+ * writes the best of five timed runs (after a warm-up), in milliseconds, to ms.  Their
+ * algorithmic traffic is 32 (N + (2K - 1) M) bytes (the entries read once, every node written
+ * once), for an HBM throughput figure free of the concurrent Step 1 kernels. */
+int vc_diag_fold(const vc_commitment *cm, double *ms);
+
 /* Diagnostic: measured throughput of the 32 x 32 -> 64-bit multiply-add on `device`, in
  * 10^12 multiply-adds per second (best of five timed launches of a probe kernel that keeps
  * every SIMD busy with independent chains).  The roofline's ALU peak. */

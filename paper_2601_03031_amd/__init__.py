@@ -62,6 +62,7 @@ def lib():
         L.vc_commit_batch.argtypes = [u32, C.POINTER(vp), C.POINTER(vp), C.POINTER(u32), vp, vp, C.POINTER(vp), vp]
         L.vc_tune_msm.argtypes = [C.c_int, u32, u32, C.c_char_p]
         L.vc_tune_load.argtypes = [C.c_char_p]
+        L.vc_diag_fold.argtypes = [vp, C.POINTER(C.c_double)]
         L.vc_diag_mad_rate.argtypes = [C.c_int, C.POINTER(C.c_double)]
         L.vc_exec_create.argtypes = [C.c_int, u32, C.POINTER(vp)]
         L.vc_exec_free.argtypes = [vp]
@@ -468,6 +469,13 @@ def vc_proof_get(pr: Proofs, i: int) -> bytes:
 def vc_verify(pp: Params, C_bytes: bytes, b: int, i: int, m_i: int, proof: bytes) -> int:
     return _check(lib().vc_verify(pp.ptr, C_bytes, pp.N, b, i, int(m_i).to_bytes(32, "little"), proof, len(proof)),
                   "vc_verify")
+
+
+def vc_diag_fold(cm) -> float:
+    """Milliseconds of the y-tree passes over cm's entries, alone on the device."""
+    ms = C.c_double(0)
+    _check(lib().vc_diag_fold(cm.ptr, C.byref(ms)), "vc_diag_fold")
+    return ms.value
 
 
 def vc_diag_mad_rate(device: int = 0) -> float:

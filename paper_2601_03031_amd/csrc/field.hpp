@@ -278,9 +278,18 @@ DEV uint64_t approx(const fe &a, int n) {
   uint64_t lo = a.l[0] & 0x3fffffffu;
   if (n <= 64) return (uint64_t)a.l[0] | ((uint64_t)a.l[1] << 32);
   int s = n - 34, w = s >> 5, sh = s & 31;
-  uint64_t v = (uint64_t)a.l[w] >> sh;
-  if (w + 1 < 8) v |= (uint64_t)a.l[w + 1] << (32 - sh);
-  if (w + 2 < 8 && sh > 30) v |= (uint64_t)a.l[w + 2] << (64 - sh);
+  // words w, w + 1, w + 2 (zero past the top) picked by selects: an index into the limbs
+  // would put the element in scratch memory
+  uint32_t a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    a0 = i == w ? a.l[i] : a0;
+    a1 = i == w + 1 ? a.l[i] : a1;
+    a2 = i == w + 2 ? a.l[i] : a2;
+  }
+  uint64_t v = (uint64_t)a0 >> sh;
+  v |= (uint64_t)a1 << (32 - sh);
+  if (sh > 30) v |= (uint64_t)a2 << (64 - sh);
   return lo | ((v & 0x3ffffffffull) << 30);
 }
 

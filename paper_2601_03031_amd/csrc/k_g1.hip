@@ -284,42 +284,67 @@ __global__ void __launch_bounds__(TPB) k_oa_init(const g1_aff *Cj, const g2_aff 
 }
 
 // Several levels of the y-tree (fold rows, canonical F_r) in one pass: thread (g, a) takes
-// the 2^s nodes g 2^s .. (g + 1) 2^s - 1 of level h0 in column a (at level 0 their values
+// the 2^S nodes g 2^S .. (g + 1) 2^S - 1 of level h0 in column a (at level 0 their values
 // y[0][j][a] = rho_j m[jM + a], written out first: the Montgomery product of a
 // Montgomery-form rho with a canonical m is the canonical product) and writes their sums at
-// levels h0 + 1 .. h0 + s.  Consecutive threads take
-// consecutive columns, so every row access is coalesced; the entries are read once and
+// levels h0 + 1 .. h0 + S.  The nodes are taken left to right with one pending left sibling
+// per level (a binary counter: S + 1 live elements); the steps are expanded at compile time
+// (ystep), so every index is fixed and nothing goes to scratch memory.  Consecutive threads
+// take consecutive columns, so every row access is coalesced; the entries are read once and
 // every node is written once.
+struct YCtx {
+  const fe *m, *rho;
+  fe *Y;
+  uint64_t M, K, g, a, in;
+  uint32_t h0;
+};
+
+// node Q has reached level h0 + L: keep it as a left child, or add it to its left sibling and
+// write the parent at level h0 + L + 1, then carry on upward
+template <int S, int Q, int L>
+__device__ __forceinline__ void ycarry(const YCtx &c, fe (&pend)[S], fe cur) {
+  if constexpr (L < S) {
+    if constexpr (((Q >> L) & 1) == 0) {
+      pend[L] = cur;
+    } else {
+      cur = fr_add(pend[L], cur);
+      const uint64_t out = 2 * c.K - ((2 * c.K) >> (c.h0 + L + 1));
+      c.Y[(out + (c.g << (S - L - 1)) + (Q >> (L + 1))) * c.M + c.a] = cur;
+      ycarry<S, Q, L + 1>(c, pend, cur);
+    }
+  }
+}
+
+template <int S, int Q>
+__device__ __forceinline__ void ystep(const YCtx &c, fe (&pend)[S]) {
+  if constexpr (Q < (1 << S)) {
+    const uint64_t node = (c.g << S) + Q;
+    fe cur;
+    if (c.h0 == 0) {
+      cur = fr_mul(c.rho[node], c.m[node * c.M + c.a]);
+      c.Y[node * c.M + c.a] = cur;
+    } else {
+      cur = c.Y[(c.in + node) * c.M + c.a];
+    }
+    ycarry<S, Q, 0>(c, pend, cur);
+    ystep<S, Q + 1>(c, pend);
+  }
+}
+
 template <int S>
 __global__ void __launch_bounds__(TPB) k_ytree(const S2Job *J, uint32_t G, uint64_t M, uint64_t K, uint32_t h0) {
   const uint64_t groups = (K >> h0) >> S;
   uint64_t id = gtid();
   if (id >= G * groups * M) return;
   const S2Job &jb = J[id / (groups * M)];  // each job's threads in turn
-  const fe *m = jb.m, *rho = jb.rho;
-  fe *Y = jb.Y;
   id %= groups * M;
-  const uint64_t g = id / M, a = id % M;
-  fe v[1 << S];
-  const uint64_t in = 2 * K - ((2 * K) >> h0);  // first row of level h0
-#pragma unroll
-  for (int q = 0; q < (1 << S); q++) {
-    const uint64_t node = (g << S) + q;
-    if (h0 == 0) {
-      v[q] = fr_mul(rho[node], m[node * M + a]);
-      Y[node * M + a] = v[q];
-    } else {
-      v[q] = Y[(in + node) * M + a];
-    }
-  }
-#pragma unroll
-  for (int l = 1; l <= S; l++) {
-    const uint64_t out = 2 * K - ((2 * K) >> (h0 + l));
-#pragma unroll
-    for (int q = 0; q < (1 << (S - l)); q++) {
-      v[q] = fr_add(v[2 * q], v[2 * q + 1]);
-      Y[(out + (g << (S - l)) + q) * M + a] = v[q];
-    }
+  YCtx c{jb.m, jb.rho, jb.Y, M, K, id / M, id % M, 2 * K - ((2 * K) >> h0), h0};
+  fe pend[S > 0 ? S : 1];
+  if constexpr (S == 0) {
+    // level 0 alone (K = 1): the rows of the nodes
+    c.Y[c.g * M + c.a] = fr_mul(c.rho[c.g], c.m[c.g * M + c.a]);
+  } else {
+    ystep<S, 0>(c, pend);
   }
 }
 
