@@ -1,4 +1,7 @@
 // Kernels: transcript and Merkle hashing, batching coefficients, KZG quotient.
+// (helpers inlined: out of line, the SHA-256 state and message blocks passed by reference went
+// through scratch memory)
+#define VC_INLINE_HELPERS 1
 #include "kcommon.hpp"
 
 #define FC_CHUNK 32

@@ -135,17 +135,61 @@ __global__ void __launch_bounds__(TPBW) kw_oa_fold_g1(const void *Ain, const voi
   wst(Bout, k * K + i, b);
 }
 
-// Miller values of the direct rounds (the pairs of L_j and R_j, laid out as by ks_oa_miller) on
-// the wide layout, for rounds whose batches fill the device; each value differs from the
-// engine's only by factors the final exponentiation removes
+// Miller values of the direct rounds on the wide layout, for rounds whose batches fill the
+// device: the pairs of L_j (side 0: A[h + i] with V[i]) and R_j (side 1: A[i] with V[h + i]),
+// C consecutive pairs per 8-lane group sharing one accumulator (one F_p12 squaring per step for
+// the C pairs, each pair's lines multiplied in turn).  Product ch of batch k, side s goes to
+// F[(2k + s) K/2 + ch], ch < h / C; it is the product of the C pairs' Miller values, which
+// differ from the engine's only by factors the final exponentiation removes.
+template <int C>
 __global__ void __launch_bounds__(TPBW) kw_oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h,
                                                     void *F) {
+  const uint64_t nch = h / C;
   uint64_t id = wgid();
-  if (id >= nb * 2 * h) return;
-  uint64_t k = id / (2 * h), r = id % (2 * h), side = r / h, i = r % h;
-  g1_aff P = wld<g1_aff>(A, side ? k * K + i : k * K + h + i);
-  g2_aff Q = wld<g2_aff>(V, side ? k * K + h + i : k * K + i);
-  wst(F, (k * 2 + side) * (K / 2) + i, miller_loop(P, Q));
+  if (id >= nb * 2 * nch) return;
+  uint64_t k = id / (2 * nch), r = id % (2 * nch), side = r / nch, ch = r % nch;
+  g1_aff P[C];
+  g2_aff Q[C];
+  proj2 T[C];
+  bool live[C];
+#pragma unroll
+  for (int c = 0; c < C; c++) {
+    const uint64_t i = ch * C + c;
+    P[c] = wld<g1_aff>(A, side ? k * K + i : k * K + h + i);
+    Q[c] = wld<g2_aff>(V, side ? k * K + h + i : k * K + i);
+    live[c] = !aff_is_inf(P[c]) && !aff_is_inf(Q[c]);  // a pair with the identity contributes 1
+    T[c] = {Q[c].x, Q[c].y, f2_one()};
+  }
+  fp12 f = f12_one();
+  fp2 l0, l1, l2;
+  for (int i = 63; i >= 0; i--) {
+    if (i != 63) f = f12_sqr(f);
+#pragma unroll
+    for (int c = 0; c < C; c++)
+      if (live[c]) {
+        miller_dbl(T[c], P[c].x, P[c].y, l0, l1, l2);
+        f = f12_mul_line(f, l0, l1, l2);
+      }
+    if ((bn::ATE_LOOP >> i) & 1) {
+#pragma unroll
+      for (int c = 0; c < C; c++)
+        if (live[c]) {
+          miller_add(T[c], Q[c], P[c].x, P[c].y, l0, l1, l2);
+          f = f12_mul_line(f, l0, l1, l2);
+        }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; c++)
+    if (live[c]) {
+      g2_aff Q1 = g2_frobenius(Q[c]);
+      g2_aff Q2 = aff_neg(g2_frobenius(Q1));
+      miller_add(T[c], Q1, P[c].x, P[c].y, l0, l1, l2);
+      f = f12_mul_line(f, l0, l1, l2);
+      miller_add(T[c], Q2, P[c].x, P[c].y, l0, l1, l2);
+      f = f12_mul_line(f, l0, l1, l2);
+    }
+  wst(F, (k * 2 + side) * (K / 2) + ch, f);
 }
 
 // v_j = v_L o v_R^{1/x_j} (Eq. folding) on the wide layout: the direct rounds, where the batches
@@ -334,8 +378,16 @@ void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const 
                 uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st) {
   LW(kw_oa_fold_g1, nb * h, Ain, Bin, Aout, Bout, Xinv, static_cast<const glv::Dec *>(dec), K, nb, h, j, lK);
 }
-void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st) {
-  LW(kw_oa_miller, nb * 2 * h, A, V, K, nb, h, F);
+uint64_t oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st) {
+  // two pairs per product when the round has pairs enough to keep the device full with half
+  // as many groups (2^20, b = 1: 886 -> 810 ms); fewer pairs keep one pair per group, whose
+  // parallelism they need (2^16, b = 1: 93 ms with one, 104 with two)
+  if (nb * 2 * h >= (1ull << 18) && h >= 2) {
+    LW(kw_oa_miller<2>, nb * 2 * (h / 2), A, V, K, nb, h, F);
+    return h / 2;
+  }
+  LW(kw_oa_miller<1>, nb * 2 * h, A, V, K, nb, h, F);
+  return h;
 }
 void oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
                 uint32_t lK, hipStream_t st) {

@@ -126,7 +126,9 @@ void g2_mul(const void *P, int bc, const void *k, uint64_t n, void *out, hipStre
 void oa_g1terms(const void *A, const void *B, uint64_t K, uint64_t nb, uint64_t h, void *S, hipStream_t st);
 void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const void *Xinv, const void *dec, uint64_t K,
                 uint64_t nb, uint64_t h, uint32_t j, uint32_t lK, hipStream_t st);
-void oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st);
+// the direct rounds' Miller values, several pairs per product: returns the products per batch
+// and side (stride K/2), the length of the F_p12 tree that follows
+uint64_t oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st);
 void oa_fold_g2(const void *Vin, void *Vout, const void *Xinv, uint64_t K, uint64_t nb, uint64_t h, uint32_t j,
                 uint32_t lK, hipStream_t st);
 // HyperEval terms of every job's g* (the root row of its y-tree): level d of job x at

@@ -1308,7 +1308,8 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
       // and copied to the job's batches
       const uint64_t nbm = j == 1 ? G : nb;
       const g1_aff *Am = j == 1 ? CjG : Ab[cur];
-      if (nbm * h >= WIDE_FOLD_MIN) klw::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
+      uint64_t nprod = h;  // Miller products per batch and side, reduced by the tree below
+      if (nbm * h >= WIDE_FOLD_MIN) nprod = klw::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       else ks::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
       // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
@@ -1330,7 +1331,7 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
         }
         if (int rc2 = launch_g1terms(j0)) return rc2;
       }
-      ks::f12_reduce(F, 2 * nbm, K / 2, h, cnt_dir, st);
+      ks::f12_reduce(F, 2 * nbm, K / 2, nprod, cnt_dir, st);
       if (j == 1) {
         ks::final_exp(F, K / 2, 2 * nbm, LT, RT, 1, st);
         kl::bcast_round1(LT, RT, nb, nbj, lK, Lgt, Rgt, st);
