@@ -658,6 +658,9 @@ def fe_programs():
     mk("f12_mul", lambda X, Y: X.mul(Y), 2)
     mk("f12_csqr", cyclo_sqr, 1)
     mk("f12_csqr_mul", lambda X, Y: cyclo_sqr(X).mul(Y), 2)
+    # (the conjugate is the inverse in the cyclotomic subgroup: its sign changes fold into
+    # the product's coefficients, so this costs the levels of f12_csqr_mul)
+    mk("f12_csqr_cmul", lambda X, Y: cyclo_sqr(X).mul(Y.conj()), 2)
     mk("f12_frob1", lambda X: frob12(X, 1), 1)
     mk("f12_frob2", lambda X: frob12(X, 2), 1)
     mk("f12_frob3", lambda X: frob12(X, 3), 1)
@@ -696,6 +699,25 @@ def fe_programs():
 UNAF = naf(U)
 
 
+def wnaf(k, w):
+    """width-w signed digits of k (odd digits |d| < 2^(w-1), most significant first)"""
+    d = []
+    while k:
+        if k & 1:
+            z = k % (1 << w)
+            if z >= 1 << (w - 1):
+                z -= 1 << w
+            k -= z
+        else:
+            z = 0
+        d.append(z)
+        k //= 2
+    return d[::-1]
+
+
+UW4 = wnaf(U, 4)
+
+
 def fe_sequence():
     """Final exponentiation f^((p^12 - 1)/r) as calls of the F_p12 programs on buffers of
     12 slots: easy part conj(f) f^{-1}, then (.)^{p^2} (.); hard part through f^u, f^{u^2},
@@ -729,17 +751,24 @@ def fe_sequence():
     release(f1)
 
     def pow_u(x):
-        xc = call("f12_conj", x)
+        # x^u over the width-4 signed digits of u (14 nonzero of 63 against 24 for the NAF):
+        # the odd powers x^3, x^5, x^7 first, a negative digit multiplies by the conjugate
+        x2 = call("f12_csqr", x)
+        tab = {1: x}
+        for e in (3, 5, 7):
+            tab[e] = call("f12_mul", tab[e - 2], x2)
+        release(x2)
+        assert UW4[0] == 1
         acc = x
-        for d in UNAF[1:]:
+        for d in UW4[1:]:
             if d == 0:
                 nxt = call("f12_csqr", acc)
             else:
-                nxt = call("f12_csqr_mul", acc, x if d == 1 else xc)
+                nxt = call("f12_csqr_mul" if d > 0 else "f12_csqr_cmul", acc, tab[abs(d)])
             if acc != x:
                 release(acc)
             acc = nxt
-        release(xc)
+        release(tab[3], tab[5], tab[7])
         return acc
 
     a = pow_u(f)
