@@ -180,8 +180,8 @@ int vc_open_all_ex(const vc_params *pp, const vc_commitment *cm, uint32_t b, vc_
  * executor exs[0..nexec) (each with its own host thread and stream); the jobs are
  * independent latency-bound chains, so several of them share the device; the largest
  * vectors are started first.  All params and
- * executors must be on one device.  Returns VC_OK, or the first error; on error every
- * outs[i] is NULL.  While profiling is enabled the jobs run one at a time. */
+ * executors must be on one device and the executors distinct (VC_EINVAL otherwise).  Returns
+ * VC_OK, or the first error; on error every outs[i] is NULL.  While profiling is enabled the jobs run one at a time. */
 int vc_open_all_batch(uint32_t n, const vc_params *const *pps, const vc_commitment *const *cms, const uint32_t *bs,
                       uint32_t nexec, vc_exec *const *exs, vc_proofs **outs);
 

@@ -276,14 +276,14 @@ static void exec_release(vc_exec *ex) {
 VC_API void vc_exec_free(vc_exec *ex) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!ex) return;
-  hipSetDevice(ex->device);
+  (void)hipSetDevice(ex->device);
   drop_graph(ex);
-  if (ex->ws) hipFree(ex->ws);
-  if (ex->cnt) hipFree(ex->cnt);
+  if (ex->ws) (void)hipFree(ex->ws);
+  if (ex->cnt) (void)hipFree(ex->cnt);
   for (auto sd : ex->own)
-    if (sd) hipStreamDestroy(sd);
+    if (sd) (void)hipStreamDestroy(sd);
   for (auto ev : ex->ev)
-    if (ev) hipEventDestroy(ev);
+    if (ev) (void)hipEventDestroy(ev);
   delete ex;
   (void)hipGetLastError();  // a release reports nothing and leaves no error behind
 }
@@ -507,8 +507,8 @@ VC_API int vc_params_load(const uint8_t *srs, size_t len, int device, vc_params 
 VC_API void vc_params_free(vc_params *pp) {
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pp) return;
-  hipSetDevice(pp->device);
-  if (pp->mem) hipFree(pp->mem);
+  (void)hipSetDevice(pp->device);
+  if (pp->mem) (void)hipFree(pp->mem);
   vc_exec_free(pp->ex);
   delete pp;
   (void)hipGetLastError();  // a release reports nothing and leaves no error behind
@@ -1464,8 +1464,12 @@ VC_API int vc_open_all_grouped(uint32_t n, const vc_params *const *pps, const vc
   (void)hipGetLastError();  // errors left by other HIP clients are not ours
   if (!pps || !cms || !bs || !exs || !outs || nexec < 1 || max_group < 1) return VC_EINVAL;
   for (uint32_t i = 0; i < n; i++) outs[i] = nullptr;
-  for (uint32_t t = 0; t < nexec; t++)
-    if (!exs[t]) return VC_EINVAL;
+  // every executor on one device and none twice (each one is driven by its own host thread)
+  for (uint32_t t = 0; t < nexec; t++) {
+    if (!exs[t] || exs[t]->device != exs[0]->device) return VC_EINVAL;
+    for (uint32_t u = 0; u < t; u++)
+      if (exs[u] == exs[t]) return VC_EINVAL;
+  }
   for (uint32_t i = 0; i < n; i++)
     if (!pps[i] || !cms[i] || cms[i]->pp != pps[i] || pps[i]->device != exs[0]->device || bs[i] < 1 ||
         bs[i] > pps[i]->K)
@@ -1779,7 +1783,7 @@ int gather(const void *base, const std::vector<uint64_t> &idx, const std::vector
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpy(outb.data(), at<void>(d, oo), n * 32, hipMemcpyDeviceToHost);
-  hipFree(d);
+  (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "gather");
   return VC_OK;
 }
@@ -2585,7 +2589,7 @@ VC_API int vc_diag_field(int which, int op, uint64_t n, const void *a, const voi
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpy(out, static_cast<char *>(d) + 2 * n * 32, n * 32, hipMemcpyDeviceToHost);
-  hipFree(d);
+  (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "vc_diag_field");
   return VC_OK;
 }
@@ -2658,9 +2662,9 @@ VC_API int vc_diag_mad_rate(int device, double *tera_per_s) {
     double mads = (double)blocks * 256.0 * 8.0 * iters;
     if (e == hipSuccess && rep > 0 && ms > 0) best = std::max(best, mads / (ms * 1e-3) / 1e12);
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  hipFree(d);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "vc_diag_mad_rate");
   *tera_per_s = best;
   return VC_OK;

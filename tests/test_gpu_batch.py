@@ -97,6 +97,10 @@ def test_batch_on_one_executor_and_errors(vc):
     with pytest.raises(vc.VCError) as e:
         vc.vc_open_all_batch([(pp, cms[0], 4)], [])
     assert e.value.code == vc.VC_EINVAL
+    say("batch with one executor given twice")
+    with pytest.raises(vc.VCError) as e:
+        vc.vc_open_all_batch([(pp, cms[0], 4), (pp, cms[1], 5)], [ex, ex])
+    assert e.value.code == vc.VC_EINVAL
     for ns in (0, 7):
         with pytest.raises(vc.VCError) as e:
             vc.vc_exec_create(0, ns)
