@@ -13,6 +13,7 @@
 #include "g2mul.hpp"
 #include "gtpow.hpp"
 #include "g1mul.hpp"
+#include "oa_terms.hpp"
 
 #define API extern "C" __attribute__((visibility("default")))
 
@@ -773,3 +774,11 @@ API uint64_t hc_count(int op) {
   return n - c;
 }
 #endif
+
+// the index map of the terms taken one round ahead (oa_terms.hpp): term id as (a, v, out)
+API void hc_oa_term(uint64_t id, uint64_t K, uint64_t nb, uint64_t q, uint64_t *out) {
+  oat::Term t = oat::term(id, K, nb, q);
+  out[0] = t.a;
+  out[1] = t.v;
+  out[2] = t.out;
+}
