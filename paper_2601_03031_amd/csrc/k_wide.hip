@@ -162,19 +162,22 @@ __global__ void __launch_bounds__(TPBW) kw_oa_miller(const void *A, const void *
   }
   fp12 f = f12_one();
   fp2 l0, l1, l2;
-  for (int i = 63; i >= 0; i--) {
-    if (i != 63) f = f12_sqr(f);
+  // over the non-adjacent form of 6u + 2 (d_65 = 1 starts T = Q; d_64 = 0): 21 additions of
+  // +-Q against 36 for the binary digits
+  for (int i = 64; i >= 0; i--) {
+    if (i != 64) f = f12_sqr(f);
 #pragma unroll
     for (int c = 0; c < C; c++)
       if (live[c]) {
         miller_dbl(T[c], P[c].x, P[c].y, l0, l1, l2);
         f = f12_mul_line(f, l0, l1, l2);
       }
-    if ((bn::ATE_LOOP >> i) & 1) {
+    const bool pos = i < 64 && ((bn::ATE_NAF_POS >> i) & 1), neg = i < 64 && ((bn::ATE_NAF_NEG >> i) & 1);
+    if (pos || neg) {
 #pragma unroll
       for (int c = 0; c < C; c++)
         if (live[c]) {
-          miller_add(T[c], Q[c], P[c].x, P[c].y, l0, l1, l2);
+          miller_add(T[c], pos ? Q[c] : aff_neg(Q[c]), P[c].x, P[c].y, l0, l1, l2);
           f = f12_mul_line(f, l0, l1, l2);
         }
     }

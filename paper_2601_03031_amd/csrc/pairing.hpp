@@ -61,13 +61,17 @@ inline NOINL fp12 miller_loop(const g1_aff &P, const g2_aff &Q) {
   fp12 f = f12_one();
   if (aff_is_inf(P) || aff_is_inf(Q)) return f;
   proj2 T = {Q.x, Q.y, f2_one()};
+  const g2_aff Qn = aff_neg(Q);
   fp2 l0, l1, l2;
-  for (int i = 63; i >= 0; i--) {
-    if (i != 63) f = f12_sqr(f);
+  // over the non-adjacent form of 6u + 2 (d_65 = 1 starts T = Q; d_64 = 0): 21 additions of
+  // +-Q against 36 for the binary digits
+  for (int i = 64; i >= 0; i--) {
+    if (i != 64) f = f12_sqr(f);
     miller_dbl(T, P.x, P.y, l0, l1, l2);
     f = f12_mul_line(f, l0, l1, l2);
-    if ((bn::ATE_LOOP >> i) & 1) {
-      miller_add(T, Q, P.x, P.y, l0, l1, l2);
+    const bool pos = i < 64 && ((bn::ATE_NAF_POS >> i) & 1), neg = i < 64 && ((bn::ATE_NAF_NEG >> i) & 1);
+    if (pos || neg) {
+      miller_add(T, pos ? Q : Qn, P.x, P.y, l0, l1, l2);
       f = f12_mul_line(f, l0, l1, l2);
     }
   }
