@@ -383,8 +383,12 @@ void oa_fold_g1(const void *Ain, const void *Bin, void *Aout, void *Bout, const 
 }
 uint64_t oa_miller(const void *A, const void *V, uint64_t K, uint64_t nb, uint64_t h, void *F, hipStream_t st) {
   // two pairs per product when the round has pairs enough to keep the device full with half
-  // as many groups (2^20, b = 1: 886 -> 810 ms); fewer pairs keep one pair per group, whose
-  // parallelism they need (2^16, b = 1: 93 ms with one, 104 with two)
+  // as many groups (2^20, b = 1: 886 -> 810 ms), four from 2^19 pairs; fewer pairs keep one
+  // pair per group, whose parallelism they need (2^16, b = 1: 93 ms with one, 104 with two)
+  if (nb * 2 * h >= (1ull << 19) && h >= 4) {
+    LW(kw_oa_miller<4>, nb * 2 * (h / 4), A, V, K, nb, h, F);
+    return h / 4;
+  }
   if (nb * 2 * h >= (1ull << 18) && h >= 2) {
     LW(kw_oa_miller<2>, nb * 2 * (h / 2), A, V, K, nb, h, F);
     return h / 2;
