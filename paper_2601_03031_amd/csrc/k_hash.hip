@@ -158,85 +158,63 @@ __global__ void __launch_bounds__(64) k_oa_transcript(const fp12 *Lgt, const fp1
 // ---------------------------------------------------------------- KZG proof of v_l
 // f_v(X) = prod_{j=1}^{l} (1 + x_j^{-1} X^{2^{l-j+1}}): only even powers X^{2s} (s < K) occur,
 // with coefficient prod over the set bits t of s of x_{l-t}^{-1}.  z = H2F(DST_FC_Z, x_l || v_l);
-// q = (f_v - f_v(z)) / (X - z) has q_m = z^{-(m+1)} sum_{i > m} c_i z^i, computed with
-// block-wide scans.  One block of KZG_T threads per batch, D = 2K - 1 coefficients.
+// q = (f_v - f_v(z)) / (X - z) has q_m = sum_{i > m} c_i z^{i-m-1} (m < D - 1), that is
+// q_m = c_{m+1} + z q_{m+1} with q_{D-1} = 0: a suffix scan whose step with offset s adds
+// z^s q[m + s] to q[m] (the multiplier z^s is the same for every element, so a step costs one
+// product and no inverse is needed).  One block of KZG_T threads per batch, D = 2K - 1.
+
+// c_{m+1}, the scan's input at m
+__device__ __forceinline__ fe kzg_coef(const fe *Xinv, uint64_t k, uint32_t lK, uint64_t m) {
+  const uint64_t i = m + 1;
+  if (i & 1) return fe_zero();
+  const uint64_t s2 = i >> 1;
+  fe c = f_one<FpR>();
+  for (uint32_t bt = 0; bt < lK; bt++)
+    if ((s2 >> bt) & 1) c = fr_mul(c, Xinv[k * lK + (lK - bt) - 1]);
+  return c;
+}
+
 __global__ void __launch_bounds__(KZG_T) k_kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K,
                                                       uint32_t lK, fe *Q, fe *zout) {
   CHAIN_PRIORITY();
-  extern __shared__ fe sh[];  // 2 * D elements
+  extern __shared__ fe sh[];  // D - 1 elements
   uint64_t k = blockIdx.x;
-  uint64_t D = 2 * K - 1;
-  fe *pw = sh, *acc = sh + D;
+  const uint64_t n = 2 * K - 2;
+  fe *acc = sh;
   __shared__ uint32_t zmsg[16 + 8 + 32 + 24], t2[16];
   uint32_t t = threadIdx.x;
-  // z = H2F(DST_FC_Z, x_l || v_l): lanes encode, every wave hashes (sha::Coop); the inverse
-  // runs on the scalar unit
+  // z = H2F(DST_FC_Z, x_l || v_l): lanes encode, every wave hashes (sha::Coop)
   if (t < 16) zmsg[t] = 0;
   if (t == 16) sha::put_words<FpR>(zmsg + 16, X[k * lK + lK - 1]);
   if (t > 16 && t <= 20) sha::put_words<FpP>(zmsg + 24 + 8 * (t - 17), reinterpret_cast<const fe *>(V + k * K)[t - 17]);
   __syncthreads();
   const fe zz = sha::xmd_fr_coop(sha::Coop{(int)t, KZG_T}, zmsg, 160, DSTR_FC_Z, t2);
-  const fe zi = f_inv_uniform<FpR>(zz, bn::R_R3);
   if (t == 0) zout[k] = zz;
-  // pw[i] = z^i via inclusive product scan of (1, z, z, ...)
-  for (uint64_t i = t; i < D; i += KZG_T) pw[i] = (i == 0) ? f_one<FpR>() : zz;
+  for (uint64_t m = t; m < n; m += KZG_T) acc[m] = kzg_coef(Xinv, k, lK, m);
   __syncthreads();
-  for (uint64_t s = 1; s < D; s <<= 1) {
+  fe zs = zz;  // z^s
+  for (uint64_t s = 1; s < n; s <<= 1) {
     fe vals[KZG_PER];
     int nv = 0;
-    for (uint64_t i = t; i < D; i += KZG_T, nv++) vals[nv] = (i >= s) ? fr_mul(pw[i], pw[i - s]) : pw[i];
+    for (uint64_t m = t; m < n; m += KZG_T, nv++) vals[nv] = (m + s < n) ? fr_add(acc[m], fr_mul(zs, acc[m + s])) : acc[m];
     __syncthreads();
     nv = 0;
-    for (uint64_t i = t; i < D; i += KZG_T, nv++) pw[i] = vals[nv];
+    for (uint64_t m = t; m < n; m += KZG_T, nv++) acc[m] = vals[nv];
     __syncthreads();
+    zs = fr_mul(zs, zs);
   }
-  // acc[i] = c_i z^i
-  for (uint64_t i = t; i < D; i += KZG_T) {
-    fe c = fe_zero();
-    if ((i & 1) == 0) {
-      uint64_t s2 = i >> 1;
-      c = f_one<FpR>();
-      for (uint32_t bt = 0; bt < lK; bt++)
-        if ((s2 >> bt) & 1) c = fr_mul(c, Xinv[k * lK + (lK - bt) - 1]);
-    }
-    acc[i] = fr_mul(c, pw[i]);
-  }
-  __syncthreads();
-  // suffix sums acc[i] = sum_{i' >= i} c_i' z^i'
-  for (uint64_t s = 1; s < D; s <<= 1) {
-    fe vals[KZG_PER];
-    int nv = 0;
-    for (uint64_t i = t; i < D; i += KZG_T, nv++) vals[nv] = (i + s < D) ? fr_add(acc[i], acc[i + s]) : acc[i];
-    __syncthreads();
-    nv = 0;
-    for (uint64_t i = t; i < D; i += KZG_T, nv++) acc[i] = vals[nv];
-    __syncthreads();
-  }
-  // pw[i] = z^{-i}
-  for (uint64_t i = t; i < D; i += KZG_T) pw[i] = (i == 0) ? f_one<FpR>() : zi;
-  __syncthreads();
-  for (uint64_t s = 1; s < D; s <<= 1) {
-    fe vals[KZG_PER];
-    int nv = 0;
-    for (uint64_t i = t; i < D; i += KZG_T, nv++) vals[nv] = (i >= s) ? fr_mul(pw[i], pw[i - s]) : pw[i];
-    __syncthreads();
-    nv = 0;
-    for (uint64_t i = t; i < D; i += KZG_T, nv++) pw[i] = vals[nv];
-    __syncthreads();
-  }
-  // q_m = z^{-(m+1)} * acc[m+1], m < D - 1
-  for (uint64_t m = t; m + 1 < D; m += KZG_T) Q[k * (D - 1) + m] = fr_mul(pw[m + 1], acc[m + 1]);
+  for (uint64_t m = t; m < n; m += KZG_T) Q[k * n + m] = acc[m];
 }
 
-// The same quotient for K > 1024, whose 2(2K - 1) working values do not fit in shared
-// memory: the scans run over global arrays (two per scan, read and written alternately),
-// with the same operations in the same order.  gws: 4 (2K - 1) elements per batch.
+// The same quotient for K > 1024, whose 2K - 2 working values do not fit in shared memory: the
+// scan runs over two global arrays, read and written alternately, with the same operations in
+// the same order.  gws: 4 (2K - 1) elements per batch.
 __global__ void __launch_bounds__(KZG_T) k_kzg_quotient_g(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K,
                                                         uint32_t lK, fe *Q, fe *zout, fe *gws) {
   CHAIN_PRIORITY();
   uint64_t k = blockIdx.x;
-  uint64_t D = 2 * K - 1;
-  fe *pa = gws + k * 4 * D, *pb = pa + D, *aa = pa + 2 * D, *ab = pa + 3 * D;
+  const uint64_t n = 2 * K - 2;
+  fe *aa = gws + k * 4 * (2 * K - 1), *ab = aa + n;
   __shared__ uint32_t zmsg[16 + 8 + 32 + 24], t2[16];
   uint32_t t = threadIdx.x;
   if (t < 16) zmsg[t] = 0;
@@ -244,43 +222,17 @@ __global__ void __launch_bounds__(KZG_T) k_kzg_quotient_g(const fe *Xinv, const 
   if (t > 16 && t <= 20) sha::put_words<FpP>(zmsg + 24 + 8 * (t - 17), reinterpret_cast<const fe *>(V + k * K)[t - 17]);
   __syncthreads();
   const fe zz = sha::xmd_fr_coop(sha::Coop{(int)t, KZG_T}, zmsg, 160, DSTR_FC_Z, t2);
-  const fe zi = f_inv_uniform<FpR>(zz, bn::R_R3);
   if (t == 0) zout[k] = zz;
-  // z^i: inclusive product scan of (1, z, z, ...)
-  for (uint64_t i = t; i < D; i += KZG_T) pa[i] = (i == 0) ? f_one<FpR>() : zz;
+  for (uint64_t m = t; m < n; m += KZG_T) aa[m] = kzg_coef(Xinv, k, lK, m);
   __syncthreads();
-  for (uint64_t s = 1; s < D; s <<= 1) {
-    for (uint64_t i = t; i < D; i += KZG_T) pb[i] = (i >= s) ? fr_mul(pa[i], pa[i - s]) : pa[i];
-    __syncthreads();
-    fe *tmp = pa; pa = pb; pb = tmp;
-  }
-  // c_i z^i
-  for (uint64_t i = t; i < D; i += KZG_T) {
-    fe c = fe_zero();
-    if ((i & 1) == 0) {
-      uint64_t s2 = i >> 1;
-      c = f_one<FpR>();
-      for (uint32_t bt = 0; bt < lK; bt++)
-        if ((s2 >> bt) & 1) c = fr_mul(c, Xinv[k * lK + (lK - bt) - 1]);
-    }
-    aa[i] = fr_mul(c, pa[i]);
-  }
-  __syncthreads();
-  // suffix sums
-  for (uint64_t s = 1; s < D; s <<= 1) {
-    for (uint64_t i = t; i < D; i += KZG_T) ab[i] = (i + s < D) ? fr_add(aa[i], aa[i + s]) : aa[i];
+  fe zs = zz;
+  for (uint64_t s = 1; s < n; s <<= 1) {
+    for (uint64_t m = t; m < n; m += KZG_T) ab[m] = (m + s < n) ? fr_add(aa[m], fr_mul(zs, aa[m + s])) : aa[m];
     __syncthreads();
     fe *tmp = aa; aa = ab; ab = tmp;
+    zs = fr_mul(zs, zs);
   }
-  // z^{-i}
-  for (uint64_t i = t; i < D; i += KZG_T) pa[i] = (i == 0) ? f_one<FpR>() : zi;
-  __syncthreads();
-  for (uint64_t s = 1; s < D; s <<= 1) {
-    for (uint64_t i = t; i < D; i += KZG_T) pb[i] = (i >= s) ? fr_mul(pa[i], pa[i - s]) : pa[i];
-    __syncthreads();
-    fe *tmp = pa; pa = pb; pb = tmp;
-  }
-  for (uint64_t m = t; m + 1 < D; m += KZG_T) Q[k * (D - 1) + m] = fr_mul(pa[m + 1], aa[m + 1]);
+  for (uint64_t m = t; m < n; m += KZG_T) Q[k * n + m] = aa[m];
 }
 
 // ================================================================ open-all, step 2
@@ -361,10 +313,10 @@ void kzg_quotient(const fe *Xinv, const fe *X, const g2_aff *V, uint64_t K, uint
     LAUNCH(k_kzg_quotient_g, dim3((unsigned)nb), dim3(KZG_T), 0, Xinv, X, V, K, lK, Q, z, gws);
     return;
   }
-  size_t shm = 2 * (2 * K - 1) * sizeof(fe);
+  size_t shm = (2 * K - 2) * sizeof(fe);
   static const bool attr_set = [] {  // once per process (thread-safe initialisation)
     (void)hipFuncSetAttribute((const void *)k_kzg_quotient, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              2 * (2 * KZG_T) * (int)sizeof(fe));
+                              (2 * KZG_T) * (int)sizeof(fe));
     return true;
   }();
   (void)attr_set;
