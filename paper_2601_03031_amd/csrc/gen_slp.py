@@ -1275,6 +1275,7 @@ class Kernel:
         head = name.split(".")[0]
         if head in self.segs:
             seg = self.segs[head]
+            assert 1 <= seg <= 3  # the interpreter packs the bases of segments 1..3 only
             off = int(name.split(".")[1])
             return (seg << 9) | off
         return self.state[name]
@@ -1386,6 +1387,7 @@ def emit(kernels):
     descs = []
     for k in kernels:
         w("// kernel %s: %d slots (%d state, %d constants)" % (k.name, k.nslots, len(k.state), len(k.consts)))
+        assert k.nslots <= 512  # absolute slots are 9-bit offsets in segment 0
         w("static constexpr int %s_NSLOT = %d;" % (k.name.upper(), k.nslots))
         w("static constexpr int %s_CBASE = %d;" % (k.name.upper(), k.cbase))
         w("static constexpr int %s_NCONST = %d;" % (k.name.upper(), len(k.consts)))
