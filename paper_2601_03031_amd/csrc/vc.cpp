@@ -139,7 +139,7 @@ struct vc_exec {
   uint32_t nown = 0;
   hipStream_t main = nullptr;
   hipStream_t side[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t ev[21] = {};
+  hipEvent_t ev[23] = {};
   uint32_t *cnt = nullptr;
   uint64_t cnt_n = 0;
   bool cnt_dirty = false;  // counters to be zeroed before the next use (new, or left by a failed call)
@@ -1217,6 +1217,17 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
   // exponentiations), side 5 their G1 side; the caller's stream combines and hashes.
   hipStream_t sg = s2, sf = ex->side[2], sfp[2] = {ex->side[2], ex->side[3]}, sq = ex->side[4];
   kl::oa_init(CjG, pp->h, K, nb, nbj, A, V, B, st);
+  // Round 1's Miller loops pair A = aux with v, which do not depend on the batching vectors b:
+  // they start on side stream 1 as soon as the arrays are set, beside the hashing of r (event 22
+  // marks them done; the round-1 multiples follow them on that stream)
+  uint64_t nprod1 = K / 2;
+  {
+    if (int rc2 = stream_wait(ex, 21, st, s1)) return rc2;
+    const uint64_t h1 = K / 2;
+    if (G * h1 >= WIDE_FOLD_MIN) nprod1 = klw::oa_miller(CjG, Vb[0], K, G, h1, F, s1);
+    else ks::oa_miller(CjG, Vb[0], K, G, h1, F, s1);
+    if (int rc2 = ev_mark(ex, 22, s1)) return rc2;
+  }
   // multiples 2^{32 m} A[i] (m = 1..3) of the whole arrays A of round j (for its split fold
   // and the split G1 terms of round j + 1) and 2^{16 m} V[h + i] of the halves V[h..) (for
   // its split fold), into set j & 1 (round 1 on side stream 1, later rounds on the fold
@@ -1309,19 +1320,23 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
       const uint64_t nbm = j == 1 ? G : nb;
       const g1_aff *Am = j == 1 ? CjG : Ab[cur];
       uint64_t nprod = h;  // Miller products per batch and side, reduced by the tree below
-      if (nbm * h >= WIDE_FOLD_MIN) nprod = klw::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
+      if (j == 1) nprod = nprod1;  // round 1's Miller loops run on side stream 1 (above)
+      else if (nbm * h >= WIDE_FOLD_MIN) nprod = klw::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       else ks::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
       // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
       if (j == 1 && split_round(1)) {
-        if (int rc2 = stream_wait(ex, 14, st, s1)) return rc2;
         launch_fold_mults(1, s1);
         if (int rc2 = ev_mark(ex, 15, s1)) return rc2;
       }
       // the terms of round j0 from the arrays of the last direct round, after its Miller
       // loops (the G1 side after the multiples of the arrays)
       if (ahead && j + 1 == j0) {
-        if (int rc2 = stream_wait(ex, 19, st, sfp[j0 & 1])) return rc2;
+        if (j == 1) {
+          if (int rc2 = ev_wait(ex, 22, sfp[j0 & 1])) return rc2;
+        } else if (int rc2 = stream_wait(ex, 19, st, sfp[j0 & 1])) {
+          return rc2;
+        }
         if (int rc2 = launch_terms(j0)) return rc2;
         if (j == 1) {
           if (split_round(1))
@@ -1331,6 +1346,8 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
         }
         if (int rc2 = launch_g1terms(j0)) return rc2;
       }
+      if (j == 1)
+        if (int rc2 = ev_wait(ex, 22, st)) return rc2;
       ks::f12_reduce(F, 2 * nbm, K / 2, nprod, cnt_dir, st);
       if (j == 1) {
         ks::final_exp(F, K / 2, 2 * nbm, LT, RT, 1, st);
