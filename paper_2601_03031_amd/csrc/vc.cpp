@@ -1219,7 +1219,7 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
   kl::oa_init(CjG, pp->h, K, nb, nbj, A, V, B, st);
   // Round 1's Miller loops pair A = aux with v, which do not depend on the batching vectors b:
   // they start on side stream 1 as soon as the arrays are set, beside the hashing of r (event 22
-  // marks them done; the round-1 multiples follow them on that stream)
+  // marks them done)
   uint64_t nprod1 = K / 2;
   {
     if (int rc2 = stream_wait(ex, 21, st, s1)) return rc2;
@@ -1237,6 +1237,14 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
     const int cur = (j - 1) & 1;
     ks::fold_mults(Ab[cur], n, nb * n, Vb[cur] + hh, hh, nb * hh, K, FM1[j & 1], FM2[j & 1], s);
   };
+  // the multiples of the round-1 arrays (for the split fold of round 1 and the split G1 terms of
+  // round 2, whose chain they start) on side stream 5 beside the round-1 Miller loops, as soon as
+  // the arrays are set (event 15 marks them done)
+  if (split_round(1)) {
+    if (int rc2 = ev_wait(ex, 21, sq)) return rc2;
+    launch_fold_mults(1, sq);
+    if (int rc2 = ev_mark(ex, 15, sq)) return rc2;
+  }
   fe *er = at<fe>(ws, o_er), *eT = at<fe>(ws, o_T), *eg = at<fe>(ws, o_eg), *eq = at<fe>(ws, o_eq);
   if (eval_r) {
     // the point, T(r_L), C_F = sum_j T_j C_j, then b = r_0 T for the one batch
@@ -1323,12 +1331,6 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
       if (j == 1) nprod = nprod1;  // round 1's Miller loops run on side stream 1 (above)
       else if (nbm * h >= WIDE_FOLD_MIN) nprod = klw::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       else ks::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
-      // the multiples of the round-1 arrays (for the split fold and the split G1 terms of
-      // round 2) on side stream 1, after the round-1 Miller loops so as not to slow them
-      if (j == 1 && split_round(1)) {
-        launch_fold_mults(1, s1);
-        if (int rc2 = ev_mark(ex, 15, s1)) return rc2;
-      }
       // the terms of round j0 from the arrays of the last direct round, after its Miller
       // loops (the G1 side after the multiples of the arrays)
       if (ahead && j + 1 == j0) {
