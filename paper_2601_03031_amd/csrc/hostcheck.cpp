@@ -302,14 +302,16 @@ API int hc_slp_lane(int op, int n, const int *k, const uint8_t *xs, uint8_t *out
     wr_raw(out, slp::from29(r));
     return 0;
   }
+  // op 0/2: one offset (a product factor); op 3/4: twice the offset (a 16-term sum whose two
+  // halves each start at it, as the interpreter's linear combinations)
   int64_t acc[9];
-  for (int j = 0; j < 9; j++) acc[j] = slp::OFF29[j];
+  for (int j = 0; j < 9; j++) acc[j] = (op >= 3 ? 2 : 1) * slp::OFF29[j];
   for (int i = 0; i < n; i++) {
     slp::f29 x = slp::to29(rd_raw(xs + 32 * i));
     for (int j = 0; j < 9; j++) acc[j] += (int64_t)k[i] * (int32_t)x.l[j];
   }
   slp::f29 r = slp::red29(acc);
-  wr_raw(out, slp::from29(op == 2 ? r : slp::canon29(r)));
+  wr_raw(out, slp::from29(op == 2 || op == 4 ? r : slp::canon29(r)));
   return 0;
 }
 

@@ -219,6 +219,28 @@ def test_engine_lane_arithmetic(hc):
         hc.hc_slp_lane(2, n, karr, blob, o)
         raw = int.from_bytes(o.raw, "big")
         assert raw < 2 * P and raw % P == sum(k * x for k, x in zip(ks, xs)) % P
+    # full-width sums: up to 16 terms, coefficient magnitudes summing to the encoder's limit
+    # (32767), the columns started at one offset (a product factor) or at two (a 16-term sum)
+    for trial in range(3000):
+        n = rng.randrange(1, 17)
+        budget = 32767
+        ks = []
+        for i in range(n):
+            c = rng.randrange(0, min(budget, 127 * 32) + 1) if trial % 3 else min(budget, 127 * 32)
+            budget -= c
+            ks.append(c if rng.random() < 0.5 else -c)
+        xs = [rng.choice(edge) if rng.random() < 0.3 else rng.randrange(2 * P) for _ in range(n)]
+        karr = (C.c_int * n)(*ks)
+        blob = b"".join(x.to_bytes(32, "big") for x in xs)
+        want = sum(k * x for k, x in zip(ks, xs)) % P
+        for op in (2, 4):
+            o = buf(32)
+            hc.hc_slp_lane(op, n, karr, blob, o)
+            raw = int.from_bytes(o.raw, "big")
+            assert raw < 2 * P and raw % P == want, (op, ks, xs)
+        o = buf(32)
+        hc.hc_slp_lane(3, n, karr, blob, o)
+        assert int.from_bytes(o.raw, "big") == want
     rinv = pow(1 << 261, -1, P)
     for trial in range(2000):
         a = rng.choice(edge) if trial % 5 == 0 else rng.randrange(2 * P)
