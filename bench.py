@@ -38,8 +38,8 @@ MADS_PER_FMUL = 136                        # 8x32-bit CIOS: 64 + 64 products + 8
 AHEAD_MAX_PAIRS = 4096                     # the library's switch to next-round terms (batches x K)
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a reference copy
 # (profiles/ks_final_exp2_n16_b256_hbm_counters.md); valid for the kernel build it was taken on
-TRAFFIC_BYTES = {"ks_final_exp2": round((418.5 * 2.000 + 14.2 * 1.000) * 1024),
-                 "ks_oa_pterms": round((820.6 * 2.000 + 127.0 * 1.000) * 1024)}
+TRAFFIC_BYTES = {"ks_final_exp2": round((417.0 * 2.000 + 14.2 * 1.000) * 1024),
+                 "ks_oa_pterms": round((827.6 * 2.000 + 127.0 * 1.000) * 1024)}
 FOLD_SPLIT_MAX = 256                       # folds of at most this many pairs run split in four parts
 DIRECT_MIN = 512                           # rounds of more pairs than this run direct in the ahead mode
 KZG_SPLIT_MAX = 8192                       # KZG proofs of at most this many split jobs run split
