@@ -1228,6 +1228,11 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
     else ks::oa_miller(CjG, Vb[0], K, G, h1, F, s1);
     if (int rc2 = ev_mark(ex, 22, s1)) return rc2;
   }
+  // the pairing side of the terms (side streams 3 and 4) reads only the arrays: it is ordered
+  // after their set-up, not after the hashing of r
+  if (int rc2 = stream_wait(ex, 2, st, sf)) return rc2;
+  if (ahead)
+    if (int rc2 = stream_wait(ex, 17, st, sfp[1])) return rc2;
   // multiples 2^{32 m} A[i] (m = 1..3) of the whole arrays A of round j (for its split fold
   // and the split G1 terms of round j + 1) and 2^{16 m} V[h + i] of the halves V[h..) (for
   // its split fold), into set j & 1 (round 1 on side stream 1, later rounds on the fold
@@ -1275,11 +1280,8 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
     return VC_OK;
   };
   if (int rc2 = stream_wait(ex, 1, st, sg)) return rc2;
-  if (int rc2 = stream_wait(ex, 2, st, sf)) return rc2;
-  if (ahead) {
-    if (int rc2 = stream_wait(ex, 17, st, sfp[1])) return rc2;
+  if (ahead)
     if (int rc2 = stream_wait(ex, 18, st, sq)) return rc2;
-  }
   // terms of round jn >= 2 from the arrays of round jn - 1 (one buffer set per round parity):
   // the pairing side (Miller loops, group products, final exponentiations, squaring
   // multiples) on side stream 3 + (jn & 1), ready at event 6 + (jn & 1) ...
@@ -1332,13 +1334,12 @@ static int open_all_group(const vc_params *cpp, const vc_commitment *const *cms,
       else if (nbm * h >= WIDE_FOLD_MIN) nprod = klw::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       else ks::oa_miller(Am, Vb[cur], K, nbm, h, F, st);
       // the terms of round j0 from the arrays of the last direct round, after its Miller
-      // loops (the G1 side after the multiples of the arrays)
+      // loops (the G1 side after the multiples of the arrays); from the arrays of round 1 as
+      // soon as they are set (their stream waits for nothing else), beside the round-1 Miller
+      // loops
       if (ahead && j + 1 == j0) {
-        if (j == 1) {
-          if (int rc2 = ev_wait(ex, 22, sfp[j0 & 1])) return rc2;
-        } else if (int rc2 = stream_wait(ex, 19, st, sfp[j0 & 1])) {
-          return rc2;
-        }
+        if (j > 1)
+          if (int rc2 = stream_wait(ex, 19, st, sfp[j0 & 1])) return rc2;
         if (int rc2 = launch_terms(j0)) return rc2;
         if (j == 1) {
           if (split_round(1))
